@@ -1,0 +1,245 @@
+"""The multigrid components, spelled out plainly in NumPy.
+
+This is the oracle for the pieces of the V-cycle (one smoothing sweep, one
+restriction, one prolongation, one coarsest solve, one V-cycle), used to
+check the GPU kernels element by element.  The paper fixes the system
+(Eq. st_system), the transfer structure I = T (x) M (x) S (Eq.
+space_time_tran) with bisection stencils [1 2 1]/4 (Sec. 4.2, SMG and STMG
+items), a block-Jacobi smoother over time slabs (Sec. 3.2), an exact
+coarsest solve and Newton around the linear solver.  What it leaves open
+is read as follows (each reading is listed with its reason in the design
+notes):
+
+* operator: the DG form with the lumped mass divided out,
+    (A U)_{n,i} = sum_j Kq[i,j] U_{n,j} + dt b_i (-nu Lap + lam) U_{n,i}
+                  - [n > 0] l_i(0) U_{n-1,M}
+  with M_q = dt diag(b) and J_q = l(0) e_M^T (exact for right Radau nodes);
+  coarse levels rediscretize with their own h and dt;
+* smoother: damped block-Jacobi over chunks of `chunk` consecutive slabs;
+  each chunk is inverted approximately by forward substitution in time
+  with a point-block (M x M) diagonal in space:
+    d_n = B^{-1} (r_n + [n mod chunk != 0] l(0) d_{n-1,M}),  U += omega d,
+  B = Kq + dt diag(b) (2 nu/hx^2 + 2 nu/hy^2 + lam);  chunk = 1 is the
+  plain point-block Jacobi over slabs;
+* space transfer: full weighting [1 2 1]/4 per dimension and linear
+  interpolation, vertex-centred (coarse point X is fine point 2X);
+* time transfer: slab n is identified with its end point T_{n+1}; coarse
+  slab J is fine slab 2J+1, the stencil is [1 2 1]/2 (restriction = P^T,
+  scaled so that rediscretized coarse operators match R A P), T_0 carries a
+  zero correction, the node index is left alone (M_l^{l+1} = I);
+* semi-coarsening: at each level coarsen in space if
+  mu = nu dt / h^2 >= mu_crit, else in time (Sec. 3.2: mu << 1 -> time,
+  mu >> 1 -> space), falling back to the other direction when one is not
+  possible, until the level holds at most `min_coarse` unknowns.
+"""
+import numpy as np
+
+from . import radau
+
+
+class Level:
+    def __init__(self, nx, ny, N, M, dt, nu, lam, length, dim, tab):
+        self.nx, self.ny, self.N, self.M, self.dt = nx, ny, N, M, dt
+        self.nu, self.lam, self.dim = nu, lam, dim
+        self.hx = length[0] / nx
+        self.hy = length[1] / ny if dim == 2 else 1.0
+        self.Kq, self.b, self.l0 = tab["Kq"], tab["b"], tab["l0"]
+        cx = nu / self.hx ** 2
+        cy = nu / self.hy ** 2 if dim == 2 else 0.0
+        self.cx, self.cy = cx, cy
+        dgl = 2 * cx + 2 * cy + lam
+        self.B = self.Kq + dt * np.diag(self.b) * dgl
+        self.Binv = np.linalg.inv(self.B)
+
+    @property
+    def shape(self):
+        return (self.N, self.M, self.ny, self.nx)
+
+    def lap(self, U):
+        out = self.cx * (np.roll(U, 1, -1) + np.roll(U, -1, -1) - 2 * U)
+        if self.dim == 2:
+            out = out + self.cy * (np.roll(U, 1, -2) + np.roll(U, -1, -2) - 2 * U)
+        return out
+
+    def apply(self, U):
+        out = np.einsum("ij,njyx->niyx", self.Kq, U)
+        out = out + self.dt * self.b[None, :, None, None] * (-self.lap(U) + self.lam * U)
+        out[1:] -= self.l0[None, :, None, None] * U[:-1, -1][:, None]
+        return out
+
+    def smooth(self, U, f, omega, chunk):
+        r = f - self.apply(U)
+        d = np.zeros_like(U)
+        for n in range(self.N):
+            rhs = r[n].copy()
+            if n % chunk != 0:
+                rhs = rhs + self.l0[:, None, None] * d[n - 1, -1][None]
+            d[n] = np.einsum("ij,jyx->iyx", self.Binv, rhs)
+        return U + omega * d
+
+    def slab_matrix(self):
+        """Dense diagonal block of the level operator (one slab)."""
+        K = self.M * self.ny * self.nx
+        E = np.eye(K).reshape(K, 1, self.M, self.ny, self.nx)
+        cols = []
+        for k in range(K):
+            e = E[k]
+            v = np.einsum("ij,njyx->niyx", self.Kq, e) + \
+                self.dt * self.b[None, :, None, None] * (-self.lap(e) + self.lam * e)
+            cols.append(v.reshape(-1))
+        return np.array(cols).T
+
+    def exact_solve(self, f):
+        A = self.slab_matrix()
+        U = np.zeros(self.shape)
+        for n in range(self.N):
+            rhs = f[n].copy()
+            if n > 0:
+                rhs = rhs + self.l0[:, None, None] * U[n - 1, -1][None]
+            U[n] = np.linalg.solve(A, rhs.reshape(-1)).reshape(self.M, self.ny, self.nx)
+        return U
+
+
+def restrict_space(r, dim):
+    r = 0.25 * np.roll(r, 1, -1) + 0.5 * r + 0.25 * np.roll(r, -1, -1)
+    r = r[..., ::2]
+    if dim == 2:
+        r = 0.25 * np.roll(r, 1, -2) + 0.5 * r + 0.25 * np.roll(r, -1, -2)
+        r = r[..., ::2, :]
+    return r
+
+
+def prolong_space(e, dim):
+    sh = list(e.shape)
+    sh[-1] *= 2
+    f = np.zeros(sh)
+    f[..., ::2] = e
+    f[..., 1::2] = 0.5 * (e + np.roll(e, -1, -1))
+    if dim == 2:
+        sh = list(f.shape)
+        sh[-2] *= 2
+        g = np.zeros(sh)
+        g[..., ::2, :] = f
+        g[..., 1::2, :] = 0.5 * (f + np.roll(f, -1, -2))
+        f = g
+    return f
+
+
+def restrict_time(r):
+    N = r.shape[0]
+    c = np.zeros((N // 2,) + r.shape[1:])
+    for J in range(N // 2):
+        c[J] = 0.5 * r[2 * J] + r[2 * J + 1]
+        if 2 * J + 2 < N:
+            c[J] += 0.5 * r[2 * J + 2]
+    return c
+
+
+def prolong_time(e):
+    Nc = e.shape[0]
+    f = np.zeros((2 * Nc,) + e.shape[1:])
+    for J in range(Nc):
+        f[2 * J + 1] = e[J]
+        f[2 * J] = 0.5 * e[J] + (0.5 * e[J - 1] if J > 0 else 0.0)
+    return f
+
+
+def hierarchy(prob, coarsen="auto", mu_crit=1.0, min_coarse=64, max_levels=30):
+    """Level list and the coarsening kind between consecutive levels.
+
+    kinds[l] is 's' (space), 't' (time) or 'st' (both) for the step l -> l+1.
+    Periodic boundary conditions only.
+    """
+    assert prob["bc"] == "periodic"
+    tab = radau.tables(prob["M"])
+    dim = prob["dim"]
+    nx = prob["nx"][0]
+    ny = prob["nx"][1] if dim == 2 else 1
+    N, dt = prob["N"], prob["dt"]
+    mk = lambda nx_, ny_, N_, dt_: Level(nx_, ny_, N_, prob["M"], dt_, prob["nu"],
+                                         prob.get("lambda", 0.0), prob["length"], dim, tab)
+    levels = [mk(nx, ny, N, dt)]
+    kinds = []
+    while len(levels) < max_levels:
+        l = levels[-1]
+        if l.M * l.nx * l.ny * l.N <= min_coarse:
+            break
+        can_s = l.nx % 2 == 0 and l.nx >= 4 and (dim == 1 or (l.ny % 2 == 0 and l.ny >= 4))
+        can_t = l.N % 2 == 0
+        mu = l.nu * l.dt / min(l.hx, l.hy if dim == 2 else l.hx) ** 2
+        if coarsen == "space":
+            k = "s" if can_s else None
+        elif coarsen == "spacetime":
+            k = "st" if (can_s and can_t) else ("s" if can_s else ("t" if can_t else None))
+        else:
+            if mu >= mu_crit and can_s:
+                k = "s"
+            elif can_t:
+                k = "t"
+            elif can_s:
+                k = "s"
+            else:
+                k = None
+        if k is None:
+            break
+        nx2 = l.nx // 2 if "s" in k else l.nx
+        ny2 = (l.ny // 2 if dim == 2 else 1) if "s" in k else l.ny
+        N2 = l.N // 2 if "t" in k else l.N
+        dt2 = 2 * l.dt if "t" in k else l.dt
+        levels.append(mk(nx2, ny2, N2, dt2))
+        kinds.append(k)
+    return levels, kinds
+
+
+def restrict(r, kind, dim):
+    if "s" in kind:
+        r = restrict_space(r, dim)
+    if "t" in kind:
+        r = restrict_time(r)
+    return r
+
+
+def prolong(e, kind, dim):
+    if "t" in kind:
+        e = prolong_time(e)
+    if "s" in kind:
+        e = prolong_space(e, dim)
+    return e
+
+
+def vcycle(levels, kinds, U, f, omega=0.8, chunk=16, nu_pre=1, nu_post=1, l=0):
+    lev = levels[l]
+    if l == len(levels) - 1:
+        return lev.exact_solve(f)
+    for _ in range(nu_pre):
+        U = lev.smooth(U, f, omega, chunk)
+    r = f - lev.apply(U)
+    fc = restrict(r, kinds[l], lev.dim)
+    ec = vcycle(levels, kinds, np.zeros(levels[l + 1].shape), fc, omega, chunk, nu_pre, nu_post, l + 1)
+    U = U + prolong(ec, kinds[l], lev.dim)
+    for _ in range(nu_post):
+        U = lev.smooth(U, f, omega, chunk)
+    return U
+
+
+def rhs(levels, u0):
+    lev = levels[0]
+    f = np.zeros(lev.shape)
+    f[0] = lev.l0[:, None, None] * np.asarray(u0).reshape(lev.ny, lev.nx)[None]
+    return f
+
+
+def solve(prob, u0, rtol=1e-12, max_cycles=200, **kw):
+    """V-cycles from a zero initial guess until ||b - A U|| <= rtol ||b||."""
+    hk = {k: kw.pop(k) for k in ("coarsen", "mu_crit", "min_coarse", "max_levels") if k in kw}
+    levels, kinds = hierarchy(prob, **hk)
+    f = rhs(levels, u0)
+    U = np.zeros(levels[0].shape)
+    nb = np.linalg.norm(f)
+    hist = []
+    for _ in range(max_cycles):
+        U = vcycle(levels, kinds, U, f, **kw)
+        hist.append(np.linalg.norm(f - levels[0].apply(U)) / nb)
+        if hist[-1] <= rtol:
+            break
+    return U, hist

@@ -1,0 +1,101 @@
+"""Oracle pins for the multigrid components: transfer identities, the
+smoother's fixed point, the V-cycle's fixed point (the stepper's solution)."""
+import numpy as np
+import pytest
+
+import stmg_inputs as si
+from oracle import mg, stepper
+
+
+def _inner(a, b):
+    return float(np.sum(a * b))
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_space_transfer_adjoint(dim):
+    rng = np.random.default_rng(0)
+    shp_f = (3, 2, 8 if dim == 2 else 1, 16)
+    shp_c = (3, 2, 4 if dim == 2 else 1, 8)
+    f = rng.standard_normal(shp_f)
+    c = rng.standard_normal(shp_c)
+    # R = 2^{-d} P^T
+    assert abs(_inner(mg.restrict_space(f, dim), c) - 2.0 ** (-dim) * _inner(f, mg.prolong_space(c, dim))) < 1e-12
+
+
+def test_time_transfer_adjoint():
+    rng = np.random.default_rng(1)
+    f = rng.standard_normal((8, 3, 2, 2))
+    c = rng.standard_normal((4, 3, 2, 2))
+    # time restriction is exactly P^T
+    assert abs(_inner(mg.restrict_time(f), c) - _inner(f, mg.prolong_time(c))) < 1e-12
+
+
+def test_transfer_constants_and_linears():
+    c = np.ones((2, 1, 4, 4))
+    assert np.abs(mg.prolong_space(c, 2) - 1).max() == 0
+    assert np.abs(mg.restrict_space(np.ones((2, 1, 8, 8)), 2) - 1).max() == 0
+    # linear in slab end time is reproduced exactly (T_0 carries zero)
+    Nc = 4
+    e = (np.arange(Nc) + 1.0)[:, None, None, None] * 2.0 * np.ones((1, 2, 1, 3))
+    f = mg.prolong_time(e)
+    assert np.abs(f[:, 0, 0, 0] - (np.arange(2 * Nc) + 1.0)).max() == 0
+    # interior time restriction of a constant gives 2 (rediscretization scale)
+    r = mg.restrict_time(np.ones((8, 1, 1, 1)))
+    assert np.allclose(r[:-1, 0, 0, 0], 2.0) and r[-1, 0, 0, 0] == 1.5
+
+
+def test_hierarchy_auto_rule():
+    prob = si.problem(2, 64, 3, 64, 1.0, nu=0.04, lam=1.0)  # mu = 2.56 on the finest level
+    levels, kinds = mg.hierarchy(prob)
+    assert kinds[0] == "s"            # mu >= 1: space first
+    assert kinds[1] == "t"            # mu = 0.64 after one space step
+    for l, k in zip(levels, kinds):
+        mu = l.nu * l.dt / l.hx ** 2
+        if k == "s":
+            assert mu >= 1.0 or l.N % 2 == 1
+    last = levels[-1]
+    assert last.M * last.nx * last.ny * last.N <= 64
+
+
+@pytest.mark.parametrize("chunk", [1, 4, 16])
+def test_smoother_fixed_point(chunk):
+    prob = si.problem(2, 16, 3, 8, 0.5, nu=0.02, lam=1.0)
+    u0 = si.u0_rd2d(prob, 9)
+    levels, _ = mg.hierarchy(prob)
+    Ue = stepper.solve_linear(prob, u0)
+    f = mg.rhs(levels, u0)
+    assert np.abs(levels[0].apply(Ue) - f).max() < 1e-13
+    U1 = levels[0].smooth(Ue, f, 0.8, chunk)
+    assert np.abs(U1 - Ue).max() < 1e-13
+
+
+def test_exact_coarse_solve():
+    prob = si.problem(2, 8, 2, 6, 0.5, nu=0.02, lam=1.0)
+    levels, _ = mg.hierarchy(prob, min_coarse=10 ** 9)
+    u0 = si.u0_rd2d(prob, 3)
+    f = mg.rhs(levels, u0)
+    U = levels[0].exact_solve(f)
+    assert np.abs(U - stepper.solve_linear(prob, u0)).max() < 1e-13
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("heat1d", {}),
+    ("rd2d-small", {}),
+    ("rd2d-small", {"coarsen": "space"}),
+    ("rd2d-small", {"coarsen": "spacetime"}),
+    ("rd2d-small", {"chunk": 1}),
+])
+def test_vcycle_converges_to_stepper(name, kw):
+    if name == "heat1d":
+        prob = si.config("heat1d")
+        u0 = si.initial("heat1d", prob)
+    else:
+        prob = si.problem(2, 32, 3, 32, 1.0, nu=1e-2 * 32 / 256 * 8, lam=1.0)
+        u0 = si.u0_rd2d(prob, 2)
+    U, hist = mg.solve(prob, u0, rtol=1e-12, max_cycles=150, **kw)
+    assert hist[-1] <= 1e-12
+    Ue = stepper.solve_linear(prob, u0)
+    assert np.linalg.norm(U - Ue) <= 1e-10 * np.linalg.norm(Ue)
+    rates = [hist[i + 1] / hist[i] for i in range(len(hist) - 1)]
+    if not kw:
+        assert np.median(rates) < 0.5, rates
