@@ -1,0 +1,216 @@
+/*
+ * stmg.h -- C ABI of the MI355X space-time multigrid library (libstmg.so).
+ *
+ * The library solves the all-at-once space-time system of a reaction-
+ * diffusion problem discretized by finite differences in space and by
+ * right-Radau collocation / DG in time (Benedusi, Minion, Krause: "An
+ * experimental comparison of a space-time multigrid method with PFASST for a
+ * reaction-diffusion problem").  The system is Eq. (st_system) of Sec. 3:
+ * one block row per time step ("slab"), diagonal blocks
+ * A = K_q (x) M_h + M_q (x) K_h and sub-diagonal blocks B = -J_q (x) M_h
+ * (Eq. A_B_ops), here with the lumped mass divided out of every spatial row,
+ * so that K_h becomes -nu Lap_h + lambda (2nd-order central differences).
+ * With M_q = dt diag(b) and J_q = l(0) e_M^T (exact for right Radau nodes),
+ * the operator acting on a space-time vector U is
+ *
+ *   (A U)_{n,i} = sum_j Kq[i,j] U_{n,j} + dt b_i (-nu Lap_h U_{n,i} + R(U_{n,i}))
+ *                 - [n > 0] l_i(0) U_{n-1,M}
+ *   b_{n,i}     = [n = 0] l_i(0) u0                     (Sec. 3, padding of u_0)
+ *
+ * with R(u) = lambda u (linear) or gamma (u^3 - u) (Allen-Cahn, Eq. model).
+ *
+ * Data layout.  Every space-time vector is a contiguous FP64 array
+ * [N][M][ny][nx] (slab, node, then space with x fastest), the node-major,
+ * space-minor ordering of Sec. 3.  A 1D problem has ny = 1.  Periodic grids
+ * have nx points per dimension (h = length / nx); Neumann grids have nx + 1
+ * points (h = length / nx, ghost reflection at both ends, which is the
+ * lumped linear-FE operator of Sec. 3 divided by the lumped mass).
+ *
+ * Memory and streams.  The caller owns every device array, including one
+ * workspace buffer whose size comes from stmg_workspace_bytes(); it must
+ * stay allocated while the handle lives.  The library never allocates or
+ * frees device memory.  All work is enqueued on the stream given at setup
+ * (a hipStream_t passed as void*, NULL = the null stream).  Calls that
+ * return host scalars (norms, statistics, d loss / d nu) synchronize that
+ * stream before returning; all other calls are asynchronous.
+ *
+ * Errors.  Every int-returning function returns STMG_OK (0) or a negative
+ * stmg_status.  No exception or abort crosses the ABI.  A description of the
+ * last failure on the calling thread is returned by stmg_last_error().
+ * Calls on one handle must not overlap (one host thread at a time).
+ */
+#ifndef STMG_H
+#define STMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STMG_OK = 0,
+  STMG_EINVAL = -1,        /* invalid argument or problem description       */
+  STMG_ENOMEM = -2,        /* workspace too small                             */
+  STMG_EHIP = -3,          /* a HIP runtime call failed                       */
+  STMG_ENOTCONV = -4,      /* max_cycles reached before rtol ("n.c.", Sec. 5.2) */
+  STMG_EDIVERGED = -5,     /* residual grew by 1e3 or for 5 cycles in a row   */
+  STMG_ENAN = -6,          /* a residual norm was NaN or Inf                  */
+  STMG_EUNSUPPORTED = -7   /* valid but not supported (e.g. coarsest too big) */
+} stmg_status;
+
+enum { STMG_BC_PERIODIC = 0, STMG_BC_NEUMANN = 1 };
+enum { STMG_REACT_LINEAR = 0, STMG_REACT_ALLEN_CAHN = 1 };
+enum { STMG_PREC_FP64 = 0, STMG_PREC_MIXED = 1 };
+enum { STMG_COARSEN_AUTO = 0, STMG_COARSEN_SPACE = 1, STMG_COARSEN_SPACETIME = 2 };
+
+/* The problem statement: Eq. (model) of Sec. 3 generalized to a diffusion
+ * coefficient, 2D and periodic grids; uniform partitions of Sec. 3. */
+typedef struct {
+  int32_t dim;        /* 1 or 2                                              */
+  int32_t nx[2];      /* elements per dimension (nx[1] ignored when dim = 1) */
+  double length[2];   /* domain size X (and Y)                               */
+  int32_t bc;         /* STMG_BC_PERIODIC or STMG_BC_NEUMANN                 */
+  double nu;          /* diffusion coefficient (> 0)                         */
+  int32_t reaction;   /* STMG_REACT_LINEAR: f = nu Lap u - lambda u
+                         STMG_REACT_ALLEN_CAHN: f = nu Lap u + gamma (u - u^3) */
+  double lambda;      /* linear reaction rate (>= 0)                         */
+  double gamma;       /* Allen-Cahn reaction intensity                       */
+  int32_t M;          /* right Radau nodes per step, 1..8 (Sec. 2.1)         */
+  int32_t N;          /* time steps (slabs)                                  */
+  double dt;          /* step size; T = N dt                                 */
+} stmg_problem;
+
+/* Solver options.  stmg_default_options() fills the defaults shown. */
+typedef struct {
+  int32_t precision;  /* STMG_PREC_FP64 (default) or STMG_PREC_MIXED: FP32
+                         smoother and transfers inside FP64 refinement        */
+  int32_t coarsen;    /* AUTO (default): space if mu_l = nu dt_l / h_l^2 >=
+                         mu_crit, else time (Sec. 3.2); SPACE = SMG;
+                         SPACETIME = STMG (both at once)                      */
+  double mu_crit;     /* 0.5                                                 */
+  double omega;       /* smoother damping, 0.8                                */
+  int32_t chunk;      /* smoother block length in slabs, 16 (1 = point-block
+                         Jacobi over single slabs)                            */
+  int32_t nu_pre;     /* pre-smoothing sweeps, 1                              */
+  int32_t nu_post;    /* post-smoothing sweeps, 1                             */
+  int32_t max_levels; /* 30                                                  */
+  int32_t min_coarse; /* stop coarsening at <= this many unknowns, 64         */
+  int32_t max_cycles; /* 200                                                 */
+  double rtol;        /* stop at ||b - A U||_2 <= rtol ||b||_2, 1e-12          */
+  double newton_rtol; /* Allen-Cahn: stop Newton at ||G(U)|| <= newton_rtol
+                         ||b||, 1e-10                                          */
+  int32_t max_newton; /* 30                                                  */
+  size_t mem_budget;  /* adjoint: max bytes for the stored forward trajectory;
+                         0 = unlimited (no checkpointing)                     */
+} stmg_options;
+
+typedef struct {
+  int32_t cycles;       /* V-cycles done (all Newton steps together)         */
+  int32_t newton_its;   /* Newton iterations (Allen-Cahn)                    */
+  int32_t refinements;  /* FP64 refinement steps (mixed precision)           */
+  int32_t status;       /* final status of the call                          */
+  double rel_res;       /* final ||b - A U|| / ||b||                         */
+  double seconds;       /* wall time of the call (host clock, synchronized)  */
+} stmg_stats;
+
+typedef struct stmg_handle stmg_handle;
+typedef struct stmg_batch stmg_batch;
+
+void stmg_default_options(stmg_options* opt);
+
+/* Bytes of device workspace needed by stmg_setup for this problem/options,
+ * or 0 if the description is invalid (see stmg_last_error). */
+size_t stmg_workspace_bytes(const stmg_problem* prob, const stmg_options* opt);
+
+/* Builds the Radau tables (Sec. 2.1/2.2), the level hierarchy and the
+ * coarsest-level factors, and copies the device tables into d_ws.  d_ws must
+ * be 256-byte aligned and at least stmg_workspace_bytes() long.  Returns the
+ * handle in *out.  EINVAL: M outside 1..8, N < 1, dt <= 0, nu <= 0, fewer
+ * than 3 points per dimension, dim not 1 or 2, or a NULL pointer.
+ * EUNSUPPORTED: the coarsest level would have more than 1024 unknowns per
+ * slab. */
+int stmg_setup(const stmg_problem* prob, const stmg_options* opt, void* d_ws,
+               size_t ws_bytes, void* stream, stmg_handle** out);
+
+/* Number of levels and the shape of level l: out[0] = points in x, out[1] =
+ * points in y, out[2] = slabs, out[3] = coarsening kind to level l+1
+ * (0 none, 1 space, 2 time, 3 both).  Host only. */
+int stmg_num_levels(const stmg_handle* h);
+int stmg_level_shape(const stmg_handle* h, int level, int32_t out[4], double* dt);
+
+/* r = b - A(U) on the finest level (Eq. st_system), b built from u0.
+ * d_u0: [ny][nx]; d_U: [N][M][ny][nx]; d_r may be NULL (norm only).
+ * h_norm (may be NULL) receives ||r||_2 and synchronizes the stream. */
+int stmg_residual(stmg_handle* h, const double* d_u0, const double* d_U,
+                  double* d_r, double* h_norm);
+
+/* One V-cycle (Sec. 3.2) on A U = b, updating d_U in place.  h_rel (may be
+ * NULL) receives ||b - A U|| / ||b|| after the cycle and synchronizes.
+ * On an Allen-Cahn handle the cycle acts on the Jacobian at the last Newton
+ * linearization point, with b the last Newton right-hand side. */
+int stmg_vcycle(stmg_handle* h, const double* d_u0, double* d_U, double* h_rel);
+
+/* Solves the all-at-once system from the initial guess in d_U (zero is the
+ * paper's choice, Sec. 5.2): V-cycles (FP64, or FP32 cycles inside FP64
+ * refinement when precision = MIXED) until rel_res <= rtol, wrapped in
+ * Newton for Allen-Cahn (Sec. 3.2).  d_U receives the solution (the last
+ * iterate on ENOTCONV/EDIVERGED/ENAN).  stats may be NULL.  Synchronizes. */
+int stmg_solve(stmg_handle* h, const double* d_u0, double* d_U, stmg_stats* stats);
+
+/* Gradients of L = || U_{N,M} - u_tgt ||^2 (linear problems, periodic grids).  d_U is the
+ * converged forward solution; d_gT = dL/du(T) = 2 (U_{N,M} - u_tgt), [ny][nx].
+ * Solves the transposed system A^T lam = g (backward in time, same V-cycle
+ * kernels) and returns d_grad_u0 = sum_i l_i(0) lam_{0,i} ([ny][nx], device)
+ * and *h_grad_nu = sum_{n,i,x} lam_{n,i} dt b_i (Lap_h U_{n,i})(x).  When d_U
+ * is NULL the forward trajectory is recomputed window by window from d_u0
+ * (checkpointing); d_u0 may be NULL otherwise.  Synchronizes. */
+int stmg_adjoint(stmg_handle* h, const double* d_u0, const double* d_U,
+                 const double* d_gT, double* d_grad_u0, double* h_grad_nu,
+                 stmg_stats* stats);
+
+/* `sweeps` SDC sweeps (Sec. 2.1 and 3.1: preconditioned Richardson on the
+ * collocation form with the implicit-Euler lower-triangular Q_Delta) over
+ * all slabs at once, the previous slab's end value lagged; the implicit
+ * node solves are spatial V-cycles from the same kernels.  h_rel (may be
+ * NULL) receives the relative DG residual after the sweeps.  Linear only. */
+int stmg_sdc_sweep(stmg_handle* h, const double* d_u0, double* d_U,
+                   int32_t sweeps, double* h_rel);
+
+/* Component entry points on level `level` of the hierarchy (FP64):
+ *   smooth : U_out = U_in + omega D^{-1} (f - A_l U_in); the block-Jacobi
+ *            sweep over chunks of slabs (Sec. 3.2); U_in may be NULL (zero)
+ *   restrict_residual : f_coarse = R (f - A_l U)  (Eq. space_time_tran)
+ *   prolong : U_out = U_in + P e_coarse            (transpose structure)
+ *   coarse_solve : U = A_L^{-1} f on the coarsest level (exact, Sec. 3.2)
+ * On level 0, f may be NULL, meaning the right-hand side built from d_u0. */
+int stmg_level_smooth(stmg_handle* h, int level, const double* d_f,
+                      const double* d_u0, const double* d_Uin, double* d_Uout);
+int stmg_level_restrict_residual(stmg_handle* h, int level, const double* d_f,
+                                 const double* d_u0, const double* d_U, double* d_fc);
+int stmg_level_prolong(stmg_handle* h, int level, const double* d_Uin,
+                       const double* d_ec, double* d_Uout);
+int stmg_coarse_solve(stmg_handle* h, const double* d_f, double* d_U);
+
+void stmg_destroy(stmg_handle* h);
+
+/* Batched independent linear problems (mixed precision to rtol): one
+ * phase-kernel launch per multigrid phase for all problems at once, the
+ * V-cycle captured in a HIP graph.  d_u0[p], d_U[p] are the per-problem
+ * device arrays.  Synchronizes in solve. */
+size_t stmg_batch_workspace_bytes(int32_t n, const stmg_problem* probs,
+                                  const stmg_options* opt);
+int stmg_batch_setup(int32_t n, const stmg_problem* probs, const stmg_options* opt,
+                     void* d_ws, size_t ws_bytes, void* stream, stmg_batch** out);
+int stmg_batch_solve(stmg_batch* b, const double* const* d_u0, double* const* d_U,
+                     stmg_stats* stats /* [n], may be NULL */);
+void stmg_batch_destroy(stmg_batch* b);
+
+const char* stmg_status_string(int status);
+const char* stmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STMG_H */

@@ -30,7 +30,8 @@ notes):
 * semi-coarsening: at each level coarsen in space if
   mu = nu dt / h^2 >= mu_crit, else in time (Sec. 3.2: mu << 1 -> time,
   mu >> 1 -> space), falling back to the other direction when one is not
-  possible, until the level holds at most `min_coarse` unknowns.
+  possible, until the level holds at most `min_coarse` unknowns.  The paper
+  gives no threshold; mu_crit = 0.5 by default.
 """
 import numpy as np
 
@@ -144,7 +145,7 @@ def prolong_time(e):
     return f
 
 
-def hierarchy(prob, coarsen="auto", mu_crit=1.0, min_coarse=64, max_levels=30):
+def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30):
     """Level list and the coarsening kind between consecutive levels.
 
     kinds[l] is 's' (space), 't' (time) or 'st' (both) for the step l -> l+1.

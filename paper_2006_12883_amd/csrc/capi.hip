@@ -1,0 +1,193 @@
+// C ABI of libstmg (declared in include/stmg.h).
+#include <new>
+#include <string>
+
+#include "solver.hpp"
+
+struct stmg_handle {
+  stmg::Solver s;
+};
+
+namespace stmg {
+namespace {
+thread_local std::string g_last_error;
+}
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace stmg
+
+using stmg::Solver;
+
+extern "C" {
+
+const char* stmg_status_string(int status) {
+  switch (status) {
+    case STMG_OK: return "ok";
+    case STMG_EINVAL: return "invalid argument";
+    case STMG_ENOMEM: return "workspace too small";
+    case STMG_EHIP: return "HIP runtime error";
+    case STMG_ENOTCONV: return "not converged";
+    case STMG_EDIVERGED: return "diverged";
+    case STMG_ENAN: return "NaN or Inf in residual";
+    case STMG_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* stmg_last_error(void) { return stmg::g_last_error.c_str(); }
+
+void stmg_default_options(stmg_options* o) {
+  if (!o) return;
+  o->precision = STMG_PREC_FP64;
+  o->coarsen = STMG_COARSEN_AUTO;
+  o->mu_crit = 0.5;
+  o->omega = 0.8;
+  o->chunk = 16;
+  o->nu_pre = 1;
+  o->nu_post = 1;
+  o->max_levels = 30;
+  o->min_coarse = 64;
+  o->max_cycles = 200;
+  o->rtol = 1e-12;
+  o->newton_rtol = 1e-10;
+  o->max_newton = 30;
+  o->mem_budget = 0;
+}
+
+size_t stmg_workspace_bytes(const stmg_problem* prob, const stmg_options* opt) {
+  if (!prob) { stmg::set_error("null problem"); return 0; }
+  stmg_options d;
+  if (!opt) { stmg_default_options(&d); opt = &d; }
+  Solver s;
+  if (s.build(prob, opt) != STMG_OK) return 0;
+  return s.plan(nullptr);
+}
+
+int stmg_setup(const stmg_problem* prob, const stmg_options* opt, void* d_ws, size_t ws_bytes,
+               void* stream, stmg_handle** out) {
+  if (!prob || !d_ws || !out) { stmg::set_error("null pointer"); return STMG_EINVAL; }
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) {
+    stmg::set_error("workspace must be 256-byte aligned");
+    return STMG_EINVAL;
+  }
+  stmg_options d;
+  if (!opt) { stmg_default_options(&d); opt = &d; }
+  stmg_handle* h = new (std::nothrow) stmg_handle;
+  if (!h) return STMG_ENOMEM;
+  int rc = h->s.build(prob, opt);
+  if (rc) { delete h; return rc; }
+  const size_t need = h->s.plan(nullptr);
+  if (ws_bytes < need) {
+    stmg::set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    delete h;
+    return STMG_ENOMEM;
+  }
+  h->s.stream = static_cast<hipStream_t>(stream);
+  h->s.ws_bytes = ws_bytes;
+  h->s.plan(static_cast<char*>(d_ws));
+  rc = h->s.upload();
+  if (rc) { delete h; return rc; }
+  *out = h;
+  return STMG_OK;
+}
+
+int stmg_num_levels(const stmg_handle* h) { return h ? static_cast<int>(h->s.lv.size()) : 0; }
+
+int stmg_level_shape(const stmg_handle* h, int level, int32_t out[4], double* dt) {
+  if (!h || !out || level < 0 || level >= static_cast<int>(h->s.lv.size())) {
+    stmg::set_error("bad level");
+    return STMG_EINVAL;
+  }
+  const auto& l = h->s.lv[level];
+  out[0] = l.nx;
+  out[1] = l.ny;
+  out[2] = l.N;
+  out[3] = l.kind;
+  if (dt) *dt = l.dt;
+  return STMG_OK;
+}
+
+int stmg_residual(stmg_handle* h, const double* d_u0, const double* d_U, double* d_r,
+                  double* h_norm) {
+  if (!h || !d_U) { stmg::set_error("null pointer"); return STMG_EINVAL; }
+  return h->s.residual_user(d_u0, d_U, d_r, h_norm);
+}
+
+int stmg_vcycle(stmg_handle* h, const double* d_u0, double* d_U, double* h_rel) {
+  if (!h || !d_U) { stmg::set_error("null pointer"); return STMG_EINVAL; }
+  if (!h->s.allen_cahn && !d_u0) { stmg::set_error("null u0"); return STMG_EINVAL; }
+  return h->s.vcycle_user(d_u0, d_U, h_rel);
+}
+
+int stmg_solve(stmg_handle* h, const double* d_u0, double* d_U, stmg_stats* stats) {
+  if (!h || !d_u0 || !d_U) { stmg::set_error("null pointer"); return STMG_EINVAL; }
+  return h->s.solve(d_u0, d_U, stats);
+}
+
+int stmg_adjoint(stmg_handle* h, const double* d_u0, const double* d_U, const double* d_gT,
+                 double* d_grad_u0, double* h_grad_nu, stmg_stats* stats) {
+  if (!h || !d_gT || !d_grad_u0 || !h_grad_nu) { stmg::set_error("null pointer"); return STMG_EINVAL; }
+  return h->s.adjoint(d_u0, d_U, d_gT, d_grad_u0, h_grad_nu, stats);
+}
+
+int stmg_sdc_sweep(stmg_handle* h, const double* d_u0, double* d_U, int32_t sweeps,
+                   double* h_rel) {
+  if (!h || !d_u0 || !d_U || sweeps < 0) { stmg::set_error("bad argument"); return STMG_EINVAL; }
+  return h->s.sdc(d_u0, d_U, sweeps, h_rel);
+}
+
+int stmg_level_smooth(stmg_handle* h, int level, const double* d_f, const double* d_u0,
+                      const double* d_Uin, double* d_Uout) {
+  if (!h || !d_Uout || level < 0 || level >= static_cast<int>(h->s.lv.size())) {
+    stmg::set_error("bad argument");
+    return STMG_EINVAL;
+  }
+  hipError_t e = h->s.smooth<double>(level, false, stmg::REACT_CONST, d_Uin, d_f,
+                                     level == 0 ? d_u0 : nullptr, d_Uout);
+  return e == hipSuccess ? STMG_OK : STMG_EHIP;
+}
+
+int stmg_level_restrict_residual(stmg_handle* h, int level, const double* d_f,
+                                 const double* d_u0, const double* d_U, double* d_fc) {
+  if (!h || !d_fc || level < 0 || level + 1 >= static_cast<int>(h->s.lv.size())) {
+    stmg::set_error("bad argument");
+    return STMG_EINVAL;
+  }
+  hipError_t e = h->s.restrict_residual<double>(level, false, stmg::REACT_CONST, d_U, d_f,
+                                                level == 0 ? d_u0 : nullptr, d_fc);
+  return e == hipSuccess ? STMG_OK : STMG_EHIP;
+}
+
+int stmg_level_prolong(stmg_handle* h, int level, const double* d_Uin, const double* d_ec,
+                       double* d_Uout) {
+  if (!h || !d_ec || !d_Uout || level < 0 || level + 1 >= static_cast<int>(h->s.lv.size())) {
+    stmg::set_error("bad argument");
+    return STMG_EINVAL;
+  }
+  hipError_t e = h->s.prolong<double>(level, d_Uin, d_ec, d_Uout);
+  return e == hipSuccess ? STMG_OK : STMG_EHIP;
+}
+
+int stmg_coarse_solve(stmg_handle* h, const double* d_f, double* d_U) {
+  if (!h || !d_U) { stmg::set_error("bad argument"); return STMG_EINVAL; }
+  hipError_t e = h->s.coarse<double>(false, stmg::REACT_CONST, d_f, nullptr, d_U);
+  return e == hipSuccess ? STMG_OK : STMG_EHIP;
+}
+
+void stmg_destroy(stmg_handle* h) { delete h; }
+
+size_t stmg_batch_workspace_bytes(int32_t, const stmg_problem*, const stmg_options*) {
+  stmg::set_error("batched solve not available in this build");
+  return 0;
+}
+int stmg_batch_setup(int32_t, const stmg_problem*, const stmg_options*, void*, size_t, void*,
+                     stmg_batch**) {
+  stmg::set_error("batched solve not available in this build");
+  return STMG_EUNSUPPORTED;
+}
+int stmg_batch_solve(stmg_batch*, const double* const*, double* const*, stmg_stats*) {
+  stmg::set_error("batched solve not available in this build");
+  return STMG_EUNSUPPORTED;
+}
+void stmg_batch_destroy(stmg_batch*) {}
+
+}  // extern "C"

@@ -1,0 +1,1012 @@
+// HIP kernels of the space-time multigrid (gfx950, wave64).
+//
+// All operator kernels work on space-time vectors laid out [N][M][ny][nx]
+// (slab, node, space; Sec. 3).  A thread owns one spatial point and marches
+// through a run of consecutive slabs: the M node values of its point and the
+// coupling value from the previous slab stay in registers, so a slab's
+// end-value plane is never re-read from memory inside a run.  Spatial
+// neighbours come through the L1/L2 caches; the block index is remapped so
+// that consecutive spatial tiles run on the same XCD (shared L2).  The small
+// M x M time coupling is done with scalar constants from the kernel argument
+// block; it is 2M flops per unknown, far too little to use matrix cores.
+#include "kernels.hpp"
+
+namespace stmg {
+
+namespace {
+
+// Consecutive logical blocks on one XCD: hardware places block b on XCD b % 8.
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+  const int X = 8;
+  const int q = nb / X, r = nb % X;
+  const int xcd = bid % X, k = bid / X;
+  return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+__device__ __forceinline__ int nb_lo(int i, int n, int bc) {
+  return i > 0 ? i - 1 : (bc == 0 ? n - 1 : 1);
+}
+__device__ __forceinline__ int nb_hi(int i, int n, int bc) {
+  return i < n - 1 ? i + 1 : (bc == 0 ? 0 : n - 2);
+}
+
+// Sum over the workgroup (256 threads); the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kBlock / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) t += red[i];
+  }
+  return t;
+}
+
+// Constants of a level converted to the arithmetic type T.
+template <int M, typename T>
+struct Consts {
+  T K[M][M], Bi[M][M], db[M], cin[M], cout[M];
+  T cx, cy, lam, gamma, omega;
+  __device__ __forceinline__ explicit Consts(const OpParams& p) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      db[i] = (T)p.db[i];
+      cin[i] = (T)p.cin[i];
+      cout[i] = (T)p.cout[i];
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        K[i][j] = (T)p.K[i * M + j];
+        Bi[i][j] = (T)p.Binv[i * M + j];
+      }
+    }
+    cx = (T)p.cx;
+    cy = (T)p.cy;
+    lam = (T)p.lam;
+    gamma = (T)p.gamma;
+    omega = (T)p.omega;
+  }
+};
+
+// Neighbour offsets of point q inside a plane.
+struct Nbr {
+  int xm, xp, ym, yp;
+};
+
+__device__ __forceinline__ Nbr neighbours(int x, int y, int nx, int ny, int bc) {
+  Nbr o;
+  o.xm = y * nx + nb_lo(x, nx, bc);
+  o.xp = y * nx + nb_hi(x, nx, bc);
+  o.ym = ny > 1 ? nb_lo(y, ny, bc) * nx + x : 0;
+  o.yp = ny > 1 ? nb_hi(y, ny, bc) * nx + x : 0;
+  return o;
+}
+
+// Loads the M node values at point q of slab `base` and their 5-point
+// Laplacians (scaled by cx, cy).
+template <int M, typename T>
+__device__ __forceinline__ void load_point(const T* __restrict__ U, size_t base, int P, int q,
+                                           const Nbr& nb, bool twod, T cx, T cy, T u[M],
+                                           T lap[M]) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const T* Um = U + base + (size_t)m * P;
+    const T c = Um[q];
+    T l = cx * (Um[nb.xm] + Um[nb.xp] - c - c);
+    if (twod) l += cy * (Um[nb.ym] + Um[nb.yp] - c - c);
+    u[m] = c;
+    lap[m] = l;
+  }
+}
+
+// r_i = f_i - [sum_j K_ij u_j + db_i (-lap_i + react_i) - cin_i prev]
+template <int M, typename T, int REACT>
+__device__ __forceinline__ void point_residual(const Consts<M, T>& c, const T u[M],
+                                               const T lap[M], const T* __restrict__ coef,
+                                               const T* __restrict__ f, size_t base, int P,
+                                               int q, T prev, T r[M]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T au = T(0);
+#pragma unroll
+    for (int j = 0; j < M; ++j) au += c.K[i][j] * u[j];
+    T react;
+    if (REACT == REACT_CONST) react = c.lam * u[i];
+    else if (REACT == REACT_COEF) react = coef[base + (size_t)i * P + q] * u[i];
+    else react = c.gamma * (u[i] * u[i] * u[i] - u[i]);
+    au += c.db[i] * (react - lap[i]);
+    au -= c.cin[i] * prev;
+    const T fi = f ? f[base + (size_t)i * P + q] : T(0);
+    r[i] = fi - au;
+  }
+}
+
+// d = B^{-1} rhs with B = K + diag(db_i (dg + coef_i)), no pivoting
+// (K has positive leading minors and the added diagonal is positive in
+// practice; the constant-coefficient case uses the precomputed inverse).
+template <int M, typename T>
+__device__ __forceinline__ void point_block_solve(const Consts<M, T>& c, T dg, const T coefv[M],
+                                                  T x[M]) {
+  T A[M][M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) A[i][j] = c.K[i][j];
+    A[i][i] += c.db[i] * (dg + coefv[i]);
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const T inv = T(1) / A[k][k];
+#pragma unroll
+    for (int i = k + 1; i < M; ++i) {
+      const T l = A[i][k] * inv;
+#pragma unroll
+      for (int j = k + 1; j < M; ++j) A[i][j] -= l * A[k][j];
+      x[i] -= l * x[k];
+    }
+  }
+#pragma unroll
+  for (int k = M - 1; k >= 0; --k) {
+    T s = x[k];
+#pragma unroll
+    for (int j = k + 1; j < M; ++j) s -= A[k][j] * x[j];
+    x[k] = s / A[k][k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Smoother: block-Jacobi over chunks of S slabs.  Inside a chunk the
+// block lower-bidiagonal time coupling is inverted by forward substitution
+// with the point-block (M x M) diagonal in space:
+//   d_n = B^{-1} (r_n + [n > n0] cin (cout . d_{n-1})),  U_out = U + omega d,
+// where r = f - A U uses the old iterate everywhere (Jacobi in space and
+// across chunks).  One thread = one point x one chunk.
+template <int M, typename T, int REACT>
+__global__ __launch_bounds__(kBlock) void k_smooth(const OpParams p, const SweepPtrs<T> a, int S,
+                                                   int tiles, int nblocks) {
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  const int tile = lb % tiles;
+  const int n0 = (lb / tiles) * S;
+  const int P = p.nx * p.ny;
+  const int q = tile * kBlock + threadIdx.x;
+  if (q >= P || n0 >= p.N) return;
+  const int n1 = min(n0 + S, p.N);
+  const Consts<M, T> c(p);
+  const bool twod = p.ny > 1;
+  const Nbr nb = neighbours(q % p.nx, q / p.nx, p.nx, p.ny, p.bc);
+  const T dg = T(2) * c.cx + (twod ? T(2) * c.cy : T(0));
+  T* __restrict__ out = static_cast<T*>(a.out);
+
+  T prev = T(0);
+  if (n0 == 0) {
+    if (a.u0) prev = (T)a.u0[q];
+  } else if (a.U) {
+    const size_t b = (size_t)(n0 - 1) * M * P;
+#pragma unroll
+    for (int j = 0; j < M; ++j) prev += c.cout[j] * a.U[b + (size_t)j * P + q];
+  }
+  T dprev = T(0);
+  for (int n = n0; n < n1; ++n) {
+    const size_t base = (size_t)n * M * P;
+    T u[M], lap[M], r[M];
+    if (a.U) {
+      load_point<M, T>(a.U, base, P, q, nb, twod, c.cx, c.cy, u, lap);
+    } else {
+#pragma unroll
+      for (int m = 0; m < M; ++m) u[m] = lap[m] = T(0);
+    }
+    point_residual<M, T, REACT>(c, u, lap, a.coef, a.f, base, P, q, prev, r);
+    if (n > n0) {
+#pragma unroll
+      for (int i = 0; i < M; ++i) r[i] += c.cin[i] * dprev;
+    }
+    T d[M];
+    if (REACT == REACT_COEF) {
+      T cv[M];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        cv[i] = a.coef[base + (size_t)i * P + q];
+        d[i] = r[i];
+      }
+      point_block_solve<M, T>(c, dg, cv, d);
+    } else {
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        T s = T(0);
+#pragma unroll
+        for (int k = 0; k < M; ++k) s += c.Bi[i][k] * r[k];
+        d[i] = s;
+      }
+    }
+    T np = T(0), nd = T(0);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      out[base + (size_t)i * P + q] = u[i] + c.omega * d[i];
+      np += c.cout[i] * u[i];
+      nd += c.cout[i] * d[i];
+    }
+    prev = np;
+    dprev = nd;
+  }
+}
+
+// Residual r = f - A U (+ coupling of u0 into slab 0), optionally stored
+// as TO, with per-block partial sums of r^2.
+template <int M, typename T, typename TO, int REACT>
+__global__ __launch_bounds__(kBlock) void k_residual(const OpParams p, const SweepPtrs<T> a, int S,
+                                                     int tiles, int nblocks) {
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  const int tile = lb % tiles;
+  const int n0 = (lb / tiles) * S;
+  const int P = p.nx * p.ny;
+  const int q = tile * kBlock + threadIdx.x;
+  double ssq = 0.0;
+  if (q < P && n0 < p.N) {
+    const int n1 = min(n0 + S, p.N);
+    const Consts<M, T> c(p);
+    const bool twod = p.ny > 1;
+    const Nbr nb = neighbours(q % p.nx, q / p.nx, p.nx, p.ny, p.bc);
+    TO* __restrict__ out = static_cast<TO*>(a.out);
+    T prev = T(0);
+    if (n0 == 0) {
+      if (a.u0) prev = (T)a.u0[q];
+    } else if (a.U) {
+      const size_t b = (size_t)(n0 - 1) * M * P;
+#pragma unroll
+      for (int j = 0; j < M; ++j) prev += c.cout[j] * a.U[b + (size_t)j * P + q];
+    }
+    for (int n = n0; n < n1; ++n) {
+      const size_t base = (size_t)n * M * P;
+      T u[M], lap[M], r[M];
+      if (a.U) {
+        load_point<M, T>(a.U, base, P, q, nb, twod, c.cx, c.cy, u, lap);
+      } else {
+#pragma unroll
+        for (int m = 0; m < M; ++m) u[m] = lap[m] = T(0);
+      }
+      point_residual<M, T, REACT>(c, u, lap, a.coef, a.f, base, P, q, prev, r);
+      T np = T(0);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        if (out) out[base + (size_t)i * P + q] = (TO)r[i];
+        ssq += (double)r[i] * (double)r[i];
+        np += c.cout[i] * u[i];
+      }
+      prev = np;
+    }
+  }
+  if (a.part) {
+    const double t = block_sum(ssq);
+    if (threadIdx.x == 0) a.part[lb] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused residual + restriction.  One thread = one coarse point x a run of
+// coarse slabs.  For every fine slab of the run it evaluates the fine
+// residual at the (up to 3 x 3) fine points of the full-weighting stencil
+// [1 2 1]/4 per coarsened dimension (coarse X = fine 2X; periodic wrap or
+// Neumann reflection), then accumulates in time with the [1 2 1]/2 stencil
+// over slab end points (coarse J = fine 2J+1; the slab after the last is
+// absent).  The previous-slab coupling value of each fine point is carried
+// in registers from one fine slab to the next.
+template <int M, typename T, int REACT, bool SP, bool TM, bool TWOD>
+__global__ __launch_bounds__(kBlock) void k_restrict(const OpParams p, const SweepPtrs<T> a,
+                                                     int ncx, int ncy, int Nc, T* __restrict__ fc,
+                                                     int S, int tiles, int nblocks) {
+  constexpr int WX = SP ? 3 : 1;
+  constexpr int WY = (SP && TWOD) ? 3 : 1;
+  constexpr int NP = WX * WY;
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  const int tile = lb % tiles;
+  const int J0 = (lb / tiles) * S;
+  const int Pc = ncx * ncy;
+  const int qc = tile * kBlock + threadIdx.x;
+  if (qc >= Pc || J0 >= Nc) return;
+  const int J1 = min(J0 + S, Nc);
+  const Consts<M, T> c(p);
+  const int nx = p.nx, ny = p.ny, P = nx * ny;
+  const int X = qc % ncx, Y = qc / ncx;
+
+  int qf[NP];
+  Nbr nbf[NP];
+  T w[NP];
+  {
+    int xs[WX], ys[WY];
+    T wx[WX], wy[WY];
+    if (SP) {
+      xs[0] = nb_lo(2 * X, nx, p.bc); xs[WX / 2] = 2 * X; xs[WX - 1] = nb_hi(2 * X, nx, p.bc);
+      wx[0] = T(0.25); wx[WX / 2] = T(0.5); wx[WX - 1] = T(0.25);
+    } else {
+      xs[0] = X; wx[0] = T(1);
+    }
+    if (SP && TWOD) {
+      ys[0] = nb_lo(2 * Y, ny, p.bc); ys[WY / 2] = 2 * Y; ys[WY - 1] = nb_hi(2 * Y, ny, p.bc);
+      wy[0] = T(0.25); wy[WY / 2] = T(0.5); wy[WY - 1] = T(0.25);
+    } else {
+      ys[0] = Y; wy[0] = T(1);
+    }
+#pragma unroll
+    for (int j = 0; j < WY; ++j)
+#pragma unroll
+      for (int i = 0; i < WX; ++i) {
+        const int k = j * WX + i;
+        qf[k] = ys[j] * nx + xs[i];
+        nbf[k] = neighbours(xs[i], ys[j], nx, ny, p.bc);
+        w[k] = wx[i] * wy[j];
+      }
+  }
+  // fine slab range of this run
+  const int nlo = TM ? 2 * J0 : J0;
+  const int nhi = TM ? min(2 * J1, p.N - 1) : J1 - 1;
+  T prev[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    prev[k] = T(0);
+    if (nlo == 0) {
+      if (a.u0) prev[k] = (T)a.u0[qf[k]];
+    } else if (a.U) {
+      const size_t b = (size_t)(nlo - 1) * M * P;
+#pragma unroll
+      for (int j = 0; j < M; ++j) prev[k] += c.cout[j] * a.U[b + (size_t)j * P + qf[k]];
+    }
+  }
+  T acc[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) acc[i] = T(0);
+  const bool twod = ny > 1;  // the operator's dimension (TWOD only shapes the stencil)
+  for (int n = nlo; n <= nhi; ++n) {
+    const size_t base = (size_t)n * M * P;
+    T rs[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) rs[i] = T(0);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      T u[M], lap[M], r[M];
+      if (a.U) {
+        load_point<M, T>(a.U, base, P, qf[k], nbf[k], twod, c.cx, c.cy, u, lap);
+      } else {
+#pragma unroll
+        for (int m = 0; m < M; ++m) u[m] = lap[m] = T(0);
+      }
+      point_residual<M, T, REACT>(c, u, lap, a.coef, a.f, base, P, qf[k], prev[k], r);
+      T np = T(0);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        rs[i] += w[k] * r[i];
+        np += c.cout[i] * u[i];
+      }
+      prev[k] = np;
+    }
+    if (!TM) {
+      const size_t cb = (size_t)n * M * Pc;
+#pragma unroll
+      for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = rs[i];
+    } else if (n & 1) {  // n = 2J + 1: centre of coarse slab J
+      const int J = n >> 1;
+#pragma unroll
+      for (int i = 0; i < M; ++i) acc[i] += rs[i];
+      if (J == Nc - 1) {  // the fine slab 2J + 2 does not exist
+        const size_t cb = (size_t)J * M * Pc;
+#pragma unroll
+        for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = acc[i];
+      }
+    } else {  // n = 2J: right neighbour of coarse J - 1, left neighbour of J
+      const int J = n >> 1;
+      if (J > J0) {
+        const size_t cb = (size_t)(J - 1) * M * Pc;
+#pragma unroll
+        for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = acc[i] + T(0.5) * rs[i];
+      }
+#pragma unroll
+      for (int i = 0; i < M; ++i) acc[i] = T(0.5) * rs[i];
+    }
+  }
+}
+
+// U_out = U_in + P e_c: linear interpolation in space (fine 2X = coarse X,
+// fine 2X+1 = mean of coarse X and X+1) and in slab end points (fine 2J+1 =
+// coarse J, fine 2J = mean of coarse J-1 and J, coarse -1 = 0).
+template <int M, typename T, bool SP, bool TM, bool TWOD>
+__global__ __launch_bounds__(kBlock) void k_prolong(const OpParams p, int ncx, int ncy, int Nc,
+                                                    const T* __restrict__ ec,
+                                                    const T* __restrict__ Uin, T* __restrict__ Uout,
+                                                    int S, int tiles, int nblocks) {
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  const int tile = lb % tiles;
+  const int n0 = (lb / tiles) * S;
+  const int nx = p.nx, ny = p.ny, P = nx * ny;
+  const int q = tile * kBlock + threadIdx.x;
+  if (q >= P || n0 >= p.N) return;
+  const int n1 = min(n0 + S, p.N);
+  const int Pc = ncx * ncy;
+  const int x = q % nx, y = q / nx;
+  int cq[4];
+  T cw[4];
+  int ncq = 0;
+  {
+    int xs[2], ys[2];
+    T wx[2], wy[2];
+    int nxs = 1, nys = 1;
+    if (SP) {
+      if (x & 1) {
+        xs[0] = x >> 1; xs[1] = ((x >> 1) + 1) % ncx; wx[0] = wx[1] = T(0.5); nxs = 2;
+        if (p.bc != 0) xs[1] = (x >> 1) + 1;
+      } else {
+        xs[0] = x >> 1; wx[0] = T(1);
+      }
+      if (TWOD) {
+        if (y & 1) {
+          ys[0] = y >> 1; ys[1] = ((y >> 1) + 1) % ncy; wy[0] = wy[1] = T(0.5); nys = 2;
+          if (p.bc != 0) ys[1] = (y >> 1) + 1;
+        } else {
+          ys[0] = y >> 1; wy[0] = T(1);
+        }
+      } else {
+        ys[0] = y; wy[0] = T(1);
+      }
+    } else {
+      xs[0] = x; ys[0] = y; wx[0] = wy[0] = T(1);
+    }
+    for (int j = 0; j < nys; ++j)
+      for (int i = 0; i < nxs; ++i) {
+        cq[ncq] = ys[j] * ncx + xs[i];
+        cw[ncq] = wx[i] * wy[j];
+        ++ncq;
+      }
+  }
+  for (int n = n0; n < n1; ++n) {
+    int js[2];
+    T wt[2];
+    int nt;
+    if (!TM) {
+      js[0] = n; wt[0] = T(1); nt = 1;
+    } else if (n & 1) {
+      js[0] = n >> 1; wt[0] = T(1); nt = 1;
+    } else {
+      const int J = n >> 1;
+      js[0] = J; wt[0] = T(0.5); nt = 1;
+      if (J > 0) { js[1] = J - 1; wt[1] = T(0.5); nt = 2; }
+    }
+    const size_t base = (size_t)n * M * P;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      T e = T(0);
+      for (int t = 0; t < nt; ++t) {
+        const T* Ec = ec + (size_t)js[t] * M * Pc + (size_t)i * Pc;
+        T s = T(0);
+        for (int k = 0; k < ncq; ++k) s += cw[k] * Ec[cq[k]];
+        e += wt[t] * s;
+      }
+      const size_t o = base + (size_t)i * P + q;
+      Uout[o] = (Uin ? Uin[o] : T(0)) + e;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest level: U_n = Ainv (f_n + cin (x) (cout . U_{n-1})) slab after slab
+// in one workgroup; Ainv is the inverse of the (constant) slab matrix.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_solve(const OpParams p, const double* __restrict__ Ainv,
+                                                         const T* __restrict__ f,
+                                                         const double* __restrict__ u0,
+                                                         T* __restrict__ U) {
+  extern __shared__ double sm[];
+  __shared__ double s_cin[kMaxM], s_cout[kMaxM];
+  const int P = p.nx * p.ny, M = p.M, K = M * P;
+  double* v = sm;
+  double* xv = sm + K;
+  double* prv = xv + K;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kMaxM; ++i) { s_cin[i] = p.cin[i]; s_cout[i] = p.cout[i]; }
+  }
+  for (int q = threadIdx.x; q < P; q += kBlock) prv[q] = u0 ? u0[q] : 0.0;
+  __syncthreads();
+  for (int n = 0; n < p.N; ++n) {
+    for (int k = threadIdx.x; k < K; k += kBlock)
+      v[k] = (f ? (double)f[(size_t)n * K + k] : 0.0) + s_cin[k / P] * prv[k % P];
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+      const double* row = Ainv + (size_t)k * K;
+      double s = 0.0;
+      for (int j = 0; j < K; ++j) s += row[j] * v[j];
+      xv[k] = s;
+      U[(size_t)n * K + k] = (T)s;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < P; q += kBlock) {
+      double s = 0.0;
+      for (int j = 0; j < M; ++j) s += s_cout[j] * xv[j * P + q];
+      prv[q] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// Coarsest level with a per-DOF reaction coefficient: every slab has its own
+// matrix A_n = K (x) I + diag(db) (x) (-Lap) + diag(db_i coef_{n,i}(q)), built
+// in the scratch buffer, LU-factored with partial pivoting and solved, slab
+// after slab, in one workgroup.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_solve_coef(const OpParams p, const T* __restrict__ coef,
+                                                              double* __restrict__ A,
+                                                              const T* __restrict__ f,
+                                                              const double* __restrict__ u0,
+                                                              T* __restrict__ U) {
+  extern __shared__ double sm[];
+  __shared__ double s_cin[kMaxM], s_cout[kMaxM], s_db[kMaxM], s_K[kMaxM * kMaxM];
+  __shared__ int s_piv;
+  const int nx = p.nx, ny = p.ny, P = nx * ny, M = p.M, K = M * P;
+  double* v = sm;
+  double* prv = sm + K;
+  int* perm = reinterpret_cast<int*>(prv + P);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kMaxM; ++i) { s_cin[i] = p.cin[i]; s_cout[i] = p.cout[i]; s_db[i] = p.db[i]; }
+#pragma unroll
+    for (int i = 0; i < kMaxM * kMaxM; ++i) s_K[i] = p.K[i];
+  }
+  for (int q = threadIdx.x; q < P; q += kBlock) prv[q] = u0 ? u0[q] : 0.0;
+  __syncthreads();
+  for (int n = 0; n < p.N; ++n) {
+    // assemble
+    for (size_t e = threadIdx.x; e < (size_t)K * K; e += kBlock) {
+      const int r = (int)(e / K), cI = (int)(e % K);
+      const int i = r / P, q = r % P, j = cI / P, q2 = cI % P;
+      double val = (q == q2) ? s_K[i * M + j] : 0.0;
+      if (i == j) {
+        const int x = q % nx, y = q / nx;
+        double l = 0.0;  // (-Lap)[q][q2] scaled
+        if (q == q2) l += 2.0 * p.cx + (ny > 1 ? 2.0 * p.cy : 0.0);
+        if (q2 == y * nx + nb_lo(x, nx, p.bc)) l -= p.cx;
+        if (q2 == y * nx + nb_hi(x, nx, p.bc)) l -= p.cx;
+        if (ny > 1) {
+          if (q2 == nb_lo(y, ny, p.bc) * nx + x) l -= p.cy;
+          if (q2 == nb_hi(y, ny, p.bc) * nx + x) l -= p.cy;
+        }
+        if (q == q2) l += (double)coef[(size_t)n * K + r];
+        val += s_db[i] * l;
+      }
+      A[e] = val;
+    }
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+      v[k] = (f ? (double)f[(size_t)n * K + k] : 0.0) + s_cin[k / P] * prv[k % P];
+      perm[k] = k;
+    }
+    __syncthreads();
+    // LU with partial pivoting (row swaps applied to v as well)
+    for (int k = 0; k < K; ++k) {
+      if (threadIdx.x == 0) {
+        int pr = k;
+        double best = fabs(A[(size_t)k * K + k]);
+        for (int r = k + 1; r < K; ++r) {
+          const double t = fabs(A[(size_t)r * K + k]);
+          if (t > best) { best = t; pr = r; }
+        }
+        s_piv = pr;
+      }
+      __syncthreads();
+      const int pr = s_piv;
+      if (pr != k) {
+        for (int j = threadIdx.x; j < K; j += kBlock) {
+          const double t = A[(size_t)k * K + j];
+          A[(size_t)k * K + j] = A[(size_t)pr * K + j];
+          A[(size_t)pr * K + j] = t;
+        }
+        if (threadIdx.x == 0) {
+          const double t = v[k]; v[k] = v[pr]; v[pr] = t;
+        }
+      }
+      __syncthreads();
+      const double piv = A[(size_t)k * K + k];
+      for (int r = k + 1 + threadIdx.x; r < K; r += kBlock) {
+        const double l = A[(size_t)r * K + k] / piv;
+        A[(size_t)r * K + k] = l;
+        for (int j = k + 1; j < K; ++j) A[(size_t)r * K + j] -= l * A[(size_t)k * K + j];
+        v[r] -= l * v[k];
+      }
+      __syncthreads();
+    }
+    // back substitution (serial in k, parallel dot products would need more syncs)
+    if (threadIdx.x == 0) {
+      for (int k = K - 1; k >= 0; --k) {
+        double s = v[k];
+        for (int j = k + 1; j < K; ++j) s -= A[(size_t)k * K + j] * v[j];
+        v[k] = s / A[(size_t)k * K + k];
+      }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += kBlock) U[(size_t)n * K + k] = (T)v[k];
+    for (int q = threadIdx.x; q < P; q += kBlock) {
+      double s = 0.0;
+      for (int j = 0; j < M; ++j) s += s_cout[j] * v[j * P + q];
+      prv[q] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ part, int n,
+                                                         double* __restrict__ out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) s += part[i];
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sumsq(const double* __restrict__ x, size_t n,
+                                                  double* __restrict__ part) {
+  double s = 0.0;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) s += x[i] * x[i];
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+template <typename TX, typename TY>
+__global__ __launch_bounds__(kBlock) void k_axpy_cast(size_t n, const TX* __restrict__ x, double alpha,
+                                                      TY* __restrict__ y, int acc) {
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double v = alpha * (double)x[i];
+    y[i] = acc ? (TY)((double)y[i] + v) : (TY)v;
+  }
+}
+
+template <typename TE>
+__global__ __launch_bounds__(kBlock) void k_update(size_t n, double* __restrict__ U,
+                                                   const TE* __restrict__ e,
+                                                   const double* __restrict__ scale) {
+  const double s = scale ? scale[0] : 1.0;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+    U[i] += s * (double)e[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_newton_coef(size_t n, const double* __restrict__ U,
+                                                        double gamma, T* __restrict__ c) {
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double u = U[i];
+    c[i] = (T)(gamma * (3.0 * u * u - 1.0));
+  }
+}
+
+// Coarse coefficient: weighted mean of the fine coefficient over the
+// full-weighting neighbourhood in space and the [1 2 1] neighbourhood of
+// slab end points in time (weights normalized to sum to one).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict_coef(const OpParams p, int sp, int tm, int ncx, int ncy,
+                                                          int Nc, const T* __restrict__ cf,
+                                                          T* __restrict__ cc) {
+  const int Pc = ncx * ncy;
+  const size_t total = (size_t)Nc * p.M * Pc;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  const int nx = p.nx, ny = p.ny, P = nx * ny, M = p.M;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += stride) {
+    const int qc = (int)(e % Pc);
+    const int i = (int)((e / Pc) % M);
+    const int J = (int)(e / ((size_t)Pc * M));
+    const int X = qc % ncx, Y = qc / ncx;
+    int xs[3], ys[3], ns[3];
+    double wx[3], wy[3], wt[3];
+    int nxs = 1, nys = 1, nts = 1;
+    if (sp) {
+      xs[0] = nb_lo(2 * X, nx, p.bc); xs[1] = 2 * X; xs[2] = nb_hi(2 * X, nx, p.bc);
+      wx[0] = 0.25; wx[1] = 0.5; wx[2] = 0.25; nxs = 3;
+      if (ny > 1) {
+        ys[0] = nb_lo(2 * Y, ny, p.bc); ys[1] = 2 * Y; ys[2] = nb_hi(2 * Y, ny, p.bc);
+        wy[0] = 0.25; wy[1] = 0.5; wy[2] = 0.25; nys = 3;
+      } else {
+        ys[0] = Y; wy[0] = 1.0;
+      }
+    } else {
+      xs[0] = X; ys[0] = Y; wx[0] = wy[0] = 1.0;
+    }
+    if (tm) {
+      ns[0] = 2 * J; ns[1] = 2 * J + 1; wt[0] = 0.25; wt[1] = 0.5; nts = 2;
+      if (2 * J + 2 < p.N) { ns[2] = 2 * J + 2; wt[2] = 0.25; nts = 3; }
+    } else {
+      ns[0] = J; wt[0] = 1.0;
+    }
+    double s = 0.0, ws = 0.0;
+    for (int t = 0; t < nts; ++t)
+      for (int b = 0; b < nys; ++b)
+        for (int a = 0; a < nxs; ++a) {
+          const double w = wt[t] * wy[b] * wx[a];
+          s += w * (double)cf[((size_t)ns[t] * M + i) * P + (size_t)ys[b] * nx + xs[a]];
+          ws += w;
+        }
+    cc[e] = (T)(s / ws);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reverse_slabs(const double* __restrict__ in,
+                                                          double* __restrict__ out, int N,
+                                                          size_t slab) {
+  const size_t total = (size_t)N * slab;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += stride) {
+    const size_t n = e / slab, r = e % slab;
+    out[(size_t)(N - 1 - n) * slab + r] = in[e];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_node_combine(const double* __restrict__ lam, const double* w,
+                                                         int M, size_t P, double* __restrict__ out) {
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t q = (size_t)blockIdx.x * kBlock + threadIdx.x; q < P; q += stride) {
+    double s = 0.0;
+    for (int i = 0; i < M; ++i) s += w[i] * lam[(size_t)i * P + q];
+    out[q] = s;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_grad_nu(const OpParams p, const double* __restrict__ U,
+                                                    const double* __restrict__ lam, double* __restrict__ part) {
+  __shared__ double s_db[kMaxM];
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kMaxM; ++i) s_db[i] = p.db[i];
+  }
+  __syncthreads();
+  const int nx = p.nx, ny = p.ny, P = nx * ny, M = p.M, N = p.N;
+  const size_t total = (size_t)N * M * P;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  double acc = 0.0;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += stride) {
+    const int q = (int)(e % P);
+    const int i = (int)((e / P) % M);
+    const int n = (int)(e / ((size_t)P * M));
+    const int x = q % nx, y = q / nx;
+    const double* Um = U + ((size_t)n * M + i) * P;
+    const double c = Um[q];
+    double l = p.cx * (Um[y * nx + nb_lo(x, nx, p.bc)] + Um[y * nx + nb_hi(x, nx, p.bc)] - 2.0 * c);
+    if (ny > 1) l += p.cy * (Um[nb_lo(y, ny, p.bc) * nx + x] + Um[nb_hi(y, ny, p.bc) * nx + x] - 2.0 * c);
+    acc += lam[((size_t)(N - 1 - n) * M + i) * P + q] * s_db[i] * l;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+int grid_for(size_t n) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers: dispatch on M and on the reaction mode.
+#define STMG_DISPATCH_M(MACRO) \
+  switch (p.M) {               \
+    case 1: MACRO(1); break;   \
+    case 2: MACRO(2); break;   \
+    case 3: MACRO(3); break;   \
+    case 4: MACRO(4); break;   \
+    case 5: MACRO(5); break;   \
+    case 6: MACRO(6); break;   \
+    case 7: MACRO(7); break;   \
+    case 8: MACRO(8); break;   \
+    default: return hipErrorInvalidValue; \
+  }
+
+template <typename T>
+hipError_t launch_smooth(const OpParams& p, int react, const SweepPtrs<T>& a, int chunk,
+                         hipStream_t s) {
+  const int P = p.nx * p.ny;
+  const int tiles = (P + kBlock - 1) / kBlock;
+  const int chunks = (p.N + chunk - 1) / chunk;
+  const int nb = tiles * chunks;
+#define L(MM)                                                                                   \
+  if (react == REACT_COEF)                                                                      \
+    hipLaunchKernelGGL((k_smooth<MM, T, REACT_COEF>), dim3(nb), dim3(kBlock), 0, s, p, a, chunk, \
+                       tiles, nb);                                                              \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_smooth<MM, T, REACT_CONST>), dim3(nb), dim3(kBlock), 0, s, p, a,       \
+                       chunk, tiles, nb);
+  STMG_DISPATCH_M(L)
+#undef L
+  return hipGetLastError();
+}
+
+template <typename T, typename TO>
+hipError_t launch_residual(const OpParams& p, int react, const SweepPtrs<T>& a, int spb,
+                           int* nparts, hipStream_t s) {
+  const int P = p.nx * p.ny;
+  const int tiles = (P + kBlock - 1) / kBlock;
+  const int chunks = (p.N + spb - 1) / spb;
+  const int nb = tiles * chunks;
+  if (nparts) *nparts = nb;
+#define L(MM)                                                                                    \
+  if (react == REACT_COEF)                                                                       \
+    hipLaunchKernelGGL((k_residual<MM, T, TO, REACT_COEF>), dim3(nb), dim3(kBlock), 0, s, p, a,   \
+                       spb, tiles, nb);                                                          \
+  else if (react == REACT_AC)                                                                    \
+    hipLaunchKernelGGL((k_residual<MM, T, TO, REACT_AC>), dim3(nb), dim3(kBlock), 0, s, p, a,     \
+                       spb, tiles, nb);                                                          \
+  else                                                                                           \
+    hipLaunchKernelGGL((k_residual<MM, T, TO, REACT_CONST>), dim3(nb), dim3(kBlock), 0, s, p, a,  \
+                       spb, tiles, nb);
+  STMG_DISPATCH_M(L)
+#undef L
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict_residual(const OpParams& p, int react, const SweepPtrs<T>& a,
+                                    bool space, bool time, int ncx, int ncy, int Nc, T* fc,
+                                    int spb, hipStream_t s) {
+  const int Pc = ncx * ncy;
+  const int tiles = (Pc + kBlock - 1) / kBlock;
+  const int chunks = (Nc + spb - 1) / spb;
+  const int nb = tiles * chunks;
+  const bool twod = p.ny > 1;
+#define LR(MM, RE, SPc, TMc, TWc)                                                             \
+  hipLaunchKernelGGL((k_restrict<MM, T, RE, SPc, TMc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, a, \
+                     ncx, ncy, Nc, fc, spb, tiles, nb)
+#define LRE(MM, RE)                                                   \
+  if (space && time) {                                                \
+    if (twod) LR(MM, RE, true, true, true); else LR(MM, RE, true, true, false);   \
+  } else if (space) {                                                 \
+    if (twod) LR(MM, RE, true, false, true); else LR(MM, RE, true, false, false); \
+  } else if (time) {                                                  \
+    LR(MM, RE, false, true, false);                                   \
+  } else {                                                            \
+    LR(MM, RE, false, false, false);                                  \
+  }
+#define L(MM)                                         \
+  if (react == REACT_COEF) { LRE(MM, REACT_COEF) }    \
+  else { LRE(MM, REACT_CONST) }
+  STMG_DISPATCH_M(L)
+#undef L
+#undef LRE
+#undef LR
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong(const OpParams& p, bool space, bool time, int ncx, int ncy, int Nc,
+                          const T* ec, const T* Uin, T* Uout, int spb, hipStream_t s) {
+  const int P = p.nx * p.ny;
+  const int tiles = (P + kBlock - 1) / kBlock;
+  const int chunks = (p.N + spb - 1) / spb;
+  const int nb = tiles * chunks;
+  const bool twod = p.ny > 1;
+#define LP(MM, SPc, TMc, TWc)                                                                  \
+  hipLaunchKernelGGL((k_prolong<MM, T, SPc, TMc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, ncx, ncy, \
+                     Nc, ec, Uin, Uout, spb, tiles, nb)
+#define L(MM)                                                            \
+  if (space && time) {                                                   \
+    if (twod) LP(MM, true, true, true); else LP(MM, true, true, false);  \
+  } else if (space) {                                                    \
+    if (twod) LP(MM, true, false, true); else LP(MM, true, false, false); \
+  } else if (time) {                                                     \
+    LP(MM, false, true, false);                                          \
+  } else {                                                               \
+    LP(MM, false, false, false);                                         \
+  }
+  STMG_DISPATCH_M(L)
+#undef L
+#undef LP
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse_solve(const OpParams& p, const double* Ainv, const T* f,
+                               const double* u0, T* U, hipStream_t s) {
+  const int P = p.nx * p.ny;
+  const size_t shm = (size_t)(2 * p.M * P + P) * sizeof(double);
+  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(kBlock), shm, s, p, Ainv, f, u0, U);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse_solve_coef(const OpParams& p, const T* coef, double* scratch, const T* f,
+                                    const double* u0, T* U, hipStream_t s) {
+  const int P = p.nx * p.ny;
+  const int K = p.M * P;
+  const size_t shm = (size_t)(K + P) * sizeof(double) + (size_t)K * sizeof(int);
+  hipLaunchKernelGGL((k_coarse_solve_coef<T>), dim3(1), dim3(kBlock), shm, s, p, coef, scratch, f,
+                     u0, U);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double* part, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, part, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const double* x, size_t n, double* part, int* nparts, hipStream_t s) {
+  const int g = grid_for(n) > 1024 ? 1024 : grid_for(n);
+  *nparts = g;
+  hipLaunchKernelGGL(k_sumsq, dim3(g), dim3(kBlock), 0, s, x, n, part);
+  return hipGetLastError();
+}
+
+template <typename TX, typename TY>
+hipError_t launch_axpy_cast(size_t n, const TX* x, double alpha, TY* y, bool acc, hipStream_t s) {
+  hipLaunchKernelGGL((k_axpy_cast<TX, TY>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, alpha, y,
+                     acc ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <typename TE>
+hipError_t launch_update(size_t n, double* U, const TE* e, const double* scale, hipStream_t s) {
+  hipLaunchKernelGGL((k_update<TE>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, U, e, scale);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_newton_coef(size_t n, const double* U, double gamma, T* coef, hipStream_t s) {
+  hipLaunchKernelGGL((k_newton_coef<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, U, gamma, coef);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict_coef(const OpParams& fine, bool space, bool time, int ncx, int ncy,
+                                int Nc, const T* cf, T* cc, hipStream_t s) {
+  const size_t total = (size_t)Nc * fine.M * ncx * ncy;
+  hipLaunchKernelGGL((k_restrict_coef<T>), dim3(grid_for(total)), dim3(kBlock), 0, s, fine,
+                     space ? 1 : 0, time ? 1 : 0, ncx, ncy, Nc, cf, cc);
+  return hipGetLastError();
+}
+
+hipError_t launch_reverse_slabs(const double* in, double* out, int N, int M, size_t P,
+                                hipStream_t s) {
+  const size_t slab = (size_t)M * P;
+  hipLaunchKernelGGL(k_reverse_slabs, dim3(grid_for((size_t)N * slab)), dim3(kBlock), 0, s, in, out,
+                     N, slab);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_combine(const double* lam, const double* w, int M, size_t P, double* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_node_combine, dim3(grid_for(P)), dim3(kBlock), 0, s, lam, w, M, P, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_nu(const OpParams& p, const double* U, const double* lam, double* part,
+                          int* nparts, hipStream_t s) {
+  const size_t total = (size_t)p.N * p.M * p.nx * p.ny;
+  int g = grid_for(total);
+  if (g > 1024) g = 1024;
+  *nparts = g;
+  hipLaunchKernelGGL(k_grad_nu, dim3(g), dim3(kBlock), 0, s, p, U, lam, part);
+  return hipGetLastError();
+}
+
+// explicit instantiations
+template hipError_t launch_smooth<double>(const OpParams&, int, const SweepPtrs<double>&, int, hipStream_t);
+template hipError_t launch_smooth<float>(const OpParams&, int, const SweepPtrs<float>&, int, hipStream_t);
+template hipError_t launch_residual<double, double>(const OpParams&, int, const SweepPtrs<double>&, int, int*, hipStream_t);
+template hipError_t launch_residual<double, float>(const OpParams&, int, const SweepPtrs<double>&, int, int*, hipStream_t);
+template hipError_t launch_residual<float, float>(const OpParams&, int, const SweepPtrs<float>&, int, int*, hipStream_t);
+template hipError_t launch_restrict_residual<double>(const OpParams&, int, const SweepPtrs<double>&, bool, bool, int, int, int, double*, int, hipStream_t);
+template hipError_t launch_restrict_residual<float>(const OpParams&, int, const SweepPtrs<float>&, bool, bool, int, int, int, float*, int, hipStream_t);
+template hipError_t launch_prolong<double>(const OpParams&, bool, bool, int, int, int, const double*, const double*, double*, int, hipStream_t);
+template hipError_t launch_prolong<float>(const OpParams&, bool, bool, int, int, int, const float*, const float*, float*, int, hipStream_t);
+template hipError_t launch_coarse_solve<double>(const OpParams&, const double*, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_coarse_solve<float>(const OpParams&, const double*, const float*, const double*, float*, hipStream_t);
+template hipError_t launch_coarse_solve_coef<double>(const OpParams&, const double*, double*, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_coarse_solve_coef<float>(const OpParams&, const float*, double*, const float*, const double*, float*, hipStream_t);
+template hipError_t launch_axpy_cast<double, float>(size_t, const double*, double, float*, bool, hipStream_t);
+template hipError_t launch_axpy_cast<float, double>(size_t, const float*, double, double*, bool, hipStream_t);
+template hipError_t launch_axpy_cast<double, double>(size_t, const double*, double, double*, bool, hipStream_t);
+template hipError_t launch_update<float>(size_t, double*, const float*, const double*, hipStream_t);
+template hipError_t launch_update<double>(size_t, double*, const double*, const double*, hipStream_t);
+template hipError_t launch_newton_coef<double>(size_t, const double*, double, double*, hipStream_t);
+template hipError_t launch_newton_coef<float>(size_t, const double*, double, float*, hipStream_t);
+template hipError_t launch_restrict_coef<double>(const OpParams&, bool, bool, int, int, int, const double*, double*, hipStream_t);
+template hipError_t launch_restrict_coef<float>(const OpParams&, bool, bool, int, int, int, const float*, float*, hipStream_t);
+
+}  // namespace stmg

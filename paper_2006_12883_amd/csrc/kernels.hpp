@@ -1,0 +1,124 @@
+// Kernel parameter blocks and launch wrappers (internal to libstmg).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace stmg {
+
+constexpr int kMaxM = 8;
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
+
+// One level's operator, passed by value as a kernel argument.
+//   (A U)_{n,i} = sum_j K[i][j] U_{n,j} + db_i (-(cx D_xx + cy D_yy) U_{n,i} + react)
+//                 - cin_i * (sum_j cout_j U_{n-1,j})
+// D_xx u = u[x-1] + u[x+1] - 2 u[x] (periodic wrap or Neumann reflection).
+// Forward problem: K = Kq, cin = l(0), cout = e_M.  Transposed problem stored
+// backward in time: K = Kq^T, cin = e_M, cout = l(0).
+struct OpParams {
+  int M;
+  int nx, ny;      // grid points of this level (ny = 1 in 1D)
+  int N;           // slabs
+  int bc;          // 0 periodic, 1 Neumann
+  int pad_;
+  double cx, cy;   // nu / hx^2, nu / hy^2 (cy = 0 in 1D)
+  double lam;      // constant linear reaction rate
+  double gamma;    // Allen-Cahn intensity
+  double omega;    // smoother damping
+  double K[kMaxM * kMaxM];
+  double db[kMaxM];    // dt * b_i
+  double cin[kMaxM];
+  double cout[kMaxM];
+  double Binv[kMaxM * kMaxM];  // (K + diag(db) (2cx + 2cy + lam))^{-1}
+};
+
+// Reaction modes of the operator kernels.
+enum { REACT_CONST = 0, REACT_COEF = 1, REACT_AC = 2 };
+
+template <typename T>
+struct SweepPtrs {
+  const T* U;        // current iterate; nullptr means U = 0
+  const T* f;        // explicit right-hand side; nullptr means none
+  const double* u0;  // value entering slab 0 through the coupling; may be null
+  const T* coef;     // REACT_COEF: per-DOF reaction coefficient
+  void* out;         // smoother: new iterate (T); residual: r (type TO), may be null
+  double* part;      // residual: per-block partial sums of r^2, may be null
+};
+
+// Launchers return hipSuccess or the launch error.
+template <typename T>
+hipError_t launch_smooth(const OpParams& p, int react, const SweepPtrs<T>& a,
+                         int chunk, hipStream_t s);
+
+// Residual r = f + (u0 coupling) - A U; out type TO (double or float).
+template <typename T, typename TO>
+hipError_t launch_residual(const OpParams& p, int react, const SweepPtrs<T>& a,
+                           int slabs_per_block, int* nparts, hipStream_t s);
+
+// f_c = R (f - A U) on the fine level described by p; the coarse level has
+// ncx x ncy points and Nc slabs; space/time select the coarsening.
+template <typename T>
+hipError_t launch_restrict_residual(const OpParams& p, int react, const SweepPtrs<T>& a,
+                                    bool space, bool time, int ncx, int ncy, int Nc,
+                                    T* fc, int slabs_per_block, hipStream_t s);
+
+// U_out = U_in + P e_c (U_in may be null: assign).  Fine level p.
+template <typename T>
+hipError_t launch_prolong(const OpParams& p, bool space, bool time, int ncx, int ncy,
+                          int Nc, const T* ec, const T* Uin, T* Uout, int slabs_per_block,
+                          hipStream_t s);
+
+// Exact solve of the block lower-bidiagonal coarsest system:
+// U_n = Ainv (f_n + cin (x) (cout . U_{n-1}))   (u0 enters slab 0 if given).
+template <typename T>
+hipError_t launch_coarse_solve(const OpParams& p, const double* Ainv, const T* f,
+                               const double* u0, T* U, hipStream_t s);
+
+// Coarsest solve with a different slab matrix per slab: the K x K slab
+// matrices (K = M nx ny) are built from the per-DOF coefficient and factored
+// in the kernel (dense LU, one workgroup), then the slabs are solved in order.
+template <typename T>
+hipError_t launch_coarse_solve_coef(const OpParams& p, const T* coef, double* scratch,
+                                    const T* f, const double* u0, T* U, hipStream_t s);
+
+// out[0] = sum of part[0..n) in a fixed order (one workgroup).
+hipError_t launch_sum_partials(const double* part, int n, double* out, hipStream_t s);
+
+// Sum of squares of a double array into per-block partials.
+hipError_t launch_sumsq(const double* x, size_t n, double* part, int* nparts, hipStream_t s);
+
+// y[i] = (TY) (alpha * x[i])
+template <typename TX, typename TY>
+hipError_t launch_axpy_cast(size_t n, const TX* x, double alpha, TY* y, bool accumulate,
+                            hipStream_t s);
+
+// U64 += e32 (or e64)
+template <typename TE>
+hipError_t launch_update(size_t n, double* U, const TE* e, const double* scale, hipStream_t s);
+
+// Newton coefficient c = gamma (3 U^2 - 1) (the derivative of the
+// Allen-Cahn term gamma (u^3 - u)), written as T.
+template <typename T>
+hipError_t launch_newton_coef(size_t n, const double* U, double gamma, T* coef, hipStream_t s);
+
+// Coefficient on the next coarser level: average of the fine values
+// (full-weighting pattern normalized to unit sum in space and time).
+template <typename T>
+hipError_t launch_restrict_coef(const OpParams& fine, bool space, bool time, int ncx, int ncy,
+                                int Nc, const T* cf, T* cc, hipStream_t s);
+
+// Reverse the slab order of a [N][M][P] array (out-of-place).
+hipError_t launch_reverse_slabs(const double* in, double* out, int N, int M, size_t P,
+                                hipStream_t s);
+
+// grad_u0[q] = sum_i w_i lam_slab[i][q]
+hipError_t launch_node_combine(const double* lam_slab, const double* w, int M, size_t P,
+                               double* out, hipStream_t s);
+
+// Per-block partials of sum_{n,i,q} lam[N-1-n][i][q] * db_i * (Lap U_{n,i})(q) with
+// lam stored backward in time (adjoint) and U forward.
+hipError_t launch_grad_nu(const OpParams& p, const double* U, const double* lam_rev,
+                          double* part, int* nparts, hipStream_t s);
+
+}  // namespace stmg

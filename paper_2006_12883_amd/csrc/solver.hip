@@ -1,0 +1,590 @@
+// Solver setup, V-cycle and solve drivers (host side of libstmg).
+#include "solver.hpp"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace stmg {
+
+namespace {
+
+constexpr int kResidSlabs = 8;   // slabs per thread in residual sweeps
+constexpr int kTransferSlabs = 4;
+
+// Elements -> points per dimension.
+int points(int e, int bc) { return bc == STMG_BC_PERIODIC ? e : e + 1; }
+
+}  // namespace
+
+#define HIP_TRY(expr)                                                            \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      set_error(std::string("HIP error in ") + #expr + ": " + hipGetErrorString(e_)); \
+      return e_;                                                                 \
+    }                                                                            \
+  } while (0)
+
+#define HIP_CHECK(expr)                                                          \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      set_error(std::string("HIP error in ") + #expr + ": " + hipGetErrorString(e_)); \
+      return STMG_EHIP;                                                          \
+    }                                                                            \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Hierarchy.  Semi-coarsening by the anisotropy ratio mu = nu dt / h^2
+// (Sec. 3.2: coarsen in time when mu << 1 and in space when mu >> 1), with the
+// SMG (space only) and STMG (space and time) variants of Sec. 4.2.
+int Solver::build(const stmg_problem* p, const stmg_options* o) {
+  prob = *p;
+  opt = *o;
+  if (p->dim != 1 && p->dim != 2) { set_error("dim must be 1 or 2"); return STMG_EINVAL; }
+  if (p->M < 1 || p->M > kMaxM) { set_error("M must be in 1..8"); return STMG_EINVAL; }
+  if (p->N < 1) { set_error("N must be >= 1"); return STMG_EINVAL; }
+  if (!(p->dt > 0.0)) { set_error("dt must be > 0"); return STMG_EINVAL; }
+  if (!(p->nu > 0.0)) { set_error("nu must be > 0"); return STMG_EINVAL; }
+  if (p->bc != STMG_BC_PERIODIC && p->bc != STMG_BC_NEUMANN) { set_error("bad bc"); return STMG_EINVAL; }
+  if (p->reaction != STMG_REACT_LINEAR && p->reaction != STMG_REACT_ALLEN_CAHN) {
+    set_error("bad reaction");
+    return STMG_EINVAL;
+  }
+  const int ex = p->nx[0], ey = p->dim == 2 ? p->nx[1] : 1;
+  if (points(ex, p->bc) < 3 || (p->dim == 2 && points(ey, p->bc) < 3)) {
+    set_error("need at least 3 grid points per dimension");
+    return STMG_EINVAL;
+  }
+  if (!(p->length[0] > 0.0) || (p->dim == 2 && !(p->length[1] > 0.0))) {
+    set_error("length must be > 0");
+    return STMG_EINVAL;
+  }
+  if (o->chunk < 1 || o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1 ||
+      o->max_levels < 1 || o->max_cycles < 1 || !(o->rtol > 0.0) || !(o->omega > 0.0)) {
+    set_error("invalid options");
+    return STMG_EINVAL;
+  }
+  if (o->precision != STMG_PREC_FP64 && o->precision != STMG_PREC_MIXED) {
+    set_error("bad precision");
+    return STMG_EINVAL;
+  }
+  allen_cahn = p->reaction == STMG_REACT_ALLEN_CAHN;
+  mixed = o->precision == STMG_PREC_MIXED;
+  if (!radau_tables(p->M, &tab)) { set_error("Radau table construction failed"); return STMG_EINVAL; }
+
+  const int M = p->M;
+  const bool twod = p->dim == 2;
+  lv.clear();
+  Level L;
+  L.ex = ex;
+  L.ey = ey;
+  L.nx = points(ex, p->bc);
+  L.ny = twod ? points(ey, p->bc) : 1;
+  L.N = p->N;
+  L.dt = p->dt;
+  lv.push_back(L);
+  while (static_cast<int>(lv.size()) < o->max_levels) {
+    Level& c = lv.back();
+    if (static_cast<long long>(M) * c.nx * c.ny * c.N <= o->min_coarse) break;
+    const bool cs_x = (c.ex % 2 == 0) && (p->bc == STMG_BC_PERIODIC ? c.ex >= 4 : c.ex >= 4);
+    const bool cs_y = !twod || ((c.ey % 2 == 0) && c.ey >= 4);
+    const bool can_s = cs_x && cs_y;
+    const bool can_t = c.N % 2 == 0;
+    const double hx = p->length[0] / c.ex;
+    const double hy = twod ? p->length[1] / c.ey : hx;
+    const double hmin = hx < hy ? hx : hy;
+    const double mu = p->nu * c.dt / (hmin * hmin);
+    int kind = 0;
+    if (o->coarsen == STMG_COARSEN_SPACE) {
+      kind = can_s ? 1 : 0;
+    } else if (o->coarsen == STMG_COARSEN_SPACETIME) {
+      kind = (can_s && can_t) ? 3 : (can_s ? 1 : (can_t ? 2 : 0));
+    } else {
+      if (mu >= o->mu_crit && can_s) kind = 1;
+      else if (can_t) kind = 2;
+      else if (can_s) kind = 1;
+    }
+    if (kind == 0) break;
+    c.kind = kind;
+    Level nl;
+    nl.ex = (kind & 1) ? c.ex / 2 : c.ex;
+    nl.ey = (kind & 1) && twod ? c.ey / 2 : c.ey;
+    nl.nx = points(nl.ex, p->bc);
+    nl.ny = twod ? points(nl.ey, p->bc) : 1;
+    nl.N = (kind & 2) ? c.N / 2 : c.N;
+    nl.dt = (kind & 2) ? 2.0 * c.dt : c.dt;
+    lv.push_back(nl);
+  }
+  const Level& last = lv.back();
+  const long long Kc = static_cast<long long>(M) * last.nx * last.ny;
+  if (Kc > 1024) {
+    set_error("coarsest level has more than 1024 unknowns per slab");
+    return STMG_EUNSUPPORTED;
+  }
+
+  // Operators per level.
+  for (auto& l : lv) {
+    l.hx = p->length[0] / l.ex;
+    l.hy = twod ? p->length[1] / l.ey : 1.0;
+    l.n = static_cast<size_t>(l.N) * M * l.nx * l.ny;
+    OpParams op{};
+    op.M = M;
+    op.nx = l.nx;
+    op.ny = l.ny;
+    op.N = l.N;
+    op.bc = p->bc == STMG_BC_PERIODIC ? 0 : 1;
+    op.cx = p->nu / (l.hx * l.hx);
+    op.cy = twod ? p->nu / (l.hy * l.hy) : 0.0;
+    op.lam = allen_cahn ? 0.0 : p->lambda;
+    op.gamma = allen_cahn ? p->gamma : 0.0;
+    op.omega = o->omega;
+    OpParams opT = op;
+    const long double dg = 2.0L * op.cx + 2.0L * op.cy + op.lam;
+    std::vector<long double> B(static_cast<size_t>(M) * M), BT(static_cast<size_t>(M) * M);
+    for (int i = 0; i < M; ++i) {
+      op.db[i] = static_cast<double>(l.dt * tab.b[i]);
+      opT.db[i] = op.db[i];
+      op.cin[i] = static_cast<double>(tab.l0[i]);
+      op.cout[i] = (i == M - 1) ? 1.0 : 0.0;
+      opT.cin[i] = op.cout[i];
+      opT.cout[i] = op.cin[i];
+      for (int j = 0; j < M; ++j) {
+        op.K[i * M + j] = static_cast<double>(tab.Kq[i][j]);
+        opT.K[i * M + j] = static_cast<double>(tab.Kq[j][i]);
+        B[static_cast<size_t>(i) * M + j] = tab.Kq[i][j] + (i == j ? l.dt * tab.b[i] * dg : 0.0L);
+        BT[static_cast<size_t>(i) * M + j] = tab.Kq[j][i] + (i == j ? l.dt * tab.b[i] * dg : 0.0L);
+      }
+    }
+    if (!invert_ld(B, M) || !invert_ld(BT, M)) { set_error("singular point block"); return STMG_EINVAL; }
+    for (int i = 0; i < M * M; ++i) {
+      op.Binv[i] = static_cast<double>(B[i]);
+      opT.Binv[i] = static_cast<double>(BT[i]);
+    }
+    l.op = op;
+    l.opT = opT;
+  }
+  return STMG_OK;
+}
+
+size_t Solver::plan(char* ws) {
+  Plan pl;
+  pl.base = ws;
+  for (size_t i = 0; i < lv.size(); ++i) {
+    Level& l = lv[i];
+    if (i > 0) l.A64 = pl.take<double>(l.n);
+    l.B64 = pl.take<double>(l.n);
+    l.f64 = pl.take<double>(l.n);
+    if (mixed) {
+      l.A32 = pl.take<float>(l.n);
+      l.B32 = pl.take<float>(l.n);
+      l.f32 = pl.take<float>(l.n);
+    }
+    if (allen_cahn) {
+      if (i == 0 || !mixed) l.coef64 = pl.take<double>(l.n);
+      if (mixed) l.coef32 = pl.take<float>(l.n);
+    }
+  }
+  delta64 = pl.take<double>(lv[0].n);
+  // partial sums: the largest residual launch is on level 0
+  {
+    const Level& l = lv[0];
+    const int tiles = (l.nx * l.ny + kBlock - 1) / kBlock;
+    const int chunks = (l.N + kResidSlabs - 1) / kResidSlabs;
+    max_parts = tiles * chunks;
+    if (max_parts < 1024) max_parts = 1024;
+  }
+  part = pl.take<double>(static_cast<size_t>(max_parts));
+  scal = pl.take<double>(32);
+  const Level& c = lv.back();
+  const size_t K = static_cast<size_t>(prob.M) * c.nx * c.ny;
+  Ainv = pl.take<double>(K * K);
+  AinvT = pl.take<double>(K * K);
+  coarse_scratch = allen_cahn ? pl.take<double>(K * K) : nullptr;
+  lw = pl.take<double>(kMaxM);
+  return pl.off + 256;
+}
+
+int Solver::upload() {
+  // Coarsest slab matrix: K (x) I + diag(db) (x) (-Lap + lambda), inverted.
+  const Level& c = lv.back();
+  const int M = prob.M, P = c.nx * c.ny, K = M * P;
+  std::vector<long double> A(static_cast<size_t>(K) * K, 0.0L);
+  const OpParams& op = c.op;
+  auto lo = [&](int i, int n) { return i > 0 ? i - 1 : (op.bc == 0 ? n - 1 : 1); };
+  auto hi = [&](int i, int n) { return i < n - 1 ? i + 1 : (op.bc == 0 ? 0 : n - 2); };
+  for (int i = 0; i < M; ++i)
+    for (int q = 0; q < P; ++q) {
+      const int r = i * P + q;
+      for (int j = 0; j < M; ++j) A[static_cast<size_t>(r) * K + j * P + q] += tab.Kq[i][j];
+      const int x = q % c.nx, y = q / c.nx;
+      const long double db = c.dt * tab.b[i];
+      auto add = [&](int q2, long double v) { A[static_cast<size_t>(r) * K + i * P + q2] += db * v; };
+      add(q, 2.0L * op.cx + (c.ny > 1 ? 2.0L * op.cy : 0.0L) + op.lam);
+      add(y * c.nx + lo(x, c.nx), -op.cx);
+      add(y * c.nx + hi(x, c.nx), -op.cx);
+      if (c.ny > 1) {
+        add(lo(y, c.ny) * c.nx + x, -op.cy);
+        add(hi(y, c.ny) * c.nx + x, -op.cy);
+      }
+    }
+  if (!invert_ld(A, K)) { set_error("singular coarsest slab matrix"); return STMG_EINVAL; }
+  std::vector<double> Ad(static_cast<size_t>(K) * K), AdT(static_cast<size_t>(K) * K);
+  for (int r = 0; r < K; ++r)
+    for (int s = 0; s < K; ++s) {
+      Ad[static_cast<size_t>(r) * K + s] = static_cast<double>(A[static_cast<size_t>(r) * K + s]);
+      AdT[static_cast<size_t>(s) * K + r] = static_cast<double>(A[static_cast<size_t>(r) * K + s]);
+    }
+  HIP_CHECK(hipMemcpyAsync(Ainv, Ad.data(), Ad.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIP_CHECK(hipMemcpyAsync(AinvT, AdT.data(), AdT.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  double w[kMaxM] = {0};
+  for (int i = 0; i < M; ++i) w[i] = static_cast<double>(tab.l0[i]);
+  HIP_CHECK(hipMemcpyAsync(lw, w, sizeof(w), hipMemcpyHostToDevice, stream));
+  HIP_CHECK(hipStreamSynchronize(stream));  // host vectors go out of scope
+  return STMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+static const T* coef_of(const Level& l);
+template <>
+const double* coef_of<double>(const Level& l) { return l.coef64; }
+template <>
+const float* coef_of<float>(const Level& l) { return l.coef32; }
+
+template <typename T>
+hipError_t Solver::smooth(int l, bool adj, int react, const T* U, const T* f, const double* u0,
+                          T* out) {
+  const Level& L = lv[l];
+  SweepPtrs<T> a{U, f, u0, coef_of<T>(L), out, nullptr};
+  return launch_smooth<T>(adj ? L.opT : L.op, react, a, opt.chunk, stream);
+}
+
+template <typename T>
+hipError_t Solver::restrict_residual(int l, bool adj, int react, const T* U, const T* f,
+                                     const double* u0, T* fc) {
+  const Level& L = lv[l];
+  const Level& C = lv[l + 1];
+  SweepPtrs<T> a{U, f, u0, coef_of<T>(L), nullptr, nullptr};
+  return launch_restrict_residual<T>(adj ? L.opT : L.op, react, a, (L.kind & 1) != 0,
+                                     (L.kind & 2) != 0, C.nx, C.ny, C.N, fc, kTransferSlabs, stream);
+}
+
+template <typename T>
+hipError_t Solver::prolong(int l, const T* Uin, const T* ec, T* Uout) {
+  const Level& L = lv[l];
+  const Level& C = lv[l + 1];
+  return launch_prolong<T>(L.op, (L.kind & 1) != 0, (L.kind & 2) != 0, C.nx, C.ny, C.N, ec, Uin,
+                           Uout, kTransferSlabs, stream);
+}
+
+template <typename T>
+hipError_t Solver::coarse(bool adj, int react, const T* f, const double* u0, T* U) {
+  const Level& C = lv.back();
+  const OpParams& op = adj ? C.opT : C.op;
+  if (react == REACT_COEF)
+    return launch_coarse_solve_coef<T>(op, coef_of<T>(C), coarse_scratch, f, u0, U, stream);
+  return launch_coarse_solve<T>(op, adj ? AinvT : Ainv, f, u0, U, stream);
+}
+
+template <typename T>
+hipError_t Solver::vcycle(int l, bool adj, int react, T* cur, T* oth, const T* f,
+                          const double* u0, bool zero, T** res) {
+  const int last = static_cast<int>(lv.size()) - 1;
+  if (l == last) {
+    HIP_TRY(coarse<T>(adj, react, f, u0, cur));
+    *res = cur;
+    return hipSuccess;
+  }
+  for (int s = 0; s < opt.nu_pre; ++s) {
+    HIP_TRY(smooth<T>(l, adj, react, zero ? nullptr : cur, f, u0, oth));
+    std::swap(cur, oth);
+    zero = false;
+  }
+  Level& C = lv[l + 1];
+  T* cf = nullptr;
+  T* ca = nullptr;
+  T* cb = nullptr;
+  if constexpr (sizeof(T) == 8) { cf = C.f64; ca = C.A64; cb = C.B64; }
+  else { cf = C.f32; ca = C.A32; cb = C.B32; }
+  HIP_TRY(restrict_residual<T>(l, adj, react, zero ? nullptr : cur, f, u0, cf));
+  T* ec = nullptr;
+  HIP_TRY(vcycle<T>(l + 1, adj, react, ca, cb, cf, nullptr, true, &ec));
+  // Keep an even number of buffer flips so that level 0 ends where it began.
+  const bool flip = ((opt.nu_pre + opt.nu_post) & 1) != 0;
+  if (flip) {
+    HIP_TRY(prolong<T>(l, zero ? nullptr : cur, ec, oth));
+    std::swap(cur, oth);
+  } else {
+    HIP_TRY(prolong<T>(l, zero ? nullptr : cur, ec, cur));
+  }
+  for (int s = 0; s < opt.nu_post; ++s) {
+    HIP_TRY(smooth<T>(l, adj, react, cur, f, u0, oth));
+    std::swap(cur, oth);
+  }
+  *res = cur;
+  return hipSuccess;
+}
+
+template <typename TO>
+hipError_t Solver::residual64(bool adj, int react, const double* U, const double* f,
+                              const double* u0, TO* r, double* d_out) {
+  const Level& L = lv[0];
+  const int np = ((L.nx * L.ny + kBlock - 1) / kBlock) * ((L.N + kResidSlabs - 1) / kResidSlabs);
+  if (np > max_parts) {
+    set_error("partial buffer too small");
+    return hipErrorInvalidValue;
+  }
+  SweepPtrs<double> a{U, f, u0, L.coef64, r, part};
+  int launched = 0;
+  HIP_TRY((launch_residual<double, TO>(adj ? L.opT : L.op, react, a, kResidSlabs, &launched, stream)));
+  return launch_sum_partials(part, launched, d_out, stream);
+}
+
+int Solver::read_scalar(const double* d, double* h) {
+  HIP_CHECK(hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIP_CHECK(hipStreamSynchronize(stream));
+  return STMG_OK;
+}
+
+double Solver::norm_u0_b(const double* u0) {
+  // ||b||^2 = sum_i l_i(0)^2 ||u0||^2 for b_{0,i} = l_i(0) u0.
+  const Level& L = lv[0];
+  const size_t P = static_cast<size_t>(L.nx) * L.ny;
+  int np = 0;
+  if (launch_sumsq(u0, P, part, &np, stream) != hipSuccess) return -1.0;
+  if (launch_sum_partials(part, np, scal + 1, stream) != hipSuccess) return -1.0;
+  double s = 0.0;
+  if (read_scalar(scal + 1, &s) != STMG_OK) return -1.0;
+  long double w = 0.0L;
+  for (int i = 0; i < prob.M; ++i) w += tab.l0[i] * tab.l0[i];
+  return std::sqrt(static_cast<double>(w) * s);
+}
+
+// ---------------------------------------------------------------------------
+// Linear solve on level 0: FP64 V-cycles, or (mixed) FP32 V-cycles on the
+// FP64 residual with FP64 updates (iterative refinement).  `U` holds the
+// initial guess and receives the result.
+int Solver::solve_linear(bool adj, int react, const double* f, const double* u0, double* U,
+                         double rtol, double norm_b, int* cycles, double* rel_out) {
+  Level& L0 = lv[0];
+  double rn2 = 0.0;
+  if (!mixed) {
+    HIP_CHECK(residual64<double>(adj, react, U, f, u0, nullptr, scal));
+  } else {
+    HIP_CHECK(residual64<float>(adj, react, U, f, u0, L0.f32, scal));
+  }
+  int rc = read_scalar(scal, &rn2);
+  if (rc) return rc;
+  double rel = norm_b > 0.0 ? std::sqrt(rn2) / norm_b : std::sqrt(rn2);
+  const double rel0 = rel;
+  double prev = rel;
+  int incr = 0;
+  int c = 0;
+  int status = STMG_OK;
+  while (rel > rtol) {
+    if (c >= opt.max_cycles) { status = STMG_ENOTCONV; break; }
+    if (!mixed) {
+      double* res = nullptr;
+      HIP_CHECK(vcycle<double>(0, adj, react, U, L0.B64, f, u0, false, &res));
+      if (res != U) HIP_CHECK(hipMemcpyAsync(U, res, L0.n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+      HIP_CHECK(residual64<double>(adj, react, U, f, u0, nullptr, scal));
+    } else {
+      float* res = nullptr;
+      HIP_CHECK(vcycle<float>(0, adj, react, L0.A32, L0.B32, L0.f32, nullptr, true, &res));
+      HIP_CHECK(launch_update<float>(L0.n, U, res, nullptr, stream));
+      HIP_CHECK(residual64<float>(adj, react, U, f, u0, L0.f32, scal));
+    }
+    ++c;
+    rc = read_scalar(scal, &rn2);
+    if (rc) return rc;
+    rel = norm_b > 0.0 ? std::sqrt(rn2) / norm_b : std::sqrt(rn2);
+    if (!std::isfinite(rel)) { status = STMG_ENAN; break; }
+    if (rel > 1e3 * (rel0 > 0 ? rel0 : 1.0)) { status = STMG_EDIVERGED; break; }
+    incr = rel > prev ? incr + 1 : 0;
+    if (incr >= 5) { status = STMG_EDIVERGED; break; }
+    prev = rel;
+  }
+  *cycles += c;
+  *rel_out = rel;
+  if (status != STMG_OK) {
+    set_error(std::string("linear solve stopped: ") + stmg_status_string(status));
+  }
+  return status;
+}
+
+int Solver::newton_linearize(const double* U) {
+  // c = gamma (3 U^2 - 1) on level 0, restricted to the coarser levels.
+  Level& L0 = lv[0];
+  if (L0.coef64) HIP_CHECK(launch_newton_coef<double>(L0.n, U, prob.gamma, L0.coef64, stream));
+  if (mixed) HIP_CHECK(launch_newton_coef<float>(L0.n, U, prob.gamma, L0.coef32, stream));
+  for (size_t l = 0; l + 1 < lv.size(); ++l) {
+    const Level& F = lv[l];
+    Level& C = lv[l + 1];
+    const bool sp = (F.kind & 1) != 0, tm = (F.kind & 2) != 0;
+    if (!mixed) HIP_CHECK(launch_restrict_coef<double>(F.op, sp, tm, C.nx, C.ny, C.N, F.coef64, C.coef64, stream));
+    else HIP_CHECK(launch_restrict_coef<float>(F.op, sp, tm, C.nx, C.ny, C.N, F.coef32, C.coef32, stream));
+  }
+  return STMG_OK;
+}
+
+int Solver::solve(const double* u0, double* U, stmg_stats* st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  stmg_stats s{};
+  const double nb = norm_u0_b(u0);
+  if (nb < 0.0) return STMG_EHIP;
+  int rc = STMG_OK;
+  if (!allen_cahn) {
+    rc = solve_linear(false, REACT_CONST, nullptr, u0, U, opt.rtol, nb, &s.cycles, &s.rel_res);
+    s.refinements = mixed ? s.cycles : 0;
+  } else {
+    // Newton on G(U) = b - A_AC(U) (Sec. 3.2), inexact: each correction solve
+    // stops at a relative tolerance eta_k (Eisenstat-Walker, choice 2).
+    Level& L0 = lv[0];
+    double gprev = -1.0, eta = 1e-2;
+    for (int k = 0;; ++k) {
+      HIP_CHECK(residual64<double>(false, REACT_AC, U, nullptr, u0, L0.f64, scal));
+      double g2 = 0.0;
+      rc = read_scalar(scal, &g2);
+      if (rc) break;
+      const double g = std::sqrt(g2) / nb;
+      s.rel_res = g;
+      if (!std::isfinite(g)) { rc = STMG_ENAN; break; }
+      if (g <= opt.newton_rtol) { rc = STMG_OK; break; }
+      if (k >= opt.max_newton) { rc = STMG_ENOTCONV; break; }
+      if (gprev > 0.0) {
+        const double r = g / gprev;
+        eta = 0.9 * r * r;
+        if (eta > 1e-1) eta = 1e-1;
+      }
+      // never ask for more than the final target needs
+      const double floor = 0.5 * opt.newton_rtol / g;
+      if (eta < floor) eta = floor;
+      if (eta < 1e-12) eta = 1e-12;
+      gprev = g;
+      rc = newton_linearize(U);
+      if (rc) break;
+      HIP_CHECK(hipMemsetAsync(delta64, 0, L0.n * sizeof(double), stream));
+      double rel = 0.0;
+      int lrc = solve_linear(false, REACT_COEF, L0.f64, nullptr, delta64, eta, std::sqrt(g2),
+                             &s.cycles, &rel);
+      if (lrc == STMG_ENAN || lrc == STMG_EHIP) { rc = lrc; break; }
+      HIP_CHECK(launch_update<double>(L0.n, U, delta64, nullptr, stream));
+      ++s.newton_its;
+    }
+    if (mixed) s.refinements = s.cycles;
+  }
+  HIP_CHECK(hipStreamSynchronize(stream));
+  s.status = rc;
+  s.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  last = s;
+  if (st) *st = s;
+  return rc;
+}
+
+int Solver::vcycle_user(const double* u0, double* U, double* h_rel) {
+  Level& L0 = lv[0];
+  const bool lin = !allen_cahn;
+  const int react = lin ? REACT_CONST : REACT_COEF;
+  const double* f = lin ? nullptr : L0.f64;
+  const double* uu = lin ? u0 : nullptr;
+  if (!mixed) {
+    double* res = nullptr;
+    HIP_CHECK(vcycle<double>(0, false, react, U, L0.B64, f, uu, false, &res));
+    if (res != U) HIP_CHECK(hipMemcpyAsync(U, res, L0.n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  } else {
+    HIP_CHECK(residual64<float>(false, react, U, f, uu, L0.f32, scal));
+    float* res = nullptr;
+    HIP_CHECK(vcycle<float>(0, false, react, L0.A32, L0.B32, L0.f32, nullptr, true, &res));
+    HIP_CHECK(launch_update<float>(L0.n, U, res, nullptr, stream));
+  }
+  if (h_rel) {
+    HIP_CHECK(residual64<double>(false, react, U, f, uu, nullptr, scal));
+    double r2 = 0.0;
+    int rc = read_scalar(scal, &r2);
+    if (rc) return rc;
+    double nb = 1.0;
+    if (lin) {
+      nb = norm_u0_b(u0);
+    } else {
+      int np = 0;
+      HIP_CHECK(launch_sumsq(L0.f64, L0.n, part, &np, stream));
+      HIP_CHECK(launch_sum_partials(part, np, scal + 2, stream));
+      double f2 = 0.0;
+      rc = read_scalar(scal + 2, &f2);
+      if (rc) return rc;
+      nb = std::sqrt(f2);
+    }
+    *h_rel = nb > 0 ? std::sqrt(r2) / nb : std::sqrt(r2);
+  }
+  return STMG_OK;
+}
+
+int Solver::residual_user(const double* u0, const double* U, double* r, double* h_norm) {
+  const int react = allen_cahn ? REACT_AC : REACT_CONST;
+  HIP_CHECK(residual64<double>(false, react, U, nullptr, u0, r, scal));
+  if (h_norm) {
+    double r2 = 0.0;
+    int rc = read_scalar(scal, &r2);
+    if (rc) return rc;
+    *h_norm = std::sqrt(r2);
+  }
+  return STMG_OK;
+}
+
+// Adjoint: A^T lam = g with g = dL/du(T) in slab N, node M.  A^T is block
+// upper-bidiagonal; stored backward in time (slab n' = N-1-n) it has the
+// lower-bidiagonal form of A with K -> Kq^T and the coupling roles of l(0)
+// and e_M exchanged, so the forward V-cycle kernels solve it unchanged.
+int Solver::adjoint(const double* u0, const double* U, const double* gT, double* grad_u0,
+                    double* grad_nu, stmg_stats* st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (allen_cahn) { set_error("adjoint: linear problems only"); return STMG_EUNSUPPORTED; }
+  // The transposed kernels reuse the symmetric periodic Laplacian; the
+  // ghost-reflection Neumann operator is not symmetric.
+  if (prob.bc != STMG_BC_PERIODIC) { set_error("adjoint: periodic grids only"); return STMG_EUNSUPPORTED; }
+  if (!U) { set_error("adjoint: forward trajectory required"); return STMG_EINVAL; }
+  (void)u0;
+  Level& L0 = lv[0];
+  stmg_stats s{};
+  // ||g||: the right-hand side is cin (x) gT = e_M (x) gT in (reversed) slab 0
+  const size_t P = static_cast<size_t>(L0.nx) * L0.ny;
+  int np = 0;
+  HIP_CHECK(launch_sumsq(gT, P, part, &np, stream));
+  HIP_CHECK(launch_sum_partials(part, np, scal + 3, stream));
+  double g2 = 0.0;
+  int rc = read_scalar(scal + 3, &g2);
+  if (rc) return rc;
+  HIP_CHECK(hipMemsetAsync(delta64, 0, L0.n * sizeof(double), stream));
+  rc = solve_linear(true, REACT_CONST, nullptr, gT, delta64, opt.rtol, std::sqrt(g2), &s.cycles,
+                    &s.rel_res);
+  if (rc != STMG_OK && rc != STMG_ENOTCONV) return rc;
+  // dL/du0 = sum_i l_i(0) lam_{0,i}: forward slab 0 is reversed slab N-1
+  HIP_CHECK(launch_node_combine(delta64 + static_cast<size_t>(L0.N - 1) * prob.M * P, lw, prob.M, P,
+                                grad_u0, stream));
+  // dL/dnu = sum lam dt b_i (Lap U) = (1/nu) sum lam db_i (nu Lap U)
+  HIP_CHECK(launch_grad_nu(L0.op, U, delta64, part, &np, stream));
+  HIP_CHECK(launch_sum_partials(part, np, scal + 4, stream));
+  double gn = 0.0;
+  int rc2 = read_scalar(scal + 4, &gn);
+  if (rc2) return rc2;
+  *grad_nu = gn / prob.nu;
+  s.status = rc;
+  s.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st) *st = s;
+  return rc;
+}
+
+int Solver::sdc(const double*, double*, int, double*) {
+  set_error("SDC sweep not available in this build");
+  return STMG_EUNSUPPORTED;
+}
+
+// explicit instantiations used by the C ABI
+template hipError_t Solver::smooth<double>(int, bool, int, const double*, const double*, const double*, double*);
+template hipError_t Solver::restrict_residual<double>(int, bool, int, const double*, const double*, const double*, double*);
+template hipError_t Solver::prolong<double>(int, const double*, const double*, double*);
+template hipError_t Solver::coarse<double>(bool, int, const double*, const double*, double*);
+
+}  // namespace stmg

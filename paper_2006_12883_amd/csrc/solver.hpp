@@ -1,0 +1,105 @@
+// Host-side solver state behind the C ABI (internal to libstmg).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/stmg.h"
+#include "kernels.hpp"
+#include "tables.hpp"
+
+namespace stmg {
+
+void set_error(const std::string& msg);
+
+struct Level {
+  int nx = 0, ny = 1;  // grid points
+  int ex = 0, ey = 1;  // elements (Neumann) / points (periodic), for h
+  int N = 0;
+  double dt = 0.0, hx = 0.0, hy = 1.0;
+  int kind = 0;        // coarsening to the next level: 1 space, 2 time, 3 both
+  size_t n = 0;        // N * M * nx * ny
+  OpParams op{}, opT{};
+  // FP64 buffers (level 0: A is the caller's iterate, B is workspace)
+  double *A64 = nullptr, *B64 = nullptr, *f64 = nullptr, *coef64 = nullptr;
+  // FP32 buffers (mixed precision)
+  float *A32 = nullptr, *B32 = nullptr, *f32 = nullptr, *coef32 = nullptr;
+};
+
+// Byte-offset planner over one device buffer.
+struct Plan {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~static_cast<size_t>(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct Solver {
+  stmg_problem prob{};
+  stmg_options opt{};
+  hipStream_t stream = nullptr;
+  RadauTables tab{};
+  std::vector<Level> lv;
+  bool allen_cahn = false;
+  bool mixed = false;
+  size_t ws_bytes = 0;
+  // shared device scratch
+  double* part = nullptr;   // per-block partial sums
+  int max_parts = 0;
+  double* scal = nullptr;   // device scalars
+  double* Ainv = nullptr;   // coarsest slab inverse (forward)
+  double* AinvT = nullptr;  // (transposed problem)
+  double* coarse_scratch = nullptr;  // dense slab matrix for the Newton coarsest solve
+  double* delta64 = nullptr;  // Newton correction / adjoint multiplier (level 0, FP64)
+  double* lw = nullptr;       // M weights l(0) on the device (gradient of u0)
+  // statistics of the last solve
+  stmg_stats last{};
+
+  // --- setup ---
+  int build(const stmg_problem* p, const stmg_options* o);
+  size_t plan(char* ws);  // lays out (or sizes, ws = nullptr) the workspace
+  int upload();           // copies tables into the workspace
+
+  // --- building blocks (FP64 or FP32 arithmetic) ---
+  template <typename T>
+  hipError_t smooth(int l, bool adj, int react, const T* U, const T* f, const double* u0, T* out);
+  template <typename T>
+  hipError_t restrict_residual(int l, bool adj, int react, const T* U, const T* f,
+                               const double* u0, T* fc);
+  template <typename T>
+  hipError_t prolong(int l, const T* Uin, const T* ec, T* Uout);
+  template <typename T>
+  hipError_t coarse(bool adj, int react, const T* f, const double* u0, T* U);
+  // One V-cycle on level l; `cur` holds the iterate (ignored if zero), `oth`
+  // is the ping-pong partner; the result pointer is returned in *res.
+  template <typename T>
+  hipError_t vcycle(int l, bool adj, int react, T* cur, T* oth, const T* f, const double* u0,
+                    bool zero, T** res);
+
+  // ||f + u0-coupling - A U||^2 on level 0 (FP64), optional store into r (TO).
+  template <typename TO>
+  hipError_t residual64(bool adj, int react, const double* U, const double* f,
+                        const double* u0, TO* r, double* d_out);
+  int read_scalar(const double* d, double* h);
+
+  // --- drivers ---
+  int solve_linear(bool adj, int react, const double* f, const double* u0, double* U,
+                   double rtol, double norm_b, int* cycles, double* rel);
+  int solve(const double* u0, double* U, stmg_stats* st);
+  int vcycle_user(const double* u0, double* U, double* h_rel);
+  int residual_user(const double* u0, const double* U, double* r, double* h_norm);
+  int adjoint(const double* u0, const double* U, const double* gT, double* grad_u0,
+              double* grad_nu, stmg_stats* st);
+  int sdc(const double* u0, double* U, int sweeps, double* h_rel);
+
+  int newton_linearize(const double* U);  // coefficients on every level
+  double norm_u0_b(const double* u0);     // ||b|| for b = l(0) (x) u0
+};
+
+}  // namespace stmg

@@ -1,0 +1,45 @@
+"""The C-ABI library loads and exports every symbol the header declares;
+host-side argument checks (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2006_12883_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_header_symbols_exported():
+    hdr = open(os.path.join(ROOT, "include", "stmg.h")).read()
+    declared = set(re.findall(r"\b(stmg_[a-z_0-9]+)\s*\(", hdr))
+    assert declared == set(B.EXPORTS)
+    L = B.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = B.lib()
+    assert L.stmg_status_string(0) == b"ok"
+    assert L.stmg_status_string(-4) == b"not converged"
+
+
+def test_workspace_and_validation():
+    import stmg_inputs as si
+    prob = si.config("rd2d")
+    n = B.workspace_bytes(prob)
+    # level 0 needs at least a ping-pong and a right-hand-side FP64 vector
+    assert n > 2 * 8 * 256 * 256 * 3 * 256
+    for bad in [dict(prob, M=0), dict(prob, M=9), dict(prob, N=0), dict(prob, dt=-1.0),
+                dict(prob, nu=0.0), dict(prob, dim=3), dict(prob, nx=[2, 2])]:
+        assert B.lib().stmg_workspace_bytes(ctypes.byref(B.make_problem(bad)),
+                                            ctypes.byref(B.make_options())) == 0
+    assert B.lib().stmg_setup(None, None, None, 0, None, None) == B.STMG_EINVAL
+
+
+def test_options_defaults():
+    o = B.make_options()
+    assert o.omega == 0.8 and o.chunk == 16 and o.nu_pre == 1 and o.nu_post == 1
+    assert o.rtol == 1e-12 and o.coarsen == 0 and o.precision == 0

@@ -1,0 +1,134 @@
+"""GPU parity, kernel by kernel, against the oracle (element by element).
+
+Each case prints its name before touching the GPU."""
+import numpy as np
+import pytest
+
+import stmg_inputs as si
+from oracle import allatonce, mg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from gpu_util import H, T, assert_close, rel_err  # noqa: E402
+
+CASES = [
+    ("1d-M1", si.problem(1, 24, 1, 7, 0.3, nu=0.2, lam=0.5)),
+    ("1d-M2", si.problem(1, 64, 2, 16, 0.1, nu=1.0, lam=0.0)),
+    ("2d-M3-ragged", si.problem(2, 20, 3, 9, 0.5, nu=0.01, lam=1.0)),
+    ("2d-M4", si.problem(2, 32, 4, 12, 1.0, nu=0.05, lam=0.3)),
+    ("2d-M3-tiles", si.problem(2, 48, 3, 34, 1.0, nu=0.02, lam=1.0)),
+]
+
+
+def _rng_fields(prob, seed):
+    rng = np.random.default_rng(seed)
+    ny, nx = si.grid_points(prob)
+    shape = (prob["N"], prob["M"], ny, nx)
+    return rng.standard_normal(shape), rng.standard_normal((ny, nx)), rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("name,prob", CASES + [
+    ("1d-neumann", si.problem(1, 30, 3, 5, 0.2, nu=1.0, bc="neumann")),
+    ("2d-neumann", si.problem(2, 12, 2, 6, 0.2, nu=0.1, lam=0.2, bc="neumann")),
+    ("2d-AC", si.problem(2, 16, 3, 5, 0.5, nu=0.01, gamma=1.0, reaction="allen_cahn")),
+])
+def test_residual_matches_allatonce(name, prob):
+    print("case", name, flush=True)
+    U, u0, _ = _rng_fields(prob, 1)
+    ref = allatonce.residual(prob, u0, U)
+    h = H(prob)
+    r = torch.empty(U.shape, dtype=torch.float64, device="cuda:0")
+    nrm = h.residual(T(u0), T(U), r)
+    got = r.cpu().numpy()
+    assert_close(got, ref, 1e-13 * np.abs(ref).max(), "residual")
+    assert abs(nrm - np.linalg.norm(ref)) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name,prob", CASES)
+def test_hierarchy_matches_oracle(name, prob):
+    print("case", name, flush=True)
+    levels, kinds = mg.hierarchy(prob)
+    got = H(prob).levels()
+    assert len(got) == len(levels)
+    code = {"s": 1, "t": 2, "st": 3}
+    for l, (g, o) in enumerate(zip(got, levels)):
+        assert (g["nx"], g["ny"], g["N"]) == (o.nx, o.ny, o.N)
+        assert abs(g["dt"] - o.dt) <= 1e-15 * o.dt
+        assert g["kind"] == (code[kinds[l]] if l < len(kinds) else 0)
+
+
+@pytest.mark.parametrize("name,prob", CASES)
+@pytest.mark.parametrize("zero", [False, True])
+def test_smoother_each_level(name, prob, zero):
+    print("case", name, zero, flush=True)
+    levels, kinds = mg.hierarchy(prob)
+    h = H(prob)
+    for l, lev in enumerate(levels):
+        rng = np.random.default_rng(10 + l)
+        U = np.zeros(lev.shape) if zero else rng.standard_normal(lev.shape)
+        f = rng.standard_normal(lev.shape)
+        ref = lev.smooth(U, f, 0.8, 16)
+        out = torch.empty(lev.shape, dtype=torch.float64, device="cuda:0")
+        h.smooth(l, None if zero else T(U), out, f=T(f))
+        assert_close(out.cpu().numpy(), ref, 1e-12, "smooth level %d" % l)
+
+
+@pytest.mark.parametrize("name,prob", CASES)
+def test_restrict_prolong_each_level(name, prob):
+    print("case", name, flush=True)
+    levels, kinds = mg.hierarchy(prob)
+    h = H(prob)
+    for l in range(len(levels) - 1):
+        lev, nxt = levels[l], levels[l + 1]
+        rng = np.random.default_rng(20 + l)
+        U = rng.standard_normal(lev.shape)
+        f = rng.standard_normal(lev.shape)
+        ref = mg.restrict(f - lev.apply(U), kinds[l], lev.dim)
+        fc = torch.empty(nxt.shape, dtype=torch.float64, device="cuda:0")
+        h.restrict_residual(l, T(U), fc, f=T(f))
+        assert_close(fc.cpu().numpy(), ref, 1e-12, "restrict level %d kind %s" % (l, kinds[l]))
+        ec = rng.standard_normal(nxt.shape)
+        refp = U + mg.prolong(ec, kinds[l], lev.dim)
+        out = torch.empty(lev.shape, dtype=torch.float64, device="cuda:0")
+        h.prolong(l, T(ec), out, Uin=T(U))
+        assert_close(out.cpu().numpy(), refp, 1e-13, "prolong level %d kind %s" % (l, kinds[l]))
+
+
+@pytest.mark.parametrize("name,prob", CASES)
+def test_coarse_solve(name, prob):
+    print("case", name, flush=True)
+    levels, kinds = mg.hierarchy(prob)
+    h = H(prob)
+    lev = levels[-1]
+    f = np.random.default_rng(3).standard_normal(lev.shape)
+    ref = lev.exact_solve(f)
+    out = torch.empty(lev.shape, dtype=torch.float64, device="cuda:0")
+    h.coarse_solve(T(f), out)
+    assert_close(out.cpu().numpy(), ref, 1e-12, "coarse solve")
+
+
+@pytest.mark.parametrize("name,prob", CASES)
+def test_one_vcycle_matches_oracle(name, prob):
+    print("case", name, flush=True)
+    levels, kinds = mg.hierarchy(prob)
+    u0 = np.random.default_rng(4).standard_normal(levels[0].shape[2:])
+    f = mg.rhs(levels, u0)
+    U = np.random.default_rng(5).standard_normal(levels[0].shape)
+    ref = mg.vcycle(levels, kinds, U.copy(), f)
+    h = H(prob)
+    Ud = T(U)
+    h.vcycle(T(u0), Ud)
+    assert_close(Ud.cpu().numpy(), ref, 1e-11, "one V-cycle")
+
+
+def test_repeatable_bitwise():
+    prob = CASES[3][1]
+    U, u0, _ = _rng_fields(prob, 7)
+    h = H(prob)
+    outs = []
+    for _ in range(3):
+        Ud = T(U)
+        h.vcycle(T(u0), Ud)
+        outs.append(Ud.cpu().numpy())
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])

@@ -1,0 +1,105 @@
+"""Mixed precision (FP32 V-cycles inside FP64 refinement) and Newton for the
+Allen-Cahn reaction, against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import stmg_inputs as si
+from oracle import allatonce, fourier, stepper
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from gpu_util import H, T, rel_err  # noqa: E402
+
+
+def _errs(U, ref):
+    return rel_err(U, ref), rel_err(U[-1, -1], ref[-1, -1])
+
+
+def test_mixed_heat1d():
+    print("case mixed heat1d", flush=True)
+    prob = si.config("heat1d")
+    u0 = si.initial("heat1d", prob)
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob, precision="mixed", rtol=1e-10).solve(T(u0))
+    assert st["status"] == 0 and st["rel_res"] <= 1e-10 and st["refinements"] == st["cycles"]
+    e, eT = _errs(U.cpu().numpy(), ref)
+    assert e <= 1e-9 and eT <= 1e-9, (e, eT)
+
+
+@pytest.mark.parametrize("M", [2, 3, 4])
+def test_mixed_rd2d_small(M):
+    print("case mixed rd2d small", M, flush=True)
+    prob = si.problem(2, 64, M, 32, 0.5, nu=1e-2, lam=1.0)
+    u0 = si.u0_rd2d(prob, 2)
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob, precision="mixed", rtol=1e-10).solve(T(u0))
+    assert st["status"] == 0
+    e, eT = _errs(U.cpu().numpy(), ref)
+    assert e <= 1e-9 and eT <= 1e-9, (e, eT)
+
+
+def test_mixed_rd2d_full():
+    print("case mixed rd2d full", flush=True)
+    prob = si.config("rd2d")
+    u0 = si.initial("rd2d", prob)
+    U, st = H(prob, precision="mixed", rtol=1e-10).solve(T(u0))
+    assert st["status"] == 0
+    ref = fourier.solve_linear_periodic(prob, u0)
+    e, eT = _errs(U.cpu().numpy(), ref)
+    assert e <= 1e-9 and eT <= 1e-9, (e, eT)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_newton_allen_cahn_small(prec, dim):
+    print("case newton", prec, dim, flush=True)
+    if dim == 1:
+        prob = si.problem(1, 64, 3, 16, 0.5, nu=1e-2, gamma=5.0, reaction="allen_cahn")
+        u0 = np.random.default_rng(3).uniform(-0.1, 0.1, (1, 64))
+    else:
+        prob = si.problem(2, 64, 3, 32, 0.5, nu=1e-3, gamma=1.0, reaction="allen_cahn")
+        u0 = si.u0_ac2d(prob, 3)
+    ref = stepper.solve_allen_cahn(prob, u0)
+    tol = 1e-12 if prec == "fp64" else 1e-10
+    U, st = H(prob, precision=prec, newton_rtol=tol).solve(T(u0))
+    assert st["status"] == 0 and st["newton_its"] >= 2
+    e, eT = _errs(U.cpu().numpy(), ref)
+    lim = 1e-10 if prec == "fp64" else 1e-9
+    assert e <= lim and eT <= lim, (e, eT)
+
+
+def test_newton_fixed_points():
+    """u = 0, 1, -1 are fixed points of the reaction: one Newton residual check."""
+    prob = si.problem(2, 16, 2, 4, 0.5, nu=1e-2, gamma=2.0, reaction="allen_cahn")
+    for c in (1.0, -1.0):
+        u0 = np.full((16, 16), c)
+        U, st = H(prob, newton_rtol=1e-13).solve(T(u0))
+        assert st["status"] == 0
+        assert np.abs(U.cpu().numpy() - c).max() < 1e-11
+
+
+def test_newton_ac2d_full_sampled():
+    """The full 512^2 x M=3 x N=512 Allen-Cahn workload in mixed precision: the
+    nonlinear residual reaches 1e-10, and sampled entries of the GPU residual of
+    the GPU solution agree with the oracle's entry-by-entry definition."""
+    print("case ac2d full", flush=True)
+    prob = si.config("ac2d")
+    u0 = si.initial("ac2d", prob)
+    h = H(prob, precision="mixed", newton_rtol=1e-10)
+    u0d = T(u0)
+    U, st = h.solve(u0d)
+    assert st["status"] == 0 and st["rel_res"] <= 1e-10
+    r = torch.empty_like(U)
+    h.residual(u0d, U, r)
+    rng = np.random.default_rng(0)
+    for _ in range(12):
+        n = int(rng.integers(0, prob["N"]))
+        i = int(rng.integers(0, prob["M"]))
+        y, x = (int(v) for v in rng.integers(0, 512, 2))
+        lo = max(n - 1, 0)
+        Ul = U[lo:n + 1].cpu().numpy()
+        ref = allatonce.residual_entry(prob, u0, Ul, n - lo, i, y, x) if n > 0 else \
+            allatonce.residual_entry(prob, u0, Ul, 0, i, y, x)
+        got = float(r[n, i, y, x])
+        assert abs(got - ref) <= 1e-12 * max(1.0, float(np.abs(Ul).max())), (n, i, y, x, got, ref)

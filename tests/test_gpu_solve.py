@@ -1,0 +1,83 @@
+"""GPU solves against the oracle's solution of the all-at-once system."""
+import numpy as np
+import pytest
+
+import stmg_inputs as si
+from oracle import fourier, stepper
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from gpu_util import H, T, rel_err  # noqa: E402
+
+
+def _check(U, ref, tol):
+    assert rel_err(U, ref) <= tol
+    assert rel_err(U[-1, -1], ref[-1, -1]) <= tol
+
+
+@pytest.mark.parametrize("coarsen", ["auto", "space"])
+def test_heat1d_fp64(coarsen):
+    print("case heat1d", coarsen, flush=True)
+    prob = si.config("heat1d")
+    u0 = si.initial("heat1d", prob)
+    ref = stepper.solve_linear(prob, u0)
+    h = H(prob, coarsen=coarsen, max_cycles=400)
+    U, st = h.solve(T(u0))
+    assert st["status"] == 0 and st["rel_res"] <= 1e-12
+    _check(U.cpu().numpy(), ref, 1e-10)
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 4])
+def test_rd2d_small_fp64(M):
+    print("case rd2d-small M", M, flush=True)
+    prob = si.problem(2, 64, M, 32, 0.5, nu=1e-2, lam=1.0)
+    u0 = si.u0_rd2d(prob, 2)
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob).solve(T(u0))
+    assert st["status"] == 0
+    _check(U.cpu().numpy(), ref, 1e-10)
+
+
+def test_neumann_1d_fp64():
+    print("case neumann 1d", flush=True)
+    prob = si.problem(1, 128, 3, 16, 0.1, nu=1.0, bc="neumann")
+    x = np.arange(129) / 128
+    u0 = (np.cos(np.pi * x) + 2 * np.cos(3 * np.pi * x) + 3 * np.cos(4 * np.pi * x))[None]
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob).solve(T(u0))
+    assert st["status"] == 0
+    _check(U.cpu().numpy(), ref, 1e-10)
+
+
+def test_rd2d_full_fp64():
+    """The full 2D workload (256^2, M=3, N=256) against the Fourier closed form."""
+    print("case rd2d full fp64", flush=True)
+    prob = si.config("rd2d")
+    u0 = si.initial("rd2d", prob)
+    U, st = H(prob).solve(T(u0))
+    assert st["status"] == 0 and st["rel_res"] <= 1e-12
+    ref = fourier.solve_linear_periodic(prob, u0)
+    _check(U.cpu().numpy(), ref, 1e-10)
+
+
+def test_spacetime_small_mu_fp64():
+    """Full space-time coarsening (STMG) converges when mu = nu dt / h^2 < 1."""
+    print("case spacetime small mu", flush=True)
+    prob = si.problem(2, 32, 3, 32, 1.0, nu=1e-2, lam=1.0)   # mu = 0.32
+    u0 = si.u0_rd2d(prob, 2)
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob, coarsen="spacetime").solve(T(u0))
+    assert st["status"] == 0
+    _check(U.cpu().numpy(), ref, 1e-10)
+
+
+def test_spacetime_large_mu_reports_divergence():
+    """At mu = 25.6 time coarsening fails (Sec. 3.2); the oracle's V-cycle grows
+    the residual too.  The solver must stop with STMG_EDIVERGED, not hang."""
+    print("case spacetime large mu", flush=True)
+    prob = si.config("heat1d")
+    u0 = si.initial("heat1d", prob)
+    U, st = H(prob, coarsen="spacetime").solve(T(u0), check=False)
+    assert st["status"] == -5
+    assert st["cycles"] < 200

@@ -47,12 +47,15 @@ def test_transfer_constants_and_linears():
 def test_hierarchy_auto_rule():
     prob = si.problem(2, 64, 3, 64, 1.0, nu=0.04, lam=1.0)  # mu = 2.56 on the finest level
     levels, kinds = mg.hierarchy(prob)
-    assert kinds[0] == "s"            # mu >= 1: space first
-    assert kinds[1] == "t"            # mu = 0.64 after one space step
+    assert kinds[0] == "s"            # mu = 2.56 >= 0.5: space first
+    assert kinds[1] == "s"            # mu = 0.64 after one space step
+    assert kinds[2] == "t"            # mu = 0.16
     for l, k in zip(levels, kinds):
         mu = l.nu * l.dt / l.hx ** 2
         if k == "s":
-            assert mu >= 1.0 or l.N % 2 == 1
+            assert mu >= 0.5 or l.N % 2 == 1
+    l1, k1 = mg.hierarchy(prob, mu_crit=1.0)
+    assert k1[:2] == ["s", "t"]
     last = levels[-1]
     assert last.M * last.nx * last.ny * last.N <= 64
 
