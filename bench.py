@@ -32,8 +32,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=20)
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain device copy of known size (HBM counter calibration)")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only time the level-0 smoothing sweep and a plain device copy of the "
+                         "same bytes (used for the HBM counter runs)")
     return ap.parse_args()
 
 
@@ -61,6 +62,34 @@ def cpu_baseline(prob, u0, cycles_per_solve):
             "seconds_per_vcycle": t}
 
 
+def time_kernels(h, U, u0, iters):
+    """Level-0 smoothing sweep and a plain copy of the same byte count, each
+    timed with HIP events on the solver's stream."""
+    import torch
+    Uin = U.clone()
+    Uout = torch.empty_like(U)
+    s = h.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    h.smooth(0, Uin, Uout, u0=u0)
+    e0.record(s)
+    for _ in range(iters):
+        h.smooth(0, Uin, Uout, u0=u0)
+    e1.record(s)
+    e1.synchronize()
+    k_ms = e0.elapsed_time(e1) / iters
+    x = torch.ones(U.numel(), dtype=torch.float64, device=U.device)
+    y = torch.empty_like(x)
+    with torch.cuda.stream(s):
+        y.copy_(x)
+        e0.record(s)
+        for _ in range(iters):
+            y.copy_(x)
+        e1.record(s)
+    e1.synchronize()
+    c_ms = e0.elapsed_time(e1) / iters
+    return k_ms, c_ms, 2.0 * x.numel() * 8
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -77,6 +106,14 @@ def main():
     u0 = torch.as_tensor(u0n).to(dev)
     shape = (prob["N"], prob["M"], 256, 256)
     dof = float(np.prod(shape))
+    if a.kernel_only:
+        h = stmg.Handle(prob, device=dev)
+        U = torch.randn(shape, dtype=torch.float64, device=dev)
+        k_ms, c_ms, cbytes = time_kernels(h, U, u0, a.kernel_iters)
+        kb = smoother_bytes_per_dof() * dof
+        print(json.dumps({"smoother_ms": k_ms, "smoother_GBs": kb / k_ms / 1e6,
+                          "copy_ms": c_ms, "copy_bytes": cbytes, "copy_GBs": cbytes / c_ms / 1e6}))
+        return
 
     h = stmg.Handle(prob, device=dev)
     U = torch.zeros(shape, dtype=torch.float64, device=dev)
@@ -121,28 +158,10 @@ def main():
     print("time-to-1e-10 done", file=sys.stderr, flush=True)
 
     # dominant kernel: the level-0 smoothing sweep, timed with HIP events
-    Uin = U.clone()
-    Uout = torch.empty_like(U)
-    s = h.stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    h.smooth(0, Uin, Uout, u0=u0)
-    ev0.record(s)
-    for _ in range(a.kernel_iters):
-        h.smooth(0, Uin, Uout, u0=u0)
-    ev1.record(s)
-    ev1.synchronize()
-    k_ms = ev0.elapsed_time(ev1) / a.kernel_iters
+    k_ms, c_ms, cbytes = time_kernels(h, U, u0, a.kernel_iters)
     kbytes = smoother_bytes_per_dof() * dof
     achieved = kbytes / (k_ms * 1e-3) / 1e9
     print("kernel timing done", file=sys.stderr, flush=True)
-
-    if a.copy_probe:
-        x = torch.empty(int(dof), dtype=torch.float64, device=dev).fill_(1.0)
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
 
     out = {
         "metric": "space-time DOF*V-cycles/s (FP64 STMG solve to 1e-12) + time-to-1e-10 residual, mixed vs FP64, 1 GPU",
@@ -165,7 +184,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_smooth<3,double,0> (level 0)", "kernel_ms": k_ms,
-                     "bytes_per_launch": kbytes},
+                     "bytes_per_launch": kbytes,
+                     "copy_GBs_same_bytes": cbytes / (c_ms * 1e-3) / 1e9},
     }
     if not a.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)

@@ -91,8 +91,9 @@ typedef struct {
                          SPACETIME = STMG (both at once)                      */
   double mu_crit;     /* 0.5                                                 */
   double omega;       /* smoother damping, 0.8                                */
-  int32_t chunk;      /* smoother block length in slabs, 16 (1 = point-block
-                         Jacobi over single slabs)                            */
+  int32_t chunk;      /* smoother block length in slabs on the finest level,
+                         16 (1 = point-block Jacobi over single slabs)        */
+  int32_t chunk_coarse; /* the same on the coarser levels, 4                  */
   int32_t nu_pre;     /* pre-smoothing sweeps, 1                              */
   int32_t nu_post;    /* post-smoothing sweeps, 1                             */
   int32_t max_levels; /* 30                                                  */

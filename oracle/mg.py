@@ -20,7 +20,8 @@ notes):
   with a point-block (M x M) diagonal in space:
     d_n = B^{-1} (r_n + [n mod chunk != 0] l(0) d_{n-1,M}),  U += omega d,
   B = Kq + dt diag(b) (2 nu/hx^2 + 2 nu/hy^2 + lam);  chunk = 1 is the
-  plain point-block Jacobi over slabs;
+  plain point-block Jacobi over slabs; the coarser levels use their own
+  (shorter) `chunk_coarse`;
 * space transfer: full weighting [1 2 1]/4 per dimension and linear
   interpolation, vertex-centred (coarse point X is fine point 2X);
 * time transfer: slab n is identified with its end point T_{n+1}; coarse
@@ -208,18 +209,22 @@ def prolong(e, kind, dim):
     return e
 
 
-def vcycle(levels, kinds, U, f, omega=0.8, chunk=16, nu_pre=1, nu_post=1, l=0):
+def vcycle(levels, kinds, U, f, omega=0.8, chunk=16, nu_pre=1, nu_post=1, l=0, chunk_coarse=4):
+    """One V-cycle; the smoother's block length is `chunk` slabs on the finest
+    level and `chunk_coarse` on the coarser ones."""
     lev = levels[l]
     if l == len(levels) - 1:
         return lev.exact_solve(f)
+    ch = chunk if l == 0 else chunk_coarse
     for _ in range(nu_pre):
-        U = lev.smooth(U, f, omega, chunk)
+        U = lev.smooth(U, f, omega, ch)
     r = f - lev.apply(U)
     fc = restrict(r, kinds[l], lev.dim)
-    ec = vcycle(levels, kinds, np.zeros(levels[l + 1].shape), fc, omega, chunk, nu_pre, nu_post, l + 1)
+    ec = vcycle(levels, kinds, np.zeros(levels[l + 1].shape), fc, omega, chunk, nu_pre, nu_post, l + 1,
+                chunk_coarse)
     U = U + prolong(ec, kinds[l], lev.dim)
     for _ in range(nu_post):
-        U = lev.smooth(U, f, omega, chunk)
+        U = lev.smooth(U, f, omega, ch)
     return U
 
 

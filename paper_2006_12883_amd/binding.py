@@ -38,7 +38,8 @@ class Problem(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("coarsen", ctypes.c_int32), ("mu_crit", ctypes.c_double),
-                ("omega", ctypes.c_double), ("chunk", ctypes.c_int32), ("nu_pre", ctypes.c_int32),
+                ("omega", ctypes.c_double), ("chunk", ctypes.c_int32), ("chunk_coarse", ctypes.c_int32),
+                ("nu_pre", ctypes.c_int32),
                 ("nu_post", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("min_coarse", ctypes.c_int32),
                 ("max_cycles", ctypes.c_int32), ("rtol", ctypes.c_double), ("newton_rtol", ctypes.c_double),
                 ("max_newton", ctypes.c_int32), ("mem_budget", ctypes.c_size_t)]

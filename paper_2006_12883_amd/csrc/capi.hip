@@ -42,6 +42,7 @@ void stmg_default_options(stmg_options* o) {
   o->mu_crit = 0.5;
   o->omega = 0.8;
   o->chunk = 16;
+  o->chunk_coarse = 4;
   o->nu_pre = 1;
   o->nu_post = 1;
   o->max_levels = 30;

@@ -172,64 +172,74 @@ __global__ __launch_bounds__(kBlock) void k_smooth(const OpParams p, const Sweep
   const int n0 = (lb / tiles) * S;
   const int P = p.nx * p.ny;
   const int q = tile * kBlock + threadIdx.x;
-  if (q >= P || n0 >= p.N) return;
-  const int n1 = min(n0 + S, p.N);
-  const Consts<M, T> c(p);
-  const bool twod = p.ny > 1;
-  const Nbr nb = neighbours(q % p.nx, q / p.nx, p.nx, p.ny, p.bc);
-  const T dg = T(2) * c.cx + (twod ? T(2) * c.cy : T(0));
-  T* __restrict__ out = static_cast<T*>(a.out);
+  double ssq = 0.0;  // ||f - A U||^2 of the input iterate (optional output)
+  if (q < P && n0 < p.N) {
+    const int n1 = min(n0 + S, p.N);
+    const Consts<M, T> c(p);
+    const bool twod = p.ny > 1;
+    const Nbr nb = neighbours(q % p.nx, q / p.nx, p.nx, p.ny, p.bc);
+    const T dg = T(2) * c.cx + (twod ? T(2) * c.cy : T(0));
+    T* __restrict__ out = static_cast<T*>(a.out);
 
-  T prev = T(0);
-  if (n0 == 0) {
-    if (a.u0) prev = (T)a.u0[q];
-  } else if (a.U) {
-    const size_t b = (size_t)(n0 - 1) * M * P;
+    T prev = T(0);
+    if (n0 == 0) {
+      if (a.u0) prev = (T)a.u0[q];
+    } else if (a.U) {
+      const size_t b = (size_t)(n0 - 1) * M * P;
 #pragma unroll
-    for (int j = 0; j < M; ++j) prev += c.cout[j] * a.U[b + (size_t)j * P + q];
+      for (int j = 0; j < M; ++j) prev += c.cout[j] * a.U[b + (size_t)j * P + q];
+    }
+    T dprev = T(0);
+    for (int n = n0; n < n1; ++n) {
+      const size_t base = (size_t)n * M * P;
+      T u[M], lap[M], r[M];
+      if (a.U) {
+        load_point<M, T>(a.U, base, P, q, nb, twod, c.cx, c.cy, u, lap);
+      } else {
+#pragma unroll
+        for (int m = 0; m < M; ++m) u[m] = lap[m] = T(0);
+      }
+      point_residual<M, T, REACT>(c, u, lap, a.coef, a.f, base, P, q, prev, r);
+      if (a.part) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) ssq += (double)r[i] * (double)r[i];
+      }
+      if (n > n0) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) r[i] += c.cin[i] * dprev;
+      }
+      T d[M];
+      if (REACT == REACT_COEF) {
+        T cv[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          cv[i] = a.coef[base + (size_t)i * P + q];
+          d[i] = r[i];
+        }
+        point_block_solve<M, T>(c, dg, cv, d);
+      } else {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          T sm = T(0);
+#pragma unroll
+          for (int k = 0; k < M; ++k) sm += c.Bi[i][k] * r[k];
+          d[i] = sm;
+        }
+      }
+      T np = T(0), nd = T(0);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        out[base + (size_t)i * P + q] = u[i] + c.omega * d[i];
+        np += c.cout[i] * u[i];
+        nd += c.cout[i] * d[i];
+      }
+      prev = np;
+      dprev = nd;
+    }
   }
-  T dprev = T(0);
-  for (int n = n0; n < n1; ++n) {
-    const size_t base = (size_t)n * M * P;
-    T u[M], lap[M], r[M];
-    if (a.U) {
-      load_point<M, T>(a.U, base, P, q, nb, twod, c.cx, c.cy, u, lap);
-    } else {
-#pragma unroll
-      for (int m = 0; m < M; ++m) u[m] = lap[m] = T(0);
-    }
-    point_residual<M, T, REACT>(c, u, lap, a.coef, a.f, base, P, q, prev, r);
-    if (n > n0) {
-#pragma unroll
-      for (int i = 0; i < M; ++i) r[i] += c.cin[i] * dprev;
-    }
-    T d[M];
-    if (REACT == REACT_COEF) {
-      T cv[M];
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        cv[i] = a.coef[base + (size_t)i * P + q];
-        d[i] = r[i];
-      }
-      point_block_solve<M, T>(c, dg, cv, d);
-    } else {
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        T s = T(0);
-#pragma unroll
-        for (int k = 0; k < M; ++k) s += c.Bi[i][k] * r[k];
-        d[i] = s;
-      }
-    }
-    T np = T(0), nd = T(0);
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      out[base + (size_t)i * P + q] = u[i] + c.omega * d[i];
-      np += c.cout[i] * u[i];
-      nd += c.cout[i] * d[i];
-    }
-    prev = np;
-    dprev = nd;
+  if (a.part) {
+    const double t = block_sum(ssq);
+    if (threadIdx.x == 0) a.part[lb] = t;
   }
 }
 
@@ -407,6 +417,147 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const OpParams p, const Swe
   }
 }
 
+// Fused residual + space restriction with an LDS tile.  A workgroup owns a
+// TCX x TCY tile of coarse points and a run of coarse slabs.  For each fine
+// slab it evaluates the residual once at every fine point of the
+// (2 TCX + 1) x (2 TCY + 1) fine tile (coarse X = fine 2X, tile origin at fine
+// 2 X0 - 1) into LDS, then every thread applies the [1 2 1]/4 full-weighting
+// stencil of its coarse point from LDS and, with time coarsening, the
+// [1 2 1]/2 stencil over slab end points in registers.  The coupling value of
+// each fine point from the previous fine slab stays in the registers of the
+// thread that owns that fine point.
+template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY>
+__global__ __launch_bounds__(kBlock) void k_restrict_lds(const OpParams p, const SweepPtrs<T> a,
+                                                         int ncx, int ncy, int Nc,
+                                                         T* __restrict__ fc, int S, int tiles_x,
+                                                         int tiles, int nblocks) {
+  constexpr int FW = 2 * TCX + 1;
+  constexpr int FH = TWOD ? 2 * TCY + 1 : 1;
+  constexpr int NF = FW * FH;
+  constexpr int KMAX = (NF + kBlock - 1) / kBlock;
+  __shared__ T rs[M][FH][FW];
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  const int tile = lb % tiles;
+  const int J0 = (lb / tiles) * S;
+  if (J0 >= Nc) return;  // whole workgroup leaves together
+  const int J1 = min(J0 + S, Nc);
+  const int X0 = (tile % tiles_x) * TCX;
+  const int Y0 = TWOD ? (tile / tiles_x) * TCY : 0;
+  const Consts<M, T> c(p);
+  const int nx = p.nx, ny = p.ny, P = nx * ny;
+  const bool twod = ny > 1;
+  const int Pc = ncx * ncy;
+
+  // fine points owned by this thread in the LDS tile
+  int qf[KMAX];
+  Nbr nbf[KMAX];
+  T prev[KMAX];
+  const int nlo = TM ? 2 * J0 : J0;
+  const int nhi = TM ? min(2 * J1, p.N - 1) : J1 - 1;
+#pragma unroll
+  for (int kk = 0; kk < KMAX; ++kk) {
+    const int k = threadIdx.x + kk * kBlock;
+    int fx = 2 * X0 - 1 + (k % FW);
+    int fy = TWOD ? 2 * Y0 - 1 + (k / FW) : 0;
+    // periodic wrap or Neumann reflection, then clamp (points beyond the
+    // coarse grid's extent are computed but never used)
+    if (fx < 0) fx = nb_lo(0, nx, p.bc);
+    if (fx >= nx) fx = p.bc == 0 ? fx - nx : 2 * (nx - 1) - fx;
+    fx = fx < 0 ? 0 : (fx >= nx ? nx - 1 : fx);
+    if (TWOD) {
+      if (fy < 0) fy = nb_lo(0, ny, p.bc);
+      if (fy >= ny) fy = p.bc == 0 ? fy - ny : 2 * (ny - 1) - fy;
+      fy = fy < 0 ? 0 : (fy >= ny ? ny - 1 : fy);
+    }
+    qf[kk] = fy * nx + fx;
+    nbf[kk] = neighbours(fx, fy, nx, ny, p.bc);
+    prev[kk] = T(0);
+    if (k < NF) {
+      if (nlo == 0) {
+        if (a.u0) prev[kk] = (T)a.u0[qf[kk]];
+      } else if (a.U) {
+        const size_t b = (size_t)(nlo - 1) * M * P;
+#pragma unroll
+        for (int j = 0; j < M; ++j) prev[kk] += c.cout[j] * a.U[b + (size_t)j * P + qf[kk]];
+      }
+    }
+  }
+  // this thread's coarse point
+  const int tx = threadIdx.x % TCX, ty = threadIdx.x / TCX;
+  const int X = X0 + tx, Y = Y0 + ty;
+  const bool cvalid = (threadIdx.x < TCX * TCY) && X < ncx && Y < ncy;
+  const int qc = Y * ncx + X;
+  T acc[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) acc[i] = T(0);
+
+  for (int n = nlo; n <= nhi; ++n) {
+    const size_t base = (size_t)n * M * P;
+#pragma unroll
+    for (int kk = 0; kk < KMAX; ++kk) {
+      const int k = threadIdx.x + kk * kBlock;
+      if (k < NF) {
+        T u[M], lap[M], r[M];
+        if (a.U) {
+          load_point<M, T>(a.U, base, P, qf[kk], nbf[kk], twod, c.cx, c.cy, u, lap);
+        } else {
+#pragma unroll
+          for (int m = 0; m < M; ++m) u[m] = lap[m] = T(0);
+        }
+        point_residual<M, T, REACT>(c, u, lap, a.coef, a.f, base, P, qf[kk], prev[kk], r);
+        T np = T(0);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          rs[i][k / FW][k % FW] = r[i];
+          np += c.cout[i] * u[i];
+        }
+        prev[kk] = np;
+      }
+    }
+    __syncthreads();
+    if (cvalid) {
+      T rc[M];
+      const int cx0 = 2 * tx, cy0 = TWOD ? 2 * ty : 0;
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        T sx0 = T(0.25) * rs[i][cy0][cx0] + T(0.5) * rs[i][cy0][cx0 + 1] + T(0.25) * rs[i][cy0][cx0 + 2];
+        if (TWOD) {
+          const T sx1 = T(0.25) * rs[i][cy0 + 1][cx0] + T(0.5) * rs[i][cy0 + 1][cx0 + 1] +
+                        T(0.25) * rs[i][cy0 + 1][cx0 + 2];
+          const T sx2 = T(0.25) * rs[i][cy0 + 2][cx0] + T(0.5) * rs[i][cy0 + 2][cx0 + 1] +
+                        T(0.25) * rs[i][cy0 + 2][cx0 + 2];
+          sx0 = T(0.25) * sx0 + T(0.5) * sx1 + T(0.25) * sx2;
+        }
+        rc[i] = sx0;
+      }
+      if (!TM) {
+        const size_t cb = (size_t)n * M * Pc;
+#pragma unroll
+        for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = rc[i];
+      } else if (n & 1) {
+        const int J = n >> 1;
+#pragma unroll
+        for (int i = 0; i < M; ++i) acc[i] += rc[i];
+        if (J == Nc - 1) {
+          const size_t cb = (size_t)J * M * Pc;
+#pragma unroll
+          for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = acc[i];
+        }
+      } else {
+        const int J = n >> 1;
+        if (J > J0) {
+          const size_t cb = (size_t)(J - 1) * M * Pc;
+#pragma unroll
+          for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = acc[i] + T(0.5) * rc[i];
+        }
+#pragma unroll
+        for (int i = 0; i < M; ++i) acc[i] = T(0.5) * rc[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // U_out = U_in + P e_c: linear interpolation in space (fine 2X = coarse X,
 // fine 2X+1 = mean of coarse X and X+1) and in slab end points (fine 2J+1 =
 // coarse J, fine 2J = mean of coarse J-1 and J, coarse -1 = 0).
@@ -484,6 +635,556 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const OpParams p, int ncx, i
       const size_t o = base + (size_t)i * P + q;
       Uout[o] = (Uin ? Uin[o] : T(0)) + e;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Register-blocked kernels for periodic grids with even point counts.  A
+// thread owns a 2 x BY block of points (BY = 2 in 2D, 1 in 1D) and marches
+// through its slabs.  Per node and slab it issues BY + 2 two-wide row loads
+// (its own rows and the halo rows y0 - 1, y0 + BY) and 2 BY single loads for
+// the x halo, instead of five loads per point: the interior y-neighbours come
+// from its own registers.  Results are identical to the single-point kernels.
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> { using type = double2; };
+template <>
+struct Vec2<float> { using type = float2; };
+
+template <typename T>
+__device__ __forceinline__ void ld2(const T* __restrict__ p, T& a, T& b) {
+  const typename Vec2<T>::type v = *reinterpret_cast<const typename Vec2<T>::type*>(p);
+  a = v.x;
+  b = v.y;
+}
+template <typename T>
+__device__ __forceinline__ void st2(T* __restrict__ p, T a, T b) {
+  typename Vec2<T>::type v;
+  v.x = a;
+  v.y = b;
+  *reinterpret_cast<typename Vec2<T>::type*>(p) = v;
+}
+
+// Geometry of the 2 x BY block owned by thread t of a plane (periodic).
+template <int BY>
+struct Blk {
+  int x0, y0, xm, xp, ylo, yhi;
+  __device__ __forceinline__ Blk(int t, int nx, int ny) {
+    const int hx = nx >> 1;
+    x0 = (t % hx) * 2;
+    y0 = (t / hx) * BY;
+    xm = x0 > 0 ? x0 - 1 : nx - 1;
+    xp = x0 + 2 < nx ? x0 + 2 : 0;
+    ylo = y0 > 0 ? y0 - 1 : ny - 1;
+    yhi = y0 + BY < ny ? y0 + BY : 0;
+  }
+  // plane offset of block point k (k = j * 2 + i)
+  __device__ __forceinline__ int q(int k, int nx) const { return (y0 + (k >> 1)) * nx + x0 + (k & 1); }
+};
+
+// Values and scaled 5-point Laplacians of the block's points, all M nodes.
+template <int M, typename T, int BY, bool TWOD>
+__device__ __forceinline__ void load_blk(const T* __restrict__ U, size_t base, int P, int nx,
+                                         const Blk<BY>& b, T cx, T cy, T u[2 * BY][M],
+                                         T lap[2 * BY][M]) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const T* Um = U + base + (size_t)m * P;
+    T rw[BY + 2][2];
+#pragma unroll
+    for (int j = 0; j < BY; ++j) ld2(Um + (b.y0 + j) * nx + b.x0, rw[j + 1][0], rw[j + 1][1]);
+    if (TWOD) {
+      ld2(Um + b.ylo * nx + b.x0, rw[0][0], rw[0][1]);
+      ld2(Um + b.yhi * nx + b.x0, rw[BY + 1][0], rw[BY + 1][1]);
+    }
+#pragma unroll
+    for (int j = 0; j < BY; ++j) {
+      const int row = (b.y0 + j) * nx;
+      const T l = Um[row + b.xm], r = Um[row + b.xp];
+      const T c0 = rw[j + 1][0], c1 = rw[j + 1][1];
+      T l0 = cx * (l + c1 - c0 - c0);
+      T l1 = cx * (c0 + r - c1 - c1);
+      if (TWOD) {
+        l0 += cy * (rw[j][0] + rw[j + 2][0] - c0 - c0);
+        l1 += cy * (rw[j][1] + rw[j + 2][1] - c1 - c1);
+      }
+      u[2 * j][m] = c0;
+      u[2 * j + 1][m] = c1;
+      lap[2 * j][m] = l0;
+      lap[2 * j + 1][m] = l1;
+    }
+  }
+}
+
+// Loads an M-node field (f or coef) on the block's own points.
+template <int M, typename T, int BY>
+__device__ __forceinline__ void load_own(const T* __restrict__ F, size_t base, int P, int nx,
+                                         const Blk<BY>& b, T v[2 * BY][M]) {
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int j = 0; j < BY; ++j)
+      ld2(F + base + (size_t)m * P + (b.y0 + j) * nx + b.x0, v[2 * j][m], v[2 * j + 1][m]);
+}
+
+template <int M, typename T, int BY>
+__device__ __forceinline__ void store_own(T* __restrict__ F, size_t base, int P, int nx,
+                                          const Blk<BY>& b, const T v[2 * BY][M]) {
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int j = 0; j < BY; ++j)
+      st2(F + base + (size_t)m * P + (b.y0 + j) * nx + b.x0, v[2 * j][m], v[2 * j + 1][m]);
+}
+
+// Coupling value entering the run at slab n0 for every block point.
+template <int M, typename T, int BY>
+__device__ __forceinline__ void run_prev(const Consts<M, T>& c, const SweepPtrs<T>& a, int n0, int P,
+                                         int nx, const Blk<BY>& b, T prev[2 * BY]) {
+#pragma unroll
+  for (int k = 0; k < 2 * BY; ++k) prev[k] = T(0);
+  if (n0 == 0) {
+    if (a.u0) {
+#pragma unroll
+      for (int j = 0; j < BY; ++j) {
+        const double* q = a.u0 + (b.y0 + j) * nx + b.x0;
+        prev[2 * j] = (T)q[0];
+        prev[2 * j + 1] = (T)q[1];
+      }
+    }
+  } else if (a.U) {
+    T v[2 * BY][M];
+    load_own<M, T, BY>(a.U, (size_t)(n0 - 1) * M * P, P, nx, b, v);
+#pragma unroll
+    for (int k = 0; k < 2 * BY; ++k)
+#pragma unroll
+      for (int j = 0; j < M; ++j) prev[k] += c.cout[j] * v[k][j];
+  }
+}
+
+// r = f - [K u + db (react - lap) - cin prev] with preloaded f and coef.
+template <int M, typename T, int REACT>
+__device__ __forceinline__ void resid_vals(const Consts<M, T>& c, const T u[M], const T lap[M],
+                                           const T fv[M], const T cv[M], T prev, T r[M]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T au = T(0);
+#pragma unroll
+    for (int j = 0; j < M; ++j) au += c.K[i][j] * u[j];
+    T react;
+    if (REACT == REACT_CONST) react = c.lam * u[i];
+    else if (REACT == REACT_COEF) react = cv[i] * u[i];
+    else react = c.gamma * (u[i] * u[i] * u[i] - u[i]);
+    au += c.db[i] * (react - lap[i]);
+    au -= c.cin[i] * prev;
+    r[i] = fv[i] - au;
+  }
+}
+
+// Smoother (same mathematics as k_smooth) on 2 x BY blocks.
+template <int M, typename T, int REACT, int BY, bool TWOD>
+__global__ __launch_bounds__(kBlock) void k_smooth_blk(const OpParams p, const SweepPtrs<T> a, int S,
+                                                       int tiles, int nblocks) {
+  constexpr int NP = 2 * BY;
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  const int tile = lb % tiles;
+  const int n0 = (lb / tiles) * S;
+  const int nx = p.nx, P = nx * p.ny;
+  const int t = tile * kBlock + threadIdx.x;
+  double ssq = 0.0;
+  if (t < (nx >> 1) * (p.ny / BY) && n0 < p.N) {
+    const int n1 = min(n0 + S, p.N);
+    const Consts<M, T> c(p);
+    const Blk<BY> b(t, nx, p.ny);
+    const T dg = T(2) * c.cx + (TWOD ? T(2) * c.cy : T(0));
+    T* __restrict__ out = static_cast<T*>(a.out);
+    T prev[NP], dprev[NP];
+    run_prev<M, T, BY>(c, a, n0, P, nx, b, prev);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) dprev[k] = T(0);
+    for (int n = n0; n < n1; ++n) {
+      const size_t base = (size_t)n * M * P;
+      T u[NP][M], lap[NP][M], fv[NP][M], cv[NP][M], o[NP][M];
+      if (a.U) {
+        load_blk<M, T, BY, TWOD>(a.U, base, P, nx, b, c.cx, c.cy, u, lap);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) u[k][m] = lap[k][m] = T(0);
+      }
+      if (a.f) {
+        load_own<M, T, BY>(a.f, base, P, nx, b, fv);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) fv[k][m] = T(0);
+      }
+      if (REACT == REACT_COEF) load_own<M, T, BY>(a.coef, base, P, nx, b, cv);
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        T r[M], d[M];
+        resid_vals<M, T, REACT>(c, u[k], lap[k], fv[k], cv[k], prev[k], r);
+        if (a.part) {
+#pragma unroll
+          for (int i = 0; i < M; ++i) ssq += (double)r[i] * (double)r[i];
+        }
+        if (n > n0) {
+#pragma unroll
+          for (int i = 0; i < M; ++i) r[i] += c.cin[i] * dprev[k];
+        }
+        if (REACT == REACT_COEF) {
+#pragma unroll
+          for (int i = 0; i < M; ++i) d[i] = r[i];
+          point_block_solve<M, T>(c, dg, cv[k], d);
+        } else {
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            T sm = T(0);
+#pragma unroll
+            for (int j = 0; j < M; ++j) sm += c.Bi[i][j] * r[j];
+            d[i] = sm;
+          }
+        }
+        T np = T(0), nd = T(0);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          o[k][i] = u[k][i] + c.omega * d[i];
+          np += c.cout[i] * u[k][i];
+          nd += c.cout[i] * d[i];
+        }
+        prev[k] = np;
+        dprev[k] = nd;
+      }
+      store_own<M, T, BY>(out, base, P, nx, b, o);
+    }
+  }
+  if (a.part) {
+    const double tt = block_sum(ssq);
+    if (threadIdx.x == 0) a.part[lb] = tt;
+  }
+}
+
+// Residual (optionally stored as TO) with per-block partial sums of r^2.
+template <int M, typename T, typename TO, int REACT, int BY, bool TWOD>
+__global__ __launch_bounds__(kBlock) void k_residual_blk(const OpParams p, const SweepPtrs<T> a, int S,
+                                                         int tiles, int nblocks) {
+  constexpr int NP = 2 * BY;
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  const int tile = lb % tiles;
+  const int n0 = (lb / tiles) * S;
+  const int nx = p.nx, P = nx * p.ny;
+  const int t = tile * kBlock + threadIdx.x;
+  double ssq = 0.0;
+  if (t < (nx >> 1) * (p.ny / BY) && n0 < p.N) {
+    const int n1 = min(n0 + S, p.N);
+    const Consts<M, T> c(p);
+    const Blk<BY> b(t, nx, p.ny);
+    TO* __restrict__ out = static_cast<TO*>(a.out);
+    T prev[NP];
+    run_prev<M, T, BY>(c, a, n0, P, nx, b, prev);
+    for (int n = n0; n < n1; ++n) {
+      const size_t base = (size_t)n * M * P;
+      T u[NP][M], lap[NP][M], fv[NP][M], cv[NP][M];
+      TO o[NP][M];
+      if (a.U) {
+        load_blk<M, T, BY, TWOD>(a.U, base, P, nx, b, c.cx, c.cy, u, lap);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) u[k][m] = lap[k][m] = T(0);
+      }
+      if (a.f) {
+        load_own<M, T, BY>(a.f, base, P, nx, b, fv);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) fv[k][m] = T(0);
+      }
+      if (REACT == REACT_COEF) load_own<M, T, BY>(a.coef, base, P, nx, b, cv);
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        T r[M];
+        resid_vals<M, T, REACT>(c, u[k], lap[k], fv[k], cv[k], prev[k], r);
+        T np = T(0);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          ssq += (double)r[i] * (double)r[i];
+          o[k][i] = (TO)r[i];
+          np += c.cout[i] * u[k][i];
+        }
+        prev[k] = np;
+      }
+      if (out) store_own<M, TO, BY>(out, base, P, nx, b, o);
+    }
+  }
+  if (a.part) {
+    const double tt = block_sum(ssq);
+    if (threadIdx.x == 0) a.part[lb] = tt;
+  }
+}
+
+// Fused residual + restriction on 2 x BY blocks with an LDS tile.  A
+// workgroup owns TCX x TCY coarse points; its 256 threads own the 2 x BY
+// fine blocks whose lower-left point is fine (2X, 2Y), so the fine tile is
+// (2 TCX) x (BY TCY) owned points plus one halo column (fine x = 2 X0 - 1)
+// and, in 2D, one halo row (fine y = 2 Y0 - 1); the halo residuals are
+// computed by single-point work items.  Space coarsening only (the time
+// stencil, if any, is applied in registers as in k_restrict_lds).
+template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY>
+__global__ __launch_bounds__(kBlock) void k_restrict_blk(const OpParams p, const SweepPtrs<T> a,
+                                                         int ncx, int ncy, int Nc,
+                                                         T* __restrict__ fc, int S, int tiles_x,
+                                                         int tiles, int nblocks) {
+  constexpr int BY = TWOD ? 2 : 1;
+  constexpr int FW = 2 * TCX + 1;
+  constexpr int FH = TWOD ? 2 * TCY + 1 : 1;
+  constexpr int NHALO = TWOD ? FW + FH - 1 : 1;  // halo column + halo row (corner once)
+  static_assert(TCX * TCY == kBlock, "one owned fine block per thread");
+  __shared__ T rs[M][FH][FW];
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  const int tile = lb % tiles;
+  const int J0 = (lb / tiles) * S;
+  if (J0 >= Nc) return;
+  const int J1 = min(J0 + S, Nc);
+  const int X0 = (tile % tiles_x) * TCX;
+  const int Y0 = TWOD ? (tile / tiles_x) * TCY : 0;
+  const Consts<M, T> c(p);
+  const int nx = p.nx, ny = p.ny, P = nx * ny;
+  const int Pc = ncx * ncy;
+  const int tx = threadIdx.x % TCX, ty = threadIdx.x / TCX;
+  const int X = X0 + tx, Y = Y0 + ty;
+  const bool own = X < ncx && Y < ncy;  // this thread's coarse point (and fine block) exists
+  const int nlo = TM ? 2 * J0 : J0;
+  const int nhi = TM ? min(2 * J1, p.N - 1) : J1 - 1;
+
+  // owned block: fine (2X .. 2X+1) x (2Y .. 2Y+1) (1D: 2X .. 2X+1), the
+  // block with plane index Y (nx / 2) + X
+  const Blk<BY> b(own ? (TWOD ? Y : 0) * (nx >> 1) + X : 0, nx, ny);
+  T prev[2 * BY];
+#pragma unroll
+  for (int k = 0; k < 2 * BY; ++k) prev[k] = T(0);
+  if (own) run_prev<M, T, BY>(c, a, nlo, P, nx, b, prev);
+  // halo work item of this thread (if any)
+  const int hk = threadIdx.x;
+  const bool hown = hk < NHALO;
+  int hq = 0;
+  Nbr hn{0, 0, 0, 0};
+  bool hvalid = false;
+  int hx = 0, hy = 0;  // LDS coordinates
+  if (hown) {
+    int fx, fy;
+    if (hk < FH) {  // halo column, tile x = 0, tile y = hk
+      hx = 0; hy = hk;
+      fx = 2 * X0 - 1;
+      fy = TWOD ? 2 * Y0 - 1 + hk : 0;
+    } else {        // halo row, tile y = 0, tile x = hk - FH + 1
+      hx = hk - FH + 1; hy = 0;
+      fx = 2 * X0 - 1 + hx;
+      fy = 2 * Y0 - 1;
+    }
+    if (fx < 0) fx += nx;
+    if (fy < 0) fy += ny;
+    // only needed if a coarse point of this tile uses it
+    const int cxn = min(TCX, ncx - X0), cyn = TWOD ? min(TCY, ncy - Y0) : 1;
+    hvalid = hx <= 2 * cxn && hy <= (TWOD ? 2 * cyn : 0) && fx < nx && fy < ny;
+    if (hvalid) {
+      hq = fy * nx + fx;
+      hn = neighbours(fx, fy, nx, ny, 0);
+    }
+  }
+  T hprev = T(0);
+  if (hvalid) {
+    if (nlo == 0) {
+      if (a.u0) hprev = (T)a.u0[hq];
+    } else if (a.U) {
+      const size_t bb = (size_t)(nlo - 1) * M * P;
+#pragma unroll
+      for (int j = 0; j < M; ++j) hprev += c.cout[j] * a.U[bb + (size_t)j * P + hq];
+    }
+  }
+  T acc[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) acc[i] = T(0);
+  const int qc = Y * ncx + X;
+  for (int n = nlo; n <= nhi; ++n) {
+    const size_t base = (size_t)n * M * P;
+    if (own) {
+      T u[2 * BY][M], lap[2 * BY][M], fv[2 * BY][M], cv[2 * BY][M];
+      if (a.U) {
+        load_blk<M, T, BY, TWOD>(a.U, base, P, nx, b, c.cx, c.cy, u, lap);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 2 * BY; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) u[k][m] = lap[k][m] = T(0);
+      }
+      if (a.f) {
+        load_own<M, T, BY>(a.f, base, P, nx, b, fv);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 2 * BY; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) fv[k][m] = T(0);
+      }
+      if (REACT == REACT_COEF) load_own<M, T, BY>(a.coef, base, P, nx, b, cv);
+#pragma unroll
+      for (int k = 0; k < 2 * BY; ++k) {
+        T r[M];
+        resid_vals<M, T, REACT>(c, u[k], lap[k], fv[k], cv[k], prev[k], r);
+        T np = T(0);
+        const int lx = 2 * tx + 1 + (k & 1), ly = TWOD ? 2 * ty + 1 + (k >> 1) : 0;
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          rs[i][ly][lx] = r[i];
+          np += c.cout[i] * u[k][i];
+        }
+        prev[k] = np;
+      }
+    }
+    if (hvalid) {
+      T u[M], lap[M], r[M];
+      if (a.U) {
+        load_point<M, T>(a.U, base, P, hq, hn, TWOD, c.cx, c.cy, u, lap);
+      } else {
+#pragma unroll
+        for (int m = 0; m < M; ++m) u[m] = lap[m] = T(0);
+      }
+      point_residual<M, T, REACT>(c, u, lap, a.coef, a.f, base, P, hq, hprev, r);
+      T np = T(0);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        rs[i][hy][hx] = r[i];
+        np += c.cout[i] * u[i];
+      }
+      hprev = np;
+    }
+    __syncthreads();
+    if (own) {
+      T rc[M];
+      const int cx0 = 2 * tx, cy0 = TWOD ? 2 * ty : 0;
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        T sx0 = T(0.25) * rs[i][cy0][cx0] + T(0.5) * rs[i][cy0][cx0 + 1] + T(0.25) * rs[i][cy0][cx0 + 2];
+        if (TWOD) {
+          const T sx1 = T(0.25) * rs[i][cy0 + 1][cx0] + T(0.5) * rs[i][cy0 + 1][cx0 + 1] +
+                        T(0.25) * rs[i][cy0 + 1][cx0 + 2];
+          const T sx2 = T(0.25) * rs[i][cy0 + 2][cx0] + T(0.5) * rs[i][cy0 + 2][cx0 + 1] +
+                        T(0.25) * rs[i][cy0 + 2][cx0 + 2];
+          sx0 = T(0.25) * sx0 + T(0.5) * sx1 + T(0.25) * sx2;
+        }
+        rc[i] = sx0;
+      }
+      if (!TM) {
+        const size_t cb = (size_t)n * M * Pc;
+#pragma unroll
+        for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = rc[i];
+      } else if (n & 1) {
+        const int J = n >> 1;
+#pragma unroll
+        for (int i = 0; i < M; ++i) acc[i] += rc[i];
+        if (J == Nc - 1) {
+          const size_t cb = (size_t)J * M * Pc;
+#pragma unroll
+          for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = acc[i];
+        }
+      } else {
+        const int J = n >> 1;
+        if (J > J0) {
+          const size_t cb = (size_t)(J - 1) * M * Pc;
+#pragma unroll
+          for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = acc[i] + T(0.5) * rc[i];
+        }
+#pragma unroll
+        for (int i = 0; i < M; ++i) acc[i] = T(0.5) * rc[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Prolongation + correction on 2 x BY fine blocks (space coarsening: the
+// block of coarse point (X, Y) is fine (2X .. 2X+1) x (2Y .. 2Y+1); time
+// interpolation as in k_prolong).
+template <int M, typename T, bool SP, bool TM, int BY, bool TWOD>
+__global__ __launch_bounds__(kBlock) void k_prolong_blk(const OpParams p, int ncx, int ncy, int Nc,
+                                                        const T* __restrict__ ec,
+                                                        const T* __restrict__ Uin,
+                                                        T* __restrict__ Uout, int S, int tiles,
+                                                        int nblocks) {
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  const int tile = lb % tiles;
+  const int n0 = (lb / tiles) * S;
+  const int nx = p.nx, ny = p.ny, P = nx * ny;
+  const int t = tile * kBlock + threadIdx.x;
+  if (t >= (nx >> 1) * (ny / BY) || n0 >= p.N) return;
+  const int n1 = min(n0 + S, p.N);
+  const int Pc = ncx * ncy;
+  const Blk<BY> b(t, nx, ny);
+  // coarse points feeding the block
+  int c00, c10, c01, c11;
+  if (SP) {
+    const int X = b.x0 >> 1, Y = TWOD ? (b.y0 >> 1) : 0;
+    const int X1 = X + 1 < ncx ? X + 1 : 0, Y1 = TWOD ? (Y + 1 < ncy ? Y + 1 : 0) : 0;
+    c00 = Y * ncx + X; c10 = Y * ncx + X1; c01 = Y1 * ncx + X; c11 = Y1 * ncx + X1;
+  } else {
+    c00 = c10 = c01 = c11 = 0;
+  }
+  for (int n = n0; n < n1; ++n) {
+    int js[2];
+    T wt[2];
+    int nt;
+    if (!TM) { js[0] = n; wt[0] = T(1); nt = 1; }
+    else if (n & 1) { js[0] = n >> 1; wt[0] = T(1); nt = 1; }
+    else {
+      const int J = n >> 1;
+      js[0] = J; wt[0] = T(0.5); nt = 1;
+      if (J > 0) { js[1] = J - 1; wt[1] = T(0.5); nt = 2; }
+    }
+    const size_t base = (size_t)n * M * P;
+    T v[2 * BY][M];
+    if (Uin) load_own<M, T, BY>(Uin, base, P, nx, b, v);
+    else {
+#pragma unroll
+      for (int k = 0; k < 2 * BY; ++k)
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[k][m] = T(0);
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      T e[2 * BY];
+#pragma unroll
+      for (int k = 0; k < 2 * BY; ++k) e[k] = T(0);
+      for (int tt = 0; tt < nt; ++tt) {
+        const T* Ec = ec + (size_t)js[tt] * M * Pc + (size_t)m * Pc;
+        if (SP) {
+          const T a00 = Ec[c00], a10 = Ec[c10];
+          e[0] += wt[tt] * a00;
+          e[1] += wt[tt] * (T(0.5) * (a00 + a10));
+          if (TWOD) {
+            const T a01 = Ec[c01], a11 = Ec[c11];
+            e[2] += wt[tt] * (T(0.5) * (a00 + a01));
+            e[3] += wt[tt] * (T(0.25) * (a00 + a10 + a01 + a11));
+          }
+        } else {
+          // time only: same spatial grid
+          T a0, a1;
+#pragma unroll
+          for (int j = 0; j < BY; ++j) {
+            ld2(Ec + (b.y0 + j) * nx + b.x0, a0, a1);
+            e[2 * j] += wt[tt] * a0;
+            e[2 * j + 1] += wt[tt] * a1;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 2 * BY; ++k) v[k][m] += e[k];
+    }
+    store_own<M, T, BY>(Uout, base, P, nx, b, v);
   }
 }
 
@@ -800,13 +1501,35 @@ int grid_for(size_t n) {
     default: return hipErrorInvalidValue; \
   }
 
+// The register-blocked kernels cover periodic grids with even point counts.
+static bool blocked(const OpParams& p) {
+  return p.bc == 0 && (p.nx % 2) == 0 && (p.ny == 1 || (p.ny % 2) == 0);
+}
+static int plane_threads(const OpParams& p) {
+  if (blocked(p)) return (p.nx / 2) * (p.ny > 1 ? p.ny / 2 : 1);
+  return p.nx * p.ny;
+}
+
+int smooth_blocks(const OpParams& p, int chunk) {
+  return ((plane_threads(p) + kBlock - 1) / kBlock) * ((p.N + chunk - 1) / chunk);
+}
+
 template <typename T>
 hipError_t launch_smooth(const OpParams& p, int react, const SweepPtrs<T>& a, int chunk,
                          hipStream_t s) {
-  const int P = p.nx * p.ny;
-  const int tiles = (P + kBlock - 1) / kBlock;
-  const int chunks = (p.N + chunk - 1) / chunk;
-  const int nb = tiles * chunks;
+  const int nb = smooth_blocks(p, chunk);
+  const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
+  if (blocked(p)) {
+#define LB(MM, RE, BYc, TWc) \
+  hipLaunchKernelGGL((k_smooth_blk<MM, T, RE, BYc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, a, chunk, tiles, nb)
+#define L(MM)                                                                 \
+  if (p.ny > 1) { if (react == REACT_COEF) LB(MM, REACT_COEF, 2, true); else LB(MM, REACT_CONST, 2, true); } \
+  else { if (react == REACT_COEF) LB(MM, REACT_COEF, 1, false); else LB(MM, REACT_CONST, 1, false); }
+    STMG_DISPATCH_M(L)
+#undef L
+#undef LB
+    return hipGetLastError();
+  }
 #define L(MM)                                                                                   \
   if (react == REACT_COEF)                                                                      \
     hipLaunchKernelGGL((k_smooth<MM, T, REACT_COEF>), dim3(nb), dim3(kBlock), 0, s, p, a, chunk, \
@@ -822,11 +1545,26 @@ hipError_t launch_smooth(const OpParams& p, int react, const SweepPtrs<T>& a, in
 template <typename T, typename TO>
 hipError_t launch_residual(const OpParams& p, int react, const SweepPtrs<T>& a, int spb,
                            int* nparts, hipStream_t s) {
-  const int P = p.nx * p.ny;
-  const int tiles = (P + kBlock - 1) / kBlock;
+  const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
   const int chunks = (p.N + spb - 1) / spb;
   const int nb = tiles * chunks;
   if (nparts) *nparts = nb;
+  if (blocked(p)) {
+#define LB(MM, RE, BYc, TWc)                                                                     \
+  hipLaunchKernelGGL((k_residual_blk<MM, T, TO, RE, BYc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, a, \
+                     spb, tiles, nb)
+#define LBR(MM, BYc, TWc)                                                    \
+  if (react == REACT_COEF) LB(MM, REACT_COEF, BYc, TWc);                     \
+  else if (react == REACT_AC) LB(MM, REACT_AC, BYc, TWc);                    \
+  else LB(MM, REACT_CONST, BYc, TWc);
+#define L(MM) \
+  if (p.ny > 1) { LBR(MM, 2, true) } else { LBR(MM, 1, false) }
+    STMG_DISPATCH_M(L)
+#undef L
+#undef LBR
+#undef LB
+    return hipGetLastError();
+  }
 #define L(MM)                                                                                    \
   if (react == REACT_COEF)                                                                       \
     hipLaunchKernelGGL((k_residual<MM, T, TO, REACT_COEF>), dim3(nb), dim3(kBlock), 0, s, p, a,   \
@@ -846,30 +1584,80 @@ template <typename T>
 hipError_t launch_restrict_residual(const OpParams& p, int react, const SweepPtrs<T>& a,
                                     bool space, bool time, int ncx, int ncy, int Nc, T* fc,
                                     int spb, hipStream_t s) {
+  const bool twod = p.ny > 1;
+  if (space && blocked(p) && p.M <= 4) {
+    // register-blocked fine tiles, 16 x 16 coarse points (2D) or 256 (1D)
+    const int tcx = twod ? 16 : 256;
+    const int tcy = twod ? 16 : 1;
+    const int tiles_x = (ncx + tcx - 1) / tcx;
+    const int tiles = tiles_x * ((ncy + tcy - 1) / tcy);
+    const int nb = tiles * ((Nc + spb - 1) / spb);
+#define LRB(MM, RE, TMc, TWc, CX, CY)                                                         \
+  hipLaunchKernelGGL((k_restrict_blk<MM, T, RE, TMc, TWc, CX, CY>), dim3(nb), dim3(kBlock), 0, s, \
+                     p, a, ncx, ncy, Nc, fc, spb, tiles_x, tiles, nb)
+#define LRBE(MM, RE)                                          \
+  if (twod) {                                                 \
+    if (time) LRB(MM, RE, true, true, 16, 16);                \
+    else LRB(MM, RE, false, true, 16, 16);                    \
+  } else {                                                    \
+    if (time) LRB(MM, RE, true, false, 256, 1);               \
+    else LRB(MM, RE, false, false, 256, 1);                   \
+  }
+#define LB4(MM) \
+  if (react == REACT_COEF) { LRBE(MM, REACT_COEF) } else { LRBE(MM, REACT_CONST) }
+    switch (p.M) {
+      case 1: LB4(1); break;
+      case 2: LB4(2); break;
+      case 3: LB4(3); break;
+      case 4: LB4(4); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef LB4
+#undef LRBE
+#undef LRB
+    return hipGetLastError();
+  }
+  if (space) {
+    // LDS-tiled kernel: coarse tiles of 16 x 16 (M <= 4) or 16 x 8 in 2D, 256 in 1D
+    const int tcx = twod ? 16 : 256;
+    const int tcy = twod ? (p.M <= 4 ? 16 : 8) : 1;
+    const int tiles_x = (ncx + tcx - 1) / tcx;
+    const int tiles_y = (ncy + tcy - 1) / tcy;
+    const int tiles = tiles_x * tiles_y;
+    const int chunks = (Nc + spb - 1) / spb;
+    const int nb = tiles * chunks;
+#define LRS(MM, RE, TMc, TWc, CX, CY)                                                        \
+  hipLaunchKernelGGL((k_restrict_lds<MM, T, RE, TMc, TWc, CX, CY>), dim3(nb), dim3(kBlock), 0, s, \
+                     p, a, ncx, ncy, Nc, fc, spb, tiles_x, tiles, nb)
+#define LRSE(MM, RE, CY)                                     \
+  if (twod) {                                                \
+    if (time) LRS(MM, RE, true, true, 16, CY);               \
+    else LRS(MM, RE, false, true, 16, CY);                   \
+  } else {                                                   \
+    if (time) LRS(MM, RE, true, false, 256, 1);              \
+    else LRS(MM, RE, false, false, 256, 1);                  \
+  }
+#define L(MM)                                                                     \
+  if (react == REACT_COEF) { LRSE(MM, REACT_COEF, (MM <= 4 ? 16 : 8)) }           \
+  else { LRSE(MM, REACT_CONST, (MM <= 4 ? 16 : 8)) }
+    STMG_DISPATCH_M(L)
+#undef L
+#undef LRSE
+#undef LRS
+    return hipGetLastError();
+  }
   const int Pc = ncx * ncy;
   const int tiles = (Pc + kBlock - 1) / kBlock;
   const int chunks = (Nc + spb - 1) / spb;
   const int nb = tiles * chunks;
-  const bool twod = p.ny > 1;
-#define LR(MM, RE, SPc, TMc, TWc)                                                             \
-  hipLaunchKernelGGL((k_restrict<MM, T, RE, SPc, TMc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, a, \
-                     ncx, ncy, Nc, fc, spb, tiles, nb)
-#define LRE(MM, RE)                                                   \
-  if (space && time) {                                                \
-    if (twod) LR(MM, RE, true, true, true); else LR(MM, RE, true, true, false);   \
-  } else if (space) {                                                 \
-    if (twod) LR(MM, RE, true, false, true); else LR(MM, RE, true, false, false); \
-  } else if (time) {                                                  \
-    LR(MM, RE, false, true, false);                                   \
-  } else {                                                            \
-    LR(MM, RE, false, false, false);                                  \
-  }
-#define L(MM)                                         \
-  if (react == REACT_COEF) { LRE(MM, REACT_COEF) }    \
-  else { LRE(MM, REACT_CONST) }
+#define LR(MM, RE, TMc)                                                                        \
+  hipLaunchKernelGGL((k_restrict<MM, T, RE, false, TMc, false>), dim3(nb), dim3(kBlock), 0, s, p, \
+                     a, ncx, ncy, Nc, fc, spb, tiles, nb)
+#define L(MM)                                                             \
+  if (react == REACT_COEF) { if (time) LR(MM, REACT_COEF, true); else LR(MM, REACT_COEF, false); } \
+  else { if (time) LR(MM, REACT_CONST, true); else LR(MM, REACT_CONST, false); }
   STMG_DISPATCH_M(L)
 #undef L
-#undef LRE
 #undef LR
   return hipGetLastError();
 }
@@ -877,11 +1665,27 @@ hipError_t launch_restrict_residual(const OpParams& p, int react, const SweepPtr
 template <typename T>
 hipError_t launch_prolong(const OpParams& p, bool space, bool time, int ncx, int ncy, int Nc,
                           const T* ec, const T* Uin, T* Uout, int spb, hipStream_t s) {
-  const int P = p.nx * p.ny;
-  const int tiles = (P + kBlock - 1) / kBlock;
+  const bool twod = p.ny > 1;
+  const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
   const int chunks = (p.N + spb - 1) / spb;
   const int nb = tiles * chunks;
-  const bool twod = p.ny > 1;
+  if (blocked(p)) {
+#define LPB(MM, SPc, TMc, BYc, TWc)                                                             \
+  hipLaunchKernelGGL((k_prolong_blk<MM, T, SPc, TMc, BYc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, \
+                     ncx, ncy, Nc, ec, Uin, Uout, spb, tiles, nb)
+#define LPS(MM, BYc, TWc)                                 \
+  if (space && time) LPB(MM, true, true, BYc, TWc);       \
+  else if (space) LPB(MM, true, false, BYc, TWc);         \
+  else if (time) LPB(MM, false, true, BYc, TWc);          \
+  else LPB(MM, false, false, BYc, TWc);
+#define L(MM) \
+  if (twod) { LPS(MM, 2, true) } else { LPS(MM, 1, false) }
+    STMG_DISPATCH_M(L)
+#undef L
+#undef LPS
+#undef LPB
+    return hipGetLastError();
+  }
 #define LP(MM, SPc, TMc, TWc)                                                                  \
   hipLaunchKernelGGL((k_prolong<MM, T, SPc, TMc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, ncx, ncy, \
                      Nc, ec, Uin, Uout, spb, tiles, nb)

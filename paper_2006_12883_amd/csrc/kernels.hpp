@@ -43,10 +43,12 @@ struct SweepPtrs {
   const double* u0;  // value entering slab 0 through the coupling; may be null
   const T* coef;     // REACT_COEF: per-DOF reaction coefficient
   void* out;         // smoother: new iterate (T); residual: r (type TO), may be null
-  double* part;      // residual: per-block partial sums of r^2, may be null
+  double* part;      // per-block partial sums of ||f - A U||^2 (input iterate), may be null
 };
 
 // Launchers return hipSuccess or the launch error.
+// Workgroups of a smoothing sweep (= partial sums written when a.part is set).
+int smooth_blocks(const OpParams& p, int chunk);
 template <typename T>
 hipError_t launch_smooth(const OpParams& p, int react, const SweepPtrs<T>& a,
                          int chunk, hipStream_t s);

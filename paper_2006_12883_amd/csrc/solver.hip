@@ -61,7 +61,7 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     set_error("length must be > 0");
     return STMG_EINVAL;
   }
-  if (o->chunk < 1 || o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1 ||
+  if (o->chunk < 1 || o->chunk_coarse < 1 || o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1 ||
       o->max_levels < 1 || o->max_cycles < 1 || !(o->rtol > 0.0) || !(o->omega > 0.0)) {
     set_error("invalid options");
     return STMG_EINVAL;
@@ -193,6 +193,8 @@ size_t Solver::plan(char* ws) {
     const int tiles = (l.nx * l.ny + kBlock - 1) / kBlock;
     const int chunks = (l.N + kResidSlabs - 1) / kResidSlabs;
     max_parts = tiles * chunks;
+    const int sb = smooth_blocks(l.op, chunk_of(0));
+    if (max_parts < sb) max_parts = sb;
     if (max_parts < 1024) max_parts = 1024;
   }
   part = pl.take<double>(static_cast<size_t>(max_parts));
@@ -246,6 +248,18 @@ int Solver::upload() {
 }
 
 // ---------------------------------------------------------------------------
+int Solver::chunk_of(int l) const { return l == 0 ? opt.chunk : opt.chunk_coarse; }
+
+// Slabs per thread in the transfer kernels of level l: long runs on big
+// levels (fewer re-reads at run boundaries), single slabs on small levels
+// (more parallelism; their cost is latency, not bandwidth).  No effect on
+// results.
+int Solver::transfer_slabs(int l) const {
+  const Level& L = lv[l];
+  const long long pts = static_cast<long long>(L.nx) * L.ny;
+  return pts * L.N >= (1LL << 22) ? kTransferSlabs : 1;
+}
+
 template <typename T>
 static const T* coef_of(const Level& l);
 template <>
@@ -258,7 +272,7 @@ hipError_t Solver::smooth(int l, bool adj, int react, const T* U, const T* f, co
                           T* out) {
   const Level& L = lv[l];
   SweepPtrs<T> a{U, f, u0, coef_of<T>(L), out, nullptr};
-  return launch_smooth<T>(adj ? L.opT : L.op, react, a, opt.chunk, stream);
+  return launch_smooth<T>(adj ? L.opT : L.op, react, a, chunk_of(l), stream);
 }
 
 template <typename T>
@@ -268,7 +282,8 @@ hipError_t Solver::restrict_residual(int l, bool adj, int react, const T* U, con
   const Level& C = lv[l + 1];
   SweepPtrs<T> a{U, f, u0, coef_of<T>(L), nullptr, nullptr};
   return launch_restrict_residual<T>(adj ? L.opT : L.op, react, a, (L.kind & 1) != 0,
-                                     (L.kind & 2) != 0, C.nx, C.ny, C.N, fc, kTransferSlabs, stream);
+                                     (L.kind & 2) != 0, C.nx, C.ny, C.N, fc, transfer_slabs(l + 1),
+                                     stream);
 }
 
 template <typename T>
@@ -276,7 +291,7 @@ hipError_t Solver::prolong(int l, const T* Uin, const T* ec, T* Uout) {
   const Level& L = lv[l];
   const Level& C = lv[l + 1];
   return launch_prolong<T>(L.op, (L.kind & 1) != 0, (L.kind & 2) != 0, C.nx, C.ny, C.N, ec, Uin,
-                           Uout, kTransferSlabs, stream);
+                           Uout, transfer_slabs(l), stream);
 }
 
 template <typename T>
@@ -290,14 +305,14 @@ hipError_t Solver::coarse(bool adj, int react, const T* f, const double* u0, T* 
 
 template <typename T>
 hipError_t Solver::vcycle(int l, bool adj, int react, T* cur, T* oth, const T* f,
-                          const double* u0, bool zero, T** res) {
+                          const double* u0, bool zero, T** res, int skip_pre) {
   const int last = static_cast<int>(lv.size()) - 1;
   if (l == last) {
     HIP_TRY(coarse<T>(adj, react, f, u0, cur));
     *res = cur;
     return hipSuccess;
   }
-  for (int s = 0; s < opt.nu_pre; ++s) {
+  for (int s = skip_pre; s < opt.nu_pre; ++s) {
     HIP_TRY(smooth<T>(l, adj, react, zero ? nullptr : cur, f, u0, oth));
     std::swap(cur, oth);
     zero = false;
@@ -310,7 +325,7 @@ hipError_t Solver::vcycle(int l, bool adj, int react, T* cur, T* oth, const T* f
   else { cf = C.f32; ca = C.A32; cb = C.B32; }
   HIP_TRY(restrict_residual<T>(l, adj, react, zero ? nullptr : cur, f, u0, cf));
   T* ec = nullptr;
-  HIP_TRY(vcycle<T>(l + 1, adj, react, ca, cb, cf, nullptr, true, &ec));
+  HIP_TRY(vcycle<T>(l + 1, adj, react, ca, cb, cf, nullptr, true, &ec, 0));
   // Keep an even number of buffer flips so that level 0 ends where it began.
   const bool flip = ((opt.nu_pre + opt.nu_post) & 1) != 0;
   if (flip) {
@@ -369,42 +384,63 @@ double Solver::norm_u0_b(const double* u0) {
 int Solver::solve_linear(bool adj, int react, const double* f, const double* u0, double* U,
                          double rtol, double norm_b, int* cycles, double* rel_out) {
   Level& L0 = lv[0];
-  double rn2 = 0.0;
-  if (!mixed) {
-    HIP_CHECK(residual64<double>(adj, react, U, f, u0, nullptr, scal));
-  } else {
-    HIP_CHECK(residual64<float>(adj, react, U, f, u0, L0.f32, scal));
-  }
-  int rc = read_scalar(scal, &rn2);
+  const OpParams& op0 = adj ? L0.opT : L0.op;
+  // FP64 with pre-smoothing: the first sweep of every cycle also returns
+  // ||f - A U_k|| of the incoming iterate U_k, which stays untouched in `U`
+  // (the sweep writes the ping-pong partner), so the stop test costs no extra
+  // pass over the data.
+  const bool fused = !mixed && opt.nu_pre >= 1;
+  auto norm_now = [&](double* rel) -> int {
+    double rn2 = 0.0;
+    if (fused) {
+      SweepPtrs<double> a{U, f, u0, L0.coef64, L0.B64, part};
+      HIP_CHECK(launch_smooth<double>(op0, react, a, chunk_of(0), stream));
+      HIP_CHECK(launch_sum_partials(part, smooth_blocks(op0, chunk_of(0)), scal, stream));
+    } else if (!mixed) {
+      HIP_CHECK(residual64<double>(adj, react, U, f, u0, nullptr, scal));
+    } else {
+      HIP_CHECK(residual64<float>(adj, react, U, f, u0, L0.f32, scal));
+    }
+    int rc = read_scalar(scal, &rn2);
+    if (rc) return rc;
+    *rel = norm_b > 0.0 ? std::sqrt(rn2) / norm_b : std::sqrt(rn2);
+    return STMG_OK;
+  };
+  double rel = 0.0;
+  int rc = norm_now(&rel);
   if (rc) return rc;
-  double rel = norm_b > 0.0 ? std::sqrt(rn2) / norm_b : std::sqrt(rn2);
   const double rel0 = rel;
   double prev = rel;
   int incr = 0;
   int c = 0;
   int status = STMG_OK;
-  while (rel > rtol) {
+  for (;;) {
+    if (!std::isfinite(rel)) { status = STMG_ENAN; break; }
+    if (rel <= rtol) break;
+    if (c > 0) {
+      if (rel > 1e3 * (rel0 > 0 ? rel0 : 1.0)) { status = STMG_EDIVERGED; break; }
+      incr = rel > prev ? incr + 1 : 0;
+      if (incr >= 5) { status = STMG_EDIVERGED; break; }
+    }
+    prev = rel;
     if (c >= opt.max_cycles) { status = STMG_ENOTCONV; break; }
-    if (!mixed) {
+    if (fused) {
+      // the first pre-smoothing sweep already sits in L0.B64
       double* res = nullptr;
-      HIP_CHECK(vcycle<double>(0, adj, react, U, L0.B64, f, u0, false, &res));
+      HIP_CHECK(vcycle<double>(0, adj, react, L0.B64, U, f, u0, false, &res, 1));
       if (res != U) HIP_CHECK(hipMemcpyAsync(U, res, L0.n * sizeof(double), hipMemcpyDeviceToDevice, stream));
-      HIP_CHECK(residual64<double>(adj, react, U, f, u0, nullptr, scal));
+    } else if (!mixed) {
+      double* res = nullptr;
+      HIP_CHECK(vcycle<double>(0, adj, react, U, L0.B64, f, u0, false, &res, 0));
+      if (res != U) HIP_CHECK(hipMemcpyAsync(U, res, L0.n * sizeof(double), hipMemcpyDeviceToDevice, stream));
     } else {
       float* res = nullptr;
-      HIP_CHECK(vcycle<float>(0, adj, react, L0.A32, L0.B32, L0.f32, nullptr, true, &res));
+      HIP_CHECK(vcycle<float>(0, adj, react, L0.A32, L0.B32, L0.f32, nullptr, true, &res, 0));
       HIP_CHECK(launch_update<float>(L0.n, U, res, nullptr, stream));
-      HIP_CHECK(residual64<float>(adj, react, U, f, u0, L0.f32, scal));
     }
     ++c;
-    rc = read_scalar(scal, &rn2);
+    rc = norm_now(&rel);
     if (rc) return rc;
-    rel = norm_b > 0.0 ? std::sqrt(rn2) / norm_b : std::sqrt(rn2);
-    if (!std::isfinite(rel)) { status = STMG_ENAN; break; }
-    if (rel > 1e3 * (rel0 > 0 ? rel0 : 1.0)) { status = STMG_EDIVERGED; break; }
-    incr = rel > prev ? incr + 1 : 0;
-    if (incr >= 5) { status = STMG_EDIVERGED; break; }
-    prev = rel;
   }
   *cycles += c;
   *rel_out = rel;
@@ -491,12 +527,12 @@ int Solver::vcycle_user(const double* u0, double* U, double* h_rel) {
   const double* uu = lin ? u0 : nullptr;
   if (!mixed) {
     double* res = nullptr;
-    HIP_CHECK(vcycle<double>(0, false, react, U, L0.B64, f, uu, false, &res));
+    HIP_CHECK(vcycle<double>(0, false, react, U, L0.B64, f, uu, false, &res, 0));
     if (res != U) HIP_CHECK(hipMemcpyAsync(U, res, L0.n * sizeof(double), hipMemcpyDeviceToDevice, stream));
   } else {
     HIP_CHECK(residual64<float>(false, react, U, f, uu, L0.f32, scal));
     float* res = nullptr;
-    HIP_CHECK(vcycle<float>(0, false, react, L0.A32, L0.B32, L0.f32, nullptr, true, &res));
+    HIP_CHECK(vcycle<float>(0, false, react, L0.A32, L0.B32, L0.f32, nullptr, true, &res, 0));
     HIP_CHECK(launch_update<float>(L0.n, U, res, nullptr, stream));
   }
   if (h_rel) {

@@ -66,6 +66,8 @@ struct Solver {
   size_t plan(char* ws);  // lays out (or sizes, ws = nullptr) the workspace
   int upload();           // copies tables into the workspace
 
+  int chunk_of(int l) const;        // smoother block length on level l
+  int transfer_slabs(int l) const;  // slabs per thread in transfer kernels
   // --- building blocks (FP64 or FP32 arithmetic) ---
   template <typename T>
   hipError_t smooth(int l, bool adj, int react, const T* U, const T* f, const double* u0, T* out);
@@ -78,9 +80,10 @@ struct Solver {
   hipError_t coarse(bool adj, int react, const T* f, const double* u0, T* U);
   // One V-cycle on level l; `cur` holds the iterate (ignored if zero), `oth`
   // is the ping-pong partner; the result pointer is returned in *res.
+  // skip_pre: pre-smoothing sweeps on level l already done by the caller.
   template <typename T>
   hipError_t vcycle(int l, bool adj, int react, T* cur, T* oth, const T* f, const double* u0,
-                    bool zero, T** res);
+                    bool zero, T** res, int skip_pre);
 
   // ||f + u0-coupling - A U||^2 on level 0 (FP64), optional store into r (TO).
   template <typename TO>

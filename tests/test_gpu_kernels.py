@@ -18,6 +18,8 @@ CASES = [
     ("2d-M3-ragged", si.problem(2, 20, 3, 9, 0.5, nu=0.01, lam=1.0)),
     ("2d-M4", si.problem(2, 32, 4, 12, 1.0, nu=0.05, lam=0.3)),
     ("2d-M3-tiles", si.problem(2, 48, 3, 34, 1.0, nu=0.02, lam=1.0)),
+    ("2d-M6", si.problem(2, 16, 6, 6, 0.2, nu=0.05, lam=0.5)),
+    ("1d-odd", si.problem(1, 25, 2, 8, 0.2, nu=0.3, lam=0.1)),
 ]
 
 
@@ -68,7 +70,7 @@ def test_smoother_each_level(name, prob, zero):
         rng = np.random.default_rng(10 + l)
         U = np.zeros(lev.shape) if zero else rng.standard_normal(lev.shape)
         f = rng.standard_normal(lev.shape)
-        ref = lev.smooth(U, f, 0.8, 16)
+        ref = lev.smooth(U, f, 0.8, 16 if l == 0 else 4)
         out = torch.empty(lev.shape, dtype=torch.float64, device="cuda:0")
         h.smooth(l, None if zero else T(U), out, f=T(f))
         assert_close(out.cpu().numpy(), ref, 1e-12, "smooth level %d" % l)
