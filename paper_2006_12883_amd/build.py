@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstmg.so")
-SOURCES = ["kernels.hip", "solver.hip", "capi.hip", "tables.cpp"]
+SOURCES = ["inst_smooth_f64.hip", "inst_smooth_f32.hip", "inst_restrict_f64.hip", "inst_restrict_f32.hip",
+           "inst_resid.hip", "inst_prolong.hip", "kernels_misc.hip", "solver.hip", "capi.hip", "tables.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

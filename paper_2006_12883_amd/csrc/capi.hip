@@ -154,7 +154,7 @@ int stmg_level_restrict_residual(stmg_handle* h, int level, const double* d_f,
     return STMG_EINVAL;
   }
   hipError_t e = h->s.restrict_residual<double>(level, false, stmg::REACT_CONST, d_U, d_f,
-                                                level == 0 ? d_u0 : nullptr, d_fc);
+                                                level == 0 ? d_u0 : nullptr, d_fc, nullptr, nullptr);
   return e == hipSuccess ? STMG_OK : STMG_EHIP;
 }
 

@@ -59,17 +59,32 @@ hipError_t launch_residual(const OpParams& p, int react, const SweepPtrs<T>& a,
                            int slabs_per_block, int* nparts, hipStream_t s);
 
 // f_c = R (f - A U) on the fine level described by p; the coarse level has
-// ncx x ncy points and Nc slabs; space/time select the coarsening.
+// ncx x ncy points and Nc slabs; space/time select the coarsening.  If uc is
+// given (with the coarse level's operator pc, coefficient coefc and smoother
+// block length cs) the kernel may also write the coarse level's first
+// smoothing sweep from a zero iterate into uc; *smoothed tells whether it did.
 template <typename T>
 hipError_t launch_restrict_residual(const OpParams& p, int react, const SweepPtrs<T>& a,
                                     bool space, bool time, int ncx, int ncy, int Nc,
-                                    T* fc, int slabs_per_block, hipStream_t s);
+                                    T* fc, int slabs_per_block, hipStream_t s,
+                                    const OpParams* pc = nullptr, T* uc = nullptr,
+                                    const T* coefc = nullptr, int cs = 0,
+                                    bool* smoothed = nullptr);
 
 // U_out = U_in + P e_c (U_in may be null: assign).  Fine level p.
 template <typename T>
 hipError_t launch_prolong(const OpParams& p, bool space, bool time, int ncx, int ncy,
                           int Nc, const T* ec, const T* Uin, T* Uout, int slabs_per_block,
                           hipStream_t s);
+
+// Prolongation fused with one smoothing sweep: U' = U_in + P e_c, then
+// out = U' + omega D^{-1} (f - A U') (a.U = U_in, may be null; a.out = out).
+// Periodic grids with even sizes only (hipErrorNotSupported otherwise).
+template <typename T>
+hipError_t launch_prolong_smooth(const OpParams& p, int react, const SweepPtrs<T>& a, bool space,
+                                 bool time, int ncx, int ncy, int Nc, const T* ec, int chunk,
+                                 hipStream_t s);
+bool blocked_layout(const OpParams& p);
 
 // Exact solve of the block lower-bidiagonal coarsest system:
 // U_n = Ainv (f_n + cin (x) (cout . U_{n-1}))   (u0 enters slab 0 if given).

@@ -1,4 +1,5 @@
-// HIP kernels of the space-time multigrid (gfx950, wave64).
+// Device code of the space-time multigrid kernels (included by the
+// instantiation units; internal to libstmg).
 //
 // All operator kernels work on space-time vectors laid out [N][M][ny][nx]
 // (slab, node, space; Sec. 3).  A thread owns one spatial point and marches
@@ -9,6 +10,7 @@
 // that consecutive spatial tiles run on the same XCD (shared L2).  The small
 // M x M time coupling is done with scalar constants from the kernel argument
 // block; it is 2M flops per unknown, far too little to use matrix cores.
+#pragma once
 #include "kernels.hpp"
 
 namespace stmg {
@@ -935,11 +937,17 @@ __global__ __launch_bounds__(kBlock) void k_residual_blk(const OpParams p, const
 // and, in 2D, one halo row (fine y = 2 Y0 - 1); the halo residuals are
 // computed by single-point work items.  Space coarsening only (the time
 // stencil, if any, is applied in registers as in k_restrict_lds).
-template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY>
+//
+// With ZS the kernel also does the coarse level's first smoothing sweep from
+// a zero iterate (U_c = omega D_c^{-1} f_c along the coarse chunks of cs
+// slabs, which the run [J0, J1) contains whole) and writes it to uc.
+template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY, bool ZS>
 __global__ __launch_bounds__(kBlock) void k_restrict_blk(const OpParams p, const SweepPtrs<T> a,
                                                          int ncx, int ncy, int Nc,
                                                          T* __restrict__ fc, int S, int tiles_x,
-                                                         int tiles, int nblocks) {
+                                                         int tiles, int nblocks, const OpParams pc,
+                                                         T* __restrict__ uc,
+                                                         const T* __restrict__ coefc, int cs) {
   constexpr int BY = TWOD ? 2 : 1;
   constexpr int FW = 2 * TCX + 1;
   constexpr int FH = TWOD ? 2 * TCY + 1 : 1;
@@ -1010,6 +1018,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_blk(const OpParams p, const
   T acc[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) acc[i] = T(0);
+  T zdprev = T(0);
   const int qc = Y * ncx + X;
   for (int n = nlo; n <= nhi; ++n) {
     const size_t base = (size_t)n * M * P;
@@ -1079,25 +1088,57 @@ __global__ __launch_bounds__(kBlock) void k_restrict_blk(const OpParams p, const
         }
         rc[i] = sx0;
       }
-      if (!TM) {
-        const size_t cb = (size_t)n * M * Pc;
+      // complete coarse slab J: store f_c and, with ZS, one zero-guess sweep
+      auto emit = [&](int J, const T* v) {
+        const size_t cb = (size_t)J * M * Pc;
 #pragma unroll
-        for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = rc[i];
+        for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = v[i];
+        if (ZS) {
+          const Consts<M, T> k(pc);
+          T rr[M], d[M];
+#pragma unroll
+          for (int i = 0; i < M; ++i) rr[i] = v[i] + ((J % cs) != 0 ? k.cin[i] * zdprev : T(0));
+          if (REACT == REACT_COEF) {
+            T cvv[M];
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+              cvv[i] = coefc[cb + (size_t)i * Pc + qc];
+              d[i] = rr[i];
+            }
+            const T dgc = T(2) * k.cx + (TWOD ? T(2) * k.cy : T(0));
+            point_block_solve<M, T>(k, dgc, cvv, d);
+          } else {
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+              T sm = T(0);
+#pragma unroll
+              for (int j = 0; j < M; ++j) sm += k.Bi[i][j] * rr[j];
+              d[i] = sm;
+            }
+          }
+          T nd = T(0);
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            uc[cb + (size_t)i * Pc + qc] = k.omega * d[i];
+            nd += k.cout[i] * d[i];
+          }
+          zdprev = nd;
+        }
+      };
+      if (!TM) {
+        emit(n, rc);
       } else if (n & 1) {
         const int J = n >> 1;
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[i] += rc[i];
-        if (J == Nc - 1) {
-          const size_t cb = (size_t)J * M * Pc;
-#pragma unroll
-          for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = acc[i];
-        }
+        if (J == Nc - 1) emit(J, acc);
       } else {
         const int J = n >> 1;
         if (J > J0) {
-          const size_t cb = (size_t)(J - 1) * M * Pc;
+          T v[M];
 #pragma unroll
-          for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = acc[i] + T(0.5) * rc[i];
+          for (int i = 0; i < M; ++i) v[i] = acc[i] + T(0.5) * rc[i];
+          emit(J - 1, v);
         }
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[i] = T(0.5) * rc[i];
@@ -1185,6 +1226,221 @@ __global__ __launch_bounds__(kBlock) void k_prolong_blk(const OpParams p, int nc
       for (int k = 0; k < 2 * BY; ++k) v[k][m] += e[k];
     }
     store_own<M, T, BY>(Uout, base, P, nx, b, v);
+  }
+}
+
+// Prolongation fused with the first post-smoothing sweep:
+//   U' = U + P e_c,  U_out = U' + omega D^{-1} (f - A U')
+// on 2 x BY blocks.  U' is formed in registers on the block's own points and
+// on its halo (rows y0 - 1, y0 + BY, columns x0 - 1, x0 + 2), so it is never
+// stored.  Space interpolation is linear per dimension (fine 2X = coarse X),
+// time interpolation is linear in slab end points (coarse -1 = 0).
+template <int M, typename T, int REACT, bool SP, bool TM, int BY, bool TWOD>
+__global__ __launch_bounds__(kBlock) void k_prolong_smooth_blk(const OpParams p, const SweepPtrs<T> a,
+                                                               int ncx, int ncy, int Nc,
+                                                               const T* __restrict__ ec, int S,
+                                                               int tiles, int nblocks) {
+  constexpr int NP = 2 * BY;
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  const int tile = lb % tiles;
+  const int n0 = (lb / tiles) * S;
+  const int nx = p.nx, ny = p.ny, P = nx * ny;
+  const int Pc = ncx * ncy;
+  const int t = tile * kBlock + threadIdx.x;
+  double ssq = 0.0;
+  if (t < (nx >> 1) * (ny / BY) && n0 < p.N) {
+    const int n1 = min(n0 + S, p.N);
+    const Consts<M, T> c(p);
+    const Blk<BY> b(t, nx, ny);
+    const T dg = T(2) * c.cx + (TWOD ? T(2) * c.cy : T(0));
+    T* __restrict__ out = static_cast<T*>(a.out);
+    // coarse neighbourhood of the block (space coarsening): offsets -1, 0, +1
+    int cxs[3], cys[3];
+    if (SP) {
+      const int X = b.x0 >> 1, Y = TWOD ? (b.y0 >> 1) : 0;
+      cxs[0] = X > 0 ? X - 1 : ncx - 1; cxs[1] = X; cxs[2] = X + 1 < ncx ? X + 1 : 0;
+      if (TWOD) { cys[0] = Y > 0 ? Y - 1 : ncy - 1; cys[1] = Y; cys[2] = Y + 1 < ncy ? Y + 1 : 0; }
+      else { cys[0] = cys[1] = cys[2] = 0; }
+    }
+    // Correction at the 4 x (BY + 2) fine positions (dx = -1..2, dy = -1..BY)
+    // of node m in fine slab n; only the own rows' dx = -1..2 and the halo
+    // rows' dx = 0..1 are used.
+    auto corr = [&](int n, int m, T cr[BY + 2][4]) {
+      int js[2];
+      T wt[2];
+      int nt;
+      if (!TM) { js[0] = n; wt[0] = T(1); nt = 1; }
+      else if (n & 1) { js[0] = n >> 1; wt[0] = T(1); nt = 1; }
+      else {
+        const int J = n >> 1;
+        js[0] = J; wt[0] = T(0.5); nt = 1;
+        if (J > 0) { js[1] = J - 1; wt[1] = T(0.5); nt = 2; }
+      }
+#pragma unroll
+      for (int j = 0; j < BY + 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cr[j][i] = T(0);
+      for (int tt = 0; tt < nt; ++tt) {
+        const T* Ec = ec + (size_t)js[tt] * M * Pc + (size_t)m * Pc;
+        const T w = wt[tt];
+        if (SP) {
+          T cv[3][3];
+#pragma unroll
+          for (int yy = 0; yy < (TWOD ? 3 : 1); ++yy)
+#pragma unroll
+            for (int xx = 0; xx < 3; ++xx) cv[yy][xx] = Ec[cys[TWOD ? yy : 0] * ncx + cxs[xx]];
+          // x interpolation of each coarse row at fine dx = -1, 0, 1, 2
+          T rx[3][4];
+#pragma unroll
+          for (int yy = 0; yy < (TWOD ? 3 : 1); ++yy) {
+            rx[yy][0] = T(0.5) * (cv[yy][0] + cv[yy][1]);
+            rx[yy][1] = cv[yy][1];
+            rx[yy][2] = T(0.5) * (cv[yy][1] + cv[yy][2]);
+            rx[yy][3] = cv[yy][2];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (TWOD) {
+              cr[0][i] += w * T(0.5) * (rx[0][i] + rx[1][i]);  // dy = -1
+              cr[1][i] += w * rx[1][i];                         // dy = 0
+              cr[2][i] += w * T(0.5) * (rx[1][i] + rx[2][i]);  // dy = 1
+              cr[3][i] += w * rx[2][i];                         // dy = 2
+            } else {
+              cr[1][i] += w * rx[0][i];
+            }
+          }
+        } else {
+          // time only: the coarse grid is the fine grid
+#pragma unroll
+          for (int j = 0; j < BY + 2; ++j) {
+            if (!TWOD && j != 1) continue;
+            const int yy = j == 0 ? b.ylo : (j == BY + 1 ? b.yhi : b.y0 + j - 1);
+            T v0, v1;
+            ld2(Ec + yy * nx + b.x0, v0, v1);
+            cr[j][1] += w * v0;
+            cr[j][2] += w * v1;
+            if (j >= 1 && j <= BY) {
+              cr[j][0] += w * Ec[yy * nx + b.xm];
+              cr[j][3] += w * Ec[yy * nx + b.xp];
+            }
+          }
+        }
+      }
+    };
+    // U' on the block's own points of slab n, node m (for the run's coupling)
+    T prev[NP], dprev[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) { prev[k] = T(0); dprev[k] = T(0); }
+    if (n0 == 0) {
+      if (a.u0) {
+#pragma unroll
+        for (int j = 0; j < BY; ++j) {
+          const double* q = a.u0 + (b.y0 + j) * nx + b.x0;
+          prev[2 * j] = (T)q[0];
+          prev[2 * j + 1] = (T)q[1];
+        }
+      }
+    } else {
+      const size_t pb = (size_t)(n0 - 1) * M * P;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        T cr[BY + 2][4];
+        corr(n0 - 1, m, cr);
+#pragma unroll
+        for (int j = 0; j < BY; ++j) {
+          T v0 = T(0), v1 = T(0);
+          if (a.U) ld2(a.U + pb + (size_t)m * P + (b.y0 + j) * nx + b.x0, v0, v1);
+          prev[2 * j] += c.cout[m] * (v0 + cr[j + 1][1]);
+          prev[2 * j + 1] += c.cout[m] * (v1 + cr[j + 1][2]);
+        }
+      }
+    }
+    for (int n = n0; n < n1; ++n) {
+      const size_t base = (size_t)n * M * P;
+      T u[NP][M], lap[NP][M], fv[NP][M], cv[NP][M], o[NP][M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        T cr[BY + 2][4];
+        corr(n, m, cr);
+        const T* Um = a.U ? a.U + base + (size_t)m * P : nullptr;
+        T rw[BY + 2][2];
+#pragma unroll
+        for (int j = 0; j < BY + 2; ++j) {
+          if (!TWOD && j != 1) continue;
+          const int yy = j == 0 ? b.ylo : (j == BY + 1 ? b.yhi : b.y0 + j - 1);
+          T v0 = T(0), v1 = T(0);
+          if (Um) ld2(Um + yy * nx + b.x0, v0, v1);
+          rw[j][0] = v0 + cr[j][1];
+          rw[j][1] = v1 + cr[j][2];
+        }
+#pragma unroll
+        for (int j = 0; j < BY; ++j) {
+          const int row = (b.y0 + j) * nx;
+          const T l = (Um ? Um[row + b.xm] : T(0)) + cr[j + 1][0];
+          const T r = (Um ? Um[row + b.xp] : T(0)) + cr[j + 1][3];
+          const T c0 = rw[j + 1][0], c1 = rw[j + 1][1];
+          T l0 = c.cx * (l + c1 - c0 - c0);
+          T l1 = c.cx * (c0 + r - c1 - c1);
+          if (TWOD) {
+            l0 += c.cy * (rw[j][0] + rw[j + 2][0] - c0 - c0);
+            l1 += c.cy * (rw[j][1] + rw[j + 2][1] - c1 - c1);
+          }
+          u[2 * j][m] = c0;
+          u[2 * j + 1][m] = c1;
+          lap[2 * j][m] = l0;
+          lap[2 * j + 1][m] = l1;
+        }
+      }
+      if (a.f) {
+        load_own<M, T, BY>(a.f, base, P, nx, b, fv);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) fv[k][m] = T(0);
+      }
+      if (REACT == REACT_COEF) load_own<M, T, BY>(a.coef, base, P, nx, b, cv);
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        T r[M], d[M];
+        resid_vals<M, T, REACT>(c, u[k], lap[k], fv[k], cv[k], prev[k], r);
+        if (a.part) {
+#pragma unroll
+          for (int i = 0; i < M; ++i) ssq += (double)r[i] * (double)r[i];
+        }
+        if (n > n0) {
+#pragma unroll
+          for (int i = 0; i < M; ++i) r[i] += c.cin[i] * dprev[k];
+        }
+        if (REACT == REACT_COEF) {
+#pragma unroll
+          for (int i = 0; i < M; ++i) d[i] = r[i];
+          point_block_solve<M, T>(c, dg, cv[k], d);
+        } else {
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            T sm = T(0);
+#pragma unroll
+            for (int j = 0; j < M; ++j) sm += c.Bi[i][j] * r[j];
+            d[i] = sm;
+          }
+        }
+        T np = T(0), nd = T(0);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          o[k][i] = u[k][i] + c.omega * d[i];
+          np += c.cout[i] * u[k][i];
+          nd += c.cout[i] * d[i];
+        }
+        prev[k] = np;
+        dprev[k] = nd;
+      }
+      store_own<M, T, BY>(out, base, P, nx, b, o);
+    }
+  }
+  if (a.part) {
+    const double tt = block_sum(ssq);
+    if (threadIdx.x == 0) a.part[lb] = tt;
   }
 }
 
@@ -1333,22 +1589,9 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve_coef(const OpParams p, 
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ part, int n,
-                                                         double* __restrict__ out) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) s += part[i];
-  const double t = block_sum(s);
-  if (threadIdx.x == 0) out[0] = t;
-}
 
-__global__ __launch_bounds__(kBlock) void k_sumsq(const double* __restrict__ x, size_t n,
-                                                  double* __restrict__ part) {
-  double s = 0.0;
-  const size_t stride = (size_t)gridDim.x * kBlock;
-  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) s += x[i] * x[i];
-  const double t = block_sum(s);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
+
+
 
 template <typename TX, typename TY>
 __global__ __launch_bounds__(kBlock) void k_axpy_cast(size_t n, const TX* __restrict__ x, double alpha,
@@ -1429,55 +1672,13 @@ __global__ __launch_bounds__(kBlock) void k_restrict_coef(const OpParams p, int 
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_reverse_slabs(const double* __restrict__ in,
-                                                          double* __restrict__ out, int N,
-                                                          size_t slab) {
-  const size_t total = (size_t)N * slab;
-  const size_t stride = (size_t)gridDim.x * kBlock;
-  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += stride) {
-    const size_t n = e / slab, r = e % slab;
-    out[(size_t)(N - 1 - n) * slab + r] = in[e];
-  }
-}
 
-__global__ __launch_bounds__(kBlock) void k_node_combine(const double* __restrict__ lam, const double* w,
-                                                         int M, size_t P, double* __restrict__ out) {
-  const size_t stride = (size_t)gridDim.x * kBlock;
-  for (size_t q = (size_t)blockIdx.x * kBlock + threadIdx.x; q < P; q += stride) {
-    double s = 0.0;
-    for (int i = 0; i < M; ++i) s += w[i] * lam[(size_t)i * P + q];
-    out[q] = s;
-  }
-}
 
-__global__ __launch_bounds__(kBlock) void k_grad_nu(const OpParams p, const double* __restrict__ U,
-                                                    const double* __restrict__ lam, double* __restrict__ part) {
-  __shared__ double s_db[kMaxM];
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < kMaxM; ++i) s_db[i] = p.db[i];
-  }
-  __syncthreads();
-  const int nx = p.nx, ny = p.ny, P = nx * ny, M = p.M, N = p.N;
-  const size_t total = (size_t)N * M * P;
-  const size_t stride = (size_t)gridDim.x * kBlock;
-  double acc = 0.0;
-  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += stride) {
-    const int q = (int)(e % P);
-    const int i = (int)((e / P) % M);
-    const int n = (int)(e / ((size_t)P * M));
-    const int x = q % nx, y = q / nx;
-    const double* Um = U + ((size_t)n * M + i) * P;
-    const double c = Um[q];
-    double l = p.cx * (Um[y * nx + nb_lo(x, nx, p.bc)] + Um[y * nx + nb_hi(x, nx, p.bc)] - 2.0 * c);
-    if (ny > 1) l += p.cy * (Um[nb_lo(y, ny, p.bc) * nx + x] + Um[nb_hi(y, ny, p.bc) * nx + x] - 2.0 * c);
-    acc += lam[((size_t)(N - 1 - n) * M + i) * P + q] * s_db[i] * l;
-  }
-  const double t = block_sum(acc);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
 
-int grid_for(size_t n) {
+
+
+
+inline int grid_for(size_t n) {
   size_t b = (n + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
   if (b < 1) b = 1;
@@ -1485,332 +1686,4 @@ int grid_for(size_t n) {
 }
 
 }  // namespace
-
-// ---------------------------------------------------------------------------
-// Launchers: dispatch on M and on the reaction mode.
-#define STMG_DISPATCH_M(MACRO) \
-  switch (p.M) {               \
-    case 1: MACRO(1); break;   \
-    case 2: MACRO(2); break;   \
-    case 3: MACRO(3); break;   \
-    case 4: MACRO(4); break;   \
-    case 5: MACRO(5); break;   \
-    case 6: MACRO(6); break;   \
-    case 7: MACRO(7); break;   \
-    case 8: MACRO(8); break;   \
-    default: return hipErrorInvalidValue; \
-  }
-
-// The register-blocked kernels cover periodic grids with even point counts.
-static bool blocked(const OpParams& p) {
-  return p.bc == 0 && (p.nx % 2) == 0 && (p.ny == 1 || (p.ny % 2) == 0);
-}
-static int plane_threads(const OpParams& p) {
-  if (blocked(p)) return (p.nx / 2) * (p.ny > 1 ? p.ny / 2 : 1);
-  return p.nx * p.ny;
-}
-
-int smooth_blocks(const OpParams& p, int chunk) {
-  return ((plane_threads(p) + kBlock - 1) / kBlock) * ((p.N + chunk - 1) / chunk);
-}
-
-template <typename T>
-hipError_t launch_smooth(const OpParams& p, int react, const SweepPtrs<T>& a, int chunk,
-                         hipStream_t s) {
-  const int nb = smooth_blocks(p, chunk);
-  const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
-  if (blocked(p)) {
-#define LB(MM, RE, BYc, TWc) \
-  hipLaunchKernelGGL((k_smooth_blk<MM, T, RE, BYc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, a, chunk, tiles, nb)
-#define L(MM)                                                                 \
-  if (p.ny > 1) { if (react == REACT_COEF) LB(MM, REACT_COEF, 2, true); else LB(MM, REACT_CONST, 2, true); } \
-  else { if (react == REACT_COEF) LB(MM, REACT_COEF, 1, false); else LB(MM, REACT_CONST, 1, false); }
-    STMG_DISPATCH_M(L)
-#undef L
-#undef LB
-    return hipGetLastError();
-  }
-#define L(MM)                                                                                   \
-  if (react == REACT_COEF)                                                                      \
-    hipLaunchKernelGGL((k_smooth<MM, T, REACT_COEF>), dim3(nb), dim3(kBlock), 0, s, p, a, chunk, \
-                       tiles, nb);                                                              \
-  else                                                                                          \
-    hipLaunchKernelGGL((k_smooth<MM, T, REACT_CONST>), dim3(nb), dim3(kBlock), 0, s, p, a,       \
-                       chunk, tiles, nb);
-  STMG_DISPATCH_M(L)
-#undef L
-  return hipGetLastError();
-}
-
-template <typename T, typename TO>
-hipError_t launch_residual(const OpParams& p, int react, const SweepPtrs<T>& a, int spb,
-                           int* nparts, hipStream_t s) {
-  const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
-  const int chunks = (p.N + spb - 1) / spb;
-  const int nb = tiles * chunks;
-  if (nparts) *nparts = nb;
-  if (blocked(p)) {
-#define LB(MM, RE, BYc, TWc)                                                                     \
-  hipLaunchKernelGGL((k_residual_blk<MM, T, TO, RE, BYc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, a, \
-                     spb, tiles, nb)
-#define LBR(MM, BYc, TWc)                                                    \
-  if (react == REACT_COEF) LB(MM, REACT_COEF, BYc, TWc);                     \
-  else if (react == REACT_AC) LB(MM, REACT_AC, BYc, TWc);                    \
-  else LB(MM, REACT_CONST, BYc, TWc);
-#define L(MM) \
-  if (p.ny > 1) { LBR(MM, 2, true) } else { LBR(MM, 1, false) }
-    STMG_DISPATCH_M(L)
-#undef L
-#undef LBR
-#undef LB
-    return hipGetLastError();
-  }
-#define L(MM)                                                                                    \
-  if (react == REACT_COEF)                                                                       \
-    hipLaunchKernelGGL((k_residual<MM, T, TO, REACT_COEF>), dim3(nb), dim3(kBlock), 0, s, p, a,   \
-                       spb, tiles, nb);                                                          \
-  else if (react == REACT_AC)                                                                    \
-    hipLaunchKernelGGL((k_residual<MM, T, TO, REACT_AC>), dim3(nb), dim3(kBlock), 0, s, p, a,     \
-                       spb, tiles, nb);                                                          \
-  else                                                                                           \
-    hipLaunchKernelGGL((k_residual<MM, T, TO, REACT_CONST>), dim3(nb), dim3(kBlock), 0, s, p, a,  \
-                       spb, tiles, nb);
-  STMG_DISPATCH_M(L)
-#undef L
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_restrict_residual(const OpParams& p, int react, const SweepPtrs<T>& a,
-                                    bool space, bool time, int ncx, int ncy, int Nc, T* fc,
-                                    int spb, hipStream_t s) {
-  const bool twod = p.ny > 1;
-  if (space && blocked(p) && p.M <= 4) {
-    // register-blocked fine tiles, 16 x 16 coarse points (2D) or 256 (1D)
-    const int tcx = twod ? 16 : 256;
-    const int tcy = twod ? 16 : 1;
-    const int tiles_x = (ncx + tcx - 1) / tcx;
-    const int tiles = tiles_x * ((ncy + tcy - 1) / tcy);
-    const int nb = tiles * ((Nc + spb - 1) / spb);
-#define LRB(MM, RE, TMc, TWc, CX, CY)                                                         \
-  hipLaunchKernelGGL((k_restrict_blk<MM, T, RE, TMc, TWc, CX, CY>), dim3(nb), dim3(kBlock), 0, s, \
-                     p, a, ncx, ncy, Nc, fc, spb, tiles_x, tiles, nb)
-#define LRBE(MM, RE)                                          \
-  if (twod) {                                                 \
-    if (time) LRB(MM, RE, true, true, 16, 16);                \
-    else LRB(MM, RE, false, true, 16, 16);                    \
-  } else {                                                    \
-    if (time) LRB(MM, RE, true, false, 256, 1);               \
-    else LRB(MM, RE, false, false, 256, 1);                   \
-  }
-#define LB4(MM) \
-  if (react == REACT_COEF) { LRBE(MM, REACT_COEF) } else { LRBE(MM, REACT_CONST) }
-    switch (p.M) {
-      case 1: LB4(1); break;
-      case 2: LB4(2); break;
-      case 3: LB4(3); break;
-      case 4: LB4(4); break;
-      default: return hipErrorInvalidValue;
-    }
-#undef LB4
-#undef LRBE
-#undef LRB
-    return hipGetLastError();
-  }
-  if (space) {
-    // LDS-tiled kernel: coarse tiles of 16 x 16 (M <= 4) or 16 x 8 in 2D, 256 in 1D
-    const int tcx = twod ? 16 : 256;
-    const int tcy = twod ? (p.M <= 4 ? 16 : 8) : 1;
-    const int tiles_x = (ncx + tcx - 1) / tcx;
-    const int tiles_y = (ncy + tcy - 1) / tcy;
-    const int tiles = tiles_x * tiles_y;
-    const int chunks = (Nc + spb - 1) / spb;
-    const int nb = tiles * chunks;
-#define LRS(MM, RE, TMc, TWc, CX, CY)                                                        \
-  hipLaunchKernelGGL((k_restrict_lds<MM, T, RE, TMc, TWc, CX, CY>), dim3(nb), dim3(kBlock), 0, s, \
-                     p, a, ncx, ncy, Nc, fc, spb, tiles_x, tiles, nb)
-#define LRSE(MM, RE, CY)                                     \
-  if (twod) {                                                \
-    if (time) LRS(MM, RE, true, true, 16, CY);               \
-    else LRS(MM, RE, false, true, 16, CY);                   \
-  } else {                                                   \
-    if (time) LRS(MM, RE, true, false, 256, 1);              \
-    else LRS(MM, RE, false, false, 256, 1);                  \
-  }
-#define L(MM)                                                                     \
-  if (react == REACT_COEF) { LRSE(MM, REACT_COEF, (MM <= 4 ? 16 : 8)) }           \
-  else { LRSE(MM, REACT_CONST, (MM <= 4 ? 16 : 8)) }
-    STMG_DISPATCH_M(L)
-#undef L
-#undef LRSE
-#undef LRS
-    return hipGetLastError();
-  }
-  const int Pc = ncx * ncy;
-  const int tiles = (Pc + kBlock - 1) / kBlock;
-  const int chunks = (Nc + spb - 1) / spb;
-  const int nb = tiles * chunks;
-#define LR(MM, RE, TMc)                                                                        \
-  hipLaunchKernelGGL((k_restrict<MM, T, RE, false, TMc, false>), dim3(nb), dim3(kBlock), 0, s, p, \
-                     a, ncx, ncy, Nc, fc, spb, tiles, nb)
-#define L(MM)                                                             \
-  if (react == REACT_COEF) { if (time) LR(MM, REACT_COEF, true); else LR(MM, REACT_COEF, false); } \
-  else { if (time) LR(MM, REACT_CONST, true); else LR(MM, REACT_CONST, false); }
-  STMG_DISPATCH_M(L)
-#undef L
-#undef LR
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_prolong(const OpParams& p, bool space, bool time, int ncx, int ncy, int Nc,
-                          const T* ec, const T* Uin, T* Uout, int spb, hipStream_t s) {
-  const bool twod = p.ny > 1;
-  const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
-  const int chunks = (p.N + spb - 1) / spb;
-  const int nb = tiles * chunks;
-  if (blocked(p)) {
-#define LPB(MM, SPc, TMc, BYc, TWc)                                                             \
-  hipLaunchKernelGGL((k_prolong_blk<MM, T, SPc, TMc, BYc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, \
-                     ncx, ncy, Nc, ec, Uin, Uout, spb, tiles, nb)
-#define LPS(MM, BYc, TWc)                                 \
-  if (space && time) LPB(MM, true, true, BYc, TWc);       \
-  else if (space) LPB(MM, true, false, BYc, TWc);         \
-  else if (time) LPB(MM, false, true, BYc, TWc);          \
-  else LPB(MM, false, false, BYc, TWc);
-#define L(MM) \
-  if (twod) { LPS(MM, 2, true) } else { LPS(MM, 1, false) }
-    STMG_DISPATCH_M(L)
-#undef L
-#undef LPS
-#undef LPB
-    return hipGetLastError();
-  }
-#define LP(MM, SPc, TMc, TWc)                                                                  \
-  hipLaunchKernelGGL((k_prolong<MM, T, SPc, TMc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, ncx, ncy, \
-                     Nc, ec, Uin, Uout, spb, tiles, nb)
-#define L(MM)                                                            \
-  if (space && time) {                                                   \
-    if (twod) LP(MM, true, true, true); else LP(MM, true, true, false);  \
-  } else if (space) {                                                    \
-    if (twod) LP(MM, true, false, true); else LP(MM, true, false, false); \
-  } else if (time) {                                                     \
-    LP(MM, false, true, false);                                          \
-  } else {                                                               \
-    LP(MM, false, false, false);                                         \
-  }
-  STMG_DISPATCH_M(L)
-#undef L
-#undef LP
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_coarse_solve(const OpParams& p, const double* Ainv, const T* f,
-                               const double* u0, T* U, hipStream_t s) {
-  const int P = p.nx * p.ny;
-  const size_t shm = (size_t)(2 * p.M * P + P) * sizeof(double);
-  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(kBlock), shm, s, p, Ainv, f, u0, U);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_coarse_solve_coef(const OpParams& p, const T* coef, double* scratch, const T* f,
-                                    const double* u0, T* U, hipStream_t s) {
-  const int P = p.nx * p.ny;
-  const int K = p.M * P;
-  const size_t shm = (size_t)(K + P) * sizeof(double) + (size_t)K * sizeof(int);
-  hipLaunchKernelGGL((k_coarse_solve_coef<T>), dim3(1), dim3(kBlock), shm, s, p, coef, scratch, f,
-                     u0, U);
-  return hipGetLastError();
-}
-
-hipError_t launch_sum_partials(const double* part, int n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, part, n, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_sumsq(const double* x, size_t n, double* part, int* nparts, hipStream_t s) {
-  const int g = grid_for(n) > 1024 ? 1024 : grid_for(n);
-  *nparts = g;
-  hipLaunchKernelGGL(k_sumsq, dim3(g), dim3(kBlock), 0, s, x, n, part);
-  return hipGetLastError();
-}
-
-template <typename TX, typename TY>
-hipError_t launch_axpy_cast(size_t n, const TX* x, double alpha, TY* y, bool acc, hipStream_t s) {
-  hipLaunchKernelGGL((k_axpy_cast<TX, TY>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, alpha, y,
-                     acc ? 1 : 0);
-  return hipGetLastError();
-}
-
-template <typename TE>
-hipError_t launch_update(size_t n, double* U, const TE* e, const double* scale, hipStream_t s) {
-  hipLaunchKernelGGL((k_update<TE>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, U, e, scale);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_newton_coef(size_t n, const double* U, double gamma, T* coef, hipStream_t s) {
-  hipLaunchKernelGGL((k_newton_coef<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, U, gamma, coef);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_restrict_coef(const OpParams& fine, bool space, bool time, int ncx, int ncy,
-                                int Nc, const T* cf, T* cc, hipStream_t s) {
-  const size_t total = (size_t)Nc * fine.M * ncx * ncy;
-  hipLaunchKernelGGL((k_restrict_coef<T>), dim3(grid_for(total)), dim3(kBlock), 0, s, fine,
-                     space ? 1 : 0, time ? 1 : 0, ncx, ncy, Nc, cf, cc);
-  return hipGetLastError();
-}
-
-hipError_t launch_reverse_slabs(const double* in, double* out, int N, int M, size_t P,
-                                hipStream_t s) {
-  const size_t slab = (size_t)M * P;
-  hipLaunchKernelGGL(k_reverse_slabs, dim3(grid_for((size_t)N * slab)), dim3(kBlock), 0, s, in, out,
-                     N, slab);
-  return hipGetLastError();
-}
-
-hipError_t launch_node_combine(const double* lam, const double* w, int M, size_t P, double* out,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_node_combine, dim3(grid_for(P)), dim3(kBlock), 0, s, lam, w, M, P, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_grad_nu(const OpParams& p, const double* U, const double* lam, double* part,
-                          int* nparts, hipStream_t s) {
-  const size_t total = (size_t)p.N * p.M * p.nx * p.ny;
-  int g = grid_for(total);
-  if (g > 1024) g = 1024;
-  *nparts = g;
-  hipLaunchKernelGGL(k_grad_nu, dim3(g), dim3(kBlock), 0, s, p, U, lam, part);
-  return hipGetLastError();
-}
-
-// explicit instantiations
-template hipError_t launch_smooth<double>(const OpParams&, int, const SweepPtrs<double>&, int, hipStream_t);
-template hipError_t launch_smooth<float>(const OpParams&, int, const SweepPtrs<float>&, int, hipStream_t);
-template hipError_t launch_residual<double, double>(const OpParams&, int, const SweepPtrs<double>&, int, int*, hipStream_t);
-template hipError_t launch_residual<double, float>(const OpParams&, int, const SweepPtrs<double>&, int, int*, hipStream_t);
-template hipError_t launch_residual<float, float>(const OpParams&, int, const SweepPtrs<float>&, int, int*, hipStream_t);
-template hipError_t launch_restrict_residual<double>(const OpParams&, int, const SweepPtrs<double>&, bool, bool, int, int, int, double*, int, hipStream_t);
-template hipError_t launch_restrict_residual<float>(const OpParams&, int, const SweepPtrs<float>&, bool, bool, int, int, int, float*, int, hipStream_t);
-template hipError_t launch_prolong<double>(const OpParams&, bool, bool, int, int, int, const double*, const double*, double*, int, hipStream_t);
-template hipError_t launch_prolong<float>(const OpParams&, bool, bool, int, int, int, const float*, const float*, float*, int, hipStream_t);
-template hipError_t launch_coarse_solve<double>(const OpParams&, const double*, const double*, const double*, double*, hipStream_t);
-template hipError_t launch_coarse_solve<float>(const OpParams&, const double*, const float*, const double*, float*, hipStream_t);
-template hipError_t launch_coarse_solve_coef<double>(const OpParams&, const double*, double*, const double*, const double*, double*, hipStream_t);
-template hipError_t launch_coarse_solve_coef<float>(const OpParams&, const float*, double*, const float*, const double*, float*, hipStream_t);
-template hipError_t launch_axpy_cast<double, float>(size_t, const double*, double, float*, bool, hipStream_t);
-template hipError_t launch_axpy_cast<float, double>(size_t, const float*, double, double*, bool, hipStream_t);
-template hipError_t launch_axpy_cast<double, double>(size_t, const double*, double, double*, bool, hipStream_t);
-template hipError_t launch_update<float>(size_t, double*, const float*, const double*, hipStream_t);
-template hipError_t launch_update<double>(size_t, double*, const double*, const double*, hipStream_t);
-template hipError_t launch_newton_coef<double>(size_t, const double*, double, double*, hipStream_t);
-template hipError_t launch_newton_coef<float>(size_t, const double*, double, float*, hipStream_t);
-template hipError_t launch_restrict_coef<double>(const OpParams&, bool, bool, int, int, int, const double*, double*, hipStream_t);
-template hipError_t launch_restrict_coef<float>(const OpParams&, bool, bool, int, int, int, const float*, float*, hipStream_t);
-
 }  // namespace stmg

@@ -1,0 +1,131 @@
+// Non-template launchers and elementwise / reduction instantiations.
+#include "launchers.hpp"
+
+namespace stmg {
+
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ part, int n,
+                                                         double* __restrict__ out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) s += part[i];
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sumsq(const double* __restrict__ x, size_t n,
+                                                  double* __restrict__ part) {
+  double s = 0.0;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) s += x[i] * x[i];
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reverse_slabs(const double* __restrict__ in,
+                                                          double* __restrict__ out, int N,
+                                                          size_t slab) {
+  const size_t total = (size_t)N * slab;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += stride) {
+    const size_t n = e / slab, r = e % slab;
+    out[(size_t)(N - 1 - n) * slab + r] = in[e];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_node_combine(const double* __restrict__ lam, const double* w,
+                                                         int M, size_t P, double* __restrict__ out) {
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t q = (size_t)blockIdx.x * kBlock + threadIdx.x; q < P; q += stride) {
+    double s = 0.0;
+    for (int i = 0; i < M; ++i) s += w[i] * lam[(size_t)i * P + q];
+    out[q] = s;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_grad_nu(const OpParams p, const double* __restrict__ U,
+                                                    const double* __restrict__ lam, double* __restrict__ part) {
+  __shared__ double s_db[kMaxM];
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kMaxM; ++i) s_db[i] = p.db[i];
+  }
+  __syncthreads();
+  const int nx = p.nx, ny = p.ny, P = nx * ny, M = p.M, N = p.N;
+  const size_t total = (size_t)N * M * P;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  double acc = 0.0;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += stride) {
+    const int q = (int)(e % P);
+    const int i = (int)((e / P) % M);
+    const int n = (int)(e / ((size_t)P * M));
+    const int x = q % nx, y = q / nx;
+    const double* Um = U + ((size_t)n * M + i) * P;
+    const double c = Um[q];
+    double l = p.cx * (Um[y * nx + nb_lo(x, nx, p.bc)] + Um[y * nx + nb_hi(x, nx, p.bc)] - 2.0 * c);
+    if (ny > 1) l += p.cy * (Um[nb_lo(y, ny, p.bc) * nx + x] + Um[nb_hi(y, ny, p.bc) * nx + x] - 2.0 * c);
+    acc += lam[((size_t)(N - 1 - n) * M + i) * P + q] * s_db[i] * l;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+}  // namespace
+
+int smooth_blocks(const OpParams& p, int chunk) {
+  return ((plane_threads(p) + kBlock - 1) / kBlock) * ((p.N + chunk - 1) / chunk);
+}
+
+bool blocked_layout(const OpParams& p) { return blocked(p); }
+
+hipError_t launch_sum_partials(const double* part, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, part, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const double* x, size_t n, double* part, int* nparts, hipStream_t s) {
+  const int g = grid_for(n) > 1024 ? 1024 : grid_for(n);
+  *nparts = g;
+  hipLaunchKernelGGL(k_sumsq, dim3(g), dim3(kBlock), 0, s, x, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_reverse_slabs(const double* in, double* out, int N, int M, size_t P,
+                                hipStream_t s) {
+  const size_t slab = (size_t)M * P;
+  hipLaunchKernelGGL(k_reverse_slabs, dim3(grid_for((size_t)N * slab)), dim3(kBlock), 0, s, in, out,
+                     N, slab);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_combine(const double* lam, const double* w, int M, size_t P, double* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_node_combine, dim3(grid_for(P)), dim3(kBlock), 0, s, lam, w, M, P, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_nu(const OpParams& p, const double* U, const double* lam, double* part,
+                          int* nparts, hipStream_t s) {
+  const size_t total = (size_t)p.N * p.M * p.nx * p.ny;
+  int g = grid_for(total);
+  if (g > 1024) g = 1024;
+  *nparts = g;
+  hipLaunchKernelGGL(k_grad_nu, dim3(g), dim3(kBlock), 0, s, p, U, lam, part);
+  return hipGetLastError();
+}
+
+template hipError_t launch_coarse_solve<double>(const OpParams&, const double*, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_coarse_solve<float>(const OpParams&, const double*, const float*, const double*, float*, hipStream_t);
+template hipError_t launch_coarse_solve_coef<double>(const OpParams&, const double*, double*, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_coarse_solve_coef<float>(const OpParams&, const float*, double*, const float*, const double*, float*, hipStream_t);
+template hipError_t launch_axpy_cast<double, float>(size_t, const double*, double, float*, bool, hipStream_t);
+template hipError_t launch_axpy_cast<float, double>(size_t, const float*, double, double*, bool, hipStream_t);
+template hipError_t launch_axpy_cast<double, double>(size_t, const double*, double, double*, bool, hipStream_t);
+template hipError_t launch_update<float>(size_t, double*, const float*, const double*, hipStream_t);
+template hipError_t launch_update<double>(size_t, double*, const double*, const double*, hipStream_t);
+template hipError_t launch_newton_coef<double>(size_t, const double*, double, double*, hipStream_t);
+template hipError_t launch_newton_coef<float>(size_t, const double*, double, float*, hipStream_t);
+template hipError_t launch_restrict_coef<double>(const OpParams&, bool, bool, int, int, int, const double*, double*, hipStream_t);
+template hipError_t launch_restrict_coef<float>(const OpParams&, bool, bool, int, int, int, const float*, float*, hipStream_t);
+
+}  // namespace stmg

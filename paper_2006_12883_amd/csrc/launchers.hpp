@@ -1,0 +1,321 @@
+// Kernel launchers (templates; instantiated in the inst_*.hip units).
+#pragma once
+#include "kernels_impl.hpp"
+
+namespace stmg {
+
+// ---------------------------------------------------------------------------
+// Launchers: dispatch on M and on the reaction mode.
+#define STMG_DISPATCH_M(MACRO) \
+  switch (p.M) {               \
+    case 1: MACRO(1); break;   \
+    case 2: MACRO(2); break;   \
+    case 3: MACRO(3); break;   \
+    case 4: MACRO(4); break;   \
+    case 5: MACRO(5); break;   \
+    case 6: MACRO(6); break;   \
+    case 7: MACRO(7); break;   \
+    case 8: MACRO(8); break;   \
+    default: return hipErrorInvalidValue; \
+  }
+
+// The register-blocked kernels cover periodic grids with even point counts.
+inline bool blocked(const OpParams& p) {
+  return p.bc == 0 && (p.nx % 2) == 0 && (p.ny == 1 || (p.ny % 2) == 0);
+}
+inline int plane_threads(const OpParams& p) {
+  if (blocked(p)) return (p.nx / 2) * (p.ny > 1 ? p.ny / 2 : 1);
+  return p.nx * p.ny;
+}
+
+
+
+
+
+template <typename T>
+hipError_t launch_smooth(const OpParams& p, int react, const SweepPtrs<T>& a, int chunk,
+                         hipStream_t s) {
+  const int nb = smooth_blocks(p, chunk);
+  const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
+  if (blocked(p)) {
+#define LB(MM, RE, BYc, TWc) \
+  hipLaunchKernelGGL((k_smooth_blk<MM, T, RE, BYc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, a, chunk, tiles, nb)
+#define L(MM)                                                                 \
+  if (p.ny > 1) { if (react == REACT_COEF) LB(MM, REACT_COEF, 2, true); else LB(MM, REACT_CONST, 2, true); } \
+  else { if (react == REACT_COEF) LB(MM, REACT_COEF, 1, false); else LB(MM, REACT_CONST, 1, false); }
+    STMG_DISPATCH_M(L)
+#undef L
+#undef LB
+    return hipGetLastError();
+  }
+#define L(MM)                                                                                   \
+  if (react == REACT_COEF)                                                                      \
+    hipLaunchKernelGGL((k_smooth<MM, T, REACT_COEF>), dim3(nb), dim3(kBlock), 0, s, p, a, chunk, \
+                       tiles, nb);                                                              \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_smooth<MM, T, REACT_CONST>), dim3(nb), dim3(kBlock), 0, s, p, a,       \
+                       chunk, tiles, nb);
+  STMG_DISPATCH_M(L)
+#undef L
+  return hipGetLastError();
+}
+
+template <typename T, typename TO>
+hipError_t launch_residual(const OpParams& p, int react, const SweepPtrs<T>& a, int spb,
+                           int* nparts, hipStream_t s) {
+  const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
+  const int chunks = (p.N + spb - 1) / spb;
+  const int nb = tiles * chunks;
+  if (nparts) *nparts = nb;
+  if (blocked(p)) {
+#define LB(MM, RE, BYc, TWc)                                                                     \
+  hipLaunchKernelGGL((k_residual_blk<MM, T, TO, RE, BYc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, a, \
+                     spb, tiles, nb)
+#define LBR(MM, BYc, TWc)                                                    \
+  if (react == REACT_COEF) LB(MM, REACT_COEF, BYc, TWc);                     \
+  else if (react == REACT_AC) LB(MM, REACT_AC, BYc, TWc);                    \
+  else LB(MM, REACT_CONST, BYc, TWc);
+#define L(MM) \
+  if (p.ny > 1) { LBR(MM, 2, true) } else { LBR(MM, 1, false) }
+    STMG_DISPATCH_M(L)
+#undef L
+#undef LBR
+#undef LB
+    return hipGetLastError();
+  }
+#define L(MM)                                                                                    \
+  if (react == REACT_COEF)                                                                       \
+    hipLaunchKernelGGL((k_residual<MM, T, TO, REACT_COEF>), dim3(nb), dim3(kBlock), 0, s, p, a,   \
+                       spb, tiles, nb);                                                          \
+  else if (react == REACT_AC)                                                                    \
+    hipLaunchKernelGGL((k_residual<MM, T, TO, REACT_AC>), dim3(nb), dim3(kBlock), 0, s, p, a,     \
+                       spb, tiles, nb);                                                          \
+  else                                                                                           \
+    hipLaunchKernelGGL((k_residual<MM, T, TO, REACT_CONST>), dim3(nb), dim3(kBlock), 0, s, p, a,  \
+                       spb, tiles, nb);
+  STMG_DISPATCH_M(L)
+#undef L
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict_residual(const OpParams& p, int react, const SweepPtrs<T>& a,
+                                    bool space, bool time, int ncx, int ncy, int Nc, T* fc,
+                                    int spb, hipStream_t s, const OpParams* pc, T* uc,
+                                    const T* coefc, int cs, bool* smoothed) {
+  const bool twod = p.ny > 1;
+  if (smoothed) *smoothed = false;
+  if (space && blocked(p) && p.M <= 4) {
+    const bool zs = uc != nullptr && pc != nullptr && cs >= 1 && (spb % cs) == 0;
+    if (smoothed) *smoothed = zs;
+    const OpParams& pcc = zs ? *pc : p;
+    // register-blocked fine tiles, 16 x 16 coarse points (2D) or 256 (1D)
+    const int tcx = twod ? 16 : 256;
+    const int tcy = twod ? 16 : 1;
+    const int tiles_x = (ncx + tcx - 1) / tcx;
+    const int tiles = tiles_x * ((ncy + tcy - 1) / tcy);
+    const int nb = tiles * ((Nc + spb - 1) / spb);
+#define LRB(MM, RE, TMc, TWc, CX, CY)                                                            \
+  if (zs)                                                                                           \
+    hipLaunchKernelGGL((k_restrict_blk<MM, T, RE, TMc, TWc, CX, CY, true>), dim3(nb), dim3(kBlock), 0, \
+                       s, p, a, ncx, ncy, Nc, fc, spb, tiles_x, tiles, nb, pcc, uc, coefc, cs);     \
+  else                                                                                              \
+    hipLaunchKernelGGL((k_restrict_blk<MM, T, RE, TMc, TWc, CX, CY, false>), dim3(nb), dim3(kBlock), 0, \
+                       s, p, a, ncx, ncy, Nc, fc, spb, tiles_x, tiles, nb, pcc, uc, coefc, cs)
+#define LRBE(MM, RE)                                          \
+  if (twod) {                                                 \
+    if (time) LRB(MM, RE, true, true, 16, 16);                \
+    else LRB(MM, RE, false, true, 16, 16);                    \
+  } else {                                                    \
+    if (time) LRB(MM, RE, true, false, 256, 1);               \
+    else LRB(MM, RE, false, false, 256, 1);                   \
+  }
+#define LB4(MM) \
+  if (react == REACT_COEF) { LRBE(MM, REACT_COEF) } else { LRBE(MM, REACT_CONST) }
+    switch (p.M) {
+      case 1: LB4(1); break;
+      case 2: LB4(2); break;
+      case 3: LB4(3); break;
+      case 4: LB4(4); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef LB4
+#undef LRBE
+#undef LRB
+    return hipGetLastError();
+  }
+  if (space) {
+    // LDS-tiled kernel: coarse tiles of 16 x 16 (M <= 4) or 16 x 8 in 2D, 256 in 1D
+    const int tcx = twod ? 16 : 256;
+    const int tcy = twod ? (p.M <= 4 ? 16 : 8) : 1;
+    const int tiles_x = (ncx + tcx - 1) / tcx;
+    const int tiles_y = (ncy + tcy - 1) / tcy;
+    const int tiles = tiles_x * tiles_y;
+    const int chunks = (Nc + spb - 1) / spb;
+    const int nb = tiles * chunks;
+#define LRS(MM, RE, TMc, TWc, CX, CY)                                                        \
+  hipLaunchKernelGGL((k_restrict_lds<MM, T, RE, TMc, TWc, CX, CY>), dim3(nb), dim3(kBlock), 0, s, \
+                     p, a, ncx, ncy, Nc, fc, spb, tiles_x, tiles, nb)
+#define LRSE(MM, RE, CY)                                     \
+  if (twod) {                                                \
+    if (time) LRS(MM, RE, true, true, 16, CY);               \
+    else LRS(MM, RE, false, true, 16, CY);                   \
+  } else {                                                   \
+    if (time) LRS(MM, RE, true, false, 256, 1);              \
+    else LRS(MM, RE, false, false, 256, 1);                  \
+  }
+#define L(MM)                                                                     \
+  if (react == REACT_COEF) { LRSE(MM, REACT_COEF, (MM <= 4 ? 16 : 8)) }           \
+  else { LRSE(MM, REACT_CONST, (MM <= 4 ? 16 : 8)) }
+    STMG_DISPATCH_M(L)
+#undef L
+#undef LRSE
+#undef LRS
+    return hipGetLastError();
+  }
+  const int Pc = ncx * ncy;
+  const int tiles = (Pc + kBlock - 1) / kBlock;
+  const int chunks = (Nc + spb - 1) / spb;
+  const int nb = tiles * chunks;
+#define LR(MM, RE, TMc)                                                                        \
+  hipLaunchKernelGGL((k_restrict<MM, T, RE, false, TMc, false>), dim3(nb), dim3(kBlock), 0, s, p, \
+                     a, ncx, ncy, Nc, fc, spb, tiles, nb)
+#define L(MM)                                                             \
+  if (react == REACT_COEF) { if (time) LR(MM, REACT_COEF, true); else LR(MM, REACT_COEF, false); } \
+  else { if (time) LR(MM, REACT_CONST, true); else LR(MM, REACT_CONST, false); }
+  STMG_DISPATCH_M(L)
+#undef L
+#undef LR
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong(const OpParams& p, bool space, bool time, int ncx, int ncy, int Nc,
+                          const T* ec, const T* Uin, T* Uout, int spb, hipStream_t s) {
+  const bool twod = p.ny > 1;
+  const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
+  const int chunks = (p.N + spb - 1) / spb;
+  const int nb = tiles * chunks;
+  if (blocked(p)) {
+#define LPB(MM, SPc, TMc, BYc, TWc)                                                             \
+  hipLaunchKernelGGL((k_prolong_blk<MM, T, SPc, TMc, BYc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, \
+                     ncx, ncy, Nc, ec, Uin, Uout, spb, tiles, nb)
+#define LPS(MM, BYc, TWc)                                 \
+  if (space && time) LPB(MM, true, true, BYc, TWc);       \
+  else if (space) LPB(MM, true, false, BYc, TWc);         \
+  else if (time) LPB(MM, false, true, BYc, TWc);          \
+  else LPB(MM, false, false, BYc, TWc);
+#define L(MM) \
+  if (twod) { LPS(MM, 2, true) } else { LPS(MM, 1, false) }
+    STMG_DISPATCH_M(L)
+#undef L
+#undef LPS
+#undef LPB
+    return hipGetLastError();
+  }
+#define LP(MM, SPc, TMc, TWc)                                                                  \
+  hipLaunchKernelGGL((k_prolong<MM, T, SPc, TMc, TWc>), dim3(nb), dim3(kBlock), 0, s, p, ncx, ncy, \
+                     Nc, ec, Uin, Uout, spb, tiles, nb)
+#define L(MM)                                                            \
+  if (space && time) {                                                   \
+    if (twod) LP(MM, true, true, true); else LP(MM, true, true, false);  \
+  } else if (space) {                                                    \
+    if (twod) LP(MM, true, false, true); else LP(MM, true, false, false); \
+  } else if (time) {                                                     \
+    LP(MM, false, true, false);                                          \
+  } else {                                                               \
+    LP(MM, false, false, false);                                         \
+  }
+  STMG_DISPATCH_M(L)
+#undef L
+#undef LP
+  return hipGetLastError();
+}
+
+
+template <typename T>
+hipError_t launch_prolong_smooth(const OpParams& p, int react, const SweepPtrs<T>& a, bool space,
+                                 bool time, int ncx, int ncy, int Nc, const T* ec, int chunk,
+                                 hipStream_t s) {
+  if (!blocked(p)) return hipErrorNotSupported;
+  const bool twod = p.ny > 1;
+  const int nb = smooth_blocks(p, chunk);
+  const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
+#define LF(MM, RE, SPc, TMc, BYc, TWc)                                                            \
+  hipLaunchKernelGGL((k_prolong_smooth_blk<MM, T, RE, SPc, TMc, BYc, TWc>), dim3(nb), dim3(kBlock), \
+                     0, s, p, a, ncx, ncy, Nc, ec, chunk, tiles, nb)
+#define LFS(MM, RE, BYc, TWc)                                   \
+  if (space && time) LF(MM, RE, true, true, BYc, TWc);          \
+  else if (space) LF(MM, RE, true, false, BYc, TWc);            \
+  else LF(MM, RE, false, true, BYc, TWc);
+#define LFR(MM, RE) \
+  if (twod) { LFS(MM, RE, 2, true) } else { LFS(MM, RE, 1, false) }
+#define L(MM) \
+  if (react == REACT_COEF) { LFR(MM, REACT_COEF) } else { LFR(MM, REACT_CONST) }
+  STMG_DISPATCH_M(L)
+#undef L
+#undef LFR
+#undef LFS
+#undef LF
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse_solve(const OpParams& p, const double* Ainv, const T* f,
+                               const double* u0, T* U, hipStream_t s) {
+  const int P = p.nx * p.ny;
+  const size_t shm = (size_t)(2 * p.M * P + P) * sizeof(double);
+  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(kBlock), shm, s, p, Ainv, f, u0, U);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse_solve_coef(const OpParams& p, const T* coef, double* scratch, const T* f,
+                                    const double* u0, T* U, hipStream_t s) {
+  const int P = p.nx * p.ny;
+  const int K = p.M * P;
+  const size_t shm = (size_t)(K + P) * sizeof(double) + (size_t)K * sizeof(int);
+  hipLaunchKernelGGL((k_coarse_solve_coef<T>), dim3(1), dim3(kBlock), shm, s, p, coef, scratch, f,
+                     u0, U);
+  return hipGetLastError();
+}
+
+
+
+
+
+template <typename TX, typename TY>
+hipError_t launch_axpy_cast(size_t n, const TX* x, double alpha, TY* y, bool acc, hipStream_t s) {
+  hipLaunchKernelGGL((k_axpy_cast<TX, TY>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, alpha, y,
+                     acc ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <typename TE>
+hipError_t launch_update(size_t n, double* U, const TE* e, const double* scale, hipStream_t s) {
+  hipLaunchKernelGGL((k_update<TE>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, U, e, scale);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_newton_coef(size_t n, const double* U, double gamma, T* coef, hipStream_t s) {
+  hipLaunchKernelGGL((k_newton_coef<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, U, gamma, coef);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict_coef(const OpParams& fine, bool space, bool time, int ncx, int ncy,
+                                int Nc, const T* cf, T* cc, hipStream_t s) {
+  const size_t total = (size_t)Nc * fine.M * ncx * ncy;
+  hipLaunchKernelGGL((k_restrict_coef<T>), dim3(grid_for(total)), dim3(kBlock), 0, s, fine,
+                     space ? 1 : 0, time ? 1 : 0, ncx, ncy, Nc, cf, cc);
+  return hipGetLastError();
+}
+
+
+
+
+
+
+
+}  // namespace stmg

@@ -277,13 +277,16 @@ hipError_t Solver::smooth(int l, bool adj, int react, const T* U, const T* f, co
 
 template <typename T>
 hipError_t Solver::restrict_residual(int l, bool adj, int react, const T* U, const T* f,
-                                     const double* u0, T* fc) {
+                                     const double* u0, T* fc, T* uc, bool* smoothed) {
   const Level& L = lv[l];
   const Level& C = lv[l + 1];
   SweepPtrs<T> a{U, f, u0, coef_of<T>(L), nullptr, nullptr};
+  int spb = transfer_slabs(l + 1);
+  const int cs = chunk_of(l + 1);
+  if (uc && spb % cs != 0) spb = ((spb + cs - 1) / cs) * cs;
   return launch_restrict_residual<T>(adj ? L.opT : L.op, react, a, (L.kind & 1) != 0,
-                                     (L.kind & 2) != 0, C.nx, C.ny, C.N, fc, transfer_slabs(l + 1),
-                                     stream);
+                                     (L.kind & 2) != 0, C.nx, C.ny, C.N, fc, spb, stream,
+                                     adj ? &C.opT : &C.op, uc, coef_of<T>(C), cs, smoothed);
 }
 
 template <typename T>
@@ -301,6 +304,16 @@ hipError_t Solver::coarse(bool adj, int react, const T* f, const double* u0, T* 
   if (react == REACT_COEF)
     return launch_coarse_solve_coef<T>(op, coef_of<T>(C), coarse_scratch, f, u0, U, stream);
   return launch_coarse_solve<T>(op, adj ? AinvT : Ainv, f, u0, U, stream);
+}
+
+template <typename T>
+hipError_t Solver::prolong_smooth(int l, bool adj, int react, const T* Uin, const T* ec,
+                                  const T* f, const double* u0, T* out) {
+  const Level& L = lv[l];
+  const Level& C = lv[l + 1];
+  SweepPtrs<T> a{Uin, f, u0, coef_of<T>(L), out, nullptr};
+  return launch_prolong_smooth<T>(adj ? L.opT : L.op, react, a, (L.kind & 1) != 0,
+                                  (L.kind & 2) != 0, C.nx, C.ny, C.N, ec, chunk_of(l), stream);
 }
 
 template <typename T>
@@ -323,18 +336,33 @@ hipError_t Solver::vcycle(int l, bool adj, int react, T* cur, T* oth, const T* f
   T* cb = nullptr;
   if constexpr (sizeof(T) == 8) { cf = C.f64; ca = C.A64; cb = C.B64; }
   else { cf = C.f32; ca = C.A32; cb = C.B32; }
-  HIP_TRY(restrict_residual<T>(l, adj, react, zero ? nullptr : cur, f, u0, cf));
+  // Descend: the restriction also does the coarse level's first smoothing
+  // sweep from a zero iterate when the kernel supports it.
+  const bool want = fuse && opt.nu_pre >= 1 && l + 1 < last;
+  bool smoothed = false;
+  HIP_TRY(restrict_residual<T>(l, adj, react, zero ? nullptr : cur, f, u0, cf,
+                               want ? ca : nullptr, &smoothed));
   T* ec = nullptr;
-  HIP_TRY(vcycle<T>(l + 1, adj, react, ca, cb, cf, nullptr, true, &ec, 0));
-  // Keep an even number of buffer flips so that level 0 ends where it began.
-  const bool flip = ((opt.nu_pre + opt.nu_post) & 1) != 0;
-  if (flip) {
-    HIP_TRY(prolong<T>(l, zero ? nullptr : cur, ec, oth));
+  HIP_TRY(vcycle<T>(l + 1, adj, react, ca, cb, cf, nullptr, !smoothed, &ec, smoothed ? 1 : 0));
+  // Ascend: prolongation fused with the first post-smoothing sweep where the
+  // grid layout allows it.
+  int post = opt.nu_post;
+  const OpParams& op = adj ? lv[l].opT : lv[l].op;
+  if (fuse && post >= 1 && blocked_layout(op)) {
+    HIP_TRY(prolong_smooth<T>(l, adj, react, zero ? nullptr : cur, ec, f, u0, oth));
     std::swap(cur, oth);
+    --post;
   } else {
-    HIP_TRY(prolong<T>(l, zero ? nullptr : cur, ec, cur));
+    // Keep an even number of buffer flips so that level 0 ends where it began.
+    const bool flip = ((opt.nu_pre + opt.nu_post) & 1) != 0;
+    if (flip) {
+      HIP_TRY(prolong<T>(l, zero ? nullptr : cur, ec, oth));
+      std::swap(cur, oth);
+    } else {
+      HIP_TRY(prolong<T>(l, zero ? nullptr : cur, ec, cur));
+    }
   }
-  for (int s = 0; s < opt.nu_post; ++s) {
+  for (int s = 0; s < post; ++s) {
     HIP_TRY(smooth<T>(l, adj, react, cur, f, u0, oth));
     std::swap(cur, oth);
   }
@@ -619,7 +647,7 @@ int Solver::sdc(const double*, double*, int, double*) {
 
 // explicit instantiations used by the C ABI
 template hipError_t Solver::smooth<double>(int, bool, int, const double*, const double*, const double*, double*);
-template hipError_t Solver::restrict_residual<double>(int, bool, int, const double*, const double*, const double*, double*);
+template hipError_t Solver::restrict_residual<double>(int, bool, int, const double*, const double*, const double*, double*, double*, bool*);
 template hipError_t Solver::prolong<double>(int, const double*, const double*, double*);
 template hipError_t Solver::coarse<double>(bool, int, const double*, const double*, double*);
 

@@ -48,6 +48,7 @@ struct Solver {
   std::vector<Level> lv;
   bool allen_cahn = false;
   bool mixed = false;
+  bool fuse = true;  // fused restriction+presmooth / prolongation+postsmooth kernels
   size_t ws_bytes = 0;
   // shared device scratch
   double* part = nullptr;   // per-block partial sums
@@ -71,9 +72,14 @@ struct Solver {
   // --- building blocks (FP64 or FP32 arithmetic) ---
   template <typename T>
   hipError_t smooth(int l, bool adj, int react, const T* U, const T* f, const double* u0, T* out);
+  // f_c = R (f - A U); with uc also the coarse level's first smoothing sweep
+  // from zero into uc when possible (*smoothed reports it).
   template <typename T>
   hipError_t restrict_residual(int l, bool adj, int react, const T* U, const T* f,
-                               const double* u0, T* fc);
+                               const double* u0, T* fc, T* uc = nullptr, bool* smoothed = nullptr);
+  template <typename T>
+  hipError_t prolong_smooth(int l, bool adj, int react, const T* Uin, const T* ec, const T* f,
+                            const double* u0, T* out);
   template <typename T>
   hipError_t prolong(int l, const T* Uin, const T* ec, T* Uout);
   template <typename T>
