@@ -105,6 +105,7 @@ typedef struct {
   int32_t max_newton; /* 30                                                  */
   size_t mem_budget;  /* adjoint: max bytes for the stored forward trajectory;
                          0 = unlimited (no checkpointing)                     */
+  int32_t sdc;        /* 1: reserve workspace for stmg_sdc_sweep, 0 (default) */
 } stmg_options;
 
 typedef struct {
@@ -160,22 +161,43 @@ int stmg_vcycle(stmg_handle* h, const double* d_u0, double* d_U, double* h_rel);
  * iterate on ENOTCONV/EDIVERGED/ENAN).  stats may be NULL.  Synchronizes. */
 int stmg_solve(stmg_handle* h, const double* d_u0, double* d_U, stmg_stats* stats);
 
+/* Like stmg_solve but returns only the end value u(T) = U_{N,M} ([ny][nx])
+ * in d_uT.  Only on a handle whose options' mem_budget is too small for the
+ * trajectory (time windows, see stmg_num_windows): the solve runs window by
+ * window and keeps the window start values as checkpoints in the workspace,
+ * so the trajectory is never stored.  EUNSUPPORTED on other handles. */
+int stmg_solve_end(stmg_handle* h, const double* d_u0, double* d_uT, stmg_stats* stats);
+
+/* Number of time windows (0: the handle holds the whole trajectory).  A
+ * positive mem_budget smaller than about five FP64 trajectories makes the
+ * handle split the N slabs into windows of W = 2^k slabs, W the largest with
+ * six window vectors within the budget.  stmg_solve then solves window after
+ * window (exact: the system is block lower-triangular); stmg_vcycle,
+ * stmg_residual and the stmg_level_* calls return EUNSUPPORTED.  Host only. */
+int stmg_num_windows(const stmg_handle* h);
+
 /* Gradients of L = || U_{N,M} - u_tgt ||^2 (linear problems, periodic grids).  d_U is the
  * converged forward solution; d_gT = dL/du(T) = 2 (U_{N,M} - u_tgt), [ny][nx].
  * Solves the transposed system A^T lam = g (backward in time, same V-cycle
  * kernels) and returns d_grad_u0 = sum_i l_i(0) lam_{0,i} ([ny][nx], device)
- * and *h_grad_nu = sum_{n,i,x} lam_{n,i} dt b_i (Lap_h U_{n,i})(x).  When d_U
- * is NULL the forward trajectory is recomputed window by window from d_u0
- * (checkpointing); d_u0 may be NULL otherwise.  Synchronizes. */
+ * and *h_grad_nu = sum_{n,i,x} lam_{n,i} dt b_i (Lap_h U_{n,i})(x).  On a
+ * windowed handle the windows are processed backward in time, each with its
+ * trajectory taken from d_U or, when d_U is NULL, recomputed from its
+ * checkpoint (d_u0 required then).  Without windows d_U is required and d_u0
+ * may be NULL.  Synchronizes. */
 int stmg_adjoint(stmg_handle* h, const double* d_u0, const double* d_U,
                  const double* d_gT, double* d_grad_u0, double* h_grad_nu,
                  stmg_stats* stats);
 
 /* `sweeps` SDC sweeps (Sec. 2.1 and 3.1: preconditioned Richardson on the
- * collocation form with the implicit-Euler lower-triangular Q_Delta) over
- * all slabs at once, the previous slab's end value lagged; the implicit
- * node solves are spatial V-cycles from the same kernels.  h_rel (may be
- * NULL) receives the relative DG residual after the sweeps.  Linear only. */
+ * collocation form U = 1 (x) u_{n-1} + dt (Q (x) I) F(U), with the
+ * implicit-Euler lower-triangular Q_Delta) over all slabs at once, the
+ * previous slab's end value lagged (Jacobi across slabs).  Per sweep and
+ * node m the implicit solve (I - dt Q_Delta[m][m] L) delta_m = ... runs as
+ * spatial V-cycles (the same kernels with M = 1, all slabs batched) to rtol.
+ * d_U is updated in place; h_rel (may be NULL) receives ||b - A U|| / ||b||
+ * (DG form) afterwards.  Linear problems on a handle set up with
+ * options.sdc = 1 (EUNSUPPORTED otherwise). */
 int stmg_sdc_sweep(stmg_handle* h, const double* d_u0, double* d_U,
                    int32_t sweeps, double* h_rel);
 

@@ -52,6 +52,7 @@ void stmg_default_options(stmg_options* o) {
   o->newton_rtol = 1e-10;
   o->max_newton = 30;
   o->mem_budget = 0;
+  o->sdc = 0;
 }
 
 size_t stmg_workspace_bytes(const stmg_problem* prob, const stmg_options* opt) {
@@ -124,6 +125,11 @@ int stmg_solve(stmg_handle* h, const double* d_u0, double* d_U, stmg_stats* stat
   return h->s.solve(d_u0, d_U, stats);
 }
 
+int stmg_solve_end(stmg_handle* h, const double* d_u0, double* d_uT, stmg_stats* stats) {
+  if (!h || !d_u0 || !d_uT) { stmg::set_error("null pointer"); return STMG_EINVAL; }
+  return h->s.solve_end(d_u0, d_uT, stats);
+}
+
 int stmg_adjoint(stmg_handle* h, const double* d_u0, const double* d_U, const double* d_gT,
                  double* d_grad_u0, double* h_grad_nu, stmg_stats* stats) {
   if (!h || !d_gT || !d_grad_u0 || !h_grad_nu) { stmg::set_error("null pointer"); return STMG_EINVAL; }
@@ -136,12 +142,15 @@ int stmg_sdc_sweep(stmg_handle* h, const double* d_u0, double* d_U, int32_t swee
   return h->s.sdc(d_u0, d_U, sweeps, h_rel);
 }
 
+int stmg_num_windows(const stmg_handle* h) { return h ? h->s.nwin : 0; }
+
 int stmg_level_smooth(stmg_handle* h, int level, const double* d_f, const double* d_u0,
                       const double* d_Uin, double* d_Uout) {
   if (!h || !d_Uout || level < 0 || level >= static_cast<int>(h->s.lv.size())) {
     stmg::set_error("bad argument");
     return STMG_EINVAL;
   }
+  if (h->s.win) { stmg::set_error("windowed handle"); return STMG_EUNSUPPORTED; }
   hipError_t e = h->s.smooth<double>(level, false, stmg::REACT_CONST, d_Uin, d_f,
                                      level == 0 ? d_u0 : nullptr, d_Uout);
   return e == hipSuccess ? STMG_OK : STMG_EHIP;

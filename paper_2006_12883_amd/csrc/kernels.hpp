@@ -138,4 +138,13 @@ hipError_t launch_node_combine(const double* lam_slab, const double* w, int M, s
 hipError_t launch_grad_nu(const OpParams& p, const double* U, const double* lam_rev,
                           double* part, int* nparts, hipStream_t s);
 
+// SDC helpers: in-place r <- G r per point ([N][M][P], G M x M row-major on
+// the device); rhs = r[:, m, :] + acc; U[:, m, :] += d and
+// acc += w (cx D_xx + cy D_yy - lam) d.
+hipError_t launch_node_transform(double* r, int N, int M, int P, const double* G, hipStream_t s);
+hipError_t launch_sdc_gather(const double* r, const double* acc, double* rhs, int N, int M, int P,
+                             int m, hipStream_t s);
+hipError_t launch_sdc_update(double* U, double* acc, const double* d, int N, int M, int nx, int ny,
+                             int bc, double cx, double cy, double lam, double w, int m, hipStream_t s);
+
 }  // namespace stmg

@@ -1464,7 +1464,10 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(const OpParams p, const
   }
   for (int q = threadIdx.x; q < P; q += kBlock) prv[q] = u0 ? u0[q] : 0.0;
   __syncthreads();
-  for (int n = 0; n < p.N; ++n) {
+  // decoupled slabs (no time coupling): one workgroup per slab
+  const int nbeg = gridDim.x > 1 ? (int)blockIdx.x : 0;
+  const int nend = gridDim.x > 1 ? (int)blockIdx.x + 1 : p.N;
+  for (int n = nbeg; n < nend; ++n) {
     for (int k = threadIdx.x; k < K; k += kBlock)
       v[k] = (f ? (double)f[(size_t)n * K + k] : 0.0) + s_cin[k / P] * prv[k % P];
     __syncthreads();
@@ -1685,5 +1688,59 @@ inline int grid_for(size_t n) {
   return (int)b;
 }
 
+
+// SDC: in-place per-point M x M transform r <- G r on [N][M][P] (G row-major).
+__global__ __launch_bounds__(kBlock) void k_node_transform(double* __restrict__ r, int N, int M, int P,
+                                                           const double* __restrict__ G) {
+  __shared__ double g[kMaxM * kMaxM];
+  if (threadIdx.x < kMaxM * kMaxM) g[threadIdx.x] = threadIdx.x < M * M ? G[threadIdx.x] : 0.0;
+  __syncthreads();
+  const size_t total = (size_t)N * P;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += stride) {
+    const size_t n = e / P, q = e % P;
+    double v[kMaxM], w[kMaxM];
+    for (int i = 0; i < M; ++i) v[i] = r[(n * M + i) * P + q];
+    for (int i = 0; i < M; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < M; ++j) s += g[i * M + j] * v[j];
+      w[i] = s;
+    }
+    for (int i = 0; i < M; ++i) r[(n * M + i) * P + q] = w[i];
+  }
+}
+
+// SDC: rhs[n][q] = r[n][m][q] + acc[n][q]
+__global__ __launch_bounds__(kBlock) void k_sdc_gather(const double* __restrict__ r, const double* __restrict__ acc,
+                                                       double* __restrict__ rhs, int N, int M, int P, int m) {
+  const size_t total = (size_t)N * P;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += stride) {
+    const size_t n = e / P, q = e % P;
+    rhs[e] = r[(n * M + m) * P + q] + acc[e];
+  }
+}
+
+// SDC: U[n][m][q] += d[n][q];  acc[n][q] += w (nu Lap - lambda) d [n][q]
+// (periodic or Neumann 5-point stencil on the plane of each slab).
+__global__ __launch_bounds__(kBlock) void k_sdc_update(double* __restrict__ U, double* __restrict__ acc,
+                                                       const double* __restrict__ d, int N, int M, int nx,
+                                                       int ny, int bc, double cx, double cy, double lam,
+                                                       double w, int m) {
+  const int P = nx * ny;
+  const size_t total = (size_t)N * P;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += stride) {
+    const size_t n = e / P;
+    const int q = (int)(e % P);
+    const int x = q % nx, y = q / nx;
+    const double* D = d + n * P;
+    const double c = D[q];
+    double l = cx * (D[y * nx + nb_lo(x, nx, bc)] + D[y * nx + nb_hi(x, nx, bc)] - 2.0 * c);
+    if (ny > 1) l += cy * (D[nb_lo(y, ny, bc) * nx + x] + D[nb_hi(y, ny, bc) * nx + x] - 2.0 * c);
+    U[(n * M + m) * P + q] += c;
+    acc[e] += w * (l - lam * c);
+  }
+}
 }  // namespace
 }  // namespace stmg

@@ -114,6 +114,24 @@ hipError_t launch_grad_nu(const OpParams& p, const double* U, const double* lam,
   return hipGetLastError();
 }
 
+hipError_t launch_node_transform(double* r, int N, int M, int P, const double* G, hipStream_t s) {
+  hipLaunchKernelGGL(k_node_transform, dim3(grid_for((size_t)N * P)), dim3(kBlock), 0, s, r, N, M, P, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_sdc_gather(const double* r, const double* acc, double* rhs, int N, int M, int P,
+                             int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_sdc_gather, dim3(grid_for((size_t)N * P)), dim3(kBlock), 0, s, r, acc, rhs, N, M, P, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_sdc_update(double* U, double* acc, const double* d, int N, int M, int nx, int ny,
+                             int bc, double cx, double cy, double lam, double w, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_sdc_update, dim3(grid_for((size_t)N * nx * ny)), dim3(kBlock), 0, s, U, acc, d, N,
+                     M, nx, ny, bc, cx, cy, lam, w, m);
+  return hipGetLastError();
+}
+
 template hipError_t launch_coarse_solve<double>(const OpParams&, const double*, const double*, const double*, double*, hipStream_t);
 template hipError_t launch_coarse_solve<float>(const OpParams&, const double*, const float*, const double*, float*, hipStream_t);
 template hipError_t launch_coarse_solve_coef<double>(const OpParams&, const double*, double*, const double*, const double*, double*, hipStream_t);

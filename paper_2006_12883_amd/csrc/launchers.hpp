@@ -265,7 +265,10 @@ hipError_t launch_coarse_solve(const OpParams& p, const double* Ainv, const T* f
                                const double* u0, T* U, hipStream_t s) {
   const int P = p.nx * p.ny;
   const size_t shm = (size_t)(2 * p.M * P + P) * sizeof(double);
-  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(kBlock), shm, s, p, Ainv, f, u0, U);
+  bool coupled = false;
+  for (int i = 0; i < p.M; ++i) coupled = coupled || p.cin[i] != 0.0;
+  const int grid = (!coupled && !u0) ? p.N : 1;  // independent slabs in parallel
+  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(grid), dim3(kBlock), shm, s, p, Ainv, f, u0, U);
   return hipGetLastError();
 }
 

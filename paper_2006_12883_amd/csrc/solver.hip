@@ -1,6 +1,7 @@
 // Solver setup, V-cycle and solve drivers (host side of libstmg).
 #include "solver.hpp"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -91,7 +92,7 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     const bool cs_x = (c.ex % 2 == 0) && (p->bc == STMG_BC_PERIODIC ? c.ex >= 4 : c.ex >= 4);
     const bool cs_y = !twod || ((c.ey % 2 == 0) && c.ey >= 4);
     const bool can_s = cs_x && cs_y;
-    const bool can_t = c.N % 2 == 0;
+    const bool can_t = c.N % 2 == 0 && !decoupled;
     const double hx = p->length[0] / c.ex;
     const double hy = twod ? p->length[1] / c.ey : hx;
     const double hmin = hx < hy ? hx : hy;
@@ -146,8 +147,8 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     for (int i = 0; i < M; ++i) {
       op.db[i] = static_cast<double>(l.dt * tab.b[i]);
       opT.db[i] = op.db[i];
-      op.cin[i] = static_cast<double>(tab.l0[i]);
-      op.cout[i] = (i == M - 1) ? 1.0 : 0.0;
+      op.cin[i] = decoupled ? 0.0 : static_cast<double>(tab.l0[i]);
+      op.cout[i] = (i == M - 1 && !decoupled) ? 1.0 : 0.0;
       opT.cin[i] = op.cout[i];
       opT.cout[i] = op.cin[i];
       for (int j = 0; j < M; ++j) {
@@ -165,12 +166,86 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     l.op = op;
     l.opT = opT;
   }
+  // SDC node solvers
+  sdcn.clear();
+  if (o->sdc && !decoupled) {
+    if (allen_cahn) { set_error("SDC sweeps: linear problems only"); return STMG_EUNSUPPORTED; }
+    for (int m = 0; m < M; ++m) {
+      const long double dc = tab.c[m] - (m > 0 ? tab.c[m - 1] : 0.0L);
+      sdc_w[m] = static_cast<double>(p->dt * dc);
+      stmg_problem sp = *p;
+      sp.M = 1;
+      sp.dt = sdc_w[m];
+      stmg_options so = *o;
+      so.sdc = 0;
+      so.mem_budget = 0;
+      so.precision = STMG_PREC_FP64;
+      so.coarsen = STMG_COARSEN_SPACE;
+      std::unique_ptr<Solver> sub(new Solver());
+      sub->decoupled = true;
+      int rc = sub->build(&sp, &so);
+      if (rc) return rc;
+      sdcn.push_back(std::move(sub));
+    }
+  }
+  // Windows: the FP64 path keeps about five full vectors on level 0 (the
+  // caller's U, ping-pong, right-hand side, Newton/adjoint vector and the
+  // adjoint's own ping-pong).
+  win_W = 0;
+  nwin = 0;
+  win.reset();
+  win_last.reset();
+  const size_t P = static_cast<size_t>(lv[0].nx) * lv[0].ny;
+  const size_t slab = static_cast<size_t>(M) * P * sizeof(double);
+  if (o->mem_budget > 0 && 5 * slab * static_cast<size_t>(p->N) > o->mem_budget) {
+    long long W = static_cast<long long>(o->mem_budget / (6 * slab));
+    if (W < 1) W = 1;
+    // largest power of two not above the budget, so windows coarsen in time
+    long long w2 = 1;
+    while (w2 * 2 <= W) w2 *= 2;
+    W = w2;
+    if (W < p->N) {
+      sdcn.clear();  // SDC sweeps act on the whole trajectory
+      win_W = static_cast<int>(W);
+      nwin = (p->N + win_W - 1) / win_W;
+      stmg_options so = *o;
+      so.mem_budget = 0;
+      stmg_problem sp = *p;
+      sp.N = win_W;
+      win.reset(new Solver());
+      int rc = win->build(&sp, &so);
+      if (rc) return rc;
+      const int lastN = p->N - (nwin - 1) * win_W;
+      if (lastN != win_W) {
+        sp.N = lastN;
+        win_last.reset(new Solver());
+        rc = win_last->build(&sp, &so);
+        if (rc) return rc;
+      }
+    }
+  }
   return STMG_OK;
 }
 
 size_t Solver::plan(char* ws) {
   Plan pl;
   pl.base = ws;
+  if (win) {
+    // windowed handle: the sub-solvers' workspaces, checkpoints, one window
+    const size_t P = static_cast<size_t>(lv[0].nx) * lv[0].ny;
+    const size_t wb = win->plan(nullptr);
+    char* wbase = pl.take<char>(wb);
+    win->plan(wbase);
+    if (win_last) {
+      const size_t lb = win_last->plan(nullptr);
+      char* lbase = pl.take<char>(lb);
+      win_last->plan(lbase);
+    }
+    ckpt = pl.take<double>(static_cast<size_t>(nwin) * P);
+    Uw = pl.take<double>(static_cast<size_t>(win_W) * prob.M * P);
+    gw = pl.take<double>(2 * P);
+    return pl.off + 256;
+  }
   for (size_t i = 0; i < lv.size(); ++i) {
     Level& l = lv[i];
     if (i > 0) l.A64 = pl.take<double>(l.n);
@@ -205,10 +280,29 @@ size_t Solver::plan(char* ws) {
   AinvT = pl.take<double>(K * K);
   coarse_scratch = allen_cahn ? pl.take<double>(K * K) : nullptr;
   lw = pl.take<double>(kMaxM);
+  if (!sdcn.empty()) {
+    for (auto& sub : sdcn) {
+      const size_t b = sub->plan(nullptr);
+      sub->plan(pl.take<char>(b));
+    }
+    sdc_acc = pl.take<double>(static_cast<size_t>(lv[0].N) * lv[0].nx * lv[0].ny);
+    sdc_G = pl.take<double>(kMaxM * kMaxM);
+  }
   return pl.off + 256;
 }
 
 int Solver::upload() {
+  if (win) {
+    win->stream = stream;
+    int rc = win->upload();
+    if (rc) return rc;
+    if (win_last) {
+      win_last->stream = stream;
+      rc = win_last->upload();
+      if (rc) return rc;
+    }
+    return STMG_OK;
+  }
   // Coarsest slab matrix: K (x) I + diag(db) (x) (-Lap + lambda), inverted.
   const Level& c = lv.back();
   const int M = prob.M, P = c.nx * c.ny, K = M * P;
@@ -243,6 +337,18 @@ int Solver::upload() {
   double w[kMaxM] = {0};
   for (int i = 0; i < M; ++i) w[i] = static_cast<double>(tab.l0[i]);
   HIP_CHECK(hipMemcpyAsync(lw, w, sizeof(w), hipMemcpyHostToDevice, stream));
+  double G[kMaxM * kMaxM] = {0};
+  if (!sdcn.empty()) {
+    // collocation residual = Q diag(b)^{-1} (DG residual), per slab and point
+    for (int i = 0; i < M; ++i)
+      for (int j = 0; j < M; ++j) G[i * M + j] = static_cast<double>(tab.Q[i][j] / tab.b[j]);
+    HIP_CHECK(hipMemcpyAsync(sdc_G, G, sizeof(G), hipMemcpyHostToDevice, stream));
+    for (auto& sub : sdcn) {
+      sub->stream = stream;
+      int rc = sub->upload();
+      if (rc) return rc;
+    }
+  }
   HIP_CHECK(hipStreamSynchronize(stream));  // host vectors go out of scope
   return STMG_OK;
 }
@@ -496,6 +602,26 @@ int Solver::newton_linearize(const double* U) {
 int Solver::solve(const double* u0, double* U, stmg_stats* st) {
   const auto t0 = std::chrono::steady_clock::now();
   stmg_stats s{};
+  if (win) {
+    // window after window; window w starts from the end value of window w-1
+    const size_t P = static_cast<size_t>(lv[0].nx) * lv[0].ny;
+    const size_t slab = static_cast<size_t>(prob.M) * P;
+    int rc = STMG_OK;
+    for (int w = 0; w < nwin && rc == STMG_OK; ++w) {
+      const double* us = w == 0 ? u0 : U + (static_cast<size_t>(w) * win_W - 1) * slab + (prob.M - 1) * P;
+      stmg_stats sw{};
+      rc = sub(w)->solve(us, U + static_cast<size_t>(w) * win_W * slab, &sw);
+      s.cycles += sw.cycles;
+      s.newton_its += sw.newton_its;
+      s.refinements += sw.refinements;
+      s.rel_res = std::max(s.rel_res, sw.rel_res);
+    }
+    s.status = rc;
+    s.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    last = s;
+    if (st) *st = s;
+    return rc;
+  }
   const double nb = norm_u0_b(u0);
   if (nb < 0.0) return STMG_EHIP;
   int rc = STMG_OK;
@@ -548,6 +674,7 @@ int Solver::solve(const double* u0, double* U, stmg_stats* st) {
 }
 
 int Solver::vcycle_user(const double* u0, double* U, double* h_rel) {
+  if (win) { set_error("stmg_vcycle: not available on a windowed handle"); return STMG_EUNSUPPORTED; }
   Level& L0 = lv[0];
   const bool lin = !allen_cahn;
   const int react = lin ? REACT_CONST : REACT_COEF;
@@ -586,6 +713,7 @@ int Solver::vcycle_user(const double* u0, double* U, double* h_rel) {
 }
 
 int Solver::residual_user(const double* u0, const double* U, double* r, double* h_norm) {
+  if (win) { set_error("stmg_residual: not available on a windowed handle"); return STMG_EUNSUPPORTED; }
   const int react = allen_cahn ? REACT_AC : REACT_CONST;
   HIP_CHECK(residual64<double>(false, react, U, nullptr, u0, r, scal));
   if (h_norm) {
@@ -595,6 +723,37 @@ int Solver::residual_user(const double* u0, const double* U, double* r, double* 
     *h_norm = std::sqrt(r2);
   }
   return STMG_OK;
+}
+
+// Solve and keep only the end value u(T) = U_{N,M} (P values).  On a
+// windowed handle the trajectory is never stored: one window at a time, the
+// window start values go to the checkpoint planes.
+int Solver::solve_end(const double* u0, double* uT, stmg_stats* st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!win) {
+    set_error("stmg_solve_end needs a memory budget that requires time windows");
+    return STMG_EUNSUPPORTED;
+  }
+  const size_t P = static_cast<size_t>(lv[0].nx) * lv[0].ny;
+  stmg_stats s{};
+  int rc = STMG_OK;
+  for (int w = 0; w < nwin && rc == STMG_OK; ++w) {
+    const double* us = w == 0 ? u0 : ckpt + static_cast<size_t>(w) * P;
+    stmg_stats sw{};
+    HIP_CHECK(hipMemsetAsync(Uw, 0, static_cast<size_t>(window_len(w)) * prob.M * P * sizeof(double), stream));
+    rc = sub(w)->solve(us, Uw, &sw);
+    s.cycles += sw.cycles;
+    s.newton_its += sw.newton_its;
+    s.rel_res = std::max(s.rel_res, sw.rel_res);
+    const double* end = Uw + (static_cast<size_t>(window_len(w) - 1) * prob.M + (prob.M - 1)) * P;
+    double* dst = (w + 1 < nwin) ? ckpt + static_cast<size_t>(w + 1) * P : uT;
+    HIP_CHECK(hipMemcpyAsync(dst, end, P * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  }
+  HIP_CHECK(hipStreamSynchronize(stream));
+  s.status = rc;
+  s.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st) *st = s;
+  return rc;
 }
 
 // Adjoint: A^T lam = g with g = dL/du(T) in slab N, node M.  A^T is block
@@ -608,6 +767,54 @@ int Solver::adjoint(const double* u0, const double* U, const double* gT, double*
   // The transposed kernels reuse the symmetric periodic Laplacian; the
   // ghost-reflection Neumann operator is not symmetric.
   if (prob.bc != STMG_BC_PERIODIC) { set_error("adjoint: periodic grids only"); return STMG_EUNSUPPORTED; }
+  if (win) {
+    // Windows backward in time.  Window w's transposed system receives from
+    // window w+1 the coupling e_M (x) (l(0)^T lam_{first slab of w+1}), which is
+    // exactly the "dL/du0" output of window w+1; the window's trajectory is
+    // taken from U or recomputed from its checkpoint.
+    if (!U && !u0) { set_error("adjoint: need the trajectory or u0"); return STMG_EINVAL; }
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t P = static_cast<size_t>(lv[0].nx) * lv[0].ny;
+    const size_t slab = static_cast<size_t>(prob.M) * P;
+    stmg_stats s{};
+    int rc = STMG_OK;
+    if (!U) {
+      stmg_stats sf{};
+      rc = solve_end(u0, gw + P, &sf);  // fills the checkpoints
+      if (rc) return rc;
+      s.cycles += sf.cycles;
+    }
+    double gsum = 0.0;
+    const double* g = gT;
+    for (int w = nwin - 1; w >= 0; --w) {
+      const double* Uwin = nullptr;
+      if (U) {
+        Uwin = U + static_cast<size_t>(w) * win_W * slab;
+      } else {
+        const double* us = w == 0 ? u0 : ckpt + static_cast<size_t>(w) * P;
+        HIP_CHECK(hipMemsetAsync(Uw, 0, static_cast<size_t>(window_len(w)) * slab * sizeof(double), stream));
+        stmg_stats sw{};
+        rc = sub(w)->solve(us, Uw, &sw);
+        if (rc) return rc;
+        s.cycles += sw.cycles;
+        Uwin = Uw;
+      }
+      double gn = 0.0;
+      stmg_stats sa{};
+      double* gout = (w == 0) ? grad_u0 : gw + static_cast<size_t>(w & 1) * P;
+      rc = sub(w)->adjoint(nullptr, Uwin, g, gout, &gn, &sa);
+      if (rc && rc != STMG_ENOTCONV) return rc;
+      s.cycles += sa.cycles;
+      s.rel_res = std::max(s.rel_res, sa.rel_res);
+      gsum += gn;
+      g = gout;
+    }
+    *grad_nu = gsum;
+    s.status = rc;
+    s.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (st) *st = s;
+    return rc;
+  }
   if (!U) { set_error("adjoint: forward trajectory required"); return STMG_EINVAL; }
   (void)u0;
   Level& L0 = lv[0];
@@ -640,9 +847,52 @@ int Solver::adjoint(const double* u0, const double* U, const double* gT, double*
   return rc;
 }
 
-int Solver::sdc(const double*, double*, int, double*) {
-  set_error("SDC sweep not available in this build");
-  return STMG_EUNSUPPORTED;
+// SDC sweeps (Sec. 2.1, 3.1).  One sweep: r_col = Q diag(b)^{-1} r_DG, then
+// for m = 1..M:  (I - dt dc_m L) delta_m = r_col,m + dt sum_{j<m} dc_j L delta_j
+// with the node solves as batched spatial V-cycles, U_m += delta_m.
+int Solver::sdc(const double* u0, double* U, int sweeps, double* h_rel) {
+  if (sdcn.empty() || win) {
+    set_error("stmg_sdc_sweep: set up the handle with options.sdc = 1 (linear problems)");
+    return STMG_EUNSUPPORTED;
+  }
+  Level& L0 = lv[0];
+  const int N = L0.N, M = prob.M, P = L0.nx * L0.ny;
+  const size_t NP = static_cast<size_t>(N) * P;
+  for (int s = 0; s < sweeps; ++s) {
+    HIP_CHECK(residual64<double>(false, REACT_CONST, U, nullptr, u0, delta64, scal));
+    HIP_CHECK(launch_node_transform(delta64, N, M, P, sdc_G, stream));
+    HIP_CHECK(hipMemsetAsync(sdc_acc, 0, NP * sizeof(double), stream));
+    for (int m = 0; m < M; ++m) {
+      Solver* S = sdcn[m].get();
+      double* rhs = S->lv[0].f64;
+      HIP_CHECK(launch_sdc_gather(delta64, sdc_acc, rhs, N, M, P, m, stream));
+      int np = 0;
+      HIP_CHECK(launch_sumsq(rhs, NP, S->part, &np, stream));
+      HIP_CHECK(launch_sum_partials(S->part, np, S->scal + 5, stream));
+      double r2 = 0.0;
+      int rc = read_scalar(S->scal + 5, &r2);
+      if (rc) return rc;
+      HIP_CHECK(hipMemsetAsync(S->delta64, 0, NP * sizeof(double), stream));
+      if (r2 > 0.0) {
+        int cyc = 0;
+        double rel = 0.0;
+        rc = S->solve_linear(false, REACT_CONST, rhs, nullptr, S->delta64, opt.rtol, std::sqrt(r2),
+                             &cyc, &rel);
+        if (rc) return rc;
+      }
+      HIP_CHECK(launch_sdc_update(U, sdc_acc, S->delta64, N, M, L0.nx, L0.ny, L0.op.bc, L0.op.cx,
+                                  L0.op.cy, L0.op.lam, sdc_w[m], m, stream));
+    }
+  }
+  if (h_rel) {
+    HIP_CHECK(residual64<double>(false, REACT_CONST, U, nullptr, u0, nullptr, scal));
+    double r2 = 0.0;
+    int rc = read_scalar(scal, &r2);
+    if (rc) return rc;
+    const double nb = norm_u0_b(u0);
+    *h_rel = nb > 0.0 ? std::sqrt(r2) / nb : std::sqrt(r2);
+  }
+  return STMG_OK;
 }
 
 // explicit instantiations used by the C ABI

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -61,6 +62,31 @@ struct Solver {
   double* lw = nullptr;       // M weights l(0) on the device (gradient of u0)
   // statistics of the last solve
   stmg_stats last{};
+
+  // Time windows (adjoint checkpointing).  When the options' memory budget
+  // cannot hold the trajectory, the handle drives a sub-solver for W slabs
+  // (and one for the shorter last window): A is block lower-triangular, so
+  // solving window after window, each started from the previous window's end
+  // value, is exact.  Only window start values (checkpoints) are kept.
+  int win_W = 0;        // 0: no windows
+  int nwin = 0;
+  std::unique_ptr<Solver> win, win_last;
+  double* ckpt = nullptr;  // start value of window w >= 1, plane w
+  double* Uw = nullptr;    // one window's trajectory
+  double* gw = nullptr;    // two planes: coupling passed backward between windows
+  Solver* sub(int w) { return (w == nwin - 1 && win_last) ? win_last.get() : win.get(); }
+  int window_len(int w) const { return (w == nwin - 1) ? prob.N - (nwin - 1) * win_W : win_W; }
+  int solve_end(const double* u0, double* uT, stmg_stats* st);
+
+  // Independent slabs (no time coupling, space coarsening only): the
+  // Helmholtz solves of the SDC sweep.
+  bool decoupled = false;
+  // SDC: one M = 1 sub-solver per collocation node (operator
+  // I - dt dc_m L on every slab), the accumulated explicit part, Q diag(b)^-1.
+  std::vector<std::unique_ptr<Solver>> sdcn;
+  double* sdc_acc = nullptr;
+  double* sdc_G = nullptr;
+  double sdc_w[kMaxM] = {0};  // dt * (c_m - c_{m-1})
 
   // --- setup ---
   int build(const stmg_problem* p, const stmg_options* o);

@@ -88,7 +88,21 @@ class Handle:
             B.check(rc, "stmg_solve")
         return U, st.as_dict()
 
+    def num_windows(self):
+        return B.lib().stmg_num_windows(self.h)
+
+    def solve_end(self, u0, check=True):
+        """Solve and return only u(T) (windowed handles: no trajectory stored)."""
+        uT = torch.empty(self.space_shape, dtype=torch.float64, device=self.device)
+        st = B.Stats()
+        rc = B.lib().stmg_solve_end(self.h, _ptr(u0), _ptr(uT), ctypes.byref(st))
+        if check:
+            B.check(rc, "stmg_solve_end")
+        return uT, st.as_dict()
+
     def adjoint(self, U, gT, u0=None):
+        """(dL/du0, dL/dnu, stats) for L with dL/du(T) = gT; U may be None on a
+        windowed handle (the trajectory is recomputed from u0)."""
         g = torch.empty(self.space_shape, dtype=torch.float64, device=self.device)
         gnu = ctypes.c_double()
         st = B.Stats()

@@ -102,3 +102,30 @@ def test_vcycle_converges_to_stepper(name, kw):
     rates = [hist[i + 1] / hist[i] for i in range(len(hist) - 1)]
     if not kw:
         assert np.median(rates) < 0.5, rates
+
+
+def test_sdc_fixed_point_and_convergence():
+    """The collocation solution is a fixed point of the SDC sweep, and sweeps
+    from zero converge to it (Sec. 2.1: SDC's fixed point is Radau IIA)."""
+    from oracle import sdc
+    prob = si.problem(1, 16, 3, 6, 0.3, nu=0.1, lam=0.5)
+    u0 = np.random.default_rng(2).standard_normal((1, 16))
+    Ue = stepper.solve_linear(prob, u0)
+    assert np.abs(sdc.sweep(prob, u0, Ue) - Ue).max() < 1e-13
+    U = np.zeros_like(Ue)
+    for _ in range(60):
+        U = sdc.sweep(prob, u0, U)
+    assert np.abs(U - Ue).max() < 1e-11 * np.abs(Ue).max()
+
+
+def test_sdc_m1_is_backward_euler():
+    """With M = 1, Q_Delta = Q: one sweep solves each slab exactly for the
+    lagged initial value, so N sweeps from zero give backward Euler exactly."""
+    from oracle import sdc
+    prob = si.problem(2, 6, 1, 4, 0.2, nu=0.05, lam=0.3)
+    u0 = np.random.default_rng(3).standard_normal((6, 6))
+    Ue = stepper.solve_linear(prob, u0)
+    U = np.zeros_like(Ue)
+    for _ in range(prob["N"]):
+        U = sdc.sweep(prob, u0, U)
+    assert np.abs(U - Ue).max() < 1e-13
