@@ -46,3 +46,18 @@ def solve_linear_periodic(prob, u0):
             U[n, m] = np.fft.ifft2(St[:, m].reshape(ny, nx)).real
         cur = St[:, M - 1]
     return U
+
+
+def end_value_periodic(prob, u0):
+    """u(T) = U_{N,M} only: the coefficient of mode k is R(dt sigma_k)^N u0_hat(k)
+    with R(z) = e_M^T (I - z Q)^{-1} 1 the stability function of the step."""
+    assert prob["bc"] == "periodic"
+    M, N, dt = prob["M"], prob["N"], prob["dt"]
+    Q = radau.tables(M)["Q"]
+    sg = sigma(prob)
+    ny, nx = sg.shape
+    z = (dt * sg).reshape(-1)
+    A = np.eye(M)[None] - z[:, None, None] * Q[None]
+    R = np.linalg.solve(A, np.ones((z.size, M, 1)))[:, M - 1, 0]
+    uh = np.fft.fft2(np.asarray(u0, dtype=np.float64).reshape(ny, nx)).reshape(-1)
+    return np.fft.ifft2((R ** N * uh).reshape(ny, nx)).real

@@ -185,19 +185,6 @@ int stmg_coarse_solve(stmg_handle* h, const double* d_f, double* d_U) {
 
 void stmg_destroy(stmg_handle* h) { delete h; }
 
-size_t stmg_batch_workspace_bytes(int32_t, const stmg_problem*, const stmg_options*) {
-  stmg::set_error("batched solve not available in this build");
-  return 0;
-}
-int stmg_batch_setup(int32_t, const stmg_problem*, const stmg_options*, void*, size_t, void*,
-                     stmg_batch**) {
-  stmg::set_error("batched solve not available in this build");
-  return STMG_EUNSUPPORTED;
-}
-int stmg_batch_solve(stmg_batch*, const double* const*, double* const*, stmg_stats*) {
-  stmg::set_error("batched solve not available in this build");
-  return STMG_EUNSUPPORTED;
-}
-void stmg_batch_destroy(stmg_batch*) {}
+
 
 }  // extern "C"

@@ -786,12 +786,9 @@ __device__ __forceinline__ void resid_vals(const Consts<M, T>& c, const T u[M], 
 
 // Smoother (same mathematics as k_smooth) on 2 x BY blocks.
 template <int M, typename T, int REACT, int BY, bool TWOD>
-__global__ __launch_bounds__(kBlock) void k_smooth_blk(const OpParams p, const SweepPtrs<T> a, int S,
-                                                       int tiles, int nblocks) {
+__device__ __forceinline__ void smooth_blk_body(const OpParams& p, const SweepPtrs<T>& a, int S,
+                                                int tile, int n0, int pslot) {
   constexpr int NP = 2 * BY;
-  const int lb = xcd_remap(blockIdx.x, nblocks);
-  const int tile = lb % tiles;
-  const int n0 = (lb / tiles) * S;
   const int nx = p.nx, P = nx * p.ny;
   const int t = tile * kBlock + threadIdx.x;
   double ssq = 0.0;
@@ -865,18 +862,22 @@ __global__ __launch_bounds__(kBlock) void k_smooth_blk(const OpParams p, const S
   }
   if (a.part) {
     const double tt = block_sum(ssq);
-    if (threadIdx.x == 0) a.part[lb] = tt;
+    if (threadIdx.x == 0) a.part[pslot] = tt;
   }
+}
+
+template <int M, typename T, int REACT, int BY, bool TWOD>
+__global__ __launch_bounds__(kBlock) void k_smooth_blk(const OpParams p, const SweepPtrs<T> a, int S,
+                                                       int tiles, int nblocks) {
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  smooth_blk_body<M, T, REACT, BY, TWOD>(p, a, S, lb % tiles, (lb / tiles) * S, lb);
 }
 
 // Residual (optionally stored as TO) with per-block partial sums of r^2.
 template <int M, typename T, typename TO, int REACT, int BY, bool TWOD>
-__global__ __launch_bounds__(kBlock) void k_residual_blk(const OpParams p, const SweepPtrs<T> a, int S,
-                                                         int tiles, int nblocks) {
+__device__ __forceinline__ void residual_blk_body(const OpParams& p, const SweepPtrs<T>& a, int S,
+                                                  int tile, int n0, int pslot) {
   constexpr int NP = 2 * BY;
-  const int lb = xcd_remap(blockIdx.x, nblocks);
-  const int tile = lb % tiles;
-  const int n0 = (lb / tiles) * S;
   const int nx = p.nx, P = nx * p.ny;
   const int t = tile * kBlock + threadIdx.x;
   double ssq = 0.0;
@@ -926,8 +927,15 @@ __global__ __launch_bounds__(kBlock) void k_residual_blk(const OpParams p, const
   }
   if (a.part) {
     const double tt = block_sum(ssq);
-    if (threadIdx.x == 0) a.part[lb] = tt;
+    if (threadIdx.x == 0) a.part[pslot] = tt;
   }
+}
+
+template <int M, typename T, typename TO, int REACT, int BY, bool TWOD>
+__global__ __launch_bounds__(kBlock) void k_residual_blk(const OpParams p, const SweepPtrs<T> a, int S,
+                                                         int tiles, int nblocks) {
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  residual_blk_body<M, T, TO, REACT, BY, TWOD>(p, a, S, lb % tiles, (lb / tiles) * S, lb);
 }
 
 // Fused residual + restriction on 2 x BY blocks with an LDS tile.  A
@@ -942,21 +950,18 @@ __global__ __launch_bounds__(kBlock) void k_residual_blk(const OpParams p, const
 // a zero iterate (U_c = omega D_c^{-1} f_c along the coarse chunks of cs
 // slabs, which the run [J0, J1) contains whole) and writes it to uc.
 template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY, bool ZS>
-__global__ __launch_bounds__(kBlock) void k_restrict_blk(const OpParams p, const SweepPtrs<T> a,
-                                                         int ncx, int ncy, int Nc,
-                                                         T* __restrict__ fc, int S, int tiles_x,
-                                                         int tiles, int nblocks, const OpParams pc,
-                                                         T* __restrict__ uc,
-                                                         const T* __restrict__ coefc, int cs) {
+__device__ __forceinline__ void restrict_blk_body(const OpParams& p, const SweepPtrs<T>& a, int ncx,
+                                                  int ncy, int Nc, T* __restrict__ fc, int S,
+                                                  int tiles_x, int tile, int J0, const OpParams& pc,
+                                                  T* __restrict__ uc, const T* __restrict__ coefc,
+                                                  int cs, T* lds) {
   constexpr int BY = TWOD ? 2 : 1;
   constexpr int FW = 2 * TCX + 1;
   constexpr int FH = TWOD ? 2 * TCY + 1 : 1;
   constexpr int NHALO = TWOD ? FW + FH - 1 : 1;  // halo column + halo row (corner once)
   static_assert(TCX * TCY == kBlock, "one owned fine block per thread");
-  __shared__ T rs[M][FH][FW];
-  const int lb = xcd_remap(blockIdx.x, nblocks);
-  const int tile = lb % tiles;
-  const int J0 = (lb / tiles) * S;
+  // LDS tile rs[M][FH][FW] provided by the caller (one allocation per kernel)
+  T (*rs)[FH][FW] = reinterpret_cast<T (*)[FH][FW]>(lds);
   if (J0 >= Nc) return;
   const int J1 = min(J0 + S, Nc);
   const int X0 = (tile % tiles_x) * TCX;
@@ -1148,6 +1153,150 @@ __global__ __launch_bounds__(kBlock) void k_restrict_blk(const OpParams p, const
   }
 }
 
+template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY, bool ZS>
+__global__ __launch_bounds__(kBlock) void k_restrict_blk(const OpParams p, const SweepPtrs<T> a,
+                                                         int ncx, int ncy, int Nc,
+                                                         T* __restrict__ fc, int S, int tiles_x,
+                                                         int tiles, int nblocks, const OpParams pc,
+                                                         T* __restrict__ uc,
+                                                         const T* __restrict__ coefc, int cs) {
+  constexpr int FW = 2 * TCX + 1;
+  constexpr int FH = TWOD ? 2 * TCY + 1 : 1;
+  __shared__ T rs[M * FH * FW];
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  restrict_blk_body<M, T, REACT, TM, TWOD, TCX, TCY, ZS>(p, a, ncx, ncy, Nc, fc, S, tiles_x, lb % tiles,
+                                                         (lb / tiles) * S, pc, uc, coefc, cs, rs);
+}
+
+// Fused residual + time restriction (no space coarsening) on 2 x BY blocks:
+// the coarse grid is the fine grid in space, coarse slab J = fine slab 2J+1
+// with the [1 2 1]/2 stencil over slab end points; with ZS also the coarse
+// level's first smoothing sweep from zero (as in restrict_blk_body).
+template <int M, typename T, int REACT, int BY, bool TWOD, bool ZS>
+__device__ __forceinline__ void restrict_t_body(const OpParams& p, const SweepPtrs<T>& a, int Nc,
+                                                T* __restrict__ fc, int S, int tile, int J0,
+                                                const OpParams& pc, T* __restrict__ uc,
+                                                const T* __restrict__ coefc, int cs) {
+  constexpr int NP = 2 * BY;
+  const int nx = p.nx, P = nx * p.ny;
+  const int t = tile * kBlock + threadIdx.x;
+  if (t >= (nx >> 1) * (p.ny / BY) || J0 >= Nc) return;
+  const int J1 = min(J0 + S, Nc);
+  const Consts<M, T> c(p);
+  const Blk<BY> b(t, nx, p.ny);
+  const int nlo = 2 * J0, nhi = min(2 * J1, p.N - 1);
+  T prev[NP];
+  run_prev<M, T, BY>(c, a, nlo, P, nx, b, prev);
+  T acc[NP][M];
+  T zd[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    zd[k] = T(0);
+#pragma unroll
+    for (int i = 0; i < M; ++i) acc[k][i] = T(0);
+  }
+  auto emit = [&](int J, T v[NP][M]) {
+    const size_t cb = (size_t)J * M * P;
+    store_own<M, T, BY>(fc, cb, P, nx, b, v);
+    if (ZS) {
+      const Consts<M, T> k(pc);
+      T cvv[NP][M], o[NP][M];
+      if (REACT == REACT_COEF) load_own<M, T, BY>(coefc, cb, P, nx, b, cvv);
+      const T dgc = T(2) * k.cx + (TWOD ? T(2) * k.cy : T(0));
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        T d[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) d[i] = v[q][i] + ((J % cs) != 0 ? k.cin[i] * zd[q] : T(0));
+        if (REACT == REACT_COEF) {
+          point_block_solve<M, T>(k, dgc, cvv[q], d);
+        } else {
+          T rr[M];
+#pragma unroll
+          for (int i = 0; i < M; ++i) rr[i] = d[i];
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            T sm = T(0);
+#pragma unroll
+            for (int j = 0; j < M; ++j) sm += k.Bi[i][j] * rr[j];
+            d[i] = sm;
+          }
+        }
+        T nd = T(0);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          o[q][i] = k.omega * d[i];
+          nd += k.cout[i] * d[i];
+        }
+        zd[q] = nd;
+      }
+      store_own<M, T, BY>(uc, cb, P, nx, b, o);
+    }
+  };
+  for (int n = nlo; n <= nhi; ++n) {
+    const size_t base = (size_t)n * M * P;
+    T u[NP][M], lap[NP][M], fv[NP][M], cv[NP][M], rr[NP][M];
+    if (a.U) {
+      load_blk<M, T, BY, TWOD>(a.U, base, P, nx, b, c.cx, c.cy, u, lap);
+    } else {
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int m = 0; m < M; ++m) u[k][m] = lap[k][m] = T(0);
+    }
+    if (a.f) {
+      load_own<M, T, BY>(a.f, base, P, nx, b, fv);
+    } else {
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int m = 0; m < M; ++m) fv[k][m] = T(0);
+    }
+    if (REACT == REACT_COEF) load_own<M, T, BY>(a.coef, base, P, nx, b, cv);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      resid_vals<M, T, REACT>(c, u[k], lap[k], fv[k], cv[k], prev[k], rr[k]);
+      T np = T(0);
+#pragma unroll
+      for (int i = 0; i < M; ++i) np += c.cout[i] * u[k][i];
+      prev[k] = np;
+    }
+    if (n & 1) {
+      const int J = n >> 1;
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int i = 0; i < M; ++i) acc[k][i] += rr[k][i];
+      if (J == Nc - 1) emit(J, acc);
+    } else {
+      const int J = n >> 1;
+      if (J > J0) {
+        T v[NP][M];
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+          for (int i = 0; i < M; ++i) v[k][i] = acc[k][i] + T(0.5) * rr[k][i];
+        emit(J - 1, v);
+      }
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int i = 0; i < M; ++i) acc[k][i] = T(0.5) * rr[k][i];
+    }
+  }
+}
+
+template <int M, typename T, int REACT, int BY, bool TWOD, bool ZS>
+__global__ __launch_bounds__(kBlock) void k_restrict_t_blk(const OpParams p, const SweepPtrs<T> a, int Nc,
+                                                           T* __restrict__ fc, int S, int tiles,
+                                                           int nblocks, const OpParams pc,
+                                                           T* __restrict__ uc,
+                                                           const T* __restrict__ coefc, int cs) {
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  restrict_t_body<M, T, REACT, BY, TWOD, ZS>(p, a, Nc, fc, S, lb % tiles, (lb / tiles) * S, pc, uc,
+                                             coefc, cs);
+}
+
 // Prolongation + correction on 2 x BY fine blocks (space coarsening: the
 // block of coarse point (X, Y) is fine (2X .. 2X+1) x (2Y .. 2Y+1); time
 // interpolation as in k_prolong).
@@ -1236,14 +1385,10 @@ __global__ __launch_bounds__(kBlock) void k_prolong_blk(const OpParams p, int nc
 // stored.  Space interpolation is linear per dimension (fine 2X = coarse X),
 // time interpolation is linear in slab end points (coarse -1 = 0).
 template <int M, typename T, int REACT, bool SP, bool TM, int BY, bool TWOD>
-__global__ __launch_bounds__(kBlock) void k_prolong_smooth_blk(const OpParams p, const SweepPtrs<T> a,
-                                                               int ncx, int ncy, int Nc,
-                                                               const T* __restrict__ ec, int S,
-                                                               int tiles, int nblocks) {
+__device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const SweepPtrs<T>& a, int ncx,
+                                                    int ncy, int Nc, const T* __restrict__ ec, int S,
+                                                    int tile, int n0, int pslot) {
   constexpr int NP = 2 * BY;
-  const int lb = xcd_remap(blockIdx.x, nblocks);
-  const int tile = lb % tiles;
-  const int n0 = (lb / tiles) * S;
   const int nx = p.nx, ny = p.ny, P = nx * ny;
   const int Pc = ncx * ncy;
   const int t = tile * kBlock + threadIdx.x;
@@ -1440,18 +1585,44 @@ __global__ __launch_bounds__(kBlock) void k_prolong_smooth_blk(const OpParams p,
   }
   if (a.part) {
     const double tt = block_sum(ssq);
-    if (threadIdx.x == 0) a.part[lb] = tt;
+    if (threadIdx.x == 0) a.part[pslot] = tt;
   }
+}
+
+template <int M, typename T, int REACT, bool SP, bool TM, int BY, bool TWOD>
+__global__ __launch_bounds__(kBlock) void k_prolong_smooth_blk(const OpParams p, const SweepPtrs<T> a,
+                                                               int ncx, int ncy, int Nc,
+                                                               const T* __restrict__ ec, int S,
+                                                               int tiles, int nblocks) {
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  prolong_smooth_body<M, T, REACT, SP, TM, BY, TWOD>(p, a, ncx, ncy, Nc, ec, S, lb % tiles,
+                                                     (lb / tiles) * S, lb);
 }
 
 // ---------------------------------------------------------------------------
 // Coarsest level: U_n = Ainv (f_n + cin (x) (cout . U_{n-1})) slab after slab
 // in one workgroup; Ainv is the inverse of the (constant) slab matrix.
 template <typename T>
+__device__ __forceinline__ void coarse_solve_body(const OpParams& p, const double* __restrict__ Ainv,
+                                                  const T* __restrict__ f,
+                                                  const double* __restrict__ u0,
+                                                  T* __restrict__ U, int nbeg_in, int nend_in);
+
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarse_solve(const OpParams p, const double* __restrict__ Ainv,
                                                          const T* __restrict__ f,
                                                          const double* __restrict__ u0,
                                                          T* __restrict__ U) {
+  // decoupled slabs (no time coupling): one workgroup per slab
+  if (gridDim.x > 1) coarse_solve_body<T>(p, Ainv, f, u0, U, blockIdx.x, blockIdx.x + 1);
+  else coarse_solve_body<T>(p, Ainv, f, u0, U, 0, p.N);
+}
+
+template <typename T>
+__device__ __forceinline__ void coarse_solve_body(const OpParams& p, const double* __restrict__ Ainv,
+                                                  const T* __restrict__ f,
+                                                  const double* __restrict__ u0,
+                                                  T* __restrict__ U, int nbeg, int nend) {
   extern __shared__ double sm[];
   __shared__ double s_cin[kMaxM], s_cout[kMaxM];
   const int P = p.nx * p.ny, M = p.M, K = M * P;
@@ -1464,9 +1635,6 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(const OpParams p, const
   }
   for (int q = threadIdx.x; q < P; q += kBlock) prv[q] = u0 ? u0[q] : 0.0;
   __syncthreads();
-  // decoupled slabs (no time coupling): one workgroup per slab
-  const int nbeg = gridDim.x > 1 ? (int)blockIdx.x : 0;
-  const int nend = gridDim.x > 1 ? (int)blockIdx.x + 1 : p.N;
   for (int n = nbeg; n < nend; ++n) {
     for (int k = threadIdx.x; k < K; k += kBlock)
       v[k] = (f ? (double)f[(size_t)n * K + k] : 0.0) + s_cin[k / P] * prv[k % P];

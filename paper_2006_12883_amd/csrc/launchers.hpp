@@ -173,6 +173,29 @@ hipError_t launch_restrict_residual(const OpParams& p, int react, const SweepPtr
 #undef LRS
     return hipGetLastError();
   }
+  if (!space && time && blocked(p)) {
+    const bool zs = uc != nullptr && pc != nullptr && cs >= 1 && (spb % cs) == 0;
+    if (smoothed) *smoothed = zs;
+    const OpParams& pcc = zs ? *pc : p;
+    const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
+    const int nb = tiles * ((Nc + spb - 1) / spb);
+#define LT(MM, RE, BYc, TWc)                                                                       \
+  if (zs)                                                                                           \
+    hipLaunchKernelGGL((k_restrict_t_blk<MM, T, RE, BYc, TWc, true>), dim3(nb), dim3(kBlock), 0, s, p, a, \
+                       Nc, fc, spb, tiles, nb, pcc, uc, coefc, cs);                                 \
+  else                                                                                              \
+    hipLaunchKernelGGL((k_restrict_t_blk<MM, T, RE, BYc, TWc, false>), dim3(nb), dim3(kBlock), 0, s, p, a, \
+                       Nc, fc, spb, tiles, nb, pcc, uc, coefc, cs)
+#define LTS(MM, RE) \
+  if (twod) { LT(MM, RE, 2, true); } else { LT(MM, RE, 1, false); }
+#define L(MM) \
+  if (react == REACT_COEF) { LTS(MM, REACT_COEF) } else { LTS(MM, REACT_CONST) }
+    STMG_DISPATCH_M(L)
+#undef L
+#undef LTS
+#undef LT
+    return hipGetLastError();
+  }
   const int Pc = ncx * ncy;
   const int tiles = (Pc + kBlock - 1) / kBlock;
   const int chunks = (Nc + spb - 1) / spb;

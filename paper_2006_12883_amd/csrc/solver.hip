@@ -89,8 +89,9 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   while (static_cast<int>(lv.size()) < o->max_levels) {
     Level& c = lv.back();
     if (static_cast<long long>(M) * c.nx * c.ny * c.N <= o->min_coarse) break;
-    const bool cs_x = (c.ex % 2 == 0) && (p->bc == STMG_BC_PERIODIC ? c.ex >= 4 : c.ex >= 4);
-    const bool cs_y = !twod || ((c.ey % 2 == 0) && c.ey >= 4);
+    const int q = batch_member ? 4 : 2;
+    const bool cs_x = (c.ex % q == 0) && c.ex >= 4;
+    const bool cs_y = !twod || ((c.ey % q == 0) && c.ey >= 4);
     const bool can_s = cs_x && cs_y;
     const bool can_t = c.N % 2 == 0 && !decoupled;
     const double hx = p->length[0] / c.ex;
@@ -230,6 +231,22 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
 size_t Solver::plan(char* ws) {
   Plan pl;
   pl.base = ws;
+  if (batch_member) {
+    for (auto& l : lv) {
+      l.A32 = pl.take<float>(l.n);
+      l.B32 = pl.take<float>(l.n);
+      l.f32 = pl.take<float>(l.n);
+    }
+    max_parts = 1024;
+    part = pl.take<double>(1024);
+    scal = pl.take<double>(32);
+    const Level& c = lv.back();
+    const size_t K = static_cast<size_t>(prob.M) * c.nx * c.ny;
+    Ainv = pl.take<double>(K * K);
+    AinvT = pl.take<double>(K * K);
+    lw = pl.take<double>(kMaxM);
+    return pl.off + 256;
+  }
   if (win) {
     // windowed handle: the sub-solvers' workspaces, checkpoints, one window
     const size_t P = static_cast<size_t>(lv[0].nx) * lv[0].ny;

@@ -81,6 +81,10 @@ struct Solver {
   // Independent slabs (no time coupling, space coarsening only): the
   // Helmholtz solves of the SDC sweep.
   bool decoupled = false;
+  // Member of a batch: FP32 level buffers only, and space coarsening only
+  // while the coarse grid keeps an even point count (register-blocked
+  // kernels on every level).
+  bool batch_member = false;
   // SDC: one M = 1 sub-solver per collocation node (operator
   // I - dt dc_m L on every slab), the accumulated explicit part, Q diag(b)^-1.
   std::vector<std::unique_ptr<Solver>> sdcn;

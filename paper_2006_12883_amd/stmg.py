@@ -140,3 +140,55 @@ def solve(u0, prob, **opts):
         return h.solve(u0)
     finally:
         h.close()
+
+
+class Batch:
+    """Many independent 2D periodic linear problems solved together
+    (stmg_batch_*): FP32 V-cycles inside FP64 refinement, one graph replay
+    per refinement step for all problems."""
+
+    def __init__(self, probs, device="cuda", **opts):
+        self.probs = [dict(p) for p in probs]
+        self.device = torch.device(device)
+        n = len(probs)
+        self._p = (B.Problem * n)(*[B.make_problem(p) for p in probs])
+        self._o = B.make_options(**opts)
+        L = B.lib()
+        nbytes = L.stmg_batch_workspace_bytes(n, self._p, ctypes.byref(self._o))
+        if nbytes == 0:
+            raise B.STMGError(B.STMG_EUNSUPPORTED, "stmg_batch_workspace_bytes")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        B.check(L.stmg_batch_setup(n, self._p, ctypes.byref(self._o), ctypes.c_void_p(base + off), nbytes,
+                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "stmg_batch_setup")
+        self.h = h
+        self.shapes = []
+        for p in probs:
+            ny, nx = p["nx"][1], p["nx"][0]
+            self.shapes.append((p["N"], p["M"], ny, nx))
+
+    def solve(self, u0s, Us=None, check=True):
+        n = len(self.probs)
+        if Us is None:
+            Us = [torch.zeros(s, dtype=torch.float64, device=self.device) for s in self.shapes]
+        pu0 = (ctypes.c_void_p * n)(*[_ptr(u).value for u in u0s])
+        pU = (ctypes.c_void_p * n)(*[_ptr(U).value for U in Us])
+        st = (B.Stats * n)()
+        rc = B.lib().stmg_batch_solve(self.h, pu0, pU, st)
+        if check:
+            B.check(rc, "stmg_batch_solve")
+        return Us, [s.as_dict() for s in st]
+
+    def close(self):
+        if getattr(self, "h", None):
+            B.lib().stmg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

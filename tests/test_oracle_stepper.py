@@ -180,3 +180,10 @@ def test_allen_cahn_fixed_points_and_dense():
     V = allatonce.dense_solve(prob, u0)
     assert np.abs(U - V).max() < 1e-13
     assert np.abs(allatonce.residual(prob, u0, U)).max() < 1e-13
+
+
+def test_fourier_end_value_matches_stepper():
+    prob = si.problem(2, 16, 3, 7, 0.4, nu=0.02, lam=0.6)
+    u0 = si.u0_rd2d(prob, 3)
+    U = stepper.solve_linear(prob, u0)
+    assert np.abs(fourier.end_value_periodic(prob, u0) - U[-1, -1]).max() <= 1e-13 * np.abs(U).max()
