@@ -24,6 +24,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the level-0 smoothing sweep from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs (scaled by a device copy of known size; see
+# profiles/k_smooth_blk_rd2d_level0.md), valid only for the kernel source it
+# was measured on.
+TRAFFIC = {"kernels_impl_sha256_prefix": "e89f6e0364023732", "bytes_per_launch": 450.6e6 + 402.65e6}
+
+
+def measured_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2006_12883_amd", "csrc", "kernels_impl.hpp")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return TRAFFIC["bytes_per_launch"] if h == TRAFFIC["kernels_impl_sha256_prefix"] else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -31,6 +44,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (Allen-Cahn Newton, adjoint, batch)")
     ap.add_argument("--kernel-iters", type=int, default=20)
     ap.add_argument("--kernel-only", action="store_true",
                     help="only time the level-0 smoothing sweep and a plain device copy of the "
@@ -44,10 +59,12 @@ def smoother_bytes_per_dof():
     return 16.0
 
 
-def cpu_baseline(prob, u0, cycles_per_solve):
-    """The oracle's plain NumPy V-cycle on the same workload, 1 thread."""
+def cpu_baseline(prob, u0, gpu_solutions):
+    """The CPU leg: the oracle's plain NumPy V-cycle on the same workload
+    (1 thread), plus the oracle's closed-form solution of the workload, which
+    gives the error of each GPU result against the FP64 oracle."""
     from threadpoolctl import threadpool_limits
-    from oracle import mg
+    from oracle import fourier, mg
     with threadpool_limits(limits=1):
         levels, kinds = mg.hierarchy(prob)
         f = mg.rhs(levels, u0)
@@ -55,11 +72,21 @@ def cpu_baseline(prob, u0, cycles_per_solve):
         t0 = time.perf_counter()
         U = mg.vcycle(levels, kinds, U, f)
         t = time.perf_counter() - t0
+        del U, f
+        t1 = time.perf_counter()
+        ref = fourier.solve_linear_periodic(prob, u0)
+        tf = time.perf_counter() - t1
     dof = float(np.prod(levels[0].shape))
+    errs = {}
+    for k, V in gpu_solutions.items():
+        errs[k] = {"rel_err": float(np.linalg.norm(V - ref) / np.linalg.norm(ref)),
+                   "rel_err_at_T": float(np.linalg.norm(V[-1, -1] - ref[-1, -1]) / np.linalg.norm(ref[-1, -1]))}
     return {"value": dof / t, "unit": "DOF*V-cycles/s", "cores": 1, "kind": "oracle",
             "sample": "one V-cycle of the oracle's NumPy multigrid (oracle.mg) on the full "
                       "256^2 x M=3 x N=256 workload, 1 thread; %.1f s" % t,
-            "seconds_per_vcycle": t}
+            "seconds_per_vcycle": t,
+            "fourier_closed_form_seconds": tf,
+            "gpu_error_vs_oracle": errs}
 
 
 def time_kernels(h, U, u0, iters):
@@ -88,6 +115,72 @@ def time_kernels(h, U, u0, iters):
     e1.synchronize()
     c_ms = e0.elapsed_time(e1) / iters
     return k_ms, c_ms, 2.0 * x.numel() * 8
+
+
+def extras(dev):
+    """The other synthetic workloads, each timed once after a warm-up call."""
+    import torch
+    import stmg_inputs as si
+    from paper_2006_12883_amd import stmg
+    out = {}
+    # 2D Allen-Cahn 512^2 x M=3 x N=512, Newton with FP32 V-cycles inside FP64 refinement
+    prob = si.config("ac2d")
+    u0 = torch.as_tensor(si.initial("ac2d", prob)).to(dev)
+    h = stmg.Handle(prob, device=dev, precision="mixed", newton_rtol=1e-10)
+    U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
+    h.solve(u0, U)
+    U.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = h.solve(u0, U)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    dof = float(np.prod(h.shape))
+    out["allen_cahn_512x512_M3_N512_mixed"] = {
+        "seconds_to_1e-10": t, "newton_its": st["newton_its"], "vcycles": st["cycles"],
+        "rel_res": st["rel_res"], "dof": int(dof), "dof_vcycles_per_s": dof * st["cycles"] / t}
+    del h, U
+    torch.cuda.empty_cache()
+    print("allen-cahn done", file=sys.stderr, flush=True)
+    # adjoint on the 256^2 workload: gradient w.r.t. u0 and nu
+    prob = si.config("adj2d")
+    u0n = si.initial("adj2d", prob)
+    u0 = torch.as_tensor(u0n).to(dev)
+    tgt = torch.as_tensor(si.u_tgt_adj2d(prob)).to(dev)
+    h = stmg.Handle(prob, device=dev)
+    U, _ = h.solve(u0)
+    g = 2.0 * (U[-1, -1] - tgt)
+    h.adjoint(U, g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gu0, gnu, st = h.adjoint(U, g)
+    torch.cuda.synchronize()
+    out["adjoint_256x256_M3_N256_fp64"] = {"seconds": time.perf_counter() - t0, "vcycles": st["cycles"],
+                                          "rel_res": st["rel_res"], "dL_dnu": gnu}
+    del h, U
+    torch.cuda.empty_cache()
+    print("adjoint done", file=sys.stderr, flush=True)
+    # 64 batched problems, FP32 V-cycles in FP64 refinement to 1e-10
+    probs = si.batch64()
+    u0s = [torch.as_tensor(si.batch_u0(p, i)).to(dev) for i, p in enumerate(probs)]
+    b = stmg.Batch(probs, device=dev, rtol=1e-10)
+    Us, _ = b.solve(u0s)
+    for U in Us:
+        U.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Us, sts = b.solve(u0s, Us)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    dofs = [float(np.prod(U.shape)) for U in Us]
+    out["batch64_mixed"] = {"seconds_to_1e-10": t, "problems": len(probs), "total_dof": int(sum(dofs)),
+                            "max_cycles": max(st["cycles"] for st in sts),
+                            "dof_vcycles_per_s": sum(d * st["cycles"] for d, st in zip(dofs, sts)) / t,
+                            "max_rel_res": max(st["rel_res"] for st in sts)}
+    del b, Us
+    torch.cuda.empty_cache()
+    print("batch done", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -138,6 +231,7 @@ def main():
 
     # time to a 1e-10 residual: FP64 vs mixed precision
     ttr = {}
+    sols = {"solve_fp64_rtol1e-12": U.cpu().numpy()}
     for prec in ("fp64", "mixed"):
         hh = stmg.Handle(prob, device=dev, precision=prec, rtol=1e-10)
         V = torch.zeros(shape, dtype=torch.float64, device=dev)
@@ -153,6 +247,7 @@ def main():
             if best is None or el < best[0]:
                 best = (el, st)
         ttr[prec] = {"seconds": best[0], "cycles": best[1]["cycles"], "rel_res": best[1]["rel_res"]}
+        sols["solve_" + prec + "_rtol1e-10"] = V.cpu().numpy()
         hh.close()
         del V
     print("time-to-1e-10 done", file=sys.stderr, flush=True)
@@ -182,14 +277,18 @@ def main():
                    "final_rel_res": max(rels)},
         "time_to_1e-10": ttr,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_smooth<3,double,0> (level 0)", "kernel_ms": k_ms,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "k_smooth_blk<3,double,0,2,true> (level 0)", "kernel_ms": k_ms,
                      "bytes_per_launch": kbytes,
                      "copy_GBs_same_bytes": cbytes / (c_ms * 1e-3) / 1e9},
     }
+    if not a.no_extras:
+        del h, U
+        torch.cuda.empty_cache()
+        out["other_workloads"] = extras(dev)
     if not a.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob, u0n, cycles / a.steps)
+        out["cpu_baseline"] = cpu_baseline(prob, u0n, sols)
     print(json.dumps(out), flush=True)
 
 

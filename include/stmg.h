@@ -106,6 +106,11 @@ typedef struct {
   size_t mem_budget;  /* adjoint: max bytes for the stored forward trajectory;
                          0 = unlimited (no checkpointing)                     */
   int32_t sdc;        /* 1: reserve workspace for stmg_sdc_sweep, 0 (default) */
+  int32_t autotune;   /* 1: at setup, time the launch shapes of the transfer
+                         kernels per level and keep the fastest (results are
+                         bitwise identical for every shape); choices are
+                         cached in the JSON file named by $STMG_TUNE_CACHE.
+                         0 (default): fixed shapes                            */
 } stmg_options;
 
 typedef struct {
@@ -167,6 +172,11 @@ int stmg_solve(stmg_handle* h, const double* d_u0, double* d_U, stmg_stats* stat
  * window and keeps the window start values as checkpoints in the workspace,
  * so the trajectory is never stored.  EUNSUPPORTED on other handles. */
 int stmg_solve_end(stmg_handle* h, const double* d_u0, double* d_uT, stmg_stats* stats);
+
+/* Slabs per workgroup run of the restriction from `level` to level + 1 (the
+ * autotuned value with options.autotune, else the fixed default); 0 for the
+ * coarsest level.  Host only. */
+int stmg_tuned_shape(const stmg_handle* h, int level);
 
 /* Number of time windows (0: the handle holds the whole trajectory).  A
  * positive mem_budget smaller than about five FP64 trajectories makes the

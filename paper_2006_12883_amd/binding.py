@@ -22,7 +22,7 @@ COARSEN = {"auto": 0, "space": 1, "spacetime": 2}
 EXPORTS = [
     "stmg_default_options", "stmg_workspace_bytes", "stmg_setup", "stmg_num_levels",
     "stmg_level_shape", "stmg_residual", "stmg_vcycle", "stmg_solve", "stmg_solve_end",
-    "stmg_num_windows", "stmg_adjoint",
+    "stmg_num_windows", "stmg_tuned_shape", "stmg_adjoint",
     "stmg_sdc_sweep", "stmg_level_smooth", "stmg_level_restrict_residual",
     "stmg_level_prolong", "stmg_coarse_solve", "stmg_destroy",
     "stmg_batch_workspace_bytes", "stmg_batch_setup", "stmg_batch_solve",
@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32),
                 ("nu_post", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("min_coarse", ctypes.c_int32),
                 ("max_cycles", ctypes.c_int32), ("rtol", ctypes.c_double), ("newton_rtol", ctypes.c_double),
-                ("max_newton", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("sdc", ctypes.c_int32)]
+                ("max_newton", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("sdc", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -77,6 +78,7 @@ def lib():
             "stmg_adjoint": (ip, [vp, vp, vp, vp, vp, dp, S]),
             "stmg_solve_end": (ip, [vp, vp, vp, S]),
             "stmg_num_windows": (ip, [vp]),
+            "stmg_tuned_shape": (ip, [vp, ip]),
             "stmg_sdc_sweep": (ip, [vp, vp, vp, ctypes.c_int32, dp]),
             "stmg_level_smooth": (ip, [vp, ip, vp, vp, vp, vp]),
             "stmg_level_restrict_residual": (ip, [vp, ip, vp, vp, vp, vp]),

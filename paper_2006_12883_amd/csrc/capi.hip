@@ -53,6 +53,7 @@ void stmg_default_options(stmg_options* o) {
   o->max_newton = 30;
   o->mem_budget = 0;
   o->sdc = 0;
+  o->autotune = 0;
 }
 
 size_t stmg_workspace_bytes(const stmg_problem* prob, const stmg_options* opt) {
@@ -88,6 +89,10 @@ int stmg_setup(const stmg_problem* prob, const stmg_options* opt, void* d_ws, si
   h->s.plan(static_cast<char*>(d_ws));
   rc = h->s.upload();
   if (rc) { delete h; return rc; }
+  if (opt->autotune) {
+    rc = h->s.autotune();
+    if (rc) { delete h; return rc; }
+  }
   *out = h;
   return STMG_OK;
 }
@@ -143,6 +148,11 @@ int stmg_sdc_sweep(stmg_handle* h, const double* d_u0, double* d_U, int32_t swee
 }
 
 int stmg_num_windows(const stmg_handle* h) { return h ? h->s.nwin : 0; }
+
+int stmg_tuned_shape(const stmg_handle* h, int level) {
+  if (!h || level < 0 || level + 1 >= static_cast<int>(h->s.lv.size())) return 0;
+  return h->s.transfer_slabs(level + 1);
+}
 
 int stmg_level_smooth(stmg_handle* h, int level, const double* d_f, const double* d_u0,
                       const double* d_Uin, double* d_Uout) {

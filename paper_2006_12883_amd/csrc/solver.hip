@@ -4,7 +4,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 
 namespace stmg {
 
@@ -378,6 +383,7 @@ int Solver::chunk_of(int l) const { return l == 0 ? opt.chunk : opt.chunk_coarse
 // (more parallelism; their cost is latency, not bandwidth).  No effect on
 // results.
 int Solver::transfer_slabs(int l) const {
+  if (l < static_cast<int>(tuned.size()) && tuned[l] > 0) return tuned[l];
   const Level& L = lv[l];
   const long long pts = static_cast<long long>(L.nx) * L.ny;
   return pts * L.N >= (1LL << 22) ? kTransferSlabs : 1;
@@ -917,5 +923,115 @@ template hipError_t Solver::smooth<double>(int, bool, int, const double*, const 
 template hipError_t Solver::restrict_residual<double>(int, bool, int, const double*, const double*, const double*, double*, double*, bool*);
 template hipError_t Solver::prolong<double>(int, const double*, const double*, double*);
 template hipError_t Solver::coarse<double>(bool, int, const double*, const double*, double*);
+
+}  // namespace stmg
+
+namespace stmg {
+
+// Autotuner for the launch shape (slabs per workgroup run) of the restriction
+// kernels, level by level: each candidate is a multiple of the coarse level's
+// smoother block (so the fused coarse sweep stays possible) and gives bitwise
+// identical results; the fastest of three timed launches wins.  Choices are
+// kept in a JSON object {"key": slabs} in $STMG_TUNE_CACHE.
+namespace {
+std::string tune_key(const Solver& s, int l) {
+  const Level& F = s.lv[l];
+  std::ostringstream k;
+  k << (s.mixed ? "f32" : "f64") << "_M" << s.prob.M << "_" << F.nx << "x" << F.ny << "x" << F.N << "_k"
+    << F.kind << "_c" << s.chunk_of(l + 1);
+  return k.str();
+}
+
+std::map<std::string, int> read_cache(const char* path) {
+  std::map<std::string, int> m;
+  std::ifstream in(path);
+  if (!in) return m;
+  std::stringstream ss;
+  ss << in.rdbuf();
+  const std::string t = ss.str();
+  size_t i = 0;
+  while ((i = t.find('"', i)) != std::string::npos) {
+    const size_t j = t.find('"', i + 1);
+    if (j == std::string::npos) break;
+    const std::string key = t.substr(i + 1, j - i - 1);
+    const size_t c = t.find(':', j);
+    if (c == std::string::npos) break;
+    m[key] = std::atoi(t.c_str() + c + 1);
+    i = t.find_first_of(",}", c);
+    if (i == std::string::npos) break;
+  }
+  return m;
+}
+
+void write_cache(const char* path, const std::map<std::string, int>& m) {
+  std::ofstream out(path);
+  out << "{";
+  bool first = true;
+  for (const auto& kv : m) {
+    out << (first ? "" : ",") << "\n  \"" << kv.first << "\": " << kv.second;
+    first = false;
+  }
+  out << "\n}\n";
+}
+}  // namespace
+
+int Solver::autotune() {
+  if (win || lv.size() < 2) return STMG_OK;
+  tuned.assign(lv.size(), 0);
+  const char* path = std::getenv("STMG_TUNE_CACHE");
+  std::map<std::string, int> cache;
+  if (path) cache = read_cache(path);
+  bool dirty = false;
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  for (size_t l = 0; l + 1 < lv.size(); ++l) {
+    const std::string key = tune_key(*this, static_cast<int>(l));
+    auto it = cache.find(key);
+    if (it != cache.end() && it->second > 0) {
+      tuned[l + 1] = it->second;
+      continue;
+    }
+    const int cs = chunk_of(static_cast<int>(l) + 1);
+    float best = 1e30f;
+    int bestS = 0;
+    for (int mult : {1, 2, 4, 8}) {
+      const int S = cs * mult;
+      if (S > 64 || (mult > 1 && S > lv[l + 1].N)) break;
+      tuned[l + 1] = S;
+      Level& F = lv[l];
+      Level& C = lv[l + 1];
+      float tot = 0.0f;
+      for (int rep = 0; rep < 4; ++rep) {
+        HIP_CHECK(hipEventRecord(e0, stream));
+        if (!mixed) {
+          const bool zs = l + 2 < lv.size();
+          HIP_CHECK(restrict_residual<double>(static_cast<int>(l), false, REACT_CONST, l == 0 ? lv[0].B64 : F.A64,
+                                              l == 0 ? nullptr : F.f64, nullptr, C.f64, zs ? C.A64 : nullptr,
+                                              nullptr));
+        } else {
+          const bool zs = l + 2 < lv.size();
+          HIP_CHECK(restrict_residual<float>(static_cast<int>(l), false, REACT_CONST, F.A32, F.f32, nullptr,
+                                             C.f32, zs ? C.A32 : nullptr, nullptr));
+        }
+        HIP_CHECK(hipEventRecord(e1, stream));
+        HIP_CHECK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) tot += ms;  // first launch warms up
+      }
+      if (tot < best) { best = tot; bestS = S; }
+    }
+    tuned[l + 1] = bestS;
+    cache[key] = bestS;
+    dirty = true;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (path && dirty) write_cache(path, cache);
+  return STMG_OK;
+}
+
+template hipError_t Solver::restrict_residual<float>(int, bool, int, const float*, const float*, const double*, float*, float*, bool*);
 
 }  // namespace stmg

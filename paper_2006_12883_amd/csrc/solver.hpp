@@ -99,6 +99,8 @@ struct Solver {
 
   int chunk_of(int l) const;        // smoother block length on level l
   int transfer_slabs(int l) const;  // slabs per thread in transfer kernels
+  std::vector<int> tuned;           // autotuned transfer_slabs per level (0: default)
+  int autotune();                   // time candidate shapes, keep the fastest
   // --- building blocks (FP64 or FP32 arithmetic) ---
   template <typename T>
   hipError_t smooth(int l, bool adj, int react, const T* U, const T* f, const double* u0, T* out);

@@ -81,3 +81,27 @@ def test_spacetime_large_mu_reports_divergence():
     U, st = H(prob, coarsen="spacetime").solve(T(u0), check=False)
     assert st["status"] == -5
     assert st["cycles"] < 200
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotuned_shapes_bitwise_identical(prec, tmp_path, monkeypatch):
+    """Autotuned launch shapes change speed only: results are bitwise equal,
+    and the chosen shapes are cached and reused."""
+    print("case autotune", prec, flush=True)
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("STMG_TUNE_CACHE", str(cache))
+    prob = si.problem(2, 128, 3, 64, 1.0, nu=1e-2, lam=1.0)
+    u0 = si.u0_rd2d(prob, 2)
+    rt = 1e-12 if prec == "fp64" else 1e-10
+    U0, s0 = H(prob, precision=prec, rtol=rt).solve(T(u0))
+    ht = H(prob, precision=prec, rtol=rt, autotune=1)
+    U1, s1 = ht.solve(T(u0))
+    assert s0["cycles"] == s1["cycles"]
+    assert torch.equal(U0, U1)
+    assert cache.exists() and cache.read_text().count(":") >= 1
+    shapes = [ht.levels()[l] for l in range(len(ht.levels()))]
+    from paper_2006_12883_amd import binding as B
+    tuned = [B.lib().stmg_tuned_shape(ht.h, l) for l in range(len(shapes) - 1)]
+    assert all(t >= 1 for t in tuned)
+    h2 = H(prob, precision=prec, rtol=rt, autotune=1)  # from the cache
+    assert [B.lib().stmg_tuned_shape(h2.h, l) for l in range(len(shapes) - 1)] == tuned
