@@ -668,10 +668,54 @@ __device__ __forceinline__ void st2(T* __restrict__ p, T a, T b) {
   *reinterpret_cast<typename Vec2<T>::type*>(p) = v;
 }
 
-// Geometry of the 2 x BY block owned by thread t of a plane (periodic).
+// Global accesses through a wave-uniform base address plus a 32-bit
+// per-lane byte offset.  The base is moved to scalar registers with
+// readfirstlane (every lane of the wave holds the same value), so the loads
+// take the scalar-base form: one 32-bit offset register per access pattern
+// instead of a 64-bit address per load, which keeps the unrolled multi-plane
+// stencil kernels at two or more waves per SIMD.  Callers guarantee that the
+// pointer is the same on every active lane and that byte offsets fit in 32 bits
+// (a plane of at most 2^32 bytes).
+typedef const __attribute__((address_space(1))) char* gcptr;
+typedef __attribute__((address_space(1))) char* gptr;
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v >> 32));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+__device__ __forceinline__ gcptr ubase(const void* p) {
+  return (gcptr)uniform_u64(reinterpret_cast<unsigned long long>(p));
+}
+__device__ __forceinline__ gptr ubase_w(void* p) {
+  return (gptr)uniform_u64(reinterpret_cast<unsigned long long>(p));
+}
+template <typename T>
+__device__ __forceinline__ T ldo(gcptr b, unsigned o) {
+  return *(const __attribute__((address_space(1))) T*)(b + o);
+}
+template <typename T>
+__device__ __forceinline__ void ld2o(gcptr b, unsigned o, T& x, T& y) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *(const __attribute__((address_space(1))) v2*)(b + o);
+  x = v.x;
+  y = v.y;
+}
+template <typename T>
+__device__ __forceinline__ void st2o(gptr b, unsigned o, T x, T y) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 v;
+  v.x = x;
+  v.y = y;
+  *(__attribute__((address_space(1))) v2*)(b + o) = v;
+}
+
+// Geometry of the 2 x BY block owned by thread t of a plane (periodic), with
+// the element offsets (inside a plane) of its rows and side points.
 template <int BY>
 struct Blk {
   int x0, y0, xm, xp, ylo, yhi;
+  unsigned orow[BY + 2];  // rows ylo, y0 .. y0 + BY - 1, yhi at column x0
+  unsigned oside[BY][2];  // (y0 + j, xm) and (y0 + j, xp)
   __device__ __forceinline__ Blk(int t, int nx, int ny) {
     const int hx = nx >> 1;
     x0 = (t % hx) * 2;
@@ -680,6 +724,14 @@ struct Blk {
     xp = x0 + 2 < nx ? x0 + 2 : 0;
     ylo = y0 > 0 ? y0 - 1 : ny - 1;
     yhi = y0 + BY < ny ? y0 + BY : 0;
+    orow[0] = static_cast<unsigned>(ylo * nx + x0);
+    orow[BY + 1] = static_cast<unsigned>(yhi * nx + x0);
+#pragma unroll
+    for (int j = 0; j < BY; ++j) {
+      orow[j + 1] = static_cast<unsigned>((y0 + j) * nx + x0);
+      oside[j][0] = static_cast<unsigned>((y0 + j) * nx + xm);
+      oside[j][1] = static_cast<unsigned>((y0 + j) * nx + xp);
+    }
   }
   // plane offset of block point k (k = j * 2 + i)
   __device__ __forceinline__ int q(int k, int nx) const { return (y0 + (k >> 1)) * nx + x0 + (k & 1); }
@@ -690,20 +742,20 @@ template <int M, typename T, int BY, bool TWOD>
 __device__ __forceinline__ void load_blk(const T* __restrict__ U, size_t base, int P, int nx,
                                          const Blk<BY>& b, T cx, T cy, T u[2 * BY][M],
                                          T lap[2 * BY][M]) {
+  constexpr unsigned E = sizeof(T);
 #pragma unroll
   for (int m = 0; m < M; ++m) {
-    const T* Um = U + base + (size_t)m * P;
+    const gcptr Um = ubase(U + base + (size_t)m * P);
     T rw[BY + 2][2];
 #pragma unroll
-    for (int j = 0; j < BY; ++j) ld2(Um + (b.y0 + j) * nx + b.x0, rw[j + 1][0], rw[j + 1][1]);
+    for (int j = 0; j < BY; ++j) ld2o(Um, b.orow[j + 1] * E, rw[j + 1][0], rw[j + 1][1]);
     if (TWOD) {
-      ld2(Um + b.ylo * nx + b.x0, rw[0][0], rw[0][1]);
-      ld2(Um + b.yhi * nx + b.x0, rw[BY + 1][0], rw[BY + 1][1]);
+      ld2o(Um, b.orow[0] * E, rw[0][0], rw[0][1]);
+      ld2o(Um, b.orow[BY + 1] * E, rw[BY + 1][0], rw[BY + 1][1]);
     }
 #pragma unroll
     for (int j = 0; j < BY; ++j) {
-      const int row = (b.y0 + j) * nx;
-      const T l = Um[row + b.xm], r = Um[row + b.xp];
+      const T l = ldo<T>(Um, b.oside[j][0] * E), r = ldo<T>(Um, b.oside[j][1] * E);
       const T c0 = rw[j + 1][0], c1 = rw[j + 1][1];
       T l0 = cx * (l + c1 - c0 - c0);
       T l1 = cx * (c0 + r - c1 - c1);
@@ -724,23 +776,26 @@ template <int M, typename T, int BY>
 __device__ __forceinline__ void load_own(const T* __restrict__ F, size_t base, int P, int nx,
                                          const Blk<BY>& b, T v[2 * BY][M]) {
 #pragma unroll
-  for (int m = 0; m < M; ++m)
+  for (int m = 0; m < M; ++m) {
+    const gcptr Fm = ubase(F + base + (size_t)m * P);
 #pragma unroll
-    for (int j = 0; j < BY; ++j)
-      ld2(F + base + (size_t)m * P + (b.y0 + j) * nx + b.x0, v[2 * j][m], v[2 * j + 1][m]);
+    for (int j = 0; j < BY; ++j) ld2o(Fm, b.orow[j + 1] * sizeof(T), v[2 * j][m], v[2 * j + 1][m]);
+  }
 }
 
 template <int M, typename T, int BY>
 __device__ __forceinline__ void store_own(T* __restrict__ F, size_t base, int P, int nx,
                                           const Blk<BY>& b, const T v[2 * BY][M]) {
 #pragma unroll
-  for (int m = 0; m < M; ++m)
+  for (int m = 0; m < M; ++m) {
+    const gptr Fm = ubase_w(F + base + (size_t)m * P);
 #pragma unroll
-    for (int j = 0; j < BY; ++j)
-      st2(F + base + (size_t)m * P + (b.y0 + j) * nx + b.x0, v[2 * j][m], v[2 * j + 1][m]);
+    for (int j = 0; j < BY; ++j) st2o(Fm, b.orow[j + 1] * sizeof(T), v[2 * j][m], v[2 * j + 1][m]);
+  }
 }
 
-// Coupling value entering the run at slab n0 for every block point.
+// Coupling value entering the run at slab n0 for every block point (nodes
+// with a zero coupling weight are not read).
 template <int M, typename T, int BY>
 __device__ __forceinline__ void run_prev(const Consts<M, T>& c, const SweepPtrs<T>& a, int n0, int P,
                                          int nx, const Blk<BY>& b, T prev[2 * BY]) {
@@ -756,12 +811,18 @@ __device__ __forceinline__ void run_prev(const Consts<M, T>& c, const SweepPtrs<
       }
     }
   } else if (a.U) {
-    T v[2 * BY][M];
-    load_own<M, T, BY>(a.U, (size_t)(n0 - 1) * M * P, P, nx, b, v);
 #pragma unroll
-    for (int k = 0; k < 2 * BY; ++k)
+    for (int m = 0; m < M; ++m) {
+      if (c.cout[m] == T(0)) continue;
+      const gcptr Um = ubase(a.U + (size_t)((n0 - 1) * M + m) * P);
 #pragma unroll
-      for (int j = 0; j < M; ++j) prev[k] += c.cout[j] * v[k][j];
+      for (int j = 0; j < BY; ++j) {
+        T v0, v1;
+        ld2o(Um, b.orow[j + 1] * sizeof(T), v0, v1);
+        prev[2 * j] += c.cout[m] * v0;
+        prev[2 * j + 1] += c.cout[m] * v1;
+      }
+    }
   }
 }
 
@@ -1315,12 +1376,13 @@ __global__ __launch_bounds__(kBlock) void k_prolong_blk(const OpParams p, int nc
   const int n1 = min(n0 + S, p.N);
   const int Pc = ncx * ncy;
   const Blk<BY> b(t, nx, ny);
-  // coarse points feeding the block
-  int c00, c10, c01, c11;
+  // coarse points feeding the block (byte offsets)
+  unsigned c00, c10, c01, c11;
   if (SP) {
     const int X = b.x0 >> 1, Y = TWOD ? (b.y0 >> 1) : 0;
     const int X1 = X + 1 < ncx ? X + 1 : 0, Y1 = TWOD ? (Y + 1 < ncy ? Y + 1 : 0) : 0;
-    c00 = Y * ncx + X; c10 = Y * ncx + X1; c01 = Y1 * ncx + X; c11 = Y1 * ncx + X1;
+    c00 = (Y * ncx + X) * sizeof(T); c10 = (Y * ncx + X1) * sizeof(T);
+    c01 = (Y1 * ncx + X) * sizeof(T); c11 = (Y1 * ncx + X1) * sizeof(T);
   } else {
     c00 = c10 = c01 = c11 = 0;
   }
@@ -1350,13 +1412,13 @@ __global__ __launch_bounds__(kBlock) void k_prolong_blk(const OpParams p, int nc
 #pragma unroll
       for (int k = 0; k < 2 * BY; ++k) e[k] = T(0);
       for (int tt = 0; tt < nt; ++tt) {
-        const T* Ec = ec + (size_t)js[tt] * M * Pc + (size_t)m * Pc;
+        const gcptr Ec = ubase(ec + (size_t)js[tt] * M * Pc + (size_t)m * Pc);
         if (SP) {
-          const T a00 = Ec[c00], a10 = Ec[c10];
+          const T a00 = ldo<T>(Ec, c00), a10 = ldo<T>(Ec, c10);
           e[0] += wt[tt] * a00;
           e[1] += wt[tt] * (T(0.5) * (a00 + a10));
           if (TWOD) {
-            const T a01 = Ec[c01], a11 = Ec[c11];
+            const T a01 = ldo<T>(Ec, c01), a11 = ldo<T>(Ec, c11);
             e[2] += wt[tt] * (T(0.5) * (a00 + a01));
             e[3] += wt[tt] * (T(0.25) * (a00 + a10 + a01 + a11));
           }
@@ -1365,7 +1427,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_blk(const OpParams p, int nc
           T a0, a1;
 #pragma unroll
           for (int j = 0; j < BY; ++j) {
-            ld2(Ec + (b.y0 + j) * nx + b.x0, a0, a1);
+            ld2o(Ec, b.orow[j + 1] * sizeof(T), a0, a1);
             e[2 * j] += wt[tt] * a0;
             e[2 * j + 1] += wt[tt] * a1;
           }
@@ -1399,13 +1461,20 @@ __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const Swe
     const Blk<BY> b(t, nx, ny);
     const T dg = T(2) * c.cx + (TWOD ? T(2) * c.cy : T(0));
     T* __restrict__ out = static_cast<T*>(a.out);
-    // coarse neighbourhood of the block (space coarsening): offsets -1, 0, +1
-    int cxs[3], cys[3];
+    constexpr unsigned E = sizeof(T);
+    // coarse neighbourhood of the block (space coarsening): byte offsets of
+    // the columns and rows -1, 0, +1 around coarse point (x0 / 2, y0 / 2)
+    unsigned ocx[3] = {0, 0, 0}, ocy[3] = {0, 0, 0};
     if (SP) {
       const int X = b.x0 >> 1, Y = TWOD ? (b.y0 >> 1) : 0;
-      cxs[0] = X > 0 ? X - 1 : ncx - 1; cxs[1] = X; cxs[2] = X + 1 < ncx ? X + 1 : 0;
-      if (TWOD) { cys[0] = Y > 0 ? Y - 1 : ncy - 1; cys[1] = Y; cys[2] = Y + 1 < ncy ? Y + 1 : 0; }
-      else { cys[0] = cys[1] = cys[2] = 0; }
+      ocx[0] = (X > 0 ? X - 1 : ncx - 1) * E;
+      ocx[1] = X * E;
+      ocx[2] = (X + 1 < ncx ? X + 1 : 0) * E;
+      if (TWOD) {
+        ocy[0] = (Y > 0 ? Y - 1 : ncy - 1) * ncx * E;
+        ocy[1] = Y * ncx * E;
+        ocy[2] = (Y + 1 < ncy ? Y + 1 : 0) * ncx * E;
+      }
     }
     // Correction at the 4 x (BY + 2) fine positions (dx = -1..2, dy = -1..BY)
     // of node m in fine slab n; only the own rows' dx = -1..2 and the halo
@@ -1426,14 +1495,14 @@ __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const Swe
 #pragma unroll
         for (int i = 0; i < 4; ++i) cr[j][i] = T(0);
       for (int tt = 0; tt < nt; ++tt) {
-        const T* Ec = ec + (size_t)js[tt] * M * Pc + (size_t)m * Pc;
+        const gcptr Ec = ubase(ec + (size_t)js[tt] * M * Pc + (size_t)m * Pc);
         const T w = wt[tt];
         if (SP) {
           T cv[3][3];
 #pragma unroll
           for (int yy = 0; yy < (TWOD ? 3 : 1); ++yy)
 #pragma unroll
-            for (int xx = 0; xx < 3; ++xx) cv[yy][xx] = Ec[cys[TWOD ? yy : 0] * ncx + cxs[xx]];
+            for (int xx = 0; xx < 3; ++xx) cv[yy][xx] = ldo<T>(Ec, ocy[yy] + ocx[xx]);
           // x interpolation of each coarse row at fine dx = -1, 0, 1, 2
           T rx[3][4];
 #pragma unroll
@@ -1459,14 +1528,13 @@ __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const Swe
 #pragma unroll
           for (int j = 0; j < BY + 2; ++j) {
             if (!TWOD && j != 1) continue;
-            const int yy = j == 0 ? b.ylo : (j == BY + 1 ? b.yhi : b.y0 + j - 1);
             T v0, v1;
-            ld2(Ec + yy * nx + b.x0, v0, v1);
+            ld2o(Ec, b.orow[j] * E, v0, v1);
             cr[j][1] += w * v0;
             cr[j][2] += w * v1;
             if (j >= 1 && j <= BY) {
-              cr[j][0] += w * Ec[yy * nx + b.xm];
-              cr[j][3] += w * Ec[yy * nx + b.xp];
+              cr[j][0] += w * ldo<T>(Ec, b.oside[j - 1][0] * E);
+              cr[j][3] += w * ldo<T>(Ec, b.oside[j - 1][1] * E);
             }
           }
         }
@@ -1486,15 +1554,16 @@ __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const Swe
         }
       }
     } else {
-      const size_t pb = (size_t)(n0 - 1) * M * P;
 #pragma unroll
       for (int m = 0; m < M; ++m) {
+        if (c.cout[m] == T(0)) continue;
         T cr[BY + 2][4];
         corr(n0 - 1, m, cr);
+        const gcptr Um = a.U ? ubase(a.U + (size_t)((n0 - 1) * M + m) * P) : nullptr;
 #pragma unroll
         for (int j = 0; j < BY; ++j) {
           T v0 = T(0), v1 = T(0);
-          if (a.U) ld2(a.U + pb + (size_t)m * P + (b.y0 + j) * nx + b.x0, v0, v1);
+          if (Um) ld2o(Um, b.orow[j + 1] * E, v0, v1);
           prev[2 * j] += c.cout[m] * (v0 + cr[j + 1][1]);
           prev[2 * j + 1] += c.cout[m] * (v1 + cr[j + 1][2]);
         }
@@ -1507,22 +1576,20 @@ __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const Swe
       for (int m = 0; m < M; ++m) {
         T cr[BY + 2][4];
         corr(n, m, cr);
-        const T* Um = a.U ? a.U + base + (size_t)m * P : nullptr;
+        const gcptr Um = a.U ? ubase(a.U + base + (size_t)m * P) : nullptr;
         T rw[BY + 2][2];
 #pragma unroll
         for (int j = 0; j < BY + 2; ++j) {
           if (!TWOD && j != 1) continue;
-          const int yy = j == 0 ? b.ylo : (j == BY + 1 ? b.yhi : b.y0 + j - 1);
           T v0 = T(0), v1 = T(0);
-          if (Um) ld2(Um + yy * nx + b.x0, v0, v1);
+          if (Um) ld2o(Um, b.orow[j] * E, v0, v1);
           rw[j][0] = v0 + cr[j][1];
           rw[j][1] = v1 + cr[j][2];
         }
 #pragma unroll
         for (int j = 0; j < BY; ++j) {
-          const int row = (b.y0 + j) * nx;
-          const T l = (Um ? Um[row + b.xm] : T(0)) + cr[j + 1][0];
-          const T r = (Um ? Um[row + b.xp] : T(0)) + cr[j + 1][3];
+          const T l = (Um ? ldo<T>(Um, b.oside[j][0] * E) : T(0)) + cr[j + 1][0];
+          const T r = (Um ? ldo<T>(Um, b.oside[j][1] * E) : T(0)) + cr[j + 1][3];
           const T c0 = rw[j + 1][0], c1 = rw[j + 1][1];
           T l0 = c.cx * (l + c1 - c0 - c0);
           T l1 = c.cx * (c0 + r - c1 - c1);

@@ -471,6 +471,15 @@ hipError_t Solver::vcycle(int l, bool adj, int react, T* cur, T* oth, const T* f
   bool smoothed = false;
   HIP_TRY(restrict_residual<T>(l, adj, react, zero ? nullptr : cur, f, u0, cf,
                                want ? ca : nullptr, &smoothed));
+  if (l == 0 && gate0) {
+    // Nothing written so far touches the caller's iterate.
+    bool stop = false;
+    HIP_TRY(gate0(&stop));
+    if (stop) {
+      *res = nullptr;
+      return hipSuccess;
+    }
+  }
   T* ec = nullptr;
   HIP_TRY(vcycle<T>(l + 1, adj, react, ca, cb, cf, nullptr, !smoothed, &ec, smoothed ? 1 : 0));
   // Ascend: prolongation fused with the first post-smoothing sweep where the
@@ -547,57 +556,78 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
   // (the sweep writes the ping-pong partner), so the stop test costs no extra
   // pass over the data.
   const bool fused = !mixed && opt.nu_pre >= 1;
-  auto norm_now = [&](double* rel) -> int {
-    double rn2 = 0.0;
+  HIP_CHECK(hnorm.init());
+  // Queues ||f - A U||^2 of the current iterate and its copy to the host.
+  auto launch_norm = [&]() -> hipError_t {
     if (fused) {
       SweepPtrs<double> a{U, f, u0, L0.coef64, L0.B64, part};
-      HIP_CHECK(launch_smooth<double>(op0, react, a, chunk_of(0), stream));
-      HIP_CHECK(launch_sum_partials(part, smooth_blocks(op0, chunk_of(0)), scal, stream));
+      HIP_TRY(launch_smooth<double>(op0, react, a, chunk_of(0), stream));
+      HIP_TRY(launch_sum_partials(part, smooth_blocks(op0, chunk_of(0)), scal, stream));
     } else if (!mixed) {
-      HIP_CHECK(residual64<double>(adj, react, U, f, u0, nullptr, scal));
+      HIP_TRY(residual64<double>(adj, react, U, f, u0, nullptr, scal));
     } else {
-      HIP_CHECK(residual64<float>(adj, react, U, f, u0, L0.f32, scal));
+      HIP_TRY(residual64<float>(adj, react, U, f, u0, L0.f32, scal));
     }
-    int rc = read_scalar(scal, &rn2);
-    if (rc) return rc;
-    *rel = norm_b > 0.0 ? std::sqrt(rn2) / norm_b : std::sqrt(rn2);
-    return STMG_OK;
+    HIP_TRY(hipMemcpyAsync(hnorm.h, scal, sizeof(double), hipMemcpyDeviceToHost, stream));
+    return hipEventRecord(hnorm.ev, stream);
   };
-  double rel = 0.0;
-  int rc = norm_now(&rel);
-  if (rc) return rc;
-  const double rel0 = rel;
-  double prev = rel;
+  double rel = 0.0, rel0 = 0.0, prev = 0.0;
+  bool first = true;
   int incr = 0;
   int c = 0;
   int status = STMG_OK;
-  for (;;) {
-    if (!std::isfinite(rel)) { status = STMG_ENAN; break; }
-    if (rel <= rtol) break;
+  // Waits for the queued norm and applies the stop tests to U_c.
+  auto decide = [&](bool* stop) -> hipError_t {
+    HIP_TRY(hipEventSynchronize(hnorm.ev));
+    const double rn2 = *hnorm.h;
+    rel = norm_b > 0.0 ? std::sqrt(rn2) / norm_b : std::sqrt(rn2);
+    if (first) { rel0 = rel; prev = rel; first = false; }
+    *stop = true;
+    if (!std::isfinite(rel)) { status = STMG_ENAN; return hipSuccess; }
+    if (rel <= rtol) return hipSuccess;
     if (c > 0) {
-      if (rel > 1e3 * (rel0 > 0 ? rel0 : 1.0)) { status = STMG_EDIVERGED; break; }
+      if (rel > 1e3 * (rel0 > 0 ? rel0 : 1.0)) { status = STMG_EDIVERGED; return hipSuccess; }
       incr = rel > prev ? incr + 1 : 0;
-      if (incr >= 5) { status = STMG_EDIVERGED; break; }
+      if (incr >= 5) { status = STMG_EDIVERGED; return hipSuccess; }
     }
     prev = rel;
-    if (c >= opt.max_cycles) { status = STMG_ENOTCONV; break; }
+    if (c >= opt.max_cycles) { status = STMG_ENOTCONV; return hipSuccess; }
+    *stop = false;
+    return hipSuccess;
+  };
+  struct GateScope {
+    Solver* s;
+    ~GateScope() { s->gate0 = nullptr; }
+  } scope{this};
+  // With one level there is no restriction to overlap: decide up front.
+  const bool gated = lv.size() > 1;
+  if (gated) gate0 = decide;
+  HIP_CHECK(launch_norm());
+  for (;;) {
+    if (!gated) {
+      bool stop = false;
+      HIP_CHECK(decide(&stop));
+      if (stop) break;
+    }
     if (fused) {
       // the first pre-smoothing sweep already sits in L0.B64
       double* res = nullptr;
       HIP_CHECK(vcycle<double>(0, adj, react, L0.B64, U, f, u0, false, &res, 1));
+      if (!res) break;
       if (res != U) HIP_CHECK(hipMemcpyAsync(U, res, L0.n * sizeof(double), hipMemcpyDeviceToDevice, stream));
     } else if (!mixed) {
       double* res = nullptr;
       HIP_CHECK(vcycle<double>(0, adj, react, U, L0.B64, f, u0, false, &res, 0));
+      if (!res) break;
       if (res != U) HIP_CHECK(hipMemcpyAsync(U, res, L0.n * sizeof(double), hipMemcpyDeviceToDevice, stream));
     } else {
       float* res = nullptr;
       HIP_CHECK(vcycle<float>(0, adj, react, L0.A32, L0.B32, L0.f32, nullptr, true, &res, 0));
+      if (!res) break;
       HIP_CHECK(launch_update<float>(L0.n, U, res, nullptr, stream));
     }
     ++c;
-    rc = norm_now(&rel);
-    if (rc) return rc;
+    HIP_CHECK(launch_norm());
   }
   *cycles += c;
   *rel_out = rel;

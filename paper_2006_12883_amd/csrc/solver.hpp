@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -41,6 +42,31 @@ struct Plan {
   }
 };
 
+// Pinned host slot and event for reading a device scalar without draining
+// the stream (created on first use, on the device current at that time).
+struct HostScalar {
+  double* h = nullptr;
+  hipEvent_t ev = nullptr;
+  HostScalar() = default;
+  HostScalar(const HostScalar&) = delete;
+  HostScalar& operator=(const HostScalar&) = delete;
+  ~HostScalar() {
+    if (ev) (void)hipEventDestroy(ev);
+    if (h) (void)hipHostFree(h);
+  }
+  hipError_t init() {
+    if (!h) {
+      hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(double), hipHostMallocDefault);
+      if (e != hipSuccess) { h = nullptr; return e; }
+    }
+    if (!ev) {
+      hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) { ev = nullptr; return e; }
+    }
+    return hipSuccess;
+  }
+};
+
 struct Solver {
   stmg_problem prob{};
   stmg_options opt{};
@@ -62,6 +88,13 @@ struct Solver {
   double* lw = nullptr;       // M weights l(0) on the device (gradient of u0)
   // statistics of the last solve
   stmg_stats last{};
+  // Stop test of the linear solve: the residual norm of the incoming iterate
+  // is copied to pinned memory behind an event; the host waits on that event
+  // only after the cycle's level-0 restriction is queued (gate0 is called
+  // there by vcycle and may end the cycle, leaving the iterate untouched), so
+  // the device never idles while the host decides.
+  HostScalar hnorm;
+  std::function<hipError_t(bool*)> gate0;
 
   // Time windows (adjoint checkpointing).  When the options' memory budget
   // cannot hold the trajectory, the handle drives a sub-solver for W slabs
