@@ -111,6 +111,8 @@ typedef struct {
                          bitwise identical for every shape); choices are
                          cached in the JSON file named by $STMG_TUNE_CACHE.
                          0 (default): fixed shapes                            */
+  int32_t inner_cycles; /* mixed precision: FP32 V-cycles on each correction
+                         equation per FP64 refinement step, 2                 */
 } stmg_options;
 
 typedef struct {

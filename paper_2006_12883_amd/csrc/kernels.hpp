@@ -58,6 +58,17 @@ template <typename T, typename TO>
 hipError_t launch_residual(const OpParams& p, int react, const SweepPtrs<T>& a,
                            int slabs_per_block, int* nparts, hipStream_t s);
 
+// One iterative-refinement step of the mixed-precision solve fused into one
+// sweep (register-blocked layouts only, else hipErrorNotSupported): a.out =
+// U' = a.U + e (e may be null), r = a.f + (u0 coupling) - A U' in FP64 with
+// per-block partial sums of r^2 in a.part (*nparts blocks), r32 = (float) r,
+// and with e1 set the first FP32 smoothing sweep from zero for A e = r32 over
+// chunks of `chunk` slabs.  react: REACT_CONST or REACT_COEF (coef32 for the
+// FP32 sweep).
+hipError_t launch_refine(const OpParams& p, int react, const SweepPtrs<double>& a, const float* e,
+                         float* r32, float* e1, const float* coef32, int chunk, int* nparts,
+                         hipStream_t s);
+
 // f_c = R (f - A U) on the fine level described by p; the coarse level has
 // ncx x ncy points and Nc slabs; space/time select the coarsening.  If uc is
 // given (with the coarse level's operator pc, coefficient coefc and smoother

@@ -845,6 +845,59 @@ __device__ __forceinline__ void resid_vals(const Consts<M, T>& c, const T u[M], 
   }
 }
 
+// One point's smoothing update: d = D^{-1} r (block solve with the point's
+// reaction coefficient for REACT_COEF), returning cout . d.
+template <int M, typename T, int REACT>
+__device__ __forceinline__ T point_correction(const Consts<M, T>& c, T dg, const T cv[M], const T r[M],
+                                              T d[M]) {
+  if (REACT == REACT_COEF) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) d[i] = r[i];
+    point_block_solve<M, T>(c, dg, cv, d);
+  } else {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      T sm = T(0);
+#pragma unroll
+      for (int j = 0; j < M; ++j) sm += c.Bi[i][j] * r[j];
+      d[i] = sm;
+    }
+  }
+  T nd = T(0);
+#pragma unroll
+  for (int i = 0; i < M; ++i) nd += c.cout[i] * d[i];
+  return nd;
+}
+
+// resid_vals in two steps for a coupling value known only later:
+// au = K u + db (react - lap), then r = f - (au - cin prev).
+template <int M, typename T, int REACT>
+__device__ __forceinline__ void resid_partial(const Consts<M, T>& c, const T u[M], const T lap[M],
+                                              const T cv[M], T au[M]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T s = T(0);
+#pragma unroll
+    for (int j = 0; j < M; ++j) s += c.K[i][j] * u[j];
+    T react;
+    if (REACT == REACT_CONST) react = c.lam * u[i];
+    else if (REACT == REACT_COEF) react = cv[i] * u[i];
+    else react = c.gamma * (u[i] * u[i] * u[i] - u[i]);
+    s += c.db[i] * (react - lap[i]);
+    au[i] = s;
+  }
+}
+template <int M, typename T>
+__device__ __forceinline__ void resid_finish(const Consts<M, T>& c, const T au[M], const T fv[M], T prev,
+                                             T r[M]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T s = au[i];
+    s -= c.cin[i] * prev;
+    r[i] = fv[i] - s;
+  }
+}
+
 // Smoother (same mathematics as k_smooth) on 2 x BY blocks.
 template <int M, typename T, int REACT, int BY, bool TWOD>
 __device__ __forceinline__ void smooth_blk_body(const OpParams& p, const SweepPtrs<T>& a, int S,
@@ -999,6 +1052,178 @@ __global__ __launch_bounds__(kBlock) void k_residual_blk(const OpParams p, const
   residual_blk_body<M, T, TO, REACT, BY, TWOD>(p, a, S, lb % tiles, (lb / tiles) * S, lb);
 }
 
+// Values and scaled Laplacians of U' = U + e on the block's points (U in
+// FP64, the correction e in FP32, e may be null), all M nodes.  U' is formed
+// with the same FP64 additions as a stored update would use.
+template <int M, int BY, bool TWOD>
+__device__ __forceinline__ void load_blk_sum(const double* __restrict__ U, const float* __restrict__ e,
+                                             size_t base, int P, const Blk<BY>& b, double cx, double cy,
+                                             double u[2 * BY][M], double lap[2 * BY][M]) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const gcptr Um = ubase(U + base + (size_t)m * P);
+    const gcptr Em = e ? ubase(e + base + (size_t)m * P) : nullptr;
+    double rw[BY + 2][2];
+#pragma unroll
+    for (int j = 0; j < BY + 2; ++j) {
+      if (!TWOD && j != 1) continue;
+      ld2o(Um, b.orow[j] * 8u, rw[j][0], rw[j][1]);
+      if (Em) {
+        float e0, e1;
+        ld2o(Em, b.orow[j] * 4u, e0, e1);
+        rw[j][0] = rw[j][0] + (double)e0;
+        rw[j][1] = rw[j][1] + (double)e1;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < BY; ++j) {
+      double l = ldo<double>(Um, b.oside[j][0] * 8u), r = ldo<double>(Um, b.oside[j][1] * 8u);
+      if (Em) {
+        l = l + (double)ldo<float>(Em, b.oside[j][0] * 4u);
+        r = r + (double)ldo<float>(Em, b.oside[j][1] * 4u);
+      }
+      const double c0 = rw[j + 1][0], c1 = rw[j + 1][1];
+      double l0 = cx * (l + c1 - c0 - c0);
+      double l1 = cx * (c0 + r - c1 - c1);
+      if (TWOD) {
+        l0 += cy * (rw[j][0] + rw[j + 2][0] - c0 - c0);
+        l1 += cy * (rw[j][1] + rw[j + 2][1] - c1 - c1);
+      }
+      u[2 * j][m] = c0;
+      u[2 * j + 1][m] = c1;
+      lap[2 * j][m] = l0;
+      lap[2 * j + 1][m] = l1;
+    }
+  }
+}
+
+// One iterative-refinement step of the mixed-precision solve, fused into a
+// single sweep over the finest level (2 x BY blocks, runs of S slabs = one
+// smoother chunk):
+//   U' = U + e                 (FP64 iterate plus FP32 correction, e may be null)
+//   r  = f - A U'              (FP64, per-block partial sums of r^2 in a.part)
+//   a.out <- U' (FP64), r32 <- (float) r  (the next correction equation's
+//   right-hand side), and with e1 set that equation's first smoothing sweep
+//   from a zero iterate, in FP32: e1 = omega D^{-1} (r32 + cin (x) cout . d_prev).
+// The results equal those of the separate update, FP64 residual and FP32
+// smoothing kernels, operation for operation.
+template <int M, int REACT, int BY, bool TWOD>
+__device__ __forceinline__ void refine_blk_body(const OpParams& p, const SweepPtrs<double>& a,
+                                                const float* __restrict__ e, float* __restrict__ r32,
+                                                float* __restrict__ e1, const float* __restrict__ coef32,
+                                                int S, int tile, int n0, int pslot) {
+  constexpr int NP = 2 * BY;
+  const int nx = p.nx, P = nx * p.ny;
+  const int t = tile * kBlock + threadIdx.x;
+  double ssq = 0.0;
+  if (t < (nx >> 1) * (p.ny / BY) && n0 < p.N) {
+    const int n1 = min(n0 + S, p.N);
+    const Consts<M, double> c(p);
+    const Blk<BY> b(t, nx, p.ny);
+    double prev[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) prev[k] = 0.0;
+    if (n0 == 0) {
+      if (a.u0) {
+#pragma unroll
+        for (int j = 0; j < BY; ++j) {
+          const double* q = a.u0 + (b.y0 + j) * nx + b.x0;
+          prev[2 * j] = q[0];
+          prev[2 * j + 1] = q[1];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        if (c.cout[m] == 0.0) continue;
+        const size_t off = (size_t)((n0 - 1) * M + m) * P;
+        const gcptr Um = ubase(a.U + off);
+        const gcptr Em = e ? ubase(e + off) : nullptr;
+#pragma unroll
+        for (int j = 0; j < BY; ++j) {
+          double v0, v1;
+          ld2o(Um, b.orow[j + 1] * 8u, v0, v1);
+          if (Em) {
+            float e0, e1v;
+            ld2o(Em, b.orow[j + 1] * 4u, e0, e1v);
+            v0 = v0 + (double)e0;
+            v1 = v1 + (double)e1v;
+          }
+          prev[2 * j] += c.cout[m] * v0;
+          prev[2 * j + 1] += c.cout[m] * v1;
+        }
+      }
+    }
+    float dprev[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) dprev[k] = 0.0f;
+    for (int n = n0; n < n1; ++n) {
+      const size_t base = (size_t)n * M * P;
+      double u[NP][M], lap[NP][M], fv[NP][M], cv[NP][M];
+      float rr[NP][M];
+      load_blk_sum<M, BY, TWOD>(a.U, e, base, P, b, c.cx, c.cy, u, lap);
+      if (a.f) {
+        load_own<M, double, BY>(a.f, base, P, nx, b, fv);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) fv[k][m] = 0.0;
+      }
+      if (REACT == REACT_COEF) load_own<M, double, BY>(a.coef, base, P, nx, b, cv);
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        double r[M];
+        resid_vals<M, double, REACT>(c, u[k], lap[k], fv[k], cv[k], prev[k], r);
+        double np = 0.0;
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          ssq += r[i] * r[i];
+          rr[k][i] = (float)r[i];
+          np += c.cout[i] * u[k][i];
+        }
+        prev[k] = np;
+      }
+      store_own<M, double, BY>(static_cast<double*>(a.out), base, P, nx, b, u);
+      store_own<M, float, BY>(r32, base, P, nx, b, rr);
+      if (e1) {
+        const Consts<M, float> c32(p);
+        const float dg = 2.0f * c32.cx + (TWOD ? 2.0f * c32.cy : 0.0f);
+        float cv32[NP][M], o[NP][M];
+        if (REACT == REACT_COEF) load_own<M, float, BY>(coef32, base, P, nx, b, cv32);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          float r[M], d[M];
+#pragma unroll
+          for (int i = 0; i < M; ++i) r[i] = rr[k][i];
+          if (n > n0) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) r[i] += c32.cin[i] * dprev[k];
+          }
+          dprev[k] = point_correction<M, float, REACT>(c32, dg, cv32[k], r, d);
+#pragma unroll
+          for (int i = 0; i < M; ++i) o[k][i] = c32.omega * d[i];
+        }
+        store_own<M, float, BY>(e1, base, P, nx, b, o);
+      }
+    }
+  }
+  if (a.part) {
+    const double tt = block_sum(ssq);
+    if (threadIdx.x == 0) a.part[pslot] = tt;
+  }
+}
+
+template <int M, int REACT, int BY, bool TWOD>
+__global__ __launch_bounds__(kBlock) void k_refine_blk(const OpParams p, const SweepPtrs<double> a,
+                                                       const float* __restrict__ e, float* __restrict__ r32,
+                                                       float* __restrict__ e1,
+                                                       const float* __restrict__ coef32, int S, int tiles,
+                                                       int nblocks) {
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  refine_blk_body<M, REACT, BY, TWOD>(p, a, e, r32, e1, coef32, S, lb % tiles, (lb / tiles) * S, lb);
+}
+
 // Fused residual + restriction on 2 x BY blocks with an LDS tile.  A
 // workgroup owns TCX x TCY coarse points; its 256 threads own the 2 x BY
 // fine blocks whose lower-left point is fine (2X, 2Y), so the fine tile is
@@ -1010,7 +1235,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_blk(const OpParams p, const
 // With ZS the kernel also does the coarse level's first smoothing sweep from
 // a zero iterate (U_c = omega D_c^{-1} f_c along the coarse chunks of cs
 // slabs, which the run [J0, J1) contains whole) and writes it to uc.
-template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY, bool ZS>
+template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY, bool ZS, bool HF = true>
 __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const SweepPtrs<T>& a, int ncx,
                                                   int ncy, int Nc, T* __restrict__ fc, int S,
                                                   int tiles_x, int tile, int J0, const OpParams& pc,
@@ -1098,7 +1323,7 @@ __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const Sweep
 #pragma unroll
           for (int m = 0; m < M; ++m) u[k][m] = lap[k][m] = T(0);
       }
-      if (a.f) {
+      if (HF && a.f) {
         load_own<M, T, BY>(a.f, base, P, nx, b, fv);
       } else {
 #pragma unroll
@@ -1129,7 +1354,7 @@ __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const Sweep
 #pragma unroll
         for (int m = 0; m < M; ++m) u[m] = lap[m] = T(0);
       }
-      point_residual<M, T, REACT>(c, u, lap, a.coef, a.f, base, P, hq, hprev, r);
+      point_residual<M, T, REACT>(c, u, lap, a.coef, HF ? a.f : nullptr, base, P, hq, hprev, r);
       T np = T(0);
 #pragma unroll
       for (int i = 0; i < M; ++i) {
@@ -1214,7 +1439,8 @@ __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const Sweep
   }
 }
 
-template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY, bool ZS>
+// HF: the right-hand side pointer may be non-null (false: f = 0 known at compile time).
+template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY, bool ZS, bool HF>
 __global__ __launch_bounds__(kBlock) void k_restrict_blk(const OpParams p, const SweepPtrs<T> a,
                                                          int ncx, int ncy, int Nc,
                                                          T* __restrict__ fc, int S, int tiles_x,
@@ -1225,7 +1451,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_blk(const OpParams p, const
   constexpr int FH = TWOD ? 2 * TCY + 1 : 1;
   __shared__ T rs[M * FH * FW];
   const int lb = xcd_remap(blockIdx.x, nblocks);
-  restrict_blk_body<M, T, REACT, TM, TWOD, TCX, TCY, ZS>(p, a, ncx, ncy, Nc, fc, S, tiles_x, lb % tiles,
+  restrict_blk_body<M, T, REACT, TM, TWOD, TCX, TCY, ZS, HF>(p, a, ncx, ncy, Nc, fc, S, tiles_x, lb % tiles,
                                                          (lb / tiles) * S, pc, uc, coefc, cs, rs);
 }
 
@@ -1358,6 +1584,198 @@ __global__ __launch_bounds__(kBlock) void k_restrict_t_blk(const OpParams p, con
                                              coefc, cs);
 }
 
+// Slab-parallel form of restrict_t_body for small levels (latency-bound): a
+// workgroup covers SL consecutive coarse slabs (one coarse smoother chunk, SL
+// a power of two with kBlock / SL a multiple of the wave size) of
+// kBlock / SL blocks.  The thread of coarse slab J forms the fine residuals of
+// slabs 2J and 2J+1, the last slab row also of 2J+2; the coupling value of
+// slab 2J-1 and the residual of slab 2J+2 come from the neighbouring slab row
+// through LDS.  With ZS one thread per block then runs the coarse zero-guess
+// sweep along the chunk.  Arithmetic as in restrict_t_body, operation for
+// operation.  LDS: kBlock * 2BY * (M + 1) values of T, plus kBlock * 2BY * M
+// for REACT_COEF.
+template <int M, typename T, int REACT, int BY, bool TWOD, bool ZS>
+__device__ __forceinline__ void restrict_t_sp_body(const OpParams& p, const SweepPtrs<T>& a, int Nc,
+                                                   T* __restrict__ fc, int SL, int tile, int J0,
+                                                   const OpParams& pc, T* __restrict__ uc,
+                                                   const T* __restrict__ coefc, int cs, T* lds) {
+  constexpr int NP = 2 * BY;
+  const int NB = kBlock / SL;
+  const int tid = threadIdx.x;
+  const int sl = tid / NB, pb = tid - sl * NB;
+  const int nx = p.nx, P = nx * p.ny;
+  const int t = tile * NB + pb;
+  const int J = J0 + sl;
+  const bool blk_ok = t < (nx >> 1) * (p.ny / BY);
+  const bool act = blk_ok && J < Nc;
+  T (*sR)[NP][M] = reinterpret_cast<T (*)[NP][M]>(lds);
+  T (*sP)[NP] = reinterpret_cast<T (*)[NP]>(lds + kBlock * NP * M);
+  T (*sC)[NP][M] = reinterpret_cast<T (*)[NP][M]>(lds + kBlock * NP * (M + 1));
+  const Consts<M, T> c(p);
+  const Blk<BY> b(blk_ok ? t : 0, nx, p.ny);
+  const int n = 2 * J;
+  const bool last = J == Nc - 1;                     // no fine slab 2J+2
+  const bool third = act && !last && sl == SL - 1;   // slab 2J+2 formed here
+  T au0[NP][M], f0[NP][M], r1[NP][M], r2[NP][M], prev[NP];
+  if (act) {
+    T np0[NP];
+    {
+      T u[NP][M], lap[NP][M], cv[NP][M];
+      const size_t base = (size_t)n * M * P;
+      if (a.U) {
+        load_blk<M, T, BY, TWOD>(a.U, base, P, nx, b, c.cx, c.cy, u, lap);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) u[k][m] = lap[k][m] = T(0);
+      }
+      if (a.f) {
+        load_own<M, T, BY>(a.f, base, P, nx, b, f0);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) f0[k][m] = T(0);
+      }
+      if (REACT == REACT_COEF) load_own<M, T, BY>(a.coef, base, P, nx, b, cv);
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        resid_partial<M, T, REACT>(c, u[k], lap[k], cv[k], au0[k]);
+        T np = T(0);
+#pragma unroll
+        for (int i = 0; i < M; ++i) np += c.cout[i] * u[k][i];
+        np0[k] = np;
+      }
+    }
+    // fine slabs 2J+1 and (last row) 2J+2, whose couplings are local
+    const int nslab = third ? 2 : 1;
+    for (int e = 0; e < nslab; ++e) {
+      const size_t base = (size_t)(n + 1 + e) * M * P;
+      T u[NP][M], lap[NP][M], fv[NP][M], cv[NP][M];
+      if (a.U) {
+        load_blk<M, T, BY, TWOD>(a.U, base, P, nx, b, c.cx, c.cy, u, lap);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) u[k][m] = lap[k][m] = T(0);
+      }
+      if (a.f) {
+        load_own<M, T, BY>(a.f, base, P, nx, b, fv);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) fv[k][m] = T(0);
+      }
+      if (REACT == REACT_COEF) load_own<M, T, BY>(a.coef, base, P, nx, b, cv);
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        T np = T(0);
+#pragma unroll
+        for (int i = 0; i < M; ++i) np += c.cout[i] * u[k][i];
+        if (e == 0) {
+          resid_vals<M, T, REACT>(c, u[k], lap[k], fv[k], cv[k], np0[k], r1[k]);
+          np0[k] = np;  // now the coupling value of slab 2J+1
+        } else {
+          resid_vals<M, T, REACT>(c, u[k], lap[k], fv[k], cv[k], np0[k], r2[k]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) sP[tid][k] = np0[k];
+    if (sl == 0) run_prev<M, T, BY>(c, a, n, P, nx, b, prev);
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      if (sl > 0) prev[k] = sP[tid - NB][k];
+      T r0[M];
+      resid_finish<M, T>(c, au0[k], f0[k], prev[k], r0);
+#pragma unroll
+      for (int i = 0; i < M; ++i) sR[tid][k][i] = r0[i];
+    }
+  }
+  __syncthreads();
+  T v[NP][M];
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        T acc = T(0.5) * sR[tid][k][i];
+        acc += r1[k][i];
+        if (!last) acc = acc + T(0.5) * (third ? r2[k][i] : sR[tid + NB][k][i]);
+        v[k][i] = acc;
+      }
+    store_own<M, T, BY>(fc, (size_t)J * M * P, P, nx, b, v);
+  }
+  if (ZS) {
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int i = 0; i < M; ++i) sR[tid][k][i] = v[k][i];
+      if (REACT == REACT_COEF) {
+        T cvv[NP][M];
+        load_own<M, T, BY>(coefc, (size_t)J * M * P, P, nx, b, cvv);
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+          for (int i = 0; i < M; ++i) sC[tid][k][i] = cvv[k][i];
+      }
+    }
+    __syncthreads();
+    const Consts<M, T> kc(pc);
+    if (sl == 0 && blk_ok) {
+      const T dgc = T(2) * kc.cx + (TWOD ? T(2) * kc.cy : T(0));
+      T zd[NP];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) zd[k] = T(0);
+      for (int ss = 0; ss < SL && J0 + ss < Nc; ++ss) {
+        const int q = ss * NB + pb;
+        const bool cpl = ((J0 + ss) % cs) != 0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          T r[M], d[M], cq[M];
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            r[i] = sR[q][k][i] + (cpl ? kc.cin[i] * zd[k] : T(0));
+            cq[i] = REACT == REACT_COEF ? sC[q][k][i] : T(0);
+          }
+          zd[k] = point_correction<M, T, REACT>(kc, dgc, cq, r, d);
+#pragma unroll
+          for (int i = 0; i < M; ++i) sR[q][k][i] = d[i];
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+      T o[NP][M];
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int i = 0; i < M; ++i) o[k][i] = kc.omega * sR[tid][k][i];
+      store_own<M, T, BY>(uc, (size_t)J * M * P, P, nx, b, o);
+    }
+  }
+}
+
+template <int M, typename T, int REACT, int BY, bool TWOD, bool ZS>
+__global__ __launch_bounds__(kBlock) void k_restrict_t_sp(const OpParams p, const SweepPtrs<T> a, int Nc,
+                                                          T* __restrict__ fc, int SL, int tiles,
+                                                          int nblocks, const OpParams pc,
+                                                          T* __restrict__ uc,
+                                                          const T* __restrict__ coefc, int cs) {
+  extern __shared__ __align__(16) unsigned char smem_rt[];
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  restrict_t_sp_body<M, T, REACT, BY, TWOD, ZS>(p, a, Nc, fc, SL, lb % tiles, (lb / tiles) * SL, pc, uc,
+                                                coefc, cs, reinterpret_cast<T*>(smem_rt));
+}
+
 // Prolongation + correction on 2 x BY fine blocks (space coarsening: the
 // block of coarse point (X, Y) is fine (2X .. 2X+1) x (2Y .. 2Y+1); time
 // interpolation as in k_prolong).
@@ -1440,12 +1858,171 @@ __global__ __launch_bounds__(kBlock) void k_prolong_blk(const OpParams p, int nc
   }
 }
 
+// Coarse neighbourhood of block b for the space prolongation: byte offsets of
+// the coarse columns and rows -1, 0, +1 around coarse point (x0 / 2, y0 / 2).
+template <typename T, bool SP, bool TWOD, int BY>
+struct CoarseNbr {
+  unsigned ocx[3] = {0, 0, 0}, ocy[3] = {0, 0, 0};
+  __device__ __forceinline__ CoarseNbr(const Blk<BY>& b, int ncx, int ncy) {
+    constexpr unsigned E = sizeof(T);
+    if (SP) {
+      const int X = b.x0 >> 1, Y = TWOD ? (b.y0 >> 1) : 0;
+      ocx[0] = (X > 0 ? X - 1 : ncx - 1) * E;
+      ocx[1] = X * E;
+      ocx[2] = (X + 1 < ncx ? X + 1 : 0) * E;
+      if (TWOD) {
+        ocy[0] = (Y > 0 ? Y - 1 : ncy - 1) * ncx * E;
+        ocy[1] = Y * ncx * E;
+        ocy[2] = (Y + 1 < ncy ? Y + 1 : 0) * ncx * E;
+      }
+    }
+  }
+};
+
+// Coarse correction interpolated to the 4 x (BY + 2) fine positions of
+// block b (dx = -1..2, dy = -1..BY) for node m of fine slab n; only the own
+// rows' dx = -1..2 and the halo rows' dx = 0..1 are used.  Space
+// interpolation is linear per dimension (fine 2X = coarse X), time
+// interpolation linear in slab end points (coarse slab -1 is zero).
+template <int M, typename T, bool SP, bool TM, int BY, bool TWOD>
+__device__ __forceinline__ void corr_blk(const T* __restrict__ ec, int n, int m, int Pc,
+                                         const Blk<BY>& b, const CoarseNbr<T, SP, TWOD, BY>& cn,
+                                         T cr[BY + 2][4]) {
+  constexpr unsigned E = sizeof(T);
+  int js[2];
+  T wt[2];
+  int nt;
+  if (!TM) { js[0] = n; wt[0] = T(1); nt = 1; }
+  else if (n & 1) { js[0] = n >> 1; wt[0] = T(1); nt = 1; }
+  else {
+    const int J = n >> 1;
+    js[0] = J; wt[0] = T(0.5); nt = 1;
+    if (J > 0) { js[1] = J - 1; wt[1] = T(0.5); nt = 2; }
+  }
+#pragma unroll
+  for (int j = 0; j < BY + 2; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cr[j][i] = T(0);
+  for (int tt = 0; tt < nt; ++tt) {
+    const gcptr Ec = ubase(ec + (size_t)js[tt] * M * Pc + (size_t)m * Pc);
+    const T w = wt[tt];
+    if (SP) {
+      T cv[3][3];
+#pragma unroll
+      for (int yy = 0; yy < (TWOD ? 3 : 1); ++yy)
+#pragma unroll
+        for (int xx = 0; xx < 3; ++xx) cv[yy][xx] = ldo<T>(Ec, cn.ocy[yy] + cn.ocx[xx]);
+      // x interpolation of each coarse row at fine dx = -1, 0, 1, 2
+      T rx[3][4];
+#pragma unroll
+      for (int yy = 0; yy < (TWOD ? 3 : 1); ++yy) {
+        rx[yy][0] = T(0.5) * (cv[yy][0] + cv[yy][1]);
+        rx[yy][1] = cv[yy][1];
+        rx[yy][2] = T(0.5) * (cv[yy][1] + cv[yy][2]);
+        rx[yy][3] = cv[yy][2];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (TWOD) {
+          cr[0][i] += w * T(0.5) * (rx[0][i] + rx[1][i]);  // dy = -1
+          cr[1][i] += w * rx[1][i];                         // dy = 0
+          cr[2][i] += w * T(0.5) * (rx[1][i] + rx[2][i]);  // dy = 1
+          cr[3][i] += w * rx[2][i];                         // dy = 2
+        } else {
+          cr[1][i] += w * rx[0][i];
+        }
+      }
+    } else {
+      // time only: the coarse grid is the fine grid
+#pragma unroll
+      for (int j = 0; j < BY + 2; ++j) {
+        if (!TWOD && j != 1) continue;
+        T v0, v1;
+        ld2o(Ec, b.orow[j] * E, v0, v1);
+        cr[j][1] += w * v0;
+        cr[j][2] += w * v1;
+        if (j >= 1 && j <= BY) {
+          cr[j][0] += w * ldo<T>(Ec, b.oside[j - 1][0] * E);
+          cr[j][3] += w * ldo<T>(Ec, b.oside[j - 1][1] * E);
+        }
+      }
+    }
+  }
+}
+
+// U' = U + P e_c on the own points of block b in fine slab n: node values
+// and scaled 5-point Laplacians (U' is formed on the halo too, never stored).
+// U may be null (zero).
+template <int M, typename T, bool SP, bool TM, int BY, bool TWOD>
+__device__ __forceinline__ void prolonged_blk(const Consts<M, T>& c, const T* __restrict__ U,
+                                              const T* __restrict__ ec, int n, int P, int Pc,
+                                              const Blk<BY>& b,
+                                              const CoarseNbr<T, SP, TWOD, BY>& cn,
+                                              T u[2 * BY][M], T lap[2 * BY][M]) {
+  constexpr unsigned E = sizeof(T);
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    T cr[BY + 2][4];
+    corr_blk<M, T, SP, TM, BY, TWOD>(ec, n, m, Pc, b, cn, cr);
+    const gcptr Um = U ? ubase(U + (size_t)(n * M + m) * P) : nullptr;
+    T rw[BY + 2][2];
+#pragma unroll
+    for (int j = 0; j < BY + 2; ++j) {
+      if (!TWOD && j != 1) continue;
+      T v0 = T(0), v1 = T(0);
+      if (Um) ld2o(Um, b.orow[j] * E, v0, v1);
+      rw[j][0] = v0 + cr[j][1];
+      rw[j][1] = v1 + cr[j][2];
+    }
+#pragma unroll
+    for (int j = 0; j < BY; ++j) {
+      const T l = (Um ? ldo<T>(Um, b.oside[j][0] * E) : T(0)) + cr[j + 1][0];
+      const T r = (Um ? ldo<T>(Um, b.oside[j][1] * E) : T(0)) + cr[j + 1][3];
+      const T c0 = rw[j + 1][0], c1 = rw[j + 1][1];
+      T l0 = c.cx * (l + c1 - c0 - c0);
+      T l1 = c.cx * (c0 + r - c1 - c1);
+      if (TWOD) {
+        l0 += c.cy * (rw[j][0] + rw[j + 2][0] - c0 - c0);
+        l1 += c.cy * (rw[j][1] + rw[j + 2][1] - c1 - c1);
+      }
+      u[2 * j][m] = c0;
+      u[2 * j + 1][m] = c1;
+      lap[2 * j][m] = l0;
+      lap[2 * j + 1][m] = l1;
+    }
+  }
+}
+
+// Coupling value cout . U'_n on the own points of block b (nodes with a zero
+// weight are not read).
+template <int M, typename T, bool SP, bool TM, int BY, bool TWOD>
+__device__ __forceinline__ void prolonged_cout(const Consts<M, T>& c, const T* __restrict__ U,
+                                               const T* __restrict__ ec, int n, int P, int Pc,
+                                               const Blk<BY>& b,
+                                               const CoarseNbr<T, SP, TWOD, BY>& cn,
+                                               T prev[2 * BY]) {
+  constexpr unsigned E = sizeof(T);
+#pragma unroll
+  for (int k = 0; k < 2 * BY; ++k) prev[k] = T(0);
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    if (c.cout[m] == T(0)) continue;
+    T cr[BY + 2][4];
+    corr_blk<M, T, SP, TM, BY, TWOD>(ec, n, m, Pc, b, cn, cr);
+    const gcptr Um = U ? ubase(U + (size_t)(n * M + m) * P) : nullptr;
+#pragma unroll
+    for (int j = 0; j < BY; ++j) {
+      T v0 = T(0), v1 = T(0);
+      if (Um) ld2o(Um, b.orow[j + 1] * E, v0, v1);
+      prev[2 * j] += c.cout[m] * (v0 + cr[j + 1][1]);
+      prev[2 * j + 1] += c.cout[m] * (v1 + cr[j + 1][2]);
+    }
+  }
+}
+
 // Prolongation fused with the first post-smoothing sweep:
 //   U' = U + P e_c,  U_out = U' + omega D^{-1} (f - A U')
-// on 2 x BY blocks.  U' is formed in registers on the block's own points and
-// on its halo (rows y0 - 1, y0 + BY, columns x0 - 1, x0 + 2), so it is never
-// stored.  Space interpolation is linear per dimension (fine 2X = coarse X),
-// time interpolation is linear in slab end points (coarse -1 = 0).
+// on 2 x BY blocks, each thread marching through its run of S slabs.
 template <int M, typename T, int REACT, bool SP, bool TM, int BY, bool TWOD>
 __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const SweepPtrs<T>& a, int ncx,
                                                     int ncy, int Nc, const T* __restrict__ ec, int S,
@@ -1459,88 +2036,9 @@ __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const Swe
     const int n1 = min(n0 + S, p.N);
     const Consts<M, T> c(p);
     const Blk<BY> b(t, nx, ny);
+    const CoarseNbr<T, SP, TWOD, BY> cn(b, ncx, ncy);
     const T dg = T(2) * c.cx + (TWOD ? T(2) * c.cy : T(0));
     T* __restrict__ out = static_cast<T*>(a.out);
-    constexpr unsigned E = sizeof(T);
-    // coarse neighbourhood of the block (space coarsening): byte offsets of
-    // the columns and rows -1, 0, +1 around coarse point (x0 / 2, y0 / 2)
-    unsigned ocx[3] = {0, 0, 0}, ocy[3] = {0, 0, 0};
-    if (SP) {
-      const int X = b.x0 >> 1, Y = TWOD ? (b.y0 >> 1) : 0;
-      ocx[0] = (X > 0 ? X - 1 : ncx - 1) * E;
-      ocx[1] = X * E;
-      ocx[2] = (X + 1 < ncx ? X + 1 : 0) * E;
-      if (TWOD) {
-        ocy[0] = (Y > 0 ? Y - 1 : ncy - 1) * ncx * E;
-        ocy[1] = Y * ncx * E;
-        ocy[2] = (Y + 1 < ncy ? Y + 1 : 0) * ncx * E;
-      }
-    }
-    // Correction at the 4 x (BY + 2) fine positions (dx = -1..2, dy = -1..BY)
-    // of node m in fine slab n; only the own rows' dx = -1..2 and the halo
-    // rows' dx = 0..1 are used.
-    auto corr = [&](int n, int m, T cr[BY + 2][4]) {
-      int js[2];
-      T wt[2];
-      int nt;
-      if (!TM) { js[0] = n; wt[0] = T(1); nt = 1; }
-      else if (n & 1) { js[0] = n >> 1; wt[0] = T(1); nt = 1; }
-      else {
-        const int J = n >> 1;
-        js[0] = J; wt[0] = T(0.5); nt = 1;
-        if (J > 0) { js[1] = J - 1; wt[1] = T(0.5); nt = 2; }
-      }
-#pragma unroll
-      for (int j = 0; j < BY + 2; ++j)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) cr[j][i] = T(0);
-      for (int tt = 0; tt < nt; ++tt) {
-        const gcptr Ec = ubase(ec + (size_t)js[tt] * M * Pc + (size_t)m * Pc);
-        const T w = wt[tt];
-        if (SP) {
-          T cv[3][3];
-#pragma unroll
-          for (int yy = 0; yy < (TWOD ? 3 : 1); ++yy)
-#pragma unroll
-            for (int xx = 0; xx < 3; ++xx) cv[yy][xx] = ldo<T>(Ec, ocy[yy] + ocx[xx]);
-          // x interpolation of each coarse row at fine dx = -1, 0, 1, 2
-          T rx[3][4];
-#pragma unroll
-          for (int yy = 0; yy < (TWOD ? 3 : 1); ++yy) {
-            rx[yy][0] = T(0.5) * (cv[yy][0] + cv[yy][1]);
-            rx[yy][1] = cv[yy][1];
-            rx[yy][2] = T(0.5) * (cv[yy][1] + cv[yy][2]);
-            rx[yy][3] = cv[yy][2];
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (TWOD) {
-              cr[0][i] += w * T(0.5) * (rx[0][i] + rx[1][i]);  // dy = -1
-              cr[1][i] += w * rx[1][i];                         // dy = 0
-              cr[2][i] += w * T(0.5) * (rx[1][i] + rx[2][i]);  // dy = 1
-              cr[3][i] += w * rx[2][i];                         // dy = 2
-            } else {
-              cr[1][i] += w * rx[0][i];
-            }
-          }
-        } else {
-          // time only: the coarse grid is the fine grid
-#pragma unroll
-          for (int j = 0; j < BY + 2; ++j) {
-            if (!TWOD && j != 1) continue;
-            T v0, v1;
-            ld2o(Ec, b.orow[j] * E, v0, v1);
-            cr[j][1] += w * v0;
-            cr[j][2] += w * v1;
-            if (j >= 1 && j <= BY) {
-              cr[j][0] += w * ldo<T>(Ec, b.oside[j - 1][0] * E);
-              cr[j][3] += w * ldo<T>(Ec, b.oside[j - 1][1] * E);
-            }
-          }
-        }
-      }
-    };
-    // U' on the block's own points of slab n, node m (for the run's coupling)
     T prev[NP], dprev[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) { prev[k] = T(0); dprev[k] = T(0); }
@@ -1554,55 +2052,12 @@ __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const Swe
         }
       }
     } else {
-#pragma unroll
-      for (int m = 0; m < M; ++m) {
-        if (c.cout[m] == T(0)) continue;
-        T cr[BY + 2][4];
-        corr(n0 - 1, m, cr);
-        const gcptr Um = a.U ? ubase(a.U + (size_t)((n0 - 1) * M + m) * P) : nullptr;
-#pragma unroll
-        for (int j = 0; j < BY; ++j) {
-          T v0 = T(0), v1 = T(0);
-          if (Um) ld2o(Um, b.orow[j + 1] * E, v0, v1);
-          prev[2 * j] += c.cout[m] * (v0 + cr[j + 1][1]);
-          prev[2 * j + 1] += c.cout[m] * (v1 + cr[j + 1][2]);
-        }
-      }
+      prolonged_cout<M, T, SP, TM, BY, TWOD>(c, a.U, ec, n0 - 1, P, Pc, b, cn, prev);
     }
     for (int n = n0; n < n1; ++n) {
       const size_t base = (size_t)n * M * P;
       T u[NP][M], lap[NP][M], fv[NP][M], cv[NP][M], o[NP][M];
-#pragma unroll
-      for (int m = 0; m < M; ++m) {
-        T cr[BY + 2][4];
-        corr(n, m, cr);
-        const gcptr Um = a.U ? ubase(a.U + base + (size_t)m * P) : nullptr;
-        T rw[BY + 2][2];
-#pragma unroll
-        for (int j = 0; j < BY + 2; ++j) {
-          if (!TWOD && j != 1) continue;
-          T v0 = T(0), v1 = T(0);
-          if (Um) ld2o(Um, b.orow[j] * E, v0, v1);
-          rw[j][0] = v0 + cr[j][1];
-          rw[j][1] = v1 + cr[j][2];
-        }
-#pragma unroll
-        for (int j = 0; j < BY; ++j) {
-          const T l = (Um ? ldo<T>(Um, b.oside[j][0] * E) : T(0)) + cr[j + 1][0];
-          const T r = (Um ? ldo<T>(Um, b.oside[j][1] * E) : T(0)) + cr[j + 1][3];
-          const T c0 = rw[j + 1][0], c1 = rw[j + 1][1];
-          T l0 = c.cx * (l + c1 - c0 - c0);
-          T l1 = c.cx * (c0 + r - c1 - c1);
-          if (TWOD) {
-            l0 += c.cy * (rw[j][0] + rw[j + 2][0] - c0 - c0);
-            l1 += c.cy * (rw[j][1] + rw[j + 2][1] - c1 - c1);
-          }
-          u[2 * j][m] = c0;
-          u[2 * j + 1][m] = c1;
-          lap[2 * j][m] = l0;
-          lap[2 * j + 1][m] = l1;
-        }
-      }
+      prolonged_blk<M, T, SP, TM, BY, TWOD>(c, a.U, ec, n, P, Pc, b, cn, u, lap);
       if (a.f) {
         load_own<M, T, BY>(a.f, base, P, nx, b, fv);
       } else {
@@ -1624,25 +2079,12 @@ __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const Swe
 #pragma unroll
           for (int i = 0; i < M; ++i) r[i] += c.cin[i] * dprev[k];
         }
-        if (REACT == REACT_COEF) {
-#pragma unroll
-          for (int i = 0; i < M; ++i) d[i] = r[i];
-          point_block_solve<M, T>(c, dg, cv[k], d);
-        } else {
-#pragma unroll
-          for (int i = 0; i < M; ++i) {
-            T sm = T(0);
-#pragma unroll
-            for (int j = 0; j < M; ++j) sm += c.Bi[i][j] * r[j];
-            d[i] = sm;
-          }
-        }
-        T np = T(0), nd = T(0);
+        const T nd = point_correction<M, T, REACT>(c, dg, cv[k], r, d);
+        T np = T(0);
 #pragma unroll
         for (int i = 0; i < M; ++i) {
           o[k][i] = u[k][i] + c.omega * d[i];
           np += c.cout[i] * u[k][i];
-          nd += c.cout[i] * d[i];
         }
         prev[k] = np;
         dprev[k] = nd;
@@ -1664,6 +2106,138 @@ __global__ __launch_bounds__(kBlock) void k_prolong_smooth_blk(const OpParams p,
   const int lb = xcd_remap(blockIdx.x, nblocks);
   prolong_smooth_body<M, T, REACT, SP, TM, BY, TWOD>(p, a, ncx, ncy, Nc, ec, S, lb % tiles,
                                                      (lb / tiles) * S, lb);
+}
+
+// Slab-parallel form of the fused prolongation + post-smoothing for small
+// levels, whose cost is latency: a workgroup covers SL consecutive slabs (one
+// smoother chunk, SL a power of two) of kBlock / SL blocks, one slab per
+// thread, so every slab's loads are in flight at once.  The residuals are
+// formed in parallel (the coupling value of slab n - 1 comes from the thread
+// below through LDS), then one thread per block runs the chunk's forward
+// substitution over the M-vectors in LDS, then every thread writes its slab.
+// The arithmetic is that of prolong_smooth_body, operation for operation.
+// kBlock / SL must be a multiple of the wave size: each wave lies in one slab
+// (its plane bases are wave-uniform).
+// LDS: kBlock * 2BY * (M + 1) values of T, plus kBlock * 2BY * M for REACT_COEF.
+template <int M, typename T, int REACT, bool SP, bool TM, int BY, bool TWOD>
+__device__ __forceinline__ void prolong_smooth_sp_body(const OpParams& p, const SweepPtrs<T>& a,
+                                                       int ncx, int ncy, const T* __restrict__ ec,
+                                                       int SL, int tile, int n0, T* lds) {
+  constexpr int NP = 2 * BY;
+  const int NB = kBlock / SL;
+  const int tid = threadIdx.x;
+  const int sl = tid / NB, pb = tid - sl * NB;
+  const int nx = p.nx, ny = p.ny, P = nx * ny;
+  const int Pc = ncx * ncy;
+  const int t = tile * NB + pb;
+  const int n = n0 + sl;
+  const bool blk_ok = t < (nx >> 1) * (ny / BY);
+  const bool act = blk_ok && n < p.N;
+  T (*sR)[NP][M] = reinterpret_cast<T (*)[NP][M]>(lds);
+  T (*sP)[NP] = reinterpret_cast<T (*)[NP]>(lds + kBlock * NP * M);
+  T (*sC)[NP][M] = reinterpret_cast<T (*)[NP][M]>(lds + kBlock * NP * (M + 1));
+  const Consts<M, T> c(p);
+  const Blk<BY> b(blk_ok ? t : 0, nx, ny);
+  const CoarseNbr<T, SP, TWOD, BY> cn(b, ncx, ncy);
+  const T dg = T(2) * c.cx + (TWOD ? T(2) * c.cy : T(0));
+  T u[NP][M], lap[NP][M], fv[NP][M], cv[NP][M], prev[NP];
+  if (act) {
+    prolonged_blk<M, T, SP, TM, BY, TWOD>(c, a.U, ec, n, P, Pc, b, cn, u, lap);
+    const size_t base = (size_t)n * M * P;
+    if (a.f) {
+      load_own<M, T, BY>(a.f, base, P, nx, b, fv);
+    } else {
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int m = 0; m < M; ++m) fv[k][m] = T(0);
+    }
+    if (REACT == REACT_COEF) load_own<M, T, BY>(a.coef, base, P, nx, b, cv);
+    if (sl == 0) {
+      if (n0 == 0) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) prev[k] = T(0);
+        if (a.u0) {
+#pragma unroll
+          for (int j = 0; j < BY; ++j) {
+            const double* q = a.u0 + (b.y0 + j) * nx + b.x0;
+            prev[2 * j] = (T)q[0];
+            prev[2 * j + 1] = (T)q[1];
+          }
+        }
+      } else {
+        prolonged_cout<M, T, SP, TM, BY, TWOD>(c, a.U, ec, n0 - 1, P, Pc, b, cn, prev);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      T np = T(0);
+#pragma unroll
+      for (int i = 0; i < M; ++i) np += c.cout[i] * u[k][i];
+      sP[tid][k] = np;
+      if (REACT == REACT_COEF) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) sC[tid][k][i] = cv[k][i];
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      if (sl > 0) prev[k] = sP[tid - NB][k];
+      T r[M];
+      resid_vals<M, T, REACT>(c, u[k], lap[k], fv[k], cv[k], prev[k], r);
+#pragma unroll
+      for (int i = 0; i < M; ++i) sR[tid][k][i] = r[i];
+    }
+  }
+  __syncthreads();
+  if (sl == 0 && blk_ok) {
+    T dprev[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) dprev[k] = T(0);
+    for (int ss = 0; ss < SL && n0 + ss < p.N; ++ss) {
+      const int q = ss * NB + pb;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        T r[M], d[M], cq[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          r[i] = sR[q][k][i];
+          cq[i] = REACT == REACT_COEF ? sC[q][k][i] : T(0);
+        }
+        if (ss > 0) {
+#pragma unroll
+          for (int i = 0; i < M; ++i) r[i] += c.cin[i] * dprev[k];
+        }
+        dprev[k] = point_correction<M, T, REACT>(c, dg, cq, r, d);
+#pragma unroll
+        for (int i = 0; i < M; ++i) sR[q][k][i] = d[i];
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+    T o[NP][M];
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+      for (int i = 0; i < M; ++i) o[k][i] = u[k][i] + c.omega * sR[tid][k][i];
+    store_own<M, T, BY>(static_cast<T*>(a.out), (size_t)n * M * P, P, nx, b, o);
+  }
+}
+
+template <int M, typename T, int REACT, bool SP, bool TM, int BY, bool TWOD>
+__global__ __launch_bounds__(kBlock) void k_prolong_smooth_sp(const OpParams p, const SweepPtrs<T> a,
+                                                              int ncx, int ncy,
+                                                              const T* __restrict__ ec, int SL,
+                                                              int tiles, int nblocks) {
+  extern __shared__ __align__(16) unsigned char smem_ps[];
+  const int lb = xcd_remap(blockIdx.x, nblocks);
+  prolong_smooth_sp_body<M, T, REACT, SP, TM, BY, TWOD>(p, a, ncx, ncy, ec, SL, lb % tiles,
+                                                        (lb / tiles) * SL,
+                                                        reinterpret_cast<T*>(smem_ps));
 }
 
 // ---------------------------------------------------------------------------

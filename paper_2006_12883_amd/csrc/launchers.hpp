@@ -28,6 +28,28 @@ inline int plane_threads(const OpParams& p) {
   return p.nx * p.ny;
 }
 
+// Slab-parallel kernels (one slab of a smoother chunk per thread) serve the
+// small levels, where a thread marching through its slabs waits on one
+// memory round trip per slab.  Returns the workgroup's slab count (the chunk,
+// or the next power of two >= N when one chunk holds every slab), or 0 when
+// the level is large or the chunk is not a power of two.  Every wave must
+// lie inside one slab (the kernels address each slab's planes through a
+// wave-uniform base), so a workgroup holds at most kBlock / 64 slabs.
+// level sizes (points x slabs) up to which the slab-parallel form is faster
+constexpr long long kSlabParallelMaxWork = 1LL << 19;          // prolongation + smoothing
+constexpr long long kSlabParallelMaxWorkRestrict = 1LL << 20;  // time restriction
+constexpr size_t kSlabParallelLds = 64 * 1024;
+constexpr int kSlabParallelMaxLen = kBlock / 64;
+inline int slab_parallel_len(int M, long long work, int nslabs, int chunk,
+                             long long max_work = kSlabParallelMaxWork) {
+  if (M > 4 || chunk < 1 || (chunk & (chunk - 1)) != 0) return 0;
+  if (work > max_work) return 0;
+  int sl = chunk;
+  while (sl > 1 && (sl >> 1) >= nslabs) sl >>= 1;
+  return (sl >= 2 && sl <= kSlabParallelMaxLen) ? sl : 0;
+}
+inline long long level_work(const OpParams& p) { return (long long)p.nx * p.ny * p.N; }
+
 
 
 
@@ -109,23 +131,24 @@ hipError_t launch_restrict_residual(const OpParams& p, int react, const SweepPtr
     const bool zs = uc != nullptr && pc != nullptr && cs >= 1 && (spb % cs) == 0;
     if (smoothed) *smoothed = zs;
     const OpParams& pcc = zs ? *pc : p;
-    // register-blocked fine tiles, 16 x 16 coarse points (2D) or 256 (1D)
-    const int tcx = twod ? 16 : 256;
-    const int tcy = twod ? 16 : 1;
+    // register-blocked fine tiles, 32 x 8 coarse points (2D: 512-byte fine
+    // row segments) or 256 (1D)
+    const int tcx = twod ? 32 : 256;
+    const int tcy = twod ? 8 : 1;
     const int tiles_x = (ncx + tcx - 1) / tcx;
     const int tiles = tiles_x * ((ncy + tcy - 1) / tcy);
     const int nb = tiles * ((Nc + spb - 1) / spb);
 #define LRB(MM, RE, TMc, TWc, CX, CY)                                                            \
   if (zs)                                                                                           \
-    hipLaunchKernelGGL((k_restrict_blk<MM, T, RE, TMc, TWc, CX, CY, true>), dim3(nb), dim3(kBlock), 0, \
+    hipLaunchKernelGGL((k_restrict_blk<MM, T, RE, TMc, TWc, CX, CY, true, true>), dim3(nb), dim3(kBlock), 0, \
                        s, p, a, ncx, ncy, Nc, fc, spb, tiles_x, tiles, nb, pcc, uc, coefc, cs);     \
   else                                                                                              \
-    hipLaunchKernelGGL((k_restrict_blk<MM, T, RE, TMc, TWc, CX, CY, false>), dim3(nb), dim3(kBlock), 0, \
+    hipLaunchKernelGGL((k_restrict_blk<MM, T, RE, TMc, TWc, CX, CY, false, true>), dim3(nb), dim3(kBlock), 0, \
                        s, p, a, ncx, ncy, Nc, fc, spb, tiles_x, tiles, nb, pcc, uc, coefc, cs)
 #define LRBE(MM, RE)                                          \
   if (twod) {                                                 \
-    if (time) LRB(MM, RE, true, true, 16, 16);                \
-    else LRB(MM, RE, false, true, 16, 16);                    \
+    if (time) LRB(MM, RE, true, true, 32, 8);                 \
+    else LRB(MM, RE, false, true, 32, 8);                     \
   } else {                                                    \
     if (time) LRB(MM, RE, true, false, 256, 1);               \
     else LRB(MM, RE, false, false, 256, 1);                   \
@@ -174,7 +197,42 @@ hipError_t launch_restrict_residual(const OpParams& p, int react, const SweepPtr
     return hipGetLastError();
   }
   if (!space && time && blocked(p)) {
-    const bool zs = uc != nullptr && pc != nullptr && cs >= 1 && (spb % cs) == 0;
+    const bool want_zs = uc != nullptr && pc != nullptr && cs >= 1;
+    const int sl = slab_parallel_len(p.M, level_work(p), Nc, want_zs ? cs : kSlabParallelMaxLen,
+                                    kSlabParallelMaxWorkRestrict);
+    const int NP = twod ? 4 : 2;
+    const size_t lds = (size_t)kBlock * NP *
+                       (p.M + 1 + (react == REACT_COEF && want_zs ? p.M : 0)) * sizeof(T);
+    if (sl > 0 && lds <= kSlabParallelLds) {
+      if (smoothed) *smoothed = want_zs;
+      const OpParams& pcc = want_zs ? *pc : p;
+      const int nbk = kBlock / sl;
+      const int tiles = (plane_threads(p) + nbk - 1) / nbk;
+      const int nb = tiles * ((Nc + sl - 1) / sl);
+#define LT(MM, RE, BYc, TWc)                                                                       \
+  if (want_zs)                                                                                      \
+    hipLaunchKernelGGL((k_restrict_t_sp<MM, T, RE, BYc, TWc, true>), dim3(nb), dim3(kBlock), lds, s, p, \
+                       a, Nc, fc, sl, tiles, nb, pcc, uc, coefc, cs);                               \
+  else                                                                                              \
+    hipLaunchKernelGGL((k_restrict_t_sp<MM, T, RE, BYc, TWc, false>), dim3(nb), dim3(kBlock), lds, s, p, \
+                       a, Nc, fc, sl, tiles, nb, pcc, uc, coefc, cs)
+#define LTS(MM, RE) \
+  if (twod) { LT(MM, RE, 2, true); } else { LT(MM, RE, 1, false); }
+#define L(MM) \
+  if (react == REACT_COEF) { LTS(MM, REACT_COEF) } else { LTS(MM, REACT_CONST) }
+      switch (p.M) {
+        case 1: L(1); break;
+        case 2: L(2); break;
+        case 3: L(3); break;
+        case 4: L(4); break;
+        default: return hipErrorInvalidValue;
+      }
+#undef L
+#undef LTS
+#undef LT
+      return hipGetLastError();
+    }
+    const bool zs = want_zs && (spb % cs) == 0;
     if (smoothed) *smoothed = zs;
     const OpParams& pcc = zs ? *pc : p;
     const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
@@ -262,6 +320,37 @@ hipError_t launch_prolong_smooth(const OpParams& p, int react, const SweepPtrs<T
                                  hipStream_t s) {
   if (!blocked(p)) return hipErrorNotSupported;
   const bool twod = p.ny > 1;
+  const int sl = slab_parallel_len(p.M, level_work(p), p.N, chunk);
+  const int NP = twod ? 4 : 2;
+  const size_t lds = (size_t)kBlock * NP * (p.M + 1 + (react == REACT_COEF ? p.M : 0)) * sizeof(T);
+  if (sl > 0 && a.part == nullptr && lds <= kSlabParallelLds) {
+    const int nbk = kBlock / sl;
+    const int tiles = (plane_threads(p) + nbk - 1) / nbk;
+    const int nb = tiles * ((p.N + sl - 1) / sl);
+#define LF(MM, RE, SPc, TMc, BYc, TWc)                                                           \
+  hipLaunchKernelGGL((k_prolong_smooth_sp<MM, T, RE, SPc, TMc, BYc, TWc>), dim3(nb), dim3(kBlock), \
+                     lds, s, p, a, ncx, ncy, ec, sl, tiles, nb)
+#define LFS(MM, RE, BYc, TWc)                                   \
+  if (space && time) LF(MM, RE, true, true, BYc, TWc);          \
+  else if (space) LF(MM, RE, true, false, BYc, TWc);            \
+  else LF(MM, RE, false, true, BYc, TWc);
+#define LFR(MM, RE) \
+  if (twod) { LFS(MM, RE, 2, true) } else { LFS(MM, RE, 1, false) }
+#define L(MM) \
+  if (react == REACT_COEF) { LFR(MM, REACT_COEF) } else { LFR(MM, REACT_CONST) }
+    switch (p.M) {
+      case 1: L(1); break;
+      case 2: L(2); break;
+      case 3: L(3); break;
+      case 4: L(4); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef L
+#undef LFR
+#undef LFS
+#undef LF
+    return hipGetLastError();
+  }
   const int nb = smooth_blocks(p, chunk);
   const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
 #define LF(MM, RE, SPc, TMc, BYc, TWc)                                                            \

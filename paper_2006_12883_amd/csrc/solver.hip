@@ -68,7 +68,8 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     return STMG_EINVAL;
   }
   if (o->chunk < 1 || o->chunk_coarse < 1 || o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1 ||
-      o->max_levels < 1 || o->max_cycles < 1 || !(o->rtol > 0.0) || !(o->omega > 0.0)) {
+      o->max_levels < 1 || o->max_cycles < 1 || !(o->rtol > 0.0) || !(o->omega > 0.0) ||
+      o->inner_cycles < 1) {
     set_error("invalid options");
     return STMG_EINVAL;
   }
@@ -548,7 +549,7 @@ double Solver::norm_u0_b(const double* u0) {
 // FP64 residual with FP64 updates (iterative refinement).  `U` holds the
 // initial guess and receives the result.
 int Solver::solve_linear(bool adj, int react, const double* f, const double* u0, double* U,
-                         double rtol, double norm_b, int* cycles, double* rel_out) {
+                         double rtol, double norm_b, int* cycles, double* rel_out, int* refinements) {
   Level& L0 = lv[0];
   const OpParams& op0 = adj ? L0.opT : L0.op;
   // FP64 with pre-smoothing: the first sweep of every cycle also returns
@@ -556,13 +557,34 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
   // (the sweep writes the ping-pong partner), so the stop test costs no extra
   // pass over the data.
   const bool fused = !mixed && opt.nu_pre >= 1;
+  // Mixed precision on the register-blocked layout: one fused sweep per
+  // refinement step forms U' = U + e, its FP64 residual and norm, the FP32
+  // right-hand side and the first FP32 smoothing sweep (k_refine_blk); the
+  // iterate ping-pongs between U and L0.B64.
+  const bool refine = mixed && opt.nu_pre >= 1 && blocked_layout(op0) &&
+                      (react == REACT_CONST || react == REACT_COEF);
+  const int inner = mixed ? opt.inner_cycles : 1;
   HIP_CHECK(hnorm.init());
+  double* Ucur = U;
+  double* Unext = L0.B64;
+  const float* ecur = nullptr;
+  float* e1 = L0.A32;
   // Queues ||f - A U||^2 of the current iterate and its copy to the host.
   auto launch_norm = [&]() -> hipError_t {
     if (fused) {
       SweepPtrs<double> a{U, f, u0, L0.coef64, L0.B64, part};
       HIP_TRY(launch_smooth<double>(op0, react, a, chunk_of(0), stream));
       HIP_TRY(launch_sum_partials(part, smooth_blocks(op0, chunk_of(0)), scal, stream));
+    } else if (refine) {
+      SweepPtrs<double> a{Ucur, f, u0, L0.coef64, Unext, part};
+      e1 = (ecur == L0.A32) ? L0.B32 : L0.A32;
+      int np = 0;
+      if (smooth_blocks(op0, chunk_of(0)) > max_parts) {
+        set_error("partial buffer too small");
+        return hipErrorInvalidValue;
+      }
+      HIP_TRY(launch_refine(op0, react, a, ecur, L0.f32, e1, L0.coef32, chunk_of(0), &np, stream));
+      HIP_TRY(launch_sum_partials(part, np, scal, stream));
     } else if (!mixed) {
       HIP_TRY(residual64<double>(adj, react, U, f, u0, nullptr, scal));
     } else {
@@ -574,7 +596,8 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
   double rel = 0.0, rel0 = 0.0, prev = 0.0;
   bool first = true;
   int incr = 0;
-  int c = 0;
+  int c = 0;   // outer steps (V-cycles in FP64, refinement steps in mixed precision)
+  int vc = 0;  // V-cycles
   int status = STMG_OK;
   // Waits for the queued norm and applies the stop tests to U_c.
   auto decide = [&](bool* stop) -> hipError_t {
@@ -591,7 +614,7 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
       if (incr >= 5) { status = STMG_EDIVERGED; return hipSuccess; }
     }
     prev = rel;
-    if (c >= opt.max_cycles) { status = STMG_ENOTCONV; return hipSuccess; }
+    if (vc >= opt.max_cycles) { status = STMG_ENOTCONV; return hipSuccess; }
     *stop = false;
     return hipSuccess;
   };
@@ -615,21 +638,48 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
       HIP_CHECK(vcycle<double>(0, adj, react, L0.B64, U, f, u0, false, &res, 1));
       if (!res) break;
       if (res != U) HIP_CHECK(hipMemcpyAsync(U, res, L0.n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+      ++vc;
     } else if (!mixed) {
       double* res = nullptr;
       HIP_CHECK(vcycle<double>(0, adj, react, U, L0.B64, f, u0, false, &res, 0));
       if (!res) break;
       if (res != U) HIP_CHECK(hipMemcpyAsync(U, res, L0.n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+      ++vc;
     } else {
+      // FP32 V-cycles on A e = r: the first starts from the sweep already in
+      // e1 (fused refinement) or from zero.
       float* res = nullptr;
-      HIP_CHECK(vcycle<float>(0, adj, react, L0.A32, L0.B32, L0.f32, nullptr, true, &res, 0));
+      float* oth = (e1 == L0.A32) ? L0.B32 : L0.A32;
+      if (refine) HIP_CHECK(vcycle<float>(0, adj, react, e1, oth, L0.f32, nullptr, false, &res, 1));
+      else HIP_CHECK(vcycle<float>(0, adj, react, L0.A32, L0.B32, L0.f32, nullptr, true, &res, 0));
       if (!res) break;
-      HIP_CHECK(launch_update<float>(L0.n, U, res, nullptr, stream));
+      ++vc;
+      for (int k = 1; k < inner; ++k) {
+        float* other = (res == L0.A32) ? L0.B32 : L0.A32;
+        float* r2 = nullptr;
+        const auto g = std::move(gate0);
+        gate0 = nullptr;
+        const hipError_t e = vcycle<float>(0, adj, react, res, other, L0.f32, nullptr, false, &r2, 0);
+        gate0 = g;
+        HIP_CHECK(e);
+        res = r2;
+        ++vc;
+      }
+      if (refine) {
+        std::swap(Ucur, Unext);
+        ecur = res;
+      } else {
+        HIP_CHECK(launch_update<float>(L0.n, U, res, nullptr, stream));
+      }
     }
     ++c;
     HIP_CHECK(launch_norm());
   }
-  *cycles += c;
+  // Fused refinement: the last refinement kernel wrote the final iterate to Unext.
+  if (refine && Unext != U)
+    HIP_CHECK(hipMemcpyAsync(U, Unext, L0.n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  *cycles += vc;
+  if (refinements) *refinements += mixed ? c : 0;
   *rel_out = rel;
   if (status != STMG_OK) {
     set_error(std::string("linear solve stopped: ") + stmg_status_string(status));
@@ -679,8 +729,8 @@ int Solver::solve(const double* u0, double* U, stmg_stats* st) {
   if (nb < 0.0) return STMG_EHIP;
   int rc = STMG_OK;
   if (!allen_cahn) {
-    rc = solve_linear(false, REACT_CONST, nullptr, u0, U, opt.rtol, nb, &s.cycles, &s.rel_res);
-    s.refinements = mixed ? s.cycles : 0;
+    rc = solve_linear(false, REACT_CONST, nullptr, u0, U, opt.rtol, nb, &s.cycles, &s.rel_res,
+                      &s.refinements);
   } else {
     // Newton on G(U) = b - A_AC(U) (Sec. 3.2), inexact: each correction solve
     // stops at a relative tolerance eta_k (Eisenstat-Walker, choice 2).
@@ -711,12 +761,11 @@ int Solver::solve(const double* u0, double* U, stmg_stats* st) {
       HIP_CHECK(hipMemsetAsync(delta64, 0, L0.n * sizeof(double), stream));
       double rel = 0.0;
       int lrc = solve_linear(false, REACT_COEF, L0.f64, nullptr, delta64, eta, std::sqrt(g2),
-                             &s.cycles, &rel);
+                             &s.cycles, &rel, &s.refinements);
       if (lrc == STMG_ENAN || lrc == STMG_EHIP) { rc = lrc; break; }
       HIP_CHECK(launch_update<double>(L0.n, U, delta64, nullptr, stream));
       ++s.newton_its;
     }
-    if (mixed) s.refinements = s.cycles;
   }
   HIP_CHECK(hipStreamSynchronize(stream));
   s.status = rc;

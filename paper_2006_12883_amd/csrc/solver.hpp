@@ -164,7 +164,7 @@ struct Solver {
 
   // --- drivers ---
   int solve_linear(bool adj, int react, const double* f, const double* u0, double* U,
-                   double rtol, double norm_b, int* cycles, double* rel);
+                   double rtol, double norm_b, int* cycles, double* rel, int* refinements = nullptr);
   int solve(const double* u0, double* U, stmg_stats* st);
   int vcycle_user(const double* u0, double* U, double* h_rel);
   int residual_user(const double* u0, const double* U, double* r, double* h_norm);

@@ -22,7 +22,8 @@ def test_mixed_heat1d():
     u0 = si.initial("heat1d", prob)
     ref = stepper.solve_linear(prob, u0)
     U, st = H(prob, precision="mixed", rtol=1e-10).solve(T(u0))
-    assert st["status"] == 0 and st["rel_res"] <= 1e-10 and st["refinements"] == st["cycles"]
+    # two FP32 V-cycles per FP64 refinement step by default
+    assert st["status"] == 0 and st["rel_res"] <= 1e-10 and st["cycles"] == 2 * st["refinements"]
     e, eT = _errs(U.cpu().numpy(), ref)
     assert e <= 1e-9 and eT <= 1e-9, (e, eT)
 
@@ -35,6 +36,32 @@ def test_mixed_rd2d_small(M):
     ref = stepper.solve_linear(prob, u0)
     U, st = H(prob, precision="mixed", rtol=1e-10).solve(T(u0))
     assert st["status"] == 0
+    e, eT = _errs(U.cpu().numpy(), ref)
+    assert e <= 1e-9 and eT <= 1e-9, (e, eT)
+
+
+@pytest.mark.parametrize("inner", [1, 2, 3])
+def test_mixed_inner_cycles(inner):
+    """Any number of FP32 cycles per refinement step reaches the FP64 tolerance."""
+    print("case mixed inner cycles", inner, flush=True)
+    prob = si.problem(2, 64, 3, 32, 0.5, nu=1e-2, lam=1.0)
+    u0 = si.u0_rd2d(prob, 5)
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob, precision="mixed", rtol=1e-10, inner_cycles=inner).solve(T(u0))
+    assert st["status"] == 0 and st["rel_res"] <= 1e-10
+    assert st["cycles"] == inner * st["refinements"]
+    e, eT = _errs(U.cpu().numpy(), ref)
+    assert e <= 1e-9 and eT <= 1e-9, (e, eT)
+
+
+def test_mixed_neumann():
+    """Neumann grids take the unfused refinement path (separate update)."""
+    print("case mixed neumann", flush=True)
+    prob = si.problem(2, 32, 3, 16, 0.5, nu=1e-2, lam=1.0, bc="neumann")
+    u0 = np.random.default_rng(11).normal(size=si.grid_points(prob)[::-1])
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob, precision="mixed", rtol=1e-10).solve(T(u0))
+    assert st["status"] == 0 and st["rel_res"] <= 1e-10
     e, eT = _errs(U.cpu().numpy(), ref)
     assert e <= 1e-9 and eT <= 1e-9, (e, eT)
 
