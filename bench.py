@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE runs (scaled by a device copy of known size; see
 # profiles/k_smooth_blk_rd2d_level0.md), valid only for the kernel source it
 # was measured on.
-TRAFFIC = {"kernels_impl_sha256_prefix": "e89f6e0364023732", "bytes_per_launch": 450.6e6 + 402.65e6}
+TRAFFIC = {"kernels_impl_sha256_prefix": "b187ddf016ab9fa1", "bytes_per_launch": 456.76e6 + 402.65e6}
 
 
 def measured_traffic():
