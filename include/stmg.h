@@ -113,6 +113,12 @@ typedef struct {
                          0 (default): fixed shapes                            */
   int32_t inner_cycles; /* mixed precision: FP32 V-cycles on each correction
                          equation per FP64 refinement step, 2                 */
+  int32_t fft_coarse; /* periodic grids with a linear reaction: coarsening
+                         also stops at the first level below the finest whose
+                         planes hold <= 1024 points and which holds <=
+                         fft_coarse unknowns; that level is solved exactly by
+                         Fourier diagonalization in space and the slab
+                         recurrence per mode.  262144; 0 = off                */
 } stmg_options;
 
 typedef struct {

@@ -33,8 +33,14 @@ notes):
   mu >> 1 -> space), falling back to the other direction when one is not
   possible, until the level holds at most `min_coarse` unknowns.  The paper
   gives no threshold; mu_crit = 0.5 by default.
+* coarsest level: coarsening also stops at the first level below the finest
+  whose planes hold at most `fft_plane` points and which holds at most
+  `fft_coarse` unknowns (0 disables the rule).  This is a choice of where the
+  exact coarse solve sits (the paper fixes the number of levels per run); the
+  exact solve itself is the same direct slab-by-slab solve on any level.
 """
 import numpy as np
+import scipy.linalg
 
 from . import radau
 
@@ -92,13 +98,17 @@ class Level:
         return np.array(cols).T
 
     def exact_solve(self, f):
-        A = self.slab_matrix()
+        """Slab after slab, A_slab U_n = f_n + l(0) (x) U_{n-1,M}, with one LU
+        factorization of the (shared) dense slab matrix."""
+        if getattr(self, "_lu", None) is None:
+            self._lu = scipy.linalg.lu_factor(self.slab_matrix())
+        lu = self._lu
         U = np.zeros(self.shape)
         for n in range(self.N):
             rhs = f[n].copy()
             if n > 0:
                 rhs = rhs + self.l0[:, None, None] * U[n - 1, -1][None]
-            U[n] = np.linalg.solve(A, rhs.reshape(-1)).reshape(self.M, self.ny, self.nx)
+            U[n] = scipy.linalg.lu_solve(lu, rhs.reshape(-1)).reshape(self.M, self.ny, self.nx)
         return U
 
 
@@ -146,7 +156,8 @@ def prolong_time(e):
     return f
 
 
-def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30):
+def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30, fft_coarse=262144,
+              fft_plane=1024):
     """Level list and the coarsening kind between consecutive levels.
 
     kinds[l] is 's' (space), 't' (time) or 'st' (both) for the step l -> l+1.
@@ -165,6 +176,8 @@ def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30):
     while len(levels) < max_levels:
         l = levels[-1]
         if l.M * l.nx * l.ny * l.N <= min_coarse:
+            break
+        if len(levels) > 1 and l.nx * l.ny <= fft_plane and l.M * l.nx * l.ny * l.N <= fft_coarse:
             break
         can_s = l.nx % 2 == 0 and l.nx >= 4 and (dim == 1 or (l.ny % 2 == 0 and l.ny >= 4))
         can_t = l.N % 2 == 0
@@ -237,7 +250,7 @@ def rhs(levels, u0):
 
 def solve(prob, u0, rtol=1e-12, max_cycles=200, **kw):
     """V-cycles from a zero initial guess until ||b - A U|| <= rtol ||b||."""
-    hk = {k: kw.pop(k) for k in ("coarsen", "mu_crit", "min_coarse", "max_levels") if k in kw}
+    hk = {k: kw.pop(k) for k in ("coarsen", "mu_crit", "min_coarse", "max_levels", "fft_coarse") if k in kw}
     levels, kinds = hierarchy(prob, **hk)
     f = rhs(levels, u0)
     U = np.zeros(levels[0].shape)

@@ -1,0 +1,568 @@
+// Exact coarsest-level solve by discrete Fourier diagonalization (periodic
+// grids, constant reaction).  With periodic boundaries every slab matrix
+// K (x) I + diag(dt b) (x) (-Lap + lambda) of Eq. (st_system) is diagonalized by
+// the 2D DFT of the plane: Fourier mode q = (kx, ky) sees the M x M matrix
+//   S_q = K + diag(dt b) (lambda_q + lambda),
+//   lambda_q = cx (2 - 2 cos(2 pi kx / nx)) + cy (2 - 2 cos(2 pi ky / ny)),
+// and the time coupling -cin (x) cout^T acts mode by mode as well.  So
+//   1. transform every plane of f (and u0) to Fourier space (k_fft_fwd),
+//   2. run the slab recurrence u_n = S_q^{-1} (f_n + cin (cout . u_{n-1}))
+//      per mode (k_fft_modes; u_{-1} enters as the transform of u0),
+//   3. transform back (k_fft_inv).
+// The transforms are direct DFTs with twiddles from a table (planes of at
+// most kFftMaxPlane points); all arithmetic is FP64 whatever the storage type.
+#include "kernels.hpp"
+
+namespace stmg {
+namespace {
+
+constexpr int kFftBlock = 256;
+
+#define STMG_DISPATCH_M_FFT(MACRO) \
+  switch (p.M) {                   \
+    case 1: MACRO(1); break;       \
+    case 2: MACRO(2); break;       \
+    case 3: MACRO(3); break;       \
+    case 4: MACRO(4); break;       \
+    case 5: MACRO(5); break;       \
+    case 6: MACRO(6); break;       \
+    case 7: MACRO(7); break;       \
+    case 8: MACRO(8); break;       \
+    default: return hipErrorInvalidValue; \
+  }
+
+// Twiddle table layout: tw[2 j] = cos(2 pi j / nx), tw[2 j + 1] = sin(2 pi j / nx)
+// for j < nx, then the same for ny (2D).  nx + ny <= kFftMaxPlane + 1 whenever
+// nx ny <= kFftMaxPlane with both >= 1, so 2 (kFftMaxPlane + 1) entries hold it.
+constexpr int kTwMax = 2 * (kFftMaxPlane + 1);
+
+// f (T, [N][M][P], may be null) and u0 (FP64 [P], may be null) to Fourier
+// space: out[pl][ky][kx] complex (re, im interleaved), planes pl < N M, then
+// the u0 plane at index N M when u0 is given.
+template <typename T>
+__global__ __launch_bounds__(kFftBlock) void k_fft_fwd(int nx, int ny, int nplanes,
+                                                       const T* __restrict__ f,
+                                                       const double* __restrict__ u0,
+                                                       const double* __restrict__ tw,
+                                                       double* __restrict__ out) {
+  __shared__ double X[kFftMaxPlane];
+  __shared__ double A[2 * kFftMaxPlane];
+  __shared__ double W[kTwMax];
+  const int P = nx * ny;
+  const int pl = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int ntw = 2 * (nx + (ny > 1 ? ny : 0));
+  for (int i = tid; i < ntw; i += kFftBlock) W[i] = tw[i];
+  if (pl < nplanes) {
+    for (int q = tid; q < P; q += kFftBlock) X[q] = f ? (double)f[(size_t)pl * P + q] : 0.0;
+  } else {
+    for (int q = tid; q < P; q += kFftBlock) X[q] = u0[q];
+  }
+  __syncthreads();
+  const double* Wx = W;
+  const double* Wy = W + 2 * nx;
+  // along x: A[y][kx] = sum_x X[y][x] exp(-i 2 pi kx x / nx)
+  for (int idx = tid; idx < P; idx += kFftBlock) {
+    const int y = idx / nx, kx = idx - y * nx;
+    double re = 0.0, im = 0.0;
+    int j = 0;
+    for (int x = 0; x < nx; ++x) {
+      const double v = X[y * nx + x];
+      re += v * Wx[2 * j];
+      im -= v * Wx[2 * j + 1];
+      j += kx;
+      if (j >= nx) j -= nx;
+    }
+    A[2 * idx] = re;
+    A[2 * idx + 1] = im;
+  }
+  __syncthreads();
+  double* o = out + (size_t)pl * 2 * P;
+  if (ny == 1) {
+    for (int idx = tid; idx < P; idx += kFftBlock) {
+      o[2 * idx] = A[2 * idx];
+      o[2 * idx + 1] = A[2 * idx + 1];
+    }
+    return;
+  }
+  // along y: F[ky][kx] = sum_y A[y][kx] exp(-i 2 pi ky y / ny)
+  for (int idx = tid; idx < P; idx += kFftBlock) {
+    const int ky = idx / nx, kx = idx - ky * nx;
+    double re = 0.0, im = 0.0;
+    int j = 0;
+    for (int y = 0; y < ny; ++y) {
+      const double ar = A[2 * (y * nx + kx)], ai = A[2 * (y * nx + kx) + 1];
+      const double c = Wy[2 * j], s = Wy[2 * j + 1];
+      re += ar * c + ai * s;
+      im += ai * c - ar * s;
+      j += ky;
+      if (j >= ny) j -= ny;
+    }
+    o[2 * idx] = re;
+    o[2 * idx + 1] = im;
+  }
+}
+
+// Radix-2 forms of the two transforms for power-of-two nx and ny: iterative
+// decimation-in-time butterflies in LDS (log2 nx + log2 ny stages instead of
+// nx + ny multiply-adds per value).  Same results as the direct DFTs up to
+// rounding.
+__device__ __forceinline__ int bitrev(int i, int lg) { return lg ? (int)(__brev((unsigned)i) >> (32 - lg)) : 0; }
+
+// In-place butterflies along one dimension of the complex array A: `rows`
+// lines of length n (power of two), element (r, i) at A + 2 (r * rs + i * es);
+// input in bit-reversed order along the line; W holds cos, sin of 2 pi k / n;
+// sgn = -1 forward, +1 inverse.
+__device__ __forceinline__ void butterflies(double* A, int rows, int n, int rs, int es, const double* W,
+                                            double sgn) {
+  const int hn = n >> 1;
+  for (int len = 2; len <= n; len <<= 1) {
+    const int half = len >> 1, step = n / len;
+    for (int b = threadIdx.x; b < rows * hn; b += kFftBlock) {
+      const int r = b / hn, k = b - r * hn;
+      const int g = k / half, j = k - g * half;
+      const int i0 = g * len + j, i1 = i0 + half;
+      const double c = W[2 * (j * step)], sn = sgn * W[2 * (j * step) + 1];
+      double* p0 = A + 2 * (r * rs + i0 * es);
+      double* p1 = A + 2 * (r * rs + i1 * es);
+      const double ar = p1[0], ai = p1[1];
+      const double tr = c * ar - sn * ai, ti = c * ai + sn * ar;
+      const double br = p0[0], bi = p0[1];
+      p1[0] = br - tr;
+      p1[1] = bi - ti;
+      p0[0] = br + tr;
+      p0[1] = bi + ti;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftBlock) void k_fft_fwd2(int nx, int ny, int lgx, int lgy, int nplanes,
+                                                        const T* __restrict__ f,
+                                                        const double* __restrict__ u0,
+                                                        const double* __restrict__ tw,
+                                                        double* __restrict__ out) {
+  __shared__ double A[2 * kFftMaxPlane];
+  __shared__ double B[2 * kFftMaxPlane];
+  __shared__ double W[kTwMax];
+  const int P = nx * ny;
+  const int pl = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int ntw = 2 * (nx + (ny > 1 ? ny : 0));
+  for (int i = tid; i < ntw; i += kFftBlock) W[i] = tw[i];
+  // A[y][x] = X[y][bitrev(x)] (P <= kFftMaxPlane: at most 4 values per thread,
+  // all loaded before the LDS writes)
+  constexpr int kPer = kFftMaxPlane / kFftBlock;
+  double v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int q = u * kFftBlock + tid;
+    v[u] = 0.0;
+    if (q < P) {
+      const int y = q / nx, x = q - y * nx;
+      const int src = y * nx + bitrev(x, lgx);
+      if (pl < nplanes) v[u] = f ? (double)f[(size_t)pl * P + src] : 0.0;
+      else v[u] = u0[src];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int q = u * kFftBlock + tid;
+    if (q < P) {
+      A[2 * q] = v[u];
+      A[2 * q + 1] = 0.0;
+    }
+  }
+  __syncthreads();
+  butterflies(A, ny, nx, nx, 1, W, -1.0);
+  double* o = out + (size_t)pl * 2 * P;
+  if (ny == 1) {
+    for (int i = tid; i < 2 * P; i += kFftBlock) o[i] = A[i];
+    return;
+  }
+  // B[y][x] = A[bitrev(y)][x], then butterflies along y
+  for (int q = tid; q < P; q += kFftBlock) {
+    const int y = q / nx, x = q - y * nx;
+    const int src = bitrev(y, lgy) * nx + x;
+    B[2 * q] = A[2 * src];
+    B[2 * q + 1] = A[2 * src + 1];
+  }
+  __syncthreads();
+  butterflies(B, nx, ny, 1, nx, W + 2 * nx, -1.0);
+  for (int i = tid; i < 2 * P; i += kFftBlock) o[i] = B[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftBlock) void k_fft_inv2(int nx, int ny, int lgx, int lgy,
+                                                        const double* __restrict__ F,
+                                                        const double* __restrict__ tw,
+                                                        T* __restrict__ U) {
+  __shared__ double A[2 * kFftMaxPlane];
+  __shared__ double B[2 * kFftMaxPlane];
+  __shared__ double W[kTwMax];
+  const int P = nx * ny;
+  const int pl = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int ntw = 2 * (nx + (ny > 1 ? ny : 0));
+  for (int i = tid; i < ntw; i += kFftBlock) W[i] = tw[i];
+  const double* src = F + (size_t)pl * 2 * P;
+  constexpr int kPer = kFftMaxPlane / kFftBlock;
+  if (ny > 1) {
+    // B[ky][kx] = F[bitrev(ky)][kx], butterflies along y
+    double vr[kPer], vi[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int q = u * kFftBlock + tid;
+      if (q < P) {
+        const int y = q / nx, x = q - y * nx;
+        const int s2 = bitrev(y, lgy) * nx + x;
+        vr[u] = src[2 * s2];
+        vi[u] = src[2 * s2 + 1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int q = u * kFftBlock + tid;
+      if (q < P) {
+        B[2 * q] = vr[u];
+        B[2 * q + 1] = vi[u];
+      }
+    }
+    __syncthreads();
+    butterflies(B, nx, ny, 1, nx, W + 2 * nx, 1.0);
+    // A[y][kx] = B[y][bitrev(kx)]
+    for (int q = tid; q < P; q += kFftBlock) {
+      const int y = q / nx, x = q - y * nx;
+      const int s2 = y * nx + bitrev(x, lgx);
+      A[2 * q] = B[2 * s2];
+      A[2 * q + 1] = B[2 * s2 + 1];
+    }
+  } else {
+    double vr[kPer], vi[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int q = u * kFftBlock + tid;
+      if (q < P) {
+        const int s2 = bitrev(q, lgx);
+        vr[u] = src[2 * s2];
+        vi[u] = src[2 * s2 + 1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int q = u * kFftBlock + tid;
+      if (q < P) {
+        A[2 * q] = vr[u];
+        A[2 * q + 1] = vi[u];
+      }
+    }
+  }
+  __syncthreads();
+  butterflies(A, ny, nx, nx, 1, W, 1.0);
+  const double scale = 1.0 / (double)P;
+  T* dst = U + (size_t)pl * P;
+  for (int q = tid; q < P; q += kFftBlock) dst[q] = (T)(A[2 * q] * scale);
+}
+
+// Per-mode slab recurrence in Fourier space, in place on F ([N][M][P]
+// complex): u_n = Sinv_q (F_n + cin p), p = cout . u_n, starting from
+// p = (transform of u0)(q) when u0F is given, else 0.  Sinv: [P][M][M] real.
+// Slabs go in groups of kFftGroup whose loads are issued together.
+constexpr int kFftGroup = 8;
+template <int M>
+__global__ __launch_bounds__(kFftBlock) void k_fft_modes(int P, int N, double* __restrict__ F,
+                                                         const double* __restrict__ u0F,
+                                                         const double* __restrict__ Sinv,
+                                                         const OpParams p) {
+  const int q = blockIdx.x * kFftBlock + threadIdx.x;
+  if (q >= P) return;
+  double S[M][M];
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j < M; ++j) S[i][j] = Sinv[((size_t)q * M + i) * M + j];
+  double pr = 0.0, pi = 0.0;
+  if (u0F) {
+    pr = u0F[2 * q];
+    pi = u0F[2 * q + 1];
+  }
+  for (int n0 = 0; n0 < N; n0 += kFftGroup) {
+    double vr[kFftGroup][M], vi[kFftGroup][M];
+#pragma unroll
+    for (int g = 0; g < kFftGroup; ++g) {
+      if (n0 + g < N) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          const size_t at = 2 * (((size_t)(n0 + g) * M + m) * P + q);
+          vr[g][m] = F[at];
+          vi[g][m] = F[at + 1];
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < kFftGroup; ++g) {
+      if (n0 + g < N) {
+        double ur[M], ui[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          vr[g][i] += p.cin[i] * pr;
+          vi[g][i] += p.cin[i] * pi;
+        }
+        double nr = 0.0, ni = 0.0;
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          double sr = 0.0, si = 0.0;
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            sr += S[i][j] * vr[g][j];
+            si += S[i][j] * vi[g][j];
+          }
+          ur[i] = sr;
+          ui[i] = si;
+          nr += p.cout[i] * sr;
+          ni += p.cout[i] * si;
+        }
+        pr = nr;
+        pi = ni;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          const size_t at = 2 * (((size_t)(n0 + g) * M + m) * P + q);
+          F[at] = ur[m];
+          F[at + 1] = ui[m];
+        }
+      }
+    }
+  }
+}
+
+// The same recurrence with the workgroup's MB modes staged in LDS for every
+// slab.  With c = cout^T S_q, beta = c . cin and d = S_q cin the coupling
+// values obey the scalar recurrence
+//   p_n = c . F_n + beta p_{n-1},
+// so every M-vector product runs in parallel over (slab, mode) and only the
+// scalar chain is sequential: (A) a_n = c . F_n, (B) p_n = a_n + beta p_{n-1}
+// per mode, (C) u_n = S_q F_n + d p_{n-1}.  Used when the workgroup's
+// N (M + 2) MB complex values fit in kFftLds.
+constexpr int kFftLds = 48 * 1024;
+constexpr int kStage = 16;
+template <int M>
+__global__ __launch_bounds__(kFftBlock) void k_fft_modes_lds(int P, int N, int MB, double* __restrict__ F,
+                                                             const double* __restrict__ u0F,
+                                                             const double* __restrict__ Sinv,
+                                                             const OpParams p) {
+  __shared__ double L[kFftLds / sizeof(double)];
+  const int q0 = blockIdx.x * MB;
+  const int mb = min(MB, P - q0);
+  const int tid = threadIdx.x;
+  const int tot = N * M * mb;
+  double* Lf = L;                          // [(n M + m) MB + qq] complex
+  double* La = L + 2 * (size_t)N * M * MB;  // [n MB + qq] complex: a_n, then p_{n-1}
+  // stage F (loads in batches, all in flight before the LDS writes)
+  for (int i0 = 0; i0 < tot; i0 += kFftBlock * kStage) {
+    double re[kStage], im[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int i = i0 + u * kFftBlock + tid;
+      if (i < tot) {
+        const int nm = i / mb, qq = i - nm * mb;
+        const size_t at = 2 * ((size_t)nm * P + q0 + qq);
+        re[u] = F[at];
+        im[u] = F[at + 1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int i = i0 + u * kFftBlock + tid;
+      if (i < tot) {
+        const int nm = i / mb, qq = i - nm * mb;
+        Lf[2 * (nm * MB + qq)] = re[u];
+        Lf[2 * (nm * MB + qq) + 1] = im[u];
+      }
+    }
+  }
+  __syncthreads();
+  // (A) a_n = c . F_n
+  for (int i = tid; i < N * mb; i += kFftBlock) {
+    const int n = i / mb, qq = i - n * mb;
+    const double* S = Sinv + (size_t)(q0 + qq) * M * M;
+    double ar = 0.0, ai = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double c = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) c += p.cout[k] * S[k * M + j];
+      const int at = 2 * ((n * M + j) * MB + qq);
+      ar += c * Lf[at];
+      ai += c * Lf[at + 1];
+    }
+    La[2 * (n * MB + qq)] = ar;
+    La[2 * (n * MB + qq) + 1] = ai;
+  }
+  __syncthreads();
+  // (B) per mode: La[n] <- p_{n-1} (the coupling value entering slab n)
+  if (tid < mb) {
+    const double* S = Sinv + (size_t)(q0 + tid) * M * M;
+    double beta = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double c = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) c += p.cout[k] * S[k * M + j];
+      beta += c * p.cin[j];
+    }
+    double pr = 0.0, pi = 0.0;
+    if (u0F) {
+      pr = u0F[2 * (q0 + tid)];
+      pi = u0F[2 * (q0 + tid) + 1];
+    }
+    for (int n = 0; n < N; ++n) {
+      const int at = 2 * (n * MB + tid);
+      const double ar = La[at], ai = La[at + 1];
+      La[at] = pr;
+      La[at + 1] = pi;
+      pr = ar + beta * pr;
+      pi = ai + beta * pi;
+    }
+  }
+  __syncthreads();
+  // (C) u_n = S_q F_n + d p_{n-1}, in place in Lf
+  for (int i = tid; i < N * mb; i += kFftBlock) {
+    const int n = i / mb, qq = i - n * mb;
+    const double* S = Sinv + (size_t)(q0 + qq) * M * M;
+    const double pr = La[2 * (n * MB + qq)], pi = La[2 * (n * MB + qq) + 1];
+    double fr[M], fi[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int at = 2 * ((n * M + j) * MB + qq);
+      fr[j] = Lf[at];
+      fi[j] = Lf[at + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      double sr = 0.0, si = 0.0, dk = 0.0;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        sr += S[k * M + j] * fr[j];
+        si += S[k * M + j] * fi[j];
+        dk += S[k * M + j] * p.cin[j];
+      }
+      const int at = 2 * ((n * M + k) * MB + qq);
+      Lf[at] = sr + dk * pr;
+      Lf[at + 1] = si + dk * pi;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < tot; i += kFftBlock) {
+    const int nm = i / mb, qq = i - nm * mb;
+    const size_t at = 2 * ((size_t)nm * P + q0 + qq);
+    F[at] = Lf[2 * (nm * MB + qq)];
+    F[at + 1] = Lf[2 * (nm * MB + qq) + 1];
+  }
+}
+
+// Back to physical space: U[pl][y][x] = Re (1/P) sum F[pl][ky][kx] exp(+i ...).
+template <typename T>
+__global__ __launch_bounds__(kFftBlock) void k_fft_inv(int nx, int ny, const double* __restrict__ F,
+                                                       const double* __restrict__ tw,
+                                                       T* __restrict__ U) {
+  __shared__ double B[2 * kFftMaxPlane];
+  __shared__ double A[2 * kFftMaxPlane];
+  __shared__ double W[kTwMax];
+  const int P = nx * ny;
+  const int pl = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int ntw = 2 * (nx + (ny > 1 ? ny : 0));
+  for (int i = tid; i < ntw; i += kFftBlock) W[i] = tw[i];
+  const double* src = F + (size_t)pl * 2 * P;
+  for (int i = tid; i < 2 * P; i += kFftBlock) B[i] = src[i];
+  __syncthreads();
+  const double* Wx = W;
+  const double* Wy = W + 2 * nx;
+  const double* R = B;
+  if (ny > 1) {
+    // along y: A[y][kx] = sum_ky B[ky][kx] exp(+i 2 pi ky y / ny)
+    for (int idx = tid; idx < P; idx += kFftBlock) {
+      const int y = idx / nx, kx = idx - y * nx;
+      double re = 0.0, im = 0.0;
+      int j = 0;
+      for (int ky = 0; ky < ny; ++ky) {
+        const double br = B[2 * (ky * nx + kx)], bi = B[2 * (ky * nx + kx) + 1];
+        const double c = Wy[2 * j], s = Wy[2 * j + 1];
+        re += br * c - bi * s;
+        im += bi * c + br * s;
+        j += y;
+        if (j >= ny) j -= ny;
+      }
+      A[2 * idx] = re;
+      A[2 * idx + 1] = im;
+    }
+    __syncthreads();
+    R = A;
+  }
+  // along x, real part only: U[y][x] = (1/P) Re sum_kx R[y][kx] exp(+i 2 pi kx x / nx)
+  const double scale = 1.0 / (double)P;
+  T* dst = U + (size_t)pl * P;
+  for (int idx = tid; idx < P; idx += kFftBlock) {
+    const int y = idx / nx, x = idx - y * nx;
+    double re = 0.0;
+    int j = 0;
+    for (int kx = 0; kx < nx; ++kx) {
+      re += R[2 * (y * nx + kx)] * Wx[2 * j] - R[2 * (y * nx + kx) + 1] * Wx[2 * j + 1];
+      j += x;
+      if (j >= nx) j -= nx;
+    }
+    dst[idx] = (T)(re * scale);
+  }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_fft_coarse(const OpParams& p, const double* Sinv, const double* tw, double* work,
+                             const T* f, const double* u0, T* U, hipStream_t s) {
+  const int P = p.nx * p.ny;
+  if (P > kFftMaxPlane || p.M < 1 || p.M > kMaxM) return hipErrorInvalidValue;
+  const int planes = p.N * p.M;
+  double* u0F = u0 ? work + (size_t)2 * planes * P : nullptr;
+  auto lg2 = [](int n) { int l = 0; while ((1 << l) < n) ++l; return (1 << l) == n ? l : -1; };
+  const int lgx = lg2(p.nx), lgy = lg2(p.ny);
+  const bool pow2 = lgx >= 0 && lgy >= 0;
+  if (pow2)
+    hipLaunchKernelGGL((k_fft_fwd2<T>), dim3(planes + (u0 ? 1 : 0)), dim3(kFftBlock), 0, s, p.nx, p.ny,
+                       lgx, lgy, planes, f, u0, tw, work);
+  else
+    hipLaunchKernelGGL((k_fft_fwd<T>), dim3(planes + (u0 ? 1 : 0)), dim3(kFftBlock), 0, s, p.nx, p.ny,
+                       planes, f, u0, tw, work);
+  // modes per workgroup for the LDS-staged recurrence (at most 64, at least 4)
+  const long long per_mode = (long long)p.N * (p.M + 2) * 2 * sizeof(double);
+  int MB = (int)(kFftLds / per_mode);
+  if (MB > 64) MB = 64;
+  if (MB >= 4) {
+    const int gb = (P + MB - 1) / MB;
+#define L(MM)                                                                                       \
+  hipLaunchKernelGGL((k_fft_modes_lds<MM>), dim3(gb), dim3(kFftBlock), 0, s, P, p.N, MB, work, u0F, \
+                     Sinv, p)
+    STMG_DISPATCH_M_FFT(L)
+#undef L
+  } else {
+    const int gb = (P + kFftBlock - 1) / kFftBlock;
+#define L(MM)                                                                                    \
+  hipLaunchKernelGGL((k_fft_modes<MM>), dim3(gb), dim3(kFftBlock), 0, s, P, p.N, work, u0F, Sinv, p)
+    STMG_DISPATCH_M_FFT(L)
+#undef L
+  }
+  if (pow2)
+    hipLaunchKernelGGL((k_fft_inv2<T>), dim3(planes), dim3(kFftBlock), 0, s, p.nx, p.ny, lgx, lgy, work,
+                       tw, U);
+  else
+    hipLaunchKernelGGL((k_fft_inv<T>), dim3(planes), dim3(kFftBlock), 0, s, p.nx, p.ny, work, tw, U);
+  return hipGetLastError();
+}
+
+template hipError_t launch_fft_coarse<double>(const OpParams&, const double*, const double*, double*,
+                                              const double*, const double*, double*, hipStream_t);
+template hipError_t launch_fft_coarse<float>(const OpParams&, const double*, const double*, double*,
+                                             const float*, const double*, float*, hipStream_t);
+
+}  // namespace stmg

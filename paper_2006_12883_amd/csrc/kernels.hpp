@@ -103,6 +103,16 @@ template <typename T>
 hipError_t launch_coarse_solve(const OpParams& p, const double* Ainv, const T* f,
                                const double* u0, T* U, hipStream_t s);
 
+// Exact coarsest solve by 2D discrete Fourier diagonalization (periodic
+// grids, constant reaction, planes of at most kFftMaxPlane points): Sinv holds
+// per mode q the M x M inverse of K + diag(db) (lambda_q + lam) ([P][M][M]),
+// tw the twiddles cos, sin of 2 pi j / nx (j < nx) then of 2 pi j / ny, work
+// 2 (N M + 1) P doubles.  f may be null (zero), u0 enters slab 0 if given.
+constexpr int kFftMaxPlane = 1024;
+template <typename T>
+hipError_t launch_fft_coarse(const OpParams& p, const double* Sinv, const double* tw, double* work,
+                             const T* f, const double* u0, T* U, hipStream_t s);
+
 // Coarsest solve with a different slab matrix per slab: the K x K slab
 // matrices (K = M nx ny) are built from the per-DOF coefficient and factored
 // in the kernel (dense LU, one workgroup), then the slabs are solved in order.

@@ -69,7 +69,7 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   }
   if (o->chunk < 1 || o->chunk_coarse < 1 || o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1 ||
       o->max_levels < 1 || o->max_cycles < 1 || !(o->rtol > 0.0) || !(o->omega > 0.0) ||
-      o->inner_cycles < 1) {
+      o->inner_cycles < 1 || o->fft_coarse < 0) {
     set_error("invalid options");
     return STMG_EINVAL;
   }
@@ -92,9 +92,16 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   L.N = p->N;
   L.dt = p->dt;
   lv.push_back(L);
+  // Periodic grids with a constant reaction can stop at a larger coarsest
+  // level: its exact solve by Fourier diagonalization costs two small DFTs
+  // per plane, while the levels below it would be latency-bound launches.
+  const bool fft_ok = p->bc == STMG_BC_PERIODIC && !allen_cahn && !batch_member;
   while (static_cast<int>(lv.size()) < o->max_levels) {
     Level& c = lv.back();
     if (static_cast<long long>(M) * c.nx * c.ny * c.N <= o->min_coarse) break;
+    if (fft_ok && lv.size() > 1 && c.nx * c.ny <= kFftMaxPlane &&
+        static_cast<long long>(M) * c.nx * c.ny * c.N <= o->fft_coarse)
+      break;
     const int q = batch_member ? 4 : 2;
     const bool cs_x = (c.ex % q == 0) && c.ex >= 4;
     const bool cs_y = !twod || ((c.ey % q == 0) && c.ey >= 4);
@@ -127,7 +134,8 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   }
   const Level& last = lv.back();
   const long long Kc = static_cast<long long>(M) * last.nx * last.ny;
-  if (Kc > 1024) {
+  fft = fft_ok && last.nx * last.ny <= kFftMaxPlane;
+  if (!fft && Kc > 1024) {
     set_error("coarsest level has more than 1024 unknowns per slab");
     return STMG_EUNSUPPORTED;
   }
@@ -299,8 +307,16 @@ size_t Solver::plan(char* ws) {
   scal = pl.take<double>(32);
   const Level& c = lv.back();
   const size_t K = static_cast<size_t>(prob.M) * c.nx * c.ny;
-  Ainv = pl.take<double>(K * K);
-  AinvT = pl.take<double>(K * K);
+  if (fft) {
+    const size_t Pc = static_cast<size_t>(c.nx) * c.ny;
+    fft_sinv = pl.take<double>(Pc * prob.M * prob.M);
+    fft_sinvT = pl.take<double>(Pc * prob.M * prob.M);
+    fft_tw = pl.take<double>(2 * (static_cast<size_t>(c.nx) + c.ny));
+    fft_work = pl.take<double>(2 * (static_cast<size_t>(c.N) * prob.M + 1) * Pc);
+  } else {
+    Ainv = pl.take<double>(K * K);
+    AinvT = pl.take<double>(K * K);
+  }
   coarse_scratch = allen_cahn ? pl.take<double>(K * K) : nullptr;
   lw = pl.take<double>(kMaxM);
   if (!sdcn.empty()) {
@@ -314,19 +330,53 @@ size_t Solver::plan(char* ws) {
   return pl.off + 256;
 }
 
-int Solver::upload() {
-  if (win) {
-    win->stream = stream;
-    int rc = win->upload();
-    if (rc) return rc;
-    if (win_last) {
-      win_last->stream = stream;
-      rc = win_last->upload();
-      if (rc) return rc;
+// Tables of the Fourier coarsest solve: per mode q = (kx, ky) the inverses of
+// Kq + diag(dt b) (lambda_q + lambda) and of its transpose (the transposed
+// problem), lambda_q = cx (2 - 2 cos(2 pi kx / nx)) + cy (2 - 2 cos(2 pi ky / ny)),
+// in long double; the DFT twiddles cos, sin of 2 pi j / n.
+int Solver::upload_fft() {
+  const Level& c = lv.back();
+  const int M = prob.M, nx = c.nx, ny = c.ny, P = nx * ny;
+  const long double twopi = 6.283185307179586476925286766559L;
+  const OpParams& op = c.op;
+  std::vector<double> S(static_cast<size_t>(P) * M * M), ST(static_cast<size_t>(P) * M * M);
+  std::vector<long double> a(static_cast<size_t>(M) * M);
+  for (int ky = 0; ky < ny; ++ky)
+    for (int kx = 0; kx < nx; ++kx) {
+      const int q = ky * nx + kx;
+      long double lq = static_cast<long double>(op.cx) * (2.0L - 2.0L * std::cos(twopi * kx / nx));
+      if (ny > 1) lq += static_cast<long double>(op.cy) * (2.0L - 2.0L * std::cos(twopi * ky / ny));
+      for (int tr = 0; tr < 2; ++tr) {
+        for (int i = 0; i < M; ++i)
+          for (int j = 0; j < M; ++j) {
+            long double v = tr ? tab.Kq[j][i] : tab.Kq[i][j];
+            if (i == j) v += c.dt * tab.b[i] * (lq + static_cast<long double>(op.lam));
+            a[static_cast<size_t>(i) * M + j] = v;
+          }
+        if (!invert_ld(a, M)) { set_error("singular Fourier mode matrix"); return STMG_EINVAL; }
+        double* dst = (tr ? ST.data() : S.data()) + static_cast<size_t>(q) * M * M;
+        for (int i = 0; i < M * M; ++i) dst[i] = static_cast<double>(a[i]);
+      }
     }
-    return STMG_OK;
+  std::vector<double> tw(2 * (static_cast<size_t>(nx) + ny));
+  for (int j = 0; j < nx; ++j) {
+    tw[2 * j] = static_cast<double>(std::cos(twopi * j / nx));
+    tw[2 * j + 1] = static_cast<double>(std::sin(twopi * j / nx));
   }
-  // Coarsest slab matrix: K (x) I + diag(db) (x) (-Lap + lambda), inverted.
+  for (int j = 0; j < ny; ++j) {
+    tw[2 * (nx + j)] = static_cast<double>(std::cos(twopi * j / ny));
+    tw[2 * (nx + j) + 1] = static_cast<double>(std::sin(twopi * j / ny));
+  }
+  HIP_CHECK(hipMemcpyAsync(fft_sinv, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIP_CHECK(hipMemcpyAsync(fft_sinvT, ST.data(), ST.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIP_CHECK(hipMemcpyAsync(fft_tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIP_CHECK(hipStreamSynchronize(stream));  // host vectors go out of scope
+  return STMG_OK;
+}
+
+// Dense inverse of the coarsest slab matrix K (x) I + diag(db) (x) (-Lap + lambda)
+// (and its transpose, for the transposed problem), in long double.
+int Solver::upload_dense() {
   const Level& c = lv.back();
   const int M = prob.M, P = c.nx * c.ny, K = M * P;
   std::vector<long double> A(static_cast<size_t>(K) * K, 0.0L);
@@ -357,6 +407,27 @@ int Solver::upload() {
     }
   HIP_CHECK(hipMemcpyAsync(Ainv, Ad.data(), Ad.size() * sizeof(double), hipMemcpyHostToDevice, stream));
   HIP_CHECK(hipMemcpyAsync(AinvT, AdT.data(), AdT.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIP_CHECK(hipStreamSynchronize(stream));  // host vectors go out of scope
+  return STMG_OK;
+}
+
+int Solver::upload() {
+  if (win) {
+    win->stream = stream;
+    int rc = win->upload();
+    if (rc) return rc;
+    if (win_last) {
+      win_last->stream = stream;
+      rc = win_last->upload();
+      if (rc) return rc;
+    }
+    return STMG_OK;
+  }
+  const int M = prob.M;
+  {
+    const int rc = fft ? upload_fft() : upload_dense();
+    if (rc) return rc;
+  }
   double w[kMaxM] = {0};
   for (int i = 0; i < M; ++i) w[i] = static_cast<double>(tab.l0[i]);
   HIP_CHECK(hipMemcpyAsync(lw, w, sizeof(w), hipMemcpyHostToDevice, stream));
@@ -433,6 +504,7 @@ hipError_t Solver::coarse(bool adj, int react, const T* f, const double* u0, T* 
   const OpParams& op = adj ? C.opT : C.op;
   if (react == REACT_COEF)
     return launch_coarse_solve_coef<T>(op, coef_of<T>(C), coarse_scratch, f, u0, U, stream);
+  if (fft) return launch_fft_coarse<T>(op, adj ? fft_sinvT : fft_sinv, fft_tw, fft_work, f, u0, U, stream);
   return launch_coarse_solve<T>(op, adj ? AinvT : Ainv, f, u0, U, stream);
 }
 

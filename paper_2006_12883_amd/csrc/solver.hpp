@@ -84,6 +84,13 @@ struct Solver {
   double* Ainv = nullptr;   // coarsest slab inverse (forward)
   double* AinvT = nullptr;  // (transposed problem)
   double* coarse_scratch = nullptr;  // dense slab matrix for the Newton coarsest solve
+  // Coarsest level solved by Fourier diagonalization (periodic grids, constant
+  // reaction): per-mode M x M inverses, twiddles, complex workspace.
+  bool fft = false;
+  double* fft_sinv = nullptr;   // [P][M][M] (forward problem)
+  double* fft_sinvT = nullptr;  // (transposed problem)
+  double* fft_tw = nullptr;
+  double* fft_work = nullptr;   // 2 (N M + 1) P
   double* delta64 = nullptr;  // Newton correction / adjoint multiplier (level 0, FP64)
   double* lw = nullptr;       // M weights l(0) on the device (gradient of u0)
   // statistics of the last solve
@@ -129,6 +136,8 @@ struct Solver {
   int build(const stmg_problem* p, const stmg_options* o);
   size_t plan(char* ws);  // lays out (or sizes, ws = nullptr) the workspace
   int upload();           // copies tables into the workspace
+  int upload_fft();       // tables of the Fourier coarsest solve
+  int upload_dense();     // dense inverse of the coarsest slab matrix
 
   int chunk_of(int l) const;        // smoother block length on level l
   int transfer_slabs(int l) const;  // slabs per thread in transfer kernels

@@ -47,11 +47,17 @@ def test_residual_matches_allatonce(name, prob):
     assert abs(nrm - np.linalg.norm(ref)) <= 1e-12 * np.linalg.norm(ref)
 
 
+# fft_coarse: the default coarsest-level rule, and 0 (deep hierarchies down to
+# a few dozen unknowns, which exercise every transfer kind on small grids)
+FFT = [262144, 0]
+
+
 @pytest.mark.parametrize("name,prob", CASES)
-def test_hierarchy_matches_oracle(name, prob):
-    print("case", name, flush=True)
-    levels, kinds = mg.hierarchy(prob)
-    got = H(prob).levels()
+@pytest.mark.parametrize("fft", FFT)
+def test_hierarchy_matches_oracle(name, prob, fft):
+    print("case", name, fft, flush=True)
+    levels, kinds = mg.hierarchy(prob, fft_coarse=fft)
+    got = H(prob, fft_coarse=fft).levels()
     assert len(got) == len(levels)
     code = {"s": 1, "t": 2, "st": 3}
     for l, (g, o) in enumerate(zip(got, levels)):
@@ -64,8 +70,8 @@ def test_hierarchy_matches_oracle(name, prob):
 @pytest.mark.parametrize("zero", [False, True])
 def test_smoother_each_level(name, prob, zero):
     print("case", name, zero, flush=True)
-    levels, kinds = mg.hierarchy(prob)
-    h = H(prob)
+    levels, kinds = mg.hierarchy(prob, fft_coarse=0)
+    h = H(prob, fft_coarse=0)
     for l, lev in enumerate(levels):
         rng = np.random.default_rng(10 + l)
         U = np.zeros(lev.shape) if zero else rng.standard_normal(lev.shape)
@@ -79,8 +85,8 @@ def test_smoother_each_level(name, prob, zero):
 @pytest.mark.parametrize("name,prob", CASES)
 def test_restrict_prolong_each_level(name, prob):
     print("case", name, flush=True)
-    levels, kinds = mg.hierarchy(prob)
-    h = H(prob)
+    levels, kinds = mg.hierarchy(prob, fft_coarse=0)
+    h = H(prob, fft_coarse=0)
     for l in range(len(levels) - 1):
         lev, nxt = levels[l], levels[l + 1]
         rng = np.random.default_rng(20 + l)
@@ -98,10 +104,13 @@ def test_restrict_prolong_each_level(name, prob):
 
 
 @pytest.mark.parametrize("name,prob", CASES)
-def test_coarse_solve(name, prob):
-    print("case", name, flush=True)
-    levels, kinds = mg.hierarchy(prob)
-    h = H(prob)
+@pytest.mark.parametrize("fft", FFT)
+def test_coarse_solve(name, prob, fft):
+    """Fourier coarsest solve (default rule, periodic) or the dense one (deep
+    hierarchies) against the oracle's direct slab-by-slab solve."""
+    print("case", name, fft, flush=True)
+    levels, kinds = mg.hierarchy(prob, fft_coarse=fft)
+    h = H(prob, fft_coarse=fft)
     lev = levels[-1]
     f = np.random.default_rng(3).standard_normal(lev.shape)
     ref = lev.exact_solve(f)
@@ -111,14 +120,15 @@ def test_coarse_solve(name, prob):
 
 
 @pytest.mark.parametrize("name,prob", CASES)
-def test_one_vcycle_matches_oracle(name, prob):
-    print("case", name, flush=True)
-    levels, kinds = mg.hierarchy(prob)
+@pytest.mark.parametrize("fft", FFT)
+def test_one_vcycle_matches_oracle(name, prob, fft):
+    print("case", name, fft, flush=True)
+    levels, kinds = mg.hierarchy(prob, fft_coarse=fft)
     u0 = np.random.default_rng(4).standard_normal(levels[0].shape[2:])
     f = mg.rhs(levels, u0)
     U = np.random.default_rng(5).standard_normal(levels[0].shape)
     ref = mg.vcycle(levels, kinds, U.copy(), f)
-    h = H(prob)
+    h = H(prob, fft_coarse=fft)
     Ud = T(U)
     h.vcycle(T(u0), Ud)
     assert_close(Ud.cpu().numpy(), ref, 1e-11, "one V-cycle")

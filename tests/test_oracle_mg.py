@@ -46,7 +46,7 @@ def test_transfer_constants_and_linears():
 
 def test_hierarchy_auto_rule():
     prob = si.problem(2, 64, 3, 64, 1.0, nu=0.04, lam=1.0)  # mu = 2.56 on the finest level
-    levels, kinds = mg.hierarchy(prob)
+    levels, kinds = mg.hierarchy(prob, fft_coarse=0)
     assert kinds[0] == "s"            # mu = 2.56 >= 0.5: space first
     assert kinds[1] == "s"            # mu = 0.64 after one space step
     assert kinds[2] == "t"            # mu = 0.16
@@ -54,10 +54,26 @@ def test_hierarchy_auto_rule():
         mu = l.nu * l.dt / l.hx ** 2
         if k == "s":
             assert mu >= 0.5 or l.N % 2 == 1
-    l1, k1 = mg.hierarchy(prob, mu_crit=1.0)
+    l1, k1 = mg.hierarchy(prob, mu_crit=1.0, fft_coarse=0)
     assert k1[:2] == ["s", "t"]
     last = levels[-1]
     assert last.M * last.nx * last.ny * last.N <= 64
+
+
+def test_hierarchy_coarsest_rule():
+    """The coarsest level is the first level below the finest with planes of at
+    most 1024 points and at most fft_coarse unknowns (else the AUTO rule runs on)."""
+    prob = si.config("rd2d")                  # 256^2 x 3 x 256
+    levels, kinds = mg.hierarchy(prob)
+    assert kinds == ["s", "s", "t", "t", "s"]
+    last = levels[-1]
+    assert (last.nx, last.ny, last.N) == (32, 32, 64)
+    deep, dk = mg.hierarchy(prob, fft_coarse=0)
+    assert len(deep) == 15 and dk[:5] == kinds
+    # the finest level itself never stops the coarsening
+    small = si.problem(2, 16, 2, 4, 0.5, nu=0.02, lam=1.0)
+    lv, kk = mg.hierarchy(small)
+    assert len(lv) == 2
 
 
 @pytest.mark.parametrize("chunk", [1, 4, 16])
@@ -87,6 +103,7 @@ def test_exact_coarse_solve():
     ("rd2d-small", {"coarsen": "space"}),
     ("rd2d-small", {"coarsen": "spacetime"}),
     ("rd2d-small", {"chunk": 1}),
+    ("rd2d-small", {"fft_coarse": 0}),
 ])
 def test_vcycle_converges_to_stepper(name, kw):
     if name == "heat1d":
