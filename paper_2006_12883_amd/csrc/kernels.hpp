@@ -44,6 +44,10 @@ struct SweepPtrs {
   const T* coef;     // REACT_COEF: per-DOF reaction coefficient
   void* out;         // smoother: new iterate (T); residual: r (type TO), may be null
   double* part;      // per-block partial sums of ||f - A U||^2 (input iterate), may be null
+  // FP32 prolongation + smoothing only: when set, also up64_out = up64 + out
+  // in FP64 on the written points (the refinement update of mixed precision)
+  const double* up64 = nullptr;
+  double* up64_out = nullptr;
 };
 
 // Launchers return hipSuccess or the launch error.

@@ -1102,7 +1102,7 @@ __device__ __forceinline__ void load_blk_sum(const double* __restrict__ U, const
 // smoother chunk):
 //   U' = U + e                 (FP64 iterate plus FP32 correction, e may be null)
 //   r  = f - A U'              (FP64, per-block partial sums of r^2 in a.part)
-//   a.out <- U' (FP64), r32 <- (float) r  (the next correction equation's
+//   a.out <- U' (FP64, if a.out is set), r32 <- (float) r  (the next correction equation's
 //   right-hand side), and with e1 set that equation's first smoothing sweep
 //   from a zero iterate, in FP32: e1 = omega D^{-1} (r32 + cin (x) cout . d_prev).
 // The results equal those of the separate update, FP64 residual and FP32
@@ -1184,7 +1184,7 @@ __device__ __forceinline__ void refine_blk_body(const OpParams& p, const SweepPt
         }
         prev[k] = np;
       }
-      store_own<M, double, BY>(static_cast<double*>(a.out), base, P, nx, b, u);
+      if (a.out) store_own<M, double, BY>(static_cast<double*>(a.out), base, P, nx, b, u);
       store_own<M, float, BY>(r32, base, P, nx, b, rr);
       if (e1) {
         const Consts<M, float> c32(p);
@@ -2090,6 +2090,17 @@ __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const Swe
         dprev[k] = nd;
       }
       store_own<M, T, BY>(out, base, P, nx, b, o);
+      if constexpr (sizeof(T) == 4) {
+        if (a.up64) {
+          double v[NP][M];
+          load_own<M, double, BY>(a.up64, base, P, nx, b, v);
+#pragma unroll
+          for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int i = 0; i < M; ++i) v[k][i] = v[k][i] + (double)o[k][i];
+          store_own<M, double, BY>(a.up64_out, base, P, nx, b, v);
+        }
+      }
     }
   }
   if (a.part) {

@@ -323,7 +323,7 @@ hipError_t launch_prolong_smooth(const OpParams& p, int react, const SweepPtrs<T
   const int sl = slab_parallel_len(p.M, level_work(p), p.N, chunk);
   const int NP = twod ? 4 : 2;
   const size_t lds = (size_t)kBlock * NP * (p.M + 1 + (react == REACT_COEF ? p.M : 0)) * sizeof(T);
-  if (sl > 0 && a.part == nullptr && lds <= kSlabParallelLds) {
+  if (sl > 0 && a.part == nullptr && a.up64 == nullptr && lds <= kSlabParallelLds) {
     const int nbk = kBlock / sl;
     const int tiles = (plane_threads(p) + nbk - 1) / nbk;
     const int nb = tiles * ((p.N + sl - 1) / sl);

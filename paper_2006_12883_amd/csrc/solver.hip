@@ -514,6 +514,13 @@ hipError_t Solver::prolong_smooth(int l, bool adj, int react, const T* Uin, cons
   const Level& L = lv[l];
   const Level& C = lv[l + 1];
   SweepPtrs<T> a{Uin, f, u0, coef_of<T>(L), out, nullptr};
+  if constexpr (sizeof(T) == 4) {
+    if (l == 0 && up_in) {
+      a.up64 = up_in;
+      a.up64_out = up_out;
+      up_done = true;
+    }
+  }
   return launch_prolong_smooth<T>(adj ? L.opT : L.op, react, a, (L.kind & 1) != 0,
                                   (L.kind & 2) != 0, C.nx, C.ny, C.N, ec, chunk_of(l), stream);
 }
@@ -648,7 +655,9 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
       HIP_TRY(launch_smooth<double>(op0, react, a, chunk_of(0), stream));
       HIP_TRY(launch_sum_partials(part, smooth_blocks(op0, chunk_of(0)), scal, stream));
     } else if (refine) {
-      SweepPtrs<double> a{Ucur, f, u0, L0.coef64, Unext, part};
+      // U' = Ucur + ecur when the correction was not folded into the last
+      // FP32 kernel of the previous step (ecur set), else Ucur as it is
+      SweepPtrs<double> a{Ucur, f, u0, L0.coef64, ecur ? Unext : nullptr, part};
       e1 = (ecur == L0.A32) ? L0.B32 : L0.A32;
       int np = 0;
       if (smooth_blocks(op0, chunk_of(0)) > max_parts) {
@@ -720,8 +729,22 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
     } else {
       // FP32 V-cycles on A e = r: the first starts from the sweep already in
       // e1 (fused refinement) or from zero.
+      // With the fused refinement the last cycle's level-0 post-smoothing also
+      // writes Unext = Ucur + e in FP64 (up_in / up_out) when it is the fused
+      // prolongation kernel; otherwise the next refinement sweep adds e.
       float* res = nullptr;
       float* oth = (e1 == L0.A32) ? L0.B32 : L0.A32;
+      if (refine) {
+        // at the refinement sweep the iterate is Unext when it formed U' there
+        if (ecur) std::swap(Ucur, Unext);
+        ecur = nullptr;
+      }
+      struct UpScope {
+        Solver* s;
+        ~UpScope() { s->up_in = nullptr; s->up_out = nullptr; }
+      } up_scope{this};
+      up_done = false;
+      if (refine && inner == 1) { up_in = Ucur; up_out = Unext; }
       if (refine) HIP_CHECK(vcycle<float>(0, adj, react, e1, oth, L0.f32, nullptr, false, &res, 1));
       else HIP_CHECK(vcycle<float>(0, adj, react, L0.A32, L0.B32, L0.f32, nullptr, true, &res, 0));
       if (!res) break;
@@ -729,6 +752,7 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
       for (int k = 1; k < inner; ++k) {
         float* other = (res == L0.A32) ? L0.B32 : L0.A32;
         float* r2 = nullptr;
+        if (refine && k == inner - 1) { up_in = Ucur; up_out = Unext; }
         const auto g = std::move(gate0);
         gate0 = nullptr;
         const hipError_t e = vcycle<float>(0, adj, react, res, other, L0.f32, nullptr, false, &r2, 0);
@@ -737,9 +761,11 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
         res = r2;
         ++vc;
       }
+      up_in = nullptr;
+      up_out = nullptr;
       if (refine) {
-        std::swap(Ucur, Unext);
-        ecur = res;
+        if (up_done) std::swap(Ucur, Unext);  // Unext = Ucur + e is written
+        else ecur = res;                      // the next sweep forms Ucur + e
       } else {
         HIP_CHECK(launch_update<float>(L0.n, U, res, nullptr, stream));
       }
@@ -747,9 +773,12 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
     ++c;
     HIP_CHECK(launch_norm());
   }
-  // Fused refinement: the last refinement kernel wrote the final iterate to Unext.
-  if (refine && Unext != U)
-    HIP_CHECK(hipMemcpyAsync(U, Unext, L0.n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  // Fused refinement: the final iterate is the last refinement sweep's U',
+  // Unext when that sweep added the correction, else Ucur.
+  if (refine) {
+    double* fin = ecur ? Unext : Ucur;
+    if (fin != U) HIP_CHECK(hipMemcpyAsync(U, fin, L0.n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  }
   *cycles += vc;
   if (refinements) *refinements += mixed ? c : 0;
   *rel_out = rel;

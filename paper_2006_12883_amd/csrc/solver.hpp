@@ -102,6 +102,12 @@ struct Solver {
   // the device never idles while the host decides.
   HostScalar hnorm;
   std::function<hipError_t(bool*)> gate0;
+  // Mixed precision: when set, the level-0 FP32 prolongation + smoothing also
+  // writes up_out = up_in + (its FP32 result) in FP64 (the refinement update)
+  // and sets up_done.
+  const double* up_in = nullptr;
+  double* up_out = nullptr;
+  bool up_done = false;
 
   // Time windows (adjoint checkpointing).  When the options' memory budget
   // cannot hold the trajectory, the handle drives a sub-solver for W slabs
