@@ -648,12 +648,14 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
   double* Unext = L0.B64;
   const float* ecur = nullptr;
   float* e1 = L0.A32;
-  // Queues ||f - A U||^2 of the current iterate and its copy to the host.
+  // Queues ||f - A U||^2 of the current iterate, written straight into the
+  // pinned host slot, and an event behind it.
+  double* const out = hnorm.d;
   auto launch_norm = [&]() -> hipError_t {
     if (fused) {
       SweepPtrs<double> a{U, f, u0, L0.coef64, L0.B64, part};
       HIP_TRY(launch_smooth<double>(op0, react, a, chunk_of(0), stream));
-      HIP_TRY(launch_sum_partials(part, smooth_blocks(op0, chunk_of(0)), scal, stream));
+      HIP_TRY(launch_sum_partials(part, smooth_blocks(op0, chunk_of(0)), out, stream));
     } else if (refine) {
       // U' = Ucur + ecur when the correction was not folded into the last
       // FP32 kernel of the previous step (ecur set), else Ucur as it is
@@ -665,13 +667,12 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
         return hipErrorInvalidValue;
       }
       HIP_TRY(launch_refine(op0, react, a, ecur, L0.f32, e1, L0.coef32, chunk_of(0), &np, stream));
-      HIP_TRY(launch_sum_partials(part, np, scal, stream));
+      HIP_TRY(launch_sum_partials(part, np, out, stream));
     } else if (!mixed) {
-      HIP_TRY(residual64<double>(adj, react, U, f, u0, nullptr, scal));
+      HIP_TRY(residual64<double>(adj, react, U, f, u0, nullptr, out));
     } else {
-      HIP_TRY(residual64<float>(adj, react, U, f, u0, L0.f32, scal));
+      HIP_TRY(residual64<float>(adj, react, U, f, u0, L0.f32, out));
     }
-    HIP_TRY(hipMemcpyAsync(hnorm.h, scal, sizeof(double), hipMemcpyDeviceToHost, stream));
     return hipEventRecord(hnorm.ev, stream);
   };
   double rel = 0.0, rel0 = 0.0, prev = 0.0;

@@ -44,8 +44,10 @@ struct Plan {
 
 // Pinned host slot and event for reading a device scalar without draining
 // the stream (created on first use, on the device current at that time).
+// Kernels write the slot through its device alias `d`, so no copy is queued.
 struct HostScalar {
   double* h = nullptr;
+  double* d = nullptr;
   hipEvent_t ev = nullptr;
   HostScalar() = default;
   HostScalar(const HostScalar&) = delete;
@@ -56,8 +58,11 @@ struct HostScalar {
   }
   hipError_t init() {
     if (!h) {
-      hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(double), hipHostMallocDefault);
+      hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(double),
+                                   hipHostMallocMapped | hipHostMallocCoherent);
       if (e != hipSuccess) { h = nullptr; return e; }
+      e = hipHostGetDevicePointer(reinterpret_cast<void**>(&d), h, 0);
+      if (e != hipSuccess) return e;
     }
     if (!ev) {
       hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);

@@ -54,6 +54,21 @@ def test_mixed_inner_cycles(inner):
     assert e <= 1e-9 and eT <= 1e-9, (e, eT)
 
 
+@pytest.mark.parametrize("kw", [{"nu_post": 0}, {"max_levels": 1}])
+def test_mixed_unfolded_update(kw):
+    """Where the last level-0 kernel is not the fused prolongation + smoothing
+    (V(1,0) cycles, a single level) the refinement sweep adds the FP32
+    correction itself; the solve still reaches the FP64 tolerance."""
+    print("case mixed unfolded update", kw, flush=True)
+    prob = si.problem(2, 32, 3, 16, 0.5, nu=1e-2, lam=1.0)
+    u0 = si.u0_rd2d(prob, 6)
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob, precision="mixed", rtol=1e-10, max_cycles=400, **kw).solve(T(u0))
+    assert st["status"] == 0 and st["rel_res"] <= 1e-10
+    e, eT = _errs(U.cpu().numpy(), ref)
+    assert e <= 1e-9 and eT <= 1e-9, (e, eT)
+
+
 def test_mixed_neumann():
     """Neumann grids take the unfused refinement path (separate update)."""
     print("case mixed neumann", flush=True)
