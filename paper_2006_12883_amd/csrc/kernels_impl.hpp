@@ -1235,7 +1235,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_blk(const OpParams p, const S
 // With ZS the kernel also does the coarse level's first smoothing sweep from
 // a zero iterate (U_c = omega D_c^{-1} f_c along the coarse chunks of cs
 // slabs, which the run [J0, J1) contains whole) and writes it to uc.
-template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY, bool ZS, bool HF = true>
+template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY, bool ZS>
 __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const SweepPtrs<T>& a, int ncx,
                                                   int ncy, int Nc, T* __restrict__ fc, int S,
                                                   int tiles_x, int tile, int J0, const OpParams& pc,
@@ -1323,7 +1323,7 @@ __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const Sweep
 #pragma unroll
           for (int m = 0; m < M; ++m) u[k][m] = lap[k][m] = T(0);
       }
-      if (HF && a.f) {
+      if (a.f) {
         load_own<M, T, BY>(a.f, base, P, nx, b, fv);
       } else {
 #pragma unroll
@@ -1354,7 +1354,7 @@ __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const Sweep
 #pragma unroll
         for (int m = 0; m < M; ++m) u[m] = lap[m] = T(0);
       }
-      point_residual<M, T, REACT>(c, u, lap, a.coef, HF ? a.f : nullptr, base, P, hq, hprev, r);
+      point_residual<M, T, REACT>(c, u, lap, a.coef, a.f, base, P, hq, hprev, r);
       T np = T(0);
 #pragma unroll
       for (int i = 0; i < M; ++i) {
@@ -1439,8 +1439,7 @@ __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const Sweep
   }
 }
 
-// HF: the right-hand side pointer may be non-null (false: f = 0 known at compile time).
-template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY, bool ZS, bool HF>
+template <int M, typename T, int REACT, bool TM, bool TWOD, int TCX, int TCY, bool ZS>
 __global__ __launch_bounds__(kBlock) void k_restrict_blk(const OpParams p, const SweepPtrs<T> a,
                                                          int ncx, int ncy, int Nc,
                                                          T* __restrict__ fc, int S, int tiles_x,
@@ -1451,7 +1450,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_blk(const OpParams p, const
   constexpr int FH = TWOD ? 2 * TCY + 1 : 1;
   __shared__ T rs[M * FH * FW];
   const int lb = xcd_remap(blockIdx.x, nblocks);
-  restrict_blk_body<M, T, REACT, TM, TWOD, TCX, TCY, ZS, HF>(p, a, ncx, ncy, Nc, fc, S, tiles_x, lb % tiles,
+  restrict_blk_body<M, T, REACT, TM, TWOD, TCX, TCY, ZS>(p, a, ncx, ncy, Nc, fc, S, tiles_x, lb % tiles,
                                                          (lb / tiles) * S, pc, uc, coefc, cs, rs);
 }
 

@@ -140,10 +140,10 @@ hipError_t launch_restrict_residual(const OpParams& p, int react, const SweepPtr
     const int nb = tiles * ((Nc + spb - 1) / spb);
 #define LRB(MM, RE, TMc, TWc, CX, CY)                                                            \
   if (zs)                                                                                           \
-    hipLaunchKernelGGL((k_restrict_blk<MM, T, RE, TMc, TWc, CX, CY, true, true>), dim3(nb), dim3(kBlock), 0, \
+    hipLaunchKernelGGL((k_restrict_blk<MM, T, RE, TMc, TWc, CX, CY, true>), dim3(nb), dim3(kBlock), 0, \
                        s, p, a, ncx, ncy, Nc, fc, spb, tiles_x, tiles, nb, pcc, uc, coefc, cs);     \
   else                                                                                              \
-    hipLaunchKernelGGL((k_restrict_blk<MM, T, RE, TMc, TWc, CX, CY, false, true>), dim3(nb), dim3(kBlock), 0, \
+    hipLaunchKernelGGL((k_restrict_blk<MM, T, RE, TMc, TWc, CX, CY, false>), dim3(nb), dim3(kBlock), 0, \
                        s, p, a, ncx, ncy, Nc, fc, spb, tiles_x, tiles, nb, pcc, uc, coefc, cs)
 #define LRBE(MM, RE)                                          \
   if (twod) {                                                 \
