@@ -33,6 +33,14 @@ notes):
   mu >> 1 -> space), falling back to the other direction when one is not
   possible, until the level holds at most `min_coarse` unknowns.  The paper
   gives no threshold; mu_crit = 0.5 by default.
+* node coarsening (SMMG, Sec. 4.2): besides the space step, each level lowers
+  M by one until M = 1.  The paper calls the node transfer M_l^{l+1} a linear
+  interpolation; we read it as Lagrange interpolation from the coarse Radau
+  nodes to the fine ones, P[i, k] = l_k^coarse(c_i^fine) (exact for the coarse
+  polynomials, the M-coarsening PFASST uses), with restriction R = P^T.  With
+  these, P^T A_fine P equals the rediscretized coarse operator exactly in the
+  time structure (K_q, the Radau mass diag(b), l(0) and the end-node
+  coupling), so rediscretization and Galerkin agree for this transfer.
 * coarsest level: coarsening also stops at the first level below the finest
   whose planes hold at most `fft_plane` points and which holds at most
   `fft_coarse` unknowns (0 disables the rule).  This is a choice of where the
@@ -58,6 +66,7 @@ class Level:
         dgl = 2 * cx + 2 * cy + lam
         self.B = self.Kq + dt * np.diag(self.b) * dgl
         self.Binv = np.linalg.inv(self.B)
+        self.Pm = None  # node prolongation to the next coarser level (node coarsening only)
 
     @property
     def shape(self):
@@ -156,6 +165,19 @@ def prolong_time(e):
     return f
 
 
+def node_prolongation(Mf, Mc):
+    """P (Mf x Mc): the coarse Lagrange basis at the Radau nodes of the fine
+    level, P[i, k] = prod_{j != k} (c_i - C_j) / (C_k - C_j)."""
+    cf = radau.tables(Mf)["c"]
+    cc = radau.tables(Mc)["c"]
+    P = np.ones((Mf, Mc))
+    for k in range(Mc):
+        for j in range(Mc):
+            if j != k:
+                P[:, k] *= (cf - cc[j]) / (cc[k] - cc[j])
+    return P
+
+
 def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30, fft_coarse=262144,
               fft_plane=1024):
     """Level list and the coarsening kind between consecutive levels.
@@ -164,14 +186,13 @@ def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30, f
     Periodic boundary conditions only.
     """
     assert prob["bc"] == "periodic"
-    tab = radau.tables(prob["M"])
     dim = prob["dim"]
     nx = prob["nx"][0]
     ny = prob["nx"][1] if dim == 2 else 1
     N, dt = prob["N"], prob["dt"]
-    mk = lambda nx_, ny_, N_, dt_: Level(nx_, ny_, N_, prob["M"], dt_, prob["nu"],
-                                         prob.get("lambda", 0.0), prob["length"], dim, tab)
-    levels = [mk(nx, ny, N, dt)]
+    mk = lambda nx_, ny_, N_, dt_, M_: Level(nx_, ny_, N_, M_, dt_, prob["nu"], prob.get("lambda", 0.0),
+                                             prob["length"], dim, radau.tables(M_))
+    levels = [mk(nx, ny, N, dt, prob["M"])]
     kinds = []
     while len(levels) < max_levels:
         l = levels[-1]
@@ -184,6 +205,8 @@ def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30, f
         mu = l.nu * l.dt / min(l.hx, l.hy if dim == 2 else l.hx) ** 2
         if coarsen == "space":
             k = "s" if can_s else None
+        elif coarsen == "smmg":
+            k = ("sm" if l.M > 1 else "s") if can_s else ("m" if l.M > 1 else None)
         elif coarsen == "spacetime":
             k = "st" if (can_s and can_t) else ("s" if can_s else ("t" if can_t else None))
         else:
@@ -201,20 +224,26 @@ def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30, f
         ny2 = (l.ny // 2 if dim == 2 else 1) if "s" in k else l.ny
         N2 = l.N // 2 if "t" in k else l.N
         dt2 = 2 * l.dt if "t" in k else l.dt
-        levels.append(mk(nx2, ny2, N2, dt2))
+        M2 = l.M - 1 if "m" in k else l.M
+        l.Pm = node_prolongation(l.M, M2) if "m" in k else None
+        levels.append(mk(nx2, ny2, N2, dt2, M2))
         kinds.append(k)
     return levels, kinds
 
 
-def restrict(r, kind, dim):
+def restrict(r, kind, dim, Pm=None):
     if "s" in kind:
         r = restrict_space(r, dim)
     if "t" in kind:
         r = restrict_time(r)
+    if "m" in kind:
+        r = np.einsum("ik,niyx->nkyx", Pm, r)
     return r
 
 
-def prolong(e, kind, dim):
+def prolong(e, kind, dim, Pm=None):
+    if "m" in kind:
+        e = np.einsum("ik,nkyx->niyx", Pm, e)
     if "t" in kind:
         e = prolong_time(e)
     if "s" in kind:
@@ -232,10 +261,10 @@ def vcycle(levels, kinds, U, f, omega=0.8, chunk=16, nu_pre=1, nu_post=1, l=0, c
     for _ in range(nu_pre):
         U = lev.smooth(U, f, omega, ch)
     r = f - lev.apply(U)
-    fc = restrict(r, kinds[l], lev.dim)
+    fc = restrict(r, kinds[l], lev.dim, lev.Pm)
     ec = vcycle(levels, kinds, np.zeros(levels[l + 1].shape), fc, omega, chunk, nu_pre, nu_post, l + 1,
                 chunk_coarse)
-    U = U + prolong(ec, kinds[l], lev.dim)
+    U = U + prolong(ec, kinds[l], lev.dim, lev.Pm)
     for _ in range(nu_post):
         U = lev.smooth(U, f, omega, ch)
     return U
