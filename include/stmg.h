@@ -63,7 +63,8 @@ typedef enum {
 enum { STMG_BC_PERIODIC = 0, STMG_BC_NEUMANN = 1 };
 enum { STMG_REACT_LINEAR = 0, STMG_REACT_ALLEN_CAHN = 1 };
 enum { STMG_PREC_FP64 = 0, STMG_PREC_MIXED = 1 };
-enum { STMG_COARSEN_AUTO = 0, STMG_COARSEN_SPACE = 1, STMG_COARSEN_SPACETIME = 2 };
+enum { STMG_COARSEN_AUTO = 0, STMG_COARSEN_SPACE = 1, STMG_COARSEN_SPACETIME = 2,
+       STMG_COARSEN_SMMG = 3 };
 
 /* The problem statement: Eq. (model) of Sec. 3 generalized to a diffusion
  * coefficient, 2D and periodic grids; uniform partitions of Sec. 3. */
@@ -88,7 +89,10 @@ typedef struct {
                          smoother and transfers inside FP64 refinement        */
   int32_t coarsen;    /* AUTO (default): space if mu_l = nu dt_l / h_l^2 >=
                          mu_crit, else time (Sec. 3.2); SPACE = SMG;
-                         SPACETIME = STMG (both at once)                      */
+                         SPACETIME = STMG (both at once); SMMG = space
+                         coarsening with M lowered by one per level until
+                         M = 1 (Lagrange node transfer, R = P^T; linear
+                         reaction only)                                       */
   double mu_crit;     /* 0.5                                                 */
   double omega;       /* smoother damping, 0.8                                */
   int32_t chunk;      /* smoother block length in slabs on the finest level,
@@ -151,9 +155,12 @@ int stmg_setup(const stmg_problem* prob, const stmg_options* opt, void* d_ws,
 
 /* Number of levels and the shape of level l: out[0] = points in x, out[1] =
  * points in y, out[2] = slabs, out[3] = coarsening kind to level l+1
- * (0 none, 1 space, 2 time, 3 both).  Host only. */
+ * (bits: 1 space, 2 time, 4 collocation nodes; 0 none).  Host only. */
 int stmg_num_levels(const stmg_handle* h);
 int stmg_level_shape(const stmg_handle* h, int level, int32_t out[4], double* dt);
+/* Collocation nodes M_l on level l (M on every level except under SMMG), or a
+ * negative status.  Host only. */
+int stmg_level_nodes(const stmg_handle* h, int level);
 
 /* r = b - A(U) on the finest level (Eq. st_system), b built from u0.
  * d_u0: [ny][nx]; d_U: [N][M][ny][nx]; d_r may be NULL (norm only).

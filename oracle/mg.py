@@ -33,8 +33,8 @@ notes):
   mu >> 1 -> space), falling back to the other direction when one is not
   possible, until the level holds at most `min_coarse` unknowns.  The paper
   gives no threshold; mu_crit = 0.5 by default.
-* node coarsening (SMMG, Sec. 4.2): besides the space step, each level lowers
-  M by one until M = 1.  The paper calls the node transfer M_l^{l+1} a linear
+* node coarsening (SMMG, Sec. 4.2): each level coarsens in space (as SMG) and
+  lowers M by one until M = 1.  The paper calls the node transfer M_l^{l+1} a linear
   interpolation; we read it as Lagrange interpolation from the coarse Radau
   nodes to the fine ones, P[i, k] = l_k^coarse(c_i^fine) (exact for the coarse
   polynomials, the M-coarsening PFASST uses), with restriction R = P^T.  With
@@ -206,7 +206,7 @@ def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30, f
         if coarsen == "space":
             k = "s" if can_s else None
         elif coarsen == "smmg":
-            k = ("sm" if l.M > 1 else "s") if can_s else ("m" if l.M > 1 else None)
+            k = ("sm" if l.M > 1 else "s") if can_s else None
         elif coarsen == "spacetime":
             k = "st" if (can_s and can_t) else ("s" if can_s else ("t" if can_t else None))
         else:

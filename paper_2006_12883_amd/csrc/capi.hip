@@ -115,6 +115,14 @@ int stmg_level_shape(const stmg_handle* h, int level, int32_t out[4], double* dt
   return STMG_OK;
 }
 
+int stmg_level_nodes(const stmg_handle* h, int level) {
+  if (!h || level < 0 || level >= static_cast<int>(h->s.lv.size())) {
+    stmg::set_error("bad level");
+    return STMG_EINVAL;
+  }
+  return h->s.lv[level].M;
+}
+
 int stmg_residual(stmg_handle* h, const double* d_u0, const double* d_U, double* d_r,
                   double* h_norm) {
   if (!h || !d_U) { stmg::set_error("null pointer"); return STMG_EINVAL; }

@@ -150,6 +150,15 @@ template <typename T>
 hipError_t launch_restrict_coef(const OpParams& fine, bool space, bool time, int ncx, int ncy,
                                 int Nc, const T* cf, T* cc, hipStream_t s);
 
+// Node transfer between collocation node sets, pointwise in slab and space:
+// out[n][o][q] = sum_i W[o * Min + i] in[n][i][q]  (W is Mout x Min).
+struct NodeMat {
+  double W[kMaxM * kMaxM];
+};
+template <typename T>
+hipError_t launch_node_transfer(const T* in, int Min, T* out, int Mout, const NodeMat& W, int N,
+                                size_t P, hipStream_t s);
+
 // Reverse the slab order of a [N][M][P] array (out-of-place).
 hipError_t launch_reverse_slabs(const double* in, double* out, int N, int M, size_t P,
                                 hipStream_t s);

@@ -72,6 +72,37 @@ __global__ __launch_bounds__(kBlock) void k_grad_nu(const OpParams p, const doub
 
 }  // namespace
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_node_transfer(const T* __restrict__ in, int Min,
+                                                          T* __restrict__ out, int Mout, const NodeMat W,
+                                                          int N, size_t P) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= (size_t)N * P) return;
+  const size_t n = idx / P, q = idx - n * P;
+  double v[kMaxM];
+  for (int i = 0; i < Min; ++i) v[i] = (double)in[(n * Min + i) * P + q];
+  for (int o = 0; o < Mout; ++o) {
+    double s = 0.0;
+    for (int i = 0; i < Min; ++i) s += W.W[o * Min + i] * v[i];
+    out[(n * Mout + o) * P + q] = (T)s;
+  }
+}
+
+template <typename T>
+hipError_t launch_node_transfer(const T* in, int Min, T* out, int Mout, const NodeMat& W, int N,
+                                size_t P, hipStream_t s) {
+  if (Min < 1 || Min > kMaxM || Mout < 1 || Mout > kMaxM) return hipErrorInvalidValue;
+  const size_t tot = (size_t)N * P;
+  if (tot == 0) return hipSuccess;
+  const unsigned nb = (unsigned)((tot + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL((k_node_transfer<T>), dim3(nb), dim3(kBlock), 0, s, in, Min, out, Mout, W, N, P);
+  return hipGetLastError();
+}
+template hipError_t launch_node_transfer<double>(const double*, int, double*, int, const NodeMat&, int,
+                                                 size_t, hipStream_t);
+template hipError_t launch_node_transfer<float>(const float*, int, float*, int, const NodeMat&, int,
+                                                size_t, hipStream_t);
+
 int smooth_blocks(const OpParams& p, int chunk) {
   return ((plane_threads(p) + kBlock - 1) / kBlock) * ((p.N + chunk - 1) / chunk);
 }

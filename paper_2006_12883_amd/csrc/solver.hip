@@ -41,6 +41,15 @@ int points(int e, int bc) { return bc == STMG_BC_PERIODIC ? e : e + 1; }
     }                                                                            \
   } while (0)
 
+const RadauTables* Solver::tables_for(int m) {
+  if (m < 1 || m > kMaxM) return nullptr;
+  if (!mtab_ok[m]) {
+    if (!radau_tables(m, &mtab[m])) return nullptr;
+    mtab_ok[m] = true;
+  }
+  return &mtab[m];
+}
+
 // ---------------------------------------------------------------------------
 // Hierarchy.  Semi-coarsening by the anisotropy ratio mu = nu dt / h^2
 // (Sec. 3.2: coarsen in time when mu << 1 and in space when mu >> 1), with the
@@ -80,6 +89,14 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   allen_cahn = p->reaction == STMG_REACT_ALLEN_CAHN;
   mixed = o->precision == STMG_PREC_MIXED;
   if (!radau_tables(p->M, &tab)) { set_error("Radau table construction failed"); return STMG_EINVAL; }
+  if (o->coarsen == STMG_COARSEN_SMMG && allen_cahn) {
+    set_error("SMMG coarsening: linear problems only");
+    return STMG_EUNSUPPORTED;
+  }
+  if (o->coarsen < STMG_COARSEN_AUTO || o->coarsen > STMG_COARSEN_SMMG) {
+    set_error("bad coarsen");
+    return STMG_EINVAL;
+  }
 
   const int M = p->M;
   const bool twod = p->dim == 2;
@@ -90,6 +107,7 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   L.nx = points(ex, p->bc);
   L.ny = twod ? points(ey, p->bc) : 1;
   L.N = p->N;
+  L.M = M;
   L.dt = p->dt;
   lv.push_back(L);
   // Periodic grids with a constant reaction can stop at a larger coarsest
@@ -98,9 +116,9 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   const bool fft_ok = p->bc == STMG_BC_PERIODIC && !allen_cahn && !batch_member;
   while (static_cast<int>(lv.size()) < o->max_levels) {
     Level& c = lv.back();
-    if (static_cast<long long>(M) * c.nx * c.ny * c.N <= o->min_coarse) break;
+    if (static_cast<long long>(c.M) * c.nx * c.ny * c.N <= o->min_coarse) break;
     if (fft_ok && lv.size() > 1 && c.nx * c.ny <= kFftMaxPlane &&
-        static_cast<long long>(M) * c.nx * c.ny * c.N <= o->fft_coarse)
+        static_cast<long long>(c.M) * c.nx * c.ny * c.N <= o->fft_coarse)
       break;
     const int q = batch_member ? 4 : 2;
     const bool cs_x = (c.ex % q == 0) && c.ex >= 4;
@@ -114,6 +132,8 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     int kind = 0;
     if (o->coarsen == STMG_COARSEN_SPACE) {
       kind = can_s ? 1 : 0;
+    } else if (o->coarsen == STMG_COARSEN_SMMG) {
+      kind = can_s ? (c.M > 1 ? 1 | 4 : 1) : 0;
     } else if (o->coarsen == STMG_COARSEN_SPACETIME) {
       kind = (can_s && can_t) ? 3 : (can_s ? 1 : (can_t ? 2 : 0));
     } else {
@@ -129,22 +149,41 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     nl.nx = points(nl.ex, p->bc);
     nl.ny = twod ? points(nl.ey, p->bc) : 1;
     nl.N = (kind & 2) ? c.N / 2 : c.N;
+    nl.M = (kind & 4) ? c.M - 1 : c.M;
     nl.dt = (kind & 2) ? 2.0 * c.dt : c.dt;
+    if (kind & 4) {
+      // Lagrange basis of the coarse Radau nodes at the fine ones
+      const RadauTables* tf = tables_for(c.M);
+      const RadauTables* tc = tables_for(nl.M);
+      if (!tf || !tc) { set_error("Radau table construction failed"); return STMG_EINVAL; }
+      for (int i = 0; i < c.M; ++i)
+        for (int k = 0; k < nl.M; ++k) {
+          long double v = 1.0L;
+          for (int j = 0; j < nl.M; ++j)
+            if (j != k) v *= (tf->c[i] - tc->c[j]) / (tc->c[k] - tc->c[j]);
+          c.Pn.W[i * nl.M + k] = static_cast<double>(v);
+          c.Rn.W[k * c.M + i] = static_cast<double>(v);
+        }
+    }
     lv.push_back(nl);
   }
   const Level& last = lv.back();
-  const long long Kc = static_cast<long long>(M) * last.nx * last.ny;
+  const long long Kc = static_cast<long long>(last.M) * last.nx * last.ny;
   fft = fft_ok && last.nx * last.ny <= kFftMaxPlane;
   if (!fft && Kc > 1024) {
     set_error("coarsest level has more than 1024 unknowns per slab");
     return STMG_EUNSUPPORTED;
   }
 
-  // Operators per level.
+  // Operators per level (each with its own node count and tables).
   for (auto& l : lv) {
     l.hx = p->length[0] / l.ex;
     l.hy = twod ? p->length[1] / l.ey : 1.0;
-    l.n = static_cast<size_t>(l.N) * M * l.nx * l.ny;
+    l.n = static_cast<size_t>(l.N) * l.M * l.nx * l.ny;
+    const RadauTables* lt = tables_for(l.M);
+    if (!lt) { set_error("Radau table construction failed"); return STMG_EINVAL; }
+    const RadauTables& tab = *lt;
+    const int M = l.M;
     OpParams op{};
     op.M = M;
     op.nx = l.nx;
@@ -279,6 +318,12 @@ size_t Solver::plan(char* ws) {
   }
   for (size_t i = 0; i < lv.size(); ++i) {
     Level& l = lv[i];
+    if ((l.kind & 4) && i + 1 < lv.size()) {
+      const Level& c = lv[i + 1];
+      const size_t nt = static_cast<size_t>(c.N) * l.M * c.nx * c.ny;
+      l.nt64 = pl.take<double>(nt);
+      if (mixed) l.nt32 = pl.take<float>(nt);
+    }
     if (i > 0) l.A64 = pl.take<double>(l.n);
     l.B64 = pl.take<double>(l.n);
     l.f64 = pl.take<double>(l.n);
@@ -306,13 +351,13 @@ size_t Solver::plan(char* ws) {
   part = pl.take<double>(static_cast<size_t>(max_parts));
   scal = pl.take<double>(32);
   const Level& c = lv.back();
-  const size_t K = static_cast<size_t>(prob.M) * c.nx * c.ny;
+  const size_t K = static_cast<size_t>(c.M) * c.nx * c.ny;
   if (fft) {
     const size_t Pc = static_cast<size_t>(c.nx) * c.ny;
-    fft_sinv = pl.take<double>(Pc * prob.M * prob.M);
-    fft_sinvT = pl.take<double>(Pc * prob.M * prob.M);
+    fft_sinv = pl.take<double>(Pc * c.M * c.M);
+    fft_sinvT = pl.take<double>(Pc * c.M * c.M);
     fft_tw = pl.take<double>(2 * (static_cast<size_t>(c.nx) + c.ny));
-    fft_work = pl.take<double>(2 * (static_cast<size_t>(c.N) * prob.M + 1) * Pc);
+    fft_work = pl.take<double>(2 * (static_cast<size_t>(c.N) * c.M + 1) * Pc);
   } else {
     Ainv = pl.take<double>(K * K);
     AinvT = pl.take<double>(K * K);
@@ -336,7 +381,10 @@ size_t Solver::plan(char* ws) {
 // in long double; the DFT twiddles cos, sin of 2 pi j / n.
 int Solver::upload_fft() {
   const Level& c = lv.back();
-  const int M = prob.M, nx = c.nx, ny = c.ny, P = nx * ny;
+  const int M = c.M, nx = c.nx, ny = c.ny, P = nx * ny;
+  const RadauTables* lt = tables_for(M);
+  if (!lt) { set_error("Radau table construction failed"); return STMG_EINVAL; }
+  const RadauTables& tab = *lt;
   const long double twopi = 6.283185307179586476925286766559L;
   const OpParams& op = c.op;
   std::vector<double> S(static_cast<size_t>(P) * M * M), ST(static_cast<size_t>(P) * M * M);
@@ -378,7 +426,10 @@ int Solver::upload_fft() {
 // (and its transpose, for the transposed problem), in long double.
 int Solver::upload_dense() {
   const Level& c = lv.back();
-  const int M = prob.M, P = c.nx * c.ny, K = M * P;
+  const int M = c.M, P = c.nx * c.ny, K = M * P;
+  const RadauTables* lt = tables_for(M);
+  if (!lt) { set_error("Radau table construction failed"); return STMG_EINVAL; }
+  const RadauTables& tab = *lt;
   std::vector<long double> A(static_cast<size_t>(K) * K, 0.0L);
   const OpParams& op = c.op;
   auto lo = [&](int i, int n) { return i > 0 ? i - 1 : (op.bc == 0 ? n - 1 : 1); };
@@ -467,6 +518,12 @@ template <>
 const double* coef_of<double>(const Level& l) { return l.coef64; }
 template <>
 const float* coef_of<float>(const Level& l) { return l.coef32; }
+template <typename T>
+static T* nt_of(const Level& l);
+template <>
+double* nt_of<double>(const Level& l) { return l.nt64; }
+template <>
+float* nt_of<float>(const Level& l) { return l.nt32; }
 
 template <typename T>
 hipError_t Solver::smooth(int l, bool adj, int react, const T* U, const T* f, const double* u0,
@@ -484,6 +541,16 @@ hipError_t Solver::restrict_residual(int l, bool adj, int react, const T* U, con
   SweepPtrs<T> a{U, f, u0, coef_of<T>(L), nullptr, nullptr};
   int spb = transfer_slabs(l + 1);
   const int cs = chunk_of(l + 1);
+  if (L.kind & 4) {
+    // node coarsening: restrict in space with this level's nodes into the
+    // transfer buffer, then R = P^T over the nodes (no fused coarse sweep)
+    if (smoothed) *smoothed = false;
+    T* nt = nt_of<T>(L);
+    HIP_TRY(launch_restrict_residual<T>(adj ? L.opT : L.op, react, a, (L.kind & 1) != 0,
+                                        (L.kind & 2) != 0, C.nx, C.ny, C.N, nt, spb, stream));
+    return launch_node_transfer<T>(nt, L.M, fc, C.M, L.Rn, C.N, static_cast<size_t>(C.nx) * C.ny,
+                                   stream);
+  }
   if (uc && spb % cs != 0) spb = ((spb + cs - 1) / cs) * cs;
   return launch_restrict_residual<T>(adj ? L.opT : L.op, react, a, (L.kind & 1) != 0,
                                      (L.kind & 2) != 0, C.nx, C.ny, C.N, fc, spb, stream,
@@ -494,6 +561,11 @@ template <typename T>
 hipError_t Solver::prolong(int l, const T* Uin, const T* ec, T* Uout) {
   const Level& L = lv[l];
   const Level& C = lv[l + 1];
+  if (L.kind & 4) {
+    T* nt = nt_of<T>(L);
+    HIP_TRY(launch_node_transfer<T>(ec, C.M, nt, L.M, L.Pn, C.N, static_cast<size_t>(C.nx) * C.ny, stream));
+    ec = nt;
+  }
   return launch_prolong<T>(L.op, (L.kind & 1) != 0, (L.kind & 2) != 0, C.nx, C.ny, C.N, ec, Uin,
                            Uout, transfer_slabs(l), stream);
 }
@@ -514,6 +586,11 @@ hipError_t Solver::prolong_smooth(int l, bool adj, int react, const T* Uin, cons
   const Level& L = lv[l];
   const Level& C = lv[l + 1];
   SweepPtrs<T> a{Uin, f, u0, coef_of<T>(L), out, nullptr};
+  if (L.kind & 4) {
+    T* nt = nt_of<T>(L);
+    HIP_TRY(launch_node_transfer<T>(ec, C.M, nt, L.M, L.Pn, C.N, static_cast<size_t>(C.nx) * C.ny, stream));
+    ec = nt;
+  }
   if constexpr (sizeof(T) == 4) {
     if (l == 0 && up_in) {
       a.up64 = up_in;

@@ -19,8 +19,15 @@ struct Level {
   int nx = 0, ny = 1;  // grid points
   int ex = 0, ey = 1;  // elements (Neumann) / points (periodic), for h
   int N = 0;
+  int M = 0;           // collocation nodes (lowered by node coarsening)
   double dt = 0.0, hx = 0.0, hy = 1.0;
-  int kind = 0;        // coarsening to the next level: 1 space, 2 time, 3 both
+  int kind = 0;        // coarsening to the next level: bits 1 space, 2 time, 4 nodes
+  // node coarsening to the next level: prolongation Pn (M x M_next) and
+  // restriction Rn = Pn^T, and the coarse-grid buffers with this level's M
+  // that carry the transfers between the two node sets
+  NodeMat Pn{}, Rn{};
+  double* nt64 = nullptr;
+  float* nt32 = nullptr;
   size_t n = 0;        // N * M * nx * ny
   OpParams op{}, opT{};
   // FP64 buffers (level 0: A is the caller's iterate, B is workspace)
@@ -76,7 +83,10 @@ struct Solver {
   stmg_problem prob{};
   stmg_options opt{};
   hipStream_t stream = nullptr;
-  RadauTables tab{};
+  RadauTables tab{};                 // M of the problem (finest level)
+  RadauTables mtab[kMaxM + 1]{};     // per node count (node coarsening), built on demand
+  bool mtab_ok[kMaxM + 1] = {};
+  const RadauTables* tables_for(int m);
   std::vector<Level> lv;
   bool allen_cahn = false;
   bool mixed = false;

@@ -61,12 +61,14 @@ class Handle:
             a = (ctypes.c_int32 * 4)()
             dt = ctypes.c_double()
             B.check(L.stmg_level_shape(self.h, l, a, ctypes.byref(dt)), "stmg_level_shape")
-            out.append(dict(nx=a[0], ny=a[1], N=a[2], kind=a[3], dt=dt.value))
+            m = L.stmg_level_nodes(self.h, l)
+            B.check(min(m, 0), "stmg_level_nodes")
+            out.append(dict(nx=a[0], ny=a[1], N=a[2], kind=a[3], dt=dt.value, M=m))
         return out
 
     def level_shape(self, l):
         d = self.levels()[l]
-        return (d["N"], self.prob["M"], d["ny"], d["nx"])
+        return (d["N"], d["M"], d["ny"], d["nx"])
 
     # --- main entry points -----------------------------------------------
     def residual(self, u0, U, r=None):

@@ -59,9 +59,9 @@ def test_hierarchy_matches_oracle(name, prob, fft):
     levels, kinds = mg.hierarchy(prob, fft_coarse=fft)
     got = H(prob, fft_coarse=fft).levels()
     assert len(got) == len(levels)
-    code = {"s": 1, "t": 2, "st": 3}
+    code = {"s": 1, "t": 2, "st": 3, "sm": 5}
     for l, (g, o) in enumerate(zip(got, levels)):
-        assert (g["nx"], g["ny"], g["N"]) == (o.nx, o.ny, o.N)
+        assert (g["nx"], g["ny"], g["N"], g["M"]) == (o.nx, o.ny, o.N, o.M)
         assert abs(g["dt"] - o.dt) <= 1e-15 * o.dt
         assert g["kind"] == (code[kinds[l]] if l < len(kinds) else 0)
 
@@ -144,3 +144,80 @@ def test_repeatable_bitwise():
         h.vcycle(T(u0), Ud)
         outs.append(Ud.cpu().numpy())
     assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+# SMMG: space coarsening with M lowered by one per level (Sec. 4.2)
+SMMG = [
+    ("smmg-2d-M3", si.problem(2, 32, 3, 6, 0.5, nu=0.05, lam=1.0)),
+    ("smmg-2d-M4-tiles", si.problem(2, 48, 4, 5, 0.5, nu=0.02, lam=0.5)),
+    ("smmg-1d-M2", si.problem(1, 64, 2, 16, 0.1, nu=1.0, lam=0.0)),
+]
+
+
+@pytest.mark.parametrize("name,prob", SMMG)
+@pytest.mark.parametrize("fft", FFT)
+def test_smmg_hierarchy_matches_oracle(name, prob, fft):
+    print("case", name, fft, flush=True)
+    levels, kinds = mg.hierarchy(prob, coarsen="smmg", fft_coarse=fft)
+    got = H(prob, coarsen="smmg", fft_coarse=fft).levels()
+    assert len(got) == len(levels)
+    code = {"s": 1, "sm": 5}
+    for l, (g, o) in enumerate(zip(got, levels)):
+        assert (g["nx"], g["ny"], g["N"], g["M"]) == (o.nx, o.ny, o.N, o.M)
+        assert g["kind"] == (code[kinds[l]] if l < len(kinds) else 0)
+
+
+@pytest.mark.parametrize("name,prob", SMMG)
+def test_smmg_transfers_each_level(name, prob):
+    """Residual restriction and prolongation across node sets against the oracle."""
+    print("case", name, flush=True)
+    levels, kinds = mg.hierarchy(prob, coarsen="smmg", fft_coarse=0)
+    h = H(prob, coarsen="smmg", fft_coarse=0)
+    for l in range(len(levels) - 1):
+        lev, nxt = levels[l], levels[l + 1]
+        rng = np.random.default_rng(40 + l)
+        U = rng.standard_normal(lev.shape)
+        f = rng.standard_normal(lev.shape)
+        ref = mg.restrict(f - lev.apply(U), kinds[l], lev.dim, lev.Pm)
+        fc = torch.empty(nxt.shape, dtype=torch.float64, device="cuda:0")
+        h.restrict_residual(l, T(U), fc, f=T(f))
+        assert_close(fc.cpu().numpy(), ref, 1e-12, "restrict level %d kind %s" % (l, kinds[l]))
+        ec = rng.standard_normal(nxt.shape)
+        refp = U + mg.prolong(ec, kinds[l], lev.dim, lev.Pm)
+        out = torch.empty(lev.shape, dtype=torch.float64, device="cuda:0")
+        h.prolong(l, T(ec), out, Uin=T(U))
+        assert_close(out.cpu().numpy(), refp, 1e-13, "prolong level %d kind %s" % (l, kinds[l]))
+        ref_s = lev.smooth(U, f, 0.8, 16 if l == 0 else 4)
+        out_s = torch.empty(lev.shape, dtype=torch.float64, device="cuda:0")
+        h.smooth(l, T(U), out_s, f=T(f))
+        assert_close(out_s.cpu().numpy(), ref_s, 1e-12, "smooth level %d (M=%d)" % (l, lev.M))
+
+
+@pytest.mark.parametrize("name,prob", SMMG)
+@pytest.mark.parametrize("fft", FFT)
+def test_smmg_one_vcycle_matches_oracle(name, prob, fft):
+    print("case", name, fft, flush=True)
+    levels, kinds = mg.hierarchy(prob, coarsen="smmg", fft_coarse=fft)
+    u0 = np.random.default_rng(4).standard_normal(levels[0].shape[2:])
+    f = mg.rhs(levels, u0)
+    U = np.random.default_rng(5).standard_normal(levels[0].shape)
+    ref = mg.vcycle(levels, kinds, U.copy(), f)
+    h = H(prob, coarsen="smmg", fft_coarse=fft)
+    Ud = T(U)
+    h.vcycle(T(u0), Ud)
+    assert_close(Ud.cpu().numpy(), ref, 1e-11, "one SMMG V-cycle")
+
+
+def test_smmg_coarse_solve_on_lowered_nodes():
+    """The coarsest level of an SMMG hierarchy has fewer nodes than the finest;
+    both coarsest solves (Fourier and dense) use that level's own tables."""
+    prob = SMMG[0][1]
+    for fft in FFT:
+        levels, kinds = mg.hierarchy(prob, coarsen="smmg", fft_coarse=fft)
+        lev = levels[-1]
+        assert lev.M < prob["M"]
+        h = H(prob, coarsen="smmg", fft_coarse=fft)
+        f = np.random.default_rng(6).standard_normal(lev.shape)
+        out = torch.empty(lev.shape, dtype=torch.float64, device="cuda:0")
+        h.coarse_solve(T(f), out)
+        assert_close(out.cpu().numpy(), lev.exact_solve(f), 1e-12, "coarse solve M=%d" % lev.M)

@@ -106,3 +106,17 @@ def test_autotuned_shapes_bitwise_identical(prec, tmp_path, monkeypatch):
     assert all(t >= 1 for t in tuned)
     h2 = H(prob, precision=prec, rtol=rt, autotune=1)  # from the cache
     assert [B.lib().stmg_tuned_shape(h2.h, l) for l in range(len(shapes) - 1)] == tuned
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_smmg_solve_matches_stepper(prec):
+    """SMMG V-cycles (Sec. 4.2) converge to the Radau IIA trajectory."""
+    print("case smmg solve", prec, flush=True)
+    prob = si.problem(2, 64, 3, 32, 0.5, nu=1e-2, lam=1.0)
+    u0 = si.u0_rd2d(prob, 8)
+    rt = 1e-12 if prec == "fp64" else 1e-10
+    U, st = H(prob, coarsen="smmg", precision=prec, rtol=rt).solve(T(u0))
+    assert st["status"] == 0
+    ref = stepper.solve_linear(prob, u0)
+    e = rel_err(U.cpu().numpy(), ref)
+    assert e <= (1e-10 if prec == "fp64" else 1e-9), e
