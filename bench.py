@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE runs (scaled by a device copy of known size; see
 # profiles/k_smooth_blk_rd2d_level0.md), valid only for the kernel source it
 # was measured on.
-TRAFFIC = {"kernels_impl_sha256_prefix": "b187ddf016ab9fa1", "bytes_per_launch": 456.76e6 + 402.65e6}
+TRAFFIC = {"kernels_impl_sha256_prefix": "c8b7aafb6845ae61", "bytes_per_launch": 456.27e6 + 402.65e6}
 
 
 def measured_traffic():
@@ -180,6 +180,32 @@ def extras(dev):
     del b, Us
     torch.cuda.empty_cache()
     print("batch done", file=sys.stderr, flush=True)
+    # the paper's three hierarchies (Sec. 4.2) on the 256^2 workload, FP64 to
+    # 1e-10: SMG (space only), STMG (space and time at once), SMMG (space and
+    # nodes); AUTO semi-coarsening is the headline solve
+    prob = si.config("rd2d")
+    u0 = torch.as_tensor(si.initial("rd2d", prob)).to(dev)
+    dof = float(prob["N"] * prob["M"] * 256 * 256)
+    variants = {}
+    for name in ("auto", "space", "spacetime", "smmg"):
+        h = stmg.Handle(prob, device=dev, coarsen=name, rtol=1e-10, max_cycles=100)
+        U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
+        h.solve(u0, U, check=False)
+        U.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = h.solve(u0, U, check=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        lv = h.levels()
+        variants[name] = {"seconds": t, "status": st["status"], "vcycles": st["cycles"],
+                          "rel_res": st["rel_res"], "levels": len(lv),
+                          "coarsest": [lv[-1]["nx"], lv[-1]["ny"], lv[-1]["N"], lv[-1]["M"]],
+                          "dof_vcycles_per_s": dof * st["cycles"] / t}
+        del h, U
+        torch.cuda.empty_cache()
+    out["hierarchies_rd2d_fp64_to_1e-10"] = variants
+    print("hierarchies done", file=sys.stderr, flush=True)
     return out
 
 
