@@ -708,6 +708,16 @@ __device__ __forceinline__ void st2o(gptr b, unsigned o, T x, T y) {
   v.y = y;
   *(__attribute__((address_space(1))) v2*)(b + o) = v;
 }
+// The same with a non-temporal (streaming) hint: the stencil kernels' outputs
+// are read again only by the next kernel, after the whole vector is written.
+template <typename T>
+__device__ __forceinline__ void st2o_nt(gptr b, unsigned o, T x, T y) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 v;
+  v.x = x;
+  v.y = y;
+  __builtin_nontemporal_store(v, (__attribute__((address_space(1))) v2*)(b + o));
+}
 
 // Geometry of the 2 x BY block owned by thread t of a plane (periodic), with
 // the element offsets (inside a plane) of its rows and side points.
@@ -790,7 +800,7 @@ __device__ __forceinline__ void store_own(T* __restrict__ F, size_t base, int P,
   for (int m = 0; m < M; ++m) {
     const gptr Fm = ubase_w(F + base + (size_t)m * P);
 #pragma unroll
-    for (int j = 0; j < BY; ++j) st2o(Fm, b.orow[j + 1] * sizeof(T), v[2 * j][m], v[2 * j + 1][m]);
+    for (int j = 0; j < BY; ++j) st2o_nt(Fm, b.orow[j + 1] * sizeof(T), v[2 * j][m], v[2 * j + 1][m]);
   }
 }
 
@@ -1383,7 +1393,7 @@ __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const Sweep
       auto emit = [&](int J, const T* v) {
         const size_t cb = (size_t)J * M * Pc;
 #pragma unroll
-        for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] = v[i];
+        for (int i = 0; i < M; ++i) __builtin_nontemporal_store(v[i], fc + cb + (size_t)i * Pc + qc);
         if (ZS) {
           const Consts<M, T> k(pc);
           T rr[M], d[M];
@@ -1410,7 +1420,7 @@ __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const Sweep
           T nd = T(0);
 #pragma unroll
           for (int i = 0; i < M; ++i) {
-            uc[cb + (size_t)i * Pc + qc] = k.omega * d[i];
+            __builtin_nontemporal_store(k.omega * d[i], uc + cb + (size_t)i * Pc + qc);
             nd += k.cout[i] * d[i];
           }
           zdprev = nd;
