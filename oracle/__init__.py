@@ -20,4 +20,5 @@ adjoint   discrete adjoint of the sequential stepper (gradients of a
           terminal loss w.r.t. u0 and the diffusion coefficient)
 mg        the multigrid components (transfers, block-Jacobi smoother,
           level hierarchy, V-cycle) spelled out plainly in NumPy
+krylov    restarted flexible GMRES with the V-cycle as right preconditioner
 """
