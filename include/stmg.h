@@ -123,6 +123,15 @@ typedef struct {
                          fft_coarse unknowns; that level is solved exactly by
                          Fourier diagonalization in space and the slab
                          recurrence per mode.  262144; 0 = off                */
+  int32_t krylov;     /* restart length m (1..32) of an outer flexible GMRES
+                         around the cycles: one V-cycle from a zero guess is
+                         the right preconditioner of each Krylov step (FP32
+                         cycles with STMG_PREC_MIXED, the Krylov vectors stay
+                         FP64).  The stop test is unchanged (true residual,
+                         rtol), `cycles` counts V-cycles = Krylov steps and
+                         max_cycles bounds them; 2 (m + 1) more level-0
+                         vectors of workspace.  Ignored by batches.
+                         0 (default): the plain V-cycle iteration             */
 } stmg_options;
 
 typedef struct {

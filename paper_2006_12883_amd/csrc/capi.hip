@@ -56,6 +56,7 @@ void stmg_default_options(stmg_options* o) {
   o->autotune = 0;
   o->inner_cycles = 2;
   o->fft_coarse = 262144;
+  o->krylov = 0;
 }
 
 size_t stmg_workspace_bytes(const stmg_problem* prob, const stmg_options* opt) {

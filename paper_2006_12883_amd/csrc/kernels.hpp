@@ -181,4 +181,28 @@ hipError_t launch_sdc_gather(const double* r, const double* acc, double* rhs, in
 hipError_t launch_sdc_update(double* U, double* acc, const double* d, int N, int M, int nx, int ny,
                              int bc, double cx, double cy, double lam, double w, int m, hipStream_t s);
 
+// Flexible GMRES on level 0 (FP64).  A set of up to kKrylovMax + 1
+// vectors of n doubles and one coefficient per vector, both passed by value.
+constexpr int kKrylovMax = 32;
+constexpr int kKrylovParts = 1024;  // upper bound on the blocks of one Krylov pass
+struct KVecs {
+  const double* v[kKrylovMax + 1];
+};
+struct KCoef {
+  double c[kKrylovMax + 1];
+};
+// One Gram-Schmidt pass of w against V_0..V_{k-1} (k <= kKrylovMax + 1):
+// when d is given, w -= sum_i s.c[i] d[i] V_i (d on the device, typically the
+// previous pass's dot products, s the host's 1 / ||V_i||^2); then per-block
+// partials of (w, V_i) for i < k (when dots) in part[i * nb + block] and of
+// (w, w) in part[k * nb + block].  *nb receives the block count.
+hipError_t launch_kortho(double* w, const KVecs& V, int k, const KCoef& s, const double* d, size_t n,
+                         bool dots, double* part, int* nb, hipStream_t st);
+// out[c] = sum_b part[c * nb + b] for c < cols (fixed order), also written to
+// the host-visible mirror when it is given.
+hipError_t launch_kreduce(const double* part, int nb, int cols, double* out, double* mirror,
+                          hipStream_t st);
+// x += sum_{i < k} y.c[i] Z_i
+hipError_t launch_kcombine(double* x, const KVecs& Z, int k, const KCoef& y, size_t n, hipStream_t st);
+
 }  // namespace stmg

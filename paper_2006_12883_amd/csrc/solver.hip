@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <limits>
 #include <map>
 #include <sstream>
 
@@ -78,7 +79,7 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   }
   if (o->chunk < 1 || o->chunk_coarse < 1 || o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1 ||
       o->max_levels < 1 || o->max_cycles < 1 || !(o->rtol > 0.0) || !(o->omega > 0.0) ||
-      o->inner_cycles < 1 || o->fft_coarse < 0) {
+      o->inner_cycles < 1 || o->fft_coarse < 0 || o->krylov < 0 || o->krylov > kKrylovMax) {
     set_error("invalid options");
     return STMG_EINVAL;
   }
@@ -233,6 +234,7 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
       stmg_options so = *o;
       so.sdc = 0;
       so.mem_budget = 0;
+      so.krylov = 0;
       so.precision = STMG_PREC_FP64;
       so.coarsen = STMG_COARSEN_SPACE;
       std::unique_ptr<Solver> sub(new Solver());
@@ -244,15 +246,16 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   }
   // Windows: the FP64 path keeps about five full vectors on level 0 (the
   // caller's U, ping-pong, right-hand side, Newton/adjoint vector and the
-  // adjoint's own ping-pong).
+  // adjoint's own ping-pong), plus 2 (m + 1) with the Krylov method.
   win_W = 0;
   nwin = 0;
   win.reset();
   win_last.reset();
   const size_t P = static_cast<size_t>(lv[0].nx) * lv[0].ny;
   const size_t slab = static_cast<size_t>(M) * P * sizeof(double);
-  if (o->mem_budget > 0 && 5 * slab * static_cast<size_t>(p->N) > o->mem_budget) {
-    long long W = static_cast<long long>(o->mem_budget / (6 * slab));
+  const size_t vecs = 5 + (o->krylov > 0 ? 2 * static_cast<size_t>(o->krylov + 1) : 0);
+  if (o->mem_budget > 0 && vecs * slab * static_cast<size_t>(p->N) > o->mem_budget) {
+    long long W = static_cast<long long>(o->mem_budget / ((vecs + 1) * slab));
     if (W < 1) W = 1;
     // largest power of two not above the budget, so windows coarsen in time
     long long w2 = 1;
@@ -338,6 +341,13 @@ size_t Solver::plan(char* ws) {
     }
   }
   delta64 = pl.take<double>(lv[0].n);
+  if (opt.krylov > 0) {
+    const size_t vecs = static_cast<size_t>(opt.krylov) + 1;
+    kV = pl.take<double>(vecs * lv[0].n);
+    kZ = pl.take<double>(vecs * lv[0].n);
+    kpart = pl.take<double>(static_cast<size_t>(kKrylovParts) * (kKrylovMax + 2));
+    kdev = pl.take<double>(1 + 3 * (kKrylovMax + 2));
+  }
   // partial sums: the largest residual launch is on level 0
   {
     const Level& l = lv[0];
@@ -706,6 +716,7 @@ double Solver::norm_u0_b(const double* u0) {
 // initial guess and receives the result.
 int Solver::solve_linear(bool adj, int react, const double* f, const double* u0, double* U,
                          double rtol, double norm_b, int* cycles, double* rel_out, int* refinements) {
+  if (opt.krylov > 0) return solve_fgmres(adj, react, f, u0, U, rtol, norm_b, cycles, rel_out);
   Level& L0 = lv[0];
   const OpParams& op0 = adj ? L0.opT : L0.op;
   // FP64 with pre-smoothing: the first sweep of every cycle also returns
@@ -863,6 +874,167 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
   if (status != STMG_OK) {
     set_error(std::string("linear solve stopped: ") + stmg_status_string(status));
   }
+  return status;
+}
+
+// Restarted flexible GMRES (Saad, 1993) on A U = b with one V-cycle from a
+// zero guess as the right preconditioner: the paper stops its multigrid runs
+// on a preconditioned Krylov residual (Sec. 5).  The minimised residual is
+// the true one, ||b - A U||, so the stop test is the plain iteration's.
+//
+// Storage and scaling: basis vectors are kept unnormalised (V_i raw, with
+// v_i = V_i / ||V_i||); the host holds 1 / ||V_i||^2.  Step j runs the
+// preconditioner on V_j into Z_j and the residual kernel on Z_j with no
+// right-hand side, W = -A Z_j, so the direction taken is zhat_j = -Z_j and
+// A zhat_j = W.  Then h_ij = (W, v_i) and the projections W -= h_ij v_i are
+// W -= (W, V_i) / ||V_i||^2 V_i.  Classical Gram-Schmidt, whose dot products
+// are fused into the projection pass, repeated when the projection removed
+// more than half of ||W||^2 (Daniel, Gragg, Kaufman, Stewart 1976); the
+// remainder, unnormalised, is V_{j+1}.  The (m + 1) x m Hessenberg matrix is
+// reduced by Givens rotations on the host; the estimate |g_{j+1}| ends the
+// cycle, U += sum_j y_j zhat_j, and the true residual of the new U starts the
+// next cycle or ends the solve.  Host waits: one per step, two when the
+// second Gram-Schmidt pass runs, one per restart.
+int Solver::solve_fgmres(bool adj, int react, const double* f, const double* u0, double* U,
+                         double rtol, double norm_b, int* cycles, double* rel_out) {
+  Level& L0 = lv[0];
+  const int m = opt.krylov;
+  const size_t n = L0.n;
+  constexpr int kCol = kKrylovMax + 2;
+  HIP_CHECK(kh.init(1 + 3 * kCol));
+  double* const hres = kh.h;
+  double* const h1 = kh.h + 1;
+  double* const h2 = h1 + kCol;
+  double* const h3 = h2 + kCol;
+  double* const m1 = kh.d + 1;
+  double* const m2 = m1 + kCol;
+  double* const m3 = m2 + kCol;
+  double* const d1 = kdev + 1;
+  double* const d2 = d1 + kCol;
+  double* const d3 = d2 + kCol;
+  double* Vb[kKrylovMax + 1];
+  double* Zb[kKrylovMax + 1];
+  for (int i = 0; i <= m; ++i) {
+    Vb[i] = kV + static_cast<size_t>(i) * n;
+    Zb[i] = kZ + static_cast<size_t>(i) * n;
+  }
+  KVecs Vs{};
+  for (int i = 0; i <= m; ++i) Vs.v[i] = Vb[i];
+  const double scale = norm_b > 0.0 ? norm_b : 1.0;
+  std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), inv2(m + 1);
+  auto Hs = [&](int i, int j) -> double& { return H[static_cast<size_t>(i) * m + j]; };
+  auto wait = [&]() -> hipError_t {
+    HIP_TRY(hipEventRecord(kh.ev, stream));
+    return hipEventSynchronize(kh.ev);
+  };
+  // z_j = M^-1 V_j: one V-cycle from zero (FP32 on a unit-norm copy of V_j in
+  // mixed precision)
+  auto precondition = [&](int j) -> hipError_t {
+    if (!mixed) {
+      double* res = nullptr;
+      HIP_TRY(vcycle<double>(0, adj, react, Zb[j], Zb[m], Vb[j], nullptr, true, &res, 0));
+      if (res == Zb[m]) std::swap(Zb[j], Zb[m]);
+      else if (res != Zb[j]) return hipErrorInvalidValue;
+      return hipSuccess;
+    }
+    HIP_TRY((launch_axpy_cast<double, float>(n, Vb[j], std::sqrt(inv2[j]), L0.f32, false, stream)));
+    float* res = nullptr;
+    HIP_TRY(vcycle<float>(0, adj, react, L0.A32, L0.B32, L0.f32, nullptr, true, &res, 0));
+    if (!res) return hipErrorInvalidValue;
+    return launch_axpy_cast<float, double>(n, res, 1.0, Zb[j], false, stream);
+  };
+  int steps = 0;
+  int status = STMG_OK;
+  double rel = 0.0;
+  // cycles in a row that the least-squares estimate ended (estimate <=
+  // rtol) while the true residual of the updated iterate stayed above rtol:
+  // the estimate keeps falling in exact arithmetic, the true residual stops
+  // at its rounding floor, so two misses in a row mean rtol is below it
+  bool est_done = false;
+  int miss = 0;
+  for (;;) {
+    // r = b - A U is the first (unnormalised) basis vector
+    HIP_CHECK(residual64<double>(adj, react, U, f, u0, Vb[0], kh.d));
+    HIP_CHECK(wait());
+    const double beta = std::sqrt(*hres);
+    rel = beta / scale;
+    if (!std::isfinite(rel)) { status = STMG_ENAN; break; }
+    if (rel <= rtol || beta == 0.0) break;
+    if (steps >= opt.max_cycles) { status = STMG_ENOTCONV; break; }
+    miss = est_done ? miss + 1 : 0;
+    if (miss >= 2) { status = STMG_ENOTCONV; break; }
+    est_done = false;
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    inv2[0] = 1.0 / (beta * beta);
+    int k = 0;
+    bool bad = false;
+    for (int j = 0; j < m; ++j) {
+      HIP_CHECK(precondition(j));
+      HIP_CHECK(residual64<double>(adj, react, Zb[j], nullptr, nullptr, Vb[j + 1], kdev));
+      KCoef s{};
+      for (int i = 0; i <= j; ++i) s.c[i] = inv2[i];
+      int nb = 0;
+      // pass 1: (W, V_i) and ||W||^2; pass 2: project, and the same again
+      HIP_CHECK(launch_kortho(Vb[j + 1], Vs, j + 1, s, nullptr, n, true, kpart, &nb, stream));
+      HIP_CHECK(launch_kreduce(kpart, nb, j + 2, d1, m1, stream));
+      HIP_CHECK(launch_kortho(Vb[j + 1], Vs, j + 1, s, d1, n, true, kpart, &nb, stream));
+      HIP_CHECK(launch_kreduce(kpart, nb, j + 2, d2, m2, stream));
+      HIP_CHECK(wait());
+      double hcol[kKrylovMax + 1];
+      for (int i = 0; i <= j; ++i) hcol[i] = h1[i];
+      double nw2 = h2[j + 1];
+      if (nw2 < 0.5 * h1[j + 1]) {
+        // pass 3: project out the pass-2 components
+        HIP_CHECK(launch_kortho(Vb[j + 1], Vs, j + 1, s, d2, n, false, kpart, &nb, stream));
+        HIP_CHECK(launch_kreduce(kpart + static_cast<size_t>(j + 1) * nb, nb, 1, d3 + j + 1, m3 + j + 1,
+                                 stream));
+        HIP_CHECK(wait());
+        for (int i = 0; i <= j; ++i) hcol[i] += h2[i];
+        nw2 = h3[j + 1];
+      }
+      for (int i = 0; i <= j; ++i) Hs(i, j) = std::sqrt(inv2[i]) * hcol[i];
+      const double hn = std::sqrt(nw2);
+      Hs(j + 1, j) = hn;
+      ++steps;
+      k = j + 1;
+      // apply the earlier rotations to column j, then eliminate H(j+1, j)
+      for (int i = 0; i < j; ++i) {
+        const double a = Hs(i, j), b = Hs(i + 1, j);
+        Hs(i, j) = cs[i] * a + sn[i] * b;
+        Hs(i + 1, j) = -sn[i] * a + cs[i] * b;
+      }
+      const double a = Hs(j, j), b = Hs(j + 1, j);
+      const double r = std::hypot(a, b);
+      if (!std::isfinite(r)) { bad = true; break; }
+      cs[j] = r > 0.0 ? a / r : 1.0;
+      sn[j] = r > 0.0 ? b / r : 0.0;
+      Hs(j, j) = r;
+      Hs(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      if (std::fabs(g[j + 1]) <= rtol * scale) { est_done = true; break; }
+      if (steps >= opt.max_cycles || hn == 0.0) break;
+      inv2[j + 1] = 1.0 / nw2;
+    }
+    if (bad) { status = STMG_ENAN; rel = std::numeric_limits<double>::quiet_NaN(); break; }
+    // y = R^-1 g, U += sum_j y_j zhat_j = U - sum_j y_j Z_j
+    KCoef y{};
+    for (int i = k - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int q = i + 1; q < k; ++q) t -= Hs(i, q) * y.c[q];
+      y.c[i] = Hs(i, i) != 0.0 ? t / Hs(i, i) : 0.0;
+    }
+    KVecs Zs{};
+    for (int i = 0; i < k; ++i) {
+      Zs.v[i] = Zb[i];
+      y.c[i] = -y.c[i];
+    }
+    HIP_CHECK(launch_kcombine(U, Zs, k, y, n, stream));
+  }
+  *cycles += steps;
+  *rel_out = rel;
+  if (status != STMG_OK) set_error(std::string("Krylov solve stopped: ") + stmg_status_string(status));
   return status;
 }
 

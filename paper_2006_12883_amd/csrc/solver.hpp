@@ -55,6 +55,7 @@ struct Plan {
 struct HostScalar {
   double* h = nullptr;
   double* d = nullptr;
+  size_t cap = 0;  // doubles
   hipEvent_t ev = nullptr;
   HostScalar() = default;
   HostScalar(const HostScalar&) = delete;
@@ -63,11 +64,19 @@ struct HostScalar {
     if (ev) (void)hipEventDestroy(ev);
     if (h) (void)hipHostFree(h);
   }
-  hipError_t init() {
+  hipError_t init(size_t count = 1) {
+    if (h && cap < count) {
+      // callers only grow the slot count before queuing work that uses it
+      (void)hipHostFree(h);
+      h = nullptr;
+      d = nullptr;
+      cap = 0;
+    }
     if (!h) {
-      hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(double),
+      hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h), count * sizeof(double),
                                    hipHostMallocMapped | hipHostMallocCoherent);
       if (e != hipSuccess) { h = nullptr; return e; }
+      cap = count;
       e = hipHostGetDevicePointer(reinterpret_cast<void**>(&d), h, 0);
       if (e != hipSuccess) return e;
     }
@@ -107,6 +116,16 @@ struct Solver {
   double* fft_tw = nullptr;
   double* fft_work = nullptr;   // 2 (N M + 1) P
   double* delta64 = nullptr;  // Newton correction / adjoint multiplier (level 0, FP64)
+  // Flexible GMRES (opt.krylov = m > 0): m + 1 basis vectors and m + 1
+  // direction buffers (one spare for the V-cycle's ping-pong) on level 0,
+  // block partials, and the dot products of the Gram-Schmidt passes on the
+  // device (kdev) with a host-visible mirror (kh), both laid out as
+  // [restart norm | pass 1 | pass 2 | pass 3], kKrylovMax + 2 slots a pass.
+  double* kV = nullptr;
+  double* kZ = nullptr;
+  double* kpart = nullptr;
+  double* kdev = nullptr;
+  HostScalar kh;
   double* lw = nullptr;       // M weights l(0) on the device (gradient of u0)
   // statistics of the last solve
   stmg_stats last{};
@@ -195,6 +214,8 @@ struct Solver {
   // --- drivers ---
   int solve_linear(bool adj, int react, const double* f, const double* u0, double* U,
                    double rtol, double norm_b, int* cycles, double* rel, int* refinements = nullptr);
+  int solve_fgmres(bool adj, int react, const double* f, const double* u0, double* U, double rtol,
+                   double norm_b, int* cycles, double* rel);
   int solve(const double* u0, double* U, stmg_stats* st);
   int vcycle_user(const double* u0, double* U, double* h_rel);
   int residual_user(const double* u0, const double* U, double* r, double* h_norm);

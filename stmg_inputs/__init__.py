@@ -40,6 +40,35 @@ def config(name):
     raise KeyError(name)
 
 
+# The paper's 1D examples (Sec. 5): X = 1, N_x = 1024 elements, Neumann, and
+# N_t per M from its table headers.
+PAPER_NT = {1: 1024, 2: 256, 3: 32, 4: 16, 5: 8}
+
+
+def paper_heat1d(M, nx=1024):
+    """Heat equation (gamma = 0), T = 1, N_t from the table headers."""
+    return problem(1, nx, M, PAPER_NT[M], 1.0, nu=1.0, bc="neumann")
+
+
+def u0_paper_heat1d(prob):
+    """cos(pi x) + 2 cos(3 pi x) + 3 cos(4 pi x) on [0, 1]."""
+    X, _ = coords(prob)
+    return np.cos(np.pi * X) + 2 * np.cos(3 * np.pi * X) + 3 * np.cos(4 * np.pi * X)
+
+
+def paper_monodomain(M, nx=1024):
+    """Monodomain example: X = 10, T = 2, gamma = 5, N_t from the table headers."""
+    return problem(1, nx, M, PAPER_NT[M], 2.0, nu=1.0, gamma=5.0, reaction="allen_cahn", bc="neumann",
+                   length=10.0)
+
+
+def u0_paper_monodomain(prob):
+    """Narrow stimulus in the middle of [0, X]: 2 exp(-((x - X/2) / 0.1)^2)."""
+    X, _ = coords(prob)
+    L = prob["length"][0]
+    return 2.0 * np.exp(-((X - 0.5 * L) / 0.1) ** 2)
+
+
 def grid_points(prob):
     nx = prob["nx"][0] + (0 if prob["bc"] == "periodic" else 1)
     ny = 1 if prob["dim"] == 1 else prob["nx"][1] + (0 if prob["bc"] == "periodic" else 1)

@@ -37,6 +37,13 @@ def test_workspace_and_validation():
         assert B.lib().stmg_workspace_bytes(ctypes.byref(B.make_problem(bad)),
                                             ctypes.byref(B.make_options())) == 0
     assert B.lib().stmg_setup(None, None, None, 0, None, None) == B.STMG_EINVAL
+    for bad in (-1, 33):
+        assert B.lib().stmg_workspace_bytes(ctypes.byref(B.make_problem(prob)),
+                                            ctypes.byref(B.make_options(krylov=bad))) == 0
+    # the Krylov method adds 2 (m + 1) level-0 FP64 vectors
+    m = 4
+    extra = B.workspace_bytes(prob, krylov=m) - n
+    assert extra >= 2 * (m + 1) * 8 * 256 * 256 * 3 * 256
 
 
 def test_options_defaults():
@@ -44,3 +51,4 @@ def test_options_defaults():
     assert o.omega == 0.8 and o.chunk == 16 and o.chunk_coarse == 4 and o.nu_pre == 1 and o.nu_post == 1
     assert o.mu_crit == 0.5
     assert o.rtol == 1e-12 and o.coarsen == 0 and o.precision == 0
+    assert o.krylov == 0

@@ -1,0 +1,167 @@
+"""Flexible GMRES around the V-cycle (option krylov = restart length) against
+the oracle's FGMRES step by step, and on the paper's 1D workloads."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import stmg_inputs as si
+from oracle import adjoint, krylov, stepper
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from gpu_util import H, T, assert_close, rel_err  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_heat_table.json")
+SMALL = si.problem(1, 32, 3, 8, 0.5, nu=1.0)
+HIER = dict(fft_coarse=0, min_coarse=16)
+
+
+@pytest.mark.parametrize("coarsen", ["space", "smmg", "spacetime"])
+@pytest.mark.parametrize("k", [1, 2, 4, 7, 12])
+def test_fgmres_steps_match_oracle(coarsen, k):
+    """After k Krylov steps (restart 5, so k = 7 and 12 cross restarts) the
+    iterate and its residual match the oracle's FGMRES."""
+    print("case fgmres steps", coarsen, k, flush=True)
+    u0 = si.u0_heat1d(SMALL)
+    ref, hist, steps = krylov.solve(SMALL, u0, rtol=0.0, restart=5, max_steps=k, coarsen=coarsen, **HIER)
+    assert steps == k
+    h = H(SMALL, coarsen=coarsen, krylov=5, max_cycles=k, rtol=1e-30, **HIER)
+    U, st = h.solve(T(u0), check=False)
+    assert st["cycles"] == k and st["status"] == -4
+    assert_close(U.cpu().numpy(), ref, 1e-9, "iterate after %d steps" % k)
+    assert abs(st["rel_res"] - hist[-1]) <= 1e-7 * hist[-1] + 1e-14, (st["rel_res"], hist[-1])
+
+
+@pytest.mark.parametrize("restart", [1, 3, 10, 32])
+def test_fgmres_converges_to_stepper(restart):
+    print("case fgmres restart", restart, flush=True)
+    prob = si.problem(2, 64, 3, 32, 0.5, nu=1e-2, lam=1.0)
+    u0 = si.u0_rd2d(prob, 2)
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob, krylov=restart).solve(T(u0))
+    assert st["status"] == 0 and st["rel_res"] <= 1e-12
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-10
+    _, plain = H(prob).solve(T(u0))
+    if restart >= 3:
+        assert st["cycles"] < plain["cycles"], (st["cycles"], plain["cycles"])
+
+
+def test_fgmres_spacetime_where_vcycles_diverge():
+    """Full space-time coarsening at mu = 64: the plain iteration diverges,
+    FGMRES(30) around the same cycle converges to the stepper's solution."""
+    print("case fgmres spacetime", flush=True)
+    u0 = si.u0_heat1d(SMALL)
+    ref = stepper.solve_linear(SMALL, u0)
+    _, plain = H(SMALL, coarsen="spacetime", **HIER).solve(T(u0), check=False)
+    assert plain["status"] != 0
+    U, st = H(SMALL, coarsen="spacetime", krylov=30, max_cycles=400, **HIER).solve(T(u0))
+    assert st["status"] == 0
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-10
+
+
+def test_fgmres_mixed_precision():
+    """FP32 V-cycles as the (variable) preconditioner of FP64 FGMRES."""
+    print("case fgmres mixed", flush=True)
+    prob = si.problem(2, 64, 3, 32, 0.5, nu=1e-2, lam=1.0)
+    u0 = si.u0_rd2d(prob, 2)
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob, krylov=10, precision="mixed", rtol=1e-11).solve(T(u0))
+    assert st["status"] == 0 and st["rel_res"] <= 1e-11
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fgmres_newton(prec):
+    print("case fgmres newton", prec, flush=True)
+    prob = si.problem(1, 64, 3, 16, 0.5, nu=1e-2, gamma=5.0, reaction="allen_cahn")
+    u0 = np.random.default_rng(3).uniform(-0.1, 0.1, (1, 64))
+    ref = stepper.solve_allen_cahn(prob, u0)
+    tol = 1e-12 if prec == "fp64" else 1e-10
+    U, st = H(prob, krylov=8, precision=prec, newton_rtol=tol).solve(T(u0))
+    assert st["status"] == 0 and st["newton_its"] >= 2
+    assert rel_err(U.cpu().numpy(), ref) <= (1e-10 if prec == "fp64" else 1e-9)
+
+
+def test_fgmres_adjoint():
+    print("case fgmres adjoint", flush=True)
+    prob = si.problem(2, 32, 3, 16, 0.5, nu=1e-2, lam=1.0)
+    ny, nx = si.grid_points(prob)
+    rng = np.random.default_rng(7)
+    u0 = rng.standard_normal((ny, nx))
+    tgt = rng.standard_normal((ny, nx))
+    h = H(prob, krylov=6)
+    U, st = h.solve(T(u0))
+    assert st["status"] == 0
+    gu0, gnu, ast = h.adjoint(U, 2.0 * (U[-1, -1] - T(tgt)))
+    assert ast["status"] == 0
+    ref_g, ref_nu = adjoint.gradients(prob, u0, tgt)
+    assert rel_err(gu0.cpu().numpy(), ref_g) <= 1e-9
+    assert abs(gnu - ref_nu) <= 1e-9 * max(1.0, abs(ref_nu))
+
+
+def _exact_heat(prob):
+    X, _ = si.coords(prob)
+    return (np.cos(np.pi * X) * np.exp(-np.pi ** 2) + 2 * np.cos(3 * np.pi * X) * np.exp(-9 * np.pi ** 2)
+            + 3 * np.cos(4 * np.pi * X) * np.exp(-16 * np.pi ** 2))
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 4, 5])
+def test_paper_heat1d(M):
+    """The paper's heat example (N_x = 1024, N_t from its tables, stop at
+    1e-9): FGMRES around 7-level SMG cycles meets the paper's accuracy at T
+    (max error below 1e-9 against the analytic solution for M >= 2), agrees
+    with the sequential stepper, and takes fewer steps than the plain
+    iteration."""
+    coarsen = "space"
+    print("case paper heat1d", M, coarsen, flush=True)
+    g = json.load(open(GOLD))
+    prob = si.paper_heat1d(M)
+    nt = g["M1"]["Nt"] if M == 1 else g["nt_by_M"][str(M)]
+    assert prob["N"] == nt and prob["nx"][0] == g["Nx"]
+    u0 = si.u0_paper_heat1d(prob)
+    kw = dict(coarsen=coarsen, max_levels=7, max_cycles=300)
+    # the rounding floor of ||b - A U|| / ||b|| is near 1e-11 here (entries of
+    # A up to dt nu / h^2 ~ 6e4)
+    U, st = H(prob, krylov=10, rtol=1e-10, **kw).solve(T(u0))
+    assert st["status"] == 0
+    uT = U[-1, -1].cpu().numpy()
+    err = np.abs(uT - _exact_heat(prob)).max()
+    if M == 1:
+        # backward Euler at N_t = 1024: about 1e-6 (the paper's footnote)
+        assert 0.1 * g["M1"]["err_order_of_magnitude"] < err < 10 * g["M1"]["err_order_of_magnitude"]
+    else:
+        assert err < g["tol"]
+    ref = stepper.solve_linear(prob, u0)
+    assert np.abs(uT - ref[-1, -1]).max() <= 1e-10
+    # steps to the paper's tolerance, against the plain iteration
+    _, kst = H(prob, krylov=10, rtol=1e-9, **kw).solve(T(u0))
+    _, plain = H(prob, rtol=1e-9, **kw).solve(T(u0))
+    assert plain["status"] == 0 and kst["status"] == 0 and kst["cycles"] <= plain["cycles"]
+
+
+def test_paper_monodomain_m3():
+    """The paper's monodomain example (X = 10, T = 2, gamma = 5, M = 3,
+    N_t = 32): Newton with FGMRES around SMG cycles against the stepper."""
+    print("case paper monodomain", flush=True)
+    prob = si.paper_monodomain(3)
+    u0 = si.u0_paper_monodomain(prob)
+    # h = 10/1024 puts the rounding floor of the stepper's Newton residual
+    # near 1e-13, so its stop test is 1e-12 here
+    ref = stepper.solve_allen_cahn(prob, u0, tol=1e-12)
+    U, st = H(prob, krylov=10, coarsen="space", max_levels=7, newton_rtol=1e-10).solve(T(u0))
+    assert st["status"] == 0
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-8
+
+
+def test_fgmres_stops_at_rounding_floor():
+    """A tolerance below the rounding floor ends after three restarts without
+    progress, not after max_cycles."""
+    print("case fgmres floor", flush=True)
+    prob = si.paper_heat1d(4)
+    u0 = si.u0_paper_heat1d(prob)
+    U, st = H(prob, krylov=10, coarsen="space", max_levels=7, rtol=1e-16, max_cycles=1000).solve(
+        T(u0), check=False)
+    assert st["status"] == -4 and st["cycles"] < 100 and st["rel_res"] <= 1e-9, st
