@@ -184,14 +184,15 @@ hipError_t launch_sdc_update(double* U, double* acc, const double* d, int N, int
 // Flexible GMRES on level 0 (FP64).  A set of up to kKrylovMax + 1
 // vectors of n doubles and one coefficient per vector, both passed by value.
 constexpr int kKrylovMax = 32;
-constexpr int kKrylovParts = 1024;  // upper bound on the blocks of one Krylov pass
+constexpr int kKrylovParts = 4096;  // upper bound on the blocks of one Krylov pass
 struct KVecs {
   const double* v[kKrylovMax + 1];
 };
 struct KCoef {
   double c[kKrylovMax + 1];
 };
-// One Gram-Schmidt pass of w against V_0..V_{k-1} (k <= kKrylovMax + 1):
+// One Gram-Schmidt pass of w against V_0..V_{k-1} (k <= kKrylovMax + 1;
+// w and every V_i 16-byte aligned):
 // when d is given, w -= sum_i s.c[i] d[i] V_i (d on the device, typically the
 // previous pass's dot products, s the host's 1 / ||V_i||^2); then per-block
 // partials of (w, V_i) for i < k (when dots) in part[i * nb + block] and of

@@ -15,7 +15,9 @@ inline int kgrid(size_t n) {
   return static_cast<int>(b);
 }
 
-// KM: compile-time bound on k (accumulators live in registers).
+// KM: compile-time bound on k (accumulators live in registers).  Each thread
+// takes two consecutive doubles per step (16-byte loads); an odd last element
+// is taken by thread 0 of block 0.
 template <int KM>
 __global__ __launch_bounds__(kBlock) void k_kortho(double* __restrict__ w, const KVecs V, int k,
                                                    const KCoef s, const double* __restrict__ d,
@@ -31,8 +33,29 @@ __global__ __launch_bounds__(kBlock) void k_kortho(double* __restrict__ w, const
   double acc[KM + 1];
 #pragma unroll
   for (int i = 0; i <= KM; ++i) acc[i] = 0.0;
+  const size_t n2 = n >> 1;
   const size_t stride = static_cast<size_t>(gridDim.x) * kBlock;
-  for (size_t e = static_cast<size_t>(blockIdx.x) * kBlock + threadIdx.x; e < n; e += stride) {
+  for (size_t e = static_cast<size_t>(blockIdx.x) * kBlock + threadIdx.x; e < n2; e += stride) {
+    double2 x = reinterpret_cast<const double2*>(w)[e];
+    double2 v[KM];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) {
+      if (i < k) {
+        v[i] = reinterpret_cast<const double2*>(V.v[i])[e];
+        x.x -= s_coef[i] * v[i].x;
+        x.y -= s_coef[i] * v[i].y;
+      }
+    }
+    if (upd) reinterpret_cast<double2*>(w)[e] = x;
+    if (dots) {
+#pragma unroll
+      for (int i = 0; i < KM; ++i)
+        if (i < k) acc[i] += x.x * v[i].x + x.y * v[i].y;
+    }
+    acc[KM] += x.x * x.x + x.y * x.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const size_t e = n - 1;
     double x = w[e];
     double v[KM];
 #pragma unroll
@@ -83,6 +106,27 @@ __global__ __launch_bounds__(kBlock) void k_kreduce(const double* __restrict__ p
   }
 }
 
+// Two consecutive doubles per thread and step (all pointers 16-byte aligned).
+__global__ __launch_bounds__(kBlock) void k_kcombine2(double* __restrict__ x, const KVecs Z, int k,
+                                                      const KCoef y, size_t n) {
+  const size_t n2 = n >> 1;
+  const size_t stride = static_cast<size_t>(gridDim.x) * kBlock;
+  for (size_t e = static_cast<size_t>(blockIdx.x) * kBlock + threadIdx.x; e < n2; e += stride) {
+    double2 t = reinterpret_cast<const double2*>(x)[e];
+    for (int i = 0; i < k; ++i) {
+      const double2 z = reinterpret_cast<const double2*>(Z.v[i])[e];
+      t.x += y.c[i] * z.x;
+      t.y += y.c[i] * z.y;
+    }
+    reinterpret_cast<double2*>(x)[e] = t;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double t = x[n - 1];
+    for (int i = 0; i < k; ++i) t += y.c[i] * Z.v[i][n - 1];
+    x[n - 1] = t;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_kcombine(double* __restrict__ x, const KVecs Z, int k,
                                                      const KCoef y, size_t n) {
   const size_t stride = static_cast<size_t>(gridDim.x) * kBlock;
@@ -98,7 +142,10 @@ __global__ __launch_bounds__(kBlock) void k_kcombine(double* __restrict__ x, con
 hipError_t launch_kortho(double* w, const KVecs& V, int k, const KCoef& s, const double* d, size_t n,
                          bool dots, double* part, int* nb, hipStream_t st) {
   if (k < 0 || k > kKrylovMax + 1) return hipErrorInvalidValue;
-  const int g = kgrid(n);
+  if (reinterpret_cast<uintptr_t>(w) & 15) return hipErrorInvalidValue;
+  for (int i = 0; i < k; ++i)
+    if (reinterpret_cast<uintptr_t>(V.v[i]) & 15) return hipErrorInvalidValue;
+  const int g = kgrid(n >> 1);
   *nb = g;
   const int df = dots ? 1 : 0;
   if (k <= 8)
@@ -120,7 +167,12 @@ hipError_t launch_kreduce(const double* part, int nb, int cols, double* out, dou
 hipError_t launch_kcombine(double* x, const KVecs& Z, int k, const KCoef& y, size_t n, hipStream_t st) {
   if (k < 1) return hipSuccess;
   if (k > kKrylovMax + 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_kcombine, dim3(grid_for(n)), dim3(kBlock), 0, st, x, Z, k, y, n);
+  bool aligned = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+  for (int i = 0; i < k; ++i) aligned = aligned && (reinterpret_cast<uintptr_t>(Z.v[i]) & 15) == 0;
+  if (aligned)
+    hipLaunchKernelGGL(k_kcombine2, dim3(grid_for(n >> 1)), dim3(kBlock), 0, st, x, Z, k, y, n);
+  else
+    hipLaunchKernelGGL(k_kcombine, dim3(grid_for(n)), dim3(kBlock), 0, st, x, Z, k, y, n);
   return hipGetLastError();
 }
 

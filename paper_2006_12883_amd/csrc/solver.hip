@@ -343,8 +343,9 @@ size_t Solver::plan(char* ws) {
   delta64 = pl.take<double>(lv[0].n);
   if (opt.krylov > 0) {
     const size_t vecs = static_cast<size_t>(opt.krylov) + 1;
-    kV = pl.take<double>(vecs * lv[0].n);
-    kZ = pl.take<double>(vecs * lv[0].n);
+    kstride = (lv[0].n + 31) & ~static_cast<size_t>(31);
+    kV = pl.take<double>(vecs * kstride);
+    kZ = pl.take<double>(vecs * kstride);
     kpart = pl.take<double>(static_cast<size_t>(kKrylovParts) * (kKrylovMax + 2));
     kdev = pl.take<double>(1 + 3 * (kKrylovMax + 2));
   }
@@ -915,8 +916,8 @@ int Solver::solve_fgmres(bool adj, int react, const double* f, const double* u0,
   double* Vb[kKrylovMax + 1];
   double* Zb[kKrylovMax + 1];
   for (int i = 0; i <= m; ++i) {
-    Vb[i] = kV + static_cast<size_t>(i) * n;
-    Zb[i] = kZ + static_cast<size_t>(i) * n;
+    Vb[i] = kV + static_cast<size_t>(i) * kstride;
+    Zb[i] = kZ + static_cast<size_t>(i) * kstride;
   }
   KVecs Vs{};
   for (int i = 0; i <= m; ++i) Vs.v[i] = Vb[i];

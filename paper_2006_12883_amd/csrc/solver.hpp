@@ -123,6 +123,7 @@ struct Solver {
   // [restart norm | pass 1 | pass 2 | pass 3], kKrylovMax + 2 slots a pass.
   double* kV = nullptr;
   double* kZ = nullptr;
+  size_t kstride = 0;  // doubles between consecutive vectors (256-byte multiple)
   double* kpart = nullptr;
   double* kdev = nullptr;
   HostScalar kh;

@@ -165,3 +165,16 @@ def test_fgmres_stops_at_rounding_floor():
     U, st = H(prob, krylov=10, coarsen="space", max_levels=7, rtol=1e-16, max_cycles=1000).solve(
         T(u0), check=False)
     assert st["status"] == -4 and st["cycles"] < 100 and st["rel_res"] <= 1e-9, st
+
+
+def test_fgmres_odd_length():
+    """31 points x M = 3 x N = 5: an odd vector length (the vector kernels'
+    tail element)."""
+    print("case fgmres odd", flush=True)
+    prob = si.problem(1, 30, 3, 5, 0.2, nu=1.0, bc="neumann")
+    u0 = si.u0_paper_heat1d(prob)
+    assert np.prod(si.grid_points(prob)) * 3 * 5 % 2 == 1
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob, krylov=4, coarsen="space").solve(T(u0))
+    assert st["status"] == 0
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-10
