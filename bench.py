@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE runs (scaled by a device copy of known size; see
 # profiles/k_smooth_blk_rd2d_level0.md), valid only for the kernel source it
 # was measured on.
-TRAFFIC = {"kernels_impl_sha256_prefix": "c8b7aafb6845ae61", "bytes_per_launch": 456.27e6 + 402.65e6}
+TRAFFIC = {"kernels_impl_sha256_prefix": "a31422999b0b07ad", "bytes_per_launch": 432.12e6 + 402.65e6}
 
 
 def measured_traffic():
@@ -206,7 +206,75 @@ def extras(dev):
         torch.cuda.empty_cache()
     out["hierarchies_rd2d_fp64_to_1e-10"] = variants
     print("hierarchies done", file=sys.stderr, flush=True)
+    # flexible GMRES around the same V-cycle on the 256^2 workload
+    kry = {}
+    for m in (0, 5, 10):
+        h = stmg.Handle(prob, device=dev, krylov=m, rtol=1e-10)
+        U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
+        _, st, t = _timed_solve(h, u0, U)
+        kry["plain" if m == 0 else "fgmres%d" % m] = {"seconds": t, "status": st["status"],
+                                                      "vcycles": st["cycles"], "rel_res": st["rel_res"]}
+        del h, U
+        torch.cuda.empty_cache()
+    out["krylov_rd2d_fp64_to_1e-10"] = kry
+    print("krylov done", file=sys.stderr, flush=True)
+    out["paper_examples_1d"] = paper_examples(dev)
+    print("paper examples done", file=sys.stderr, flush=True)
     return out
+
+
+def _timed_solve(h, u0, U):
+    import torch
+    h.solve(u0, U, check=False)
+    U.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = h.solve(u0, U, check=False)
+    torch.cuda.synchronize()
+    return U, st, time.perf_counter() - t0
+
+
+def paper_examples(dev):
+    """The paper's 1D examples (Sec. 5) on one GPU: the heat example with
+    N_x = 1024 and N_t per M from its tables, stopped at 1e-9, with the
+    paper's hierarchies (SMG and SMMG 7 levels, STMG 5 levels), plain cycles
+    and flexible GMRES around them; and the monodomain example (X = 10,
+    T = 2, gamma = 5) with Newton around SMG.  Iteration counts and times are
+    context: the paper smooths with ILU(0)-preconditioned GMRES on CPU cores."""
+    import torch
+    import stmg_inputs as si
+    from paper_2006_12883_amd import stmg
+    heat = {}
+    runs = [("SMG7_V11", "space", 7, 0, 1), ("SMG7_V11_fgmres10", "space", 7, 10, 1),
+            ("SMG7_V33", "space", 7, 0, 3), ("SMG7_V33_fgmres10", "space", 7, 10, 3),
+            ("SMMG7_V33_fgmres30", "smmg", 7, 30, 3), ("STMG5_V33_fgmres30", "spacetime", 5, 30, 3)]
+    for M in (1, 2, 3, 4, 5):
+        prob = si.paper_heat1d(M)
+        u0 = torch.as_tensor(si.u0_paper_heat1d(prob)).to(dev)
+        row = {}
+        for name, coarsen, levels, m, nu in runs:
+            if coarsen == "smmg" and M == 1:
+                continue
+            h = stmg.Handle(prob, device=dev, coarsen=coarsen, max_levels=levels, krylov=m, nu_pre=nu,
+                            nu_post=nu, rtol=1e-9, max_cycles=300)
+            U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
+            _, st, t = _timed_solve(h, u0, U)
+            row[name] = {"ms": 1e3 * t, "status": st["status"], "vcycles": st["cycles"],
+                         "rel_res": st["rel_res"]}
+            del h, U
+        heat["M%d_Nt%d" % (M, prob["N"])] = row
+    mono = {}
+    for M in (1, 2, 3, 4, 5):
+        prob = si.paper_monodomain(M)
+        u0 = torch.as_tensor(si.u0_paper_monodomain(prob)).to(dev)
+        h = stmg.Handle(prob, device=dev, coarsen="space", max_levels=7, krylov=10, nu_pre=3, nu_post=3,
+                        newton_rtol=1e-9, max_cycles=2000)
+        U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
+        _, st, t = _timed_solve(h, u0, U)
+        mono["M%d_Nt%d" % (M, prob["N"])] = {"ms": 1e3 * t, "status": st["status"], "newton_its": st["newton_its"],
+                                            "vcycles": st["cycles"], "rel_res": st["rel_res"]}
+        del h, U
+    return {"heat_Nx1024_to_1e-9": heat, "monodomain_SMG7_V33_fgmres10_to_1e-9": mono}
 
 
 def main():
