@@ -124,6 +124,17 @@ template <typename T>
 hipError_t launch_coarse_solve_coef(const OpParams& p, const T* coef, double* scratch,
                                     const T* f, const double* u0, T* U, hipStream_t s);
 
+// The same, with the per-slab matrices inverted once per linearization:
+// W holds N blocks [A_n | A_n^{-1}] (K x 2K each, coarse_inverse_doubles(p)
+// doubles).  launch_coarse_invert_coef builds and inverts them (one workgroup
+// per slab); launch_coarse_solve_slabs runs the slab recurrence with them.
+size_t coarse_inverse_doubles(const OpParams& p);
+template <typename T>
+hipError_t launch_coarse_invert_coef(const OpParams& p, const T* coef, double* W, hipStream_t s);
+template <typename T>
+hipError_t launch_coarse_solve_slabs(const OpParams& p, const double* W, const T* f, const double* u0, T* U,
+                                     hipStream_t s);
+
 // out[0] = sum of part[0..n) in a fixed order (one workgroup).
 hipError_t launch_sum_partials(const double* part, int n, double* out, hipStream_t s);
 

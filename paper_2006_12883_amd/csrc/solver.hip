@@ -17,6 +17,7 @@ namespace stmg {
 namespace {
 
 constexpr int kResidSlabs = 8;   // slabs per thread in residual sweeps
+constexpr size_t kCoarseInvMaxBytes = size_t(1) << 30;  // Newton coarsest inverses
 constexpr int kTransferSlabs = 4;
 
 // Elements -> points per dimension.
@@ -374,6 +375,11 @@ size_t Solver::plan(char* ws) {
     AinvT = pl.take<double>(K * K);
   }
   coarse_scratch = allen_cahn ? pl.take<double>(K * K) : nullptr;
+  coarse_inv = nullptr;
+  if (allen_cahn && !batch_member) {
+    const size_t d = coarse_inverse_doubles(c.op);
+    if (d * sizeof(double) <= kCoarseInvMaxBytes) coarse_inv = pl.take<double>(d);
+  }
   lw = pl.take<double>(kMaxM);
   if (!sdcn.empty()) {
     for (auto& sub : sdcn) {
@@ -585,8 +591,10 @@ template <typename T>
 hipError_t Solver::coarse(bool adj, int react, const T* f, const double* u0, T* U) {
   const Level& C = lv.back();
   const OpParams& op = adj ? C.opT : C.op;
-  if (react == REACT_COEF)
+  if (react == REACT_COEF) {
+    if (coarse_inv && !adj) return launch_coarse_solve_slabs<T>(op, coarse_inv, f, u0, U, stream);
     return launch_coarse_solve_coef<T>(op, coef_of<T>(C), coarse_scratch, f, u0, U, stream);
+  }
   if (fft) return launch_fft_coarse<T>(op, adj ? fft_sinvT : fft_sinv, fft_tw, fft_work, f, u0, U, stream);
   return launch_coarse_solve<T>(op, adj ? AinvT : Ainv, f, u0, U, stream);
 }
@@ -1050,6 +1058,11 @@ int Solver::newton_linearize(const double* U) {
     const bool sp = (F.kind & 1) != 0, tm = (F.kind & 2) != 0;
     if (!mixed) HIP_CHECK(launch_restrict_coef<double>(F.op, sp, tm, C.nx, C.ny, C.N, F.coef64, C.coef64, stream));
     else HIP_CHECK(launch_restrict_coef<float>(F.op, sp, tm, C.nx, C.ny, C.N, F.coef32, C.coef32, stream));
+  }
+  if (coarse_inv) {
+    const Level& C = lv.back();
+    if (!mixed) HIP_CHECK(launch_coarse_invert_coef<double>(C.op, C.coef64, coarse_inv, stream));
+    else HIP_CHECK(launch_coarse_invert_coef<float>(C.op, C.coef32, coarse_inv, stream));
   }
   return STMG_OK;
 }

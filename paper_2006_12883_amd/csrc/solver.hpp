@@ -108,6 +108,10 @@ struct Solver {
   double* Ainv = nullptr;   // coarsest slab inverse (forward)
   double* AinvT = nullptr;  // (transposed problem)
   double* coarse_scratch = nullptr;  // dense slab matrix for the Newton coarsest solve
+  // Newton coarsest level: the inverted slab matrices of the current
+  // linearization (null when they would exceed kCoarseInvMaxBytes; the
+  // coarsest solve then factors slab after slab inside the cycle)
+  double* coarse_inv = nullptr;
   // Coarsest level solved by Fourier diagonalization (periodic grids, constant
   // reaction): per-mode M x M inverses, twiddles, complex workspace.
   bool fft = false;
