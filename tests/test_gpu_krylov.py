@@ -178,3 +178,37 @@ def test_fgmres_odd_length():
     U, st = H(prob, krylov=4, coarsen="space").solve(T(u0))
     assert st["status"] == 0
     assert rel_err(U.cpu().numpy(), ref) <= 1e-10
+
+
+def test_fgmres_windows():
+    """Time windows (checkpointing) with the Krylov method in each window:
+    the memory budget accounts for its 2 (m + 1) vectors."""
+    print("case fgmres windows", flush=True)
+    prob = si.problem(2, 32, 3, 48, 0.6, nu=1e-2, lam=0.5)
+    ny, nx = si.grid_points(prob)
+    m = 4
+    slab = prob["M"] * nx * ny * 8
+    budget = (5 + 2 * (m + 1) + 1) * slab * 16
+    u0 = si.u0_rd2d(prob, 6)
+    tgt = si.u_tgt_adj2d(prob, 7)
+    ref = stepper.solve_linear(prob, u0)
+    hw = H(prob, krylov=m, mem_budget=budget)
+    assert hw.num_windows() == 3
+    U, st = hw.solve(T(u0))
+    assert st["status"] == 0
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-10
+    ref_g, ref_nu = adjoint.gradients(prob, u0, tgt)
+    g, gnu, ast = hw.adjoint(U, 2.0 * (U[-1, -1] - T(tgt)))
+    assert rel_err(g.cpu().numpy(), ref_g) <= 1e-9
+    assert abs(gnu - ref_nu) <= 1e-9 * max(1.0, abs(ref_nu))
+
+
+def test_fgmres_mixed_neumann():
+    """Neumann grid (the unfused mixed path) with FP32 cycles preconditioning."""
+    print("case fgmres mixed neumann", flush=True)
+    prob = si.problem(2, 32, 3, 16, 0.5, nu=1e-2, lam=1.0, bc="neumann")
+    u0 = np.random.default_rng(11).standard_normal(si.grid_points(prob))
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob, krylov=6, precision="mixed", rtol=1e-11).solve(T(u0))
+    assert st["status"] == 0
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-9
