@@ -263,6 +263,18 @@ def paper_examples(dev):
                          "rel_res": st["rel_res"]}
             del h, U
         heat["M%d_Nt%d" % (M, prob["N"])] = row
+    weak = {}
+    for M in (1, 2, 3, 4, 5):
+        for Nt, L in si.PAPER_WEAK[M]:
+            prob = si.paper_heat1d(M, Nt=Nt)
+            u0 = torch.as_tensor(si.u0_paper_heat1d(prob)).to(dev)
+            h = stmg.Handle(prob, device=dev, coarsen="space", max_levels=L, krylov=10, nu_pre=3, nu_post=3,
+                            rtol=1e-9, max_cycles=300)
+            U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
+            _, st, t = _timed_solve(h, u0, U)
+            weak["M%d_Nt%d_L%d" % (M, Nt, L)] = {"ms": 1e3 * t, "status": st["status"], "vcycles": st["cycles"],
+                                                "rel_res": st["rel_res"]}
+            del h, U
     mono = {}
     for M in (1, 2, 3, 4, 5):
         prob = si.paper_monodomain(M)
@@ -274,7 +286,8 @@ def paper_examples(dev):
         mono["M%d_Nt%d" % (M, prob["N"])] = {"ms": 1e3 * t, "status": st["status"], "newton_its": st["newton_its"],
                                             "vcycles": st["cycles"], "rel_res": st["rel_res"]}
         del h, U
-    return {"heat_Nx1024_to_1e-9": heat, "monodomain_SMG7_V33_fgmres10_to_1e-9": mono}
+    return {"heat_Nx1024_to_1e-9": heat, "heat_weak_Nt_SMGL_V33_fgmres10_to_1e-9": weak,
+            "monodomain_SMG7_V33_fgmres10_to_1e-9": mono}
 
 
 def main():

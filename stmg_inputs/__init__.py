@@ -45,9 +45,17 @@ def config(name):
 PAPER_NT = {1: 1024, 2: 256, 3: 32, 4: 16, 5: 8}
 
 
-def paper_heat1d(M, nx=1024):
-    """Heat equation (gamma = 0), T = 1, N_t from the table headers."""
-    return problem(1, nx, M, PAPER_NT[M], 1.0, nu=1.0, bc="neumann")
+def paper_heat1d(M, nx=1024, Nt=None):
+    """Heat equation (gamma = 0), T = 1, N_t from the table headers unless given."""
+    return problem(1, nx, M, PAPER_NT[M] if Nt is None else Nt, 1.0, nu=1.0, bc="neumann")
+
+
+# Weak scaling in N_t (Example ex_3, SMG tables): (N_t, levels L) per M.
+PAPER_WEAK = {1: [(1024, 7), (2048, 8), (4096, 8), (8192, 8)],
+              2: [(256, 7), (512, 7), (1024, 8), (2048, 8)],
+              3: [(32, 7), (64, 7), (128, 8), (256, 8)],
+              4: [(16, 7), (32, 7), (64, 7), (128, 8)],
+              5: [(8, 7), (16, 7), (32, 7), (64, 7)]}
 
 
 def u0_paper_heat1d(prob):

@@ -212,3 +212,19 @@ def test_fgmres_mixed_neumann():
     U, st = H(prob, krylov=6, precision="mixed", rtol=1e-11).solve(T(u0))
     assert st["status"] == 0
     assert rel_err(U.cpu().numpy(), ref) <= 1e-9
+
+
+@pytest.mark.parametrize("M,Nt,L", [(2, 2048, 8), (5, 64, 7)])
+def test_paper_heat1d_weak(M, Nt, L):
+    """The longest runs of the paper's weak-scaling tables (Example ex_3):
+    SMG^L with FGMRES against the sequential stepper."""
+    print("case paper heat1d weak", M, Nt, flush=True)
+    assert (Nt, L) in si.PAPER_WEAK[M]
+    prob = si.paper_heat1d(M, Nt=Nt)
+    u0 = si.u0_paper_heat1d(prob)
+    U, st = H(prob, krylov=10, coarsen="space", max_levels=L, nu_pre=3, nu_post=3, rtol=1e-10,
+              max_cycles=300).solve(T(u0))
+    assert st["status"] == 0
+    ref = stepper.solve_linear(prob, u0)
+    assert np.abs(U[-1, -1].cpu().numpy() - ref[-1, -1]).max() <= 1e-10
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-8
