@@ -135,6 +135,23 @@ template <typename T>
 hipError_t launch_coarse_solve_slabs(const OpParams& p, const double* W, const T* f, const double* u0, T* U,
                                      hipStream_t s);
 
+// Coarsest level with a constant slab matrix and at most kScanMaxP points per
+// plane: the slab recurrence split into parallel applications of A_s^{-1}
+// and a P-vector recurrence p_n = g_n + G p_{n-1} in one wave.  Ainv is
+// K x K, G is P x P, H = A_s^{-1} (cin (x) I) is K x P, cout has M entries,
+// pg is N x P scratch.
+constexpr int kScanMaxP = 64;
+struct CoarseScan {
+  const double* Ainv = nullptr;
+  const double* G = nullptr;
+  const double* H = nullptr;
+  const double* cout = nullptr;
+  double* pg = nullptr;
+};
+template <typename T>
+hipError_t launch_coarse_scan(const OpParams& p, const CoarseScan& cs, const T* f, const double* u0, T* U,
+                              hipStream_t s);
+
 // out[0] = sum of part[0..n) in a fixed order (one workgroup).
 hipError_t launch_sum_partials(const double* part, int n, double* out, hipStream_t s);
 

@@ -18,6 +18,7 @@ namespace {
 
 constexpr int kResidSlabs = 8;   // slabs per thread in residual sweeps
 constexpr size_t kCoarseInvMaxBytes = size_t(1) << 30;  // Newton coarsest inverses
+constexpr int kScanMinSlabs = 32;  // shorter coarsest levels keep the one-kernel recurrence
 constexpr int kTransferSlabs = 4;
 
 // Elements -> points per dimension.
@@ -375,6 +376,21 @@ size_t Solver::plan(char* ws) {
     AinvT = pl.take<double>(K * K);
   }
   coarse_scratch = allen_cahn ? pl.take<double>(K * K) : nullptr;
+  scan = CoarseScan{};
+  scanT = CoarseScan{};
+  if (!fft && !decoupled && !batch_member && static_cast<int>(c.nx * c.ny) <= kScanMaxP && c.N >= kScanMinSlabs) {
+    const size_t Pc = static_cast<size_t>(c.nx) * c.ny;
+    double* g = pl.take<double>(Pc * Pc);
+    double* h = pl.take<double>(K * Pc);
+    double* gT = pl.take<double>(Pc * Pc);
+    double* hT = pl.take<double>(K * Pc);
+    double* co = pl.take<double>(2 * kMaxM);
+    double* pg = pl.take<double>(static_cast<size_t>(c.N) * Pc);
+    if (ws) {
+      scan = CoarseScan{Ainv, g, h, co, pg};
+      scanT = CoarseScan{AinvT, gT, hT, co + kMaxM, pg};
+    }
+  }
   coarse_inv = nullptr;
   if (allen_cahn && !batch_member) {
     const size_t d = coarse_inverse_doubles(c.op);
@@ -475,6 +491,47 @@ int Solver::upload_dense() {
     }
   HIP_CHECK(hipMemcpyAsync(Ainv, Ad.data(), Ad.size() * sizeof(double), hipMemcpyHostToDevice, stream));
   HIP_CHECK(hipMemcpyAsync(AinvT, AdT.data(), AdT.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  // split recurrence: G = (cout (x) I) A^{-1} (cin (x) I), H = A^{-1} (cin (x) I)
+  // for the forward problem and, with the transposed inverse and exchanged
+  // coupling vectors, for the transposed one
+  std::vector<double> Gd, Hd, GTd, HTd, cod;
+  if (scan.G) {
+    auto build = [&](bool tr, const OpParams& o, std::vector<double>& Gv, std::vector<double>& Hv) {
+      Gv.assign(static_cast<size_t>(P) * P, 0.0);
+      Hv.assign(static_cast<size_t>(K) * P, 0.0);
+      auto inv = [&](int r, int s) -> long double {
+        return tr ? A[static_cast<size_t>(s) * K + r] : A[static_cast<size_t>(r) * K + s];
+      };
+      for (int r = 0; r < K; ++r)
+        for (int q2 = 0; q2 < P; ++q2) {
+          long double h = 0.0L;
+          for (int m2 = 0; m2 < M; ++m2) h += inv(r, m2 * P + q2) * static_cast<long double>(o.cin[m2]);
+          Hv[static_cast<size_t>(r) * P + q2] = static_cast<double>(h);
+        }
+      for (int q = 0; q < P; ++q)
+        for (int q2 = 0; q2 < P; ++q2) {
+          long double g = 0.0L;
+          for (int m = 0; m < M; ++m) {
+            long double h = 0.0L;
+            for (int m2 = 0; m2 < M; ++m2) h += inv(m * P + q, m2 * P + q2) * static_cast<long double>(o.cin[m2]);
+            g += static_cast<long double>(o.cout[m]) * h;
+          }
+          Gv[static_cast<size_t>(q) * P + q2] = static_cast<double>(g);
+        }
+    };
+    build(false, c.op, Gd, Hd);
+    build(true, c.opT, GTd, HTd);
+    cod.assign(2 * kMaxM, 0.0);
+    for (int m = 0; m < M; ++m) {
+      cod[m] = c.op.cout[m];
+      cod[kMaxM + m] = c.opT.cout[m];
+    }
+    HIP_CHECK(hipMemcpyAsync(const_cast<double*>(scan.G), Gd.data(), Gd.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(const_cast<double*>(scan.H), Hd.data(), Hd.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(const_cast<double*>(scanT.G), GTd.data(), GTd.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(const_cast<double*>(scanT.H), HTd.data(), HTd.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(const_cast<double*>(scan.cout), cod.data(), cod.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  }
   HIP_CHECK(hipStreamSynchronize(stream));  // host vectors go out of scope
   return STMG_OK;
 }
@@ -596,6 +653,7 @@ hipError_t Solver::coarse(bool adj, int react, const T* f, const double* u0, T* 
     return launch_coarse_solve_coef<T>(op, coef_of<T>(C), coarse_scratch, f, u0, U, stream);
   }
   if (fft) return launch_fft_coarse<T>(op, adj ? fft_sinvT : fft_sinv, fft_tw, fft_work, f, u0, U, stream);
+  if (scan.G) return launch_coarse_scan<T>(op, adj ? scanT : scan, f, u0, U, stream);
   return launch_coarse_solve<T>(op, adj ? AinvT : Ainv, f, u0, U, stream);
 }
 

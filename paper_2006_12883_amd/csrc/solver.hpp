@@ -108,6 +108,9 @@ struct Solver {
   double* Ainv = nullptr;   // coarsest slab inverse (forward)
   double* AinvT = nullptr;  // (transposed problem)
   double* coarse_scratch = nullptr;  // dense slab matrix for the Newton coarsest solve
+  // Dense coarsest level with few points per plane and many slabs: the split
+  // recurrence (forward and transposed problem); empty when not used
+  CoarseScan scan{}, scanT{};
   // Newton coarsest level: the inverted slab matrices of the current
   // linearization (null when they would exceed kCoarseInvMaxBytes; the
   // coarsest solve then factors slab after slab inside the cycle)

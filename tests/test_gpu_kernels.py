@@ -221,3 +221,36 @@ def test_smmg_coarse_solve_on_lowered_nodes():
         out = torch.empty(lev.shape, dtype=torch.float64, device="cuda:0")
         h.coarse_solve(T(f), out)
         assert_close(out.cpu().numpy(), lev.exact_solve(f), 1e-12, "coarse solve M=%d" % lev.M)
+
+
+@pytest.mark.parametrize("name,prob,levels", [
+    ("1d-16pt-64slabs", si.problem(1, 32, 3, 64, 0.5, nu=1.0), 2),
+    ("2d-8x8-40slabs", si.problem(2, 16, 2, 40, 0.5, nu=0.01, lam=1.0), 2),
+    ("2d-neumann-5x5-48slabs", si.problem(2, 16, 3, 48, 0.5, nu=0.01, lam=1.0, bc="neumann"), 3),
+])
+def test_coarse_solve_split_recurrence(name, prob, levels):
+    """Dense coarsest levels with at most 64 points per plane and at least 32
+    slabs take the split recurrence (parallel A^-1 applications around a
+    one-wave P-vector recurrence): against the oracle's slab-by-slab solve
+    (periodic), or against the forward substitution of the assembled slab
+    system (Neumann)."""
+    print("case", name, flush=True)
+    h = H(prob, coarsen="space", max_levels=levels, fft_coarse=0)
+    lv = h.levels()[-1]
+    shape = (lv["N"], lv["M"], lv["ny"], lv["nx"])
+    assert lv["nx"] * lv["ny"] <= 64 and lv["N"] >= 32
+    f = np.random.default_rng(8).standard_normal(shape)
+    out = torch.empty(shape, dtype=torch.float64, device="cuda:0")
+    h.coarse_solve(T(f), out)
+    if prob["bc"] == "periodic":
+        levels_o, _ = mg.hierarchy(prob, coarsen="space", max_levels=levels, fft_coarse=0)
+        ref = levels_o[-1].exact_solve(f)
+        assert ref.shape == shape
+    else:
+        # the coarsest level rediscretizes the problem on its own grid (same
+        # domain, nx - 1 elements, its own dt): its all-at-once matrix with
+        # zero u0, solved densely
+        cp = si.problem(2, lv["nx"] - 1, prob["M"], lv["N"], lv["dt"] * lv["N"], nu=prob["nu"],
+                        lam=prob["lambda"], bc="neumann")
+        ref = np.linalg.solve(allatonce.matrix(cp).toarray(), f.reshape(-1)).reshape(shape)
+    assert_close(out.cpu().numpy(), ref, 1e-12, "coarse solve (split recurrence)")

@@ -228,3 +228,36 @@ def test_paper_heat1d_weak(M, Nt, L):
     ref = stepper.solve_linear(prob, u0)
     assert np.abs(U[-1, -1].cpu().numpy() - ref[-1, -1]).max() <= 1e-10
     assert rel_err(U.cpu().numpy(), ref) <= 1e-8
+
+
+def test_paper_heat1d_mixed_split_coarse():
+    """Mixed precision on the paper's heat example (M = 2, N_t = 256): the FP32
+    cycles' coarsest level (17 points x 256 slabs) takes the split recurrence."""
+    print("case paper heat1d mixed", flush=True)
+    prob = si.paper_heat1d(2)
+    u0 = si.u0_paper_heat1d(prob)
+    ref = stepper.solve_linear(prob, u0)
+    for kr in (0, 10):
+        U, st = H(prob, krylov=kr, precision="mixed", coarsen="space", max_levels=7, rtol=1e-10).solve(T(u0))
+        assert st["status"] == 0
+        assert np.abs(U[-1, -1].cpu().numpy() - ref[-1, -1]).max() <= 1e-10
+
+
+def test_adjoint_split_coarse():
+    """The transposed problem's coarsest level (8 x 8 points x 32 slabs) through
+    the split recurrence: gradients against the oracle's adjoint."""
+    print("case adjoint split coarse", flush=True)
+    prob = si.problem(2, 32, 3, 32, 0.5, nu=1e-2, lam=1.0)
+    ny, nx = si.grid_points(prob)
+    rng = np.random.default_rng(9)
+    u0 = rng.standard_normal((ny, nx))
+    tgt = rng.standard_normal((ny, nx))
+    h = H(prob, coarsen="space", max_levels=3, fft_coarse=0)
+    lv = h.levels()[-1]
+    assert lv["nx"] * lv["ny"] == 64 and lv["N"] == 32
+    U, st = h.solve(T(u0))
+    assert st["status"] == 0
+    g, gnu, ast = h.adjoint(U, 2.0 * (U[-1, -1] - T(tgt)))
+    ref_g, ref_nu = adjoint.gradients(prob, u0, tgt)
+    assert rel_err(g.cpu().numpy(), ref_g) <= 1e-9
+    assert abs(gnu - ref_nu) <= 1e-9 * max(1.0, abs(ref_nu))
