@@ -357,6 +357,13 @@ def main():
         sols["solve_" + prec + "_rtol1e-10"] = V.cpu().numpy()
         hh.close()
         del V
+    # the Krylov option on the same workload, kept for the error check
+    hk = stmg.Handle(prob, device=dev, krylov=5, rtol=1e-10)
+    V = torch.zeros(shape, dtype=torch.float64, device=dev)
+    hk.solve(u0, V)
+    sols["solve_fp64_fgmres5_rtol1e-10"] = V.cpu().numpy()
+    hk.close()
+    del V
     print("time-to-1e-10 done", file=sys.stderr, flush=True)
 
     # dominant kernel: the level-0 smoothing sweep, timed with HIP events

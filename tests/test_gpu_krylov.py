@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import stmg_inputs as si
-from oracle import adjoint, krylov, stepper
+from oracle import adjoint, fourier, krylov, stepper
 
 pytestmark = pytest.mark.gpu
 
@@ -261,3 +261,18 @@ def test_adjoint_split_coarse():
     ref_g, ref_nu = adjoint.gradients(prob, u0, tgt)
     assert rel_err(g.cpu().numpy(), ref_g) <= 1e-9
     assert abs(gnu - ref_nu) <= 1e-9 * max(1.0, abs(ref_nu))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fgmres_rd2d_full(prec):
+    """The full 256^2 x M=3 x N=256 workload through FGMRES(5) (the bench's
+    launch configuration) against the oracle's closed form."""
+    print("case fgmres rd2d full", prec, flush=True)
+    prob = si.config("rd2d")
+    u0 = si.initial("rd2d", prob)
+    U, st = H(prob, krylov=5, precision=prec, rtol=1e-10).solve(T(u0))
+    assert st["status"] == 0 and st["rel_res"] <= 1e-10
+    ref = fourier.solve_linear_periodic(prob, u0)
+    got = U.cpu().numpy()
+    assert rel_err(got, ref) <= 1e-9
+    assert rel_err(got[-1, -1], ref[-1, -1]) <= 1e-9
