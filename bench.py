@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (Allen-Cahn Newton, adjoint, batch)")
     ap.add_argument("--kernel-iters", type=int, default=20)
+    ap.add_argument("--krylov-only", action="store_true",
+                    help="only the flexible GMRES lines on the 256^2 workload (used for the Krylov "
+                         "kernel trace)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only time the level-0 smoothing sweep and a plain device copy of the "
                          "same bytes (used for the HBM counter runs)")
@@ -206,7 +209,21 @@ def extras(dev):
         torch.cuda.empty_cache()
     out["hierarchies_rd2d_fp64_to_1e-10"] = variants
     print("hierarchies done", file=sys.stderr, flush=True)
-    # flexible GMRES around the same V-cycle on the 256^2 workload
+    out["krylov_rd2d_fp64_to_1e-10"] = krylov_lines(dev)
+    print("krylov done", file=sys.stderr, flush=True)
+    out["paper_examples_1d"] = paper_examples(dev)
+    print("paper examples done", file=sys.stderr, flush=True)
+    return out
+
+
+def krylov_lines(dev):
+    """Flexible GMRES around the AUTO V-cycle on the 256^2 workload, FP64 to
+    1e-10, restart 5 and 10, beside the plain iteration."""
+    import torch
+    import stmg_inputs as si
+    from paper_2006_12883_amd import stmg
+    prob = si.config("rd2d")
+    u0 = torch.as_tensor(si.initial("rd2d", prob)).to(dev)
     kry = {}
     for m in (0, 5, 10):
         h = stmg.Handle(prob, device=dev, krylov=m, rtol=1e-10)
@@ -216,11 +233,7 @@ def extras(dev):
                                                       "vcycles": st["cycles"], "rel_res": st["rel_res"]}
         del h, U
         torch.cuda.empty_cache()
-    out["krylov_rd2d_fp64_to_1e-10"] = kry
-    print("krylov done", file=sys.stderr, flush=True)
-    out["paper_examples_1d"] = paper_examples(dev)
-    print("paper examples done", file=sys.stderr, flush=True)
-    return out
+    return kry
 
 
 def _timed_solve(h, u0, U):
@@ -306,6 +319,9 @@ def main():
     u0 = torch.as_tensor(u0n).to(dev)
     shape = (prob["N"], prob["M"], 256, 256)
     dof = float(np.prod(shape))
+    if a.krylov_only:
+        print(json.dumps({"krylov_rd2d_fp64_to_1e-10": krylov_lines(dev)}), flush=True)
+        return
     if a.kernel_only:
         h = stmg.Handle(prob, device=dev)
         U = torch.randn(shape, dtype=torch.float64, device=dev)
