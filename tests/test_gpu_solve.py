@@ -120,3 +120,25 @@ def test_smmg_solve_matches_stepper(prec):
     ref = stepper.solve_linear(prob, u0)
     e = rel_err(U.cpu().numpy(), ref)
     assert e <= (1e-10 if prec == "fp64" else 1e-9), e
+
+
+@pytest.mark.parametrize("name,prob", [
+    ("one-slab", si.problem(1, 16, 3, 1, 0.1, nu=1.0, lam=0.5)),
+    ("3-points", si.problem(1, 3, 2, 6, 0.2, nu=0.1, lam=0.5)),
+    ("2d-4x4", si.problem(2, 4, 2, 5, 0.3, nu=0.05, lam=0.2)),
+    ("M8", si.problem(1, 32, 8, 4, 0.2, nu=0.5, lam=0.1)),
+    ("M7-neumann", si.problem(1, 20, 7, 3, 0.3, nu=0.5, bc="neumann")),
+    ("2d-3x3-neumann", si.problem(2, 2, 2, 4, 0.2, nu=0.1, lam=0.3, bc="neumann")),
+])
+@pytest.mark.parametrize("opts", [{}, {"krylov": 3}, {"precision": "mixed", "rtol": 1e-11}])
+def test_degenerate_shapes(name, prob, opts):
+    """One slab, three grid points, 4 x 4 and 3 x 3 planes, the largest node
+    counts: the solve against the sequential stepper."""
+    print("case degenerate", name, opts, flush=True)
+    ny, nx = si.grid_points(prob)
+    u0 = np.random.default_rng(12).standard_normal((ny, nx))
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob, max_cycles=400, **opts).solve(T(u0))
+    assert st["status"] == 0
+    tol = 1e-9 if opts.get("precision") == "mixed" else 1e-10
+    _check(U.cpu().numpy(), ref, tol)
