@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (Allen-Cahn Newton, adjoint, batch)")
     ap.add_argument("--kernel-iters", type=int, default=20)
+    ap.add_argument("--only", choices=EXTRA_GROUPS, default=None,
+                    help="run only this group of the other workloads and print their JSON (for traces)")
     ap.add_argument("--krylov-only", action="store_true",
                     help="only the flexible GMRES lines on the 256^2 workload (used for the Krylov "
                          "kernel trace)")
@@ -120,8 +122,34 @@ def time_kernels(h, U, u0, iters):
     return k_ms, c_ms, 2.0 * x.numel() * 8
 
 
-def extras(dev):
-    """The other synthetic workloads, each timed once after a warm-up call."""
+EXTRA_GROUPS = ("allen_cahn", "adjoint", "batch", "hierarchies", "krylov", "paper")
+
+
+def extras(dev, only=None):
+    """The other synthetic workloads, each timed once after a warm-up call
+    (only: one of EXTRA_GROUPS, else all)."""
+    import torch
+    import stmg_inputs as si
+    from paper_2006_12883_amd import stmg
+    out = {}
+    if only in (None, "allen_cahn"):
+        out.update(_extra_allen_cahn(dev))
+    if only in (None, "adjoint"):
+        out.update(_extra_adjoint(dev))
+    if only in (None, "batch"):
+        out.update(_extra_batch(dev))
+    if only in (None, "hierarchies"):
+        out.update(_extra_hierarchies(dev))
+    if only in (None, "krylov"):
+        out["krylov_rd2d_fp64_to_1e-10"] = krylov_lines(dev)
+        print("krylov done", file=sys.stderr, flush=True)
+    if only in (None, "paper"):
+        out["paper_examples_1d"] = paper_examples(dev)
+        print("paper examples done", file=sys.stderr, flush=True)
+    return out
+
+
+def _extra_allen_cahn(dev):
     import torch
     import stmg_inputs as si
     from paper_2006_12883_amd import stmg
@@ -145,6 +173,14 @@ def extras(dev):
     del h, U
     torch.cuda.empty_cache()
     print("allen-cahn done", file=sys.stderr, flush=True)
+    return out
+
+
+def _extra_adjoint(dev):
+    import torch
+    import stmg_inputs as si
+    from paper_2006_12883_amd import stmg
+    out = {}
     # adjoint on the 256^2 workload: gradient w.r.t. u0 and nu
     prob = si.config("adj2d")
     u0n = si.initial("adj2d", prob)
@@ -163,6 +199,14 @@ def extras(dev):
     del h, U
     torch.cuda.empty_cache()
     print("adjoint done", file=sys.stderr, flush=True)
+    return out
+
+
+def _extra_batch(dev):
+    import torch
+    import stmg_inputs as si
+    from paper_2006_12883_amd import stmg
+    out = {}
     # 64 batched problems, FP32 V-cycles in FP64 refinement to 1e-10
     probs = si.batch64()
     u0s = [torch.as_tensor(si.batch_u0(p, i)).to(dev) for i, p in enumerate(probs)]
@@ -183,6 +227,14 @@ def extras(dev):
     del b, Us
     torch.cuda.empty_cache()
     print("batch done", file=sys.stderr, flush=True)
+    return out
+
+
+def _extra_hierarchies(dev):
+    import torch
+    import stmg_inputs as si
+    from paper_2006_12883_amd import stmg
+    out = {}
     # the paper's three hierarchies (Sec. 4.2) on the 256^2 workload, FP64 to
     # 1e-10: SMG (space only), STMG (space and time at once), SMMG (space and
     # nodes); AUTO semi-coarsening is the headline solve
@@ -209,10 +261,6 @@ def extras(dev):
         torch.cuda.empty_cache()
     out["hierarchies_rd2d_fp64_to_1e-10"] = variants
     print("hierarchies done", file=sys.stderr, flush=True)
-    out["krylov_rd2d_fp64_to_1e-10"] = krylov_lines(dev)
-    print("krylov done", file=sys.stderr, flush=True)
-    out["paper_examples_1d"] = paper_examples(dev)
-    print("paper examples done", file=sys.stderr, flush=True)
     return out
 
 
@@ -321,6 +369,9 @@ def main():
     dof = float(np.prod(shape))
     if a.krylov_only:
         print(json.dumps({"krylov_rd2d_fp64_to_1e-10": krylov_lines(dev)}), flush=True)
+        return
+    if a.only:
+        print(json.dumps(extras(dev, a.only)), flush=True)
         return
     if a.kernel_only:
         h = stmg.Handle(prob, device=dev)
