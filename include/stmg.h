@@ -116,7 +116,7 @@ typedef struct {
                          cached in the JSON file named by $STMG_TUNE_CACHE.
                          0 (default): fixed shapes                            */
   int32_t inner_cycles; /* mixed precision: FP32 V-cycles on each correction
-                         equation per FP64 refinement step, 2                 */
+                         equation per FP64 refinement step, 4                 */
   int32_t fft_coarse; /* periodic grids with a linear reaction: coarsening
                          also stops at the first level below the finest whose
                          planes hold <= 1024 points and which holds <=

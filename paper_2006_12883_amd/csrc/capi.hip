@@ -54,7 +54,7 @@ void stmg_default_options(stmg_options* o) {
   o->mem_budget = 0;
   o->sdc = 0;
   o->autotune = 0;
-  o->inner_cycles = 2;
+  o->inner_cycles = 4;
   o->fft_coarse = 262144;
   o->krylov = 0;
 }

@@ -22,8 +22,8 @@ def test_mixed_heat1d():
     u0 = si.initial("heat1d", prob)
     ref = stepper.solve_linear(prob, u0)
     U, st = H(prob, precision="mixed", rtol=1e-10).solve(T(u0))
-    # two FP32 V-cycles per FP64 refinement step by default
-    assert st["status"] == 0 and st["rel_res"] <= 1e-10 and st["cycles"] == 2 * st["refinements"]
+    # four FP32 V-cycles per FP64 refinement step by default
+    assert st["status"] == 0 and st["rel_res"] <= 1e-10 and st["cycles"] == 4 * st["refinements"]
     e, eT = _errs(U.cpu().numpy(), ref)
     assert e <= 1e-9 and eT <= 1e-9, (e, eT)
 
@@ -40,7 +40,7 @@ def test_mixed_rd2d_small(M):
     assert e <= 1e-9 and eT <= 1e-9, (e, eT)
 
 
-@pytest.mark.parametrize("inner", [1, 2, 3])
+@pytest.mark.parametrize("inner", [1, 2, 3, 6])
 def test_mixed_inner_cycles(inner):
     """Any number of FP32 cycles per refinement step reaches the FP64 tolerance."""
     print("case mixed inner cycles", inner, flush=True)
@@ -103,7 +103,9 @@ def test_newton_allen_cahn_small(prec, dim):
         prob = si.problem(2, 64, 3, 32, 0.5, nu=1e-3, gamma=1.0, reaction="allen_cahn")
         u0 = si.u0_ac2d(prob, 3)
     ref = stepper.solve_allen_cahn(prob, u0)
-    tol = 1e-12 if prec == "fp64" else 1e-10
+    # the error reaches about 30x the relative Newton residual on the 2D case;
+    # both precisions stop two orders of magnitude below the error bound
+    tol = 1e-12 if prec == "fp64" else 1e-11
     U, st = H(prob, precision=prec, newton_rtol=tol).solve(T(u0))
     assert st["status"] == 0 and st["newton_its"] >= 2
     e, eT = _errs(U.cpu().numpy(), ref)
