@@ -185,8 +185,10 @@ int stmg_vcycle(stmg_handle* h, const double* d_u0, double* d_U, double* h_rel);
 
 /* Solves the all-at-once system from the initial guess in d_U (zero is the
  * paper's choice, Sec. 5.2): V-cycles (FP64, or FP32 cycles inside FP64
- * refinement when precision = MIXED) until rel_res <= rtol, wrapped in
- * Newton for Allen-Cahn (Sec. 3.2).  d_U receives the solution (the last
+ * refinement when precision = MIXED) until rel_res <= rtol, or with
+ * options.krylov = m > 0 restarted flexible GMRES(m) preconditioned by one
+ * V-cycle per step (the preconditioned Krylov iteration of Sec. 5.2), wrapped
+ * in Newton for Allen-Cahn (Sec. 3.2).  d_U receives the solution (the last
  * iterate on ENOTCONV/EDIVERGED/ENAN).  stats may be NULL.  Synchronizes. */
 int stmg_solve(stmg_handle* h, const double* d_u0, double* d_U, stmg_stats* stats);
 
