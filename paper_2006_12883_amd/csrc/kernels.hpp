@@ -171,6 +171,9 @@ hipError_t launch_update(size_t n, double* U, const TE* e, const double* scale, 
 // Allen-Cahn term gamma (u^3 - u)), written as T.
 template <typename T>
 hipError_t launch_newton_coef(size_t n, const double* U, double gamma, T* coef, hipStream_t s);
+// The same coefficient written as FP64 and FP32 in one pass over U.
+hipError_t launch_newton_coef_pair(size_t n, const double* U, double gamma, double* c64, float* c32,
+                                   hipStream_t s);
 
 // Coefficient on the next coarser level: average of the fine values
 // (full-weighting pattern normalized to unit sum in space and time).

@@ -70,7 +70,46 @@ __global__ __launch_bounds__(kBlock) void k_grad_nu(const OpParams p, const doub
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// c = gamma (3 u^2 - 1) into c64 and c32, two values per thread and step
+// (U and c64 16-byte aligned, c32 8-byte aligned; the odd last value by
+// thread 0 of block 0).
+__global__ __launch_bounds__(kBlock) void k_newton_coef_pair(size_t n, const double* __restrict__ U, double gamma,
+                                                             double* __restrict__ c64, float* __restrict__ c32) {
+  const size_t n2 = n >> 1;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n2; e += stride) {
+    const double2 u = reinterpret_cast<const double2*>(U)[e];
+    double2 c;
+    c.x = gamma * (3.0 * u.x * u.x - 1.0);
+    c.y = gamma * (3.0 * u.y * u.y - 1.0);
+    reinterpret_cast<double2*>(c64)[e] = c;
+    float2 f;
+    f.x = (float)c.x;
+    f.y = (float)c.y;
+    reinterpret_cast<float2*>(c32)[e] = f;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const double u = U[n - 1];
+    const double c = gamma * (3.0 * u * u - 1.0);
+    c64[n - 1] = c;
+    c32[n - 1] = (float)c;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_newton_coef_pair(size_t n, const double* U, double gamma, double* c64, float* c32,
+                                   hipStream_t s) {
+  const bool aligned = (reinterpret_cast<uintptr_t>(U) & 15) == 0 && (reinterpret_cast<uintptr_t>(c64) & 15) == 0 &&
+                       (reinterpret_cast<uintptr_t>(c32) & 7) == 0;
+  if (!aligned) {
+    hipError_t e = launch_newton_coef<double>(n, U, gamma, c64, s);
+    if (e != hipSuccess) return e;
+    return launch_newton_coef<float>(n, U, gamma, c32, s);
+  }
+  hipLaunchKernelGGL(k_newton_coef_pair, dim3(grid_for(n >> 1)), dim3(kBlock), 0, s, n, U, gamma, c64, c32);
+  return hipGetLastError();
+}
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_node_transfer(const T* __restrict__ in, int Min,

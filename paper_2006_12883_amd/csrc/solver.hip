@@ -1108,8 +1108,12 @@ int Solver::solve_fgmres(bool adj, int react, const double* f, const double* u0,
 int Solver::newton_linearize(const double* U) {
   // c = gamma (3 U^2 - 1) on level 0, restricted to the coarser levels.
   Level& L0 = lv[0];
-  if (L0.coef64) HIP_CHECK(launch_newton_coef<double>(L0.n, U, prob.gamma, L0.coef64, stream));
-  if (mixed) HIP_CHECK(launch_newton_coef<float>(L0.n, U, prob.gamma, L0.coef32, stream));
+  if (L0.coef64 && mixed) {
+    HIP_CHECK(launch_newton_coef_pair(L0.n, U, prob.gamma, L0.coef64, L0.coef32, stream));
+  } else {
+    if (L0.coef64) HIP_CHECK(launch_newton_coef<double>(L0.n, U, prob.gamma, L0.coef64, stream));
+    if (mixed) HIP_CHECK(launch_newton_coef<float>(L0.n, U, prob.gamma, L0.coef32, stream));
+  }
   for (size_t l = 0; l + 1 < lv.size(); ++l) {
     const Level& F = lv[l];
     Level& C = lv[l + 1];
