@@ -254,3 +254,27 @@ def test_coarse_solve_split_recurrence(name, prob, levels):
                         lam=prob["lambda"], bc="neumann")
         ref = np.linalg.solve(allatonce.matrix(cp).toarray(), f.reshape(-1)).reshape(shape)
     assert_close(out.cpu().numpy(), ref, 1e-12, "coarse solve (split recurrence)")
+
+
+def test_full_size_smoother_and_vcycle():
+    """The 256^2 x M=3 x N=256 workload in the benchmark's configuration: one
+    level-0 smoothing sweep (right-hand side generated from u0, as the timed
+    kernel runs it) and one whole V-cycle, element by element against the
+    oracle."""
+    print("case full-size smoother and V-cycle", flush=True)
+    prob = si.config("rd2d")
+    levels, kinds = mg.hierarchy(prob)
+    u0 = si.initial("rd2d", prob)
+    f = mg.rhs(levels, u0)
+    U = np.random.default_rng(31).standard_normal(levels[0].shape)
+    h = H(prob)
+    assert [(l["nx"], l["N"]) for l in h.levels()] == [(lv.nx, lv.N) for lv in levels]
+    ref = levels[0].smooth(U, f, 0.8, 16)
+    out = torch.empty(levels[0].shape, dtype=torch.float64, device="cuda:0")
+    h.smooth(0, T(U), out, u0=T(u0))
+    assert_close(out.cpu().numpy(), ref, 1e-12, "full-size smooth")
+    del out, ref
+    ref = mg.vcycle(levels, kinds, U.copy(), f)
+    Ud = T(U)
+    h.vcycle(T(u0), Ud)
+    assert_close(Ud.cpu().numpy(), ref, 1e-11, "full-size V-cycle")
