@@ -157,8 +157,9 @@ def test_paper_monodomain_m3():
 
 
 def test_fgmres_stops_at_rounding_floor():
-    """A tolerance below the rounding floor ends after three restarts without
-    progress, not after max_cycles."""
+    """A tolerance below the rounding floor ends once two restart cycles in a
+    row were ended by the least-squares estimate while the true residual
+    stayed above the tolerance, not after max_cycles."""
     print("case fgmres floor", flush=True)
     prob = si.paper_heat1d(4)
     u0 = si.u0_paper_heat1d(prob)
