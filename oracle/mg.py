@@ -57,6 +57,7 @@ class Level:
     def __init__(self, nx, ny, N, M, dt, nu, lam, length, dim, tab):
         self.nx, self.ny, self.N, self.M, self.dt = nx, ny, N, M, dt
         self.nu, self.lam, self.dim = nu, lam, dim
+        self.length = [float(length[0]), float(length[1])]
         self.hx = length[0] / nx
         self.hy = length[1] / ny if dim == 2 else 1.0
         self.Kq, self.b, self.l0 = tab["Kq"], tab["b"], tab["l0"]
@@ -251,23 +252,37 @@ def prolong(e, kind, dim, Pm=None):
     return e
 
 
-def vcycle(levels, kinds, U, f, omega=0.8, chunk=16, nu_pre=1, nu_post=1, l=0, chunk_coarse=4):
+def vcycle(levels, kinds, U, f, omega=0.8, chunk=16, nu_pre=1, nu_post=1, l=0, chunk_coarse=4,
+           smoothers=None):
     """One V-cycle; the smoother's block length is `chunk` slabs on the finest
-    level and `chunk_coarse` on the coarser ones."""
+    level and `chunk_coarse` on the coarser ones.  `smoothers`, if given, is
+    one map (U, f) -> U' per level that replaces the block-Jacobi sweep (each
+    pre- and post-smoothing step calls it once)."""
     lev = levels[l]
     if l == len(levels) - 1:
         return lev.exact_solve(f)
     ch = chunk if l == 0 else chunk_coarse
+
+    def sweep(V):
+        return smoothers[l](V, f) if smoothers is not None else lev.smooth(V, f, omega, ch)
+
     for _ in range(nu_pre):
-        U = lev.smooth(U, f, omega, ch)
+        U = sweep(U)
     r = f - lev.apply(U)
     fc = restrict(r, kinds[l], lev.dim, lev.Pm)
     ec = vcycle(levels, kinds, np.zeros(levels[l + 1].shape), fc, omega, chunk, nu_pre, nu_post, l + 1,
-                chunk_coarse)
+                chunk_coarse, smoothers)
     U = U + prolong(ec, kinds[l], lev.dim, lev.Pm)
     for _ in range(nu_post):
-        U = lev.smooth(U, f, omega, ch)
+        U = sweep(U)
     return U
+
+
+def level_problem(lev):
+    """The problem statement a level rediscretizes (periodic, same domain)."""
+    nx = [lev.nx, lev.ny if lev.dim == 2 else 1]
+    return dict(dim=lev.dim, nx=nx, length=list(lev.length), bc="periodic", nu=lev.nu,
+                reaction="linear", **{"lambda": lev.lam}, gamma=0.0, M=lev.M, N=lev.N, dt=lev.dt)
 
 
 def rhs(levels, u0):
