@@ -21,4 +21,8 @@ adjoint   discrete adjoint of the sequential stepper (gradients of a
 mg        the multigrid components (transfers, block-Jacobi smoother,
           level hierarchy, V-cycle) spelled out plainly in NumPy
 krylov    restarted flexible GMRES with the V-cycle as right preconditioner
+ilu       ILU(0) and the ILU(0)-preconditioned GMRES smoother of the paper
+galerkin  assembled transfers and Galerkin coarse operators R A P
+paper_hierarchies  runner: the paper's hierarchies on its 1D heat example
+          with both smoothers and both coarse-operator choices
 """
