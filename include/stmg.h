@@ -132,6 +132,16 @@ typedef struct {
                          max_cycles bounds them; 2 (m + 1) more level-0
                          vectors of workspace.  Ignored by batches.
                          0 (default): the plain V-cycle iteration             */
+  int32_t krylov_left; /* with krylov > 0: 1 = left preconditioning, GMRES on
+                         M^-1 A U = M^-1 b stopping when the preconditioned
+                         residual ||M^-1 (b - A U)|| has fallen by rtol
+                         against its value at the initial guess (PETSc's
+                         default, the stop the paper reports, Sec. 5.2);
+                         rel_res still reports the true residual and cycles
+                         counts every V-cycle (one more per restart).  The
+                         V-cycle must then be a fixed operator: FP64 or FP32
+                         cycles alike.  0 (default): flexible GMRES, right
+                         preconditioning, true-residual stop                 */
 } stmg_options;
 
 typedef struct {

@@ -94,9 +94,12 @@ def fgmres(apply, precond, b, x0=None, restart=10, rtol=1e-9, max_steps=200):
     return x.reshape(shape), hist, steps
 
 
-def solve(prob, u0, rtol=1e-9, max_steps=200, restart=10, **kw):
+def solve(prob, u0, rtol=1e-9, max_steps=200, restart=10, left=False, **kw):
     """FGMRES on the all-at-once system with one oracle V-cycle (from zero)
-    as the preconditioner; keyword arguments as for `mg.solve`."""
+    as the preconditioner; keyword arguments as for `mg.solve`.  With left,
+    GMRES on the left-preconditioned system M A x = M f (M = one V-cycle):
+    the residual it minimises and stops on is the preconditioned one, and
+    hist is relative to ||M f||."""
     from . import mg
     hk = {k: kw.pop(k) for k in ("coarsen", "mu_crit", "min_coarse", "max_levels", "fft_coarse") if k in kw}
     levels, kinds = mg.hierarchy(prob, **hk)
@@ -105,4 +108,7 @@ def solve(prob, u0, rtol=1e-9, max_steps=200, restart=10, **kw):
     def precond(v):
         return mg.vcycle(levels, kinds, np.zeros(levels[0].shape), v, **kw)
 
+    if left:
+        return fgmres(lambda v: precond(levels[0].apply(v)), lambda v: v, precond(f), restart=restart,
+                      rtol=rtol, max_steps=max_steps)
     return fgmres(levels[0].apply, precond, f, restart=restart, rtol=rtol, max_steps=max_steps)

@@ -45,7 +45,8 @@ class Options(ctypes.Structure):
                 ("max_cycles", ctypes.c_int32), ("rtol", ctypes.c_double), ("newton_rtol", ctypes.c_double),
                 ("max_newton", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("sdc", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("inner_cycles", ctypes.c_int32),
-                ("fft_coarse", ctypes.c_int32), ("krylov", ctypes.c_int32)]
+                ("fft_coarse", ctypes.c_int32), ("krylov", ctypes.c_int32),
+                ("krylov_left", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -57,6 +57,7 @@ void stmg_default_options(stmg_options* o) {
   o->inner_cycles = 4;
   o->fft_coarse = 262144;
   o->krylov = 0;
+  o->krylov_left = 0;
 }
 
 size_t stmg_workspace_bytes(const stmg_problem* prob, const stmg_options* opt) {

@@ -81,7 +81,8 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   }
   if (o->chunk < 1 || o->chunk_coarse < 1 || o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1 ||
       o->max_levels < 1 || o->max_cycles < 1 || !(o->rtol > 0.0) || !(o->omega > 0.0) ||
-      o->inner_cycles < 1 || o->fft_coarse < 0 || o->krylov < 0 || o->krylov > kKrylovMax) {
+      o->inner_cycles < 1 || o->fft_coarse < 0 || o->krylov < 0 || o->krylov > kKrylovMax ||
+      o->krylov_left < 0 || o->krylov_left > 1) {
     set_error("invalid options");
     return STMG_EINVAL;
   }
@@ -994,21 +995,35 @@ int Solver::solve_fgmres(bool adj, int react, const double* f, const double* u0,
     HIP_TRY(hipEventRecord(kh.ev, stream));
     return hipEventSynchronize(kh.ev);
   };
-  // z_j = M^-1 V_j: one V-cycle from zero (FP32 on a unit-norm copy of V_j in
-  // mixed precision)
-  auto precondition = [&](int j) -> hipError_t {
+  // out = M^-1 (alpha in): one V-cycle from zero (FP32 on a cast copy in
+  // mixed precision); the result lands in *out, which may trade places with
+  // the ping-pong partner *spare
+  int vcount = 0;
+  auto vcyc = [&](const double* in, double alpha, double** out, double** spare) -> hipError_t {
+    ++vcount;
     if (!mixed) {
       double* res = nullptr;
-      HIP_TRY(vcycle<double>(0, adj, react, Zb[j], Zb[m], Vb[j], nullptr, true, &res, 0));
-      if (res == Zb[m]) std::swap(Zb[j], Zb[m]);
-      else if (res != Zb[j]) return hipErrorInvalidValue;
+      HIP_TRY(vcycle<double>(0, adj, react, *out, *spare, in, nullptr, true, &res, 0));
+      if (res == *spare) std::swap(*out, *spare);
+      else if (res != *out) return hipErrorInvalidValue;
       return hipSuccess;
     }
-    HIP_TRY((launch_axpy_cast<double, float>(n, Vb[j], std::sqrt(inv2[j]), L0.f32, false, stream)));
+    HIP_TRY((launch_axpy_cast<double, float>(n, in, alpha, L0.f32, false, stream)));
     float* res = nullptr;
     HIP_TRY(vcycle<float>(0, adj, react, L0.A32, L0.B32, L0.f32, nullptr, true, &res, 0));
     if (!res) return hipErrorInvalidValue;
-    return launch_axpy_cast<float, double>(n, res, 1.0, Zb[j], false, stream);
+    return launch_axpy_cast<float, double>(n, res, 1.0, *out, false, stream);
+  };
+  // Left preconditioning (GMRES on M^-1 A U = M^-1 b, stop on the
+  // preconditioned residual): the basis is built from W = M^-1 (-A V_j) in
+  // place of -A M^-1 V_j; Zb[0] holds -A V_j (or the restart residual) and
+  // Zb[1] is the cycle's ping-pong partner.
+  const bool left = opt.krylov_left != 0;
+  double* T = Zb[0];
+  double* spare = Zb[1];
+  double pscale = 0.0;  // first preconditioned residual norm (left)
+  auto sync_vs = [&]() {
+    for (int i = 0; i <= m; ++i) Vs.v[i] = Vb[i];
   };
   int steps = 0;
   int status = STMG_OK;
@@ -1020,14 +1035,33 @@ int Solver::solve_fgmres(bool adj, int react, const double* f, const double* u0,
   bool est_done = false;
   int miss = 0;
   for (;;) {
-    // r = b - A U is the first (unnormalised) basis vector
-    HIP_CHECK(residual64<double>(adj, react, U, f, u0, Vb[0], kh.d));
+    // r = b - A U is the first (unnormalised) basis vector; with left
+    // preconditioning M^-1 r is
+    HIP_CHECK(residual64<double>(adj, react, U, f, u0, left ? T : Vb[0], kh.d));
     HIP_CHECK(wait());
-    const double beta = std::sqrt(*hres);
-    rel = beta / scale;
+    const double rnorm = std::sqrt(*hres);
+    rel = rnorm / scale;
     if (!std::isfinite(rel)) { status = STMG_ENAN; break; }
-    if (rel <= rtol || beta == 0.0) break;
-    if (steps >= opt.max_cycles) { status = STMG_ENOTCONV; break; }
+    if (rnorm == 0.0) break;
+    double beta = rnorm;
+    double crit = rel;  // the quantity the stop test compares with rtol
+    if (left) {
+      // (this cycle also checks the final iterate, so the count may end one
+      // above max_cycles)
+      HIP_CHECK(vcyc(T, 1.0, &Vb[0], &spare));
+      sync_vs();
+      int nb = 0;
+      HIP_CHECK(launch_kortho(Vb[0], Vs, 0, KCoef{}, nullptr, n, false, kpart, &nb, stream));
+      HIP_CHECK(launch_kreduce(kpart, nb, 1, d1, m1, stream));
+      HIP_CHECK(wait());
+      beta = std::sqrt(h1[0]);
+      if (!std::isfinite(beta)) { status = STMG_ENAN; break; }
+      if (pscale == 0.0) pscale = beta;
+      if (beta == 0.0) break;
+      crit = beta / pscale;
+    }
+    if (crit <= rtol) break;
+    if ((left ? vcount : steps) >= opt.max_cycles) { status = STMG_ENOTCONV; break; }
     miss = est_done ? miss + 1 : 0;
     if (miss >= 2) { status = STMG_ENOTCONV; break; }
     est_done = false;
@@ -1037,8 +1071,14 @@ int Solver::solve_fgmres(bool adj, int react, const double* f, const double* u0,
     int k = 0;
     bool bad = false;
     for (int j = 0; j < m; ++j) {
-      HIP_CHECK(precondition(j));
-      HIP_CHECK(residual64<double>(adj, react, Zb[j], nullptr, nullptr, Vb[j + 1], kdev));
+      if (left) {
+        HIP_CHECK(residual64<double>(adj, react, Vb[j], nullptr, nullptr, T, kdev));
+        HIP_CHECK(vcyc(T, 1.0, &Vb[j + 1], &spare));
+        sync_vs();
+      } else {
+        HIP_CHECK(vcyc(Vb[j], std::sqrt(inv2[j]), &Zb[j], &Zb[m]));
+        HIP_CHECK(residual64<double>(adj, react, Zb[j], nullptr, nullptr, Vb[j + 1], kdev));
+      }
       KCoef s{};
       for (int i = 0; i <= j; ++i) s.c[i] = inv2[i];
       int nb = 0;
@@ -1060,8 +1100,11 @@ int Solver::solve_fgmres(bool adj, int react, const double* f, const double* u0,
         for (int i = 0; i <= j; ++i) hcol[i] += h2[i];
         nw2 = h3[j + 1];
       }
-      for (int i = 0; i <= j; ++i) Hs(i, j) = std::sqrt(inv2[i]) * hcol[i];
-      const double hn = std::sqrt(nw2);
+      // right: the direction is zhat_j = -Z_j with A zhat_j = W; left: the
+      // basis vector v_j = V_j / ||V_j|| itself, with (-M^-1 A) v_j = W / ||V_j||
+      const double aj = left ? std::sqrt(inv2[j]) : 1.0;
+      for (int i = 0; i <= j; ++i) Hs(i, j) = aj * std::sqrt(inv2[i]) * hcol[i];
+      const double hn = aj * std::sqrt(nw2);
       Hs(j + 1, j) = hn;
       ++steps;
       k = j + 1;
@@ -1080,12 +1123,13 @@ int Solver::solve_fgmres(bool adj, int react, const double* f, const double* u0,
       Hs(j + 1, j) = 0.0;
       g[j + 1] = -sn[j] * g[j];
       g[j] = cs[j] * g[j];
-      if (std::fabs(g[j + 1]) <= rtol * scale) { est_done = true; break; }
-      if (steps >= opt.max_cycles || hn == 0.0) break;
+      if (std::fabs(g[j + 1]) <= rtol * (left ? pscale : scale)) { est_done = true; break; }
+      if ((left ? vcount : steps) >= opt.max_cycles || hn == 0.0) break;
       inv2[j + 1] = 1.0 / nw2;
     }
     if (bad) { status = STMG_ENAN; rel = std::numeric_limits<double>::quiet_NaN(); break; }
-    // y = R^-1 g, U += sum_j y_j zhat_j = U - sum_j y_j Z_j
+    // y = R^-1 g; right: U += sum_j y_j zhat_j = U - sum_j y_j Z_j; left:
+    // the operator of the Arnoldi relation is -M^-1 A, so U -= sum_j y_j v_j
     KCoef y{};
     for (int i = k - 1; i >= 0; --i) {
       double t = g[i];
@@ -1094,12 +1138,12 @@ int Solver::solve_fgmres(bool adj, int react, const double* f, const double* u0,
     }
     KVecs Zs{};
     for (int i = 0; i < k; ++i) {
-      Zs.v[i] = Zb[i];
-      y.c[i] = -y.c[i];
+      Zs.v[i] = left ? Vb[i] : Zb[i];
+      y.c[i] = left ? -y.c[i] * std::sqrt(inv2[i]) : -y.c[i];
     }
     HIP_CHECK(launch_kcombine(U, Zs, k, y, n, stream));
   }
-  *cycles += steps;
+  *cycles += vcount;
   *rel_out = rel;
   if (status != STMG_OK) set_error(std::string("Krylov solve stopped: ") + stmg_status_string(status));
   return status;

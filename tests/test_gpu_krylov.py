@@ -277,3 +277,35 @@ def test_fgmres_rd2d_full(prec):
     got = U.cpu().numpy()
     assert rel_err(got, ref) <= 1e-9
     assert rel_err(got[-1, -1], ref[-1, -1]) <= 1e-9
+
+
+@pytest.mark.parametrize("coarsen", ["space", "smmg"])
+@pytest.mark.parametrize("k", [1, 3, 5, 7])
+def test_left_preconditioned_steps_match_oracle(coarsen, k):
+    """Left preconditioning (GMRES on M^-1 A U = M^-1 b, one V-cycle as M):
+    the iterate after k Krylov steps (restart 5) against the oracle's GMRES
+    on the same left-preconditioned system.  The V-cycle count is k plus one
+    per restart residual plus the final check."""
+    print("case left steps", coarsen, k, flush=True)
+    u0 = si.u0_heat1d(SMALL)
+    ref, hist, steps = krylov.solve(SMALL, u0, rtol=0.0, restart=5, max_steps=k, left=True, coarsen=coarsen,
+                                    **HIER)
+    assert steps == k
+    cycles = k + 1 + (k - 1) // 5
+    h = H(SMALL, coarsen=coarsen, krylov=5, krylov_left=1, max_cycles=cycles, rtol=1e-30, **HIER)
+    U, st = h.solve(T(u0), check=False)
+    assert st["status"] == -4 and st["cycles"] == cycles + 1
+    assert_close(U.cpu().numpy(), ref, 1e-9, "left-preconditioned iterate after %d steps" % k)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_left_preconditioned_paper_heat1d(prec):
+    """The paper's heat example (M = 3) with the preconditioned-residual stop
+    at 1e-9: the end value against the stepper."""
+    print("case left paper heat1d", prec, flush=True)
+    prob = si.paper_heat1d(3)
+    u0 = si.u0_paper_heat1d(prob)
+    U, st = H(prob, krylov=10, krylov_left=1, precision=prec, coarsen="space", max_levels=7, rtol=1e-9).solve(T(u0))
+    assert st["status"] == 0
+    ref = stepper.solve_linear(prob, u0)
+    assert np.abs(U[-1, -1].cpu().numpy() - ref[-1, -1]).max() <= 1e-9

@@ -117,3 +117,32 @@ def test_vcycle_preconditioned_solve(coarsen, restart):
     else:
         assert vh[-1] <= 1e-10
         assert steps < len(vh)
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_left_preconditioned_minimises_preconditioned_residual(k):
+    # GMRES on P A x = P b: after k steps x minimises ||P (b - A x)|| over
+    # K_k(P A, P b), spanned here by explicit powers
+    rng = np.random.default_rng(8)
+    n = 25
+    A, b = _system(n, 9)
+    P = np.eye(n) + 0.2 * rng.standard_normal((n, n)) / np.sqrt(n)
+    x, hist, _ = krylov.fgmres(lambda v: P @ (A @ v), lambda v: v, P @ b, restart=10, rtol=0.0, max_steps=k)
+    cols = [P @ b]
+    for _ in range(k - 1):
+        cols.append(P @ (A @ cols[-1]))
+    S = np.stack(cols, axis=1)
+    y = np.linalg.lstsq(P @ A @ S, P @ b, rcond=None)[0]
+    xs = S @ y
+    assert np.abs(x - xs).max() <= 1e-9 * np.abs(xs).max()
+    assert abs(hist[-1] - np.linalg.norm(P @ (b - A @ xs)) / np.linalg.norm(P @ b)) <= 1e-12
+
+
+def test_left_preconditioned_vcycle_solve():
+    prob = si.problem(1, 32, 3, 8, 0.5, nu=1.0)
+    u0 = si.u0_heat1d(prob)
+    kw = dict(coarsen="space", fft_coarse=0, min_coarse=16)
+    U, hist, steps = krylov.solve(prob, u0, rtol=1e-11, restart=10, left=True, **kw)
+    ref = allatonce.dense_solve(prob, u0)
+    assert hist[-1] <= 1e-11
+    assert np.abs(U - ref).max() <= 1e-8 * np.abs(ref).max()
