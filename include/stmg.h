@@ -119,10 +119,11 @@ typedef struct {
                          equation per FP64 refinement step, 4                 */
   int32_t fft_coarse; /* periodic grids with a linear reaction: coarsening
                          also stops at the first level below the finest whose
-                         planes hold <= 1024 points and which holds <=
+                         planes hold <= 1024 points (2D: or have power-of-two
+                         sides of <= 64 points) and which holds <=
                          fft_coarse unknowns; that level is solved exactly by
                          Fourier diagonalization in space and the slab
-                         recurrence per mode.  262144; 0 = off                */
+                         recurrence per mode.  4194304; 0 = off               */
   int32_t krylov;     /* restart length m (1..32) of an outer flexible GMRES
                          around the cycles: one V-cycle from a zero guess is
                          the right preconditioner of each Krylov step (FP32

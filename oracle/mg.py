@@ -42,13 +42,18 @@ notes):
   time structure (K_q, the Radau mass diag(b), l(0) and the end-node
   coupling), so rediscretization and Galerkin agree for this transfer.
 * coarsest level: coarsening also stops at the first level below the finest
-  whose planes hold at most `fft_plane` points and which holds at most
+  whose planes hold at most `fft_plane` points (or, in 2D, whose sides are
+  powers of two of at most `fft_side` points) and which holds at most
   `fft_coarse` unknowns (0 disables the rule).  This is a choice of where the
   exact coarse solve sits (the paper fixes the number of levels per run); the
-  exact solve itself is the same direct slab-by-slab solve on any level.
+  exact solve itself is the same direct slab-by-slab solve on any level
+  (one LU factorization of the slab matrix: dense up to 4096 unknowns per
+  slab, sparse above).
 """
 import numpy as np
 import scipy.linalg
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from . import radau
 
@@ -107,18 +112,41 @@ class Level:
             cols.append(v.reshape(-1))
         return np.array(cols).T
 
-    def exact_solve(self, f):
+    def slab_matrix_sparse(self):
+        """The same slab block assembled from its Kronecker structure,
+        Kq (x) I + diag(dt b) (x) (-Lap + lam I), with the periodic 1D second
+        differences Lap = cx D_x (+ cy D_y) on the [y][x] ordering."""
+        def d2(n, c):
+            I = sp.identity(n, format="csr")
+            S = sp.csr_matrix((np.ones(n), (np.arange(n), (np.arange(n) + 1) % n)), shape=(n, n))
+            return c * (S + S.T - 2 * I)
+        lap = sp.kron(sp.identity(self.ny), d2(self.nx, self.cx))
+        if self.dim == 2:
+            lap = lap + sp.kron(d2(self.ny, self.cy), sp.identity(self.nx))
+        P = self.nx * self.ny
+        return sp.csc_matrix(sp.kron(self.Kq, sp.identity(P)) +
+                             sp.kron(self.dt * np.diag(self.b), -lap + self.lam * sp.identity(P)))
+
+    def exact_solve(self, f, dense=None):
         """Slab after slab, A_slab U_n = f_n + l(0) (x) U_{n-1,M}, with one LU
-        factorization of the (shared) dense slab matrix."""
-        if getattr(self, "_lu", None) is None:
-            self._lu = scipy.linalg.lu_factor(self.slab_matrix())
-        lu = self._lu
+        factorization of the (shared) slab matrix: dense for at most 4096
+        unknowns per slab, sparse (SuperLU) above, or as `dense` says."""
+        if dense is None:
+            dense = self.M * self.nx * self.ny <= 4096
+        key = "_lu" if dense else "_splu"
+        if getattr(self, key, None) is None:
+            if dense:
+                self._lu = scipy.linalg.lu_factor(self.slab_matrix())
+            else:
+                self._splu = spla.splu(self.slab_matrix_sparse())
         U = np.zeros(self.shape)
         for n in range(self.N):
             rhs = f[n].copy()
             if n > 0:
                 rhs = rhs + self.l0[:, None, None] * U[n - 1, -1][None]
-            U[n] = scipy.linalg.lu_solve(lu, rhs.reshape(-1)).reshape(self.M, self.ny, self.nx)
+            b = rhs.reshape(-1)
+            x = scipy.linalg.lu_solve(self._lu, b) if dense else self._splu.solve(b)
+            U[n] = x.reshape(self.M, self.ny, self.nx)
         return U
 
 
@@ -179,8 +207,8 @@ def node_prolongation(Mf, Mc):
     return P
 
 
-def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30, fft_coarse=262144,
-              fft_plane=1024):
+def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30, fft_coarse=1 << 22,
+              fft_plane=1024, fft_side=64):
     """Level list and the coarsening kind between consecutive levels.
 
     kinds[l] is 's' (space), 't' (time) or 'st' (both) for the step l -> l+1.
@@ -199,7 +227,9 @@ def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30, f
         l = levels[-1]
         if l.M * l.nx * l.ny * l.N <= min_coarse:
             break
-        if len(levels) > 1 and l.nx * l.ny <= fft_plane and l.M * l.nx * l.ny * l.N <= fft_coarse:
+        pow2_sides = dim == 2 and all(n >= 2 and n & (n - 1) == 0 and n <= fft_side for n in (l.nx, l.ny))
+        if len(levels) > 1 and (l.nx * l.ny <= fft_plane or pow2_sides) and \
+                l.M * l.nx * l.ny * l.N <= fft_coarse:
             break
         can_s = l.nx % 2 == 0 and l.nx >= 4 and (dim == 1 or (l.ny % 2 == 0 and l.ny >= 4))
         can_t = l.N % 2 == 0

@@ -55,7 +55,7 @@ void stmg_default_options(stmg_options* o) {
   o->sdc = 0;
   o->autotune = 0;
   o->inner_cycles = 4;
-  o->fft_coarse = 262144;
+  o->fft_coarse = 1 << 22;
   o->krylov = 0;
   o->krylov_left = 0;
 }

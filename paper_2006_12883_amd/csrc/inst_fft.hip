@@ -5,12 +5,14 @@
 //   S_q = K + diag(dt b) (lambda_q + lambda),
 //   lambda_q = cx (2 - 2 cos(2 pi kx / nx)) + cy (2 - 2 cos(2 pi ky / ny)),
 // and the time coupling -cin (x) cout^T acts mode by mode as well.  So
-//   1. transform every plane of f (and u0) to Fourier space (k_fft_fwd),
+//   1. transform every plane of f (and u0) to Fourier space (k_fft_fwd*),
 //   2. run the slab recurrence u_n = S_q^{-1} (f_n + cin (cout . u_{n-1}))
-//      per mode (k_fft_modes; u_{-1} enters as the transform of u0),
-//   3. transform back (k_fft_inv).
-// The transforms are direct DFTs with twiddles from a table (planes of at
-// most kFftMaxPlane points); all arithmetic is FP64 whatever the storage type.
+//      per mode (k_fft_modes_*; u_{-1} enters as the transform of u0),
+//   3. transform back (k_fft_inv*).
+// The transforms are radix-2 FFTs for power-of-two sides (in registers for
+// 2D planes with sides of at most kFftRegSide, else in LDS) and direct DFTs
+// with twiddles from a table otherwise (planes of at most kFftMaxPlane
+// points); all arithmetic is FP64 whatever the storage type.
 #include "kernels.hpp"
 
 namespace stmg {
@@ -268,76 +270,7 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_inv2(int nx, int ny, int lgx,
 // Per-mode slab recurrence in Fourier space, in place on F ([N][M][P]
 // complex): u_n = Sinv_q (F_n + cin p), p = cout . u_n, starting from
 // p = (transform of u0)(q) when u0F is given, else 0.  Sinv: [P][M][M] real.
-// Slabs go in groups of kFftGroup whose loads are issued together.
-constexpr int kFftGroup = 8;
-template <int M>
-__global__ __launch_bounds__(kFftBlock) void k_fft_modes(int P, int N, double* __restrict__ F,
-                                                         const double* __restrict__ u0F,
-                                                         const double* __restrict__ Sinv,
-                                                         const OpParams p) {
-  const int q = blockIdx.x * kFftBlock + threadIdx.x;
-  if (q >= P) return;
-  double S[M][M];
-#pragma unroll
-  for (int i = 0; i < M; ++i)
-#pragma unroll
-    for (int j = 0; j < M; ++j) S[i][j] = Sinv[((size_t)q * M + i) * M + j];
-  double pr = 0.0, pi = 0.0;
-  if (u0F) {
-    pr = u0F[2 * q];
-    pi = u0F[2 * q + 1];
-  }
-  for (int n0 = 0; n0 < N; n0 += kFftGroup) {
-    double vr[kFftGroup][M], vi[kFftGroup][M];
-#pragma unroll
-    for (int g = 0; g < kFftGroup; ++g) {
-      if (n0 + g < N) {
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-          const size_t at = 2 * (((size_t)(n0 + g) * M + m) * P + q);
-          vr[g][m] = F[at];
-          vi[g][m] = F[at + 1];
-        }
-      }
-    }
-#pragma unroll
-    for (int g = 0; g < kFftGroup; ++g) {
-      if (n0 + g < N) {
-        double ur[M], ui[M];
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-          vr[g][i] += p.cin[i] * pr;
-          vi[g][i] += p.cin[i] * pi;
-        }
-        double nr = 0.0, ni = 0.0;
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-          double sr = 0.0, si = 0.0;
-#pragma unroll
-          for (int j = 0; j < M; ++j) {
-            sr += S[i][j] * vr[g][j];
-            si += S[i][j] * vi[g][j];
-          }
-          ur[i] = sr;
-          ui[i] = si;
-          nr += p.cout[i] * sr;
-          ni += p.cout[i] * si;
-        }
-        pr = nr;
-        pi = ni;
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-          const size_t at = 2 * (((size_t)(n0 + g) * M + m) * P + q);
-          F[at] = ur[m];
-          F[at + 1] = ui[m];
-        }
-      }
-    }
-  }
-}
-
-// The same recurrence with the workgroup's MB modes staged in LDS for every
-// slab.  With c = cout^T S_q, beta = c . cin and d = S_q cin the coupling
+// Here the workgroup's MB modes are staged in LDS for every slab.  With c = cout^T S_q, beta = c . cin and d = S_q cin the coupling
 // values obey the scalar recurrence
 //   p_n = c . F_n + beta p_{n-1},
 // so every M-vector product runs in parallel over (slab, mode) and only the
@@ -516,19 +449,422 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_inv(int nx, int ny, const dou
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident transforms for 2D planes with power-of-two sides of at
+// most 64 points (fft_reg_plane).  A wave holds 64 / n lines of n points, lane
+// l the point l mod n of line l / n; one radix-2 stage of span h pairs lane l
+// with lane l ^ h.  The forward transform runs decimation in frequency
+// (natural order in, bit-reversed order out), the inverse decimation in time
+// (bit-reversed in, natural out), so no permutation is ever applied: the
+// Fourier coefficients stay in bit-reversed order.  Between the two
+// directions the plane is transposed through LDS (padded lines).
+//
+// Planes are real, so F(-kx, -ky) = conj F(kx, ky) and only the columns
+// kx = 0 .. nx/2 are kept: in bit-reversed order these are the even columns
+// kx' = 2c (kx < nx/2) and kx' = 1 (kx = nx/2), stored as compact columns
+// c = 0 .. nx/2 (column nx/2 for kx' = 1): the spectrum of a plane is
+// [nx/2 + 1][ny] complex, ky in bit-reversed order, and the per-mode tables
+// follow that order.
+constexpr int kRegBlock = 512;
+constexpr int kRegWaves = kRegBlock / 64;
+constexpr int kRegLds = kFftRegSide * (kFftRegSide / 2 + 2);
+
+// A thread takes R lines per direction (R = P / 512, at least 1): all R are
+// loaded first and every butterfly stage runs over the R lines together, so
+// the loads and the shuffles of different lines overlap.  The butterflies are
+// branch-free: the lower lane of a pair uses the twiddle 1 and the sign +1.
+//
+// Decimation in frequency along lines of n points.  W: cos, sin of 2 pi j / n
+// for j < n; sgn -1 forward.  Lower lane of a pair: u + v; upper: (u - v) w^j
+// with j = (l mod h) n / (2 h), i.e. (sigma own + partner) w with sigma = -1.
+template <int R>
+__device__ __forceinline__ void dif_lines(double (&re)[R], double (&im)[R], int n, const double* W,
+                                          double sgn) {
+  const int lane = threadIdx.x & 63;
+  for (int h = n >> 1; h >= 1; h >>= 1) {
+    const bool up = (lane & h) != 0;
+    const int j = (lane & (h - 1)) * (n / (2 * h));
+    const double c = up ? W[2 * j] : 1.0, s = up ? sgn * W[2 * j + 1] : 0.0;
+    const double sig = up ? -1.0 : 1.0;
+    double pr[R], pi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      pr[r] = __shfl_xor(re[r], h);
+      pi[r] = __shfl_xor(im[r], h);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double ar = fma(sig, re[r], pr[r]), ai = fma(sig, im[r], pi[r]);
+      re[r] = ar * c - ai * s;
+      im[r] = ar * s + ai * c;
+    }
+  }
+}
+
+// Decimation in time along lines of n points (bit-reversed input): every lane
+// forms x = own w^j (w = 1 on the lower lane), the pair exchanges x; lower:
+// u + t, upper: u - t (t = v w^j).
+template <int R>
+__device__ __forceinline__ void dit_lines(double (&re)[R], double (&im)[R], int n, const double* W,
+                                          double sgn) {
+  const int lane = threadIdx.x & 63;
+  for (int h = 1; h < n; h <<= 1) {
+    const bool up = (lane & h) != 0;
+    const int j = (lane & (h - 1)) * (n / (2 * h));
+    const double c = up ? W[2 * j] : 1.0, s = up ? sgn * W[2 * j + 1] : 0.0;
+    const double sig = up ? -1.0 : 1.0;
+    double xr[R], xi[R], pr[R], pi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      xr[r] = re[r] * c - im[r] * s;
+      xi[r] = re[r] * s + im[r] * c;
+      pr[r] = __shfl_xor(xr[r], h);
+      pi[r] = __shfl_xor(xi[r], h);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      re[r] = fma(sig, xr[r], pr[r]);
+      im[r] = fma(sig, xi[r], pi[r]);
+    }
+  }
+}
+
+// Lines handled by a thread: line r is (wid + kRegWaves r) lpw + line along
+// the other direction.  R = P / 512 (at least 1) lines cover a full
+// direction; the real-valued row passes pair rows r and r + RP in one complex
+// line (RP = R / 2 when R >= 2); the compact columns (nx/2 + 1 of them) take
+// RC = R / 2 + 1 lines (R >= 2).
+template <int R>
+struct RegLines {
+  static constexpr int RP = R >= 2 ? R / 2 : 1;
+  static constexpr int RC = R >= 2 ? R / 2 + 1 : 1;
+};
+
+__device__ __forceinline__ int brev_n(int i, int lg) { return (int)(__brev((unsigned)i) >> (32 - lg)); }
+
+// Forward: plane pl of f (or u0 for pl == nplanes) -> out[pl][c][ky'].
+// Rows: two real rows a, b form z = a + i b; after the transform
+// A[k] = (Z[k] + conj Z[-k]) / 2, B[k] = (Z[k] - conj Z[-k]) / 2i, with Z[-k]
+// read from the lane holding bit-reversed (n - k) mod n; lanes of the kept
+// columns write them to the tile [c][y] (stride ny + 1).
+template <typename T, int R>
+__global__ __launch_bounds__(kRegBlock) void k_fft_fwd_reg(int nx, int ny, int lgx, int nplanes,
+                                                           const T* __restrict__ f,
+                                                           const double* __restrict__ u0,
+                                                           const double* __restrict__ tw,
+                                                           double* __restrict__ out) {
+  constexpr int RP = RegLines<R>::RP, RC = RegLines<R>::RC;
+  constexpr bool PACK = R >= 2;
+  __shared__ double Tr[kRegLds];
+  __shared__ double Ti[kRegLds];
+  __shared__ double W[4 * kFftRegSide];
+  const int P = nx * ny, nh = nx >> 1, Ph = (nh + 1) * ny;
+  const int pl = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int i = tid; i < 2 * (nx + ny); i += kRegBlock) W[i] = tw[i];
+  const double* src = pl < nplanes ? nullptr : u0;
+  auto ld = [&](int y, int x) -> double {
+    if (y >= ny) return 0.0;
+    if (src) return src[y * nx + x];
+    return f ? (double)f[(size_t)pl * P + y * nx + x] : 0.0;
+  };
+  // rows: lane = x in, kx' = pos out
+  {
+    const int lpw = 64 / nx, line = lane / nx, pos = lane - line * nx;
+    double re[RP], im[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      re[r] = ld((wid + kRegWaves * r) * lpw + line, pos);
+      im[r] = PACK ? ld((wid + kRegWaves * (r + RP)) * lpw + line, pos) : 0.0;
+    }
+    __syncthreads();  // W
+    dif_lines<RP>(re, im, nx, W, -1.0);
+    // lane of the partner coefficient Z[-k], k = bitrev(pos); kept column
+    const int kn = (nx - brev_n(pos, lgx)) & (nx - 1);
+    const int src_lane = line * nx + brev_n(kn, lgx);
+    const bool keep = (pos & 1) == 0 || pos == 1;
+    const int c = (pos & 1) ? nh : pos >> 1;
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int ya = (wid + kRegWaves * r) * lpw + line;
+      if (PACK) {
+        const int yb = (wid + kRegWaves * (r + RP)) * lpw + line;
+        const double wr = __shfl(re[r], src_lane), wi = __shfl(im[r], src_lane);
+        if (keep && ya < ny) {
+          Tr[c * (ny + 1) + ya] = 0.5 * (re[r] + wr);
+          Ti[c * (ny + 1) + ya] = 0.5 * (im[r] - wi);
+        }
+        if (keep && yb < ny) {
+          Tr[c * (ny + 1) + yb] = 0.5 * (im[r] + wi);
+          Ti[c * (ny + 1) + yb] = 0.5 * (wr - re[r]);
+        }
+      } else if (keep && ya < ny) {
+        Tr[c * (ny + 1) + ya] = re[r];
+        Ti[c * (ny + 1) + ya] = im[r];
+      }
+    }
+  }
+  __syncthreads();
+  // kept columns: lane = y in, ky' out
+  {
+    const int lpw = 64 / ny, line = lane / ny, pos = lane - line * ny;
+    double re[RC], im[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      const int c = (wid + kRegWaves * r) * lpw + line;
+      re[r] = c <= nh ? Tr[c * (ny + 1) + pos] : 0.0;
+      im[r] = c <= nh ? Ti[c * (ny + 1) + pos] : 0.0;
+    }
+    dif_lines<RC>(re, im, ny, W + 2 * nx, -1.0);
+    double2* o = reinterpret_cast<double2*>(out + (size_t)pl * 2 * Ph);
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      const int c = (wid + kRegWaves * r) * lpw + line;
+      if (c <= nh) o[c * ny + pos] = make_double2(re[r], im[r]);
+    }
+  }
+}
+
+// Inverse: F[pl][c][ky'] -> U[pl][y][x] = Re (1/P) sum F exp(+i ...).
+// Columns: the kept columns back to y (tile [y][c], stride nh + 2).  Rows:
+// lane kx' takes its column from the tile, for the dropped columns (odd
+// kx' != 1, kx > nx/2) as the conjugate of column nx - kx; the row spectra
+// are Hermitian (the field is real), so two rows a, b go through one
+// transform of A + i B and come out as its real and imaginary parts.
+template <typename T, int R>
+__global__ __launch_bounds__(kRegBlock) void k_fft_inv_reg(int nx, int ny, int lgx,
+                                                           const double* __restrict__ F,
+                                                           const double* __restrict__ tw,
+                                                           T* __restrict__ U) {
+  constexpr int RP = RegLines<R>::RP, RC = RegLines<R>::RC;
+  constexpr bool PACK = R >= 2;
+  __shared__ double Tr[kRegLds];
+  __shared__ double Ti[kRegLds];
+  __shared__ double W[4 * kFftRegSide];
+  const int P = nx * ny, nh = nx >> 1, Ph = (nh + 1) * ny, ts = nh + 2;
+  const int pl = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int i = tid; i < 2 * (nx + ny); i += kRegBlock) W[i] = tw[i];
+  // kept columns: lane = ky' in, y out
+  {
+    const int lpw = 64 / ny, line = lane / ny, pos = lane - line * ny;
+    const double2* src = reinterpret_cast<const double2*>(F + (size_t)pl * 2 * Ph);
+    double re[RC], im[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      const int c = (wid + kRegWaves * r) * lpw + line;
+      const double2 v = c <= nh ? src[c * ny + pos] : make_double2(0.0, 0.0);
+      re[r] = v.x;
+      im[r] = v.y;
+    }
+    __syncthreads();  // W
+    dit_lines<RC>(re, im, ny, W + 2 * nx, 1.0);
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      const int c = (wid + kRegWaves * r) * lpw + line;
+      if (c <= nh) {
+        Tr[pos * ts + c] = re[r];
+        Ti[pos * ts + c] = im[r];
+      }
+    }
+  }
+  __syncthreads();
+  // rows: lane = kx' in, x out
+  {
+    const int lpw = 64 / nx, line = lane / nx, pos = lane - line * nx;
+    int c;
+    double cs = 1.0;  // -1: conjugate
+    if ((pos & 1) == 0) c = pos >> 1;
+    else if (pos == 1) c = nh;
+    else {
+      c = brev_n(nx - brev_n(pos, lgx), lgx) >> 1;
+      cs = -1.0;
+    }
+    double re[RP], im[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int ya = (wid + kRegWaves * r) * lpw + line;
+      const double ar = ya < ny ? Tr[ya * ts + c] : 0.0;
+      const double ai = ya < ny ? cs * Ti[ya * ts + c] : 0.0;
+      if (PACK) {
+        const int yb = (wid + kRegWaves * (r + RP)) * lpw + line;
+        const double br = yb < ny ? Tr[yb * ts + c] : 0.0;
+        const double bi = yb < ny ? cs * Ti[yb * ts + c] : 0.0;
+        re[r] = ar - bi;
+        im[r] = ai + br;
+      } else {
+        re[r] = ar;
+        im[r] = ai;
+      }
+    }
+    dit_lines<RP>(re, im, nx, W, 1.0);
+    const double scale = 1.0 / (double)P;
+    T* dst = U + (size_t)pl * P;
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int ya = (wid + kRegWaves * r) * lpw + line;
+      if (ya < ny) dst[ya * nx + pos] = (T)(re[r] * scale);
+      if (PACK) {
+        const int yb = (wid + kRegWaves * (r + RP)) * lpw + line;
+        if (yb < ny) dst[yb * nx + pos] = (T)(im[r] * scale);
+      }
+    }
+  }
+}
+
+// Per-mode slab recurrence for long time axes (the workgroup's modes do not
+// fit in LDS for all slabs): kChunkQ modes x kChunkC runs of consecutive
+// slabs per workgroup.  With c = cout^T S_q, beta = c . cin, d = S_q cin:
+//   (1) each run folds a_n = c . F_n into s = a_n + beta s from s = 0 and
+//       records s and beta^len;
+//   (2) one thread per mode chains the runs: p entering run r+1 is
+//       s_r + beta^len_r p entering run r (p entering run 0 = transform of
+//       u0, or 0);
+//   (3) each run replays its slabs from its entering p:
+//       u_n = S_q F_n + d p_{n-1}, p_n = a_n + beta p_{n-1}, in place in F.
+// The same recurrence as k_fft_modes_lds, with the chain regrouped by runs.
+constexpr int kChunkQ = 16;
+constexpr int kChunkC = kFftBlock / kChunkQ;
+constexpr int kChunkG = 4;  // slabs whose loads are issued together
+template <int M>
+__global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, double* __restrict__ F,
+                                                               const double* __restrict__ u0F,
+                                                               const double* __restrict__ Sinv,
+                                                               const OpParams p) {
+  __shared__ double Sr[kChunkC][kChunkQ], Si[kChunkC][kChunkQ], Bp[kChunkC][kChunkQ];
+  const int qq = threadIdx.x % kChunkQ, ch = threadIdx.x / kChunkQ;
+  const int q = blockIdx.x * kChunkQ + qq;
+  const bool act = q < P;
+  const int len = (N + kChunkC - 1) / kChunkC;
+  const int n0 = min(ch * len, N), n1 = min(n0 + len, N);
+  double S[M][M], cv[M], dv[M], beta = 0.0;
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j < M; ++j) S[i][j] = act ? Sinv[((size_t)q * M + i) * M + j] : 0.0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    double cj = 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) cj += p.cout[k] * S[k][j];
+    cv[j] = cj;
+    beta += cj * p.cin[j];
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    double dk = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) dk += S[k][j] * p.cin[j];
+    dv[k] = dk;
+  }
+  double2* Fc = reinterpret_cast<double2*>(F);
+  // (1)
+  double sr = 0.0, si = 0.0, bp = 1.0;
+  if (act) {
+    for (int g0 = n0; g0 < n1; g0 += kChunkG) {
+      double2 v[kChunkG][M];
+#pragma unroll
+      for (int g = 0; g < kChunkG; ++g)
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+          v[g][m] = g0 + g < n1 ? Fc[((size_t)(g0 + g) * M + m) * P + q] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int g = 0; g < kChunkG; ++g) {
+        if (g0 + g < n1) {
+          double ar = 0.0, ai = 0.0;
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            ar += cv[j] * v[g][j].x;
+            ai += cv[j] * v[g][j].y;
+          }
+          sr = ar + beta * sr;
+          si = ai + beta * si;
+          bp *= beta;
+        }
+      }
+    }
+  }
+  Sr[ch][qq] = sr;
+  Si[ch][qq] = si;
+  Bp[ch][qq] = bp;
+  __syncthreads();
+  // (2): the entering p of every run replaces its (s, beta^len) in LDS
+  if (ch == 0 && act) {
+    double pr = 0.0, pi = 0.0;
+    if (u0F) {
+      pr = u0F[2 * q];
+      pi = u0F[2 * q + 1];
+    }
+    for (int r = 0; r < kChunkC; ++r) {
+      const double s0 = Sr[r][qq], s1 = Si[r][qq], b = Bp[r][qq];
+      Sr[r][qq] = pr;
+      Si[r][qq] = pi;
+      pr = s0 + b * pr;
+      pi = s1 + b * pi;
+    }
+  }
+  __syncthreads();
+  // (3)
+  if (act) {
+    double pr = Sr[ch][qq], pi = Si[ch][qq];
+    for (int g0 = n0; g0 < n1; g0 += kChunkG) {
+      double2 v[kChunkG][M];
+#pragma unroll
+      for (int g = 0; g < kChunkG; ++g)
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+          v[g][m] = g0 + g < n1 ? Fc[((size_t)(g0 + g) * M + m) * P + q] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int g = 0; g < kChunkG; ++g) {
+        if (g0 + g < n1) {
+          double ar = 0.0, ai = 0.0;
+#pragma unroll
+          for (int k = 0; k < M; ++k) {
+            double ur = dv[k] * pr, ui = dv[k] * pi;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              ur += S[k][j] * v[g][j].x;
+              ui += S[k][j] * v[g][j].y;
+            }
+            Fc[((size_t)(g0 + g) * M + k) * P + q] = make_double2(ur, ui);
+            ar += cv[k] * v[g][k].x;
+            ai += cv[k] * v[g][k].y;
+          }
+          pr = ar + beta * pr;
+          pi = ai + beta * pi;
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 template <typename T>
 hipError_t launch_fft_coarse(const OpParams& p, const double* Sinv, const double* tw, double* work,
                              const T* f, const double* u0, T* U, hipStream_t s) {
   const int P = p.nx * p.ny;
-  if (P > kFftMaxPlane || p.M < 1 || p.M > kMaxM) return hipErrorInvalidValue;
+  const bool reg = fft_reg_plane(p.nx, p.ny);
+  if ((!reg && P > kFftMaxPlane) || p.M < 1 || p.M > kMaxM) return hipErrorInvalidValue;
   const int planes = p.N * p.M;
-  double* u0F = u0 ? work + (size_t)2 * planes * P : nullptr;
+  // modes per plane in Fourier space (the kept half for the register path)
+  const int PF = reg ? (p.nx / 2 + 1) * p.ny : P;
+  double* u0F = u0 ? work + (size_t)2 * planes * PF : nullptr;
   auto lg2 = [](int n) { int l = 0; while ((1 << l) < n) ++l; return (1 << l) == n ? l : -1; };
   const int lgx = lg2(p.nx), lgy = lg2(p.ny);
   const bool pow2 = lgx >= 0 && lgy >= 0;
-  if (pow2)
+  // lines per thread and direction for the register transforms
+  const int R = P <= kRegBlock ? 1 : P / kRegBlock;
+#define LREG(RR, KERNEL, GRID, ...)                                                        \
+  switch (RR) {                                                                            \
+    case 1: hipLaunchKernelGGL((KERNEL<T, 1>), dim3(GRID), dim3(kRegBlock), 0, s, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL((KERNEL<T, 2>), dim3(GRID), dim3(kRegBlock), 0, s, __VA_ARGS__); break; \
+    case 4: hipLaunchKernelGGL((KERNEL<T, 4>), dim3(GRID), dim3(kRegBlock), 0, s, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL((KERNEL<T, 8>), dim3(GRID), dim3(kRegBlock), 0, s, __VA_ARGS__); break; \
+  }
+  if (reg)
+    LREG(R, k_fft_fwd_reg, planes + (u0 ? 1 : 0), p.nx, p.ny, lgx, planes, f, u0, tw, work)
+  else if (pow2)
     hipLaunchKernelGGL((k_fft_fwd2<T>), dim3(planes + (u0 ? 1 : 0)), dim3(kFftBlock), 0, s, p.nx, p.ny,
                        lgx, lgy, planes, f, u0, tw, work);
   else
@@ -539,24 +875,27 @@ hipError_t launch_fft_coarse(const OpParams& p, const double* Sinv, const double
   int MB = (int)(kFftLds / per_mode);
   if (MB > 64) MB = 64;
   if (MB >= 4) {
-    const int gb = (P + MB - 1) / MB;
-#define L(MM)                                                                                       \
-  hipLaunchKernelGGL((k_fft_modes_lds<MM>), dim3(gb), dim3(kFftBlock), 0, s, P, p.N, MB, work, u0F, \
+    const int gb = (PF + MB - 1) / MB;
+#define L(MM)                                                                                        \
+  hipLaunchKernelGGL((k_fft_modes_lds<MM>), dim3(gb), dim3(kFftBlock), 0, s, PF, p.N, MB, work, u0F, \
                      Sinv, p)
     STMG_DISPATCH_M_FFT(L)
 #undef L
   } else {
-    const int gb = (P + kFftBlock - 1) / kFftBlock;
-#define L(MM)                                                                                    \
-  hipLaunchKernelGGL((k_fft_modes<MM>), dim3(gb), dim3(kFftBlock), 0, s, P, p.N, work, u0F, Sinv, p)
+    const int gb = (PF + kChunkQ - 1) / kChunkQ;
+#define L(MM)                                                                                           \
+  hipLaunchKernelGGL((k_fft_modes_chunk<MM>), dim3(gb), dim3(kFftBlock), 0, s, PF, p.N, work, u0F, Sinv, p)
     STMG_DISPATCH_M_FFT(L)
 #undef L
   }
-  if (pow2)
+  if (reg)
+    LREG(R, k_fft_inv_reg, planes, p.nx, p.ny, lgx, work, tw, U)
+  else if (pow2)
     hipLaunchKernelGGL((k_fft_inv2<T>), dim3(planes), dim3(kFftBlock), 0, s, p.nx, p.ny, lgx, lgy, work,
                        tw, U);
   else
     hipLaunchKernelGGL((k_fft_inv<T>), dim3(planes), dim3(kFftBlock), 0, s, p.nx, p.ny, work, tw, U);
+#undef LREG
   return hipGetLastError();
 }
 

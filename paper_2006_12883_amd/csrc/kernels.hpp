@@ -108,11 +108,24 @@ hipError_t launch_coarse_solve(const OpParams& p, const double* Ainv, const T* f
                                const double* u0, T* U, hipStream_t s);
 
 // Exact coarsest solve by 2D discrete Fourier diagonalization (periodic
-// grids, constant reaction, planes of at most kFftMaxPlane points): Sinv holds
-// per mode q the M x M inverse of K + diag(db) (lambda_q + lam) ([P][M][M]),
-// tw the twiddles cos, sin of 2 pi j / nx (j < nx) then of 2 pi j / ny, work
-// 2 (N M + 1) P doubles.  f may be null (zero), u0 enters slab 0 if given.
+// grids, constant reaction, planes that fft_plane_ok takes): Sinv holds
+// per mode q (in the storage order of the transforms) the M x M inverse of
+// K + diag(db) (lambda_q + lam) ([P][M][M]), tw the twiddles cos, sin of
+// 2 pi j / nx (j < nx) then of 2 pi j / ny, work 2 (N M + 1) P doubles.
+// f may be null (zero), u0 enters slab 0 if given.
 constexpr int kFftMaxPlane = 1024;
+// 2D planes whose sides are powers of two of at most kFftRegSide points take
+// radix-2 transforms held in registers: a wave holds 64 / n whole lines of n
+// points and exchanges butterfly partners by lane shuffles.  Their Fourier
+// coefficients are stored column-major in bit-reversed order (storage index
+// kx' ny + ky' holds mode (bitrev kx', bitrev ky')), and Sinv follows that order.
+constexpr int kFftRegSide = 64;
+inline bool fft_pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
+inline bool fft_reg_plane(int nx, int ny) {
+  return ny > 1 && fft_pow2(nx) && fft_pow2(ny) && nx <= kFftRegSide && ny <= kFftRegSide;
+}
+// Planes the Fourier coarsest solve takes.
+inline bool fft_plane_ok(int nx, int ny) { return nx * ny <= kFftMaxPlane || fft_reg_plane(nx, ny); }
 template <typename T>
 hipError_t launch_fft_coarse(const OpParams& p, const double* Sinv, const double* tw, double* work,
                              const T* f, const double* u0, T* U, hipStream_t s);

@@ -121,7 +121,7 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   while (static_cast<int>(lv.size()) < o->max_levels) {
     Level& c = lv.back();
     if (static_cast<long long>(c.M) * c.nx * c.ny * c.N <= o->min_coarse) break;
-    if (fft_ok && lv.size() > 1 && c.nx * c.ny <= kFftMaxPlane &&
+    if (fft_ok && lv.size() > 1 && fft_plane_ok(c.nx, c.ny) &&
         static_cast<long long>(c.M) * c.nx * c.ny * c.N <= o->fft_coarse)
       break;
     const int q = batch_member ? 4 : 2;
@@ -173,7 +173,7 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   }
   const Level& last = lv.back();
   const long long Kc = static_cast<long long>(last.M) * last.nx * last.ny;
-  fft = fft_ok && last.nx * last.ny <= kFftMaxPlane;
+  fft = fft_ok && fft_plane_ok(last.nx, last.ny);
   if (!fft && Kc > 1024) {
     set_error("coarsest level has more than 1024 unknowns per slab");
     return STMG_EUNSUPPORTED;
@@ -423,9 +423,19 @@ int Solver::upload_fft() {
   const OpParams& op = c.op;
   std::vector<double> S(static_cast<size_t>(P) * M * M), ST(static_cast<size_t>(P) * M * M);
   std::vector<long double> a(static_cast<size_t>(M) * M);
+  // storage order of the modes: row-major (ky, kx), or for the register
+  // transforms the kept half kx = 0 .. nx/2 in compact columns c (kx < nx/2:
+  // c = bitrev(kx) / 2; kx = nx/2: c = nx/2), ky bit-reversed: c ny + ky'
+  const bool reg = fft_reg_plane(nx, ny);
+  auto brev = [](int i, int n) {
+    int r = 0;
+    for (int b = 1; b < n; b <<= 1) r = (r << 1) | ((i & b) ? 1 : 0);
+    return r;
+  };
   for (int ky = 0; ky < ny; ++ky)
     for (int kx = 0; kx < nx; ++kx) {
-      const int q = ky * nx + kx;
+      if (reg && kx > nx / 2) continue;  // conjugate of a kept mode
+      const int q = reg ? (kx < nx / 2 ? brev(kx, nx) / 2 : nx / 2) * ny + brev(ky, ny) : ky * nx + kx;
       long double lq = static_cast<long double>(op.cx) * (2.0L - 2.0L * std::cos(twopi * kx / nx));
       if (ny > 1) lq += static_cast<long double>(op.cy) * (2.0L - 2.0L * std::cos(twopi * ky / ny));
       for (int tr = 0; tr < 2; ++tr) {

@@ -49,7 +49,7 @@ def test_residual_matches_allatonce(name, prob):
 
 # fft_coarse: the default coarsest-level rule, and 0 (deep hierarchies down to
 # a few dozen unknowns, which exercise every transfer kind on small grids)
-FFT = [262144, 0]
+FFT = [1 << 22, 0]
 
 
 @pytest.mark.parametrize("name,prob", CASES)
@@ -117,6 +117,43 @@ def test_coarse_solve(name, prob, fft):
     out = torch.empty(lev.shape, dtype=torch.float64, device="cuda:0")
     h.coarse_solve(T(f), out)
     assert_close(out.cpu().numpy(), ref, 1e-12, "coarse solve")
+
+
+# Coarsest planes with power-of-two sides of at most 64 points take the
+# register transforms; long time axes (N (M + 2) > 768) the run-chained mode
+# recurrence.  One space step from the finest level, fft_coarse large.
+REG = [(128, 128, 3, 160), (128, 64, 2, 12), (64, 128, 4, 7), (16, 128, 1, 9), (8, 8, 2, 300),
+       (4, 4, 5, 3), (128, 128, 2, 2)]
+
+
+def _reg_problem(nx, ny, M, N):
+    prob = si.problem(2, nx, M, N, 1.0, nu=0.02, lam=0.7)
+    prob["nx"] = [nx, ny]
+    return prob
+
+
+@pytest.mark.parametrize("nx,ny,M,N", REG)
+def test_coarse_solve_register_transforms(nx, ny, M, N):
+    print("case reg", nx, ny, M, N, flush=True)
+    prob = _reg_problem(nx, ny, M, N)
+    opt = dict(coarsen="space", fft_coarse=1 << 24)
+    levels, kinds = mg.hierarchy(prob, coarsen="space", fft_coarse=1 << 24)
+    assert len(levels) == 2
+    h = H(prob, **opt)
+    assert [(g["nx"], g["ny"], g["N"]) for g in h.levels()] == [(l.nx, l.ny, l.N) for l in levels]
+    lev = levels[-1]
+    f = np.random.default_rng(31).standard_normal(lev.shape)
+    ref = lev.exact_solve(f)
+    out = torch.empty(lev.shape, dtype=torch.float64, device="cuda:0")
+    h.coarse_solve(T(f), out)
+    assert_close(out.cpu().numpy(), ref, 1e-12, "coarse solve")
+    # one V-cycle through it
+    u0 = np.random.default_rng(32).standard_normal(levels[0].shape[2:])
+    U = np.random.default_rng(33).standard_normal(levels[0].shape)
+    refv = mg.vcycle(levels, kinds, U.copy(), mg.rhs(levels, u0))
+    Ud = T(U)
+    h.vcycle(T(u0), Ud)
+    assert_close(Ud.cpu().numpy(), refv, 1e-11, "one V-cycle")
 
 
 @pytest.mark.parametrize("name,prob", CASES)

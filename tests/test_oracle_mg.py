@@ -63,14 +63,24 @@ def test_hierarchy_auto_rule():
 
 def test_hierarchy_coarsest_rule():
     """The coarsest level is the first level below the finest with planes of at
-    most 1024 points and at most fft_coarse unknowns (else the AUTO rule runs on)."""
+    most 1024 points (or power-of-two sides of at most 64) and at most
+    fft_coarse unknowns (else the AUTO rule runs on)."""
     prob = si.config("rd2d")                  # 256^2 x 3 x 256
     levels, kinds = mg.hierarchy(prob)
-    assert kinds == ["s", "s", "t", "t", "s"]
+    assert kinds == ["s", "s"]
     last = levels[-1]
-    assert (last.nx, last.ny, last.N) == (32, 32, 64)
+    assert (last.nx, last.ny, last.N) == (64, 64, 256)
+    # planes of at most 1024 points only: down to 32^2 x 64
+    lv1, k1 = mg.hierarchy(prob, fft_side=0)
+    assert k1 == ["s", "s", "t", "t", "s"] and (lv1[-1].nx, lv1[-1].N) == (32, 64)
+    lv2, k2 = mg.hierarchy(prob, fft_coarse=262144)
+    assert k2 == k1
     deep, dk = mg.hierarchy(prob, fft_coarse=0)
-    assert len(deep) == 15 and dk[:5] == kinds
+    assert len(deep) == 15 and dk[:5] == k1
+    # non-power-of-two sides: the 1024-point rule alone
+    odd = si.problem(2, 96, 2, 8, 1.0, nu=0.02, lam=1.0)
+    lo, ko = mg.hierarchy(odd)
+    assert (lo[-1].nx, lo[-1].ny) == (24, 24)
     # the finest level itself never stops the coarsening
     small = si.problem(2, 16, 2, 4, 0.5, nu=0.02, lam=1.0)
     lv, kk = mg.hierarchy(small)
@@ -124,13 +134,27 @@ def test_smoother_fixed_point(chunk):
     assert np.abs(U1 - Ue).max() < 1e-13
 
 
-def test_exact_coarse_solve():
+@pytest.mark.parametrize("dense", [True, False])
+def test_exact_coarse_solve(dense):
+    """Both factorizations of the slab matrix (dense LU, sparse LU) against the
+    time stepper's direct solve per step."""
     prob = si.problem(2, 8, 2, 6, 0.5, nu=0.02, lam=1.0)
     levels, _ = mg.hierarchy(prob, min_coarse=10 ** 9)
     u0 = si.u0_rd2d(prob, 3)
     f = mg.rhs(levels, u0)
-    U = levels[0].exact_solve(f)
+    U = levels[0].exact_solve(f, dense=dense)
     assert np.abs(U - stepper.solve_linear(prob, u0)).max() < 1e-13
+
+
+@pytest.mark.parametrize("prob", [si.problem(2, 6, 3, 2, 0.5, nu=0.02, lam=1.0),
+                                  si.problem(1, 10, 2, 2, 0.5, nu=0.3, lam=0.1),
+                                  si.problem(2, 2, 2, 2, 0.5, nu=0.1, lam=0.0)])
+def test_slab_matrix_kronecker_form(prob):
+    """The Kronecker assembly of the slab block equals the block built column
+    by column from the level operator (two sizes of 2D, 1D, and the 2-point
+    periodic grid whose two neighbours coincide)."""
+    lev = mg.hierarchy(prob, min_coarse=10 ** 9)[0][0]
+    assert np.abs(lev.slab_matrix_sparse().toarray() - lev.slab_matrix()).max() == 0.0
 
 
 @pytest.mark.parametrize("name,kw", [
