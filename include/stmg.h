@@ -116,7 +116,8 @@ typedef struct {
                          cached in the JSON file named by $STMG_TUNE_CACHE.
                          0 (default): fixed shapes                            */
   int32_t inner_cycles; /* mixed precision: FP32 V-cycles on each correction
-                         equation per FP64 refinement step, 4                 */
+                         equation per FP64 refinement step (at most, with
+                         inner_adapt), 5                                       */
   int32_t fft_coarse; /* periodic grids with a linear reaction: coarsening
                          also stops at the first level below the finest whose
                          planes hold <= 1024 points (2D: or have power-of-two
@@ -143,6 +144,12 @@ typedef struct {
                          V-cycle must then be a fixed operator: FP64 or FP32
                          cycles alike.  0 (default): flexible GMRES, right
                          preconditioning, true-residual stop                 */
+  int32_t inner_adapt; /* mixed precision: 1 (default) = from the second
+                         refinement step on, run only as many of the
+                         inner_cycles FP32 cycles as the previous step's
+                         contraction per cycle says are needed to reach rtol
+                         (at least 1); the stop test is unchanged.  0 = always
+                         inner_cycles                                          */
 } stmg_options;
 
 typedef struct {

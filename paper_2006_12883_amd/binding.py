@@ -46,7 +46,7 @@ class Options(ctypes.Structure):
                 ("max_newton", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("sdc", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("inner_cycles", ctypes.c_int32),
                 ("fft_coarse", ctypes.c_int32), ("krylov", ctypes.c_int32),
-                ("krylov_left", ctypes.c_int32)]
+                ("krylov_left", ctypes.c_int32), ("inner_adapt", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -54,10 +54,11 @@ void stmg_default_options(stmg_options* o) {
   o->mem_budget = 0;
   o->sdc = 0;
   o->autotune = 0;
-  o->inner_cycles = 4;
+  o->inner_cycles = 5;
   o->fft_coarse = 1 << 22;
   o->krylov = 0;
   o->krylov_left = 0;
+  o->inner_adapt = 1;
 }
 
 size_t stmg_workspace_bytes(const stmg_problem* prob, const stmg_options* opt) {

@@ -82,7 +82,7 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   if (o->chunk < 1 || o->chunk_coarse < 1 || o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1 ||
       o->max_levels < 1 || o->max_cycles < 1 || !(o->rtol > 0.0) || !(o->omega > 0.0) ||
       o->inner_cycles < 1 || o->fft_coarse < 0 || o->krylov < 0 || o->krylov > kKrylovMax ||
-      o->krylov_left < 0 || o->krylov_left > 1) {
+      o->krylov_left < 0 || o->krylov_left > 1 || o->inner_adapt < 0 || o->inner_adapt > 1) {
     set_error("invalid options");
     return STMG_EINVAL;
   }
@@ -842,6 +842,8 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
     return hipEventRecord(hnorm.ev, stream);
   };
   double rel = 0.0, rel0 = 0.0, prev = 0.0;
+  double step_rel = 0.0;  // mixed: residual at the start of the previous step
+  int step_k = 0;         // and its FP32 cycles
   bool first = true;
   int incr = 0;
   int c = 0;   // outer steps (V-cycles in FP64, refinement steps in mixed precision)
@@ -916,10 +918,22 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
       else HIP_CHECK(vcycle<float>(0, adj, react, L0.A32, L0.B32, L0.f32, nullptr, true, &res, 0));
       if (!res) break;
       ++vc;
-      for (int k = 1; k < inner; ++k) {
+      // Cycles of this step: inner_cycles, or with inner_adapt (from the
+      // second step on) the count that the previous step's contraction per
+      // cycle says takes the current residual (known here: the stop test ran
+      // inside the first cycle) down to rtol.
+      int inner_now = inner;
+      if (opt.inner_adapt && step_k > 0 && rel > 0.0 && rel < step_rel) {
+        const double rho = std::pow(rel / step_rel, 1.0 / step_k);
+        const double need = std::log(rtol / rel) / std::log(rho);
+        if (need < inner) inner_now = std::max(1, static_cast<int>(std::ceil(need)));
+      }
+      step_rel = rel;
+      step_k = inner_now;
+      for (int k = 1; k < inner_now; ++k) {
         float* other = (res == L0.A32) ? L0.B32 : L0.A32;
         float* r2 = nullptr;
-        if (refine && k == inner - 1) { up_in = Ucur; up_out = Unext; }
+        if (refine && k == inner_now - 1) { up_in = Ucur; up_out = Unext; }
         const auto g = std::move(gate0);
         gate0 = nullptr;
         const hipError_t e = vcycle<float>(0, adj, react, res, other, L0.f32, nullptr, false, &r2, 0);

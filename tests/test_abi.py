@@ -51,4 +51,4 @@ def test_options_defaults():
     assert o.omega == 0.8 and o.chunk == 16 and o.chunk_coarse == 4 and o.nu_pre == 1 and o.nu_post == 1
     assert o.mu_crit == 0.5
     assert o.rtol == 1e-12 and o.coarsen == 0 and o.precision == 0
-    assert o.krylov == 0 and o.inner_cycles == 4
+    assert o.krylov == 0 and o.inner_cycles == 5 and o.inner_adapt == 1

@@ -21,10 +21,16 @@ def test_mixed_heat1d():
     prob = si.config("heat1d")
     u0 = si.initial("heat1d", prob)
     ref = stepper.solve_linear(prob, u0)
-    U, st = H(prob, precision="mixed", rtol=1e-10).solve(T(u0))
-    # four FP32 V-cycles per FP64 refinement step by default
-    assert st["status"] == 0 and st["rel_res"] <= 1e-10 and st["cycles"] == 4 * st["refinements"]
+    U, st = H(prob, precision="mixed", rtol=1e-10, inner_adapt=0).solve(T(u0))
+    # five FP32 V-cycles per FP64 refinement step
+    assert st["status"] == 0 and st["rel_res"] <= 1e-10 and st["cycles"] == 5 * st["refinements"]
     e, eT = _errs(U.cpu().numpy(), ref)
+    assert e <= 1e-9 and eT <= 1e-9, (e, eT)
+    # by default (inner_adapt) a step from the second on may stop short of five
+    Ua, sa = H(prob, precision="mixed", rtol=1e-10).solve(T(u0))
+    assert sa["status"] == 0 and sa["rel_res"] <= 1e-10
+    assert sa["refinements"] <= sa["cycles"] <= 5 * sa["refinements"] and sa["cycles"] <= st["cycles"]
+    e, eT = _errs(Ua.cpu().numpy(), ref)
     assert e <= 1e-9 and eT <= 1e-9, (e, eT)
 
 
@@ -41,15 +47,20 @@ def test_mixed_rd2d_small(M):
 
 
 @pytest.mark.parametrize("inner", [1, 2, 3, 6])
-def test_mixed_inner_cycles(inner):
-    """Any number of FP32 cycles per refinement step reaches the FP64 tolerance."""
-    print("case mixed inner cycles", inner, flush=True)
+@pytest.mark.parametrize("adapt", [0, 1])
+def test_mixed_inner_cycles(inner, adapt):
+    """Any number of FP32 cycles per refinement step reaches the FP64
+    tolerance; with inner_adapt the steps after the first may be shorter."""
+    print("case mixed inner cycles", inner, adapt, flush=True)
     prob = si.problem(2, 64, 3, 32, 0.5, nu=1e-2, lam=1.0)
     u0 = si.u0_rd2d(prob, 5)
     ref = stepper.solve_linear(prob, u0)
-    U, st = H(prob, precision="mixed", rtol=1e-10, inner_cycles=inner).solve(T(u0))
+    U, st = H(prob, precision="mixed", rtol=1e-10, inner_cycles=inner, inner_adapt=adapt).solve(T(u0))
     assert st["status"] == 0 and st["rel_res"] <= 1e-10
-    assert st["cycles"] == inner * st["refinements"]
+    if adapt:
+        assert inner + st["refinements"] - 1 <= st["cycles"] <= inner * st["refinements"]
+    else:
+        assert st["cycles"] == inner * st["refinements"]
     e, eT = _errs(U.cpu().numpy(), ref)
     assert e <= 1e-9 and eT <= 1e-9, (e, eT)
 
