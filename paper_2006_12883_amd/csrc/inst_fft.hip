@@ -714,7 +714,8 @@ __global__ __launch_bounds__(kRegBlock) void k_fft_inv_reg(int nx, int ny, int l
 
 // Per-mode slab recurrence for long time axes (the workgroup's modes do not
 // fit in LDS for all slabs): kChunkQ modes x kChunkC runs of consecutive
-// slabs per workgroup.  With c = cout^T S_q, beta = c . cin, d = S_q cin:
+// slabs per workgroup; a run of at most ChunkG<M>::G slabs is read once.
+// With c = cout^T S_q, beta = c . cin, d = S_q cin:
 //   (1) each run folds a_n = c . F_n into s = a_n + beta s from s = 0 and
 //       records s and beta^len;
 //   (2) one thread per mode chains the runs: p entering run r+1 is
@@ -725,7 +726,12 @@ __global__ __launch_bounds__(kRegBlock) void k_fft_inv_reg(int nx, int ny, int l
 // The same recurrence as k_fft_modes_lds, with the chain regrouped by runs.
 constexpr int kChunkQ = 16;
 constexpr int kChunkC = kFftBlock / kChunkQ;
-constexpr int kChunkG = 4;  // slabs whose loads are issued together
+// slabs whose loads are issued together (a run of at most this many slabs
+// keeps its values in registers from step (1) to step (3))
+template <int M>
+struct ChunkG {
+  static constexpr int G = M <= 3 ? 16 : 48 / M;
+};
 template <int M>
 __global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, double* __restrict__ F,
                                                                const double* __restrict__ u0F,
@@ -758,18 +764,20 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, dou
     dv[k] = dk;
   }
   double2* Fc = reinterpret_cast<double2*>(F);
+  constexpr int G = ChunkG<M>::G;
+  const bool cached = n1 - n0 <= G;
+  double2 v[G][M];
   // (1)
   double sr = 0.0, si = 0.0, bp = 1.0;
   if (act) {
-    for (int g0 = n0; g0 < n1; g0 += kChunkG) {
-      double2 v[kChunkG][M];
+    for (int g0 = n0; g0 < n1; g0 += G) {
 #pragma unroll
-      for (int g = 0; g < kChunkG; ++g)
+      for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int m = 0; m < M; ++m)
           v[g][m] = g0 + g < n1 ? Fc[((size_t)(g0 + g) * M + m) * P + q] : make_double2(0.0, 0.0);
 #pragma unroll
-      for (int g = 0; g < kChunkG; ++g) {
+      for (int g = 0; g < G; ++g) {
         if (g0 + g < n1) {
           double ar = 0.0, ai = 0.0;
 #pragma unroll
@@ -807,15 +815,16 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, dou
   // (3)
   if (act) {
     double pr = Sr[ch][qq], pi = Si[ch][qq];
-    for (int g0 = n0; g0 < n1; g0 += kChunkG) {
-      double2 v[kChunkG][M];
+    for (int g0 = n0; g0 < n1; g0 += G) {
+      if (!cached) {
 #pragma unroll
-      for (int g = 0; g < kChunkG; ++g)
+        for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-          v[g][m] = g0 + g < n1 ? Fc[((size_t)(g0 + g) * M + m) * P + q] : make_double2(0.0, 0.0);
+          for (int m = 0; m < M; ++m)
+            v[g][m] = g0 + g < n1 ? Fc[((size_t)(g0 + g) * M + m) * P + q] : make_double2(0.0, 0.0);
+      }
 #pragma unroll
-      for (int g = 0; g < kChunkG; ++g) {
+      for (int g = 0; g < G; ++g) {
         if (g0 + g < n1) {
           double ar = 0.0, ai = 0.0;
 #pragma unroll
