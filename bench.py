@@ -357,7 +357,7 @@ def paper_examples(dev):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU only; this build has no multi-GPU path (--gpus %d)" % a.gpus,
+        print("bench.py measures one GPU only: the solver has no multi-GPU path (--gpus %d)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
