@@ -117,7 +117,7 @@ typedef struct {
                          0 (default): fixed shapes                            */
   int32_t inner_cycles; /* mixed precision: FP32 V-cycles on each correction
                          equation per FP64 refinement step (at most, with
-                         inner_adapt), 5                                       */
+                         inner_adapt; exactly, in batches), 1..64, 5          */
   int32_t fft_coarse; /* periodic grids with a linear reaction: coarsening
                          also stops at the first level below the finest whose
                          planes hold <= 1024 points (2D: or have power-of-two
@@ -149,7 +149,7 @@ typedef struct {
                          inner_cycles FP32 cycles as the previous step's
                          contraction per cycle says are needed to reach rtol
                          (at least 1); the stop test is unchanged.  0 = always
-                         inner_cycles                                          */
+                         inner_cycles.  Ignored by batches.                    */
 } stmg_options;
 
 typedef struct {
@@ -273,9 +273,10 @@ int stmg_coarse_solve(stmg_handle* h, const double* d_f, double* d_U);
 void stmg_destroy(stmg_handle* h);
 
 /* Batched independent linear problems (mixed precision to rtol): one
- * phase-kernel launch per multigrid phase for all problems at once, the
- * V-cycle captured in a HIP graph.  d_u0[p], d_U[p] are the per-problem
- * device arrays.  Synchronizes in solve. */
+ * phase-kernel launch per multigrid phase for all problems at once, one
+ * refinement step (FP64 residual, inner_cycles FP32 V-cycles, FP64 update)
+ * captured in a HIP graph; stats report cycles = refinements x inner_cycles.
+ * d_u0[p], d_U[p] are the per-problem device arrays.  Synchronizes in solve. */
 size_t stmg_batch_workspace_bytes(int32_t n, const stmg_problem* probs,
                                   const stmg_options* opt);
 int stmg_batch_setup(int32_t n, const stmg_problem* probs, const stmg_options* opt,

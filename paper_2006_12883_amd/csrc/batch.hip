@@ -11,6 +11,8 @@
 //   D_l restriction level l -> l+1, fused with the coarse level's first sweep
 //   C   coarsest solves (one workgroup per problem)
 //   U_l prolongation fused with the first post-smoothing sweep, l -> ... -> 0
+//   (S, D_l, C, U_l again for each further FP32 cycle of the step, the level-0
+//   sweep starting from the last cycle's e; inner_cycles cycles per step)
 //   X   U += e (FP64)
 //
 // A workgroup finds its (problem, level) work item by binary search over the
@@ -112,7 +114,8 @@ __global__ __launch_bounds__(kBlock) void k_b_smooth0(const BItem* __restrict__ 
   const BItem& it = items[find_item(items, nitems, blockIdx.x)];
   if (done[it.prob]) return;
   const int lb = blockIdx.x - it.blk0;
-  SweepPtrs<float> a{nullptr, static_cast<const float*>(it.f), nullptr, nullptr, it.out, nullptr};
+  SweepPtrs<float> a{static_cast<const float*>(it.U), static_cast<const float*>(it.f), nullptr, nullptr, it.out,
+                     nullptr};
 #define C_(MM) \
   smooth_blk_body<MM, float, REACT_CONST, 2, true>(*it.op, a, it.S, lb % it.tiles, (lb / it.tiles) * it.S, 0)
   BDISPATCH(C_)
@@ -222,6 +225,7 @@ struct stmg_batch {
   // device tables (inside the workspace)
   stmg::OpParams* d_ops = nullptr;
   stmg::BItem* d_items = nullptr;
+  size_t items_cap = 0;  // entries of d_items
   double* d_part = nullptr;
   double* d_norm2 = nullptr;
   double* d_thr = nullptr;
@@ -280,10 +284,12 @@ int batch_build(stmg_batch* b, int32_t n, const stmg_problem* probs, const stmg_
   size_t nops = 0;
   for (auto& s : b->S) nops += s->lv.size();
   b->d_ops = pl.take<OpParams>(nops);
-  // work items: an upper bound (per problem: R, NRM, S0, X, C and 2 per level)
+  // work items: an upper bound (per problem: R, NRM, S0, X, C, 2 per level,
+  // and one level-0 sweep for each further FP32 cycle of a step)
   size_t nit = 0;
-  for (auto& s : b->S) nit += 6 + 2 * s->lv.size();
+  for (auto& s : b->S) nit += 6 + 2 * s->lv.size() + static_cast<size_t>(b->opt.inner_cycles - 1);
   b->d_items = pl.take<BItem>(nit);
+  b->items_cap = nit;
   // partials of phase R
   size_t nparts = 0;
   for (auto& s : b->S) {
@@ -374,6 +380,7 @@ int batch_items(stmg_batch* b) {
   }
   end();
   // D_l: restrictions; on level l >= 1 the iterate is A32 (from the fused sweep)
+  const size_t cyc0 = b->phases.size();  // first phase of the cycle below S0
   for (int l = 0; l + 1 < maxL; ++l) {
     for (int kind : {PH_DS, PH_DT}) {
       begin(kind);
@@ -452,6 +459,30 @@ int batch_items(stmg_batch* b) {
       end();
     }
   }
+  // further FP32 cycles of the step on the same correction equation: a
+  // level-0 sweep from the last cycle's e (B32) into A32, then the same
+  // restriction, coarsest and prolongation phases again
+  const size_t ncycle = b->phases.size() - cyc0;
+  for (int k = 1; k < b->opt.inner_cycles; ++k) {
+    begin(PH_S0);
+    for (int p = 0; p < b->n; ++p) {
+      Solver& s = *b->S[p];
+      if (s.lv.size() == 1) continue;  // the exact solve does not use the iterate
+      Level& L = s.lv[0];
+      BItem x = blank(p, 0);
+      x.U = L.B32;
+      x.f = L.f32;
+      x.out = L.A32;
+      x.S = s.chunk_of(0);
+      x.tiles = (plane_threads(L.op) + kBlock - 1) / kBlock;
+      add(x, smooth_blocks(L.op, x.S));
+    }
+    end();
+    for (size_t q = 0; q < ncycle; ++q) {
+      const auto ph = b->phases[cyc0 + q];
+      b->phases.push_back(ph);
+    }
+  }
   // X: U += e (level-0 result in B32)
   begin(PH_X);
   for (int p = 0; p < b->n; ++p) {
@@ -464,6 +495,10 @@ int batch_items(stmg_batch* b) {
   }
   end();
   b->nparts = static_cast<int>(poff);
+  if (it.size() > b->items_cap) {
+    set_error("batch: work item table overflow");
+    return STMG_EINVAL;
+  }
   HIP_CHECK_B(hipMemcpyAsync(b->d_items, it.data(), it.size() * sizeof(BItem), hipMemcpyHostToDevice, b->own));
   std::vector<long long> npts(b->n);
   for (int p = 0; p < b->n; ++p) npts[p] = static_cast<long long>(b->S[p]->lv[0].nx) * b->S[p]->lv[0].ny;
@@ -632,13 +667,16 @@ int stmg_batch_solve(stmg_batch* b, const double* const* d_u0, double* const* d_
       if (!done[p]) { ++cycles[p]; all = 0; }
     }
     if (all) break;
-    if (steps > b->opt.max_cycles) { status = STMG_ENOTCONV; break; }
+    if (static_cast<long long>(steps) * b->opt.inner_cycles > b->opt.max_cycles) {
+      status = STMG_ENOTCONV;
+      break;
+    }
   }
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) {
     for (int p = 0; p < n; ++p) {
       stmg_stats st{};
-      st.cycles = cycles[p];
+      st.cycles = cycles[p] * b->opt.inner_cycles;
       st.refinements = cycles[p];
       st.rel_res = nb[p] > 0 ? std::sqrt(norm2[p]) / nb[p] : std::sqrt(norm2[p]);
       st.status = !std::isfinite(st.rel_res) ? STMG_ENAN : (done[p] ? STMG_OK : STMG_ENOTCONV);

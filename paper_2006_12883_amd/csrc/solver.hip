@@ -20,6 +20,7 @@ constexpr int kResidSlabs = 8;   // slabs per thread in residual sweeps
 constexpr size_t kCoarseInvMaxBytes = size_t(1) << 30;  // Newton coarsest inverses
 constexpr int kScanMinSlabs = 32;  // shorter coarsest levels keep the one-kernel recurrence
 constexpr int kTransferSlabs = 4;
+constexpr int kInnerMax = 64;  // inner_cycles bound
 
 // Elements -> points per dimension.
 int points(int e, int bc) { return bc == STMG_BC_PERIODIC ? e : e + 1; }
@@ -81,7 +82,7 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   }
   if (o->chunk < 1 || o->chunk_coarse < 1 || o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1 ||
       o->max_levels < 1 || o->max_cycles < 1 || !(o->rtol > 0.0) || !(o->omega > 0.0) ||
-      o->inner_cycles < 1 || o->fft_coarse < 0 || o->krylov < 0 || o->krylov > kKrylovMax ||
+      o->inner_cycles < 1 || o->inner_cycles > kInnerMax || o->fft_coarse < 0 || o->krylov < 0 || o->krylov > kKrylovMax ||
       o->krylov_left < 0 || o->krylov_left > 1 || o->inner_adapt < 0 || o->inner_adapt > 1) {
     set_error("invalid options");
     return STMG_EINVAL;

@@ -37,6 +37,9 @@ def test_workspace_and_validation():
         assert B.lib().stmg_workspace_bytes(ctypes.byref(B.make_problem(bad)),
                                             ctypes.byref(B.make_options())) == 0
     assert B.lib().stmg_setup(None, None, None, 0, None, None) == B.STMG_EINVAL
+    for bad in (0, 65):
+        assert B.lib().stmg_workspace_bytes(ctypes.byref(B.make_problem(prob)),
+                                            ctypes.byref(B.make_options(inner_cycles=bad))) == 0
     for bad in (-1, 33):
         assert B.lib().stmg_workspace_bytes(ctypes.byref(B.make_problem(prob)),
                                             ctypes.byref(B.make_options(krylov=bad))) == 0
@@ -52,3 +55,15 @@ def test_options_defaults():
     assert o.mu_crit == 0.5
     assert o.rtol == 1e-12 and o.coarsen == 0 and o.precision == 0
     assert o.krylov == 0 and o.inner_cycles == 5 and o.inner_adapt == 1
+
+
+def test_batch_workspace_counts_inner_cycles():
+    """The batch work-item table grows with the FP32 cycles per refinement
+    step (one level-0 sweep item per further cycle and problem)."""
+    import stmg_inputs as si
+    probs = [si.problem(2, 32, 2, 16, 1.0, nu=1e-2, lam=0.5), si.problem(2, 48, 3, 8, 1.0, nu=1e-1, lam=1.0)]
+    arr = (B.Problem * len(probs))(*[B.make_problem(p) for p in probs])
+    sizes = [B.lib().stmg_batch_workspace_bytes(len(probs), arr, ctypes.byref(B.make_options(inner_cycles=k)))
+             for k in (1, 5, 64)]
+    assert all(x > 0 for x in sizes)
+    assert sizes[0] < sizes[1] < sizes[2]

@@ -66,3 +66,20 @@ def test_batch64_full():
         assert st["status"] == 0 and st["rel_res"] <= 1e-10, (i, st)
         ref = fourier.end_value_periodic(p, u0)
         assert rel_err(U[-1, -1].cpu().numpy(), ref) <= 1e-9, i
+
+
+@pytest.mark.parametrize("inner", [1, 3])
+def test_batch_inner_cycles(inner):
+    """One or several FP32 cycles per refinement step of the batch: every
+    problem still reaches 1e-10 and the closed form, cycles = steps x inner."""
+    from paper_2006_12883_amd import stmg
+    print("case batch inner", inner, flush=True)
+    probs = _small_batch()
+    u0s = [si.batch_u0(p, i) for i, p in enumerate(probs)]
+    b = stmg.Batch(probs, device="cuda:0", rtol=1e-10, inner_cycles=inner)
+    Us, stats = b.solve([T(u) for u in u0s])
+    for i, (p, u0, U, st) in enumerate(zip(probs, u0s, Us, stats)):
+        assert st["status"] == 0 and st["rel_res"] <= 1e-10, (i, st)
+        assert st["cycles"] == inner * st["refinements"]
+        ref = fourier.solve_linear_periodic(p, u0)
+        assert rel_err(U.cpu().numpy(), ref) <= 1e-9, i
