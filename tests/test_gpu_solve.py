@@ -142,3 +142,19 @@ def test_degenerate_shapes(name, prob, opts):
     assert st["status"] == 0
     tol = 1e-9 if opts.get("precision") == "mixed" else 1e-10
     _check(U.cpu().numpy(), ref, tol)
+
+
+@pytest.mark.parametrize("nx,M,N", [(16, 2, 5), (64, 3, 40), (8, 1, 300), (4, 4, 3)])
+def test_single_level_fourier_solve(nx, M, N):
+    """One level: the exact Fourier solve takes u0 through its own transform
+    (the extra plane of the forward transform and the entering coupling of
+    the mode recurrence); one cycle is the exact solution."""
+    print("case single-level fourier", nx, M, N, flush=True)
+    prob = si.problem(2, nx, M, N, 0.5, nu=2e-2, lam=0.4)
+    u0 = si.u0_rd2d(prob, 13)
+    ref = stepper.solve_linear(prob, u0)
+    h = H(prob, max_levels=1)
+    assert len(h.levels()) == 1
+    U, st = h.solve(T(u0))
+    assert st["status"] == 0 and st["cycles"] <= 1, st
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-12
