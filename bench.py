@@ -237,7 +237,7 @@ def _extra_hierarchies(dev):
     import stmg_inputs as si
     from paper_2006_12883_amd import stmg
     out = {}
-    # the paper's three hierarchies (Sec. 4.2) on the 256^2 workload, FP64 to
+    # the paper's three hierarchies (Sec. 5.2) on the 256^2 workload, FP64 to
     # 1e-10: SMG (space only), STMG (space and time at once), SMMG (space and
     # nodes); AUTO semi-coarsening is the headline solve
     prob = si.config("rd2d")

@@ -88,7 +88,7 @@ typedef struct {
   int32_t precision;  /* STMG_PREC_FP64 (default) or STMG_PREC_MIXED: FP32
                          smoother and transfers inside FP64 refinement        */
   int32_t coarsen;    /* AUTO (default): space if mu_l = nu dt_l / h_l^2 >=
-                         mu_crit, else time (Sec. 3.2); SPACE = SMG;
+                         mu_crit, else time (Sec. 4.2); SPACE = SMG;
                          SPACETIME = STMG (both at once); SMMG = space
                          coarsening with M lowered by one per level until
                          M = 1 (Lagrange node transfer, R = P^T; linear
@@ -195,10 +195,12 @@ int stmg_level_nodes(const stmg_handle* h, int level);
 int stmg_residual(stmg_handle* h, const double* d_u0, const double* d_U,
                   double* d_r, double* h_norm);
 
-/* One V-cycle (Sec. 3.2) on A U = b, updating d_U in place.  h_rel (may be
+/* One V-cycle (Sec. 4.2) on A U = b, updating d_U in place.  h_rel (may be
  * NULL) receives ||b - A U|| / ||b|| after the cycle and synchronizes.
  * On an Allen-Cahn handle the cycle acts on the Jacobian at the last Newton
- * linearization point, with b the last Newton right-hand side. */
+ * linearization point, with b the last Newton right-hand side; before the
+ * first stmg_solve on the handle there is none and the call returns
+ * STMG_EINVAL. */
 int stmg_vcycle(stmg_handle* h, const double* d_u0, double* d_U, double* h_rel);
 
 /* Solves the all-at-once system from the initial guess in d_U (zero is the
@@ -206,7 +208,7 @@ int stmg_vcycle(stmg_handle* h, const double* d_u0, double* d_U, double* h_rel);
  * refinement when precision = MIXED) until rel_res <= rtol, or with
  * options.krylov = m > 0 restarted flexible GMRES(m) preconditioned by one
  * V-cycle per step (the preconditioned Krylov iteration of Sec. 5.2), wrapped
- * in Newton for Allen-Cahn (Sec. 3.2).  d_U receives the solution (the last
+ * in Newton for Allen-Cahn (Sec. 4.2).  d_U receives the solution (the last
  * iterate on ENOTCONV/EDIVERGED/ENAN).  stats may be NULL.  Synchronizes. */
 int stmg_solve(stmg_handle* h, const double* d_u0, double* d_U, stmg_stats* stats);
 
@@ -227,7 +229,8 @@ int stmg_tuned_shape(const stmg_handle* h, int level);
  * handle split the N slabs into windows of W = 2^k slabs, W the largest with
  * six window vectors within the budget.  stmg_solve then solves window after
  * window (exact: the system is block lower-triangular); stmg_vcycle,
- * stmg_residual and the stmg_level_* calls return EUNSUPPORTED.  Host only. */
+ * stmg_residual, stmg_coarse_solve and the stmg_level_* calls return
+ * EUNSUPPORTED.  Host only. */
 int stmg_num_windows(const stmg_handle* h);
 
 /* Gradients of L = || U_{N,M} - u_tgt ||^2 (linear problems, periodic grids).  d_U is the
@@ -257,10 +260,10 @@ int stmg_sdc_sweep(stmg_handle* h, const double* d_u0, double* d_U,
 
 /* Component entry points on level `level` of the hierarchy (FP64):
  *   smooth : U_out = U_in + omega D^{-1} (f - A_l U_in); the block-Jacobi
- *            sweep over chunks of slabs (Sec. 3.2); U_in may be NULL (zero)
+ *            sweep over chunks of slabs (Sec. 4.2); U_in may be NULL (zero)
  *   restrict_residual : f_coarse = R (f - A_l U)  (Eq. space_time_tran)
  *   prolong : U_out = U_in + P e_coarse            (transpose structure)
- *   coarse_solve : U = A_L^{-1} f on the coarsest level (exact, Sec. 3.2)
+ *   coarse_solve : U = A_L^{-1} f on the coarsest level (exact, Sec. 4.2)
  * On level 0, f may be NULL, meaning the right-hand side built from d_u0. */
 int stmg_level_smooth(stmg_handle* h, int level, const double* d_f,
                       const double* d_u0, const double* d_Uin, double* d_Uout);

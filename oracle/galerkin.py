@@ -1,6 +1,6 @@
 """Assembled multigrid: the oracle's transfers as sparse matrices and
 Galerkin coarse operators A_{l+1} = R_l A_l P_l, for comparing the
-rediscretized coarse levels with the paper's Galerkin ones (Sec. 3.2).
+rediscretized coarse levels with the paper's Galerkin ones (Sec. 4.2).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper smooths every level with a few iterations of GMRES preconditioned
-by an incomplete LU factorisation with no fill (Sec. 3.2, "ILU(0)-PGMRES").
+by an incomplete LU factorisation with no fill (Sec. 4.2, "ILU(0)-PGMRES").
 Here:
 
 * ilu0: the factorisation restricted to the sparsity pattern of A, rows in

@@ -4,8 +4,8 @@ This is the oracle for the pieces of the V-cycle (one smoothing sweep, one
 restriction, one prolongation, one coarsest solve, one V-cycle), used to
 check the GPU kernels element by element.  The paper fixes the system
 (Eq. st_system), the transfer structure I = T (x) M (x) S (Eq.
-space_time_tran) with bisection stencils [1 2 1]/4 (Sec. 4.2, SMG and STMG
-items), a block-Jacobi smoother over time slabs (Sec. 3.2), an exact
+space_time_tran) with bisection stencils [1 2 1]/4 (Sec. 5.2, SMG and STMG
+items), a block-Jacobi smoother over time slabs (Sec. 4.2), an exact
 coarsest solve and Newton around the linear solver.  What it leaves open
 is read as follows (each reading is listed with its reason in the design
 notes):
@@ -29,11 +29,11 @@ notes):
   scaled so that rediscretized coarse operators match R A P), T_0 carries a
   zero correction, the node index is left alone (M_l^{l+1} = I);
 * semi-coarsening: at each level coarsen in space if
-  mu = nu dt / h^2 >= mu_crit, else in time (Sec. 3.2: mu << 1 -> time,
+  mu = nu dt / h^2 >= mu_crit, else in time (Sec. 4.2: mu << 1 -> time,
   mu >> 1 -> space), falling back to the other direction when one is not
   possible, until the level holds at most `min_coarse` unknowns.  The paper
   gives no threshold; mu_crit = 0.5 by default.
-* node coarsening (SMMG, Sec. 4.2): each level coarsens in space (as SMG) and
+* node coarsening (SMMG, Sec. 5.2): each level coarsens in space (as SMG) and
   lowers M by one until M = 1.  The paper calls the node transfer M_l^{l+1} a linear
   interpolation; we read it as Lagrange interpolation from the coarse Radau
   nodes to the fine ones, P[i, k] = l_k^coarse(c_i^fine) (exact for the coarse

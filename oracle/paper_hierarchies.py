@@ -10,7 +10,7 @@ so the problem is the periodic analogue of the paper's Neumann example
 (Sec. 5.3): N_x = 1024 points on [0, 1), u0 = cos 2 pi x + 2 cos 6 pi x +
 3 cos 8 pi x, nu = 1, T = 1, M = 1..5 with N_t from the paper's tables;
 SMG^7 (space coarsening, 7 levels), STMG^5 (space and time, 5 levels), SMMG^7
-(space and nodes, 7 levels) as in Sec. 4.2; each smoothing step is either one
+(space and nodes, 7 levels) as in Sec. 5.2; each smoothing step is either one
 block-Jacobi sweep (chunk 16 / 4, omega 0.8) or three ILU(0)-GMRES iterations
 (oracle.ilu), one step before and one after the coarse correction; coarse
 levels rediscretized (ours) or Galerkin products R A P (the paper's, assembled

@@ -1,4 +1,4 @@
-"""SDC sweeps on the collocation form (Sec. 2.1 and Sec. 3.1), plain NumPy.
+"""SDC sweeps on the collocation form (Sec. 2.1 and Sec. 4.1), plain NumPy.
 
 One sweep is one step of the preconditioned Richardson iteration on the
 collocation problem U_n = 1 (x) u_{n-1} + dt (Q (x) I) F(U_n) of every slab,

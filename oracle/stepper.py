@@ -39,13 +39,18 @@ def solve_linear(prob, u0):
     return U
 
 
-def solve_allen_cahn(prob, u0, tol=1e-14, max_newton=50):
+def solve_allen_cahn(prob, u0, tol=1e-14, max_newton=50, reuse=False, log=None):
     """All stage values for f(u) = nu Delta_h u + gamma (u - u^3).
 
     Each step solves G(U) = U - 1(x)u_{n-1} - dt (Q(x)I) F(U) = 0 by Newton
     with Jacobian I - dt (Q(x)I)(I(x)nu Delta_h + diag(gamma (1 - 3U^2))),
-    starting from 1(x)u_{n-1}.  The Jacobian is refactored at every Newton
-    iteration; stop when max|G| <= tol * max(1, max|U|).
+    starting from 1(x)u_{n-1}; stop when max|G| <= tol * max(1, max|U|).
+    By default the Jacobian is refactored at every Newton iteration.  With
+    reuse=True one factorization is kept across iterations and steps and
+    refactored at the current iterate only when an iteration reduces max|G|
+    by less than a factor 0.3 (a chord iteration): the stop rule, and so the
+    computed solution, are the same; only the work differs.  `log`, if given,
+    is called as log(step, iterations, refactorizations so far).
     """
     M, N, dt = prob["M"], prob["N"], prob["dt"]
     g = prob["gamma"]
@@ -56,20 +61,34 @@ def solve_allen_cahn(prob, u0, tol=1e-14, max_newton=50):
     ID = sp.kron(sp.identity(M), D)
     U = np.zeros((N, M, ny, nx))
     u = np.asarray(u0, dtype=np.float64).reshape(-1)
-    stats = []
+
+    def jacobian(V):
+        return (sp.identity(V.size) - dt * (QI @ (ID + sp.diags(g * (1.0 - 3.0 * V ** 2))))).tocsc()
+
+    lu = None
+    factors = 0
     for n in range(N):
         U0 = np.tile(u, M)
         V = U0.copy()
+        gprev = None
         for it in range(max_newton):
             F = ID @ V + g * (V - V ** 3)
             G = V - U0 - dt * (QI @ F)
-            if np.abs(G).max() <= tol * max(1.0, np.abs(V).max()):
+            gn = np.abs(G).max()
+            if gn <= tol * max(1.0, np.abs(V).max()):
                 break
-            J = sp.identity(V.size) - dt * (QI @ (ID + sp.diags(g * (1.0 - 3.0 * V ** 2))))
-            V = V - spla.spsolve(J.tocsc(), G)
+            if not reuse:
+                V = V - spla.spsolve(jacobian(V), G)
+                continue
+            if lu is None or (gprev is not None and gn > 0.3 * gprev):
+                lu = spla.splu(jacobian(V))
+                factors += 1
+            gprev = gn
+            V = V - lu.solve(G)
         else:
             raise RuntimeError("oracle Newton did not converge at step %d" % n)
-        stats.append(it)
+        if log is not None:
+            log(n, it, factors)
         U[n] = V.reshape(M, ny, nx)
         u = V[(M - 1) * u.size:]
     return U

@@ -8,6 +8,11 @@ dL/du0 and dL/dnu.  With options["mem_budget"] smaller than the trajectory the
 forward pass keeps only window checkpoints (stmg_solve_end) and the backward
 pass recomputes one window at a time.
 
+Each forward keeps its handle (workspace included: about five FP64
+trajectories, or the window buffers) alive until its backward has run or the
+graph is freed.  The backward releases them, so a second backward through the
+same graph (retain_graph=True) raises a RuntimeError.
+
 All numerical work runs in libstmg.so; this module only moves tensors.
 """
 import torch
@@ -38,6 +43,10 @@ class STMGFunction(torch.autograd.Function):
     def backward(ctx, g):
         (u0c,) = ctx.saved_tensors
         h = ctx.handle
+        if h is None:
+            raise RuntimeError(
+                "STMGFunction: backward was already run for this forward; the "
+                "solver handle and trajectory are released after the first backward")
         gT = g.detach().to(torch.float64).contiguous()
         gu0, gnu, _ = h.adjoint(ctx.traj, gT, u0=u0c)
         ctx.handle = None

@@ -243,6 +243,15 @@ struct stmg_batch {
   int nparts = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  stmg_batch() = default;
+  stmg_batch(const stmg_batch&) = delete;
+  stmg_batch& operator=(const stmg_batch&) = delete;
+  // releases what setup created, also when setup stops half-way
+  ~stmg_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (own) (void)hipStreamDestroy(own);
+  }
 };
 
 namespace stmg {
@@ -603,11 +612,11 @@ int stmg_batch_setup(int32_t n, const stmg_problem* probs, const stmg_options* o
   hipError_t e = stmg::batch_step(b.get());
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->own, &g);
+  b->graph = g;
   if (e != hipSuccess || e2 != hipSuccess || !g) {
     stmg::set_error(std::string("batch: graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
     return STMG_EHIP;
   }
-  b->graph = g;
   if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
     stmg::set_error("batch: graph instantiation failed");
     return STMG_EHIP;
@@ -688,12 +697,6 @@ int stmg_batch_solve(stmg_batch* b, const double* const* d_u0, double* const* d_
   return status;
 }
 
-void stmg_batch_destroy(stmg_batch* b) {
-  if (!b) return;
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
-  if (b->own) hipStreamDestroy(b->own);
-  delete b;
-}
+void stmg_batch_destroy(stmg_batch* b) { delete b; }
 
 }  // extern "C"

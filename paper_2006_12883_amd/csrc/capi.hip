@@ -185,6 +185,7 @@ int stmg_level_restrict_residual(stmg_handle* h, int level, const double* d_f,
     stmg::set_error("bad argument");
     return STMG_EINVAL;
   }
+  if (h->s.win) { stmg::set_error("windowed handle"); return STMG_EUNSUPPORTED; }
   hipError_t e = h->s.restrict_residual<double>(level, false, stmg::REACT_CONST, d_U, d_f,
                                                 level == 0 ? d_u0 : nullptr, d_fc, nullptr, nullptr);
   return e == hipSuccess ? STMG_OK : STMG_EHIP;
@@ -196,12 +197,14 @@ int stmg_level_prolong(stmg_handle* h, int level, const double* d_Uin, const dou
     stmg::set_error("bad argument");
     return STMG_EINVAL;
   }
+  if (h->s.win) { stmg::set_error("windowed handle"); return STMG_EUNSUPPORTED; }
   hipError_t e = h->s.prolong<double>(level, d_Uin, d_ec, d_Uout);
   return e == hipSuccess ? STMG_OK : STMG_EHIP;
 }
 
 int stmg_coarse_solve(stmg_handle* h, const double* d_f, double* d_U) {
   if (!h || !d_U) { stmg::set_error("bad argument"); return STMG_EINVAL; }
+  if (h->s.win) { stmg::set_error("windowed handle"); return STMG_EUNSUPPORTED; }
   hipError_t e = h->s.coarse<double>(false, stmg::REACT_CONST, d_f, nullptr, d_U);
   return e == hipSuccess ? STMG_OK : STMG_EHIP;
 }

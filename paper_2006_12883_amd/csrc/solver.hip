@@ -56,8 +56,8 @@ const RadauTables* Solver::tables_for(int m) {
 
 // ---------------------------------------------------------------------------
 // Hierarchy.  Semi-coarsening by the anisotropy ratio mu = nu dt / h^2
-// (Sec. 3.2: coarsen in time when mu << 1 and in space when mu >> 1), with the
-// SMG (space only) and STMG (space and time) variants of Sec. 4.2.
+// (Sec. 4.2: coarsen in time when mu << 1 and in space when mu >> 1), with the
+// SMG (space only) and STMG (space and time) variants of Sec. 5.2.
 int Solver::build(const stmg_problem* p, const stmg_options* o) {
   prob = *p;
   opt = *o;
@@ -1195,6 +1195,7 @@ int Solver::newton_linearize(const double* U) {
     if (!mixed) HIP_CHECK(launch_coarse_invert_coef<double>(C.op, C.coef64, coarse_inv, stream));
     else HIP_CHECK(launch_coarse_invert_coef<float>(C.op, C.coef32, coarse_inv, stream));
   }
+  linearized = true;
   return STMG_OK;
 }
 
@@ -1228,7 +1229,7 @@ int Solver::solve(const double* u0, double* U, stmg_stats* st) {
     rc = solve_linear(false, REACT_CONST, nullptr, u0, U, opt.rtol, nb, &s.cycles, &s.rel_res,
                       &s.refinements);
   } else {
-    // Newton on G(U) = b - A_AC(U) (Sec. 3.2), inexact: each correction solve
+    // Newton on G(U) = b - A_AC(U) (Sec. 4.2), inexact: each correction solve
     // stops at a relative tolerance eta_k (Eisenstat-Walker, choice 2).
     Level& L0 = lv[0];
     double gprev = -1.0, eta = 1e-2;
@@ -1273,6 +1274,10 @@ int Solver::solve(const double* u0, double* U, stmg_stats* st) {
 
 int Solver::vcycle_user(const double* u0, double* U, double* h_rel) {
   if (win) { set_error("stmg_vcycle: not available on a windowed handle"); return STMG_EUNSUPPORTED; }
+  if (allen_cahn && !linearized) {
+    set_error("stmg_vcycle: no linearization point yet (run stmg_solve first)");
+    return STMG_EINVAL;
+  }
   Level& L0 = lv[0];
   const bool lin = !allen_cahn;
   const int react = lin ? REACT_CONST : REACT_COEF;

@@ -98,6 +98,7 @@ struct Solver {
   const RadauTables* tables_for(int m);
   std::vector<Level> lv;
   bool allen_cahn = false;
+  bool linearized = false;  // Allen-Cahn: a Newton step has set the Jacobian coefficients
   bool mixed = false;
   bool fuse = true;  // fused restriction+presmooth / prolongation+postsmooth kernels
   size_t ws_bytes = 0;

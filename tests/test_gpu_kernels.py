@@ -183,7 +183,7 @@ def test_repeatable_bitwise():
     assert all(np.array_equal(outs[0], o) for o in outs[1:])
 
 
-# SMMG: space coarsening with M lowered by one per level (Sec. 4.2)
+# SMMG: space coarsening with M lowered by one per level (Sec. 5.2)
 SMMG = [
     ("smmg-2d-M3", si.problem(2, 32, 3, 6, 0.5, nu=0.05, lam=1.0)),
     ("smmg-2d-M4-tiles", si.problem(2, 48, 4, 5, 0.5, nu=0.02, lam=0.5)),

@@ -73,7 +73,7 @@ def test_spacetime_small_mu_fp64():
 
 
 def test_spacetime_large_mu_reports_divergence():
-    """At mu = 25.6 time coarsening fails (Sec. 3.2); the oracle's V-cycle grows
+    """At mu = 25.6 time coarsening fails (Sec. 4.2); the oracle's V-cycle grows
     the residual too.  The solver must stop with STMG_EDIVERGED, not hang."""
     print("case spacetime large mu", flush=True)
     prob = si.config("heat1d")
@@ -110,7 +110,7 @@ def test_autotuned_shapes_bitwise_identical(prec, tmp_path, monkeypatch):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_smmg_solve_matches_stepper(prec):
-    """SMMG V-cycles (Sec. 4.2) converge to the Radau IIA trajectory."""
+    """SMMG V-cycles (Sec. 5.2) converge to the Radau IIA trajectory."""
     print("case smmg solve", prec, flush=True)
     prob = si.problem(2, 64, 3, 32, 0.5, nu=1e-2, lam=1.0)
     u0 = si.u0_rd2d(prob, 8)

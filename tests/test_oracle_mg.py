@@ -114,7 +114,7 @@ def test_node_transfer_is_galerkin(Mf):
 
 def test_smmg_hierarchy():
     """SMMG lowers M by one per level until M = 1 while coarsening in space
-    (Sec. 4.2: M = max(M - l + 1, 1) on level l), then continues as SMG."""
+    (Sec. 5.2: M = max(M - l + 1, 1) on level l), then continues as SMG."""
     prob = si.problem(2, 32, 3, 4, 0.5, nu=0.05, lam=1.0)
     levels, kinds = mg.hierarchy(prob, coarsen="smmg", fft_coarse=0)
     assert kinds == ["sm", "sm", "s"]

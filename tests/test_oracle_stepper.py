@@ -156,27 +156,30 @@ def _ac_exact(u0, g, t):
     return u0 * np.exp(g * t) / np.sqrt(1 + u0 ** 2 * (np.exp(2 * g * t) - 1))
 
 
+@pytest.mark.parametrize("reuse", [False, True])
 @pytest.mark.parametrize("M", [2, 3])
-def test_allen_cahn_uniform_order(M):
-    """Spatially uniform u0 reduces u_t = nu Lap u + g (u - u^3) to a logistic-type ODE."""
+def test_allen_cahn_uniform_order(M, reuse):
+    """Spatially uniform u0 reduces u_t = nu Lap u + g (u - u^3) to a logistic-type ODE
+    (with and without reuse of the Jacobian's factorization)."""
     errs = []
     Ns = [4, 8, 16]
     for Nt in Ns:
         prob = si.problem(1, 8, M, Nt, 1.0, nu=0.1, gamma=2.0, reaction="allen_cahn")
-        U = stepper.solve_allen_cahn(prob, np.full((1, 8), 0.3))
+        U = stepper.solve_allen_cahn(prob, np.full((1, 8), 0.3), reuse=reuse)
         errs.append(abs(U[-1, -1, 0, 3] - _ac_exact(0.3, 2.0, 1.0)))
         assert np.ptp(U[-1, -1]) < 1e-14
     slopes = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert abs(slopes[-1] - (2 * M - 1)) < 0.3, slopes
 
 
-def test_allen_cahn_fixed_points_and_dense():
+@pytest.mark.parametrize("reuse", [False, True])
+def test_allen_cahn_fixed_points_and_dense(reuse):
     prob = si.problem(2, 4, 2, 3, 0.3, nu=0.05, gamma=3.0, reaction="allen_cahn")
     for c in (0.0, 1.0, -1.0):
-        U = stepper.solve_allen_cahn(prob, np.full((4, 4), c))
+        U = stepper.solve_allen_cahn(prob, np.full((4, 4), c), reuse=reuse)
         assert np.abs(U - c).max() < 1e-15
     u0 = np.random.default_rng(2).uniform(-0.8, 0.8, (4, 4))
-    U = stepper.solve_allen_cahn(prob, u0)
+    U = stepper.solve_allen_cahn(prob, u0, reuse=reuse)
     V = allatonce.dense_solve(prob, u0)
     assert np.abs(U - V).max() < 1e-13
     assert np.abs(allatonce.residual(prob, u0, U)).max() < 1e-13
@@ -187,3 +190,17 @@ def test_fourier_end_value_matches_stepper():
     u0 = si.u0_rd2d(prob, 3)
     U = stepper.solve_linear(prob, u0)
     assert np.abs(fourier.end_value_periodic(prob, u0) - U[-1, -1]).max() <= 1e-13 * np.abs(U).max()
+
+
+def test_allen_cahn_jacobian_reuse_same_solution():
+    """Keeping one factorization across Newton iterations and steps (chord
+    iteration, refactored when the contraction is weaker than 0.3) stops on the
+    same residual test, so the trajectory agrees with full Newton to rounding;
+    here with fewer factorizations than steps."""
+    prob = si.problem(2, 16, 3, 12, 0.6, nu=1e-3, gamma=1.0, reaction="allen_cahn")
+    u0 = np.random.default_rng(7).uniform(-0.1, 0.1, (16, 16))
+    seen = []
+    Ur = stepper.solve_allen_cahn(prob, u0, reuse=True, log=lambda n, it, f: seen.append(f))
+    Uf = stepper.solve_allen_cahn(prob, u0)
+    assert np.abs(Ur - Uf).max() <= 1e-13
+    assert seen[-1] < prob["N"]
