@@ -195,6 +195,24 @@ int stmg_level_nodes(const stmg_handle* h, int level);
 int stmg_residual(stmg_handle* h, const double* d_u0, const double* d_U,
                   double* d_r, double* h_norm);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * residual of stmg_residual without a handle or workspace.  The problem is
+ * described as for stmg_setup (default options); d_u0, d_U, d_r and h_norm
+ * are as in stmg_residual, and the work goes on `stream` (a hipStream_t of
+ * the current device, NULL = null stream).  The per-block partial sums of
+ * ||r||^2 live in a fixed device array of 1 MiB + 256 bytes inside the
+ * library (one per GPU, kept until the process ends); no device or pinned
+ * memory is allocated.  EINVAL when the problem needs more partial sums than
+ * that array holds (ceil(nx ny / 256) * ceil(N / 8) must not exceed 131072,
+ * e.g. 512 x 512 points with N <= 1024 slabs), and the errors of
+ * stmg_setup's problem checks.  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (other host threads, or other streams
+ * before the earlier call's stream has finished) race and must not be
+ * issued.  With h_norm non-NULL the call synchronizes `stream`. */
+int stmg_residual_noalloc(const stmg_problem* prob, const double* d_u0, const double* d_U,
+                          double* d_r, double* h_norm, void* stream);
+
 /* One V-cycle (Sec. 4.2) on A U = b, updating d_U in place.  h_rel (may be
  * NULL) receives ||b - A U|| / ||b|| after the cycle and synchronizes.
  * On an Allen-Cahn handle the cycle acts on the Jacobian at the last Newton

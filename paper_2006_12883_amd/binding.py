@@ -21,7 +21,7 @@ COARSEN = {"auto": 0, "space": 1, "spacetime": 2, "smmg": 3}
 # every symbol the header declares
 EXPORTS = [
     "stmg_default_options", "stmg_workspace_bytes", "stmg_setup", "stmg_num_levels",
-    "stmg_level_shape", "stmg_level_nodes", "stmg_residual", "stmg_vcycle", "stmg_solve", "stmg_solve_end",
+    "stmg_level_shape", "stmg_level_nodes", "stmg_residual", "stmg_residual_noalloc", "stmg_vcycle", "stmg_solve", "stmg_solve_end",
     "stmg_num_windows", "stmg_tuned_shape", "stmg_adjoint",
     "stmg_sdc_sweep", "stmg_level_smooth", "stmg_level_restrict_residual",
     "stmg_level_prolong", "stmg_coarse_solve", "stmg_destroy",
@@ -76,6 +76,7 @@ def lib():
             "stmg_level_shape": (ip, [vp, ip, ctypes.POINTER(ctypes.c_int32), dp]),
             "stmg_level_nodes": (ip, [vp, ip]),
             "stmg_residual": (ip, [vp, vp, vp, vp, dp]),
+            "stmg_residual_noalloc": (ip, [P, vp, vp, vp, dp, vp]),
             "stmg_vcycle": (ip, [vp, vp, vp, dp]),
             "stmg_solve": (ip, [vp, vp, vp, S]),
             "stmg_adjoint": (ip, [vp, vp, vp, vp, vp, dp, S]),

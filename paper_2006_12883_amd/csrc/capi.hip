@@ -1,4 +1,5 @@
 // C ABI of libstmg (declared in include/stmg.h).
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -11,7 +12,40 @@ struct stmg_handle {
 namespace stmg {
 namespace {
 thread_local std::string g_last_error;
+
+// Device scratch of the no-allocation residual (stmg_residual_noalloc): the
+// per-block partial sums of ||r||^2 and, in the last slot, their total.  One
+// copy per GPU, held until the process ends.  Host code never uses the name
+// `scratch` as an address: it takes the device address from
+// hipGetSymbolAddress once per device (noalloc_scratch below).
+constexpr int kNoAllocParts = 131072;  // 1 MiB of partial sums
+static __device__ __align__(256) double scratch[kNoAllocParts + 32];
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, with the device current).
+int noalloc_scratch(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices) {
+    set_error("stmg_residual_noalloc: no usable current device");
+    return STMG_EHIP;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("stmg_residual_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(e));
+      return STMG_EHIP;
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return STMG_OK;
 }
+}  // namespace
 void set_error(const std::string& msg) { g_last_error = msg; }
 }  // namespace stmg
 
@@ -130,6 +164,31 @@ int stmg_residual(stmg_handle* h, const double* d_u0, const double* d_U, double*
                   double* h_norm) {
   if (!h || !d_U) { stmg::set_error("null pointer"); return STMG_EINVAL; }
   return h->s.residual_user(d_u0, d_U, d_r, h_norm);
+}
+
+int stmg_residual_noalloc(const stmg_problem* prob, const double* d_u0, const double* d_U,
+                          double* d_r, double* h_norm, void* stream) {
+  if (!prob || !d_U) { stmg::set_error("null pointer"); return STMG_EINVAL; }
+  stmg_options o;
+  stmg_default_options(&o);
+  // Host-only set-up: the same tables and level-0 operator as stmg_setup builds.
+  Solver s;
+  int rc = s.build(prob, &o);
+  if (rc) return rc;
+  const long long parts = s.residual_parts();
+  if (parts > stmg::kNoAllocParts) {
+    stmg::set_error("stmg_residual_noalloc: problem needs " + std::to_string(parts) +
+                    " partial sums, the fixed scratch holds " + std::to_string(stmg::kNoAllocParts));
+    return STMG_EINVAL;
+  }
+  double* ptr = nullptr;
+  rc = stmg::noalloc_scratch(&ptr);
+  if (rc) return rc;
+  s.stream = static_cast<hipStream_t>(stream);
+  s.part = ptr;
+  s.max_parts = stmg::kNoAllocParts;
+  s.scal = ptr + stmg::kNoAllocParts;
+  return s.residual_user(d_u0, d_U, d_r, h_norm);
 }
 
 int stmg_vcycle(stmg_handle* h, const double* d_u0, double* d_U, double* h_rel) {

@@ -758,8 +758,7 @@ template <typename TO>
 hipError_t Solver::residual64(bool adj, int react, const double* U, const double* f,
                               const double* u0, TO* r, double* d_out) {
   const Level& L = lv[0];
-  const int np = ((L.nx * L.ny + kBlock - 1) / kBlock) * ((L.N + kResidSlabs - 1) / kResidSlabs);
-  if (np > max_parts) {
+  if (residual_parts() > max_parts) {
     set_error("partial buffer too small");
     return hipErrorInvalidValue;
   }
@@ -767,6 +766,12 @@ hipError_t Solver::residual64(bool adj, int react, const double* U, const double
   int launched = 0;
   HIP_TRY((launch_residual<double, TO>(adj ? L.opT : L.op, react, a, kResidSlabs, &launched, stream)));
   return launch_sum_partials(part, launched, d_out, stream);
+}
+
+long long Solver::residual_parts() const {
+  const Level& L = lv[0];
+  return ((static_cast<long long>(L.nx) * L.ny + kBlock - 1) / kBlock) *
+         ((L.N + kResidSlabs - 1) / kResidSlabs);
 }
 
 int Solver::read_scalar(const double* d, double* h) {

@@ -218,6 +218,7 @@ struct Solver {
   template <typename TO>
   hipError_t residual64(bool adj, int react, const double* U, const double* f,
                         const double* u0, TO* r, double* d_out);
+  long long residual_parts() const;  // per-block partial sums residual64 writes
   int read_scalar(const double* d, double* h);
 
   // --- drivers ---

@@ -19,6 +19,18 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def residual_noalloc(prob, u0, U, r=None):
+    """||b - A(U)|| (and r when given) through stmg_residual_noalloc: no
+    handle, no workspace, nothing allocated by the library; the work goes on
+    the current stream of U's device."""
+    n = ctypes.c_double()
+    stream = torch.cuda.current_stream(U.device)
+    B.check(B.lib().stmg_residual_noalloc(ctypes.byref(B.make_problem(prob)), _ptr(u0), _ptr(U), _ptr(r),
+                                          ctypes.byref(n), ctypes.c_void_p(stream.cuda_stream)),
+            "stmg_residual_noalloc")
+    return n.value
+
+
 class Handle:
     def __init__(self, prob, device="cuda", **opts):
         self.prob = dict(prob)
