@@ -5,9 +5,12 @@ lambda = 1, periodic [0,1]^2, 256 x 256 points, M = 3 right Radau nodes,
 N = 256 steps, T = 1 (50,331,648 space-time unknowns), seeded random
 Fourier initial data.  One step = one FP64 solve from a zero initial guess
 to a relative residual of 1e-12.  Also reported: time to a 1e-10 residual
-in FP64 and in mixed precision, the level-0 smoother's achieved HBM
-bandwidth (HIP events on the solver's stream), and the CPU oracle's V-cycle
-rate on the host.
+in FP64 and in mixed precision; the longest kernel of the V-cycle and the
+whole V-cycle against the HBM roofline (HIP events on the solver's stream,
+algorithmic bytes from the level shapes); the other synthetic workloads
+with their errors against the CPU oracle; and the oracle itself (the
+sequential Radau IIA stepper with a sparse direct solve per step) timed on
+the host.
 
 Prints one JSON line.  Only N = 1 GPU is supported.
 """
@@ -24,11 +27,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the level-0 smoothing sweep from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs (scaled by a device copy of known size; see
-# profiles/k_smooth_blk_rd2d_level0.md), valid only for the kernel source it
-# was measured on.
-TRAFFIC = {"kernels_impl_sha256_prefix": "a31422999b0b07ad", "bytes_per_launch": 432.12e6 + 402.65e6}
+# HBM traffic of the dominant kernel (level-0 prolongation + post-smoothing,
+# k_prolong_smooth_blk) from rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled
+# by what the counters read for a device copy of known size (FETCH x 2,
+# WRITE x 1; profiles/k_prolong_smooth_blk_rd2d_level0.md), valid only for
+# the kernel source the counters were taken on.
+TRAFFIC = {"kernels_impl_sha256_prefix": "a31422999b0b07ad", "bytes_per_launch": 526.3e6 + 402.7e6}
 
 
 def measured_traffic():
@@ -53,78 +57,176 @@ def parse():
                     help="only the flexible GMRES lines on the 256^2 workload (used for the Krylov "
                          "kernel trace)")
     ap.add_argument("--kernel-only", action="store_true",
-                    help="only time the level-0 smoothing sweep and a plain device copy of the "
+                    help="only time the level-0 kernels and a plain device copy of the "
                          "same bytes (used for the HBM counter runs)")
+    ap.add_argument("--cycle-only", action="store_true",
+                    help="only time back-to-back V-cycles (used for the kernel traces)")
     return ap.parse_args()
 
 
-def smoother_bytes_per_dof():
-    # level-0 smoothing sweep: read U, write U_out (the right-hand side is
-    # generated from u0 inside the kernel), FP64
-    return 16.0
+def cycle_bytes(levels, word=8):
+    """Algorithmic HBM bytes of one V(1,1) cycle with the fused kernels, from
+    the level shapes (levels[l] = dict(nx, ny, N, M, kind)):
+      level 0: pre-smoothing reads U, writes U' (the right-hand side is
+        generated from u0); the restriction reads U and writes f_c and the
+        coarse level's first sweep U_c; the prolongation + post-smoothing
+        reads U and e_c and writes U';
+      levels 0 < l < coarsest: the restriction reads U and f, writes f_c (and
+        U_c unless the next level is the coarsest); the prolongation +
+        post-smoothing reads U, f, e_c and writes U';
+      coarsest: the exact solve reads f and writes U.
+    Returns (bytes, [bytes per level])."""
+    dof = [lv["nx"] * lv["ny"] * lv["N"] * lv["M"] for lv in levels]
+    L = len(levels) - 1
+    per = []
+    for l in range(L + 1):
+        if l == L:
+            per.append(2 * word * dof[l])
+            break
+        c = dof[l + 1]
+        b = 0
+        if l == 0:
+            b += 2 * word * dof[0]                 # pre-smoothing
+            b += word * dof[0] + 2 * word * c      # restriction + coarse first sweep
+            b += 2 * word * dof[0] + word * c      # prolongation + post-smoothing
+        else:
+            b += 2 * word * dof[l] + word * c * (2 if l + 1 < L else 1)
+            b += 3 * word * dof[l] + word * c
+        per.append(b)
+    return float(sum(per)), [float(x) for x in per]
 
 
-def cpu_baseline(prob, u0, gpu_solutions):
-    """The CPU leg: the oracle's plain NumPy V-cycle on the same workload
-    (1 thread), plus the oracle's closed-form solution of the workload, which
-    gives the error of each GPU result against the FP64 oracle."""
+def host_info():
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "CPU(s)", "Thread(s) per core", "Core(s) per socket", "Socket(s)",
+                             "CPU max MHz"):
+                info[k.strip()] = v.strip()
+    except Exception:
+        pass
+    return info
+
+
+def cpu_baseline(prob, u0, gpu_solutions, gpu_seconds_per_solve):
+    """The CPU leg: the oracle's sequential Radau IIA stepper (collocation
+    form, one sparse LU of the stage matrix I - dt Q (x) L, then one
+    triangular solve pair per step) on one host thread, timed on a bounded
+    sample: the factorization and the first `steps` steps; the full solve
+    time is the factorization plus N times the per-step time.  Secondary: the
+    oracle's NumPy V-cycle rate on the same workload.  The oracle's Fourier
+    closed form of the workload gives the error of each GPU result."""
+    import scipy.sparse.linalg as spla
     from threadpoolctl import threadpool_limits
-    from oracle import fourier, mg
+    from oracle import fourier, mg, radau, space, stepper
+    steps = 8
     with threadpool_limits(limits=1):
+        Q = radau.tables(prob["M"])["Q"]
+        L = space.linear_operator(prob)
+        t0 = time.perf_counter()
+        S = stepper._stage_matrix(Q, L, prob["dt"])
+        lu = spla.splu(S)
+        t_factor = time.perf_counter() - t0
+        u = np.asarray(u0, dtype=np.float64).reshape(-1)
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            Un = lu.solve(np.tile(u, prob["M"]))
+            u = Un[(prob["M"] - 1) * u.size:]
+        t_step = (time.perf_counter() - t1) / steps
+        del lu, S
         levels, kinds = mg.hierarchy(prob)
         f = mg.rhs(levels, u0)
         U = np.zeros(levels[0].shape)
-        ncyc = 3  # about 10 s of CPU work (the first cycle includes the coarsest LU factorization)
-        t0 = time.perf_counter()
+        ncyc = 2
+        t2 = time.perf_counter()
         for _ in range(ncyc):
             U = mg.vcycle(levels, kinds, U, f)
-        t = (time.perf_counter() - t0) / ncyc
+        t_cyc = (time.perf_counter() - t2) / ncyc
         del U, f
-        t1 = time.perf_counter()
+        t3 = time.perf_counter()
         ref = fourier.solve_linear_periodic(prob, u0)
-        tf = time.perf_counter() - t1
+        tf = time.perf_counter() - t3
     dof = float(np.prod(levels[0].shape))
+    t_solve = t_factor + prob["N"] * t_step
     errs = {}
     for k, V in gpu_solutions.items():
         errs[k] = {"rel_err": float(np.linalg.norm(V - ref) / np.linalg.norm(ref)),
                    "rel_err_at_T": float(np.linalg.norm(V[-1, -1] - ref[-1, -1]) / np.linalg.norm(ref[-1, -1]))}
-    return {"value": dof / t, "unit": "DOF*V-cycles/s", "cores": 1, "kind": "oracle",
-            "sample": "%d consecutive V-cycles of the oracle's NumPy multigrid (oracle.mg) on the full "
-                      "256^2 x M=3 x N=256 workload from a zero guess, 1 thread; %.1f s" % (ncyc, ncyc * t),
-            "seconds_per_vcycle": t,
+    return {"value": t_solve, "unit": "s per full solve (time to solution of the 256^2 x 3 x 256 workload)",
+            "cores": 1, "kind": "oracle",
+            "sample": "sequential Radau IIA stepper (scipy splu of the 196,608-unknown stage matrix, then "
+                      "%d of the %d steps), 1 thread; full solve = factorization + %d x per-step time; "
+                      "%.1f s of CPU work" % (steps, prob["N"], prob["N"], t_factor + steps * t_step),
+            "factor_seconds": t_factor, "seconds_per_step": t_step,
+            "gpu_seconds_per_solve_to_1e-12": gpu_seconds_per_solve,
+            "host": host_info(),
+            "mg_vcycle": {"value": dof / t_cyc, "unit": "DOF*V-cycles/s", "seconds_per_vcycle": t_cyc,
+                          "sample": "%d consecutive V-cycles of the oracle's NumPy multigrid (oracle.mg) on "
+                                    "the full workload from a zero guess, 1 thread" % ncyc},
             "fourier_closed_form_seconds": tf,
             "gpu_error_vs_oracle": errs}
 
 
-def time_kernels(h, U, u0, iters):
-    """Level-0 smoothing sweep and a plain copy of the same byte count, each
-    timed with HIP events on the solver's stream."""
+def _events(stream, iters, fn):
+    """Average milliseconds of fn() over iters launches, HIP events on `stream`."""
     import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    e0.record(stream)
+    for _ in range(iters):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / iters
+
+
+def time_kernels(h, U, u0, iters):
+    """The level-0 kernels of the V-cycle through their component entry points
+    (smoothing sweep, residual restriction, fused prolongation + smoothing),
+    back-to-back V-cycles, and a plain copy of the smoother's byte count, each
+    timed with HIP events on the solver's stream."""
+    import ctypes
+    import torch
+    from paper_2006_12883_amd import binding as B
+    lv = h.levels()
+    c = lv[1]
+    shape1 = (c["N"], c["M"], c["ny"], c["nx"])
     Uin = U.clone()
     Uout = torch.empty_like(U)
+    ec = torch.randn(shape1, dtype=torch.float64, device=U.device)
+    fc = torch.empty(shape1, dtype=torch.float64, device=U.device)
     s = h.stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    h.smooth(0, Uin, Uout, u0=u0)
-    e0.record(s)
-    for _ in range(iters):
-        h.smooth(0, Uin, Uout, u0=u0)
-    e1.record(s)
-    e1.synchronize()
-    k_ms = e0.elapsed_time(e1) / iters
+    dof0 = float(U.numel())
+    dof1 = float(ec.numel())
+    k = {}
+    k["k_smooth_blk"] = (_events(s, iters, lambda: h.smooth(0, Uin, Uout, u0=u0)), 16.0 * dof0)
+    k["k_restrict_blk"] = (_events(s, iters, lambda: h.restrict_residual(0, Uin, fc, u0=u0)), 8.0 * dof0 + 8.0 * dof1)
+    k["k_prolong_smooth_blk"] = (_events(s, iters, lambda: h.prolong_smooth(0, ec, Uout, Uin=Uin, u0=u0)),
+                                 16.0 * dof0 + 8.0 * dof1)
+    kernels = {name: {"ms": ms, "bytes": b, "GBs": b / (ms * 1e-3) / 1e9} for name, (ms, b) in k.items()}
+    # whole cycles, no host synchronization in between
+    V = torch.zeros_like(U)
+    L = B.lib()
+    cyc = lambda: B.check(L.stmg_vcycle(h.h, ctypes.c_void_p(u0.data_ptr()), ctypes.c_void_p(V.data_ptr()), None),
+                          "stmg_vcycle")
+    cyc_ms = _events(s, iters, cyc)
     x = torch.ones(U.numel(), dtype=torch.float64, device=U.device)
     y = torch.empty_like(x)
     with torch.cuda.stream(s):
-        y.copy_(x)
-        e0.record(s)
-        for _ in range(iters):
-            y.copy_(x)
-        e1.record(s)
-    e1.synchronize()
-    c_ms = e0.elapsed_time(e1) / iters
-    return k_ms, c_ms, 2.0 * x.numel() * 8
+        c_ms = _events(s, iters, lambda: y.copy_(x))
+    del Uin, Uout, ec, fc, V, x, y
+    return kernels, cyc_ms, lv, c_ms, 2.0 * U.numel() * 8
 
 
-EXTRA_GROUPS = ("allen_cahn", "adjoint", "batch", "hierarchies", "krylov", "paper")
+EXTRA_GROUPS = ("heat1d", "allen_cahn", "adjoint", "batch", "sdc", "hierarchies", "krylov", "paper")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
 def extras(dev, only=None):
@@ -134,12 +236,16 @@ def extras(dev, only=None):
     import stmg_inputs as si
     from paper_2006_12883_amd import stmg
     out = {}
+    if only in (None, "heat1d"):
+        out.update(_extra_heat1d(dev))
     if only in (None, "allen_cahn"):
         out.update(_extra_allen_cahn(dev))
     if only in (None, "adjoint"):
         out.update(_extra_adjoint(dev))
     if only in (None, "batch"):
         out.update(_extra_batch(dev))
+    if only in (None, "sdc"):
+        out.update(_extra_sdc(dev))
     if only in (None, "hierarchies"):
         out.update(_extra_hierarchies(dev))
     if only in (None, "krylov"):
@@ -151,29 +257,77 @@ def extras(dev, only=None):
     return out
 
 
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _extra_heat1d(dev):
+    """The 1D heat workload (64 points, M = 2, N = 16, 2,048 unknowns), FP64 to
+    1e-12: cache-resident and latency-bound, so only its absolute time; the
+    error is against the oracle's stepper."""
+    import torch
+    import stmg_inputs as si
+    from oracle import stepper
+    from paper_2006_12883_amd import stmg
+    prob = si.config("heat1d")
+    u0n = si.initial("heat1d", prob)
+    u0 = torch.as_tensor(u0n).to(dev)
+    h = stmg.Handle(prob, device=dev)
+    U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
+    times = []
+    for _ in range(6):
+        U.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = h.solve(u0, U)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ref = stepper.solve_linear(prob, u0n)
+    V = U.cpu().numpy()
+    print("heat1d done", file=sys.stderr, flush=True)
+    return {"heat1d_64_M2_N16_fp64_to_1e-12": {
+        "ms_median": 1e3 * float(np.median(times[1:])), "vcycles": st["cycles"], "rel_res": st["rel_res"],
+        "levels": len(h.levels()), "rel_err_vs_oracle": _rel(V, ref), "rel_err_at_T": _rel(V[-1, -1], ref[-1, -1])}}
+
+
 def _extra_allen_cahn(dev):
     import torch
     import stmg_inputs as si
     from paper_2006_12883_amd import stmg
     out = {}
-    # 2D Allen-Cahn 512^2 x M=3 x N=512, Newton with FP32 V-cycles inside FP64 refinement
+    # 2D Allen-Cahn 512^2 x M=3 x N=512 by Newton: FP32 V-cycles inside FP64
+    # refinement, and all-FP64 cycles, to the same Newton tolerance; errors
+    # against the stored oracle solution (tests/golden/make_ac2d_golden.py)
     prob = si.config("ac2d")
     u0 = torch.as_tensor(si.initial("ac2d", prob)).to(dev)
-    h = stmg.Handle(prob, device=dev, precision="mixed", newton_rtol=1e-10)
-    U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
-    h.solve(u0, U)
-    U.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, st = h.solve(u0, U)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    dof = float(np.prod(h.shape))
-    out["allen_cahn_512x512_M3_N512_mixed"] = {
-        "seconds_to_1e-10": t, "newton_its": st["newton_its"], "vcycles": st["cycles"],
-        "rel_res": st["rel_res"], "dof": int(dof), "dof_vcycles_per_s": dof * st["cycles"] / t}
-    del h, U
-    torch.cuda.empty_cache()
+    gpath = os.path.join(GOLDEN, "ac2d_512_golden.npz")
+    g = np.load(gpath) if os.path.exists(gpath) else None
+    dof = float(prob["N"] * prob["M"] * 512 * 512)
+    for prec in ("mixed", "fp64"):
+        h = stmg.Handle(prob, device=dev, precision=prec, newton_rtol=1e-10)
+        U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
+        h.solve(u0, U)
+        U.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = h.solve(u0, U)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        line = {"seconds_to_1e-10": t, "newton_its": st["newton_its"], "vcycles": st["cycles"],
+                "refinements": st["refinements"], "rel_res": st["rel_res"], "dof": int(dof),
+                "dof_vcycles_per_s": dof * st["cycles"] / t}
+        if g is not None:
+            line["rel_err_vs_oracle_at_T"] = _rel(U[-1, -1].cpu().numpy(), g["uT"])
+            line["rel_err_vs_oracle_at_T_half"] = _rel(U[prob["N"] // 2 - 1, -1].cpu().numpy(), g["umid"])
+            norms = torch.linalg.vector_norm(U.reshape(prob["N"], prob["M"], -1), dim=2).cpu().numpy()
+            line["max_rel_err_slab_norms"] = float(np.abs(norms / g["norms"] - 1).max())
+        out["allen_cahn_512x512_M3_N512_" + prec] = line
+        del h, U
+        torch.cuda.empty_cache()
+    if g is not None:
+        out["allen_cahn_oracle"] = {"seconds": float(g["seconds"]), "factorizations": int(g["factors"]),
+                                    "newton_its": int(g["newton_its"]),
+                                    "where": "build container host, 1 core (stored with the golden)"}
     print("allen-cahn done", file=sys.stderr, flush=True)
     return out
 
@@ -183,23 +337,33 @@ def _extra_adjoint(dev):
     import stmg_inputs as si
     from paper_2006_12883_amd import stmg
     out = {}
-    # adjoint on the 256^2 workload: gradient w.r.t. u0 and nu
+    # adjoint on the 256^2 workload: gradient w.r.t. u0 and nu, FP64 and mixed
+    # precision (FP32 cycles on the transposed system inside FP64 refinement)
+    # to the same tolerance; errors against the stored oracle gradients
+    # (tests/golden/make_adj2d_golden.py)
     prob = si.config("adj2d")
     u0n = si.initial("adj2d", prob)
     u0 = torch.as_tensor(u0n).to(dev)
     tgt = torch.as_tensor(si.u_tgt_adj2d(prob)).to(dev)
-    h = stmg.Handle(prob, device=dev)
-    U, _ = h.solve(u0)
-    g = 2.0 * (U[-1, -1] - tgt)
-    h.adjoint(U, g)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    gu0, gnu, st = h.adjoint(U, g)
-    torch.cuda.synchronize()
-    out["adjoint_256x256_M3_N256_fp64"] = {"seconds": time.perf_counter() - t0, "vcycles": st["cycles"],
-                                          "rel_res": st["rel_res"], "dL_dnu": gnu}
-    del h, U
-    torch.cuda.empty_cache()
+    gpath = os.path.join(GOLDEN, "adj2d_256_golden.npz")
+    gold = np.load(gpath) if os.path.exists(gpath) else None
+    for prec in ("fp64", "mixed"):
+        h = stmg.Handle(prob, device=dev, precision=prec, rtol=1e-11)
+        U, _ = h.solve(u0)
+        g = 2.0 * (U[-1, -1] - tgt)
+        h.adjoint(U, g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gu0, gnu, st = h.adjoint(U, g)
+        torch.cuda.synchronize()
+        line = {"seconds": time.perf_counter() - t0, "vcycles": st["cycles"], "rel_res": st["rel_res"],
+                "dL_dnu": gnu}
+        if gold is not None:
+            line["rel_err_grad_u0_vs_oracle"] = _rel(gu0.cpu().numpy(), gold["grad_u0"])
+            line["rel_err_dL_dnu_vs_oracle"] = abs(gnu / float(gold["grad_nu"]) - 1.0)
+        out["adjoint_256x256_M3_N256_" + prec + "_to_1e-11"] = line
+        del h, U
+        torch.cuda.empty_cache()
     print("adjoint done", file=sys.stderr, flush=True)
     return out
 
@@ -230,6 +394,32 @@ def _extra_batch(dev):
     torch.cuda.empty_cache()
     print("batch done", file=sys.stderr, flush=True)
     return out
+
+
+def _extra_sdc(dev):
+    """SDC sweeps (the implicit-Euler preconditioned Richardson iteration on the
+    collocation form, all slabs at once) on the 256^2 workload: time per sweep
+    and the DG residual after each block of sweeps."""
+    import torch
+    import stmg_inputs as si
+    from paper_2006_12883_amd import stmg
+    prob = si.config("rd2d")
+    u0 = torch.as_tensor(si.initial("rd2d", prob)).to(dev)
+    h = stmg.Handle(prob, device=dev, sdc=1)
+    U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
+    h.sdc_sweep(u0, U, 1)
+    U.zero_()
+    torch.cuda.synchronize()
+    rels = []
+    t0 = time.perf_counter()
+    for _ in range(4):
+        rels.append(h.sdc_sweep(u0, U, 4))
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    del h, U
+    torch.cuda.empty_cache()
+    print("sdc done", file=sys.stderr, flush=True)
+    return {"sdc_rd2d_fp64": {"sweeps": 16, "seconds_per_sweep": t / 16, "rel_res_after_4_8_12_16": rels}}
 
 
 def _extra_hierarchies(dev):
@@ -378,12 +568,12 @@ def main():
     if a.only:
         print(json.dumps(extras(dev, a.only)), flush=True)
         return
-    if a.kernel_only:
+    if a.kernel_only or a.cycle_only:
         h = stmg.Handle(prob, device=dev)
         U = torch.randn(shape, dtype=torch.float64, device=dev)
-        k_ms, c_ms, cbytes = time_kernels(h, U, u0, a.kernel_iters)
-        kb = smoother_bytes_per_dof() * dof
-        print(json.dumps({"smoother_ms": k_ms, "smoother_GBs": kb / k_ms / 1e6,
+        kernels, cyc_ms, lv, c_ms, cbytes = time_kernels(h, U, u0, a.kernel_iters)
+        cb, _ = cycle_bytes(lv)
+        print(json.dumps({"kernels": kernels, "vcycle_ms": cyc_ms, "vcycle_bytes": cb,
                           "copy_ms": c_ms, "copy_bytes": cbytes, "copy_GBs": cbytes / c_ms / 1e6}))
         return
 
@@ -425,7 +615,8 @@ def main():
             el = time.perf_counter() - s0
             if best is None or el < best[0]:
                 best = (el, st)
-        ttr[prec] = {"seconds": best[0], "cycles": best[1]["cycles"], "rel_res": best[1]["rel_res"]}
+        ttr[prec] = {"seconds": best[0], "cycles": best[1]["cycles"], "rel_res": best[1]["rel_res"],
+                     "refinements": best[1]["refinements"]}
         sols["solve_" + prec + "_rtol1e-10"] = V.cpu().numpy()
         hh.close()
         del V
@@ -438,10 +629,12 @@ def main():
     del V
     print("time-to-1e-10 done", file=sys.stderr, flush=True)
 
-    # dominant kernel: the level-0 smoothing sweep, timed with HIP events
-    k_ms, c_ms, cbytes = time_kernels(h, U, u0, a.kernel_iters)
-    kbytes = smoother_bytes_per_dof() * dof
-    achieved = kbytes / (k_ms * 1e-3) / 1e9
+    # the V-cycle's kernels and whole cycles against the HBM roofline
+    kernels, cyc_ms, lv, c_ms, cbytes = time_kernels(h, U, u0, a.kernel_iters)
+    cb, per_level = cycle_bytes(lv)
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    kd = kernels[dom]
+    achieved = kd["GBs"]
     print("kernel timing done", file=sys.stderr, flush=True)
 
     out = {
@@ -463,10 +656,15 @@ def main():
                    "final_rel_res": max(rels)},
         "time_to_1e-10": ttr,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_smooth_blk<3,double,0,2,true> (level 0)", "kernel_ms": k_ms,
-                     "bytes_per_launch": kbytes,
-                     "copy_GBs_same_bytes": cbytes / (c_ms * 1e-3) / 1e9},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if dom == "k_prolong_smooth_blk" else None,
+                     "kernel": dom + " (level 0, the longest kernel of the V-cycle)",
+                     "kernel_ms": kd["ms"], "bytes_per_launch": kd["bytes"],
+                     "level0_kernels": kernels,
+                     "cycle_ms": cyc_ms, "cycle_bytes": cb, "cycle_bytes_per_level": per_level,
+                     "cycle_GBs": cb / (cyc_ms * 1e-3) / 1e9,
+                     "cycle_frac": cb / (cyc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "copy_GBs_smoother_bytes": cbytes / (c_ms * 1e-3) / 1e9},
     }
     if not a.no_extras:
         del h, U
@@ -474,7 +672,7 @@ def main():
         out["other_workloads"] = extras(dev)
     if not a.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob, u0n, sols)
+        out["cpu_baseline"] = cpu_baseline(prob, u0n, sols, ms_per_step * 1e-3)
     print(json.dumps(out), flush=True)
 
 

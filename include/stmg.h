@@ -290,6 +290,15 @@ int stmg_level_restrict_residual(stmg_handle* h, int level, const double* d_f,
 int stmg_level_prolong(stmg_handle* h, int level, const double* d_Uin,
                        const double* d_ec, double* d_Uout);
 int stmg_coarse_solve(stmg_handle* h, const double* d_f, double* d_U);
+/* The V-cycle's way up on level `level` as one fused sweep: U' = U_in +
+ * P e_coarse, then one block-Jacobi sweep U_out = U' + omega D^{-1} (f -
+ * A_l U') (Sec. 4.2: prolongation followed by post-smoothing).  The same
+ * result as stmg_level_prolong followed by stmg_level_smooth, without storing
+ * U'.  U_in may be NULL (zero); on level 0 f may be NULL (built from d_u0).
+ * EUNSUPPORTED on grids other than periodic ones with even point counts and
+ * on windowed handles. */
+int stmg_level_prolong_smooth(stmg_handle* h, int level, const double* d_f, const double* d_u0,
+                              const double* d_Uin, const double* d_ec, double* d_Uout);
 
 void stmg_destroy(stmg_handle* h);
 

@@ -261,6 +261,22 @@ int stmg_level_prolong(stmg_handle* h, int level, const double* d_Uin, const dou
   return e == hipSuccess ? STMG_OK : STMG_EHIP;
 }
 
+int stmg_level_prolong_smooth(stmg_handle* h, int level, const double* d_f, const double* d_u0,
+                              const double* d_Uin, const double* d_ec, double* d_Uout) {
+  if (!h || !d_ec || !d_Uout || level < 0 || level + 1 >= static_cast<int>(h->s.lv.size())) {
+    stmg::set_error("bad argument");
+    return STMG_EINVAL;
+  }
+  if (h->s.win) { stmg::set_error("windowed handle"); return STMG_EUNSUPPORTED; }
+  if (!stmg::blocked_layout(h->s.lv[level].op)) {
+    stmg::set_error("fused prolongation + smoothing: periodic grids with even point counts only");
+    return STMG_EUNSUPPORTED;
+  }
+  hipError_t e = h->s.prolong_smooth<double>(level, false, stmg::REACT_CONST, d_Uin, d_ec, d_f,
+                                             level == 0 ? d_u0 : nullptr, d_Uout);
+  return e == hipSuccess ? STMG_OK : STMG_EHIP;
+}
+
 int stmg_coarse_solve(stmg_handle* h, const double* d_f, double* d_U) {
   if (!h || !d_U) { stmg::set_error("bad argument"); return STMG_EINVAL; }
   if (h->s.win) { stmg::set_error("windowed handle"); return STMG_EUNSUPPORTED; }

@@ -855,11 +855,15 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
   int c = 0;   // outer steps (V-cycles in FP64, refinement steps in mixed precision)
   int vc = 0;  // V-cycles
   int status = STMG_OK;
-  // Waits for the queued norm and applies the stop tests to U_c.
+  // Waits for the queued norm and applies the stop tests to U_c.  A negative
+  // norm_b means: relative to the first residual (||b|| for a zero initial
+  // guess), so the caller needs no separate pass and read for ||b||.
+  double nb = norm_b;
   auto decide = [&](bool* stop) -> hipError_t {
     HIP_TRY(hipEventSynchronize(hnorm.ev));
     const double rn2 = *hnorm.h;
-    rel = norm_b > 0.0 ? std::sqrt(rn2) / norm_b : std::sqrt(rn2);
+    if (first && nb < 0.0) nb = rn2 > 0.0 ? std::sqrt(rn2) : 1.0;
+    rel = nb > 0.0 ? std::sqrt(rn2) / nb : std::sqrt(rn2);
     if (first) { rel0 = rel; prev = rel; first = false; }
     *stop = true;
     if (!std::isfinite(rel)) { status = STMG_ENAN; return hipSuccess; }
@@ -1018,7 +1022,9 @@ int Solver::solve_fgmres(bool adj, int react, const double* f, const double* u0,
   }
   KVecs Vs{};
   for (int i = 0; i <= m; ++i) Vs.v[i] = Vb[i];
-  const double scale = norm_b > 0.0 ? norm_b : 1.0;
+  // norm_b < 0: relative to the first residual (as in solve_linear)
+  double scale = norm_b > 0.0 ? norm_b : 1.0;
+  bool scale_first = norm_b < 0.0;
   std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), inv2(m + 1);
   auto Hs = [&](int i, int j) -> double& { return H[static_cast<size_t>(i) * m + j]; };
   auto wait = [&]() -> hipError_t {
@@ -1070,6 +1076,10 @@ int Solver::solve_fgmres(bool adj, int react, const double* f, const double* u0,
     HIP_CHECK(residual64<double>(adj, react, U, f, u0, left ? T : Vb[0], kh.d));
     HIP_CHECK(wait());
     const double rnorm = std::sqrt(*hres);
+    if (scale_first) {
+      scale = rnorm > 0.0 ? rnorm : 1.0;
+      scale_first = false;
+    }
     rel = rnorm / scale;
     if (!std::isfinite(rel)) { status = STMG_ENAN; break; }
     if (rnorm == 0.0) break;
@@ -1474,20 +1484,13 @@ int Solver::sdc(const double* u0, double* U, int sweeps, double* h_rel) {
       Solver* S = sdcn[m].get();
       double* rhs = S->lv[0].f64;
       HIP_CHECK(launch_sdc_gather(delta64, sdc_acc, rhs, N, M, P, m, stream));
-      int np = 0;
-      HIP_CHECK(launch_sumsq(rhs, NP, S->part, &np, stream));
-      HIP_CHECK(launch_sum_partials(S->part, np, S->scal + 5, stream));
-      double r2 = 0.0;
-      int rc = read_scalar(S->scal + 5, &r2);
-      if (rc) return rc;
       HIP_CHECK(hipMemsetAsync(S->delta64, 0, NP * sizeof(double), stream));
-      if (r2 > 0.0) {
-        int cyc = 0;
-        double rel = 0.0;
-        rc = S->solve_linear(false, REACT_CONST, rhs, nullptr, S->delta64, opt.rtol, std::sqrt(r2),
-                             &cyc, &rel);
-        if (rc) return rc;
-      }
+      // from a zero guess: the stop test is relative to the first residual,
+      // which is ||rhs|| (no separate norm pass or host read per node)
+      int cyc = 0;
+      double rel = 0.0;
+      const int rc = S->solve_linear(false, REACT_CONST, rhs, nullptr, S->delta64, opt.rtol, -1.0, &cyc, &rel);
+      if (rc) return rc;
       HIP_CHECK(launch_sdc_update(U, sdc_acc, S->delta64, N, M, L0.nx, L0.ny, L0.op.bc, L0.op.cx,
                                   L0.op.cy, L0.op.lam, sdc_w[m], m, stream));
     }

@@ -143,6 +143,10 @@ class Handle:
         B.check(B.lib().stmg_level_prolong(self.h, level, _ptr(Uin), _ptr(ec), _ptr(Uout)),
                 "stmg_level_prolong")
 
+    def prolong_smooth(self, level, ec, Uout, Uin=None, f=None, u0=None):
+        B.check(B.lib().stmg_level_prolong_smooth(self.h, level, _ptr(f), _ptr(u0), _ptr(Uin), _ptr(ec),
+                                                  _ptr(Uout)), "stmg_level_prolong_smooth")
+
     def coarse_solve(self, f, U):
         B.check(B.lib().stmg_coarse_solve(self.h, _ptr(f), _ptr(U)), "stmg_coarse_solve")
 

@@ -315,3 +315,36 @@ def test_full_size_smoother_and_vcycle():
     Ud = T(U)
     h.vcycle(T(u0), Ud)
     assert_close(Ud.cpu().numpy(), ref, 1e-11, "full-size V-cycle")
+
+
+@pytest.mark.parametrize("name,prob", CASES)
+def test_prolong_smooth_each_level(name, prob):
+    """The fused way up (stmg_level_prolong_smooth): U' = U + P e_c, then one
+    block-Jacobi sweep, against the oracle's prolongation followed by its
+    smoother; on level 0 also with the right-hand side built from u0."""
+    print("case", name, flush=True)
+    levels, kinds = mg.hierarchy(prob, fft_coarse=0)
+    h = H(prob, fft_coarse=0)
+    ny, nx = si.grid_points(prob)
+    blocked = prob["bc"] == "periodic" and nx % 2 == 0 and (ny == 1 or ny % 2 == 0)
+    for l in range(len(levels) - 1):
+        lev, nxt = levels[l], levels[l + 1]
+        rng = np.random.default_rng(30 + l)
+        U = rng.standard_normal(lev.shape)
+        f = rng.standard_normal(lev.shape)
+        ec = rng.standard_normal(nxt.shape)
+        out = torch.empty(lev.shape, dtype=torch.float64, device="cuda:0")
+        if not blocked:
+            with pytest.raises(Exception):
+                h.prolong_smooth(l, T(ec), out, Uin=T(U), f=T(f))
+            return
+        Up = U + mg.prolong(ec, kinds[l], lev.dim, lev.Pm)
+        ref = lev.smooth(Up, f, 0.8, 16 if l == 0 else 4)
+        h.prolong_smooth(l, T(ec), out, Uin=T(U), f=T(f))
+        assert_close(out.cpu().numpy(), ref, 1e-12, "prolong+smooth level %d kind %s" % (l, kinds[l]))
+        if l == 0:
+            u0 = rng.standard_normal((ny, nx))
+            f0 = mg.rhs(levels, u0)
+            ref0 = lev.smooth(Up, f0, 0.8, 16)
+            h.prolong_smooth(0, T(ec), out, Uin=T(U), u0=T(u0))
+            assert_close(out.cpu().numpy(), ref0, 1e-12, "prolong+smooth level 0 from u0")

@@ -1,5 +1,8 @@
 """Mixed precision (FP32 V-cycles inside FP64 refinement) and Newton for the
 Allen-Cahn reaction, against the FP64 oracle."""
+import functools
+import os
+
 import numpy as np
 import pytest
 
@@ -158,3 +161,54 @@ def test_newton_ac2d_full_sampled():
             allatonce.residual_entry(prob, u0, Ul, 0, i, y, x)
         got = float(r[n, i, y, x])
         assert abs(got - ref) <= 1e-12 * max(1.0, float(np.abs(Ul).max())), (n, i, y, x, got, ref)
+
+
+_AC2D_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ac2d_512_golden.npz")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_newton_ac2d_full_vs_oracle_golden(prec):
+    """The full 512^2 x M=3 x N=512 Allen-Cahn workload against the stored
+    oracle solution (tests/golden/make_ac2d_golden.py: the sequential Radau
+    IIA stepper with Newton per step to 1e-14): u(T), u(T/2), and the norm and
+    sum of every slab's node planes.  The error is about 30x the relative
+    Newton residual, so FP64 stops at 1e-12 and mixed precision at 1e-11."""
+    print("case ac2d full golden", prec, flush=True)
+    g = np.load(_AC2D_GOLDEN)
+    prob = si.config("ac2d")
+    u0 = si.initial("ac2d", prob)
+    tol = 1e-12 if prec == "fp64" else 1e-11
+    U, st = H(prob, precision=prec, newton_rtol=tol).solve(T(u0))
+    assert st["status"] == 0 and st["rel_res"] <= tol
+    N, M = prob["N"], prob["M"]
+    lim = 1e-10 if prec == "fp64" else 1e-9
+    assert rel_err(U[-1, -1].cpu().numpy(), g["uT"]) <= lim
+    assert rel_err(U[N // 2 - 1, -1].cpu().numpy(), g["umid"]) <= lim
+    flat = U.reshape(N, M, -1)
+    norms = torch.linalg.vector_norm(flat, dim=2).cpu().numpy()
+    sums = flat.sum(dim=2).cpu().numpy()
+    assert np.abs(norms - g["norms"]).max() <= lim * np.abs(g["norms"]).max()
+    assert np.abs(sums - g["sums"]).max() <= lim * np.abs(g["norms"]).max() * 512
+    print("ac2d %s: %d Newton its, %d cycles, err(T) %.2e" % (prec, st["newton_its"], st["cycles"],
+                                                          rel_err(U[-1, -1].cpu().numpy(), g["uT"])))
+
+
+@functools.lru_cache(maxsize=1)
+def _ac2d_reduced_oracle():
+    prob = si.problem(2, 128, 3, 128, 0.5, nu=1e-3, gamma=1.0, reaction="allen_cahn")
+    u0 = si.u0_ac2d(prob, 3)
+    return prob, u0, stepper.solve_allen_cahn(prob, u0, reuse=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_newton_ac2d_reduced_full_trajectory(prec):
+    """The reduced Allen-Cahn workload (128^2, N = 128, T = 0.5, the same nu,
+    gamma and initial-data recipe): every stage value against the oracle."""
+    print("case ac2d reduced", prec, flush=True)
+    prob, u0, ref = _ac2d_reduced_oracle()
+    tol = 1e-12 if prec == "fp64" else 1e-11
+    U, st = H(prob, precision=prec, newton_rtol=tol).solve(T(u0))
+    assert st["status"] == 0
+    e, eT = _errs(U.cpu().numpy(), ref)
+    lim = 1e-10 if prec == "fp64" else 1e-9
+    assert e <= lim and eT <= lim, (e, eT)
