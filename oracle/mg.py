@@ -23,7 +23,12 @@ notes):
   plain point-block Jacobi over slabs; the coarser levels use their own
   (shorter) `chunk_coarse`;
 * space transfer: full weighting [1 2 1]/4 per dimension and linear
-  interpolation, vertex-centred (coarse point X is fine point 2X);
+  interpolation, vertex-centred (coarse point X is fine point 2X); on
+  Neumann grids (the paper's boundary condition, Sec. 3: nx elements, nx + 1
+  points, lumped linear FE) the end points use the mirror value as their
+  missing neighbour, in the Laplacian and in the restriction alike.  For the
+  restriction this is the FE-consistent R = M_c^-1 P^T M_f with the lumped
+  masses (half weight at the end points);
 * time transfer: slab n is identified with its end point T_{n+1}; coarse
   slab J is fine slab 2J+1, the stencil is [1 2 1]/2 (restriction = P^T,
   scaled so that rediscretized coarse operators match R A P), T_0 carries a
@@ -59,12 +64,15 @@ from . import radau
 
 
 class Level:
-    def __init__(self, nx, ny, N, M, dt, nu, lam, length, dim, tab):
+    def __init__(self, nx, ny, N, M, dt, nu, lam, length, dim, tab, bc="periodic"):
+        # nx, ny: grid points; elements = points (periodic) or points - 1 (Neumann)
         self.nx, self.ny, self.N, self.M, self.dt = nx, ny, N, M, dt
-        self.nu, self.lam, self.dim = nu, lam, dim
+        self.nu, self.lam, self.dim, self.bc = nu, lam, dim, bc
         self.length = [float(length[0]), float(length[1])]
-        self.hx = length[0] / nx
-        self.hy = length[1] / ny if dim == 2 else 1.0
+        e = 0 if bc == "periodic" else 1
+        self.ex, self.ey = nx - e, (ny - e if dim == 2 else 1)
+        self.hx = length[0] / self.ex
+        self.hy = length[1] / self.ey if dim == 2 else 1.0
         self.Kq, self.b, self.l0 = tab["Kq"], tab["b"], tab["l0"]
         cx = nu / self.hx ** 2
         cy = nu / self.hy ** 2 if dim == 2 else 0.0
@@ -79,9 +87,9 @@ class Level:
         return (self.N, self.M, self.ny, self.nx)
 
     def lap(self, U):
-        out = self.cx * (np.roll(U, 1, -1) + np.roll(U, -1, -1) - 2 * U)
+        out = self.cx * (_left(U, -1, self.bc) + _right(U, -1, self.bc) - 2 * U)
         if self.dim == 2:
-            out = out + self.cy * (np.roll(U, 1, -2) + np.roll(U, -1, -2) - 2 * U)
+            out = out + self.cy * (_left(U, -2, self.bc) + _right(U, -2, self.bc) - 2 * U)
         return out
 
     def apply(self, U):
@@ -118,8 +126,15 @@ class Level:
         differences Lap = cx D_x (+ cy D_y) on the [y][x] ordering."""
         def d2(n, c):
             I = sp.identity(n, format="csr")
-            S = sp.csr_matrix((np.ones(n), (np.arange(n), (np.arange(n) + 1) % n)), shape=(n, n))
-            return c * (S + S.T - 2 * I)
+            if self.bc == "periodic":
+                S = sp.csr_matrix((np.ones(n), (np.arange(n), (np.arange(n) + 1) % n)), shape=(n, n))
+                return c * (S + S.T - 2 * I)
+            # Neumann: the mirror point doubles the inner neighbour at both ends
+            up = np.ones(n - 1)
+            lo = np.ones(n - 1)
+            up[0] = 2.0
+            lo[-1] = 2.0
+            return c * (sp.diags([lo, up], [-1, 1], shape=(n, n), format="csr") - 2 * I)
         lap = sp.kron(sp.identity(self.ny), d2(self.nx, self.cx))
         if self.dim == 2:
             lap = lap + sp.kron(d2(self.ny, self.cy), sp.identity(self.nx))
@@ -150,28 +165,53 @@ class Level:
         return U
 
 
-def restrict_space(r, dim):
-    r = 0.25 * np.roll(r, 1, -1) + 0.5 * r + 0.25 * np.roll(r, -1, -1)
+def _left(U, axis, bc):
+    """The neighbour at index i - 1 along `axis`: periodic wrap, or the mirror
+    point i + 1 at the first point (Neumann)."""
+    if bc == "periodic":
+        return np.roll(U, 1, axis)
+    n = U.shape[axis]
+    idx = np.concatenate(([1], np.arange(n - 1)))
+    return np.take(U, idx, axis=axis)
+
+
+def _right(U, axis, bc):
+    """The neighbour at index i + 1: periodic wrap, or the mirror point i - 1
+    at the last point (Neumann)."""
+    if bc == "periodic":
+        return np.roll(U, -1, axis)
+    n = U.shape[axis]
+    idx = np.concatenate((np.arange(1, n), [n - 2]))
+    return np.take(U, idx, axis=axis)
+
+
+def restrict_space(r, dim, bc="periodic"):
+    r = 0.25 * _left(r, -1, bc) + 0.5 * r + 0.25 * _right(r, -1, bc)
     r = r[..., ::2]
     if dim == 2:
-        r = 0.25 * np.roll(r, 1, -2) + 0.5 * r + 0.25 * np.roll(r, -1, -2)
+        r = 0.25 * _left(r, -2, bc) + 0.5 * r + 0.25 * _right(r, -2, bc)
         r = r[..., ::2, :]
     return r
 
 
-def prolong_space(e, dim):
-    sh = list(e.shape)
-    sh[-1] *= 2
-    f = np.zeros(sh)
+def _interp_axis(e, axis, bc):
+    """Linear interpolation to the grid with half the spacing along `axis`:
+    fine 2X = coarse X, fine 2X + 1 = mean of coarse X and X + 1 (periodic:
+    nc -> 2 nc points; Neumann: nc -> 2 nc - 1 points, both ends kept)."""
+    e = np.moveaxis(e, axis, -1)
+    nc = e.shape[-1]
+    nf = 2 * nc if bc == "periodic" else 2 * nc - 1
+    f = np.zeros(e.shape[:-1] + (nf,))
     f[..., ::2] = e
-    f[..., 1::2] = 0.5 * (e + np.roll(e, -1, -1))
+    nxt = np.roll(e, -1, -1) if bc == "periodic" else e[..., 1:]
+    f[..., 1::2] = 0.5 * ((e if bc == "periodic" else e[..., :-1]) + nxt)
+    return np.moveaxis(f, -1, axis)
+
+
+def prolong_space(e, dim, bc="periodic"):
+    f = _interp_axis(e, -1, bc)
     if dim == 2:
-        sh = list(f.shape)
-        sh[-2] *= 2
-        g = np.zeros(sh)
-        g[..., ::2, :] = f
-        g[..., 1::2, :] = 0.5 * (f + np.roll(f, -1, -2))
-        f = g
+        f = _interp_axis(f, -2, bc)
     return f
 
 
@@ -212,15 +252,18 @@ def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30, f
     """Level list and the coarsening kind between consecutive levels.
 
     kinds[l] is 's' (space), 't' (time) or 'st' (both) for the step l -> l+1.
-    Periodic boundary conditions only.
+    Periodic or Neumann grids; space coarsening halves the element count
+    (which must be even and at least 4); the Fourier coarsest-level rule is
+    for periodic grids only.
     """
-    assert prob["bc"] == "periodic"
     dim = prob["dim"]
-    nx = prob["nx"][0]
-    ny = prob["nx"][1] if dim == 2 else 1
+    bc = prob.get("bc", "periodic")
+    e = 0 if bc == "periodic" else 1
+    nx = prob["nx"][0] + e
+    ny = prob["nx"][1] + e if dim == 2 else 1
     N, dt = prob["N"], prob["dt"]
     mk = lambda nx_, ny_, N_, dt_, M_: Level(nx_, ny_, N_, M_, dt_, prob["nu"], prob.get("lambda", 0.0),
-                                             prob["length"], dim, radau.tables(M_))
+                                             prob["length"], dim, radau.tables(M_), bc)
     levels = [mk(nx, ny, N, dt, prob["M"])]
     kinds = []
     while len(levels) < max_levels:
@@ -228,10 +271,10 @@ def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30, f
         if l.M * l.nx * l.ny * l.N <= min_coarse:
             break
         pow2_sides = dim == 2 and all(n >= 2 and n & (n - 1) == 0 and n <= fft_side for n in (l.nx, l.ny))
-        if len(levels) > 1 and (l.nx * l.ny <= fft_plane or pow2_sides) and \
+        if bc == "periodic" and len(levels) > 1 and (l.nx * l.ny <= fft_plane or pow2_sides) and \
                 l.M * l.nx * l.ny * l.N <= fft_coarse:
             break
-        can_s = l.nx % 2 == 0 and l.nx >= 4 and (dim == 1 or (l.ny % 2 == 0 and l.ny >= 4))
+        can_s = l.ex % 2 == 0 and l.ex >= 4 and (dim == 1 or (l.ey % 2 == 0 and l.ey >= 4))
         can_t = l.N % 2 == 0
         mu = l.nu * l.dt / min(l.hx, l.hy if dim == 2 else l.hx) ** 2
         if coarsen == "space":
@@ -251,8 +294,8 @@ def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30, f
                 k = None
         if k is None:
             break
-        nx2 = l.nx // 2 if "s" in k else l.nx
-        ny2 = (l.ny // 2 if dim == 2 else 1) if "s" in k else l.ny
+        nx2 = l.ex // 2 + e if "s" in k else l.nx
+        ny2 = (l.ey // 2 + e if dim == 2 else 1) if "s" in k else l.ny
         N2 = l.N // 2 if "t" in k else l.N
         dt2 = 2 * l.dt if "t" in k else l.dt
         M2 = l.M - 1 if "m" in k else l.M
@@ -262,9 +305,9 @@ def hierarchy(prob, coarsen="auto", mu_crit=0.5, min_coarse=64, max_levels=30, f
     return levels, kinds
 
 
-def restrict(r, kind, dim, Pm=None):
+def restrict(r, kind, dim, Pm=None, bc="periodic"):
     if "s" in kind:
-        r = restrict_space(r, dim)
+        r = restrict_space(r, dim, bc)
     if "t" in kind:
         r = restrict_time(r)
     if "m" in kind:
@@ -272,13 +315,13 @@ def restrict(r, kind, dim, Pm=None):
     return r
 
 
-def prolong(e, kind, dim, Pm=None):
+def prolong(e, kind, dim, Pm=None, bc="periodic"):
     if "m" in kind:
         e = np.einsum("ik,nkyx->niyx", Pm, e)
     if "t" in kind:
         e = prolong_time(e)
     if "s" in kind:
-        e = prolong_space(e, dim)
+        e = prolong_space(e, dim, bc)
     return e
 
 
@@ -299,10 +342,10 @@ def vcycle(levels, kinds, U, f, omega=0.8, chunk=16, nu_pre=1, nu_post=1, l=0, c
     for _ in range(nu_pre):
         U = sweep(U)
     r = f - lev.apply(U)
-    fc = restrict(r, kinds[l], lev.dim, lev.Pm)
+    fc = restrict(r, kinds[l], lev.dim, lev.Pm, lev.bc)
     ec = vcycle(levels, kinds, np.zeros(levels[l + 1].shape), fc, omega, chunk, nu_pre, nu_post, l + 1,
                 chunk_coarse, smoothers)
-    U = U + prolong(ec, kinds[l], lev.dim, lev.Pm)
+    U = U + prolong(ec, kinds[l], lev.dim, lev.Pm, lev.bc)
     for _ in range(nu_post):
         U = sweep(U)
     return U
@@ -310,8 +353,8 @@ def vcycle(levels, kinds, U, f, omega=0.8, chunk=16, nu_pre=1, nu_post=1, l=0, c
 
 def level_problem(lev):
     """The problem statement a level rediscretizes (periodic, same domain)."""
-    nx = [lev.nx, lev.ny if lev.dim == 2 else 1]
-    return dict(dim=lev.dim, nx=nx, length=list(lev.length), bc="periodic", nu=lev.nu,
+    nx = [lev.ex, lev.ey if lev.dim == 2 else 1]
+    return dict(dim=lev.dim, nx=nx, length=list(lev.length), bc=lev.bc, nu=lev.nu,
                 reaction="linear", **{"lambda": lev.lam}, gamma=0.0, M=lev.M, N=lev.N, dt=lev.dt)
 
 

@@ -67,3 +67,23 @@ def test_batch_workspace_counts_inner_cycles():
              for k in (1, 5, 64)]
     assert all(x > 0 for x in sizes)
     assert sizes[0] < sizes[1] < sizes[2]
+
+
+def test_undersized_workspace_is_refused_on_the_host():
+    """stmg_setup checks the workspace size before it touches the device:
+    one byte short of stmg_workspace_bytes gives STMG_ENOMEM (the pointer
+    below is never dereferenced)."""
+    import stmg_inputs as si
+    prob = si.problem(2, 32, 3, 16, 0.5, nu=1e-2, lam=1.0)
+    P, O = B.make_problem(prob), B.make_options()
+    need = B.lib().stmg_workspace_bytes(ctypes.byref(P), ctypes.byref(O))
+    assert need > 0
+    h = ctypes.c_void_p()
+    rc = B.lib().stmg_setup(ctypes.byref(P), ctypes.byref(O), ctypes.c_void_p(1 << 20), need - 1, None,
+                            ctypes.byref(h))
+    assert rc == B.STMG_ENOMEM
+    assert b"workspace too small" in B.lib().stmg_last_error()
+    # misaligned workspace: EINVAL, also before any device access
+    rc = B.lib().stmg_setup(ctypes.byref(P), ctypes.byref(O), ctypes.c_void_p((1 << 20) + 8), need, None,
+                            ctypes.byref(h))
+    assert rc == B.STMG_EINVAL

@@ -22,6 +22,15 @@ CASES = [
     ("1d-odd", si.problem(1, 25, 2, 8, 0.2, nu=0.3, lam=0.1)),
 ]
 
+# Neumann grids (the paper's boundary condition, Sec. 3): mirror points in the
+# operator and the restriction, both ends kept by the interpolation
+NEUMANN = [
+    ("1d-neumann", si.problem(1, 32, 3, 8, 0.2, nu=0.5, lam=0.3, bc="neumann")),
+    ("2d-neumann", si.problem(2, 16, 2, 6, 0.5, nu=0.05, lam=1.0, bc="neumann")),
+    ("2d-neumann-M4", si.problem(2, 12, 4, 5, 0.3, nu=0.02, lam=0.5, bc="neumann")),
+    ("2d-neumann-space", si.problem(2, 20, 3, 4, 0.2, nu=0.2, lam=0.1, bc="neumann")),
+]
+
 
 def _rng_fields(prob, seed):
     rng = np.random.default_rng(seed)
@@ -52,7 +61,7 @@ def test_residual_matches_allatonce(name, prob):
 FFT = [1 << 22, 0]
 
 
-@pytest.mark.parametrize("name,prob", CASES)
+@pytest.mark.parametrize("name,prob", CASES + NEUMANN)
 @pytest.mark.parametrize("fft", FFT)
 def test_hierarchy_matches_oracle(name, prob, fft):
     print("case", name, fft, flush=True)
@@ -66,7 +75,7 @@ def test_hierarchy_matches_oracle(name, prob, fft):
         assert g["kind"] == (code[kinds[l]] if l < len(kinds) else 0)
 
 
-@pytest.mark.parametrize("name,prob", CASES)
+@pytest.mark.parametrize("name,prob", CASES + NEUMANN)
 @pytest.mark.parametrize("zero", [False, True])
 def test_smoother_each_level(name, prob, zero):
     print("case", name, zero, flush=True)
@@ -82,7 +91,7 @@ def test_smoother_each_level(name, prob, zero):
         assert_close(out.cpu().numpy(), ref, 1e-12, "smooth level %d" % l)
 
 
-@pytest.mark.parametrize("name,prob", CASES)
+@pytest.mark.parametrize("name,prob", CASES + NEUMANN)
 def test_restrict_prolong_each_level(name, prob):
     print("case", name, flush=True)
     levels, kinds = mg.hierarchy(prob, fft_coarse=0)
@@ -92,18 +101,18 @@ def test_restrict_prolong_each_level(name, prob):
         rng = np.random.default_rng(20 + l)
         U = rng.standard_normal(lev.shape)
         f = rng.standard_normal(lev.shape)
-        ref = mg.restrict(f - lev.apply(U), kinds[l], lev.dim)
+        ref = mg.restrict(f - lev.apply(U), kinds[l], lev.dim, bc=lev.bc)
         fc = torch.empty(nxt.shape, dtype=torch.float64, device="cuda:0")
         h.restrict_residual(l, T(U), fc, f=T(f))
         assert_close(fc.cpu().numpy(), ref, 1e-12, "restrict level %d kind %s" % (l, kinds[l]))
         ec = rng.standard_normal(nxt.shape)
-        refp = U + mg.prolong(ec, kinds[l], lev.dim)
+        refp = U + mg.prolong(ec, kinds[l], lev.dim, bc=lev.bc)
         out = torch.empty(lev.shape, dtype=torch.float64, device="cuda:0")
         h.prolong(l, T(ec), out, Uin=T(U))
         assert_close(out.cpu().numpy(), refp, 1e-13, "prolong level %d kind %s" % (l, kinds[l]))
 
 
-@pytest.mark.parametrize("name,prob", CASES)
+@pytest.mark.parametrize("name,prob", CASES + NEUMANN)
 @pytest.mark.parametrize("fft", FFT)
 def test_coarse_solve(name, prob, fft):
     """Fourier coarsest solve (default rule, periodic) or the dense one (deep

@@ -151,9 +151,11 @@ def test_paper_monodomain_m3():
     # h = 10/1024 puts the rounding floor of the stepper's Newton residual
     # near 1e-13, so its stop test is 1e-12 here
     ref = stepper.solve_allen_cahn(prob, u0, tol=1e-12)
-    U, st = H(prob, krylov=10, coarsen="space", max_levels=7, newton_rtol=1e-10).solve(T(u0))
+    # the error is about 100x the relative Newton residual here (h = 10/1024,
+    # mu = dt / h^2 = 655), so the solve stops at 1e-12 for a 1e-10 error
+    U, st = H(prob, krylov=10, coarsen="space", max_levels=7, newton_rtol=1e-12).solve(T(u0))
     assert st["status"] == 0
-    assert rel_err(U.cpu().numpy(), ref) <= 1e-8
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-10
 
 
 def test_fgmres_stops_at_rounding_floor():
@@ -223,12 +225,15 @@ def test_paper_heat1d_weak(M, Nt, L):
     assert (Nt, L) in si.PAPER_WEAK[M]
     prob = si.paper_heat1d(M, Nt=Nt)
     u0 = si.u0_paper_heat1d(prob)
-    U, st = H(prob, krylov=10, coarsen="space", max_levels=L, nu_pre=3, nu_post=3, rtol=1e-10,
+    # mu = dt / h^2 reaches 512 (M = 2) and 16384 (M = 5): the error of the
+    # whole trajectory is up to ~100x the relative residual, so the solve
+    # stops at 1e-12 for a 1e-10 error
+    U, st = H(prob, krylov=10, coarsen="space", max_levels=L, nu_pre=3, nu_post=3, rtol=1e-12,
               max_cycles=300).solve(T(u0))
     assert st["status"] == 0
     ref = stepper.solve_linear(prob, u0)
     assert np.abs(U[-1, -1].cpu().numpy() - ref[-1, -1]).max() <= 1e-10
-    assert rel_err(U.cpu().numpy(), ref) <= 1e-8
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-10
 
 
 def test_paper_heat1d_mixed_split_coarse():

@@ -158,3 +158,32 @@ def test_single_level_fourier_solve(nx, M, N):
     U, st = h.solve(T(u0))
     assert st["status"] == 0 and st["cycles"] <= 1, st
     assert rel_err(U.cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("reaction", ["linear", "allen_cahn"])
+def test_nan_input_reports_enan(prec, reaction):
+    """A NaN in u0 makes every residual norm NaN: the solve stops at once
+    with STMG_ENAN (the kernels run on NaN values; nothing faults)."""
+    print("case nan", prec, reaction, flush=True)
+    if reaction == "linear":
+        prob = si.problem(2, 32, 3, 16, 0.5, nu=1e-2, lam=1.0)
+    else:
+        prob = si.problem(2, 32, 3, 16, 0.5, nu=1e-3, gamma=1.0, reaction="allen_cahn")
+    u0 = si.u0_rd2d(prob, 2)
+    u0[5, 7] = np.nan
+    U, st = H(prob, precision=prec).solve(T(u0), check=False)
+    assert st["status"] == -6, st
+    assert st["cycles"] <= 1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_overdamped_smoother_reports_divergence(prec):
+    """omega = 3 makes the block-Jacobi sweep an amplifier: the residual grows
+    and the solve stops with STMG_EDIVERGED well before max_cycles."""
+    print("case omega 3", prec, flush=True)
+    prob = si.problem(2, 32, 3, 16, 0.5, nu=1e-2, lam=1.0)
+    u0 = si.u0_rd2d(prob, 2)
+    U, st = H(prob, precision=prec, omega=3.0, max_cycles=200).solve(T(u0), check=False)
+    assert st["status"] == -5, st
+    assert st["cycles"] < 100

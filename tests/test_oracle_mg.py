@@ -212,3 +212,96 @@ def test_sdc_m1_is_backward_euler():
     for _ in range(prob["N"]):
         U = sdc.sweep(prob, u0, U)
     assert np.abs(U - Ue).max() < 1e-13
+
+
+# --- Neumann grids (the paper's boundary condition, Sec. 3) -----------------
+def _interp_matrix(ec):
+    """Linear interpolation from ec + 1 coarse to 2 ec + 1 fine points as an
+    explicit matrix (fine 2J = coarse J, fine 2J + 1 = their mean)."""
+    P = np.zeros((2 * ec + 1, ec + 1))
+    for J in range(ec + 1):
+        P[2 * J, J] = 1.0
+        if J < ec:
+            P[2 * J + 1, J] = 0.5
+            P[2 * J + 1, J + 1] = 0.5
+    return P
+
+
+def _lumped_mass(e, h):
+    m = np.full(e + 1, h)
+    m[0] = m[-1] = 0.5 * h
+    return np.diag(m)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_neumann_restriction_is_fe_consistent(dim):
+    """On Neumann grids the restriction equals R = M_c^-1 P^T M_f with the
+    lumped linear-FE masses (half weight at the end points), built here as
+    explicit matrices; a sign or weight slip at an end point fails this."""
+    ef, h = 8, 0.125
+    Rx = np.linalg.inv(_lumped_mass(ef // 2, 2 * h)) @ _interp_matrix(ef // 2).T @ _lumped_mass(ef, h)
+    rng = np.random.default_rng(4)
+    ny = ef + 1 if dim == 2 else 1
+    r = rng.standard_normal((2, 3, ny, ef + 1))
+    want = np.einsum("Xx,nmyx->nmyX", Rx, r)
+    if dim == 2:
+        want = np.einsum("Yy,nmyX->nmYX", Rx, want)
+    got = mg.restrict_space(r, dim, "neumann")
+    assert np.abs(got - want).max() < 1e-14
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_neumann_prolongation_reproduces_linears(dim):
+    """Linear functions of x (and y) on the coarse Neumann grid, end points
+    included, are interpolated exactly; the interpolation matrix matches."""
+    ec = 4
+    xc = np.arange(ec + 1) * 0.25
+    xf = np.arange(2 * ec + 1) * 0.125
+    if dim == 1:
+        e = (1.5 + 2.0 * xc)[None, None, None, :]
+        f = mg.prolong_space(e, 1, "neumann")
+        assert np.abs(f[0, 0, 0] - (1.5 + 2.0 * xf)).max() < 1e-15
+    else:
+        e = (1.5 + 2.0 * xc[None, :] - 3.0 * xc[:, None])[None, None]
+        f = mg.prolong_space(e, 2, "neumann")
+        assert np.abs(f[0, 0] - (1.5 + 2.0 * xf[None, :] - 3.0 * xf[:, None])).max() < 1e-14
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal((1, 1, 1, ec + 1))
+    assert np.abs(mg.prolong_space(v, 1, "neumann")[0, 0, 0] - _interp_matrix(ec) @ v[0, 0, 0]).max() < 1e-15
+
+
+NEUMANN = [si.problem(1, 16, 3, 8, 0.2, nu=0.5, lam=0.3, bc="neumann"),
+           si.problem(2, 8, 2, 6, 0.5, nu=0.05, lam=1.0, bc="neumann")]
+
+
+@pytest.mark.parametrize("prob", NEUMANN)
+def test_neumann_operator_matches_allatonce(prob):
+    """The level operator with mirror points equals the literal assembly of the
+    all-at-once system (oracle.allatonce, built on oracle.space's Neumann
+    Laplacian), and the slab block assembled from its Kronecker form equals
+    the one built column by column."""
+    from oracle import allatonce
+    levels, _ = mg.hierarchy(prob, min_coarse=10 ** 9)
+    lev = levels[0]
+    rng = np.random.default_rng(6)
+    U = rng.standard_normal(lev.shape)
+    assert np.abs(lev.apply(U) - allatonce.apply(prob, U)).max() < 1e-12
+    assert np.abs(lev.slab_matrix_sparse().toarray() - lev.slab_matrix()).max() < 1e-12
+
+
+@pytest.mark.parametrize("prob", NEUMANN)
+def test_neumann_fixed_points_and_vcycle(prob):
+    """Smoother fixed point, exact slab solve and V-cycles on Neumann grids all
+    reach the stepper's solution."""
+    rng = np.random.default_rng(7)
+    ny, nx = si.grid_points(prob)
+    u0 = rng.standard_normal((ny, nx))
+    Ue = stepper.solve_linear(prob, u0)
+    levels, kinds = mg.hierarchy(prob, fft_coarse=0, min_coarse=16)
+    assert any("s" in k for k in kinds)
+    f = mg.rhs(levels, u0)
+    assert np.abs(levels[0].smooth(Ue, f, 0.8, 4) - Ue).max() < 1e-12
+    assert np.abs(levels[0].exact_solve(f) - Ue).max() < 1e-12
+    U, hist = mg.solve(prob, u0, rtol=1e-12, max_cycles=150, fft_coarse=0, min_coarse=16)
+    assert hist[-1] <= 1e-12
+    assert np.linalg.norm(U - Ue) <= 1e-10 * np.linalg.norm(Ue)
