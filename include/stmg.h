@@ -65,6 +65,8 @@ enum { STMG_REACT_LINEAR = 0, STMG_REACT_ALLEN_CAHN = 1 };
 enum { STMG_PREC_FP64 = 0, STMG_PREC_MIXED = 1 };
 enum { STMG_COARSEN_AUTO = 0, STMG_COARSEN_SPACE = 1, STMG_COARSEN_SPACETIME = 2,
        STMG_COARSEN_SMMG = 3 };
+enum { STMG_FORM_DG = 0, STMG_FORM_COLLOC = 1 };
+enum { STMG_SMOOTH_PBJ = 0, STMG_SMOOTH_SDC = 1 };
 
 /* The problem statement: Eq. (model) of Sec. 3 generalized to a diffusion
  * coefficient, 2D and periodic grids; uniform partitions of Sec. 3. */
@@ -110,11 +112,14 @@ typedef struct {
   size_t mem_budget;  /* adjoint: max bytes for the stored forward trajectory;
                          0 = unlimited (no checkpointing)                     */
   int32_t sdc;        /* 1: reserve workspace for stmg_sdc_sweep, 0 (default) */
-  int32_t autotune;   /* 1: at setup, time the launch shapes of the transfer
-                         kernels per level and keep the fastest (results are
-                         bitwise identical for every shape); choices are
-                         cached in the JSON file named by $STMG_TUNE_CACHE.
-                         0 (default): fixed shapes                            */
+  int32_t autotune;   /* 1: at setup (stmg_setup, stmg_batch_setup), time the
+                         launch shape of the restriction kernels (slabs per
+                         workgroup run) per level and keep the fastest
+                         (results are bitwise identical for every shape);
+                         choices are cached in the JSON file named by
+                         $STMG_TUNE_CACHE, keyed by level shape, M, precision
+                         and coarse smoother block.  0 (default): fixed
+                         shapes                                               */
   int32_t inner_cycles; /* mixed precision: FP32 V-cycles on each correction
                          equation per FP64 refinement step (at most, with
                          inner_adapt; exactly, in batches), 1..64, 5          */
@@ -150,6 +155,28 @@ typedef struct {
                          contraction per cycle says are needed to reach rtol
                          (at least 1); the stop test is unchanged.  0 = always
                          inner_cycles.  Ignored by batches.                    */
+  int32_t form;       /* the form of the all-at-once system whose residuals
+                         are reported and tested: STMG_FORM_DG (default), the
+                         DG form Eq. (st_system) of Sec. 3, or
+                         STMG_FORM_COLLOC, the collocation form of Sec. 2.1
+                         (Eq. collocation), whose residual is G r_DG per slab
+                         and grid point with G = Q diag(b)^-1 (the same
+                         solution; G l(0) = 1, so ||b|| = sqrt(M) ||u0||).
+                         Affects stmg_residual (r and its norm), rel_res and
+                         the stop tests of stmg_solve / stmg_vcycle on the
+                         forward problem; the correction equations, the
+                         smoother (invariant under G) and the adjoint stay in
+                         the DG form.  EUNSUPPORTED with krylov > 0; batches
+                         use the DG form.                                      */
+  int32_t smoother;   /* STMG_SMOOTH_PBJ (default): block-Jacobi over chunks of
+                         slabs with point-block M x M solves (Sec. 4.2);
+                         STMG_SMOOTH_SDC: on the finest level each smoothing
+                         step is one SDC sweep (the implicit-Euler
+                         preconditioned Richardson step of Sec. 2.1 and 4.1,
+                         all slabs at once, as stmg_sdc_sweep) on the
+                         collocation form; coarser levels keep block-Jacobi.
+                         FP64 linear problems without Krylov or time windows
+                         (EUNSUPPORTED otherwise)                              */
 } stmg_options;
 
 typedef struct {

@@ -141,3 +141,30 @@ def dense_solve(prob, u0, tol=1e-14, max_newton=50):
         J = Amat + g * (Rm * (3 * v ** 2 - 1)[None, :])
         v = v - np.linalg.solve(J, G)
     raise RuntimeError("dense Newton did not converge")
+
+
+def residual_colloc(prob, u0, U):
+    """Residual of the collocation form (Sec. 2.1, Eq. collocation), slab by
+    slab: r_n = 1 (x) u_{n-1} + dt (Q (x) I) F(U_n) - U_n with u_{n-1} the
+    previous slab's last stage (u0 for the first slab) and F(u) = nu Lap_h u -
+    lambda u, or nu Lap_h u + gamma (u - u^3) for Allen-Cahn.  Built from Q
+    and the spatial operator directly, not from the DG blocks."""
+    t = radau.tables(prob["M"])
+    Q, dt = t["Q"], prob["dt"]
+    D = space.laplacian(prob)
+    U = np.asarray(U, dtype=np.float64)
+    N, M = U.shape[0], U.shape[1]
+    n = D.shape[0]
+    V = U.reshape(N, M, n)
+    ac = prob.get("reaction", "linear") == "allen_cahn"
+    r = np.zeros_like(V)
+    prev = np.asarray(u0, dtype=np.float64).reshape(n)
+    for k in range(N):
+        F = np.array([prob["nu"] * (D @ V[k, j]) + (prob["gamma"] * (V[k, j] - V[k, j] ** 3) if ac
+                                                     else -prob.get("lambda", 0.0) * V[k, j])
+                      for j in range(M)])
+        for m in range(M):
+            r[k, m] = prev + dt * (Q[m] @ F) - V[k, m]
+        prev = V[k, M - 1]
+    return r.reshape(U.shape)
+

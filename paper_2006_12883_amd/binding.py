@@ -17,6 +17,8 @@ BC = {"periodic": 0, "neumann": 1}
 REACTION = {"linear": 0, "allen_cahn": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
 COARSEN = {"auto": 0, "space": 1, "spacetime": 2, "smmg": 3}
+FORM = {"dg": 0, "colloc": 1}
+SMOOTHER = {"pbj": 0, "sdc": 1}
 
 # every symbol the header declares
 EXPORTS = [
@@ -46,7 +48,8 @@ class Options(ctypes.Structure):
                 ("max_newton", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("sdc", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("inner_cycles", ctypes.c_int32),
                 ("fft_coarse", ctypes.c_int32), ("krylov", ctypes.c_int32),
-                ("krylov_left", ctypes.c_int32), ("inner_adapt", ctypes.c_int32)]
+                ("krylov_left", ctypes.c_int32), ("inner_adapt", ctypes.c_int32),
+                ("form", ctypes.c_int32), ("smoother", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -145,6 +148,10 @@ def make_options(**kw):
             v = PRECISION[v] if isinstance(v, str) else v
         if k == "coarsen":
             v = COARSEN[v] if isinstance(v, str) else v
+        if k == "form":
+            v = FORM[v] if isinstance(v, str) else v
+        if k == "smoother":
+            v = SMOOTHER[v] if isinstance(v, str) else v
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)

@@ -22,8 +22,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
+#include <map>
 #include <memory>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -240,6 +243,9 @@ struct stmg_batch {
   };
   std::vector<Phase> phases;
   std::vector<stmg::BItem> items;
+  // slabs per workgroup run of each problem's restriction to level l + 1
+  // (autotuned; 0 = the default)
+  std::vector<std::vector<int>> tune_S;
   int nparts = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -271,6 +277,8 @@ int batch_build(stmg_batch* b, int32_t n, const stmg_problem* probs, const stmg_
   b->opt.mem_budget = 0;
   b->opt.sdc = 0;
   b->opt.coarsen = STMG_COARSEN_AUTO;
+  b->opt.form = STMG_FORM_DG;
+  b->opt.smoother = STMG_SMOOTH_PBJ;
   b->S.clear();
   Plan pl;
   pl.base = ws;
@@ -317,6 +325,120 @@ int batch_build(stmg_batch* b, int32_t n, const stmg_problem* probs, const stmg_
   return STMG_OK;
 }
 
+// Work item of problem p's restriction from level l to l + 1 (space or time
+// kind) with S slabs per workgroup run (0: the default); the caller sets
+// blk0.  Returns the item's workgroup count.
+int restrict_item(stmg_batch* b, int p, int l, const std::vector<std::vector<const OpParams*>>& opp, int S,
+                  BItem* out) {
+  Solver& s = *b->S[p];
+  const int last = static_cast<int>(s.lv.size()) - 1;
+  Level& F = s.lv[l];
+  Level& C = s.lv[l + 1];
+  BItem x{};
+  x.prob = p;
+  x.M = s.prob.M;
+  x.op = opp[p][l];
+  x.opc = opp[p][l + 1];
+  x.U = F.A32;
+  x.f = F.f32;
+  x.fc = C.f32;
+  x.zs = (l + 1 < last) ? 1 : 0;
+  x.uc = x.zs ? C.A32 : nullptr;
+  x.cs = s.chunk_of(l + 1);
+  int spb = S > 0 ? S : s.transfer_slabs(l + 1);
+  if (spb % x.cs) spb = ((spb + x.cs - 1) / x.cs) * x.cs;
+  x.S = spb;
+  x.ncx = C.nx;
+  x.ncy = C.ny;
+  x.Nc = C.N;
+  if (F.kind & 1) {
+    // 16 x 16 coarse points per workgroup.  The tile shape is not tuned: it
+    // decides which fine residuals the single-point halo items compute and
+    // which the 2 x 2 blocks do, and the two code paths may round differently.
+    x.tiles_x = (C.nx + 15) / 16;
+    x.tiles = x.tiles_x * ((C.ny + 15) / 16);
+  } else {
+    x.tiles = (plane_threads(F.op) + kBlock - 1) / kBlock;
+  }
+  *out = x;
+  return x.tiles * ((C.N + spb - 1) / spb);
+}
+
+// Autotuner of the restriction launch shape (slabs per workgroup run, a
+// multiple of the coarse level's smoother block, so that the fused coarse
+// sweep stays possible; every choice gives bitwise identical results): per
+// (level shape, M, coarse chunk) each candidate is timed on one problem's own
+// level buffers, the fastest of three timed launches wins, and choices are
+// cached in $STMG_TUNE_CACHE under "batch_..." keys.
+int batch_autotune(stmg_batch* b, const std::vector<std::vector<const OpParams*>>& opp) {
+  b->tune_S.assign(b->n, {});
+  const char* path = std::getenv("STMG_TUNE_CACHE");
+  std::map<std::string, int> cache;
+  if (path) cache = tune_cache_read(path);
+  bool dirty = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_CHECK_B(hipEventCreate(&e0));
+  HIP_CHECK_B(hipEventCreate(&e1));
+  struct EvScope {
+    hipEvent_t a, b;
+    ~EvScope() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } ev_scope{e0, e1};
+  HIP_CHECK_B(hipMemsetAsync(b->d_done, 0, b->n * sizeof(int), b->own));
+  for (int p = 0; p < b->n; ++p) {
+    Solver& s = *b->S[p];
+    const int L = static_cast<int>(s.lv.size());
+    b->tune_S[p].assign(L, 0);
+    for (int l = 0; l + 1 < L; ++l) {
+      const Level& F = s.lv[l];
+      const Level& C = s.lv[l + 1];
+      const bool space = (F.kind & 1) != 0;
+      std::ostringstream k;
+      k << "batch_f32_M" << s.prob.M << "_" << F.nx << "x" << F.ny << "x" << F.N << "_k" << F.kind << "_c"
+        << s.chunk_of(l + 1) << (l + 2 < L ? "_zs" : "");
+      const std::string key = k.str();
+      auto hit = cache.find(key);
+      if (hit != cache.end() && hit->second > 0) {
+        b->tune_S[p][l] = hit->second;
+        continue;
+      }
+      const int cs = s.chunk_of(l + 1);
+      float best = 1e30f;
+      int best_S = cs;
+      {
+        for (int mult : {1, 2, 4, 8}) {
+          const int S = cs * mult;
+          if (S > 64 || (mult > 1 && S > C.N)) break;
+          BItem x{};
+          const int nb = restrict_item(b, p, l, opp, S, &x);
+          x.blk0 = 0;
+          x.nblocks = nb;
+          HIP_CHECK_B(hipMemcpyAsync(b->d_items, &x, sizeof(BItem), hipMemcpyHostToDevice, b->own));
+          float tot = 0.0f;
+          for (int rep = 0; rep < 4; ++rep) {
+            HIP_CHECK_B(hipEventRecord(e0, b->own));
+            if (space)
+              hipLaunchKernelGGL(k_b_restrict_s, dim3(nb), dim3(kBlock), 0, b->own, b->d_items, 1, b->d_done);
+            else
+              hipLaunchKernelGGL(k_b_restrict_t, dim3(nb), dim3(kBlock), 0, b->own, b->d_items, 1, b->d_done);
+            HIP_CHECK_B(hipGetLastError());
+            HIP_CHECK_B(hipEventRecord(e1, b->own));
+            HIP_CHECK_B(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIP_CHECK_B(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) tot += ms;  // the first launch warms up
+          }
+          if (tot < best) { best = tot; best_S = S; }
+        }
+      }
+      b->tune_S[p][l] = best_S;
+      cache[key] = best_S;
+      dirty = true;
+    }
+  }
+  if (path && dirty) tune_cache_write(path, cache);
+  return STMG_OK;
+}
+
 int batch_items(stmg_batch* b) {
   std::vector<OpParams> ops;
   std::vector<std::vector<const OpParams*>> opp(b->n);
@@ -326,6 +448,16 @@ int batch_items(stmg_batch* b) {
       ops.push_back(l.op);
     }
   HIP_CHECK_B(hipMemcpyAsync(b->d_ops, ops.data(), ops.size() * sizeof(OpParams), hipMemcpyHostToDevice, b->own));
+  if (b->opt.autotune) {
+    // the level buffers hold no data yet: zero the ones the candidates read
+    for (auto& sp : b->S)
+      for (auto& l : sp->lv) {
+        if (l.A32) HIP_CHECK_B(hipMemsetAsync(l.A32, 0, l.n * sizeof(float), b->own));
+        if (l.f32) HIP_CHECK_B(hipMemsetAsync(l.f32, 0, l.n * sizeof(float), b->own));
+      }
+    const int rc = batch_autotune(b, opp);
+    if (rc) return rc;
+  }
   std::vector<BItem>& it = b->items;
   it.clear();
   b->phases.clear();
@@ -400,27 +532,11 @@ int batch_items(stmg_batch* b) {
         Level& F = s.lv[l];
         Level& C = s.lv[l + 1];
         if ((kind == PH_DS) != ((F.kind & 1) != 0)) continue;
-        BItem x = blank(p, l);
-        x.opc = opp[p][l + 1];
-        x.U = F.A32;
-        x.f = F.f32;
-        x.fc = C.f32;
-        x.zs = (l + 1 < last) ? 1 : 0;
-        x.uc = x.zs ? C.A32 : nullptr;
-        x.cs = s.chunk_of(l + 1);
-        int spb = s.transfer_slabs(l + 1);
-        if (spb % x.cs) spb = ((spb + x.cs - 1) / x.cs) * x.cs;
-        x.S = spb;
-        x.ncx = C.nx;
-        x.ncy = C.ny;
-        x.Nc = C.N;
-        if (kind == PH_DS) {
-          x.tiles_x = (C.nx + 15) / 16;
-          x.tiles = x.tiles_x * ((C.ny + 15) / 16);
-        } else {
-          x.tiles = (plane_threads(F.op) + kBlock - 1) / kBlock;
-        }
-        add(x, x.tiles * ((C.N + spb - 1) / spb));
+        (void)C;
+        const bool tuned = !b->tune_S.empty() && l < static_cast<int>(b->tune_S[p].size());
+        BItem x{};
+        const int nb = restrict_item(b, p, l, opp, tuned ? b->tune_S[p][l] : 0, &x);
+        add(x, nb);
       }
       end();
     }

@@ -93,6 +93,8 @@ void stmg_default_options(stmg_options* o) {
   o->krylov = 0;
   o->krylov_left = 0;
   o->inner_adapt = 1;
+  o->form = STMG_FORM_DG;
+  o->smoother = STMG_SMOOTH_PBJ;
 }
 
 size_t stmg_workspace_bytes(const stmg_problem* prob, const stmg_options* opt) {

@@ -21,7 +21,7 @@ struct OpParams {
   int nx, ny;      // grid points of this level (ny = 1 in 1D)
   int N;           // slabs
   int bc;          // 0 periodic, 1 Neumann
-  int pad_;
+  int colloc;      // residual norms in the collocation form: ||G r|| per point, G = Q diag(b)^-1
   double cx, cy;   // nu / hx^2, nu / hy^2 (cy = 0 in 1D)
   double lam;      // constant linear reaction rate
   double gamma;    // Allen-Cahn intensity
@@ -31,6 +31,7 @@ struct OpParams {
   double cin[kMaxM];
   double cout[kMaxM];
   double Binv[kMaxM * kMaxM];  // (K + diag(db) (2cx + 2cy + lam))^{-1}
+  double G[kMaxM * kMaxM];     // Q diag(b)^-1 (collocation form of a DG residual), used when colloc
 };
 
 // Reaction modes of the operator kernels.

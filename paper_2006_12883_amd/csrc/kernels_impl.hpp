@@ -48,6 +48,25 @@ __device__ __forceinline__ double block_sum(double v) {
   return t;
 }
 
+// Adds one point's contribution to ||r||^2 (FP64) in the form of the level: the
+// DG residual as computed, or its collocation form G r with G = Q diag(b)^-1
+// (the same solution; the residuals differ by this per-point factor).
+template <int M, typename T>
+__device__ __forceinline__ void ssq_add(const OpParams& p, const T r[M], double& ssq) {
+  if (p.colloc) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < M; ++j) v += p.G[i * M + j] * (double)r[j];
+      ssq += v * v;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < M; ++i) ssq += (double)r[i] * (double)r[i];
+  }
+}
+
 // Constants of a level converted to the arithmetic type T.
 template <int M, typename T>
 struct Consts {
@@ -202,10 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth(const OpParams p, const Sweep
         for (int m = 0; m < M; ++m) u[m] = lap[m] = T(0);
       }
       point_residual<M, T, REACT>(c, u, lap, a.coef, a.f, base, P, q, prev, r);
-      if (a.part) {
-#pragma unroll
-        for (int i = 0; i < M; ++i) ssq += (double)r[i] * (double)r[i];
-      }
+      if (a.part) ssq_add<M, T>(p, r, ssq);
       if (n > n0) {
 #pragma unroll
         for (int i = 0; i < M; ++i) r[i] += c.cin[i] * dprev;
@@ -284,9 +300,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(const OpParams p, const Swe
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         if (out) out[base + (size_t)i * P + q] = (TO)r[i];
-        ssq += (double)r[i] * (double)r[i];
         np += c.cout[i] * u[i];
       }
+      ssq_add<M, T>(p, r, ssq);
       prev = np;
     }
   }
@@ -950,10 +966,7 @@ __device__ __forceinline__ void smooth_blk_body(const OpParams& p, const SweepPt
       for (int k = 0; k < NP; ++k) {
         T r[M], d[M];
         resid_vals<M, T, REACT>(c, u[k], lap[k], fv[k], cv[k], prev[k], r);
-        if (a.part) {
-#pragma unroll
-          for (int i = 0; i < M; ++i) ssq += (double)r[i] * (double)r[i];
-        }
+        if (a.part) ssq_add<M, T>(p, r, ssq);
         if (n > n0) {
 #pragma unroll
           for (int i = 0; i < M; ++i) r[i] += c.cin[i] * dprev[k];
@@ -1040,10 +1053,10 @@ __device__ __forceinline__ void residual_blk_body(const OpParams& p, const Sweep
         T np = T(0);
 #pragma unroll
         for (int i = 0; i < M; ++i) {
-          ssq += (double)r[i] * (double)r[i];
           o[k][i] = (TO)r[i];
           np += c.cout[i] * u[k][i];
         }
+        ssq_add<M, T>(p, r, ssq);
         prev[k] = np;
       }
       if (out) store_own<M, TO, BY>(out, base, P, nx, b, o);
@@ -1188,10 +1201,10 @@ __device__ __forceinline__ void refine_blk_body(const OpParams& p, const SweepPt
         double np = 0.0;
 #pragma unroll
         for (int i = 0; i < M; ++i) {
-          ssq += r[i] * r[i];
           rr[k][i] = (float)r[i];
           np += c.cout[i] * u[k][i];
         }
+        ssq_add<M, double>(p, r, ssq);
         prev[k] = np;
       }
       if (a.out) store_own<M, double, BY>(static_cast<double*>(a.out), base, P, nx, b, u);
@@ -2080,10 +2093,7 @@ __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const Swe
       for (int k = 0; k < NP; ++k) {
         T r[M], d[M];
         resid_vals<M, T, REACT>(c, u[k], lap[k], fv[k], cv[k], prev[k], r);
-        if (a.part) {
-#pragma unroll
-          for (int i = 0; i < M; ++i) ssq += (double)r[i] * (double)r[i];
-        }
+        if (a.part) ssq_add<M, T>(p, r, ssq);
         if (n > n0) {
 #pragma unroll
           for (int i = 0; i < M; ++i) r[i] += c.cin[i] * dprev[k];

@@ -91,6 +91,15 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     set_error("bad precision");
     return STMG_EINVAL;
   }
+  if (o->form != STMG_FORM_DG && o->form != STMG_FORM_COLLOC) { set_error("bad form"); return STMG_EINVAL; }
+  if (o->smoother != STMG_SMOOTH_PBJ && o->smoother != STMG_SMOOTH_SDC) {
+    set_error("bad smoother");
+    return STMG_EINVAL;
+  }
+  if (o->form == STMG_FORM_COLLOC && o->krylov > 0) {
+    set_error("collocation-form residuals with the Krylov method are not supported");
+    return STMG_EUNSUPPORTED;
+  }
   allen_cahn = p->reaction == STMG_REACT_ALLEN_CAHN;
   mixed = o->precision == STMG_PREC_MIXED;
   if (!radau_tables(p->M, &tab)) { set_error("Radau table construction failed"); return STMG_EINVAL; }
@@ -222,12 +231,23 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
       op.Binv[i] = static_cast<double>(B[i]);
       opT.Binv[i] = static_cast<double>(BT[i]);
     }
+    // collocation form of the residual norms (finest level, forward problem)
+    if (&l == &lv[0] && o->form == STMG_FORM_COLLOC) {
+      op.colloc = 1;
+      for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) op.G[i * M + j] = static_cast<double>(tab.Q[i][j] / tab.b[j]);
+    }
     l.op = op;
     l.opT = opT;
   }
   // SDC node solvers
   sdcn.clear();
-  if (o->sdc && !decoupled) {
+  if (o->smoother == STMG_SMOOTH_SDC &&
+      (allen_cahn || o->precision != STMG_PREC_FP64 || o->krylov > 0 || batch_member || decoupled)) {
+    set_error("SDC smoother: FP64 linear problems without the Krylov method only");
+    return STMG_EUNSUPPORTED;
+  }
+  if ((o->sdc || o->smoother == STMG_SMOOTH_SDC) && !decoupled) {
     if (allen_cahn) { set_error("SDC sweeps: linear problems only"); return STMG_EUNSUPPORTED; }
     for (int m = 0; m < M; ++m) {
       const long double dc = tab.c[m] - (m > 0 ? tab.c[m - 1] : 0.0L);
@@ -241,6 +261,8 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
       so.krylov = 0;
       so.precision = STMG_PREC_FP64;
       so.coarsen = STMG_COARSEN_SPACE;
+      so.smoother = STMG_SMOOTH_PBJ;
+      so.form = STMG_FORM_DG;
       std::unique_ptr<Solver> sub(new Solver());
       sub->decoupled = true;
       int rc = sub->build(&sp, &so);
@@ -305,6 +327,7 @@ size_t Solver::plan(char* ws) {
     Ainv = pl.take<double>(K * K);
     AinvT = pl.take<double>(K * K);
     lw = pl.take<double>(kMaxM);
+    form_G = pl.take<double>(kMaxM * kMaxM);
     return pl.off + 256;
   }
   if (win) {
@@ -399,6 +422,7 @@ size_t Solver::plan(char* ws) {
     if (d * sizeof(double) <= kCoarseInvMaxBytes) coarse_inv = pl.take<double>(d);
   }
   lw = pl.take<double>(kMaxM);
+  form_G = pl.take<double>(kMaxM * kMaxM);
   if (!sdcn.empty()) {
     for (auto& sub : sdcn) {
       const size_t b = sub->plan(nullptr);
@@ -568,6 +592,7 @@ int Solver::upload() {
   double w[kMaxM] = {0};
   for (int i = 0; i < M; ++i) w[i] = static_cast<double>(tab.l0[i]);
   HIP_CHECK(hipMemcpyAsync(lw, w, sizeof(w), hipMemcpyHostToDevice, stream));
+  HIP_CHECK(hipMemcpyAsync(form_G, lv[0].op.G, sizeof(lv[0].op.G), hipMemcpyHostToDevice, stream));
   double G[kMaxM * kMaxM] = {0};
   if (!sdcn.empty()) {
     // collocation residual = Q diag(b)^{-1} (DG residual), per slab and point
@@ -700,6 +725,34 @@ hipError_t Solver::vcycle(int l, bool adj, int react, T* cur, T* oth, const T* f
     *res = cur;
     return hipSuccess;
   }
+  if constexpr (sizeof(T) == 8) {
+    if (l == 0 && opt.smoother == STMG_SMOOTH_SDC && !sdcn.empty()) {
+      // Finest level smoothed by SDC sweeps (in place, right-hand side from
+      // u0), unfused transfers; the coarser levels are as below.
+      if (zero) HIP_TRY(hipMemsetAsync(cur, 0, lv[0].n * sizeof(double), stream));
+      for (int s = skip_pre; s < opt.nu_pre; ++s)
+        if (sdc_core(u0, cur, 1) != STMG_OK) return hipErrorLaunchFailure;
+      Level& C = lv[1];
+      const bool want = fuse && l + 1 < last;
+      bool smoothed = false;
+      HIP_TRY(restrict_residual<double>(0, adj, react, cur, f, u0, C.f64, want ? C.A64 : nullptr, &smoothed));
+      if (gate0) {
+        bool stop = false;
+        HIP_TRY(gate0(&stop));
+        if (stop) {
+          *res = nullptr;
+          return hipSuccess;
+        }
+      }
+      double* ec = nullptr;
+      HIP_TRY(vcycle<double>(1, adj, react, C.A64, C.B64, C.f64, nullptr, !smoothed, &ec, smoothed ? 1 : 0));
+      HIP_TRY(prolong<double>(0, cur, ec, cur));
+      for (int s = 0; s < opt.nu_post; ++s)
+        if (sdc_core(u0, cur, 1) != STMG_OK) return hipErrorLaunchFailure;
+      *res = cur;
+      return hipSuccess;
+    }
+  }
   for (int s = skip_pre; s < opt.nu_pre; ++s) {
     HIP_TRY(smooth<T>(l, adj, react, zero ? nullptr : cur, f, u0, oth));
     std::swap(cur, oth);
@@ -789,8 +842,16 @@ double Solver::norm_u0_b(const double* u0) {
   if (launch_sum_partials(part, np, scal + 1, stream) != hipSuccess) return -1.0;
   double s = 0.0;
   if (read_scalar(scal + 1, &s) != STMG_OK) return -1.0;
+  // collocation form: b_{0,i} = (G l(0))_i u0 with G = Q diag(b)^-1
   long double w = 0.0L;
-  for (int i = 0; i < prob.M; ++i) w += tab.l0[i] * tab.l0[i];
+  for (int i = 0; i < prob.M; ++i) {
+    long double v = tab.l0[i];
+    if (L.op.colloc) {
+      v = 0.0L;
+      for (int j = 0; j < prob.M; ++j) v += tab.Q[i][j] / tab.b[j] * tab.l0[j];
+    }
+    w += v * v;
+  }
   return std::sqrt(static_cast<double>(w) * s);
 }
 
@@ -807,7 +868,7 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
   // ||f - A U_k|| of the incoming iterate U_k, which stays untouched in `U`
   // (the sweep writes the ping-pong partner), so the stop test costs no extra
   // pass over the data.
-  const bool fused = !mixed && opt.nu_pre >= 1;
+  const bool fused = !mixed && opt.nu_pre >= 1 && opt.smoother == STMG_SMOOTH_PBJ;
   // Mixed precision on the register-blocked layout: one fused sweep per
   // refinement step forms U' = U + e, its FP64 residual and norm, the FP32
   // right-hand side and the first FP32 smoothing sweep (k_refine_blk); the
@@ -1316,6 +1377,13 @@ int Solver::vcycle_user(const double* u0, double* U, double* h_rel) {
     double nb = 1.0;
     if (lin) {
       nb = norm_u0_b(u0);
+    } else if (L0.op.colloc) {
+      // ||f|| in the collocation form: the residual of a zero iterate
+      HIP_CHECK(residual64<double>(false, REACT_COEF, nullptr, f, nullptr, nullptr, scal + 2));
+      double f2 = 0.0;
+      rc = read_scalar(scal + 2, &f2);
+      if (rc) return rc;
+      nb = std::sqrt(f2);
     } else {
       int np = 0;
       HIP_CHECK(launch_sumsq(L0.f64, L0.n, part, &np, stream));
@@ -1334,6 +1402,10 @@ int Solver::residual_user(const double* u0, const double* U, double* r, double* 
   if (win) { set_error("stmg_residual: not available on a windowed handle"); return STMG_EUNSUPPORTED; }
   const int react = allen_cahn ? REACT_AC : REACT_CONST;
   HIP_CHECK(residual64<double>(false, react, U, nullptr, u0, r, scal));
+  if (r && lv[0].op.colloc) {
+    const Level& L0 = lv[0];
+    HIP_CHECK(launch_node_transform(r, L0.N, prob.M, L0.nx * L0.ny, form_G, stream));
+  }
   if (h_norm) {
     double r2 = 0.0;
     int rc = read_scalar(scal, &r2);
@@ -1473,6 +1545,20 @@ int Solver::sdc(const double* u0, double* U, int sweeps, double* h_rel) {
     set_error("stmg_sdc_sweep: set up the handle with options.sdc = 1 (linear problems)");
     return STMG_EUNSUPPORTED;
   }
+  const int rc = sdc_core(u0, U, sweeps);
+  if (rc) return rc;
+  if (h_rel) {
+    HIP_CHECK(residual64<double>(false, REACT_CONST, U, nullptr, u0, nullptr, scal));
+    double r2 = 0.0;
+    const int rc2 = read_scalar(scal, &r2);
+    if (rc2) return rc2;
+    const double nb = norm_u0_b(u0);
+    *h_rel = nb > 0.0 ? std::sqrt(r2) / nb : std::sqrt(r2);
+  }
+  return STMG_OK;
+}
+
+int Solver::sdc_core(const double* u0, double* U, int sweeps) {
   Level& L0 = lv[0];
   const int N = L0.N, M = prob.M, P = L0.nx * L0.ny;
   const size_t NP = static_cast<size_t>(N) * P;
@@ -1494,14 +1580,6 @@ int Solver::sdc(const double* u0, double* U, int sweeps, double* h_rel) {
       HIP_CHECK(launch_sdc_update(U, sdc_acc, S->delta64, N, M, L0.nx, L0.ny, L0.op.bc, L0.op.cx,
                                   L0.op.cy, L0.op.lam, sdc_w[m], m, stream));
     }
-  }
-  if (h_rel) {
-    HIP_CHECK(residual64<double>(false, REACT_CONST, U, nullptr, u0, nullptr, scal));
-    double r2 = 0.0;
-    int rc = read_scalar(scal, &r2);
-    if (rc) return rc;
-    const double nb = norm_u0_b(u0);
-    *h_rel = nb > 0.0 ? std::sqrt(r2) / nb : std::sqrt(r2);
   }
   return STMG_OK;
 }
@@ -1530,7 +1608,9 @@ std::string tune_key(const Solver& s, int l) {
   return k.str();
 }
 
-std::map<std::string, int> read_cache(const char* path) {
+}  // namespace
+
+std::map<std::string, int> tune_cache_read(const char* path) {
   std::map<std::string, int> m;
   std::ifstream in(path);
   if (!in) return m;
@@ -1551,7 +1631,7 @@ std::map<std::string, int> read_cache(const char* path) {
   return m;
 }
 
-void write_cache(const char* path, const std::map<std::string, int>& m) {
+void tune_cache_write(const char* path, const std::map<std::string, int>& m) {
   std::ofstream out(path);
   out << "{";
   bool first = true;
@@ -1561,14 +1641,13 @@ void write_cache(const char* path, const std::map<std::string, int>& m) {
   }
   out << "\n}\n";
 }
-}  // namespace
 
 int Solver::autotune() {
   if (win || lv.size() < 2) return STMG_OK;
   tuned.assign(lv.size(), 0);
   const char* path = std::getenv("STMG_TUNE_CACHE");
   std::map<std::string, int> cache;
-  if (path) cache = read_cache(path);
+  if (path) cache = tune_cache_read(path);
   bool dirty = false;
   hipEvent_t e0, e1;
   HIP_CHECK(hipEventCreate(&e0));
@@ -1616,7 +1695,7 @@ int Solver::autotune() {
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  if (path && dirty) write_cache(path, cache);
+  if (path && dirty) tune_cache_write(path, cache);
   return STMG_OK;
 }
 

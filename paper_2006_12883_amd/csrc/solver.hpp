@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <functional>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -14,6 +15,11 @@
 namespace stmg {
 
 void set_error(const std::string& msg);
+
+// Autotuner cache: a flat JSON object {"key": integer} (file named by
+// $STMG_TUNE_CACHE).
+std::map<std::string, int> tune_cache_read(const char* path);
+void tune_cache_write(const char* path, const std::map<std::string, int>& m);
 
 struct Level {
   int nx = 0, ny = 1;  // grid points
@@ -136,6 +142,7 @@ struct Solver {
   double* kdev = nullptr;
   HostScalar kh;
   double* lw = nullptr;       // M weights l(0) on the device (gradient of u0)
+  double* form_G = nullptr;   // Q diag(b)^-1 on the device (collocation-form residual output)
   // statistics of the last solve
   stmg_stats last{};
   // Stop test of the linear solve: the residual norm of the incoming iterate
@@ -232,6 +239,7 @@ struct Solver {
   int adjoint(const double* u0, const double* U, const double* gT, double* grad_u0,
               double* grad_nu, stmg_stats* st);
   int sdc(const double* u0, double* U, int sweeps, double* h_rel);
+  int sdc_core(const double* u0, double* U, int sweeps);  // the sweeps, no norm
 
   int newton_linearize(const double* U);  // coefficients on every level
   double norm_u0_b(const double* u0);     // ||b|| for b = l(0) (x) u0

@@ -83,3 +83,26 @@ def test_batch_inner_cycles(inner):
         assert st["cycles"] == inner * st["refinements"]
         ref = fourier.solve_linear_periodic(p, u0)
         assert rel_err(U.cpu().numpy(), ref) <= 1e-9, i
+
+
+def test_batch_autotune_bitwise_identical(tmp_path, monkeypatch):
+    """The batch autotuner (the restrictions' slab run per level shape) changes
+    launch shapes only: solutions are bitwise equal to the untuned batch, the
+    choices are cached under "batch_" keys, and a second tuned batch reads
+    them back."""
+    import json
+    from paper_2006_12883_amd import stmg
+    print("case batch autotune", flush=True)
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("STMG_TUNE_CACHE", str(cache))
+    probs = _small_batch() + [si.problem(2, 256, 3, 64, 1.0, nu=1e-2, lam=1.0)]
+    u0s = [T(si.batch_u0(p, i)) for i, p in enumerate(probs)]
+    Ua, sa = stmg.Batch(probs, device="cuda:0", rtol=1e-10).solve(u0s)
+    Ub, sb = stmg.Batch(probs, device="cuda:0", rtol=1e-10, autotune=1).solve(u0s)
+    keys = json.loads(cache.read_text())
+    assert any(k.startswith("batch_") for k in keys)
+    assert all(v >= 1 and v % 4 == 0 for k, v in keys.items() if k.startswith("batch_"))
+    Uc, sc = stmg.Batch(probs, device="cuda:0", rtol=1e-10, autotune=1).solve(u0s)
+    for i in range(len(probs)):
+        assert sa[i]["status"] == 0 and sb[i]["cycles"] == sa[i]["cycles"]
+        assert torch.equal(Ua[i], Ub[i]) and torch.equal(Ua[i], Uc[i]), i

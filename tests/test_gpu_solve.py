@@ -187,3 +187,53 @@ def test_overdamped_smoother_reports_divergence(prec):
     U, st = H(prob, precision=prec, omega=3.0, max_cycles=200).solve(T(u0), check=False)
     assert st["status"] == -5, st
     assert st["cycles"] < 100
+
+
+COLLOC = [si.problem(2, 32, 3, 16, 0.5, nu=1e-2, lam=1.0),
+          si.problem(1, 40, 4, 8, 0.2, nu=0.5, lam=0.2, bc="neumann"),
+          si.problem(2, 16, 2, 8, 0.5, nu=1e-3, gamma=1.0, reaction="allen_cahn")]
+
+
+@pytest.mark.parametrize("prob", COLLOC)
+def test_collocation_form_residual(prob):
+    """options.form = COLLOC: stmg_residual returns the collocation-form
+    residual (Sec. 2.1) and its norm, against the oracle's residual built
+    from Q directly."""
+    from oracle import allatonce
+    print("case colloc residual", prob["dim"], prob["M"], prob["bc"], flush=True)
+    rng = np.random.default_rng(13)
+    ny, nx = si.grid_points(prob)
+    u0 = 0.5 * rng.standard_normal((ny, nx))
+    U = 0.5 * rng.standard_normal((prob["N"], prob["M"], ny, nx))
+    ref = allatonce.residual_colloc(prob, u0, U)
+    h = H(prob, form="colloc")
+    r = torch.empty(U.shape, dtype=torch.float64, device="cuda:0")
+    nrm = h.residual(T(u0), T(U), r)
+    scale = max(1.0, float(np.abs(ref).max()))
+    assert float(np.abs(r.cpu().numpy() - ref).max()) <= 1e-12 * scale
+    assert abs(nrm - np.linalg.norm(ref)) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("prob", COLLOC)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_collocation_form_solve(prob, prec):
+    """Solving with the collocation-form stop test gives the same solution;
+    rel_res is ||r_col|| / ||b_col|| with ||b_col|| = sqrt(M) ||u0||."""
+    from oracle import allatonce
+    print("case colloc solve", prob["dim"], prob["M"], prec, flush=True)
+    ny, nx = si.grid_points(prob)
+    u0 = 0.5 * np.random.default_rng(14).standard_normal((ny, nx))
+    ref = stepper.solve(prob, u0)
+    ac = prob["reaction"] == "allen_cahn"
+    opt = dict(form="colloc", precision=prec, newton_rtol=1e-12) if ac else \
+        dict(form="colloc", precision=prec, rtol=1e-12)
+    U, st = H(prob, **opt).solve(T(u0))
+    assert st["status"] == 0
+    Un = U.cpu().numpy()
+    lim = 1e-10 if prec == "fp64" else 1e-9
+    assert np.linalg.norm(Un - ref) <= lim * np.linalg.norm(ref)
+    rc = np.linalg.norm(allatonce.residual_colloc(prob, u0, Un)) / (np.sqrt(prob["M"]) * np.linalg.norm(u0))
+    # both norms of a residual at the rounding floor agree to a few per cent
+    assert rc <= 2e-12 and abs(st["rel_res"] - rc) <= 0.05 * rc + 1e-16, (rc, st["rel_res"])
+    with pytest.raises(Exception):
+        H(prob, form="colloc", krylov=4)

@@ -128,3 +128,27 @@ def test_smoother_is_dense_chunk_block_jacobi(chunk, dim):
     ref = _smooth_dense(prob, lev, f, U, 0.8, chunk)
     assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
     assert np.abs(got - U).max() > 1e-2
+
+
+@pytest.mark.parametrize("prob", [si.problem(1, 12, 3, 4, 0.3, nu=0.5, lam=0.4),
+                                  si.problem(2, 6, 2, 3, 0.5, nu=0.05, lam=1.0, bc="neumann"),
+                                  si.problem(2, 6, 4, 3, 0.5, nu=0.01, gamma=1.0, reaction="allen_cahn")])
+def test_collocation_residual(prob):
+    """The collocation-form residual (built from Q) vanishes at the stepper's
+    solution and equals Q diag(b)^-1 applied per slab and point to the DG
+    residual (built from the integral definitions of K_q, M_q, J_q): the two
+    forms have the same solution and residuals that differ by this factor."""
+    from oracle import stepper
+    rng = np.random.default_rng(12)
+    ny, nx = si.grid_points(prob)
+    u0 = 0.5 * rng.standard_normal((ny, nx))
+    U = 0.5 * rng.standard_normal((prob["N"], prob["M"], ny, nx))
+    t = radau.tables(prob["M"])
+    G = t["Q"] / t["b"][None, :]
+    rdg = allatonce.residual(prob, u0, U)
+    rc = allatonce.residual_colloc(prob, u0, U)
+    assert np.abs(rc - np.einsum("ij,njyx->niyx", G, rdg)).max() < 1e-12 * max(1.0, np.abs(rc).max())
+    # G l(0) = 1: the collocation right-hand side is 1 (x) u0
+    assert np.abs(G @ t["l0"] - 1.0).max() < 1e-13
+    Ue = stepper.solve(prob, u0)
+    assert np.abs(allatonce.residual_colloc(prob, u0, Ue)).max() < 1e-12
