@@ -435,13 +435,20 @@ def _extra_hierarchies(dev):
     out = {}
     # the paper's three hierarchies (Sec. 5.2) on the 256^2 workload, FP64 to
     # 1e-10: SMG (space only), STMG (space and time at once), SMMG (space and
-    # nodes); AUTO semi-coarsening is the headline solve
+    # nodes); AUTO semi-coarsening is the headline solve.  SMG also with
+    # Galerkin coarse levels R A P (Sec. 4.2), on the default hierarchy and on
+    # one run down to the smallest coarse grid, each beside the rediscretized
+    # one.
     prob = si.config("rd2d")
     u0 = torch.as_tensor(si.initial("rd2d", prob)).to(dev)
     dof = float(prob["N"] * prob["M"] * 256 * 256)
     variants = {}
-    for name in ("auto", "space", "spacetime", "smmg"):
-        h = stmg.Handle(prob, device=dev, coarsen=name, rtol=1e-10, max_cycles=100)
+    runs = [("auto", {}), ("space", {}), ("spacetime", {}), ("smmg", {}),
+            ("space_galerkin", dict(coarse_op="galerkin")),
+            ("space_deep", dict(fft_coarse=0)),
+            ("space_galerkin_deep", dict(fft_coarse=0, coarse_op="galerkin"))]
+    for name, extra in runs:
+        h = stmg.Handle(prob, device=dev, coarsen=name.split("_")[0], rtol=1e-10, max_cycles=100, **extra)
         U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
         h.solve(u0, U, check=False)
         U.zero_()

@@ -67,6 +67,7 @@ enum { STMG_COARSEN_AUTO = 0, STMG_COARSEN_SPACE = 1, STMG_COARSEN_SPACETIME = 2
        STMG_COARSEN_SMMG = 3 };
 enum { STMG_FORM_DG = 0, STMG_FORM_COLLOC = 1 };
 enum { STMG_SMOOTH_PBJ = 0, STMG_SMOOTH_SDC = 1 };
+enum { STMG_COARSE_REDISC = 0, STMG_COARSE_GALERKIN = 1 };
 
 /* The problem statement: Eq. (model) of Sec. 3 generalized to a diffusion
  * coefficient, 2D and periodic grids; uniform partitions of Sec. 3. */
@@ -177,6 +178,17 @@ typedef struct {
                          collocation form; coarser levels keep block-Jacobi.
                          FP64 linear problems without Krylov or time windows
                          (EUNSUPPORTED otherwise)                              */
+  int32_t coarse_op;  /* STMG_COARSE_REDISC (default): every coarse level
+                         rediscretizes the problem with its own h and dt;
+                         STMG_COARSE_GALERKIN: coarse levels A_{l+1} =
+                         R A_l P (Sec. 4.2), i.e. K_q (x) Ms + diag(dt b) (x)
+                         Ks on the slab blocks and -l(0) e_M^T (x) Ms below
+                         them, with 3 x 3 mass and stiffness stencils Ms, Ks
+                         (9 points in 2D).  Their point-block sweep uses
+                         the stencils' centres, damped by omega m_0 / sum|m|.
+                         Space coarsening only (coarsen = SPACE), periodic
+                         grids, linear reaction, Fourier coarsest solve
+                         (EUNSUPPORTED otherwise)                             */
 } stmg_options;
 
 typedef struct {

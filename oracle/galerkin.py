@@ -6,10 +6,10 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 Vectors are ordered [N][M][ny][nx] as everywhere in the oracle, so a
 transfer that coarsens time, nodes and space is the Kronecker product
-P = P_t (x) P_m (x) P_s of the one-dimensional factors of oracle.mg (1D
-grids):
+P = P_t (x) P_m (x) P_s of the one-dimensional factors of oracle.mg
+(periodic grids; in 2D P_s = P_y (x) P_x):
   space  P_s[2X, X] = 1, P_s[2X+1, X] = P_s[2X+1, X+1] = 1/2 (periodic),
-         R_s = P_s^T / 2;
+         R_s = P_s^T / 2^d;
   time   P_t[2J+1, J] = 1, P_t[2J, J] = P_t[2J, J-1] = 1/2 (J > 0),
          R_t = P_t^T;
   nodes  P_m = the Lagrange node prolongation, R_m = P_m^T.
@@ -44,10 +44,17 @@ def _time_p(Nc):
 
 
 def transfers(fine, coarse, kind):
-    """(P, R) between two consecutive 1D levels of oracle.mg.hierarchy."""
-    assert fine.dim == 1
-    Ps = _space_p(coarse.nx) if "s" in kind else sp.identity(fine.nx, format="csr")
-    Rs = 0.5 * Ps.T if "s" in kind else Ps
+    """(P, R) between two consecutive levels of oracle.mg.hierarchy (periodic)."""
+    assert fine.bc == "periodic"
+    P1 = fine.nx * fine.ny
+    if "s" in kind:
+        Ps = _space_p(coarse.nx)
+        if fine.dim == 2:
+            Ps = sp.kron(_space_p(coarse.ny), Ps, format="csr")
+        Rs = (0.5 ** fine.dim) * Ps.T
+    else:
+        Ps = sp.identity(P1, format="csr")
+        Rs = Ps
     Pt = _time_p(coarse.N) if "t" in kind else sp.identity(fine.N, format="csr")
     Pm = sp.csr_matrix(fine.Pm) if "m" in kind else sp.identity(fine.M, format="csr")
     P = sp.kron(sp.kron(Pt, Pm), Ps, format="csr")
@@ -87,3 +94,73 @@ def vcycle(As, Ps, Rs, smoothers, coarse, x, f, l=0):
 def exact_coarse(A):
     lu = spla.splu(sp.csc_matrix(A))
     return lu.solve
+
+
+def point_block_smooth(A, shape, U, f, omega, chunk):
+    """One sweep of the block-Jacobi smoother over chunks of `chunk` slabs on
+    an assembled level matrix A (vectors [N][M][P]): r = f - A U; inside a
+    chunk, forward substitution with the point-diagonal parts of the slab
+    blocks, d_n(x) = B_n(x)^-1 (r_n(x) - [n not first in chunk] C_n(x)
+    d_{n-1}(x)) with B_n(x) = A[(n, :, x), (n, :, x)] and C_n(x) =
+    A[(n, :, x), (n-1, :, x)] (M x M each); U' = U + omega d.  On a
+    rediscretized level B = K_q + dt diag(b) (2 nu/hx^2 + 2 nu/hy^2 + lam) and
+    C = -l(0) e_M^T, which is the smoother of oracle.mg; on a Galerkin level
+    the mass stencil's centre weight enters both."""
+    N, M = shape[0], shape[1]
+    P = int(np.prod(shape[2:]))
+    A = sp.csr_matrix(A)
+    u = np.asarray(U, dtype=np.float64).reshape(-1)
+    r = (np.asarray(f, dtype=np.float64).reshape(-1) - A @ u).reshape(N, M, P)
+    d = np.zeros((N, M, P))
+    idx = lambda n, x: n * M * P + np.arange(M) * P + x
+    for n in range(N):
+        for x in range(P):
+            rows = idx(n, x)
+            B = A[rows][:, rows].toarray()
+            rhs = r[n, :, x].copy()
+            if n % chunk != 0:
+                C = A[rows][:, idx(n - 1, x)].toarray()
+                rhs -= C @ d[n - 1, :, x]
+            d[n, :, x] = np.linalg.solve(B, rhs)
+    return (u + omega * d.reshape(-1)).reshape(shape)
+
+
+def damping(A, shape, omega):
+    """Damping of the point-block sweep on a level matrix (N >= 2 slabs):
+    omega m_0 / sum_x |m_x|, with m the mass stencil read off the coupling
+    block to the previous slab, -l(0) e_M^T (x) Ms (row: slab 1, node 0,
+    point 0).  The point block keeps only m_0, so a spatially smooth error
+    sees the step omega sum|m| / m_0; the factor gives it the step omega of a
+    level with identity mass (a rediscretized level, where the result is
+    omega itself).  The centre entry and the row sum are those of the stencil
+    on any periodic grid of two or more points."""
+    N, M = shape[0], shape[1]
+    P = int(np.prod(shape[2:]))
+    assert N >= 2
+    row = sp.csr_matrix(A)[M * P].toarray().ravel()
+    c = row[(M - 1) * P:M * P]          # slab 0, node M-1, every point
+    return omega * abs(c[0]) / np.abs(c).sum()
+
+
+def space_stencils(A, shape):
+    """Couplings of a translation-invariant level matrix (periodic grid, at
+    least two slabs) read off one row block: diag[i, j, dy+1, dx+1] couples
+    unknown (slab 1, node i, point (0, 0)) to (slab 1, node j, point (dy, dx))
+    and sub[...] to the same point of slab 0.  Couplings beyond the 3 x 3
+    neighbourhood are not returned (the tests check the row sums)."""
+    N, M, ny, nx = shape
+    A = sp.csr_matrix(A)
+    P = nx * ny
+    diag = np.zeros((M, M, 3, 3))
+    sub = np.zeros((M, M, 3, 3))
+    n = 1
+    for i in range(M):
+        row = A[n * M * P + i * P + 0]
+        for j in range(M):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    x, y = dx % nx, dy % ny
+                    diag[i, j, dy + 1, dx + 1] = row[0, n * M * P + j * P + y * nx + x]
+                    sub[i, j, dy + 1, dx + 1] = row[0, (n - 1) * M * P + j * P + y * nx + x]
+    return diag, sub
+

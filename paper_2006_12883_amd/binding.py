@@ -19,6 +19,7 @@ PRECISION = {"fp64": 0, "mixed": 1}
 COARSEN = {"auto": 0, "space": 1, "spacetime": 2, "smmg": 3}
 FORM = {"dg": 0, "colloc": 1}
 SMOOTHER = {"pbj": 0, "sdc": 1}
+COARSE_OP = {"redisc": 0, "galerkin": 1}
 
 # every symbol the header declares
 EXPORTS = [
@@ -49,7 +50,7 @@ class Options(ctypes.Structure):
                 ("autotune", ctypes.c_int32), ("inner_cycles", ctypes.c_int32),
                 ("fft_coarse", ctypes.c_int32), ("krylov", ctypes.c_int32),
                 ("krylov_left", ctypes.c_int32), ("inner_adapt", ctypes.c_int32),
-                ("form", ctypes.c_int32), ("smoother", ctypes.c_int32)]
+                ("form", ctypes.c_int32), ("smoother", ctypes.c_int32), ("coarse_op", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -152,6 +153,8 @@ def make_options(**kw):
             v = FORM[v] if isinstance(v, str) else v
         if k == "smoother":
             v = SMOOTHER[v] if isinstance(v, str) else v
+        if k == "coarse_op":
+            v = COARSE_OP[v] if isinstance(v, str) else v
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)

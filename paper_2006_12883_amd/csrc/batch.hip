@@ -279,6 +279,7 @@ int batch_build(stmg_batch* b, int32_t n, const stmg_problem* probs, const stmg_
   b->opt.coarsen = STMG_COARSEN_AUTO;
   b->opt.form = STMG_FORM_DG;
   b->opt.smoother = STMG_SMOOTH_PBJ;
+  b->opt.coarse_op = STMG_COARSE_REDISC;
   b->S.clear();
   Plan pl;
   pl.base = ws;

@@ -95,6 +95,7 @@ void stmg_default_options(stmg_options* o) {
   o->inner_adapt = 1;
   o->form = STMG_FORM_DG;
   o->smoother = STMG_SMOOTH_PBJ;
+  o->coarse_op = STMG_COARSE_REDISC;
 }
 
 size_t stmg_workspace_bytes(const stmg_problem* prob, const stmg_options* opt) {

@@ -283,7 +283,8 @@ template <int M>
 __global__ __launch_bounds__(kFftBlock) void k_fft_modes_lds(int P, int N, int MB, double* __restrict__ F,
                                                              const double* __restrict__ u0F,
                                                              const double* __restrict__ Sinv,
-                                                             const OpParams p) {
+                                                             const OpParams p,
+                                                             const double* __restrict__ fscale) {
   __shared__ double L[kFftLds / sizeof(double)];
   const int q0 = blockIdx.x * MB;
   const int mb = min(MB, P - q0);
@@ -300,8 +301,9 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_lds(int P, int N, int M
       if (i < tot) {
         const int nm = i / mb, qq = i - nm * mb;
         const size_t at = 2 * ((size_t)nm * P + q0 + qq);
-        re[u] = F[at];
-        im[u] = F[at + 1];
+        const double sc = fscale ? fscale[q0 + qq] : 1.0;
+        re[u] = sc * F[at];
+        im[u] = sc * F[at + 1];
       }
     }
 #pragma unroll
@@ -736,7 +738,8 @@ template <int M>
 __global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, double* __restrict__ F,
                                                                const double* __restrict__ u0F,
                                                                const double* __restrict__ Sinv,
-                                                               const OpParams p) {
+                                                               const OpParams p,
+                                                               const double* __restrict__ fscale) {
   __shared__ double Sr[kChunkC][kChunkQ], Si[kChunkC][kChunkQ], Bp[kChunkC][kChunkQ];
   const int qq = threadIdx.x % kChunkQ, ch = threadIdx.x / kChunkQ;
   const int q = blockIdx.x * kChunkQ + qq;
@@ -764,6 +767,7 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, dou
     dv[k] = dk;
   }
   double2* Fc = reinterpret_cast<double2*>(F);
+  const double fsc = (fscale && act) ? fscale[q] : 1.0;
   constexpr int G = ChunkG<M>::G;
   const bool cached = n1 - n0 <= G;
   double2 v[G][M];
@@ -774,8 +778,11 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, dou
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int m = 0; m < M; ++m)
+        for (int m = 0; m < M; ++m) {
           v[g][m] = g0 + g < n1 ? Fc[((size_t)(g0 + g) * M + m) * P + q] : make_double2(0.0, 0.0);
+          v[g][m].x *= fsc;
+          v[g][m].y *= fsc;
+        }
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         if (g0 + g < n1) {
@@ -820,8 +827,11 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, dou
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
-          for (int m = 0; m < M; ++m)
+          for (int m = 0; m < M; ++m) {
             v[g][m] = g0 + g < n1 ? Fc[((size_t)(g0 + g) * M + m) * P + q] : make_double2(0.0, 0.0);
+            v[g][m].x *= fsc;
+            v[g][m].y *= fsc;
+          }
       }
 #pragma unroll
       for (int g = 0; g < G; ++g) {
@@ -851,7 +861,7 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, dou
 
 template <typename T>
 hipError_t launch_fft_coarse(const OpParams& p, const double* Sinv, const double* tw, double* work,
-                             const T* f, const double* u0, T* U, hipStream_t s) {
+                             const T* f, const double* u0, T* U, hipStream_t s, const double* fscale) {
   const int P = p.nx * p.ny;
   const bool reg = fft_reg_plane(p.nx, p.ny);
   if ((!reg && P > kFftMaxPlane) || p.M < 1 || p.M > kMaxM) return hipErrorInvalidValue;
@@ -887,13 +897,14 @@ hipError_t launch_fft_coarse(const OpParams& p, const double* Sinv, const double
     const int gb = (PF + MB - 1) / MB;
 #define L(MM)                                                                                        \
   hipLaunchKernelGGL((k_fft_modes_lds<MM>), dim3(gb), dim3(kFftBlock), 0, s, PF, p.N, MB, work, u0F, \
-                     Sinv, p)
+                     Sinv, p, fscale)
     STMG_DISPATCH_M_FFT(L)
 #undef L
   } else {
     const int gb = (PF + kChunkQ - 1) / kChunkQ;
 #define L(MM)                                                                                           \
-  hipLaunchKernelGGL((k_fft_modes_chunk<MM>), dim3(gb), dim3(kFftBlock), 0, s, PF, p.N, work, u0F, Sinv, p)
+  hipLaunchKernelGGL((k_fft_modes_chunk<MM>), dim3(gb), dim3(kFftBlock), 0, s, PF, p.N, work, u0F, Sinv, p, \
+                     fscale)
     STMG_DISPATCH_M_FFT(L)
 #undef L
   }
@@ -909,8 +920,8 @@ hipError_t launch_fft_coarse(const OpParams& p, const double* Sinv, const double
 }
 
 template hipError_t launch_fft_coarse<double>(const OpParams&, const double*, const double*, double*,
-                                              const double*, const double*, double*, hipStream_t);
+                                              const double*, const double*, double*, hipStream_t, const double*);
 template hipError_t launch_fft_coarse<float>(const OpParams&, const double*, const double*, double*,
-                                             const float*, const double*, float*, hipStream_t);
+                                             const float*, const double*, float*, hipStream_t, const double*);
 
 }  // namespace stmg

@@ -34,6 +34,17 @@ struct OpParams {
   double G[kMaxM * kMaxM];     // Q diag(b)^-1 (collocation form of a DG residual), used when colloc
 };
 
+// Spatial stencils of a Galerkin coarse level (periodic, 3 x 3, entry
+// [(dy + 1) * 3 + dx + 1] weighs u(x + dx, y + dy); 1D uses the middle row).
+// The level operator is
+//   (A U)_{n,i} = sum_j K[i][j] (Ms U_{n,j}) + db_i (Ks U_{n,i}) - cin_i (Ms (cout . U_{n-1}))
+// with Ms = R Ms_fine P and Ks = R Ks_fine P (the finest level: Ms = I,
+// Ks = -nu Lap_h + lambda).  OpParams.Binv holds (K m_0 + diag(db) k_0)^-1.
+struct Stencil9 {
+  double m[9];
+  double k[9];
+};
+
 // Reaction modes of the operator kernels.
 enum { REACT_CONST = 0, REACT_COEF = 1, REACT_AC = 2 };
 
@@ -102,6 +113,16 @@ hipError_t launch_prolong_smooth(const OpParams& p, int react, const SweepPtrs<T
                                  hipStream_t s);
 bool blocked_layout(const OpParams& p);
 
+// Galerkin levels: r = f - A U (U may be null: zero) into out, and one
+// block-Jacobi sweep over chunks of `chunk` slabs (point-diagonal parts of
+// the slab blocks: B = K m_0 + diag(db) k_0 and the coupling cin m_0 cout^T).
+template <typename T>
+hipError_t launch_residual9(const OpParams& p, const Stencil9& st, const T* U, const T* f, T* out,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_smooth9(const OpParams& p, const Stencil9& st, const T* U, const T* f, T* out, int chunk,
+                          hipStream_t s);
+
 // Exact solve of the block lower-bidiagonal coarsest system:
 // U_n = Ainv (f_n + cin (x) (cout . U_{n-1}))   (u0 enters slab 0 if given).
 template <typename T>
@@ -127,9 +148,12 @@ inline bool fft_reg_plane(int nx, int ny) {
 }
 // Planes the Fourier coarsest solve takes.
 inline bool fft_plane_ok(int nx, int ny) { return nx * ny <= kFftMaxPlane || fft_reg_plane(nx, ny); }
+// fscale (may be null): per-mode factor applied to the transformed right-hand
+// side (a Galerkin coarsest level: 1 / the mass stencil's symbol).
 template <typename T>
 hipError_t launch_fft_coarse(const OpParams& p, const double* Sinv, const double* tw, double* work,
-                             const T* f, const double* u0, T* U, hipStream_t s);
+                             const T* f, const double* u0, T* U, hipStream_t s,
+                             const double* fscale = nullptr);
 
 // Coarsest solve with a different slab matrix per slab: the K x K slab
 // matrices (K = M nx ny) are built from the per-DOF coefficient and factored

@@ -96,6 +96,16 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     set_error("bad smoother");
     return STMG_EINVAL;
   }
+  if (o->coarse_op != STMG_COARSE_REDISC && o->coarse_op != STMG_COARSE_GALERKIN) {
+    set_error("bad coarse_op");
+    return STMG_EINVAL;
+  }
+  if (o->coarse_op == STMG_COARSE_GALERKIN &&
+      (o->coarsen != STMG_COARSEN_SPACE || p->bc != STMG_BC_PERIODIC ||
+       p->reaction != STMG_REACT_LINEAR || batch_member)) {
+    set_error("Galerkin coarse operators: space coarsening of periodic linear problems only");
+    return STMG_EUNSUPPORTED;
+  }
   if (o->form == STMG_FORM_COLLOC && o->krylov > 0) {
     set_error("collocation-form residuals with the Krylov method are not supported");
     return STMG_EUNSUPPORTED;
@@ -240,6 +250,14 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     l.op = op;
     l.opT = opT;
   }
+  if (o->coarse_op == STMG_COARSE_GALERKIN && lv.size() > 1) {
+    if (!fft) {
+      set_error("Galerkin coarse operators need a Fourier-solvable coarsest plane");
+      return STMG_EUNSUPPORTED;
+    }
+    int rc = galerkin_levels();
+    if (rc) return rc;
+  }
   // SDC node solvers
   sdcn.clear();
   if (o->smoother == STMG_SMOOTH_SDC &&
@@ -366,6 +384,10 @@ size_t Solver::plan(char* ws) {
       if (i == 0 || !mixed) l.coef64 = pl.take<double>(l.n);
       if (mixed) l.coef32 = pl.take<float>(l.n);
     }
+    if (l.g9) {
+      l.g64 = pl.take<double>(l.n);
+      if (mixed) l.g32 = pl.take<float>(l.n);
+    }
   }
   delta64 = pl.take<double>(lv[0].n);
   if (opt.krylov > 0) {
@@ -396,6 +418,7 @@ size_t Solver::plan(char* ws) {
     fft_sinvT = pl.take<double>(Pc * c.M * c.M);
     fft_tw = pl.take<double>(2 * (static_cast<size_t>(c.nx) + c.ny));
     fft_work = pl.take<double>(2 * (static_cast<size_t>(c.N) * c.M + 1) * Pc);
+    if (c.g9) fft_mscale = pl.take<double>(Pc);
   } else {
     Ainv = pl.take<double>(K * K);
     AinvT = pl.take<double>(K * K);
@@ -438,6 +461,123 @@ size_t Solver::plan(char* ws) {
 // Kq + diag(dt b) (lambda_q + lambda) and of its transpose (the transposed
 // problem), lambda_q = cx (2 - 2 cos(2 pi kx / nx)) + cy (2 - 2 cos(2 pi ky / ny)),
 // in long double; the DFT twiddles cos, sin of 2 pi j / n.
+// Galerkin coarse levels (space coarsening, periodic): the 3 x 3 mass and
+// stiffness stencils of A_{l+1} = R A_l P, obtained by applying R S P to a
+// coarse delta on a small periodic grid (16 x 16 fine points; bilinear P,
+// full weighting R = P^T / 2^d) in long double, starting from Ms = I and
+// Ks = -nu Lap_h + lambda on the finest level; and the point-block inverses
+// (K m_0 + diag(db) k_0)^-1 of the smoother.
+int Solver::galerkin_levels() {
+  const bool twod = prob.dim == 2;
+  constexpr int nc = 8, nf = 16;
+  const int nyc = twod ? nc : 1, nyf = twod ? nf : 1;
+  long double ms[9] = {0}, ks[9] = {0};
+  ms[4] = 1.0L;
+  {
+    const Level& L0 = lv[0];
+    const long double cx = L0.op.cx, cy = L0.op.cy, lam = L0.op.lam;
+    ks[4] = 2.0L * cx + (twod ? 2.0L * cy : 0.0L) + lam;
+    ks[3] = ks[5] = -cx;
+    if (twod) ks[1] = ks[7] = -cy;
+  }
+  auto rap = [&](const long double* sf, long double* out) -> bool {
+    // coarse delta at (4, 4) (1D: x = 4), prolongated, stencil, restricted
+    std::vector<long double> ec(static_cast<size_t>(nc) * nyc, 0.0L), uf(static_cast<size_t>(nf) * nyf, 0.0L),
+        vf(uf.size(), 0.0L), rc(ec.size(), 0.0L);
+    const int X0 = 4, Y0 = twod ? 4 : 0;
+    ec[static_cast<size_t>(Y0) * nc + X0] = 1.0L;
+    auto cval = [&](int X, int Y) { return ec[static_cast<size_t>(((Y % nyc) + nyc) % nyc) * nc + ((X % nc) + nc) % nc]; };
+    for (int y = 0; y < nyf; ++y)
+      for (int x = 0; x < nf; ++x) {
+        // bilinear: average of the coarse points around fine (x, y)
+        const int X = x / 2, Y = twod ? y / 2 : 0;
+        const bool ox = x & 1, oy = twod && (y & 1);
+        long double v = cval(X, Y);
+        if (ox && oy) v = 0.25L * (cval(X, Y) + cval(X + 1, Y) + cval(X, Y + 1) + cval(X + 1, Y + 1));
+        else if (ox) v = 0.5L * (cval(X, Y) + cval(X + 1, Y));
+        else if (oy) v = 0.5L * (cval(X, Y) + cval(X, Y + 1));
+        uf[static_cast<size_t>(y) * nf + x] = v;
+      }
+    auto fval = [&](const std::vector<long double>& a, int x, int y) {
+      return a[static_cast<size_t>(((y % nyf) + nyf) % nyf) * nf + ((x % nf) + nf) % nf];
+    };
+    for (int y = 0; y < nyf; ++y)
+      for (int x = 0; x < nf; ++x) {
+        long double v = 0.0L;
+        for (int k = 0; k < 9; ++k) {
+          const int dx = k % 3 - 1, dy = k / 3 - 1;
+          if (!twod && dy != 0) continue;
+          v += sf[k] * fval(uf, x + dx, y + dy);
+        }
+        vf[static_cast<size_t>(y) * nf + x] = v;
+      }
+    const long double w1[3] = {0.25L, 0.5L, 0.25L};
+    for (int Y = 0; Y < nyc; ++Y)
+      for (int X = 0; X < nc; ++X) {
+        long double v = 0.0L;
+        for (int dy = -1; dy <= 1; ++dy) {
+          if (!twod && dy != 0) continue;
+          for (int dx = -1; dx <= 1; ++dx)
+            v += (twod ? w1[dy + 1] : 1.0L) * w1[dx + 1] * fval(vf, 2 * X + dx, 2 * Y + dy);
+        }
+        rc[static_cast<size_t>(Y) * nc + X] = v;
+      }
+    // (A delta_{X0})(X) = s[X0 - X]: read the 3 x 3 neighbourhood, require zeros outside
+    long double outside = 0.0L, total = 0.0L;
+    for (int Y = 0; Y < nyc; ++Y)
+      for (int X = 0; X < nc; ++X) {
+        const long double v = rc[static_cast<size_t>(Y) * nc + X];
+        const int dx = X0 - X, dy = Y0 - Y;
+        total += std::fabs(v);
+        if (std::abs(dx) <= 1 && std::abs(dy) <= 1) out[(dy + 1) * 3 + dx + 1] = v;
+        else outside += std::fabs(v);
+      }
+    return outside <= 1e-15L * total;
+  };
+  for (size_t l = 1; l < lv.size(); ++l) {
+    if (lv[l - 1].kind != 1) {
+      set_error("Galerkin coarse operators: space coarsening only");
+      return STMG_EUNSUPPORTED;
+    }
+    long double m2[9] = {0}, k2[9] = {0};
+    if (!rap(ms, m2) || !rap(ks, k2)) { set_error("Galerkin stencil is not 3 x 3"); return STMG_EINVAL; }
+    for (int k = 0; k < 9; ++k) {
+      ms[k] = m2[k];
+      ks[k] = k2[k];
+    }
+    Level& L = lv[l];
+    L.g9 = true;
+    for (int k = 0; k < 9; ++k) {
+      L.st.m[k] = static_cast<double>(ms[k]);
+      L.st.k[k] = static_cast<double>(ks[k]);
+    }
+    const RadauTables* lt = tables_for(L.M);
+    if (!lt) { set_error("Radau table construction failed"); return STMG_EINVAL; }
+    const int M = L.M;
+    std::vector<long double> B(static_cast<size_t>(M) * M), BT(static_cast<size_t>(M) * M);
+    for (int i = 0; i < M; ++i)
+      for (int j = 0; j < M; ++j) {
+        const long double d = (i == j) ? static_cast<long double>(L.dt) * lt->b[i] * ks[4] : 0.0L;
+        B[static_cast<size_t>(i) * M + j] = lt->Kq[i][j] * ms[4] + d;
+        BT[static_cast<size_t>(i) * M + j] = lt->Kq[j][i] * ms[4] + d;
+      }
+    if (!invert_ld(B, M) || !invert_ld(BT, M)) { set_error("singular Galerkin point block"); return STMG_EINVAL; }
+    for (int i = 0; i < M * M; ++i) {
+      L.op.Binv[i] = static_cast<double>(B[i]);
+      L.opT.Binv[i] = static_cast<double>(BT[i]);
+    }
+    // damping: the point block keeps only the mass stencil's centre m_0, so
+    // on a spatially smooth error the sweep's step is omega sum|m| / m_0;
+    // scaling omega by m_0 / sum|m| gives that mode the step omega of a
+    // rediscretized level (identity mass)
+    long double msum = 0.0L;
+    for (int k = 0; k < 9; ++k) msum += std::fabs(ms[k]);
+    L.op.omega = static_cast<double>(static_cast<long double>(L.op.omega) * ms[4] / msum);
+    L.opT.omega = L.op.omega;
+  }
+  return STMG_OK;
+}
+
 int Solver::upload_fft() {
   const Level& c = lv.back();
   const int M = c.M, nx = c.nx, ny = c.ny, P = nx * ny;
@@ -447,6 +587,7 @@ int Solver::upload_fft() {
   const long double twopi = 6.283185307179586476925286766559L;
   const OpParams& op = c.op;
   std::vector<double> S(static_cast<size_t>(P) * M * M), ST(static_cast<size_t>(P) * M * M);
+  std::vector<double> mscale(c.g9 ? static_cast<size_t>(P) : 0);
   std::vector<long double> a(static_cast<size_t>(M) * M);
   // storage order of the modes: row-major (ky, kx), or for the register
   // transforms the kept half kx = 0 .. nx/2 in compact columns c (kx < nx/2:
@@ -463,11 +604,30 @@ int Solver::upload_fft() {
       const int q = reg ? (kx < nx / 2 ? brev(kx, nx) / 2 : nx / 2) * ny + brev(ky, ny) : ky * nx + kx;
       long double lq = static_cast<long double>(op.cx) * (2.0L - 2.0L * std::cos(twopi * kx / nx));
       if (ny > 1) lq += static_cast<long double>(op.cy) * (2.0L - 2.0L * std::cos(twopi * ky / ny));
+      lq += static_cast<long double>(op.lam);
+      if (c.g9) {
+        // Galerkin level: multiplied through by the mass stencil's inverse
+        // (symbols real: the stencils are symmetric), the slab coupling is
+        // pointwise again, the spatial symbol is khat / mhat and the
+        // transformed right-hand side is scaled by 1 / mhat (fft_mscale)
+        long double mh = 0.0L, kh = 0.0L;
+        for (int k = 0; k < 9; ++k) {
+          const int dx = k % 3 - 1, dy = k / 3 - 1;
+          if (ny == 1 && dy != 0) continue;
+          const long double ph = twopi * (static_cast<long double>(kx) * dx / nx +
+                                          (ny > 1 ? static_cast<long double>(ky) * dy / ny : 0.0L));
+          mh += static_cast<long double>(c.st.m[k]) * std::cos(ph);
+          kh += static_cast<long double>(c.st.k[k]) * std::cos(ph);
+        }
+        if (!(mh > 0.0L)) { set_error("Galerkin mass symbol not positive"); return STMG_EINVAL; }
+        lq = kh / mh;
+        mscale[q] = static_cast<double>(1.0L / mh);
+      }
       for (int tr = 0; tr < 2; ++tr) {
         for (int i = 0; i < M; ++i)
           for (int j = 0; j < M; ++j) {
             long double v = tr ? tab.Kq[j][i] : tab.Kq[i][j];
-            if (i == j) v += c.dt * tab.b[i] * (lq + static_cast<long double>(op.lam));
+            if (i == j) v += c.dt * tab.b[i] * lq;
             a[static_cast<size_t>(i) * M + j] = v;
           }
         if (!invert_ld(a, M)) { set_error("singular Fourier mode matrix"); return STMG_EINVAL; }
@@ -487,6 +647,9 @@ int Solver::upload_fft() {
   HIP_CHECK(hipMemcpyAsync(fft_sinv, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, stream));
   HIP_CHECK(hipMemcpyAsync(fft_sinvT, ST.data(), ST.size() * sizeof(double), hipMemcpyHostToDevice, stream));
   HIP_CHECK(hipMemcpyAsync(fft_tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  if (c.g9)
+    HIP_CHECK(hipMemcpyAsync(fft_mscale, mscale.data(), mscale.size() * sizeof(double), hipMemcpyHostToDevice,
+                             stream));
   HIP_CHECK(hipStreamSynchronize(stream));  // host vectors go out of scope
   return STMG_OK;
 }
@@ -637,9 +800,17 @@ template <>
 float* nt_of<float>(const Level& l) { return l.nt32; }
 
 template <typename T>
+static T* g9_tmp(const Level& l);
+template <>
+double* g9_tmp<double>(const Level& l) { return l.g64; }
+template <>
+float* g9_tmp<float>(const Level& l) { return l.g32; }
+
+template <typename T>
 hipError_t Solver::smooth(int l, bool adj, int react, const T* U, const T* f, const double* u0,
                           T* out) {
   const Level& L = lv[l];
+  if (L.g9) return launch_smooth9<T>(adj ? L.opT : L.op, L.st, U, f, out, chunk_of(l), stream);
   SweepPtrs<T> a{U, f, u0, coef_of<T>(L), out, nullptr};
   return launch_smooth<T>(adj ? L.opT : L.op, react, a, chunk_of(l), stream);
 }
@@ -662,6 +833,17 @@ hipError_t Solver::restrict_residual(int l, bool adj, int react, const T* U, con
     return launch_node_transfer<T>(nt, L.M, fc, C.M, L.Rn, C.N, static_cast<size_t>(C.nx) * C.ny,
                                    stream);
   }
+  if (L.g9) {
+    // Galerkin level: its residual into the level's temporary, then the
+    // transfer of that vector (the restriction kernels with a zero iterate)
+    T* tmp = g9_tmp<T>(L);
+    HIP_TRY(launch_residual9<T>(adj ? L.opT : L.op, L.st, U, f, tmp, stream));
+    a = SweepPtrs<T>{nullptr, tmp, nullptr, nullptr, nullptr, nullptr};
+    uc = nullptr;
+  }
+  // a Galerkin coarse level smooths with its own operator: no fused first sweep
+  if (C.g9) uc = nullptr;
+  if (smoothed) *smoothed = false;
   if (uc && spb % cs != 0) spb = ((spb + cs - 1) / cs) * cs;
   return launch_restrict_residual<T>(adj ? L.opT : L.op, react, a, (L.kind & 1) != 0,
                                      (L.kind & 2) != 0, C.nx, C.ny, C.N, fc, spb, stream,
@@ -689,7 +871,9 @@ hipError_t Solver::coarse(bool adj, int react, const T* f, const double* u0, T* 
     if (coarse_inv && !adj) return launch_coarse_solve_slabs<T>(op, coarse_inv, f, u0, U, stream);
     return launch_coarse_solve_coef<T>(op, coef_of<T>(C), coarse_scratch, f, u0, U, stream);
   }
-  if (fft) return launch_fft_coarse<T>(op, adj ? fft_sinvT : fft_sinv, fft_tw, fft_work, f, u0, U, stream);
+  if (fft)
+    return launch_fft_coarse<T>(op, adj ? fft_sinvT : fft_sinv, fft_tw, fft_work, f, u0, U, stream,
+                                C.g9 ? fft_mscale : nullptr);
   if (scan.G) return launch_coarse_scan<T>(op, adj ? scanT : scan, f, u0, U, stream);
   return launch_coarse_solve<T>(op, adj ? AinvT : Ainv, f, u0, U, stream);
 }
@@ -704,6 +888,14 @@ hipError_t Solver::prolong_smooth(int l, bool adj, int react, const T* Uin, cons
     T* nt = nt_of<T>(L);
     HIP_TRY(launch_node_transfer<T>(ec, C.M, nt, L.M, L.Pn, C.N, static_cast<size_t>(C.nx) * C.ny, stream));
     ec = nt;
+  }
+  if (L.g9) {
+    // Galerkin level: U' = U_in + P e_c into the level's temporary, then the
+    // 9-point smoothing sweep
+    T* tmp = g9_tmp<T>(L);
+    HIP_TRY(launch_prolong<T>(L.op, (L.kind & 1) != 0, (L.kind & 2) != 0, C.nx, C.ny, C.N, ec, Uin, tmp,
+                              transfer_slabs(l), stream));
+    return launch_smooth9<T>(adj ? L.opT : L.op, L.st, tmp, f, out, chunk_of(l), stream);
   }
   if constexpr (sizeof(T) == 4) {
     if (l == 0 && up_in) {

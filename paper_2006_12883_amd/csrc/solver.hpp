@@ -40,6 +40,13 @@ struct Level {
   double *A64 = nullptr, *B64 = nullptr, *f64 = nullptr, *coef64 = nullptr;
   // FP32 buffers (mixed precision)
   float *A32 = nullptr, *B32 = nullptr, *f32 = nullptr, *coef32 = nullptr;
+  // Galerkin coarse level (option coarse_op): its stencils and a level-sized
+  // temporary (the residual before restriction, the prolonged iterate before
+  // smoothing)
+  bool g9 = false;
+  Stencil9 st{};
+  double* g64 = nullptr;
+  float* g32 = nullptr;
 };
 
 // Byte-offset planner over one device buffer.
@@ -129,6 +136,7 @@ struct Solver {
   double* fft_sinvT = nullptr;  // (transposed problem)
   double* fft_tw = nullptr;
   double* fft_work = nullptr;   // 2 (N M + 1) P
+  double* fft_mscale = nullptr; // Galerkin coarsest level: 1 / mass symbol per mode
   double* delta64 = nullptr;  // Newton correction / adjoint multiplier (level 0, FP64)
   // Flexible GMRES (opt.krylov = m > 0): m + 1 basis vectors and m + 1
   // direction buffers (one spare for the V-cycle's ping-pong) on level 0,
@@ -194,6 +202,7 @@ struct Solver {
   int upload();           // copies tables into the workspace
   int upload_fft();       // tables of the Fourier coarsest solve
   int upload_dense();     // dense inverse of the coarsest slab matrix
+  int galerkin_levels();  // Galerkin stencils and point blocks of the coarse levels
 
   int chunk_of(int l) const;        // smoother block length on level l
   int transfer_slabs(int l) const;  // slabs per thread in transfer kernels

@@ -87,3 +87,26 @@ def test_undersized_workspace_is_refused_on_the_host():
     rc = B.lib().stmg_setup(ctypes.byref(P), ctypes.byref(O), ctypes.c_void_p((1 << 20) + 8), need, None,
                             ctypes.byref(h))
     assert rc == B.STMG_EINVAL
+
+
+def test_galerkin_option_validation_and_workspace():
+    """Galerkin coarse levels: accepted for space coarsening of periodic linear
+    problems with a Fourier coarsest level, and then take one more level-sized
+    vector per coarse level plus the mass symbol; refused (workspace 0)
+    otherwise."""
+    import stmg_inputs as si
+    prob = si.config("rd2d")
+    ws = lambda p, **o: B.lib().stmg_workspace_bytes(ctypes.byref(B.make_problem(p)),
+                                                     ctypes.byref(B.make_options(**o)))
+    n = ws(prob, coarsen="space")
+    g = ws(prob, coarsen="space", coarse_op="galerkin")
+    assert n > 0 and g > n
+    # levels 128^2 and 64^2 (the Fourier coarsest), N = 256, M = 3
+    assert g - n >= 8 * 3 * 256 * (128 * 128 + 64 * 64)
+    assert ws(prob, coarse_op="galerkin") == 0                      # coarsen auto
+    assert ws(dict(prob, bc="neumann"), coarsen="space", coarse_op="galerkin") == 0
+    ac = si.config("ac2d")
+    assert ws(ac, coarsen="space", coarse_op="galerkin") == 0       # nonlinear
+    # fft_coarse = 0: the hierarchy runs down to min_coarse, still Fourier-solved
+    assert ws(prob, coarsen="space", coarse_op="galerkin", fft_coarse=0) > 0
+    assert ws(prob, coarsen="space", coarse_op=2) == 0
