@@ -225,7 +225,7 @@ def time_kernels(h, U, u0, iters):
     return kernels, cyc_ms, lv, c_ms, 2.0 * U.numel() * 8
 
 
-EXTRA_GROUPS = ("heat1d", "allen_cahn", "adjoint", "batch", "sdc", "hierarchies", "krylov", "paper")
+EXTRA_GROUPS = ("heat1d", "allen_cahn", "adjoint", "batch", "sdc", "pfasst", "hierarchies", "krylov", "paper")
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
@@ -246,6 +246,8 @@ def extras(dev, only=None):
         out.update(_extra_batch(dev))
     if only in (None, "sdc"):
         out.update(_extra_sdc(dev))
+    if only in (None, "pfasst"):
+        out.update(_extra_pfasst(dev))
     if only in (None, "hierarchies"):
         out.update(_extra_hierarchies(dev))
     if only in (None, "krylov"):
@@ -426,6 +428,51 @@ def _extra_sdc(dev):
     torch.cuda.empty_cache()
     print("sdc done", file=sys.stderr, flush=True)
     return {"sdc_rd2d_fp64": {"sweeps": 16, "seconds_per_sweep": t / 16, "rel_res_after_4_8_12_16": rels}}
+
+
+def _extra_pfasst(dev):
+    """PFASST^L_1 (Sec. 5.2: one sweep per level, M = 1 and bisection in space
+    on the coarse levels) beside the multigrid solve, FP64 to 1e-10, on the
+    256^2 workload and the 1D heat workload: iterations, time, and the
+    difference between the two solutions."""
+    import torch
+    import stmg_inputs as si
+    from paper_2006_12883_amd import stmg
+    out = {}
+    for cfg in ("rd2d", "heat1d"):
+        prob = si.config(cfg)
+        u0 = torch.as_tensor(si.initial(cfg, prob)).to(dev)
+        h = stmg.Handle(prob, device=dev, rtol=1e-10, max_cycles=200)
+        Ur = torch.zeros(h.shape, dtype=torch.float64, device=dev)
+        h.solve(u0, Ur, check=False)
+        Ur.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, sr = h.solve(u0, Ur, check=False)
+        torch.cuda.synchronize()
+        line = {"stmg": {"seconds": time.perf_counter() - t0, "vcycles": sr["cycles"], "rel_res": sr["rel_res"]}}
+        del h
+        for L in (2, 3):
+            h = stmg.Handle(prob, device=dev, pfasst_levels=L, rtol=1e-10, max_cycles=200)
+            U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
+            h.pfasst(u0, U, check=False)
+            U.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = h.pfasst(u0, U, check=False)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            line["pfasst_L%d" % L] = {"seconds": t, "iterations": st["cycles"], "status": st["status"],
+                                      "rel_res": st["rel_res"],
+                                      "rel_diff_vs_stmg": float(torch.linalg.norm(U - Ur) / torch.linalg.norm(Ur)),
+                                      "seconds_per_iteration": t / max(1, st["cycles"])}
+            del h, U
+            torch.cuda.empty_cache()
+        out["pfasst_%s_fp64_to_1e-10" % cfg] = line
+        del Ur
+        torch.cuda.empty_cache()
+    print("pfasst done", file=sys.stderr, flush=True)
+    return out
 
 
 def _extra_hierarchies(dev):

@@ -189,6 +189,16 @@ typedef struct {
                          Space coarsening only (coarsen = SPACE), periodic
                          grids, linear reaction, Fourier coarsest solve
                          (EUNSUPPORTED otherwise)                             */
+  int32_t pfasst_levels; /* >= 2: the handle also runs PFASST
+                         (stmg_pfasst_solve) with this many levels: the
+                         problem's grid and M, then bisections in space with
+                         M = 1 (Sec. 5.2, PFASST item).  0 (default): not set
+                         up.  FP64 linear problems without Krylov or time
+                         windows; every level's element counts even, the
+                         coarsest grid at least 3 points per dimension
+                         (EUNSUPPORTED or EINVAL otherwise)                  */
+  int32_t pfasst_sweeps; /* SDC sweeps per level and PFASST iteration (nu of
+                         PFASST^L_nu; default 1)                              */
 } stmg_options;
 
 typedef struct {
@@ -314,6 +324,27 @@ int stmg_adjoint(stmg_handle* h, const double* d_u0, const double* d_U,
  * options.sdc = 1 (EUNSUPPORTED otherwise). */
 int stmg_sdc_sweep(stmg_handle* h, const double* d_u0, double* d_U,
                    int32_t sweeps, double* h_rel);
+
+/* PFASST (Sec. 4.1; Sec. 5.2, PFASST item) on the collocation form of the
+ * problem, for a handle set up with options.pfasst_levels = L >= 2.  One
+ * iteration: on levels 0 .. L-2, pfasst_sweeps SDC sweeps (the sweep of
+ * stmg_sdc_sweep on level 0; on the M = 1 levels an exact per-slab solve
+ * with the previous slab's end value from the incoming iterate), then the
+ * FAS restriction to the next level (space full weighting of the end-node
+ * values; tau_{l+1} = R_s [tau_l + dt (Q L V)_M] - dt L_{l+1} R_s V_M); on
+ * the coarsest level the serial sweep, which at M = 1 is the exact solve of
+ * its block lower-bidiagonal system (done all slabs at once by that level's
+ * own multigrid solver to rtol); going up, the coarse corrections e_n are
+ * interpolated bilinearly in space and linearly in time between the slab's
+ * start and end, V_{n,i} += P ((1 - c_i) e_{n-1} + c_i e_n), followed by
+ * the sweeps on the M = 1 levels.  d_U holds the initial guess and receives
+ * the iterate; stops at ||b - A U|| / ||b|| <= rtol (in the handle's form)
+ * or after max_cycles iterations (stats.cycles = iterations; ENOTCONV,
+ * EDIVERGED and ENAN as stmg_solve).  Inner solves stop at rtol: the SDC
+ * node solves relative to their first residual, the M = 1 level solves
+ * relative to (||f||^2 + ||u0||^2)^{1/2} of their right-hand side.
+ * EUNSUPPORTED on a handle without PFASST levels. */
+int stmg_pfasst_solve(stmg_handle* h, const double* d_u0, double* d_U, stmg_stats* stats);
 
 /* Component entry points on level `level` of the hierarchy (FP64):
  *   smooth : U_out = U_in + omega D^{-1} (f - A_l U_in); the block-Jacobi

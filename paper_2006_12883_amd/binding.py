@@ -26,7 +26,7 @@ EXPORTS = [
     "stmg_default_options", "stmg_workspace_bytes", "stmg_setup", "stmg_num_levels",
     "stmg_level_shape", "stmg_level_nodes", "stmg_residual", "stmg_residual_noalloc", "stmg_vcycle", "stmg_solve", "stmg_solve_end",
     "stmg_num_windows", "stmg_tuned_shape", "stmg_adjoint",
-    "stmg_sdc_sweep", "stmg_level_smooth", "stmg_level_restrict_residual",
+    "stmg_sdc_sweep", "stmg_pfasst_solve", "stmg_level_smooth", "stmg_level_restrict_residual",
     "stmg_level_prolong", "stmg_level_prolong_smooth", "stmg_coarse_solve", "stmg_destroy",
     "stmg_batch_workspace_bytes", "stmg_batch_setup", "stmg_batch_solve",
     "stmg_batch_destroy", "stmg_status_string", "stmg_last_error",
@@ -50,7 +50,8 @@ class Options(ctypes.Structure):
                 ("autotune", ctypes.c_int32), ("inner_cycles", ctypes.c_int32),
                 ("fft_coarse", ctypes.c_int32), ("krylov", ctypes.c_int32),
                 ("krylov_left", ctypes.c_int32), ("inner_adapt", ctypes.c_int32),
-                ("form", ctypes.c_int32), ("smoother", ctypes.c_int32), ("coarse_op", ctypes.c_int32)]
+                ("form", ctypes.c_int32), ("smoother", ctypes.c_int32), ("coarse_op", ctypes.c_int32),
+                ("pfasst_levels", ctypes.c_int32), ("pfasst_sweeps", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -88,6 +89,7 @@ def lib():
             "stmg_num_windows": (ip, [vp]),
             "stmg_tuned_shape": (ip, [vp, ip]),
             "stmg_sdc_sweep": (ip, [vp, vp, vp, ctypes.c_int32, dp]),
+            "stmg_pfasst_solve": (ip, [vp, vp, vp, S]),
             "stmg_level_smooth": (ip, [vp, ip, vp, vp, vp, vp]),
             "stmg_level_restrict_residual": (ip, [vp, ip, vp, vp, vp, vp]),
             "stmg_level_prolong": (ip, [vp, ip, vp, vp, vp]),

@@ -96,6 +96,8 @@ void stmg_default_options(stmg_options* o) {
   o->form = STMG_FORM_DG;
   o->smoother = STMG_SMOOTH_PBJ;
   o->coarse_op = STMG_COARSE_REDISC;
+  o->pfasst_levels = 0;
+  o->pfasst_sweeps = 1;
 }
 
 size_t stmg_workspace_bytes(const stmg_problem* prob, const stmg_options* opt) {
@@ -220,6 +222,11 @@ int stmg_sdc_sweep(stmg_handle* h, const double* d_u0, double* d_U, int32_t swee
                    double* h_rel) {
   if (!h || !d_u0 || !d_U || sweeps < 0) { stmg::set_error("bad argument"); return STMG_EINVAL; }
   return h->s.sdc(d_u0, d_U, sweeps, h_rel);
+}
+
+int stmg_pfasst_solve(stmg_handle* h, const double* d_u0, double* d_U, stmg_stats* stats) {
+  if (!h || !d_u0 || !d_U) { stmg::set_error("null pointer"); return STMG_EINVAL; }
+  return h->s.pfasst(d_u0, d_U, stats);
 }
 
 int stmg_num_windows(const stmg_handle* h) { return h ? h->s.nwin : 0; }

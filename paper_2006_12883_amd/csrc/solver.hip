@@ -27,6 +27,10 @@ int points(int e, int bc) { return bc == STMG_BC_PERIODIC ? e : e + 1; }
 
 }  // namespace
 
+// Cap on the V-cycles of an inner solve (SDC node solves, PFASST level
+// solves), which stop at rtol relative to their first residual.
+constexpr int kInnerMaxCycles = 200;
+
 #define HIP_TRY(expr)                                                            \
   do {                                                                           \
     hipError_t e_ = (expr);                                                      \
@@ -265,7 +269,17 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     set_error("SDC smoother: FP64 linear problems without the Krylov method only");
     return STMG_EUNSUPPORTED;
   }
-  if ((o->sdc || o->smoother == STMG_SMOOTH_SDC) && !decoupled) {
+  if (o->pfasst_levels != 0 &&
+      (o->pfasst_levels < 2 || o->pfasst_levels > 8 || o->pfasst_sweeps < 1 || o->pfasst_sweeps > 16)) {
+    set_error("pfasst_levels must be 0 or 2..8 and pfasst_sweeps 1..16");
+    return STMG_EINVAL;
+  }
+  if (o->pfasst_levels >= 2 &&
+      (allen_cahn || o->precision != STMG_PREC_FP64 || o->krylov > 0 || batch_member || decoupled)) {
+    set_error("PFASST: FP64 linear problems without the Krylov method only");
+    return STMG_EUNSUPPORTED;
+  }
+  if ((o->sdc || o->smoother == STMG_SMOOTH_SDC || o->pfasst_levels >= 2) && !decoupled) {
     if (allen_cahn) { set_error("SDC sweeps: linear problems only"); return STMG_EUNSUPPORTED; }
     for (int m = 0; m < M; ++m) {
       const long double dc = tab.c[m] - (m > 0 ? tab.c[m - 1] : 0.0L);
@@ -275,8 +289,10 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
       sp.dt = sdc_w[m];
       stmg_options so = *o;
       so.sdc = 0;
+      so.pfasst_levels = 0;
       so.mem_budget = 0;
       so.krylov = 0;
+      so.max_cycles = std::max(o->max_cycles, kInnerMaxCycles);
       so.precision = STMG_PREC_FP64;
       so.coarsen = STMG_COARSEN_SPACE;
       so.smoother = STMG_SMOOTH_PBJ;
@@ -286,6 +302,44 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
       int rc = sub->build(&sp, &so);
       if (rc) return rc;
       sdcn.push_back(std::move(sub));
+    }
+  }
+  // PFASST levels: bisection in space, M = 1
+  pf.clear();
+  if (o->pfasst_levels >= 2 && !decoupled) {
+    int ex = lv[0].ex, ey = lv[0].ey;
+    for (int l = 1; l < o->pfasst_levels; ++l) {
+      if (ex % 2 != 0 || ex / 2 < 2 || (twod && (ey % 2 != 0 || ey / 2 < 2))) {
+        set_error("PFASST: element counts must stay even down to at least 2 per dimension");
+        return STMG_EINVAL;
+      }
+      ex /= 2;
+      if (twod) ey /= 2;
+      stmg_problem sp = *p;
+      sp.nx[0] = ex;
+      sp.nx[1] = twod ? ey : 1;
+      sp.M = 1;
+      stmg_options so = *o;
+      so.pfasst_levels = 0;
+      so.sdc = 0;
+      so.mem_budget = 0;
+      so.krylov = 0;
+      so.max_cycles = std::max(o->max_cycles, kInnerMaxCycles);
+      so.precision = STMG_PREC_FP64;
+      so.smoother = STMG_SMOOTH_PBJ;
+      so.form = STMG_FORM_DG;
+      so.coarse_op = STMG_COARSE_REDISC;
+      PfLevel q;
+      q.sol.reset(new Solver());
+      if (l + 1 < o->pfasst_levels) {
+        so.coarsen = STMG_COARSEN_SPACE;
+        q.sol->decoupled = true;
+      }
+      int rc = q.sol->build(&sp, &so);
+      if (rc) return rc;
+      q.nx = q.sol->lv[0].nx;
+      q.ny = q.sol->lv[0].ny;
+      pf.push_back(std::move(q));
     }
   }
   // Windows: the FP64 path keeps about five full vectors on level 0 (the
@@ -306,6 +360,10 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     while (w2 * 2 <= W) w2 *= 2;
     W = w2;
     if (W < p->N) {
+      if (!pf.empty()) {
+        set_error("PFASST needs the whole trajectory in memory (mem_budget too small)");
+        return STMG_EUNSUPPORTED;
+      }
       sdcn.clear();  // SDC sweeps act on the whole trajectory
       win_W = static_cast<int>(W);
       nwin = (p->N + win_W - 1) / win_W;
@@ -453,6 +511,21 @@ size_t Solver::plan(char* ws) {
     }
     sdc_acc = pl.take<double>(static_cast<size_t>(lv[0].N) * lv[0].nx * lv[0].ny);
     sdc_G = pl.take<double>(kMaxM * kMaxM);
+  }
+  if (!pf.empty()) {
+    const size_t N = static_cast<size_t>(lv[0].N);
+    pf_pack = pl.take<double>(N * 2 * lv[0].nx * lv[0].ny);
+    pf_E = pl.take<double>(N * prob.M * pf[0].nx * pf[0].ny);
+    for (auto& q : pf) {
+      const size_t P = static_cast<size_t>(q.nx) * q.ny;
+      q.V = pl.take<double>(N * P);
+      q.tau = pl.take<double>(N * P);
+      q.rhs = pl.take<double>(N * P);
+      q.pack = pl.take<double>(N * 2 * P);
+      q.u0 = pl.take<double>(P);
+      const size_t b = q.sol->plan(nullptr);
+      q.sol->plan(pl.take<char>(b));
+    }
   }
   return pl.off + 256;
 }
@@ -767,6 +840,11 @@ int Solver::upload() {
       int rc = sub->upload();
       if (rc) return rc;
     }
+  }
+  for (auto& q : pf) {
+    q.sol->stream = stream;
+    int rc = q.sol->upload();
+    if (rc) return rc;
   }
   HIP_CHECK(hipStreamSynchronize(stream));  // host vectors go out of scope
   return STMG_OK;
@@ -1781,6 +1859,8 @@ template hipError_t Solver::smooth<double>(int, bool, int, const double*, const 
 template hipError_t Solver::restrict_residual<double>(int, bool, int, const double*, const double*, const double*, double*, double*, bool*);
 template hipError_t Solver::prolong<double>(int, const double*, const double*, double*);
 template hipError_t Solver::coarse<double>(bool, int, const double*, const double*, double*);
+template hipError_t Solver::residual64<double>(bool, int, const double*, const double*, const double*, double*,
+                                               double*);
 
 }  // namespace stmg
 

@@ -196,6 +196,25 @@ struct Solver {
   double* sdc_G = nullptr;
   double sdc_w[kMaxM] = {0};  // dt * (c_m - c_{m-1})
 
+  // PFASST (option pfasst_levels): the levels below level 0, each with M = 1
+  // and half the elements of the one above; per level its iterate, FAS
+  // right-hand side, the restricted pair (z, end values) from the level
+  // above, its initial value and an M = 1 solver (independent slabs on the
+  // intermediate levels, the coupled system on the coarsest).
+  struct PfLevel {
+    int nx = 0, ny = 1;
+    double* V = nullptr;
+    double* tau = nullptr;
+    double* rhs = nullptr;
+    double* pack = nullptr;  // [N][2][P]: R_s z, R_s V_M of the level above
+    double* u0 = nullptr;
+    std::unique_ptr<Solver> sol;
+  };
+  std::vector<PfLevel> pf;
+  double* pf_pack = nullptr;  // [N][2][P] on the finer level of a transfer
+  double* pf_E = nullptr;     // [N][M][P] corrections on the coarser grid
+  int pfasst(const double* u0, double* U, stmg_stats* st);
+
   // --- setup ---
   int build(const stmg_problem* p, const stmg_options* o);
   size_t plan(char* ws);  // lays out (or sizes, ws = nullptr) the workspace

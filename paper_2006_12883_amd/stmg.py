@@ -130,6 +130,17 @@ class Handle:
                 "stmg_sdc_sweep")
         return rel.value
 
+    def pfasst(self, u0, U=None, check=True):
+        """PFASST iterations (handle set up with pfasst_levels >= 2) from U
+        (zero if None); returns (U, stats)."""
+        if U is None:
+            U = torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+        st = B.Stats()
+        rc = B.lib().stmg_pfasst_solve(self.h, _ptr(u0), _ptr(U), ctypes.byref(st))
+        if check:
+            B.check(rc, "stmg_pfasst_solve")
+        return U, st.as_dict()
+
     # --- components --------------------------------------------------------
     def smooth(self, level, Uin, Uout, f=None, u0=None):
         B.check(B.lib().stmg_level_smooth(self.h, level, _ptr(f), _ptr(u0), _ptr(Uin), _ptr(Uout)),

@@ -110,3 +110,24 @@ def test_galerkin_option_validation_and_workspace():
     # fft_coarse = 0: the hierarchy runs down to min_coarse, still Fourier-solved
     assert ws(prob, coarsen="space", coarse_op="galerkin", fft_coarse=0) > 0
     assert ws(prob, coarsen="space", coarse_op=2) == 0
+
+
+def test_pfasst_option_validation_and_workspace():
+    """PFASST levels: accepted for FP64 linear problems whose element counts
+    stay even down the levels, adding the coarse levels' vectors and solvers
+    to the workspace; refused (workspace 0) otherwise."""
+    import stmg_inputs as si
+    prob = si.config("rd2d")
+    ws = lambda p, **o: B.lib().stmg_workspace_bytes(ctypes.byref(B.make_problem(p)),
+                                                     ctypes.byref(B.make_options(**o)))
+    n = ws(prob)
+    assert ws(prob, pfasst_levels=2) > n and ws(prob, pfasst_levels=3) > ws(prob, pfasst_levels=2)
+    assert ws(prob, pfasst_levels=1) == 0
+    assert ws(prob, pfasst_levels=9) == 0
+    assert ws(prob, pfasst_levels=2, pfasst_sweeps=0) == 0
+    assert ws(prob, pfasst_levels=2, precision="mixed") == 0
+    assert ws(si.config("ac2d"), pfasst_levels=2) == 0
+    assert ws(dict(prob, nx=[10, 10]), pfasst_levels=3) == 0  # 10 -> 5 elements, odd: no second halving
+    assert ws(dict(prob, nx=[12, 12]), pfasst_levels=3) > 0   # 12 -> 6 -> 3
+    assert ws(dict(prob, nx=[8, 8]), pfasst_levels=2) > 0     # 8 -> 4
+    assert ws(dict(prob, nx=[8, 8]), pfasst_levels=3) == 0    # 4 -> 2: fewer than 3 points

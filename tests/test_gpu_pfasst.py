@@ -1,0 +1,89 @@
+"""PFASST (stmg_pfasst_solve) against the oracle's PFASST iteration by
+iteration, and its converged solution against the time stepper.
+
+Each case prints its name before touching the GPU."""
+import numpy as np
+import pytest
+
+import stmg_inputs as si
+from oracle import pfasst, stepper
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from gpu_util import H, T, assert_close, rel_err  # noqa: E402
+
+
+def _rect(prob, nx, ny, ly):
+    prob = dict(prob)
+    prob["nx"] = [nx, ny]
+    prob["length"] = [prob["length"][0], ly]
+    return prob
+
+
+# (name, problem, levels, sweeps)
+CASES = [
+    ("2d-M3-L2", si.problem(2, 32, 3, 8, 0.25, nu=0.02, lam=1.0), 2, 1),
+    ("2d-M2-L3", si.problem(2, 32, 2, 6, 0.3, nu=0.05, lam=0.5), 3, 1),
+    ("2d-M4-L3-nu2", si.problem(2, 16, 4, 5, 0.2, nu=0.02, lam=0.3), 3, 2),
+    ("2d-rect-L2", _rect(si.problem(2, 32, 3, 6, 0.3, nu=0.03, lam=0.7), 32, 16, 0.5), 2, 1),
+    ("2d-neumann-L2", si.problem(2, 16, 2, 6, 0.3, nu=0.02, lam=1.0, bc="neumann"), 2, 1),
+    ("1d-M3-L3", si.problem(1, 64, 3, 12, 0.2, nu=0.1, lam=0.5), 3, 1),
+    ("1d-neumann-L3", si.problem(1, 32, 3, 8, 0.2, nu=0.1, lam=0.5, bc="neumann"), 3, 1),
+    ("1d-M1-L2", si.problem(1, 64, 1, 16, 0.3, nu=0.2, lam=0.0), 2, 1),
+]
+
+
+def _u0(prob, seed):
+    ny, nx = si.grid_points(prob)
+    return np.random.default_rng(seed).standard_normal((ny, nx))
+
+
+@pytest.mark.parametrize("name,prob,levels,nu", CASES)
+def test_iterations_match_oracle(name, prob, levels, nu):
+    """Four PFASST iterations from a random start, one call each (max_cycles
+    1), against oracle.pfasst.iteration; inner solves to 1e-13."""
+    print("case", name, flush=True)
+    u0 = _u0(prob, 1)
+    levs = pfasst.hierarchy(prob, levels)
+    u0s = pfasst.initial_values(levs, u0)
+    X = np.random.default_rng(2).standard_normal(levs[0].shape)
+    h = H(prob, pfasst_levels=levels, pfasst_sweeps=nu, rtol=1e-13, max_cycles=1)
+    Ud = T(X)
+    ref = X
+    for k in range(4):
+        ref = pfasst.iteration(levs, u0s, ref, nu)
+        _, st = h.pfasst(T(u0), Ud, check=False)
+        assert st["cycles"] == 1 and st["status"] in (0, -4), st
+        assert_close(Ud.cpu().numpy(), ref, 1e-10, "iteration %d" % (k + 1))
+
+
+SOLVES = [
+    ("rd2d-64-M3-L2", si.problem(2, 64, 3, 16, 0.5, nu=1e-2, lam=1.0), 2),
+    ("rd2d-64-M3-L3", si.problem(2, 64, 3, 16, 0.5, nu=1e-2, lam=1.0), 3),
+    ("heat1d-128-M2-L3", si.problem(1, 128, 2, 32, 0.1, nu=0.5, lam=0.0), 3),
+    ("neumann1d-L2", si.problem(1, 64, 3, 16, 0.2, nu=0.05, lam=0.3, bc="neumann"), 2),
+]
+
+
+@pytest.mark.parametrize("name,prob,levels", SOLVES)
+def test_converges_to_stepper(name, prob, levels):
+    print("case", name, flush=True)
+    ny, nx = si.grid_points(prob)
+    u0 = si.u0_rd2d(prob, 3) if prob["dim"] == 2 else np.sin(2 * np.pi * np.arange(nx) / nx)[None, :]
+    ref = stepper.solve_linear(prob, u0)
+    h = H(prob, pfasst_levels=levels, rtol=1e-12, max_cycles=200)
+    U, st = h.pfasst(T(u0))
+    print("iterations", st["cycles"], "rel", st["rel_res"], flush=True)
+    assert st["status"] == 0 and st["rel_res"] <= 1e-12
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-10
+    assert rel_err(U.cpu().numpy()[-1, -1], ref[-1, -1]) <= 1e-10
+
+
+def test_pfasst_needs_its_levels():
+    print("case no levels", flush=True)
+    prob = si.problem(2, 16, 2, 4, 0.2, nu=0.05, lam=1.0)
+    h = H(prob)
+    with pytest.raises(Exception) as e:
+        h.pfasst(T(_u0(prob, 1)))
+    assert "pfasst_levels" in str(e.value)
