@@ -434,7 +434,8 @@ def _extra_pfasst(dev):
     """PFASST^L_1 (Sec. 5.2: one sweep per level, M = 1 and bisection in space
     on the coarse levels) beside the multigrid solve, FP64 to 1e-10, on the
     256^2 workload and the 1D heat workload: iterations, time, and the
-    difference between the two solutions."""
+    difference between the two solutions; inner solves to rtol, or cut to 1 or
+    2 V-cycles (pfasst_inner_cycles)."""
     import torch
     import stmg_inputs as si
     from paper_2006_12883_amd import stmg
@@ -452,8 +453,9 @@ def _extra_pfasst(dev):
         torch.cuda.synchronize()
         line = {"stmg": {"seconds": time.perf_counter() - t0, "vcycles": sr["cycles"], "rel_res": sr["rel_res"]}}
         del h
-        for L in (2, 3):
-            h = stmg.Handle(prob, device=dev, pfasst_levels=L, rtol=1e-10, max_cycles=200)
+        for L, inner in ((2, 0), (3, 0), (2, 1), (2, 2), (3, 1)):
+            h = stmg.Handle(prob, device=dev, pfasst_levels=L, pfasst_inner_cycles=inner, rtol=1e-10,
+                            max_cycles=300)
             U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
             h.pfasst(u0, U, check=False)
             U.zero_()
@@ -462,7 +464,7 @@ def _extra_pfasst(dev):
             _, st = h.pfasst(u0, U, check=False)
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
-            line["pfasst_L%d" % L] = {"seconds": t, "iterations": st["cycles"], "status": st["status"],
+            line["pfasst_L%d" % L + ("_inner%d" % inner if inner else "")] = {"seconds": t, "iterations": st["cycles"], "status": st["status"],
                                       "rel_res": st["rel_res"],
                                       "rel_diff_vs_stmg": float(torch.linalg.norm(U - Ur) / torch.linalg.norm(Ur)),
                                       "seconds_per_iteration": t / max(1, st["cycles"])}

@@ -199,6 +199,12 @@ typedef struct {
                          (EUNSUPPORTED or EINVAL otherwise)                  */
   int32_t pfasst_sweeps; /* SDC sweeps per level and PFASST iteration (nu of
                          PFASST^L_nu; default 1)                              */
+  int32_t pfasst_inner_cycles; /* > 0: every inner solve of stmg_pfasst_solve
+                         (the SDC node solves, the M = 1 level solves) stops
+                         after at most this many V-cycles, warm-started where
+                         the sweep allows (inexact spatial solves, as the
+                         paper's few ILU(0)-PGMRES iterations); 0 (default):
+                         to rtol.  0..100                                     */
 } stmg_options;
 
 typedef struct {

@@ -51,7 +51,8 @@ class Options(ctypes.Structure):
                 ("fft_coarse", ctypes.c_int32), ("krylov", ctypes.c_int32),
                 ("krylov_left", ctypes.c_int32), ("inner_adapt", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("smoother", ctypes.c_int32), ("coarse_op", ctypes.c_int32),
-                ("pfasst_levels", ctypes.c_int32), ("pfasst_sweeps", ctypes.c_int32)]
+                ("pfasst_levels", ctypes.c_int32), ("pfasst_sweeps", ctypes.c_int32),
+                ("pfasst_inner_cycles", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

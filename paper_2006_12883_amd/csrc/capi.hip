@@ -98,6 +98,7 @@ void stmg_default_options(stmg_options* o) {
   o->coarse_op = STMG_COARSE_REDISC;
   o->pfasst_levels = 0;
   o->pfasst_sweeps = 1;
+  o->pfasst_inner_cycles = 0;
 }
 
 size_t stmg_workspace_bytes(const stmg_problem* prob, const stmg_options* opt) {

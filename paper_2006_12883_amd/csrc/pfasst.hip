@@ -166,6 +166,12 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
     return STMG_EUNSUPPORTED;
   }
   const int nl = static_cast<int>(pf.size()) + 1, nu = opt.pfasst_sweeps;
+  // the inner-solve cap holds for this call only
+  struct CapGuard {
+    int& c;
+    ~CapGuard() { c = 0; }
+  } cap_guard{inner_cap};
+  inner_cap = opt.pfasst_inner_cycles;
   const int N = lv[0].N, M0 = prob.M;
   const double dt = prob.dt;
   // level l: grid, nodes, iterate, FAS right-hand side
@@ -215,9 +221,7 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
       PF_CHECK(hipMemsetAsync(q.V, 0, N * P * sizeof(double), stream));
       return STMG_OK;
     }
-    int cyc = 0;
-    double rel = 0.0;
-    return q.sol->solve_linear(false, REACT_CONST, f, u0l, q.V, opt.rtol, nb, &cyc, &rel);
+    return inner_solve(q.sol.get(), f, u0l, q.V, nb);
   };
   // one Jacobi sweep on an M = 1 level: V_n <- (I - dt L)^-1 (V_{n-1} + tau_n)
   auto jacobi = [&](int l) -> int {

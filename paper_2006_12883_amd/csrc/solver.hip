@@ -270,8 +270,9 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     return STMG_EUNSUPPORTED;
   }
   if (o->pfasst_levels != 0 &&
-      (o->pfasst_levels < 2 || o->pfasst_levels > 8 || o->pfasst_sweeps < 1 || o->pfasst_sweeps > 16)) {
-    set_error("pfasst_levels must be 0 or 2..8 and pfasst_sweeps 1..16");
+      (o->pfasst_levels < 2 || o->pfasst_levels > 8 || o->pfasst_sweeps < 1 || o->pfasst_sweeps > 16 ||
+       o->pfasst_inner_cycles < 0 || o->pfasst_inner_cycles > 100)) {
+    set_error("pfasst_levels must be 0 or 2..8, pfasst_sweeps 1..16, pfasst_inner_cycles 0..100");
     return STMG_EINVAL;
   }
   if (o->pfasst_levels >= 2 &&
@@ -1828,6 +1829,21 @@ int Solver::sdc(const double* u0, double* U, int sweeps, double* h_rel) {
   return STMG_OK;
 }
 
+// An inner solve of the SDC sweep or of PFASST: to rtol (relative to the
+// first residual when norm_b < 0), or with inner_cap > 0 for at most that
+// many V-cycles, the cap being no failure.
+int Solver::inner_solve(Solver* S, const double* f, const double* u0, double* U, double norm_b) {
+  int cyc = 0;
+  double rel = 0.0;
+  if (inner_cap <= 0) return S->solve_linear(false, REACT_CONST, f, u0, U, opt.rtol, norm_b, &cyc, &rel);
+  const int keep = S->opt.max_cycles;
+  S->opt.max_cycles = inner_cap;
+  int rc = S->solve_linear(false, REACT_CONST, f, u0, U, opt.rtol, norm_b, &cyc, &rel);
+  S->opt.max_cycles = keep;
+  if (rc == STMG_ENOTCONV) rc = STMG_OK;
+  return rc;
+}
+
 int Solver::sdc_core(const double* u0, double* U, int sweeps) {
   Level& L0 = lv[0];
   const int N = L0.N, M = prob.M, P = L0.nx * L0.ny;
@@ -1845,7 +1861,7 @@ int Solver::sdc_core(const double* u0, double* U, int sweeps) {
       // which is ||rhs|| (no separate norm pass or host read per node)
       int cyc = 0;
       double rel = 0.0;
-      const int rc = S->solve_linear(false, REACT_CONST, rhs, nullptr, S->delta64, opt.rtol, -1.0, &cyc, &rel);
+      const int rc = inner_solve(S, rhs, nullptr, S->delta64, -1.0);
       if (rc) return rc;
       HIP_CHECK(launch_sdc_update(U, sdc_acc, S->delta64, N, M, L0.nx, L0.ny, L0.op.bc, L0.op.cx,
                                   L0.op.cy, L0.op.lam, sdc_w[m], m, stream));

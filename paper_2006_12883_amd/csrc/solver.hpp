@@ -214,6 +214,10 @@ struct Solver {
   double* pf_pack = nullptr;  // [N][2][P] on the finer level of a transfer
   double* pf_E = nullptr;     // [N][M][P] corrections on the coarser grid
   int pfasst(const double* u0, double* U, stmg_stats* st);
+  // > 0 while PFASST runs with options.pfasst_inner_cycles: the cap on the
+  // V-cycles of each inner solve (reaching it is not an error there)
+  int inner_cap = 0;
+  int inner_solve(Solver* S, const double* f, const double* u0, double* U, double norm_b);
 
   // --- setup ---
   int build(const stmg_problem* p, const stmg_options* o);

@@ -126,6 +126,9 @@ def test_pfasst_option_validation_and_workspace():
     assert ws(prob, pfasst_levels=9) == 0
     assert ws(prob, pfasst_levels=2, pfasst_sweeps=0) == 0
     assert ws(prob, pfasst_levels=2, precision="mixed") == 0
+    assert ws(prob, pfasst_levels=2, pfasst_inner_cycles=2) > 0
+    assert ws(prob, pfasst_levels=2, pfasst_inner_cycles=-1) == 0
+    assert ws(prob, pfasst_levels=2, pfasst_inner_cycles=101) == 0
     assert ws(si.config("ac2d"), pfasst_levels=2) == 0
     assert ws(dict(prob, nx=[10, 10]), pfasst_levels=3) == 0  # 10 -> 5 elements, odd: no second halving
     assert ws(dict(prob, nx=[12, 12]), pfasst_levels=3) > 0   # 12 -> 6 -> 3

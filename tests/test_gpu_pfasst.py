@@ -80,6 +80,21 @@ def test_converges_to_stepper(name, prob, levels):
     assert rel_err(U.cpu().numpy()[-1, -1], ref[-1, -1]) <= 1e-10
 
 
+@pytest.mark.parametrize("inner", [1, 2])
+def test_inexact_inner_solves_converge(inner):
+    """With every inner solve cut to `inner` V-cycles PFASST still converges
+    to the stepper's solution (more iterations, cheaper ones)."""
+    print("case inexact", inner, flush=True)
+    prob = si.problem(2, 64, 3, 16, 0.5, nu=1e-2, lam=1.0)
+    u0 = si.u0_rd2d(prob, 3)
+    ref = stepper.solve_linear(prob, u0)
+    h = H(prob, pfasst_levels=2, pfasst_inner_cycles=inner, rtol=1e-12, max_cycles=300)
+    U, st = h.pfasst(T(u0))
+    print("iterations", st["cycles"], "rel", st["rel_res"], flush=True)
+    assert st["status"] == 0
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-10
+
+
 def test_pfasst_needs_its_levels():
     print("case no levels", flush=True)
     prob = si.problem(2, 16, 2, 4, 0.2, nu=0.05, lam=1.0)
