@@ -1,4 +1,4 @@
-"""PFASST for linear problems (Sec. 4.1; Sec. 5.2, PFASST item), plain NumPy.
+"""PFASST (Sec. 4.1; Sec. 5.2, PFASST item), plain NumPy.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -32,7 +32,19 @@ One iteration (a V-cycle over the levels):
     iteration).
 
 The SDC sweep is the one of oracle.sdc (implicit-Euler Q_Delta) with the
-right-hand side tau; spatial solves are direct.  The iteration stops on the
+right-hand side tau; spatial solves are direct.  For the Allen-Cahn reaction
+the sweep is semi-implicit (IMEX, Sec. 5.4: the reaction explicit, the
+diffusion implicit): F = L + R with R(u) = gamma (u - u^3), L implicit with
+Q_Delta as above and R explicit with the explicit-Euler Q_Delta^E, whose row
+m weighs the values at the left ends of the node intervals,
+Q_Delta^E[m][j] = c_{j+1} - c_j for j = 0 .. m-1 (j = 0 being the slab's
+initial value, c_0 = 0).  In correction form, node by node:
+  (I - dt dc_m L) d_m = r_m + dt sum_{j<m} dc_j L d_j
+                        + dt sum_{j=0}^{m-1} dc_{j+1} (R(V_j + d_j) - R(V_j)),
+with V_0 the initial value and d_0 its change (zero in the Jacobi sweep, the
+change of the previous slab's end value in the serial one) and r_m the
+collocation residual with the full F and the sweep's initial value.  The
+fixed point is still the collocation solution.  The iteration stops on the
 level-0 collocation residual relative to ||1 (x) u0||.  Readings: the paper
 leaves the transfers, the time interpolation, the FAS form and the order of
 sweeps to LibPFASST; the choices above are the standard ones of PFASST
@@ -64,6 +76,7 @@ class PLevel:
         self.c, self.Q = t["c"], t["Q"]
         self.dc = np.diff(np.concatenate([[0.0], self.c]))
         self.L = space.linear_operator(prob)
+        self.gamma = prob["gamma"] if prob.get("reaction", "linear") == "allen_cahn" else 0.0
         I = sp.identity(self.L.shape[0], format="csc")
         self.lu = [spla.splu((I - self.dt * self.dc[m] * self.L).tocsc()) for m in range(self.M)]
 
@@ -71,14 +84,18 @@ class PLevel:
     def shape(self):
         return (self.N, self.M) + self.grid
 
+    def R(self, v):
+        """The explicit (reaction) part of F: gamma (u - u^3), zero when linear."""
+        return self.gamma * (v - v ** 3)
+
     def F(self, V):
-        """L applied to every node plane of V ([N][M][ny][nx])."""
+        """F = L + R applied to every node plane of V ([N][M][ny][nx])."""
         n = self.L.shape[0]
         flat = V.reshape(-1, n)
-        return np.array([self.L @ v for v in flat]).reshape(V.shape)
+        return np.array([self.L @ v + self.R(v) for v in flat]).reshape(V.shape)
 
     def C(self, V, u0):
-        """C_l(V): the collocation operator with u0 entering slab 0."""
+        """C_l(V): the collocation operator (full F) with u0 entering slab 0."""
         FV = self.F(V)
         out = np.empty_like(V)
         for k in range(self.N):
@@ -89,18 +106,23 @@ class PLevel:
 
     def sweep(self, V, u0, tau, serial):
         """One SDC sweep on C_l(V) = tau: residual node by node, implicit-Euler
-        substitution over the nodes; the previous slab's end value from V
-        (serial False) or from the slabs already swept (serial True)."""
+        substitution over the nodes (IMEX with a reaction); the previous
+        slab's end value from V (serial False) or from the slabs already swept
+        (serial True)."""
         n = self.L.shape[0]
         out = V.copy()
         for k in range(self.N):
+            prev_old = (u0 if k == 0 else V[k - 1, self.M - 1]).reshape(n)
             prev = (u0 if k == 0 else (out if serial else V)[k - 1, self.M - 1]).reshape(n)
-            LV = np.array([self.L @ V[k, j].reshape(n) for j in range(self.M)])
-            acc = np.zeros(n)
+            FV = np.array([self.L @ V[k, j].reshape(n) + self.R(V[k, j].reshape(n)) for j in range(self.M)])
+            acc = self.dt * self.dc[0] * (self.R(prev) - self.R(prev_old))
             for m in range(self.M):
-                r = tau[k, m].reshape(n) + prev + self.dt * (self.Q[m] @ LV) - V[k, m].reshape(n)
+                v = V[k, m].reshape(n)
+                r = tau[k, m].reshape(n) + prev + self.dt * (self.Q[m] @ FV) - v
                 d = self.lu[m].solve(r + acc)
                 acc = acc + self.dt * self.dc[m] * (self.L @ d)
+                if m + 1 < self.M:
+                    acc = acc + self.dt * self.dc[m + 1] * (self.R(v + d) - self.R(v))
                 out[k, m] = V[k, m] + d.reshape(self.grid)
         return out
 

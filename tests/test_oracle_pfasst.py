@@ -147,3 +147,57 @@ def test_coarse_serial_sweep_is_backward_euler():
     for k in range(prob["N"]):
         u = np.linalg.solve(np.eye(L.shape[0]) - prob["dt"] * L, u)
         assert np.abs(got[k, 0].reshape(-1) - u).max() <= 1e-13 * max(1.0, np.abs(u).max())
+
+
+# --- Allen-Cahn: the IMEX sweep ---------------------------------------------
+@pytest.mark.parametrize("dim,levels", [(1, 2), (1, 3), (2, 2), (2, 3)])
+def test_imex_pfasst_reaches_the_implicit_collocation_solution(dim, levels):
+    """With the reaction explicit in the sweeps, PFASST still converges to the
+    fully implicit Radau IIA solution of the Allen-Cahn problem (the time
+    stepper with Newton per step)."""
+    if dim == 1:
+        prob = si.problem(1, 32, 3, 8, 0.4, nu=0.05, gamma=1.0, reaction="allen_cahn")
+    else:
+        prob = si.problem(2, 16, 2, 6, 0.3, nu=0.02, gamma=1.0, reaction="allen_cahn")
+    u0 = 0.8 * np.tanh(_u0(prob, 11))
+    ref = stepper.solve_allen_cahn(prob, u0)
+    hist = []
+    U, its = pfasst.solve(prob, u0, levels=levels, rtol=1e-13, max_iter=80, history=hist)
+    assert hist[-1] <= 1e-13, hist[-5:]
+    assert np.linalg.norm(U - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("serial", [False, True])
+def test_imex_sweep_solves_its_defining_equation(serial):
+    """One IMEX sweep V -> V' satisfies, slab by slab (u_0 the slab's initial
+    value in the sweep, u_0^old the incoming one),
+      V' = 1 u_0 + dt Q_I L V' + dt Q_E R([u_0; V'])
+           + dt (Q F(V) - Q_I L V - Q_E R([u_0^old; V])) + tau
+    with Q_I = implicit Euler (lower triangular, dc_j for j <= m) and Q_E the
+    M x (M+1) explicit Euler matrix (dc_{j+1} for j < m, column 0 the initial
+    value), written here with dense Kronecker products."""
+    prob = si.problem(1, 16, 3, 4, 0.5, nu=0.1, gamma=2.0, reaction="allen_cahn")
+    lev = pfasst.PLevel(prob)
+    rng = np.random.default_rng(12)
+    u0 = 0.7 * np.tanh(rng.standard_normal(lev.grid))
+    V = 0.7 * np.tanh(rng.standard_normal(lev.shape))
+    tau = 0.01 * rng.standard_normal(lev.shape)
+    out = lev.sweep(V, u0, tau, serial=serial)
+    M, dt, n = lev.M, lev.dt, int(np.prod(lev.grid))
+    c = radau.tables(M)["c"]
+    cc = np.concatenate([[0.0], c])
+    QI = np.array([[cc[j + 1] - cc[j] if j <= m else 0.0 for j in range(M)] for m in range(M)])
+    QE = np.array([[cc[j + 1] - cc[j] if j <= m else 0.0 for j in range(M + 1)] for m in range(M)])
+    Q = radau.tables(M)["Q"]
+    L = space.linear_operator(prob).toarray()
+    R = lambda v: prob["gamma"] * (v - v ** 3)
+    for k in range(prob["N"]):
+        u_old = (u0 if k == 0 else V[k - 1, M - 1]).reshape(n)
+        u_new = (u0 if k == 0 else (out if serial else V)[k - 1, M - 1]).reshape(n)
+        Vk, Wk = V[k].reshape(M, n), out[k].reshape(M, n)
+        FV = Vk @ L.T + R(Vk)
+        ext_new = np.vstack([u_new, Wk])
+        ext_old = np.vstack([u_old, Vk])
+        rhs = (np.tile(u_new, (M, 1)) + dt * QI @ (Wk @ L.T) + dt * QE @ R(ext_new)
+               + dt * (Q @ FV - QI @ (Vk @ L.T) - QE @ R(ext_old)) + tau[k].reshape(M, n))
+        assert np.abs(Wk - rhs).max() <= 1e-12 * max(1.0, np.abs(Wk).max())
