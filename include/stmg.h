@@ -193,8 +193,9 @@ typedef struct {
                          (stmg_pfasst_solve) with this many levels: the
                          problem's grid and M, then bisections in space with
                          M = 1 (Sec. 5.2, PFASST item).  0 (default): not set
-                         up.  FP64 linear problems without Krylov or time
-                         windows; every level's element counts even, the
+                         up.  FP64 without Krylov or time windows; an
+                         Allen-Cahn reaction is explicit in the sweeps (IMEX,
+                         Sec. 5.4); every level's element counts even, the
                          coarsest grid at least 3 points per dimension
                          (EUNSUPPORTED or EINVAL otherwise)                  */
   int32_t pfasst_sweeps; /* SDC sweeps per level and PFASST iteration (nu of
@@ -319,15 +320,17 @@ int stmg_adjoint(stmg_handle* h, const double* d_u0, const double* d_U,
                  const double* d_gT, double* d_grad_u0, double* h_grad_nu,
                  stmg_stats* stats);
 
-/* `sweeps` SDC sweeps (Sec. 2.1 and 3.1: preconditioned Richardson on the
+/* `sweeps` SDC sweeps (Sec. 2.1 and 4.1: preconditioned Richardson on the
  * collocation form U = 1 (x) u_{n-1} + dt (Q (x) I) F(U), with the
  * implicit-Euler lower-triangular Q_Delta) over all slabs at once, the
  * previous slab's end value lagged (Jacobi across slabs).  Per sweep and
  * node m the implicit solve (I - dt Q_Delta[m][m] L) delta_m = ... runs as
  * spatial V-cycles (the same kernels with M = 1, all slabs batched) to rtol.
  * d_U is updated in place; h_rel (may be NULL) receives ||b - A U|| / ||b||
- * (DG form) afterwards.  Linear problems on a handle set up with
- * options.sdc = 1 (EUNSUPPORTED otherwise). */
+ * (DG form) afterwards.  With the Allen-Cahn reaction the sweep is IMEX: the
+ * reaction explicit with the explicit-Euler weights c_{j+1} - c_j on the
+ * node intervals' left ends (Sec. 5.4).  Handles set up with options.sdc = 1
+ * (EUNSUPPORTED otherwise). */
 int stmg_sdc_sweep(stmg_handle* h, const double* d_u0, double* d_U,
                    int32_t sweeps, double* h_rel);
 
@@ -343,7 +346,10 @@ int stmg_sdc_sweep(stmg_handle* h, const double* d_u0, double* d_U,
  * own multigrid solver to rtol); going up, the coarse corrections e_n are
  * interpolated bilinearly in space and linearly in time between the slab's
  * start and end, V_{n,i} += P ((1 - c_i) e_{n-1} + c_i e_n), followed by
- * the sweeps on the M = 1 levels.  d_U holds the initial guess and receives
+ * the sweeps on the M = 1 levels.  With the Allen-Cahn reaction every sweep
+ * is IMEX (reaction explicit with the explicit-Euler weights, diffusion
+ * implicit) and the coarsest serial sweep runs slab after slab.  d_U holds
+ * the initial guess and receives
  * the iterate; stops at ||b - A U|| / ||b|| <= rtol (in the handle's form)
  * or after max_cycles iterations (stats.cycles = iterations; ENOTCONV,
  * EDIVERGED and ENAN as stmg_solve).  Inner solves stop at rtol: the SDC

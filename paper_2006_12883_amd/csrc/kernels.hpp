@@ -249,6 +249,12 @@ hipError_t launch_sdc_gather(const double* r, const double* acc, double* rhs, in
                              int m, hipStream_t s);
 hipError_t launch_sdc_update(double* U, double* acc, const double* d, int N, int M, int nx, int ny,
                              int bc, double cx, double cy, double lam, double w, int m, hipStream_t s);
+// The same with an explicit Allen-Cahn reaction R(u) = gamma (u - u^3) (IMEX
+// sweep): also acc += we (R(U + d) - R(U)) with U the node's value before the
+// update (we = dt (c_{m+1} - c_m), zero after the last node).
+hipError_t launch_sdc_update_imex(double* U, double* acc, const double* d, int N, int M, int nx, int ny,
+                                  int bc, double cx, double cy, double lam, double w, double gamma,
+                                  double we, int m, hipStream_t s);
 
 // Flexible GMRES on level 0 (FP64).  A set of up to kKrylovMax + 1
 // vectors of n doubles and one coefficient per vector, both passed by value.

@@ -96,6 +96,28 @@ __global__ __launch_bounds__(kBlock) void k_newton_coef_pair(size_t n, const dou
   }
 }
 
+// SDC update with the explicit reaction of the IMEX sweep (see kernels.hpp).
+__global__ __launch_bounds__(kBlock) void k_sdc_update_imex(double* __restrict__ U, double* __restrict__ acc,
+                                                            const double* __restrict__ d, int N, int M, int nx,
+                                                            int ny, int bc, double cx, double cy, double lam,
+                                                            double w, double gamma, double we, int m) {
+  const int P = nx * ny;
+  const size_t total = (size_t)N * P;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += stride) {
+    const size_t n = e / P;
+    const int q = (int)(e % P);
+    const int x = q % nx, y = q / nx;
+    const double* D = d + n * P;
+    const double c = D[q];
+    double l = cx * (D[y * nx + nb_lo(x, nx, bc)] + D[y * nx + nb_hi(x, nx, bc)] - 2.0 * c);
+    if (ny > 1) l += cy * (D[nb_lo(y, ny, bc) * nx + x] + D[nb_hi(y, ny, bc) * nx + x] - 2.0 * c);
+    double* u = U + (n * M + m) * P + q;
+    const double uo = *u, un = uo + c;
+    *u = un;
+    acc[e] += w * (l - lam * c) + we * gamma * ((un - un * un * un) - (uo - uo * uo * uo));
+  }
+}
 }  // namespace
 
 hipError_t launch_newton_coef_pair(size_t n, const double* U, double gamma, double* c64, float* c32,
@@ -192,6 +214,14 @@ hipError_t launch_node_transform(double* r, int N, int M, int P, const double* G
 hipError_t launch_sdc_gather(const double* r, const double* acc, double* rhs, int N, int M, int P,
                              int m, hipStream_t s) {
   hipLaunchKernelGGL(k_sdc_gather, dim3(grid_for((size_t)N * P)), dim3(kBlock), 0, s, r, acc, rhs, N, M, P, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_sdc_update_imex(double* U, double* acc, const double* d, int N, int M, int nx, int ny,
+                                  int bc, double cx, double cy, double lam, double w, double gamma,
+                                  double we, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_sdc_update_imex, dim3(grid_for((size_t)N * nx * ny)), dim3(kBlock), 0, s, U, acc, d, N,
+                     M, nx, ny, bc, cx, cy, lam, w, gamma, we, m);
   return hipGetLastError();
 }
 

@@ -1,13 +1,15 @@
-// PFASST (Sec. 4.1; Sec. 5.2, PFASST item) for linear problems: multilevel
-// SDC on the collocation form with FAS corrections between levels.  Level 0
+// PFASST (Sec. 4.1; Sec. 5.2, PFASST item): multilevel SDC on the
+// collocation form with FAS corrections between levels; an Allen-Cahn
+// reaction R(u) = gamma (u - u^3) is explicit in every sweep (IMEX, Sec. 5.4)
+// and enters F = L + R in the FAS terms.  Level 0
 // is the handle's grid with its M Radau nodes, swept by the SDC sweep of the
 // handle (Solver::sdc_core); every coarser level has M = 1 and half the
 // elements of the one above, with its own M = 1 solver for the slab solves.
 //
 // Level problem, slab n, node i (V_{-1,M} = the level's initial value u0_l):
-//   V_{n,i} - dt (Q (x) L_l) V_n |_i - V_{n-1,M} = tau_{l,n,i},   tau_0 = 0.
+//   V_{n,i} - dt (Q (x) F_l) V_n |_i - V_{n-1,M} = tau_{l,n,i},   tau_0 = 0.
 // FAS restriction to level l+1 (end node, space full weighting R_s):
-//   tau_{l+1,n} = R_s [tau_{l,n,M} + dt (Q L_l V_n)_M] - dt L_{l+1} R_s V_{n,M},
+//   tau_{l+1,n} = R_s [tau_{l,n,M} + dt (Q F_l V_n)_M] - dt F_{l+1} R_s V_{n,M},
 //   V_{l+1} = R_s V_{.,M}   (the level's terms in V_{n-1,M} cancel).
 // Correction of level l (linear in time between the slab's start and end):
 //   V_{l,n,i} += P_s ((1 - c_i) e_{n-1} + c_i e_n),  e_n = V_{l+1,n} - R_s V_{l,n,M},
@@ -38,14 +40,21 @@ __device__ __forceinline__ double pf_lap(const double* __restrict__ u, int x, in
 struct PfGrid {
   int nx, ny, bc;
   double cx, cy, lam;
+  double gamma;  // explicit Allen-Cahn reaction (0: linear)
 };
+
+// F(u) at a point: (L u) + gamma (u - u^3)
+__device__ __forceinline__ double pf_F(const double* __restrict__ u, int x, int y, const PfGrid& g) {
+  const double v = u[y * g.nx + x];
+  return pf_lap(u, x, y, g.nx, g.ny, g.bc, g.cx, g.cy, g.lam) + g.gamma * (v - v * v * v);
+}
 
 // per-node weights passed by value (last row of Q, or the nodes c)
 struct PfNodes {
   double w[kMaxM];
 };
 
-// z_n = tau_n + dt sum_j q_j (L V_{n,j})  on the finer grid (tau may be null).
+// z_n = tau_n + dt sum_j q_j F(V_{n,j})  on the finer grid (tau may be null).
 __global__ __launch_bounds__(kPfBlock) void k_pf_z(const double* __restrict__ V, const double* __restrict__ tau,
                                                    double* __restrict__ z, int N, int M, PfGrid g, double dt,
                                                    PfNodes q) {
@@ -56,7 +65,7 @@ __global__ __launch_bounds__(kPfBlock) void k_pf_z(const double* __restrict__ V,
     const int x = p % g.nx, y = p / g.nx;
     double s = 0.0;
     for (int j = 0; j < M; ++j)
-      s += q.w[j] * pf_lap(V + ((size_t)n * M + j) * P, x, y, g.nx, g.ny, g.bc, g.cx, g.cy, g.lam);
+      s += q.w[j] * pf_F(V + ((size_t)n * M + j) * P, x, y, g);
     z[e] = (tau ? tau[e] : 0.0) + dt * s;
   }
 }
@@ -86,7 +95,7 @@ __global__ __launch_bounds__(kPfBlock) void k_pf_restrict(const double* __restri
   }
 }
 
-// tau_n = (R z)_n - dt L (R V_M)_n;  V_n = (R V_M)_n   on the coarser grid
+// tau_n = (R z)_n - dt F (R V_M)_n;  V_n = (R V_M)_n   on the coarser grid
 __global__ __launch_bounds__(kPfBlock) void k_pf_tau(const double* __restrict__ pack, double* __restrict__ tau,
                                                      double* __restrict__ V, int N, PfGrid g, double dt) {
   const int P = g.nx * g.ny;
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(kPfBlock) void k_pf_tau(const double* __restrict__ 
     const int x = p % g.nx, y = p / g.nx;
     const double* rz = pack + ((size_t)n * 2) * P;
     const double* rv = rz + P;
-    tau[e] = rz[p] - dt * pf_lap(rv, x, y, g.nx, g.ny, g.bc, g.cx, g.cy, g.lam);
+    tau[e] = rz[p] - dt * pf_F(rv, x, y, g);
     V[e] = rv[p];
   }
 }
@@ -131,14 +140,32 @@ __global__ __launch_bounds__(kPfBlock) void k_pf_correct(double* __restrict__ V,
   }
 }
 
-// rhs_n = V_{n-1} + tau_n  (V_{-1} = u0): the slab solves of a Jacobi sweep at M = 1
+// rhs_n = V_{n-1} + tau_n + dt R(V_n)  (V_{-1} = u0): the slab solves
+// (I - dt L) V'_n = rhs_n of a Jacobi sweep at M = 1 (R = 0 when linear)
 __global__ __launch_bounds__(kPfBlock) void k_pf_jrhs(const double* __restrict__ V, const double* __restrict__ tau,
                                                       const double* __restrict__ u0, double* __restrict__ rhs, int N,
-                                                      int P) {
+                                                      int P, double dt, double gamma) {
   const size_t total = (size_t)N * P;
   for (size_t e = (size_t)blockIdx.x * kPfBlock + threadIdx.x; e < total; e += (size_t)gridDim.x * kPfBlock) {
     const size_t n = e / P, p = e % P;
-    rhs[e] = (n > 0 ? V[e - P] : u0[p]) + tau[e];
+    const double v = V[e];
+    rhs[e] = (n > 0 ? V[e - P] : u0[p]) + tau[e] + dt * gamma * (v - v * v * v);
+  }
+}
+
+// The serial IMEX sweep at M = 1, slab n: rhs = a + dt (R(a) - R(a_old)) +
+// dt R(V_old_n) + tau_n with a the new end value of slab n - 1 (u0 for n = 0)
+// and a_old its incoming value; then (I - dt L) V_n = rhs.
+__global__ __launch_bounds__(kPfBlock) void k_pf_srhs(const double* __restrict__ V, const double* __restrict__ Vold,
+                                                      const double* __restrict__ tau, const double* __restrict__ u0,
+                                                      double* __restrict__ rhs, int n, int P, double dt,
+                                                      double gamma) {
+  auto R = [&](double v) { return gamma * (v - v * v * v); };
+  for (int p = blockIdx.x * kPfBlock + threadIdx.x; p < P; p += gridDim.x * kPfBlock) {
+    const double a = n > 0 ? V[(size_t)(n - 1) * P + p] : u0[p];
+    const double ao = n > 0 ? Vold[(size_t)(n - 1) * P + p] : u0[p];
+    const double vo = Vold[(size_t)n * P + p];
+    rhs[p] = a + dt * (R(a) - R(ao)) + dt * R(vo) + tau[(size_t)n * P + p];
   }
 }
 
@@ -175,9 +202,10 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
   const int N = lv[0].N, M0 = prob.M;
   const double dt = prob.dt;
   // level l: grid, nodes, iterate, FAS right-hand side
+  const double gam = allen_cahn ? prob.gamma : 0.0;
   auto grid = [&](int l) {
     const OpParams& o = l == 0 ? lv[0].op : pf[l - 1].sol->lv[0].op;
-    return PfGrid{o.nx, o.ny, o.bc, o.cx, o.cy, o.lam};
+    return PfGrid{o.nx, o.ny, o.bc, o.cx, o.cy, o.lam, gam};
   };
   auto nodes = [&](int l) { return l == 0 ? M0 : 1; };
   auto iter = [&](int l) { return l == 0 ? U : pf[l - 1].V; };
@@ -228,7 +256,7 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
     PfLevel& q = pf[l - 1];
     const size_t P = static_cast<size_t>(q.nx) * q.ny;
     hipLaunchKernelGGL(k_pf_jrhs, dim3(pf_blocks(N * P)), dim3(kPfBlock), 0, stream, q.V, q.tau, q.u0, q.rhs, N,
-                       static_cast<int>(P));
+                       static_cast<int>(P), dt, gam);
     PF_CHECK(hipGetLastError());
     return level_solve(q, q.rhs, nullptr);
   };
@@ -264,10 +292,43 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
                          pf[l].V, N, c, dt);
       PF_CHECK(hipGetLastError());
     }
-    // the coarsest level: its block lower-bidiagonal system, all slabs at once
-    {
+    // the coarsest level: the serial sweep.  Linear: it solves the level's
+    // block lower-bidiagonal system, done for all slabs at once.  IMEX: slab
+    // after slab with the one-slab solver, nu times.
+    if (!pf.back().serial) {
       const int rc = level_solve(pf.back(), pf.back().tau, pf.back().u0);
       if (rc) return rc;
+    } else {
+      PfLevel& q = pf.back();
+      Solver* S1 = q.sol.get();
+      const size_t P = static_cast<size_t>(q.nx) * q.ny;
+      for (int k = 0; k < nu; ++k) {
+        PF_CHECK(hipMemcpyAsync(q.rhs, q.V, N * P * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        for (int n = 0; n < N; ++n) {
+          double* rhs = q.pack + static_cast<size_t>(n) * 2 * P;  // slot 0 (R z) is spent
+          double* Vn = q.V + static_cast<size_t>(n) * P;
+          hipLaunchKernelGGL(k_pf_srhs, dim3(pf_blocks(P)), dim3(kPfBlock), 0, stream, q.V, q.rhs, q.tau, q.u0, rhs,
+                             n, static_cast<int>(P), dt, gam);
+          PF_CHECK(hipGetLastError());
+          if (S1->lv.size() == 1) {
+            PF_CHECK(S1->coarse<double>(false, REACT_CONST, rhs, nullptr, Vn));  // exact
+          } else {
+            int np = 0;
+            double b2 = 0.0;
+            PF_CHECK(launch_sumsq(rhs, P, part, &np, stream));
+            PF_CHECK(launch_sum_partials(part, np, scal + 2, stream));
+            const int rc = read_scalar(scal + 2, &b2);
+            if (rc) return rc;
+            if (!std::isfinite(b2)) return STMG_ENAN;
+            if (b2 == 0.0) {
+              PF_CHECK(hipMemsetAsync(Vn, 0, P * sizeof(double), stream));
+              continue;
+            }
+            const int rc2 = inner_solve(S1, rhs, nullptr, Vn, std::sqrt(b2));
+            if (rc2) return rc2;
+          }
+        }
+      }
     }
     // up: corrections, then the sweeps of the M = 1 levels
     for (int l = nl - 2; l >= 0; --l) {
@@ -284,7 +345,7 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
       }
     }
     // stop test on level 0
-    PF_CHECK(residual64<double>(false, REACT_CONST, U, nullptr, u0, nullptr, scal));
+    PF_CHECK(residual64<double>(false, allen_cahn ? REACT_AC : REACT_CONST, U, nullptr, u0, nullptr, scal));
     double r2 = 0.0;
     const int rc = read_scalar(scal, &r2);
     if (rc) return rc;

@@ -275,19 +275,21 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
     set_error("pfasst_levels must be 0 or 2..8, pfasst_sweeps 1..16, pfasst_inner_cycles 0..100");
     return STMG_EINVAL;
   }
-  if (o->pfasst_levels >= 2 &&
-      (allen_cahn || o->precision != STMG_PREC_FP64 || o->krylov > 0 || batch_member || decoupled)) {
-    set_error("PFASST: FP64 linear problems without the Krylov method only");
+  if (o->pfasst_levels >= 2 && (o->precision != STMG_PREC_FP64 || o->krylov > 0 || batch_member || decoupled)) {
+    set_error("PFASST: FP64 without the Krylov method only");
     return STMG_EUNSUPPORTED;
   }
   if ((o->sdc || o->smoother == STMG_SMOOTH_SDC || o->pfasst_levels >= 2) && !decoupled) {
-    if (allen_cahn) { set_error("SDC sweeps: linear problems only"); return STMG_EUNSUPPORTED; }
+    // node solves with the implicit (linear) part only: an Allen-Cahn reaction
+    // is explicit in the sweep (IMEX)
     for (int m = 0; m < M; ++m) {
       const long double dc = tab.c[m] - (m > 0 ? tab.c[m - 1] : 0.0L);
       sdc_w[m] = static_cast<double>(p->dt * dc);
       stmg_problem sp = *p;
       sp.M = 1;
       sp.dt = sdc_w[m];
+      sp.reaction = STMG_REACT_LINEAR;
+      sp.gamma = 0.0;
       stmg_options so = *o;
       so.sdc = 0;
       so.pfasst_levels = 0;
@@ -320,6 +322,8 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
       sp.nx[0] = ex;
       sp.nx[1] = twod ? ey : 1;
       sp.M = 1;
+      sp.reaction = STMG_REACT_LINEAR;  // the reaction stays explicit (IMEX)
+      sp.gamma = 0.0;
       stmg_options so = *o;
       so.pfasst_levels = 0;
       so.sdc = 0;
@@ -335,6 +339,14 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
       if (l + 1 < o->pfasst_levels) {
         so.coarsen = STMG_COARSEN_SPACE;
         q.sol->decoupled = true;
+      } else if (allen_cahn) {
+        // the serial IMEX sweep solves slab after slab: a one-slab solver,
+        // exact in one level where the plane allows (Fourier or dense)
+        sp.N = 1;
+        q.serial = true;
+        const int px = p->bc == STMG_BC_PERIODIC ? ex : ex + 1;
+        const int py = twod ? (p->bc == STMG_BC_PERIODIC ? ey : ey + 1) : 1;
+        if ((p->bc == STMG_BC_PERIODIC && fft_plane_ok(px, py)) || px * py <= 1024) so.max_levels = 1;
       }
       int rc = q.sol->build(&sp, &so);
       if (rc) return rc;
@@ -1813,13 +1825,13 @@ int Solver::adjoint(const double* u0, const double* U, const double* gT, double*
 // with the node solves as batched spatial V-cycles, U_m += delta_m.
 int Solver::sdc(const double* u0, double* U, int sweeps, double* h_rel) {
   if (sdcn.empty() || win) {
-    set_error("stmg_sdc_sweep: set up the handle with options.sdc = 1 (linear problems)");
+    set_error("stmg_sdc_sweep: set up the handle with options.sdc = 1");
     return STMG_EUNSUPPORTED;
   }
   const int rc = sdc_core(u0, U, sweeps);
   if (rc) return rc;
   if (h_rel) {
-    HIP_CHECK(residual64<double>(false, REACT_CONST, U, nullptr, u0, nullptr, scal));
+    HIP_CHECK(residual64<double>(false, allen_cahn ? REACT_AC : REACT_CONST, U, nullptr, u0, nullptr, scal));
     double r2 = 0.0;
     const int rc2 = read_scalar(scal, &r2);
     if (rc2) return rc2;
@@ -1849,7 +1861,7 @@ int Solver::sdc_core(const double* u0, double* U, int sweeps) {
   const int N = L0.N, M = prob.M, P = L0.nx * L0.ny;
   const size_t NP = static_cast<size_t>(N) * P;
   for (int s = 0; s < sweeps; ++s) {
-    HIP_CHECK(residual64<double>(false, REACT_CONST, U, nullptr, u0, delta64, scal));
+    HIP_CHECK(residual64<double>(false, allen_cahn ? REACT_AC : REACT_CONST, U, nullptr, u0, delta64, scal));
     HIP_CHECK(launch_node_transform(delta64, N, M, P, sdc_G, stream));
     HIP_CHECK(hipMemsetAsync(sdc_acc, 0, NP * sizeof(double), stream));
     for (int m = 0; m < M; ++m) {
@@ -1863,8 +1875,13 @@ int Solver::sdc_core(const double* u0, double* U, int sweeps) {
       double rel = 0.0;
       const int rc = inner_solve(S, rhs, nullptr, S->delta64, -1.0);
       if (rc) return rc;
-      HIP_CHECK(launch_sdc_update(U, sdc_acc, S->delta64, N, M, L0.nx, L0.ny, L0.op.bc, L0.op.cx,
-                                  L0.op.cy, L0.op.lam, sdc_w[m], m, stream));
+      if (allen_cahn)
+        HIP_CHECK(launch_sdc_update_imex(U, sdc_acc, S->delta64, N, M, L0.nx, L0.ny, L0.op.bc, L0.op.cx,
+                                         L0.op.cy, L0.op.lam, sdc_w[m], L0.op.gamma,
+                                         m + 1 < M ? sdc_w[m + 1] : 0.0, m, stream));
+      else
+        HIP_CHECK(launch_sdc_update(U, sdc_acc, S->delta64, N, M, L0.nx, L0.ny, L0.op.bc, L0.op.cx,
+                                    L0.op.cy, L0.op.lam, sdc_w[m], m, stream));
     }
   }
   return STMG_OK;

@@ -209,6 +209,7 @@ struct Solver {
     double* pack = nullptr;  // [N][2][P]: R_s z, R_s V_M of the level above
     double* u0 = nullptr;
     std::unique_ptr<Solver> sol;
+    bool serial = false;  // sol is a one-slab solver (the IMEX serial sweep)
   };
   std::vector<PfLevel> pf;
   double* pf_pack = nullptr;  // [N][2][P] on the finer level of a transfer

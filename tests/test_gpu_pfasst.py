@@ -95,6 +95,72 @@ def test_inexact_inner_solves_converge(inner):
     assert rel_err(U.cpu().numpy(), ref) <= 1e-10
 
 
+# Allen-Cahn: IMEX sweeps (reaction explicit), the coarsest level swept slab
+# after slab (one-slab Fourier or dense solves; the Neumann 33^2 plane takes
+# the one-slab multigrid solver)
+AC = [
+    ("2d-AC-L2", si.problem(2, 32, 3, 8, 0.4, nu=0.02, gamma=1.0, reaction="allen_cahn"), 2, 1),
+    ("2d-AC-L3-nu2", si.problem(2, 32, 2, 6, 0.3, nu=0.01, gamma=2.0, reaction="allen_cahn"), 3, 2),
+    ("1d-AC-L3", si.problem(1, 64, 3, 12, 0.5, nu=0.05, gamma=1.0, reaction="allen_cahn"), 3, 1),
+    ("1d-AC-neumann-L2", si.problem(1, 32, 2, 8, 0.4, nu=0.05, gamma=1.0, reaction="allen_cahn",
+                                    bc="neumann"), 2, 1),
+    ("2d-AC-neumann-L2", si.problem(2, 64, 2, 4, 0.1, nu=0.01, gamma=1.0, reaction="allen_cahn",
+                                    bc="neumann"), 2, 1),
+]
+
+
+def _u0_ac(prob, seed):
+    return 0.8 * np.tanh(_u0(prob, seed))
+
+
+@pytest.mark.parametrize("name,prob,levels,nu", AC)
+def test_imex_iterations_match_oracle(name, prob, levels, nu):
+    print("case", name, flush=True)
+    u0 = _u0_ac(prob, 1)
+    levs = pfasst.hierarchy(prob, levels)
+    u0s = pfasst.initial_values(levs, u0)
+    X = 0.8 * np.tanh(np.random.default_rng(2).standard_normal(levs[0].shape))
+    h = H(prob, pfasst_levels=levels, pfasst_sweeps=nu, rtol=1e-13, max_cycles=1)
+    Ud = T(X)
+    ref = X
+    for k in range(3):
+        ref = pfasst.iteration(levs, u0s, ref, nu)
+        _, st = h.pfasst(T(u0), Ud, check=False)
+        assert st["cycles"] == 1 and st["status"] in (0, -4), st
+        assert_close(Ud.cpu().numpy(), ref, 1e-10, "IMEX iteration %d" % (k + 1))
+
+
+def test_imex_sdc_sweep_matches_oracle():
+    """stmg_sdc_sweep on an Allen-Cahn handle is the IMEX sweep (the oracle's
+    level-0 PFASST sweep with tau = 0)."""
+    print("case imex sdc sweep", flush=True)
+    prob = si.problem(2, 32, 3, 8, 0.4, nu=0.02, gamma=1.5, reaction="allen_cahn")
+    u0 = _u0_ac(prob, 3)
+    lev = pfasst.PLevel(prob)
+    X = 0.8 * np.tanh(np.random.default_rng(4).standard_normal(lev.shape))
+    ref = X
+    h = H(prob, sdc=1, rtol=1e-13)
+    Ud = T(X)
+    for k in range(3):
+        ref = lev.sweep(ref, u0, np.zeros(lev.shape), serial=False)
+        h.sdc_sweep(T(u0), Ud, 1)
+        assert_close(Ud.cpu().numpy(), ref, 1e-10, "IMEX sweep %d" % (k + 1))
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_imex_converges_to_implicit_stepper(levels):
+    print("case imex solve", levels, flush=True)
+    prob = si.problem(2, 64, 3, 16, 0.5, nu=1e-3, gamma=1.0, reaction="allen_cahn")
+    u0 = si.initial("ac2d", prob)
+    ref = stepper.solve_allen_cahn(prob, u0)
+    h = H(prob, pfasst_levels=levels, rtol=1e-12, max_cycles=300)
+    U, st = h.pfasst(T(u0))
+    print("iterations", st["cycles"], "rel", st["rel_res"], flush=True)
+    assert st["status"] == 0
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-10
+    assert rel_err(U.cpu().numpy()[-1, -1], ref[-1, -1]) <= 1e-10
+
+
 def test_pfasst_needs_its_levels():
     print("case no levels", flush=True)
     prob = si.problem(2, 16, 2, 4, 0.2, nu=0.05, lam=1.0)
