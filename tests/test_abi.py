@@ -113,8 +113,8 @@ def test_galerkin_option_validation_and_workspace():
 
 
 def test_pfasst_option_validation_and_workspace():
-    """PFASST levels: accepted for FP64 linear problems whose element counts
-    stay even down the levels, adding the coarse levels' vectors and solvers
+    """PFASST levels: accepted for FP64 problems (Allen-Cahn IMEX) whose
+    element counts stay even down the levels, adding the coarse levels' vectors and solvers
     to the workspace; refused (workspace 0) otherwise."""
     import stmg_inputs as si
     prob = si.config("rd2d")
@@ -129,7 +129,8 @@ def test_pfasst_option_validation_and_workspace():
     assert ws(prob, pfasst_levels=2, pfasst_inner_cycles=2) > 0
     assert ws(prob, pfasst_levels=2, pfasst_inner_cycles=-1) == 0
     assert ws(prob, pfasst_levels=2, pfasst_inner_cycles=101) == 0
-    assert ws(si.config("ac2d"), pfasst_levels=2) == 0
+    assert ws(si.config("ac2d"), pfasst_levels=2) > 0                   # IMEX
+    assert ws(si.config("ac2d"), pfasst_levels=2, precision="mixed") == 0
     assert ws(dict(prob, nx=[10, 10]), pfasst_levels=3) == 0  # 10 -> 5 elements, odd: no second halving
     assert ws(dict(prob, nx=[12, 12]), pfasst_levels=3) > 0   # 12 -> 6 -> 3
     assert ws(dict(prob, nx=[8, 8]), pfasst_levels=2) > 0     # 8 -> 4
