@@ -123,6 +123,7 @@ template <typename T>
 hipError_t launch_smooth9(const OpParams& p, const Stencil9& st, const T* U, const T* f, T* out, int chunk,
                           hipStream_t s);
 
+
 // Exact solve of the block lower-bidiagonal coarsest system:
 // U_n = Ainv (f_n + cin (x) (cout . U_{n-1}))   (u0 enters slab 0 if given).
 template <typename T>
