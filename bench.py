@@ -598,6 +598,17 @@ def _timed_solve(h, u0, U):
     return U, st, time.perf_counter() - t0
 
 
+def _timed_pfasst(h, u0, U):
+    import torch
+    h.pfasst(u0, U, check=False)
+    U.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = h.pfasst(u0, U, check=False)
+    torch.cuda.synchronize()
+    return U, st, time.perf_counter() - t0
+
+
 def paper_examples(dev):
     """The paper's 1D examples (Sec. 5) on one GPU: the heat example with
     N_x = 1024 and N_t per M from its tables, stopped at 1e-9, with the
@@ -653,8 +664,26 @@ def paper_examples(dev):
         mono["M%d_Nt%d" % (M, prob["N"])] = {"ms": 1e3 * t, "status": st["status"], "newton_its": st["newton_its"],
                                             "vcycles": st["cycles"], "rel_res": st["rel_res"]}
         del h, U
+    # PFASST^3_1 (Sec. 5.2: M = 1 and bisection on the coarse levels, one sweep
+    # per level) on both examples, every slab at once (one slab per core in
+    # the paper's terms); inner solves to rtol and cut to 2 V-cycles;
+    # the monodomain reaction explicit (IMEX, Sec. 5.4)
+    pf = {}
+    for name, mk, u0f in (("heat", si.paper_heat1d, si.u0_paper_heat1d),
+                          ("monodomain", si.paper_monodomain, si.u0_paper_monodomain)):
+        for M in (1, 2, 3, 4, 5):
+            prob = mk(M)
+            u0 = torch.as_tensor(u0f(prob)).to(dev)
+            for inner in (0, 2):
+                h = stmg.Handle(prob, device=dev, pfasst_levels=3, pfasst_inner_cycles=inner, rtol=1e-9,
+                                max_cycles=300)
+                U = torch.zeros(h.shape, dtype=torch.float64, device=dev)
+                _, st, t = _timed_pfasst(h, u0, U)
+                pf["%s_M%d_Nt%d%s" % (name, M, prob["N"], "_inner2" if inner else "")] = {
+                    "ms": 1e3 * t, "status": st["status"], "iterations": st["cycles"], "rel_res": st["rel_res"]}
+                del h, U
     return {"heat_Nx1024_to_1e-9": heat, "heat_weak_Nt_SMGL_V33_fgmres10_to_1e-9": weak,
-            "monodomain_SMG7_V33_fgmres10_to_1e-9": mono}
+            "monodomain_SMG7_V33_fgmres10_to_1e-9": mono, "pfasst3_1_to_1e-9": pf}
 
 
 def main():
