@@ -1,6 +1,11 @@
 """Builds libstmg.so (HIP for gfx950) in-tree with hipcc.
 
 Run as ``python -m paper_2006_12883_amd.build`` or call ``build()``.
+``--host-sanitize`` builds libstmg_hostsan.so instead: the host code with
+AddressSanitizer and UndefinedBehaviorSanitizer (device code unchanged), for
+loading through ``binding.LIB_PATH`` with the ASan runtime preloaded on a
+machine without a GPU (the setup paths: hierarchies, tables, Galerkin
+stencils, PFASST levels, windows, batch sizing).
 """
 import os
 import subprocess
@@ -20,14 +25,23 @@ FLAGS = [
 ]
 
 
-def build(verbose=False, jobs=None):
+HOST_SANITIZE = ["-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build(verbose=False, jobs=None, host_sanitize=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
     procs = []
-    os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
+    bdir = os.path.join(HERE, "_build_hostsan" if host_sanitize else "_build")
+    lib = os.path.join(HERE, "libstmg_hostsan.so") if host_sanitize else LIB
+    flags = [f for f in FLAGS if f != "-shared" and not (host_sanitize and f == "-O3")]
+    if host_sanitize:
+        flags += HOST_SANITIZE
+    os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
-        obj = os.path.join(HERE, "_build", os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc] + [f for f in FLAGS if f != "-shared"] + ["-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd = [hipcc, "-x", "hip"] + cmd[1:]
         if verbose:
@@ -46,12 +60,14 @@ def build(verbose=False, jobs=None):
         for src, text in failed:
             sys.stderr.write("---- %s ----\n%s\n" % (src, text))
         raise RuntimeError("hipcc failed for " + ", ".join(s for s, _ in failed))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    if host_sanitize:
+        cmd[4:4] = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, host_sanitize="--host-sanitize" in sys.argv))
