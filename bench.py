@@ -417,8 +417,39 @@ def _extra_batch(dev):
                             "max_rel_res": max(st["rel_res"] for st in sts)}
     del b, Us
     torch.cuda.empty_cache()
+    out["batch64_mixed"]["cpu_baseline"] = _batch_cpu_baseline(probs, t)
     print("batch done", file=sys.stderr, flush=True)
     return out
+
+
+def _batch_cpu_baseline(probs, gpu_seconds):
+    """The oracle's Fourier closed form (oracle.fourier, the exact collocation
+    solution of a periodic linear problem) on a bounded sample of the batch:
+    every 4th problem, over a pool of threads, one per host core up to 16
+    (numpy's transforms and solves release the interpreter lock for part of
+    the work); the time for all 64 problems is extrapolated by unknowns."""
+    from concurrent.futures import ThreadPoolExecutor
+    import stmg_inputs as si
+    from oracle import fourier
+    idx = list(range(0, len(probs), 4))
+    work = [(probs[i], si.batch_u0(probs[i], i)) for i in idx]
+    nthreads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+
+    def one(a):
+        prob, u0 = a
+        return float(np.abs(fourier.solve_linear_periodic(prob, u0)[-1, -1]).max())
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(nthreads) as ex:
+        list(ex.map(one, work))
+    t = time.perf_counter() - t0
+    dof = lambda p: p["nx"][0] * p["nx"][1] * p["M"] * p["N"]
+    ds = float(sum(dof(p) for p, _ in work))
+    da = float(sum(dof(p) for p in probs))
+    return {"value": t * da / ds, "unit": "s for the 64 problems (extrapolated by unknowns)", "cores": nthreads,
+            "kind": "oracle", "sample": "%d of the %d problems (every 4th), the Fourier closed form, %d threads; "
+                                       "%.1f s wall" % (len(work), len(probs), nthreads, t),
+            "sample_seconds": t, "sample_dof": ds, "gpu_seconds_to_1e-10": gpu_seconds}
 
 
 def _extra_sdc(dev):
