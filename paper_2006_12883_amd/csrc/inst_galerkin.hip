@@ -4,137 +4,15 @@
 
 namespace stmg {
 namespace {
-// Galerkin coarse levels (periodic, 3 x 3 mass and stiffness stencils).  One
-// thread = one point x a run of slabs; the coupling values cout . U_{n-1} at
-// the 9 stencil points stay in registers from one slab to the next.
-
-// Plane offsets of the 9 stencil points of (x, y) (periodic wrap; 1D: the
-// middle row only).
-template <bool TWOD>
-__device__ __forceinline__ void offsets9(int x, int y, int nx, int ny, int off[9]) {
-  const int xm = x > 0 ? x - 1 : nx - 1, xp = x + 1 < nx ? x + 1 : 0;
-  const int ym = TWOD ? (y > 0 ? y - 1 : ny - 1) : y, yp = TWOD ? (y + 1 < ny ? y + 1 : 0) : y;
-  const int ys[3] = {ym, y, yp}, xs[3] = {xm, x, xp};
-#pragma unroll
-  for (int k = 0; k < 9; ++k) off[k] = ys[k / 3] * nx + xs[k % 3];
-}
-
-// The 9 stencil values of node m's plane at slab base (TWOD false: rows dy = +-1 unused).
-template <typename T, bool TWOD>
-__device__ __forceinline__ void load9(const T* __restrict__ Um, const int off[9], T v[9]) {
-#pragma unroll
-  for (int k = 0; k < 9; ++k) v[k] = (TWOD || k / 3 == 1) ? Um[off[k]] : T(0);
-}
-
-template <typename T, bool TWOD>
-__device__ __forceinline__ T apply9(const T w[9], const T v[9]) {
-  T s = T(0);
-#pragma unroll
-  for (int k = 0; k < 9; ++k)
-    if (TWOD || k / 3 == 1) s += w[k] * v[k];
-  return s;
-}
-
-// r = f - A U at point q for every slab of [n0, n1); with SMOOTH also the
-// block-Jacobi update out = U + omega d along the run (one smoother chunk).
-template <int M, typename T, bool TWOD, bool SMOOTH>
-__global__ __launch_bounds__(kBlock) void k_level9(const OpParams p, const Stencil9 st, const T* __restrict__ U,
-                                                   const T* __restrict__ f, T* __restrict__ out, int S,
-                                                   int tiles, int nblocks) {
-  const int lb = xcd_remap(blockIdx.x, nblocks);
-  const int q = (lb % tiles) * kBlock + threadIdx.x;
-  const int n0 = (lb / tiles) * S;
-  const int nx = p.nx, ny = p.ny, P = nx * ny;
-  if (q >= P || n0 >= p.N) return;
-  const int n1 = min(n0 + S, p.N);
-  const Consts<M, T> c(p);
-  T ms[9], ks[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    ms[k] = (T)st.m[k];
-    ks[k] = (T)st.k[k];
-  }
-  int off[9];
-  offsets9<TWOD>(q % nx, q / nx, nx, ny, off);
-  // coupling values entering the run: cout . U_{n0-1} at the 9 points
-  T prev[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) prev[k] = T(0);
-  if (n0 > 0 && U) {
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      if (c.cout[m] == T(0)) continue;
-      T v[9];
-      load9<T, TWOD>(U + ((size_t)(n0 - 1) * M + m) * P, off, v);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) prev[k] += c.cout[m] * v[k];
-    }
-  }
-  T dprev = T(0);
-  for (int n = n0; n < n1; ++n) {
-    const size_t base = (size_t)n * M * P;
-    T v[M][9];
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      if (U) load9<T, TWOD>(U + base + (size_t)m * P, off, v[m]);
-      else {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) v[m][k] = T(0);
-      }
-    }
-    T mv[M], r[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) mv[m] = apply9<T, TWOD>(ms, v[m]);
-    const T mprev = apply9<T, TWOD>(ms, prev);
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      T au = T(0);
-#pragma unroll
-      for (int j = 0; j < M; ++j) au += c.K[i][j] * mv[j];
-      au += c.db[i] * apply9<T, TWOD>(ks, v[i]);
-      au -= c.cin[i] * mprev;
-      const T fi = f ? f[base + (size_t)i * P + q] : T(0);
-      r[i] = fi - au;
-    }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      T s = T(0);
-#pragma unroll
-      for (int m = 0; m < M; ++m) s += c.cout[m] * v[m][k];
-      prev[k] = s;
-    }
-    if (SMOOTH) {
-      if (n > n0) {
-#pragma unroll
-        for (int i = 0; i < M; ++i) r[i] += c.cin[i] * ms[4] * dprev;
-      }
-      T d[M], nd = T(0);
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        T sm = T(0);
-#pragma unroll
-        for (int j = 0; j < M; ++j) sm += c.Bi[i][j] * r[j];
-        d[i] = sm;
-      }
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        out[base + (size_t)i * P + q] = v[i][4] + c.omega * d[i];
-        nd += c.cout[i] * d[i];
-      }
-      dprev = nd;
-    } else {
-#pragma unroll
-      for (int i = 0; i < M; ++i) out[base + (size_t)i * P + q] = r[i];
-    }
-  }
-}
-
-// The same operator on pairs of points (x0, x0 + 1), x0 even: a thread loads
-// each stencil row as one pair and two single values (4 columns for both
-// points instead of 3 for each), and keeps the coupling values cout . U_{n-1}
-// at the 3 x 4 positions.  Per point the arithmetic is that of k_level9,
-// operation for operation.  SMOOTH false: residual r = f - A U; true: one
-// smoothing sweep over the run (one chunk).
+// Galerkin coarse levels (periodic, 3 x 3 mass and stiffness stencils,
+// entry [(dy + 1) * 3 + dx + 1] weighing u(x + dx, y + dy)).  One thread =
+// one pair of points (x0, x0 + 1), x0 even, x a run of slabs: each stencil row
+// of a node plane is loaded as one pair and two single values (4 columns for
+// both points), and the coupling values cout . U_{n-1} at the 3 x 4 positions
+// stay in registers from one slab to the next.  SMOOTH false: residual
+// r = f - A U; true: one block-Jacobi sweep over the run (one smoother chunk):
+// r += cin m_0 (cout . d_{n-1}) inside the chunk, d = (K m_0 + diag(db) k_0)^-1 r,
+// U' = U + omega d.
 template <typename T>
 __device__ __forceinline__ void ld_pair(const T* __restrict__ b, T& x, T& y) {
   typedef T v2 __attribute__((ext_vector_type(2)));
@@ -305,43 +183,20 @@ static hipError_t launch_pairs(const OpParams& p, const Stencil9& st, const T* U
 }
 
 // Galerkin levels: residual (runs of 8 slabs) and smoothing sweep (runs of
-// one chunk), on point pairs when nx is even, else one thread per point.
+// one chunk).  A Galerkin level is coarsened again, so its point count is
+// even (hipErrorNotSupported otherwise).
 template <typename T>
 hipError_t launch_residual9(const OpParams& p, const Stencil9& st, const T* U, const T* f, T* out,
                             hipStream_t s) {
-  if (p.nx % 2 == 0) return launch_pairs<T, false>(p, st, U, f, out, 8, s);
-  const int P = p.nx * p.ny, S = 8;
-  const int tiles = (P + kBlock - 1) / kBlock;
-  const int nb = tiles * ((p.N + S - 1) / S);
-#define L(MM)                                                                                         \
-  if (p.ny > 1)                                                                                       \
-    hipLaunchKernelGGL((k_level9<MM, T, true, false>), dim3(nb), dim3(kBlock), 0, s, p, st, U, f, out, S, \
-                       tiles, nb);                                                                    \
-  else                                                                                                \
-    hipLaunchKernelGGL((k_level9<MM, T, false, false>), dim3(nb), dim3(kBlock), 0, s, p, st, U, f, out, S, \
-                       tiles, nb);
-  STMG_DISPATCH_M(L)
-#undef L
-  return hipGetLastError();
+  if (p.nx % 2 != 0) return hipErrorNotSupported;
+  return launch_pairs<T, false>(p, st, U, f, out, 8, s);
 }
 
 template <typename T>
 hipError_t launch_smooth9(const OpParams& p, const Stencil9& st, const T* U, const T* f, T* out, int chunk,
                           hipStream_t s) {
-  if (p.nx % 2 == 0) return launch_pairs<T, true>(p, st, U, f, out, chunk, s);
-  const int P = p.nx * p.ny;
-  const int tiles = (P + kBlock - 1) / kBlock;
-  const int nb = tiles * ((p.N + chunk - 1) / chunk);
-#define L(MM)                                                                                        \
-  if (p.ny > 1)                                                                                      \
-    hipLaunchKernelGGL((k_level9<MM, T, true, true>), dim3(nb), dim3(kBlock), 0, s, p, st, U, f, out, chunk, \
-                       tiles, nb);                                                                   \
-  else                                                                                               \
-    hipLaunchKernelGGL((k_level9<MM, T, false, true>), dim3(nb), dim3(kBlock), 0, s, p, st, U, f, out, chunk, \
-                       tiles, nb);
-  STMG_DISPATCH_M(L)
-#undef L
-  return hipGetLastError();
+  if (p.nx % 2 != 0) return hipErrorNotSupported;
+  return launch_pairs<T, true>(p, st, U, f, out, chunk, s);
 }
 
 template hipError_t launch_residual9<double>(const OpParams&, const Stencil9&, const double*, const double*, double*,

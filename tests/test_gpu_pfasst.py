@@ -31,6 +31,7 @@ CASES = [
     ("1d-M3-L3", si.problem(1, 64, 3, 12, 0.2, nu=0.1, lam=0.5), 3, 1),
     ("1d-neumann-L3", si.problem(1, 32, 3, 8, 0.2, nu=0.1, lam=0.5, bc="neumann"), 3, 1),
     ("1d-M1-L2", si.problem(1, 64, 1, 16, 0.3, nu=0.2, lam=0.0), 2, 1),
+    ("1d-M5-L3", si.problem(1, 64, 5, 6, 0.2, nu=0.1, lam=0.2), 3, 1),
 ]
 
 
@@ -168,3 +169,16 @@ def test_pfasst_needs_its_levels():
     with pytest.raises(Exception) as e:
         h.pfasst(T(_u0(prob, 1)))
     assert "pfasst_levels" in str(e.value)
+
+
+def test_full_size_pfasst_matches_multigrid():
+    """PFASST^3_1 with one V-cycle per inner solve on the 256^2 x 3 x 256
+    workload, to 1e-12, against the multigrid solve of the same system."""
+    print("case full pfasst", flush=True)
+    prob = si.config("rd2d")
+    u0 = T(si.initial("rd2d", prob))
+    Up, sp = H(prob, pfasst_levels=3, pfasst_inner_cycles=1, max_cycles=300).pfasst(u0)
+    Ur, sr = H(prob).solve(u0)
+    print("iterations", sp["cycles"], flush=True)
+    assert sp["status"] == 0 and sr["status"] == 0
+    assert float(torch.linalg.norm(Up - Ur) / torch.linalg.norm(Ur)) <= 1e-10
