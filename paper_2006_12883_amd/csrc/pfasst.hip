@@ -263,6 +263,14 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
   const double nb = norm_u0_b(u0);
   if (nb < 0.0) return STMG_EHIP;
   stmg_stats s{};
+  // the statistics are filled on every way out, an inner solve's failure too
+  auto done = [&](int status) {
+    s.status = status;
+    s.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    last = s;
+    if (st) *st = s;
+    return status;
+  };
   int status = STMG_ENOTCONV;
   double rel = 0.0, rel0 = -1.0, prev = 0.0;
   int incr = 0;
@@ -271,11 +279,11 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
     for (int l = 0; l + 1 < nl; ++l) {
       if (l == 0) {
         const int rc = sdc_core(u0, U, nu);
-        if (rc) return rc;
+        if (rc) return done(rc);
       } else {
         for (int k = 0; k < nu; ++k) {
           const int rc = jacobi(l);
-          if (rc) return rc;
+          if (rc) return done(rc);
         }
       }
       const PfGrid f = grid(l), c = grid(l + 1);
@@ -297,7 +305,7 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
     // after slab with the one-slab solver, nu times.
     if (!pf.back().serial) {
       const int rc = level_solve(pf.back(), pf.back().tau, pf.back().u0);
-      if (rc) return rc;
+      if (rc) return done(rc);
     } else {
       PfLevel& q = pf.back();
       Solver* S1 = q.sol.get();
@@ -318,14 +326,14 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
             PF_CHECK(launch_sumsq(rhs, P, part, &np, stream));
             PF_CHECK(launch_sum_partials(part, np, scal + 2, stream));
             const int rc = read_scalar(scal + 2, &b2);
-            if (rc) return rc;
-            if (!std::isfinite(b2)) return STMG_ENAN;
+            if (rc) return done(rc);
+            if (!std::isfinite(b2)) return done(STMG_ENAN);
             if (b2 == 0.0) {
               PF_CHECK(hipMemsetAsync(Vn, 0, P * sizeof(double), stream));
               continue;
             }
             const int rc2 = inner_solve(S1, rhs, nullptr, Vn, std::sqrt(b2));
-            if (rc2) return rc2;
+            if (rc2) return done(rc2);
           }
         }
       }
@@ -340,7 +348,7 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
       if (l > 0) {
         for (int k = 0; k < nu; ++k) {
           const int rc = jacobi(l);
-          if (rc) return rc;
+          if (rc) return done(rc);
         }
       }
     }
@@ -348,7 +356,7 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
     PF_CHECK(residual64<double>(false, allen_cahn ? REACT_AC : REACT_CONST, U, nullptr, u0, nullptr, scal));
     double r2 = 0.0;
     const int rc = read_scalar(scal, &r2);
-    if (rc) return rc;
+    if (rc) return done(rc);
     rel = nb > 0.0 ? std::sqrt(r2) / nb : std::sqrt(r2);
     s.cycles = it + 1;
     if (!std::isfinite(rel)) { status = STMG_ENAN; break; }
@@ -360,11 +368,7 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
     prev = rel;
   }
   s.rel_res = rel;
-  s.status = status;
-  s.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  last = s;
-  if (st) *st = s;
-  return status;
+  return done(status);
 }
 
 }  // namespace stmg

@@ -182,3 +182,19 @@ def test_full_size_pfasst_matches_multigrid():
     print("iterations", sp["cycles"], flush=True)
     assert sp["status"] == 0 and sr["status"] == 0
     assert float(torch.linalg.norm(Up - Ur) / torch.linalg.norm(Ur)) <= 1e-10
+
+
+def test_pfasst_nan_input_and_collocation_stop():
+    """A NaN in u0 ends the iteration with STMG_ENAN; with form = COLLOC the
+    stop test uses the collocation residual and reaches the same solution."""
+    print("case pfasst nan / colloc", flush=True)
+    prob = si.problem(2, 32, 3, 8, 0.25, nu=0.02, lam=1.0)
+    u0 = _u0(prob, 5)
+    bad = u0.copy()
+    bad[3, 4] = np.nan
+    _, st = H(prob, pfasst_levels=2).pfasst(T(bad), check=False)
+    assert st["status"] == -6, st
+    ref = stepper.solve_linear(prob, u0)
+    U, st = H(prob, pfasst_levels=2, form="colloc", rtol=1e-12).pfasst(T(u0))
+    assert st["status"] == 0
+    assert rel_err(U.cpu().numpy(), ref) <= 1e-10
