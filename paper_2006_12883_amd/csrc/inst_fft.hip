@@ -12,13 +12,36 @@
 // The transforms are radix-2 FFTs for power-of-two sides (in registers for
 // 2D planes with sides of at most kFftRegSide, else in LDS) and direct DFTs
 // with twiddles from a table otherwise (planes of at most kFftMaxPlane
-// points); all arithmetic is FP64 whatever the storage type.
+// points).  The arithmetic is FP64 whatever the storage type, except in
+// launch_fft_coarse32 (the FP32 cycles of mixed precision on register-
+// transform planes: FP32 tables, work space and arithmetic).
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace stmg {
 namespace {
 
 constexpr int kFftBlock = 256;
+
+// complex pairs of the arithmetic type A (FP64, or FP32 for the FP32 cycles)
+template <typename A>
+struct V2;
+template <>
+struct V2<double> {
+  typedef double2 t;
+};
+template <>
+struct V2<float> {
+  typedef float2 t;
+};
+template <typename A>
+__device__ __forceinline__ typename V2<A>::t mk2(A x, A y) {
+  typename V2<A>::t v;
+  v.x = x;
+  v.y = y;
+  return v;
+}
 
 #define STMG_DISPATCH_M_FFT(MACRO) \
   switch (p.M) {                   \
@@ -279,29 +302,29 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_inv2(int nx, int ny, int lgx,
 // N (M + 2) MB complex values fit in kFftLds.
 constexpr int kFftLds = 48 * 1024;
 constexpr int kStage = 16;
-template <int M>
-__global__ __launch_bounds__(kFftBlock) void k_fft_modes_lds(int P, int N, int MB, double* __restrict__ F,
-                                                             const double* __restrict__ u0F,
-                                                             const double* __restrict__ Sinv,
+template <int M, typename A>
+__global__ __launch_bounds__(kFftBlock) void k_fft_modes_lds(int P, int N, int MB, A* __restrict__ F,
+                                                             const A* __restrict__ u0F,
+                                                             const A* __restrict__ Sinv,
                                                              const OpParams p,
-                                                             const double* __restrict__ fscale) {
-  __shared__ double L[kFftLds / sizeof(double)];
+                                                             const A* __restrict__ fscale) {
+  __shared__ A L[kFftLds / sizeof(A)];
   const int q0 = blockIdx.x * MB;
   const int mb = min(MB, P - q0);
   const int tid = threadIdx.x;
   const int tot = N * M * mb;
-  double* Lf = L;                          // [(n M + m) MB + qq] complex
-  double* La = L + 2 * (size_t)N * M * MB;  // [n MB + qq] complex: a_n, then p_{n-1}
+  A* Lf = L;                          // [(n M + m) MB + qq] complex
+  A* La = L + 2 * (size_t)N * M * MB;  // [n MB + qq] complex: a_n, then p_{n-1}
   // stage F (loads in batches, all in flight before the LDS writes)
   for (int i0 = 0; i0 < tot; i0 += kFftBlock * kStage) {
-    double re[kStage], im[kStage];
+    A re[kStage], im[kStage];
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {
       const int i = i0 + u * kFftBlock + tid;
       if (i < tot) {
         const int nm = i / mb, qq = i - nm * mb;
         const size_t at = 2 * ((size_t)nm * P + q0 + qq);
-        const double sc = fscale ? fscale[q0 + qq] : 1.0;
+        const A sc = fscale ? fscale[q0 + qq] : A(1.0);
         re[u] = sc * F[at];
         im[u] = sc * F[at + 1];
       }
@@ -320,13 +343,13 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_lds(int P, int N, int M
   // (A) a_n = c . F_n
   for (int i = tid; i < N * mb; i += kFftBlock) {
     const int n = i / mb, qq = i - n * mb;
-    const double* S = Sinv + (size_t)(q0 + qq) * M * M;
-    double ar = 0.0, ai = 0.0;
+    const A* S = Sinv + (size_t)(q0 + qq) * M * M;
+    A ar = A(0.0), ai = A(0.0);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      double c = 0.0;
+      A c = A(0.0);
 #pragma unroll
-      for (int k = 0; k < M; ++k) c += p.cout[k] * S[k * M + j];
+      for (int k = 0; k < M; ++k) c += (A)p.cout[k] * S[k * M + j];
       const int at = 2 * ((n * M + j) * MB + qq);
       ar += c * Lf[at];
       ai += c * Lf[at + 1];
@@ -337,23 +360,23 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_lds(int P, int N, int M
   __syncthreads();
   // (B) per mode: La[n] <- p_{n-1} (the coupling value entering slab n)
   if (tid < mb) {
-    const double* S = Sinv + (size_t)(q0 + tid) * M * M;
-    double beta = 0.0;
+    const A* S = Sinv + (size_t)(q0 + tid) * M * M;
+    A beta = A(0.0);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      double c = 0.0;
+      A c = A(0.0);
 #pragma unroll
-      for (int k = 0; k < M; ++k) c += p.cout[k] * S[k * M + j];
-      beta += c * p.cin[j];
+      for (int k = 0; k < M; ++k) c += (A)p.cout[k] * S[k * M + j];
+      beta += c * (A)p.cin[j];
     }
-    double pr = 0.0, pi = 0.0;
+    A pr = A(0.0), pi = A(0.0);
     if (u0F) {
       pr = u0F[2 * (q0 + tid)];
       pi = u0F[2 * (q0 + tid) + 1];
     }
     for (int n = 0; n < N; ++n) {
       const int at = 2 * (n * MB + tid);
-      const double ar = La[at], ai = La[at + 1];
+      const A ar = La[at], ai = La[at + 1];
       La[at] = pr;
       La[at + 1] = pi;
       pr = ar + beta * pr;
@@ -364,9 +387,9 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_lds(int P, int N, int M
   // (C) u_n = S_q F_n + d p_{n-1}, in place in Lf
   for (int i = tid; i < N * mb; i += kFftBlock) {
     const int n = i / mb, qq = i - n * mb;
-    const double* S = Sinv + (size_t)(q0 + qq) * M * M;
-    const double pr = La[2 * (n * MB + qq)], pi = La[2 * (n * MB + qq) + 1];
-    double fr[M], fi[M];
+    const A* S = Sinv + (size_t)(q0 + qq) * M * M;
+    const A pr = La[2 * (n * MB + qq)], pi = La[2 * (n * MB + qq) + 1];
+    A fr[M], fi[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       const int at = 2 * ((n * M + j) * MB + qq);
@@ -375,12 +398,12 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_lds(int P, int N, int M
     }
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-      double sr = 0.0, si = 0.0, dk = 0.0;
+      A sr = A(0.0), si = A(0.0), dk = A(0.0);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         sr += S[k * M + j] * fr[j];
         si += S[k * M + j] * fi[j];
-        dk += S[k * M + j] * p.cin[j];
+        dk += S[k * M + j] * (A)p.cin[j];
       }
       const int at = 2 * ((n * M + k) * MB + qq);
       Lf[at] = sr + dk * pr;
@@ -479,16 +502,16 @@ constexpr int kRegLds = kFftRegSide * (kFftRegSide / 2 + 2);
 // Decimation in frequency along lines of n points.  W: cos, sin of 2 pi j / n
 // for j < n; sgn -1 forward.  Lower lane of a pair: u + v; upper: (u - v) w^j
 // with j = (l mod h) n / (2 h), i.e. (sigma own + partner) w with sigma = -1.
-template <int R>
-__device__ __forceinline__ void dif_lines(double (&re)[R], double (&im)[R], int n, const double* W,
-                                          double sgn) {
+template <typename A, int R>
+__device__ __forceinline__ void dif_lines(A (&re)[R], A (&im)[R], int n, const A* W,
+                                          A sgn) {
   const int lane = threadIdx.x & 63;
   for (int h = n >> 1; h >= 1; h >>= 1) {
     const bool up = (lane & h) != 0;
     const int j = (lane & (h - 1)) * (n / (2 * h));
-    const double c = up ? W[2 * j] : 1.0, s = up ? sgn * W[2 * j + 1] : 0.0;
-    const double sig = up ? -1.0 : 1.0;
-    double pr[R], pi[R];
+    const A c = up ? W[2 * j] : A(1.0), s = up ? sgn * W[2 * j + 1] : A(0.0);
+    const A sig = up ? -A(1.0) : A(1.0);
+    A pr[R], pi[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       pr[r] = __shfl_xor(re[r], h);
@@ -496,7 +519,7 @@ __device__ __forceinline__ void dif_lines(double (&re)[R], double (&im)[R], int 
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const double ar = fma(sig, re[r], pr[r]), ai = fma(sig, im[r], pi[r]);
+      const A ar = fma(sig, re[r], pr[r]), ai = fma(sig, im[r], pi[r]);
       re[r] = ar * c - ai * s;
       im[r] = ar * s + ai * c;
     }
@@ -506,16 +529,16 @@ __device__ __forceinline__ void dif_lines(double (&re)[R], double (&im)[R], int 
 // Decimation in time along lines of n points (bit-reversed input): every lane
 // forms x = own w^j (w = 1 on the lower lane), the pair exchanges x; lower:
 // u + t, upper: u - t (t = v w^j).
-template <int R>
-__device__ __forceinline__ void dit_lines(double (&re)[R], double (&im)[R], int n, const double* W,
-                                          double sgn) {
+template <typename A, int R>
+__device__ __forceinline__ void dit_lines(A (&re)[R], A (&im)[R], int n, const A* W,
+                                          A sgn) {
   const int lane = threadIdx.x & 63;
   for (int h = 1; h < n; h <<= 1) {
     const bool up = (lane & h) != 0;
     const int j = (lane & (h - 1)) * (n / (2 * h));
-    const double c = up ? W[2 * j] : 1.0, s = up ? sgn * W[2 * j + 1] : 0.0;
-    const double sig = up ? -1.0 : 1.0;
-    double xr[R], xi[R], pr[R], pi[R];
+    const A c = up ? W[2 * j] : A(1.0), s = up ? sgn * W[2 * j + 1] : A(0.0);
+    const A sig = up ? -A(1.0) : A(1.0);
+    A xr[R], xi[R], pr[R], pi[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       xr[r] = re[r] * c - im[r] * s;
@@ -549,38 +572,38 @@ __device__ __forceinline__ int brev_n(int i, int lg) { return (int)(__brev((unsi
 // A[k] = (Z[k] + conj Z[-k]) / 2, B[k] = (Z[k] - conj Z[-k]) / 2i, with Z[-k]
 // read from the lane holding bit-reversed (n - k) mod n; lanes of the kept
 // columns write them to the tile [c][y] (stride ny + 1).
-template <typename T, int R>
+template <typename T, typename A, int R>
 __global__ __launch_bounds__(kRegBlock) void k_fft_fwd_reg(int nx, int ny, int lgx, int nplanes,
                                                            const T* __restrict__ f,
                                                            const double* __restrict__ u0,
-                                                           const double* __restrict__ tw,
-                                                           double* __restrict__ out) {
+                                                           const A* __restrict__ tw,
+                                                           A* __restrict__ out) {
   constexpr int RP = RegLines<R>::RP, RC = RegLines<R>::RC;
   constexpr bool PACK = R >= 2;
-  __shared__ double Tr[kRegLds];
-  __shared__ double Ti[kRegLds];
-  __shared__ double W[4 * kFftRegSide];
+  __shared__ A Tr[kRegLds];
+  __shared__ A Ti[kRegLds];
+  __shared__ A W[4 * kFftRegSide];
   const int P = nx * ny, nh = nx >> 1, Ph = (nh + 1) * ny;
   const int pl = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (int i = tid; i < 2 * (nx + ny); i += kRegBlock) W[i] = tw[i];
   const double* src = pl < nplanes ? nullptr : u0;
-  auto ld = [&](int y, int x) -> double {
-    if (y >= ny) return 0.0;
-    if (src) return src[y * nx + x];
-    return f ? (double)f[(size_t)pl * P + y * nx + x] : 0.0;
+  auto ld = [&](int y, int x) -> A {
+    if (y >= ny) return A(0.0);
+    if (src) return (A)src[y * nx + x];
+    return f ? (A)f[(size_t)pl * P + y * nx + x] : A(0.0);
   };
   // rows: lane = x in, kx' = pos out
   {
     const int lpw = 64 / nx, line = lane / nx, pos = lane - line * nx;
-    double re[RP], im[RP];
+    A re[RP], im[RP];
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
       re[r] = ld((wid + kRegWaves * r) * lpw + line, pos);
-      im[r] = PACK ? ld((wid + kRegWaves * (r + RP)) * lpw + line, pos) : 0.0;
+      im[r] = PACK ? ld((wid + kRegWaves * (r + RP)) * lpw + line, pos) : A(0.0);
     }
     __syncthreads();  // W
-    dif_lines<RP>(re, im, nx, W, -1.0);
+    dif_lines<A, RP>(re, im, nx, W, -A(1.0));
     // lane of the partner coefficient Z[-k], k = bitrev(pos); kept column
     const int kn = (nx - brev_n(pos, lgx)) & (nx - 1);
     const int src_lane = line * nx + brev_n(kn, lgx);
@@ -591,14 +614,14 @@ __global__ __launch_bounds__(kRegBlock) void k_fft_fwd_reg(int nx, int ny, int l
       const int ya = (wid + kRegWaves * r) * lpw + line;
       if (PACK) {
         const int yb = (wid + kRegWaves * (r + RP)) * lpw + line;
-        const double wr = __shfl(re[r], src_lane), wi = __shfl(im[r], src_lane);
+        const A wr = __shfl(re[r], src_lane), wi = __shfl(im[r], src_lane);
         if (keep && ya < ny) {
-          Tr[c * (ny + 1) + ya] = 0.5 * (re[r] + wr);
-          Ti[c * (ny + 1) + ya] = 0.5 * (im[r] - wi);
+          Tr[c * (ny + 1) + ya] = A(0.5) * (re[r] + wr);
+          Ti[c * (ny + 1) + ya] = A(0.5) * (im[r] - wi);
         }
         if (keep && yb < ny) {
-          Tr[c * (ny + 1) + yb] = 0.5 * (im[r] + wi);
-          Ti[c * (ny + 1) + yb] = 0.5 * (wr - re[r]);
+          Tr[c * (ny + 1) + yb] = A(0.5) * (im[r] + wi);
+          Ti[c * (ny + 1) + yb] = A(0.5) * (wr - re[r]);
         }
       } else if (keep && ya < ny) {
         Tr[c * (ny + 1) + ya] = re[r];
@@ -610,19 +633,19 @@ __global__ __launch_bounds__(kRegBlock) void k_fft_fwd_reg(int nx, int ny, int l
   // kept columns: lane = y in, ky' out
   {
     const int lpw = 64 / ny, line = lane / ny, pos = lane - line * ny;
-    double re[RC], im[RC];
+    A re[RC], im[RC];
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
       const int c = (wid + kRegWaves * r) * lpw + line;
-      re[r] = c <= nh ? Tr[c * (ny + 1) + pos] : 0.0;
-      im[r] = c <= nh ? Ti[c * (ny + 1) + pos] : 0.0;
+      re[r] = c <= nh ? Tr[c * (ny + 1) + pos] : A(0.0);
+      im[r] = c <= nh ? Ti[c * (ny + 1) + pos] : A(0.0);
     }
-    dif_lines<RC>(re, im, ny, W + 2 * nx, -1.0);
-    double2* o = reinterpret_cast<double2*>(out + (size_t)pl * 2 * Ph);
+    dif_lines<A, RC>(re, im, ny, W + 2 * nx, -A(1.0));
+    typename V2<A>::t* o = reinterpret_cast<typename V2<A>::t*>(out + (size_t)pl * 2 * Ph);
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
       const int c = (wid + kRegWaves * r) * lpw + line;
-      if (c <= nh) o[c * ny + pos] = make_double2(re[r], im[r]);
+      if (c <= nh) o[c * ny + pos] = mk2<A>(re[r], im[r]);
     }
   }
 }
@@ -633,16 +656,16 @@ __global__ __launch_bounds__(kRegBlock) void k_fft_fwd_reg(int nx, int ny, int l
 // kx' != 1, kx > nx/2) as the conjugate of column nx - kx; the row spectra
 // are Hermitian (the field is real), so two rows a, b go through one
 // transform of A + i B and come out as its real and imaginary parts.
-template <typename T, int R>
+template <typename T, typename A, int R>
 __global__ __launch_bounds__(kRegBlock) void k_fft_inv_reg(int nx, int ny, int lgx,
-                                                           const double* __restrict__ F,
-                                                           const double* __restrict__ tw,
+                                                           const A* __restrict__ F,
+                                                           const A* __restrict__ tw,
                                                            T* __restrict__ U) {
   constexpr int RP = RegLines<R>::RP, RC = RegLines<R>::RC;
   constexpr bool PACK = R >= 2;
-  __shared__ double Tr[kRegLds];
-  __shared__ double Ti[kRegLds];
-  __shared__ double W[4 * kFftRegSide];
+  __shared__ A Tr[kRegLds];
+  __shared__ A Ti[kRegLds];
+  __shared__ A W[4 * kFftRegSide];
   const int P = nx * ny, nh = nx >> 1, Ph = (nh + 1) * ny, ts = nh + 2;
   const int pl = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -650,17 +673,17 @@ __global__ __launch_bounds__(kRegBlock) void k_fft_inv_reg(int nx, int ny, int l
   // kept columns: lane = ky' in, y out
   {
     const int lpw = 64 / ny, line = lane / ny, pos = lane - line * ny;
-    const double2* src = reinterpret_cast<const double2*>(F + (size_t)pl * 2 * Ph);
-    double re[RC], im[RC];
+    const typename V2<A>::t* src = reinterpret_cast<const typename V2<A>::t*>(F + (size_t)pl * 2 * Ph);
+    A re[RC], im[RC];
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
       const int c = (wid + kRegWaves * r) * lpw + line;
-      const double2 v = c <= nh ? src[c * ny + pos] : make_double2(0.0, 0.0);
+      const typename V2<A>::t v = c <= nh ? src[c * ny + pos] : mk2<A>(A(0.0), A(0.0));
       re[r] = v.x;
       im[r] = v.y;
     }
     __syncthreads();  // W
-    dit_lines<RC>(re, im, ny, W + 2 * nx, 1.0);
+    dit_lines<A, RC>(re, im, ny, W + 2 * nx, A(1.0));
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
       const int c = (wid + kRegWaves * r) * lpw + line;
@@ -675,23 +698,23 @@ __global__ __launch_bounds__(kRegBlock) void k_fft_inv_reg(int nx, int ny, int l
   {
     const int lpw = 64 / nx, line = lane / nx, pos = lane - line * nx;
     int c;
-    double cs = 1.0;  // -1: conjugate
+    A cs = A(1.0);  // -1: conjugate
     if ((pos & 1) == 0) c = pos >> 1;
     else if (pos == 1) c = nh;
     else {
       c = brev_n(nx - brev_n(pos, lgx), lgx) >> 1;
-      cs = -1.0;
+      cs = -A(1.0);
     }
-    double re[RP], im[RP];
+    A re[RP], im[RP];
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
       const int ya = (wid + kRegWaves * r) * lpw + line;
-      const double ar = ya < ny ? Tr[ya * ts + c] : 0.0;
-      const double ai = ya < ny ? cs * Ti[ya * ts + c] : 0.0;
+      const A ar = ya < ny ? Tr[ya * ts + c] : A(0.0);
+      const A ai = ya < ny ? cs * Ti[ya * ts + c] : A(0.0);
       if (PACK) {
         const int yb = (wid + kRegWaves * (r + RP)) * lpw + line;
-        const double br = yb < ny ? Tr[yb * ts + c] : 0.0;
-        const double bi = yb < ny ? cs * Ti[yb * ts + c] : 0.0;
+        const A br = yb < ny ? Tr[yb * ts + c] : A(0.0);
+        const A bi = yb < ny ? cs * Ti[yb * ts + c] : A(0.0);
         re[r] = ar - bi;
         im[r] = ai + br;
       } else {
@@ -699,8 +722,8 @@ __global__ __launch_bounds__(kRegBlock) void k_fft_inv_reg(int nx, int ny, int l
         im[r] = ai;
       }
     }
-    dit_lines<RP>(re, im, nx, W, 1.0);
-    const double scale = 1.0 / (double)P;
+    dit_lines<A, RP>(re, im, nx, W, A(1.0));
+    const A scale = A(1.0) / (A)P;
     T* dst = U + (size_t)pl * P;
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
@@ -734,59 +757,59 @@ template <int M>
 struct ChunkG {
   static constexpr int G = M <= 3 ? 16 : 48 / M;
 };
-template <int M>
-__global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, double* __restrict__ F,
-                                                               const double* __restrict__ u0F,
-                                                               const double* __restrict__ Sinv,
+template <int M, typename A>
+__global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, A* __restrict__ F,
+                                                               const A* __restrict__ u0F,
+                                                               const A* __restrict__ Sinv,
                                                                const OpParams p,
-                                                               const double* __restrict__ fscale) {
-  __shared__ double Sr[kChunkC][kChunkQ], Si[kChunkC][kChunkQ], Bp[kChunkC][kChunkQ];
+                                                               const A* __restrict__ fscale) {
+  __shared__ A Sr[kChunkC][kChunkQ], Si[kChunkC][kChunkQ], Bp[kChunkC][kChunkQ];
   const int qq = threadIdx.x % kChunkQ, ch = threadIdx.x / kChunkQ;
   const int q = blockIdx.x * kChunkQ + qq;
   const bool act = q < P;
   const int len = (N + kChunkC - 1) / kChunkC;
   const int n0 = min(ch * len, N), n1 = min(n0 + len, N);
-  double S[M][M], cv[M], dv[M], beta = 0.0;
+  A S[M][M], cv[M], dv[M], beta = A(0.0);
 #pragma unroll
   for (int i = 0; i < M; ++i)
 #pragma unroll
-    for (int j = 0; j < M; ++j) S[i][j] = act ? Sinv[((size_t)q * M + i) * M + j] : 0.0;
+    for (int j = 0; j < M; ++j) S[i][j] = act ? Sinv[((size_t)q * M + i) * M + j] : A(0.0);
 #pragma unroll
   for (int j = 0; j < M; ++j) {
-    double cj = 0.0;
+    A cj = A(0.0);
 #pragma unroll
-    for (int k = 0; k < M; ++k) cj += p.cout[k] * S[k][j];
+    for (int k = 0; k < M; ++k) cj += (A)p.cout[k] * S[k][j];
     cv[j] = cj;
-    beta += cj * p.cin[j];
+    beta += cj * (A)p.cin[j];
   }
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    double dk = 0.0;
+    A dk = A(0.0);
 #pragma unroll
-    for (int j = 0; j < M; ++j) dk += S[k][j] * p.cin[j];
+    for (int j = 0; j < M; ++j) dk += S[k][j] * (A)p.cin[j];
     dv[k] = dk;
   }
-  double2* Fc = reinterpret_cast<double2*>(F);
-  const double fsc = (fscale && act) ? fscale[q] : 1.0;
+  typename V2<A>::t* Fc = reinterpret_cast<typename V2<A>::t*>(F);
+  const A fsc = (fscale && act) ? fscale[q] : A(1.0);
   constexpr int G = ChunkG<M>::G;
   const bool cached = n1 - n0 <= G;
-  double2 v[G][M];
+  typename V2<A>::t v[G][M];
   // (1)
-  double sr = 0.0, si = 0.0, bp = 1.0;
+  A sr = A(0.0), si = A(0.0), bp = A(1.0);
   if (act) {
     for (int g0 = n0; g0 < n1; g0 += G) {
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-          v[g][m] = g0 + g < n1 ? Fc[((size_t)(g0 + g) * M + m) * P + q] : make_double2(0.0, 0.0);
+          v[g][m] = g0 + g < n1 ? Fc[((size_t)(g0 + g) * M + m) * P + q] : mk2<A>(A(0.0), A(0.0));
           v[g][m].x *= fsc;
           v[g][m].y *= fsc;
         }
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         if (g0 + g < n1) {
-          double ar = 0.0, ai = 0.0;
+          A ar = A(0.0), ai = A(0.0);
 #pragma unroll
           for (int j = 0; j < M; ++j) {
             ar += cv[j] * v[g][j].x;
@@ -805,13 +828,13 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, dou
   __syncthreads();
   // (2): the entering p of every run replaces its (s, beta^len) in LDS
   if (ch == 0 && act) {
-    double pr = 0.0, pi = 0.0;
+    A pr = A(0.0), pi = A(0.0);
     if (u0F) {
       pr = u0F[2 * q];
       pi = u0F[2 * q + 1];
     }
     for (int r = 0; r < kChunkC; ++r) {
-      const double s0 = Sr[r][qq], s1 = Si[r][qq], b = Bp[r][qq];
+      const A s0 = Sr[r][qq], s1 = Si[r][qq], b = Bp[r][qq];
       Sr[r][qq] = pr;
       Si[r][qq] = pi;
       pr = s0 + b * pr;
@@ -821,14 +844,14 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, dou
   __syncthreads();
   // (3)
   if (act) {
-    double pr = Sr[ch][qq], pi = Si[ch][qq];
+    A pr = Sr[ch][qq], pi = Si[ch][qq];
     for (int g0 = n0; g0 < n1; g0 += G) {
       if (!cached) {
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
           for (int m = 0; m < M; ++m) {
-            v[g][m] = g0 + g < n1 ? Fc[((size_t)(g0 + g) * M + m) * P + q] : make_double2(0.0, 0.0);
+            v[g][m] = g0 + g < n1 ? Fc[((size_t)(g0 + g) * M + m) * P + q] : mk2<A>(A(0.0), A(0.0));
             v[g][m].x *= fsc;
             v[g][m].y *= fsc;
           }
@@ -836,16 +859,16 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, dou
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         if (g0 + g < n1) {
-          double ar = 0.0, ai = 0.0;
+          A ar = A(0.0), ai = A(0.0);
 #pragma unroll
           for (int k = 0; k < M; ++k) {
-            double ur = dv[k] * pr, ui = dv[k] * pi;
+            A ur = dv[k] * pr, ui = dv[k] * pi;
 #pragma unroll
             for (int j = 0; j < M; ++j) {
               ur += S[k][j] * v[g][j].x;
               ui += S[k][j] * v[g][j].y;
             }
-            Fc[((size_t)(g0 + g) * M + k) * P + q] = make_double2(ur, ui);
+            Fc[((size_t)(g0 + g) * M + k) * P + q] = mk2<A>(ur, ui);
             ar += cv[k] * v[g][k].x;
             ai += cv[k] * v[g][k].y;
           }
@@ -859,16 +882,19 @@ __global__ __launch_bounds__(kFftBlock) void k_fft_modes_chunk(int P, int N, dou
 
 }  // namespace
 
-template <typename T>
-hipError_t launch_fft_coarse(const OpParams& p, const double* Sinv, const double* tw, double* work,
-                             const T* f, const double* u0, T* U, hipStream_t s, const double* fscale) {
+// The three steps with arithmetic type A: FP64 on every plane the Fourier
+// solve takes, FP32 on the register-transform planes only.
+template <typename T, typename A>
+static hipError_t fft_coarse_impl(const OpParams& p, const A* Sinv, const A* tw, A* work, const T* f,
+                                  const double* u0, T* U, hipStream_t s, const A* fscale) {
+  constexpr bool F64 = std::is_same<A, double>::value;
   const int P = p.nx * p.ny;
   const bool reg = fft_reg_plane(p.nx, p.ny);
-  if ((!reg && P > kFftMaxPlane) || p.M < 1 || p.M > kMaxM) return hipErrorInvalidValue;
+  if ((!reg && (P > kFftMaxPlane || !F64)) || p.M < 1 || p.M > kMaxM) return hipErrorInvalidValue;
   const int planes = p.N * p.M;
   // modes per plane in Fourier space (the kept half for the register path)
   const int PF = reg ? (p.nx / 2 + 1) * p.ny : P;
-  double* u0F = u0 ? work + (size_t)2 * planes * PF : nullptr;
+  A* u0F = u0 ? work + (size_t)2 * planes * PF : nullptr;
   auto lg2 = [](int n) { int l = 0; while ((1 << l) < n) ++l; return (1 << l) == n ? l : -1; };
   const int lgx = lg2(p.nx), lgy = lg2(p.ny);
   const bool pow2 = lgx >= 0 && lgy >= 0;
@@ -876,47 +902,67 @@ hipError_t launch_fft_coarse(const OpParams& p, const double* Sinv, const double
   const int R = P <= kRegBlock ? 1 : P / kRegBlock;
 #define LREG(RR, KERNEL, GRID, ...)                                                        \
   switch (RR) {                                                                            \
-    case 1: hipLaunchKernelGGL((KERNEL<T, 1>), dim3(GRID), dim3(kRegBlock), 0, s, __VA_ARGS__); break; \
-    case 2: hipLaunchKernelGGL((KERNEL<T, 2>), dim3(GRID), dim3(kRegBlock), 0, s, __VA_ARGS__); break; \
-    case 4: hipLaunchKernelGGL((KERNEL<T, 4>), dim3(GRID), dim3(kRegBlock), 0, s, __VA_ARGS__); break; \
-    default: hipLaunchKernelGGL((KERNEL<T, 8>), dim3(GRID), dim3(kRegBlock), 0, s, __VA_ARGS__); break; \
+    case 1: hipLaunchKernelGGL((KERNEL<T, A, 1>), dim3(GRID), dim3(kRegBlock), 0, s, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL((KERNEL<T, A, 2>), dim3(GRID), dim3(kRegBlock), 0, s, __VA_ARGS__); break; \
+    case 4: hipLaunchKernelGGL((KERNEL<T, A, 4>), dim3(GRID), dim3(kRegBlock), 0, s, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL((KERNEL<T, A, 8>), dim3(GRID), dim3(kRegBlock), 0, s, __VA_ARGS__); break; \
   }
-  if (reg)
+  if (reg) {
     LREG(R, k_fft_fwd_reg, planes + (u0 ? 1 : 0), p.nx, p.ny, lgx, planes, f, u0, tw, work)
-  else if (pow2)
-    hipLaunchKernelGGL((k_fft_fwd2<T>), dim3(planes + (u0 ? 1 : 0)), dim3(kFftBlock), 0, s, p.nx, p.ny,
-                       lgx, lgy, planes, f, u0, tw, work);
-  else
-    hipLaunchKernelGGL((k_fft_fwd<T>), dim3(planes + (u0 ? 1 : 0)), dim3(kFftBlock), 0, s, p.nx, p.ny,
-                       planes, f, u0, tw, work);
-  // modes per workgroup for the LDS-staged recurrence (at most 64, at least 4)
+  } else if constexpr (F64) {
+    if (pow2)
+      hipLaunchKernelGGL((k_fft_fwd2<T>), dim3(planes + (u0 ? 1 : 0)), dim3(kFftBlock), 0, s, p.nx, p.ny,
+                         lgx, lgy, planes, f, u0, tw, work);
+    else
+      hipLaunchKernelGGL((k_fft_fwd<T>), dim3(planes + (u0 ? 1 : 0)), dim3(kFftBlock), 0, s, p.nx, p.ny,
+                         planes, f, u0, tw, work);
+  }
+  // modes per workgroup for the LDS-staged recurrence (at most 64, at least
+  // 4), sized with 8-byte values whatever A is: where FP64 modes no longer fit
+  // four to a workgroup the time axis is long enough that the run-chunked
+  // recurrence, with 16 modes x 16 runs per workgroup, is the faster one in
+  // FP32 too
   const long long per_mode = (long long)p.N * (p.M + 2) * 2 * sizeof(double);
   int MB = (int)(kFftLds / per_mode);
   if (MB > 64) MB = 64;
   if (MB >= 4) {
     const int gb = (PF + MB - 1) / MB;
 #define L(MM)                                                                                        \
-  hipLaunchKernelGGL((k_fft_modes_lds<MM>), dim3(gb), dim3(kFftBlock), 0, s, PF, p.N, MB, work, u0F, \
+  hipLaunchKernelGGL((k_fft_modes_lds<MM, A>), dim3(gb), dim3(kFftBlock), 0, s, PF, p.N, MB, work, u0F, \
                      Sinv, p, fscale)
     STMG_DISPATCH_M_FFT(L)
 #undef L
   } else {
     const int gb = (PF + kChunkQ - 1) / kChunkQ;
 #define L(MM)                                                                                           \
-  hipLaunchKernelGGL((k_fft_modes_chunk<MM>), dim3(gb), dim3(kFftBlock), 0, s, PF, p.N, work, u0F, Sinv, p, \
+  hipLaunchKernelGGL((k_fft_modes_chunk<MM, A>), dim3(gb), dim3(kFftBlock), 0, s, PF, p.N, work, u0F, Sinv, p, \
                      fscale)
     STMG_DISPATCH_M_FFT(L)
 #undef L
   }
-  if (reg)
+  if (reg) {
     LREG(R, k_fft_inv_reg, planes, p.nx, p.ny, lgx, work, tw, U)
-  else if (pow2)
-    hipLaunchKernelGGL((k_fft_inv2<T>), dim3(planes), dim3(kFftBlock), 0, s, p.nx, p.ny, lgx, lgy, work,
-                       tw, U);
-  else
-    hipLaunchKernelGGL((k_fft_inv<T>), dim3(planes), dim3(kFftBlock), 0, s, p.nx, p.ny, work, tw, U);
+  } else if constexpr (F64) {
+    if (pow2)
+      hipLaunchKernelGGL((k_fft_inv2<T>), dim3(planes), dim3(kFftBlock), 0, s, p.nx, p.ny, lgx, lgy, work,
+                         tw, U);
+    else
+      hipLaunchKernelGGL((k_fft_inv<T>), dim3(planes), dim3(kFftBlock), 0, s, p.nx, p.ny, work, tw, U);
+  }
 #undef LREG
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_coarse(const OpParams& p, const double* Sinv, const double* tw, double* work,
+                             const T* f, const double* u0, T* U, hipStream_t s, const double* fscale) {
+  return fft_coarse_impl<T, double>(p, Sinv, tw, work, f, u0, U, s, fscale);
+}
+
+hipError_t launch_fft_coarse32(const OpParams& p, const float* Sinv, const float* tw, float* work, const float* f,
+                               const double* u0, float* U, hipStream_t s, const float* fscale) {
+  if (!fft_reg_plane(p.nx, p.ny)) return hipErrorNotSupported;
+  return fft_coarse_impl<float, float>(p, Sinv, tw, work, f, u0, U, s, fscale);
 }
 
 template hipError_t launch_fft_coarse<double>(const OpParams&, const double*, const double*, double*,

@@ -155,6 +155,11 @@ template <typename T>
 hipError_t launch_fft_coarse(const OpParams& p, const double* Sinv, const double* tw, double* work,
                              const T* f, const double* u0, T* U, hipStream_t s,
                              const double* fscale = nullptr);
+// The same in FP32 arithmetic with FP32 tables (Sinv, tw, fscale as in the
+// FP64 solve, rounded) and work space, for the FP32 cycles of mixed
+// precision; register-transform planes only (hipErrorNotSupported otherwise).
+hipError_t launch_fft_coarse32(const OpParams& p, const float* Sinv, const float* tw, float* work, const float* f,
+                               const double* u0, float* U, hipStream_t s, const float* fscale = nullptr);
 
 // Coarsest solve with a different slab matrix per slab: the K x K slab
 // matrices (K = M nx ny) are built from the per-DOF coefficient and factored

@@ -198,6 +198,7 @@ int Solver::build(const stmg_problem* p, const stmg_options* o) {
   const Level& last = lv.back();
   const long long Kc = static_cast<long long>(last.M) * last.nx * last.ny;
   fft = fft_ok && fft_plane_ok(last.nx, last.ny);
+  fft32 = fft && mixed && fft_reg_plane(last.nx, last.ny);
   if (!fft && Kc > 1024) {
     set_error("coarsest level has more than 1024 unknowns per slab");
     return STMG_EUNSUPPORTED;
@@ -490,6 +491,13 @@ size_t Solver::plan(char* ws) {
     fft_tw = pl.take<double>(2 * (static_cast<size_t>(c.nx) + c.ny));
     fft_work = pl.take<double>(2 * (static_cast<size_t>(c.N) * c.M + 1) * Pc);
     if (c.g9) fft_mscale = pl.take<double>(Pc);
+    if (fft32) {
+      fft_sinv32 = pl.take<float>(Pc * c.M * c.M);
+      fft_sinvT32 = pl.take<float>(Pc * c.M * c.M);
+      fft_tw32 = pl.take<float>(2 * (static_cast<size_t>(c.nx) + c.ny));
+      fft_work32 = pl.take<float>(2 * (static_cast<size_t>(c.N) * c.M + 1) * Pc);
+      if (c.g9) fft_mscale32 = pl.take<float>(Pc);
+    }
   } else {
     Ainv = pl.take<double>(K * K);
     AinvT = pl.take<double>(K * K);
@@ -736,6 +744,20 @@ int Solver::upload_fft() {
   if (c.g9)
     HIP_CHECK(hipMemcpyAsync(fft_mscale, mscale.data(), mscale.size() * sizeof(double), hipMemcpyHostToDevice,
                              stream));
+  std::vector<float> S32, ST32, tw32, ms32;
+  if (fft32) {
+    auto cast = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+    S32 = cast(S);
+    ST32 = cast(ST);
+    tw32 = cast(tw);
+    ms32 = cast(mscale);
+    HIP_CHECK(hipMemcpyAsync(fft_sinv32, S32.data(), S32.size() * sizeof(float), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(fft_sinvT32, ST32.data(), ST32.size() * sizeof(float), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(fft_tw32, tw32.data(), tw32.size() * sizeof(float), hipMemcpyHostToDevice, stream));
+    if (c.g9)
+      HIP_CHECK(hipMemcpyAsync(fft_mscale32, ms32.data(), ms32.size() * sizeof(float), hipMemcpyHostToDevice,
+                               stream));
+  }
   HIP_CHECK(hipStreamSynchronize(stream));  // host vectors go out of scope
   return STMG_OK;
 }
@@ -961,6 +983,11 @@ hipError_t Solver::coarse(bool adj, int react, const T* f, const double* u0, T* 
   if (react == REACT_COEF) {
     if (coarse_inv && !adj) return launch_coarse_solve_slabs<T>(op, coarse_inv, f, u0, U, stream);
     return launch_coarse_solve_coef<T>(op, coef_of<T>(C), coarse_scratch, f, u0, U, stream);
+  }
+  if constexpr (sizeof(T) == 4) {
+    if (fft32)
+      return launch_fft_coarse32(op, adj ? fft_sinvT32 : fft_sinv32, fft_tw32, fft_work32, f, u0, U, stream,
+                                 C.g9 ? fft_mscale32 : nullptr);
   }
   if (fft)
     return launch_fft_coarse<T>(op, adj ? fft_sinvT : fft_sinv, fft_tw, fft_work, f, u0, U, stream,

@@ -137,6 +137,11 @@ struct Solver {
   double* fft_tw = nullptr;
   double* fft_work = nullptr;   // 2 (N M + 1) P
   double* fft_mscale = nullptr; // Galerkin coarsest level: 1 / mass symbol per mode
+  // the same tables rounded to FP32 and an FP32 workspace, for the FP32
+  // cycles of mixed precision on register-transform planes
+  bool fft32 = false;
+  float *fft_sinv32 = nullptr, *fft_sinvT32 = nullptr, *fft_tw32 = nullptr, *fft_work32 = nullptr,
+        *fft_mscale32 = nullptr;
   double* delta64 = nullptr;  // Newton correction / adjoint multiplier (level 0, FP64)
   // Flexible GMRES (opt.krylov = m > 0): m + 1 basis vectors and m + 1
   // direction buffers (one spare for the V-cycle's ping-pong) on level 0,
