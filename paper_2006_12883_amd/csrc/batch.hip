@@ -127,7 +127,8 @@ __global__ __launch_bounds__(kBlock) void k_b_smooth0(const BItem* __restrict__ 
 
 __global__ __launch_bounds__(kBlock) void k_b_restrict_s(const BItem* __restrict__ items, int nitems,
                                                          const int* __restrict__ done) {
-  __shared__ float lds[4 * 33 * 33];
+  // restrict_blk_body's tile: M <= 4 nodes x 33 rows x 2 x 17 slots
+  __shared__ float lds[4 * 33 * 2 * 17];
   const BItem& it = items[find_item(items, nitems, blockIdx.x)];
   if (done[it.prob]) return;
   const int lb = blockIdx.x - it.blk0;

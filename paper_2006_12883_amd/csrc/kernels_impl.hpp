@@ -1269,8 +1269,14 @@ __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const Sweep
   constexpr int FH = TWOD ? 2 * TCY + 1 : 1;
   constexpr int NHALO = TWOD ? FW + FH - 1 : 1;  // halo column + halo row (corner once)
   static_assert(TCX * TCY == kBlock, "one owned fine block per thread");
-  // LDS tile rs[M][FH][FW] provided by the caller (one allocation per kernel)
-  T (*rs)[FH][FW] = reinterpret_cast<T (*)[FH][FW]>(lds);
+  // LDS tile of fine residuals provided by the caller (one allocation per
+  // kernel, M x FH x RW values): FH rows of FW = 2 TCX + 1 points, each row
+  // stored as its even columns and then its odd columns (TCX + 1 slots each),
+  // so that the lanes of a wave, which take every second column, touch
+  // consecutive words
+  constexpr int RH = TCX + 1;
+  constexpr int RW = 2 * RH;
+  auto rs = [lds](int i, int y, int x) -> T& { return lds[(i * FH + y) * RW + (x & 1) * RH + (x >> 1)]; };
   if (J0 >= Nc) return;
   const int J1 = min(J0 + S, Nc);
   const int X0 = (tile % tiles_x) * TCX;
@@ -1363,7 +1369,7 @@ __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const Sweep
         const int lx = 2 * tx + 1 + (k & 1), ly = TWOD ? 2 * ty + 1 + (k >> 1) : 0;
 #pragma unroll
         for (int i = 0; i < M; ++i) {
-          rs[i][ly][lx] = r[i];
+          rs(i, ly, lx) = r[i];
           np += c.cout[i] * u[k][i];
         }
         prev[k] = np;
@@ -1381,7 +1387,7 @@ __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const Sweep
       T np = T(0);
 #pragma unroll
       for (int i = 0; i < M; ++i) {
-        rs[i][hy][hx] = r[i];
+        rs(i, hy, hx) = r[i];
         np += c.cout[i] * u[i];
       }
       hprev = np;
@@ -1392,12 +1398,12 @@ __device__ __forceinline__ void restrict_blk_body(const OpParams& p, const Sweep
       const int cx0 = 2 * tx, cy0 = TWOD ? 2 * ty : 0;
 #pragma unroll
       for (int i = 0; i < M; ++i) {
-        T sx0 = T(0.25) * rs[i][cy0][cx0] + T(0.5) * rs[i][cy0][cx0 + 1] + T(0.25) * rs[i][cy0][cx0 + 2];
+        T sx0 = T(0.25) * rs(i, cy0, cx0) + T(0.5) * rs(i, cy0, cx0 + 1) + T(0.25) * rs(i, cy0, cx0 + 2);
         if (TWOD) {
-          const T sx1 = T(0.25) * rs[i][cy0 + 1][cx0] + T(0.5) * rs[i][cy0 + 1][cx0 + 1] +
-                        T(0.25) * rs[i][cy0 + 1][cx0 + 2];
-          const T sx2 = T(0.25) * rs[i][cy0 + 2][cx0] + T(0.5) * rs[i][cy0 + 2][cx0 + 1] +
-                        T(0.25) * rs[i][cy0 + 2][cx0 + 2];
+          const T sx1 = T(0.25) * rs(i, cy0 + 1, cx0) + T(0.5) * rs(i, cy0 + 1, cx0 + 1) +
+                        T(0.25) * rs(i, cy0 + 1, cx0 + 2);
+          const T sx2 = T(0.25) * rs(i, cy0 + 2, cx0) + T(0.5) * rs(i, cy0 + 2, cx0 + 1) +
+                        T(0.25) * rs(i, cy0 + 2, cx0 + 2);
           sx0 = T(0.25) * sx0 + T(0.5) * sx1 + T(0.25) * sx2;
         }
         rc[i] = sx0;
@@ -1471,7 +1477,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_blk(const OpParams p, const
                                                          const T* __restrict__ coefc, int cs) {
   constexpr int FW = 2 * TCX + 1;
   constexpr int FH = TWOD ? 2 * TCY + 1 : 1;
-  __shared__ T rs[M * FH * FW];
+  __shared__ T rs[M * FH * 2 * (TCX + 1)];
   const int lb = xcd_remap(blockIdx.x, nblocks);
   restrict_blk_body<M, T, REACT, TM, TWOD, TCX, TCY, ZS>(p, a, ncx, ncy, Nc, fc, S, tiles_x, lb % tiles,
                                                          (lb / tiles) * S, pc, uc, coefc, cs, rs);
