@@ -494,64 +494,117 @@ constexpr int kRegBlock = 512;
 constexpr int kRegWaves = kRegBlock / 64;
 constexpr int kRegLds = kFftRegSide * (kFftRegSide / 2 + 2);
 
+// Value held by lane (own lane xor H) of the wave; every lane must be active.
+// Spans inside a row of 16 lanes move through DPP on the vector ALU (quad
+// permutations, the half-row mirror, the row rotation by 8) instead of the
+// LDS crossbar that ds_bpermute uses: xor 1 and xor 2 are quad permutations,
+// xor 4 is the quad reversal (xor 3) followed by the half-row mirror (xor 7),
+// xor 8 is the rotation of the 16-lane row by 8.  Wider spans use
+// ds_bpermute.  The values are moved, never changed.
+template <int H>
+__device__ __forceinline__ int xor_lane_b32(int v) {
+  if constexpr (H == 1) {
+    return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  } else if constexpr (H == 2) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  } else if constexpr (H == 4) {
+    const int t = __builtin_amdgcn_update_dpp(v, v, 0x1B, 0xF, 0xF, false);  // quad_perm [3,2,1,0]
+    return __builtin_amdgcn_update_dpp(t, t, 0x141, 0xF, 0xF, false);       // row_half_mirror
+  } else if constexpr (H == 8) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else {
+    return __shfl_xor(v, H);
+  }
+}
+template <int H, typename A>
+__device__ __forceinline__ A xor_lane(A v) {
+  if constexpr (sizeof(A) == 8) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = static_cast<unsigned>(xor_lane_b32<H>(static_cast<int>(b & 0xffffffffull)));
+    const unsigned hi = static_cast<unsigned>(xor_lane_b32<H>(static_cast<int>(b >> 32)));
+    return __builtin_bit_cast(A, (static_cast<unsigned long long>(hi) << 32) | lo);
+  } else {
+    return __builtin_bit_cast(A, xor_lane_b32<H>(__builtin_bit_cast(int, v)));
+  }
+}
+
 // A thread takes R lines per direction (R = P / 512, at least 1): all R are
 // loaded first and every butterfly stage runs over the R lines together, so
 // the loads and the shuffles of different lines overlap.  The butterflies are
 // branch-free: the lower lane of a pair uses the twiddle 1 and the sign +1.
+// Lines have n <= 64 points (a power of two), so the stages are the spans
+// H < n, unrolled with H a compile-time constant.
 //
 // Decimation in frequency along lines of n points.  W: cos, sin of 2 pi j / n
 // for j < n; sgn -1 forward.  Lower lane of a pair: u + v; upper: (u - v) w^j
 // with j = (l mod h) n / (2 h), i.e. (sigma own + partner) w with sigma = -1.
+static_assert(kFftRegSide <= 64, "register lines span at most one wave (stages H <= 32)");
+template <typename A, int R, int H>
+__device__ __forceinline__ void dif_stage(A (&re)[R], A (&im)[R], int n, const A* W, A sgn) {
+  if (H >= n) return;
+  const int lane = threadIdx.x & 63;
+  const bool up = (lane & H) != 0;
+  const int j = (lane & (H - 1)) * (n / (2 * H));
+  const A c = up ? W[2 * j] : A(1.0), s = up ? sgn * W[2 * j + 1] : A(0.0);
+  const A sig = up ? -A(1.0) : A(1.0);
+  A pr[R], pi[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    pr[r] = xor_lane<H>(re[r]);
+    pi[r] = xor_lane<H>(im[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const A ar = fma(sig, re[r], pr[r]), ai = fma(sig, im[r], pi[r]);
+    re[r] = ar * c - ai * s;
+    im[r] = ar * s + ai * c;
+  }
+}
 template <typename A, int R>
 __device__ __forceinline__ void dif_lines(A (&re)[R], A (&im)[R], int n, const A* W,
                                           A sgn) {
-  const int lane = threadIdx.x & 63;
-  for (int h = n >> 1; h >= 1; h >>= 1) {
-    const bool up = (lane & h) != 0;
-    const int j = (lane & (h - 1)) * (n / (2 * h));
-    const A c = up ? W[2 * j] : A(1.0), s = up ? sgn * W[2 * j + 1] : A(0.0);
-    const A sig = up ? -A(1.0) : A(1.0);
-    A pr[R], pi[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      pr[r] = __shfl_xor(re[r], h);
-      pi[r] = __shfl_xor(im[r], h);
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const A ar = fma(sig, re[r], pr[r]), ai = fma(sig, im[r], pi[r]);
-      re[r] = ar * c - ai * s;
-      im[r] = ar * s + ai * c;
-    }
-  }
+  dif_stage<A, R, 32>(re, im, n, W, sgn);
+  dif_stage<A, R, 16>(re, im, n, W, sgn);
+  dif_stage<A, R, 8>(re, im, n, W, sgn);
+  dif_stage<A, R, 4>(re, im, n, W, sgn);
+  dif_stage<A, R, 2>(re, im, n, W, sgn);
+  dif_stage<A, R, 1>(re, im, n, W, sgn);
 }
 
 // Decimation in time along lines of n points (bit-reversed input): every lane
 // forms x = own w^j (w = 1 on the lower lane), the pair exchanges x; lower:
 // u + t, upper: u - t (t = v w^j).
+template <typename A, int R, int H>
+__device__ __forceinline__ void dit_stage(A (&re)[R], A (&im)[R], int n, const A* W, A sgn) {
+  if (H >= n) return;
+  const int lane = threadIdx.x & 63;
+  const bool up = (lane & H) != 0;
+  const int j = (lane & (H - 1)) * (n / (2 * H));
+  const A c = up ? W[2 * j] : A(1.0), s = up ? sgn * W[2 * j + 1] : A(0.0);
+  const A sig = up ? -A(1.0) : A(1.0);
+  A xr[R], xi[R], pr[R], pi[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    xr[r] = re[r] * c - im[r] * s;
+    xi[r] = re[r] * s + im[r] * c;
+    pr[r] = xor_lane<H>(xr[r]);
+    pi[r] = xor_lane<H>(xi[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    re[r] = fma(sig, xr[r], pr[r]);
+    im[r] = fma(sig, xi[r], pi[r]);
+  }
+}
 template <typename A, int R>
 __device__ __forceinline__ void dit_lines(A (&re)[R], A (&im)[R], int n, const A* W,
                                           A sgn) {
-  const int lane = threadIdx.x & 63;
-  for (int h = 1; h < n; h <<= 1) {
-    const bool up = (lane & h) != 0;
-    const int j = (lane & (h - 1)) * (n / (2 * h));
-    const A c = up ? W[2 * j] : A(1.0), s = up ? sgn * W[2 * j + 1] : A(0.0);
-    const A sig = up ? -A(1.0) : A(1.0);
-    A xr[R], xi[R], pr[R], pi[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      xr[r] = re[r] * c - im[r] * s;
-      xi[r] = re[r] * s + im[r] * c;
-      pr[r] = __shfl_xor(xr[r], h);
-      pi[r] = __shfl_xor(xi[r], h);
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      re[r] = fma(sig, xr[r], pr[r]);
-      im[r] = fma(sig, xi[r], pi[r]);
-    }
-  }
+  dit_stage<A, R, 1>(re, im, n, W, sgn);
+  dit_stage<A, R, 2>(re, im, n, W, sgn);
+  dit_stage<A, R, 4>(re, im, n, W, sgn);
+  dit_stage<A, R, 8>(re, im, n, W, sgn);
+  dit_stage<A, R, 16>(re, im, n, W, sgn);
+  dit_stage<A, R, 32>(re, im, n, W, sgn);
 }
 
 // Lines handled by a thread: line r is (wid + kRegWaves r) lpw + line along
