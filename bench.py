@@ -27,19 +27,54 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the dominant kernel (level-0 prolongation + post-smoothing,
-# k_prolong_smooth_blk) from rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled
-# by what the counters read for a device copy of known size (FETCH x 2,
-# WRITE x 1; profiles/k_prolong_smooth_blk_rd2d_level0.md), valid only for
-# the kernel source the counters were taken on.
-TRAFFIC = {"kernels_impl_sha256_prefix": "29c79ebcf9cc7990", "bytes_per_launch": 520.8e6 + 402.7e6}
+# HBM traffic of the V-cycle's longest kernels from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs, scaled by what the counters read for a device copy of known
+# size (FETCH x 2, WRITE x 1; profiles/k_prolong_smooth_blk_rd2d_level0.md),
+# valid only for the kernel source the counters were taken on.
+TRAFFIC = {
+    "k_prolong_smooth_blk": {"source": "kernels_impl.hpp", "sha256_prefix": "29c79ebcf9cc7990",
+                             "bytes_per_launch": 520.8e6 + 402.7e6},
+    # the fused level-0 sweep + restriction and its run-boundary pass
+    # (profiles/k_smooth_restrict_rd2d_level0.md)
+    "k_smooth_restrict": {"source": "smooth_restrict.hip", "sha256_prefix": "2c6d3bac56898edc",
+                          "bytes_per_launch": 415.1e6 + 607.7e6 + 18.4e6 + 13.8e6},
+}
 
 
-def measured_traffic():
+def measured_traffic(kernel):
+    """Counter-measured HBM bytes per launch of `kernel`, while its source
+    file hashes to the one the counters were taken on (else None)."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2006_12883_amd", "csrc", "kernels_impl.hpp")
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
+    src = os.path.join(ROOT, "paper_2006_12883_amd", "csrc", t["source"])
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    return TRAFFIC["bytes_per_launch"] if h == TRAFFIC["kernels_impl_sha256_prefix"] else None
+    return t["bytes_per_launch"] if h == t["sha256_prefix"] else None
+
+
+def sr_run_len(nx, ny, N, chunk=16):
+    """Slabs per workgroup of the fused level-0 sweep + restriction, as its
+    launcher chooses them: whole smoother chunks, doubled while the launch
+    keeps at least 512 workgroups (tiles of 64 x 16 fine points)."""
+    tiles = (nx // 64) * (ny // 16)
+    rl = chunk
+    while rl < N and tiles * (-(-N // (2 * rl))) >= 512:
+        rl *= 2
+    return rl
+
+
+def sr_bytes(l0, l1, word=8, chunk=16, cs=4, zs=True):
+    """Algorithmic bytes of the fused level-0 sweep + restriction with its
+    run-boundary pass: U in, U' out, f_c (and the coarse first sweep U_c) out,
+    one plane of cout . d per run boundary out; then per boundary that plane
+    in, f_c of one coarse slab and U_c of one coarse chunk read and written."""
+    P, Pc = l0["nx"] * l0["ny"], l1["nx"] * l1["ny"]
+    dof0, c = P * l0["N"] * l0["M"], Pc * l1["N"] * l1["M"]
+    nb = -(-l0["N"] // sr_run_len(l0["nx"], l0["ny"], l0["N"], chunk)) - 1
+    kern = 2 * word * dof0 + word * c * (2 if zs else 1) + word * P * nb
+    fix = nb * (word * P + 2 * word * l0["M"] * Pc * (1 + (cs if zs else 0)))
+    return float(kern + fix)
 
 
 def parse():
@@ -64,13 +99,14 @@ def parse():
     return ap.parse_args()
 
 
-def cycle_bytes(levels, word=8):
+def cycle_bytes(levels, word=8, fused0=False):
     """Algorithmic HBM bytes of one V(1,1) cycle with the fused kernels, from
     the level shapes (levels[l] = dict(nx, ny, N, M, kind)):
       level 0: pre-smoothing reads U, writes U' (the right-hand side is
         generated from u0); the restriction reads U and writes f_c and the
-        coarse level's first sweep U_c; the prolongation + post-smoothing
-        reads U and e_c and writes U';
+        coarse level's first sweep U_c (fused0: the two as one kernel, see
+        sr_bytes); the prolongation + post-smoothing reads U and e_c and
+        writes U';
       levels 0 < l < coarsest: the restriction reads U and f, writes f_c (and
         U_c unless the next level is the coarsest); the prolongation +
         post-smoothing reads U, f, e_c and writes U';
@@ -86,8 +122,11 @@ def cycle_bytes(levels, word=8):
         c = dof[l + 1]
         b = 0
         if l == 0:
-            b += 2 * word * dof[0]                 # pre-smoothing
-            b += word * dof[0] + 2 * word * c      # restriction + coarse first sweep
+            if fused0:
+                b += sr_bytes(levels[0], levels[1], word, zs=L > 1)  # sweep + restriction
+            else:
+                b += 2 * word * dof[0]                 # pre-smoothing
+                b += word * dof[0] + 2 * word * c      # restriction + coarse first sweep
             b += 2 * word * dof[0] + word * c      # prolongation + post-smoothing
         else:
             b += 2 * word * dof[l] + word * c * (2 if l + 1 < L else 1)
@@ -227,7 +266,19 @@ def time_kernels(h, U, u0, iters):
     k["k_restrict_blk"] = (_events(s, iters, lambda: h.restrict_residual(0, Uin, fc, u0=u0)), 8.0 * dof0 + 8.0 * dof1)
     k["k_prolong_smooth_blk"] = (_events(s, iters, lambda: h.prolong_smooth(0, ec, Uout, Uin=Uin, u0=u0)),
                                  16.0 * dof0 + 8.0 * dof1)
-    kernels = {name: {"ms": ms, "bytes": b, "GBs": b / (ms * 1e-3) / 1e9} for name, (ms, b) in k.items()}
+    # the V-cycle's level-0 sweep and restriction as one kernel, where the grid allows it
+    uc = torch.empty(shape1, dtype=torch.float64, device=U.device)
+    try:
+        h.smooth_restrict(0, Uout, fc, Uin=Uin, uc=uc, u0=u0)
+        fused0 = True
+    except B.STMGError:
+        fused0 = False
+    if fused0:
+        k["k_smooth_restrict"] = (_events(s, iters, lambda: h.smooth_restrict(0, Uout, fc, Uin=Uin, uc=uc, u0=u0)),
+                                  sr_bytes(lv[0], lv[1], zs=True))
+    kernels = {name: {"ms": ms, "bytes": b, "GBs": b / (ms * 1e-3) / 1e9,
+                      "in_cycle": name == "k_prolong_smooth_blk" or (name == "k_smooth_restrict") == fused0}
+               for name, (ms, b) in k.items()}
     # whole cycles, no host synchronization in between
     V = torch.zeros_like(U)
     L = B.lib()
@@ -238,8 +289,8 @@ def time_kernels(h, U, u0, iters):
     y = torch.empty_like(x)
     with torch.cuda.stream(s):
         c_ms = _events(s, iters, lambda: y.copy_(x))
-    del Uin, Uout, ec, fc, V, x, y
-    return kernels, cyc_ms, lv, c_ms, 2.0 * U.numel() * 8
+    del Uin, Uout, ec, fc, uc, V, x, y
+    return kernels, cyc_ms, lv, c_ms, 2.0 * U.numel() * 8, fused0
 
 
 EXTRA_GROUPS = ("heat1d", "allen_cahn", "adjoint", "batch", "sdc", "pfasst", "hierarchies", "krylov", "paper")
@@ -742,8 +793,8 @@ def main():
     if a.kernel_only or a.cycle_only:
         h = stmg.Handle(prob, device=dev)
         U = torch.randn(shape, dtype=torch.float64, device=dev)
-        kernels, cyc_ms, lv, c_ms, cbytes = time_kernels(h, U, u0, a.kernel_iters)
-        cb, _ = cycle_bytes(lv)
+        kernels, cyc_ms, lv, c_ms, cbytes, fused0 = time_kernels(h, U, u0, a.kernel_iters)
+        cb, _ = cycle_bytes(lv, fused0=fused0)
         print(json.dumps({"kernels": kernels, "vcycle_ms": cyc_ms, "vcycle_bytes": cb,
                           "copy_ms": c_ms, "copy_bytes": cbytes, "copy_GBs": cbytes / c_ms / 1e6}))
         return
@@ -801,10 +852,11 @@ def main():
     print("time-to-1e-10 done", file=sys.stderr, flush=True)
 
     # the V-cycle's kernels and whole cycles against the HBM roofline
-    kernels, cyc_ms, lv, c_ms, cbytes = time_kernels(h, U, u0, a.kernel_iters)
-    cb, per_level = cycle_bytes(lv)
+    kernels, cyc_ms, lv, c_ms, cbytes, fused0 = time_kernels(h, U, u0, a.kernel_iters)
+    cb, per_level = cycle_bytes(lv, fused0=fused0)
+    cb2, _ = cycle_bytes(lv)
     mb = model_cycle_bytes(lv)
-    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    dom = max((k for k in kernels if kernels[k]["in_cycle"]), key=lambda k: kernels[k]["ms"])
     kd = kernels[dom]
     achieved = kd["GBs"]
     print("kernel timing done", file=sys.stderr, flush=True)
@@ -829,13 +881,16 @@ def main():
         "time_to_1e-10": ttr,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if dom == "k_prolong_smooth_blk" else None,
+                     "traffic": measured_traffic(dom),
                      "kernel": dom + " (level 0, the longest kernel of the V-cycle)",
                      "kernel_ms": kd["ms"], "bytes_per_launch": kd["bytes"],
                      "level0_kernels": kernels,
                      "cycle_ms": cyc_ms, "cycle_bytes": cb, "cycle_bytes_per_level": per_level,
                      "cycle_GBs": cb / (cyc_ms * 1e-3) / 1e9,
                      "cycle_frac": cb / (cyc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     # priced at the bytes of separate level-0 sweep and restriction kernels
+                     "cycle_bytes_separate_level0": cb2,
+                     "cycle_frac_separate_level0": cb2 / (cyc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "copy_GBs_smoother_bytes": cbytes / (c_ms * 1e-3) / 1e9,
                      # the same cycle priced at the unfused per-unit word counts:
                      # the fusions save the difference to cycle_bytes

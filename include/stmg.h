@@ -55,7 +55,7 @@ typedef enum {
   STMG_ENOMEM = -2,        /* workspace too small                             */
   STMG_EHIP = -3,          /* a HIP runtime call failed                       */
   STMG_ENOTCONV = -4,      /* max_cycles reached before rtol ("n.c.", Sec. 5.2) */
-  STMG_EDIVERGED = -5,     /* residual grew by 1e3 or for 5 cycles in a row   */
+  STMG_EDIVERGED = -5,     /* residual grew by 1e3, or by > 10% per cycle for 5 cycles in a row */
   STMG_ENAN = -6,          /* a residual norm was NaN or Inf                  */
   STMG_EUNSUPPORTED = -7   /* valid but not supported (e.g. coarsest too big) */
 } stmg_status;
@@ -381,6 +381,21 @@ int stmg_coarse_solve(stmg_handle* h, const double* d_f, double* d_U);
  * on windowed handles. */
 int stmg_level_prolong_smooth(stmg_handle* h, int level, const double* d_f, const double* d_u0,
                               const double* d_Uin, const double* d_ec, double* d_Uout);
+/* The V-cycle's way down on level 0 as one fused sweep (Sec. 4.2: the
+ * pre-smoothing sweep, then the restriction of the new residual): U_out =
+ * U_in + omega C^{-1} (f - A_0 U_in) (the block-Jacobi sweep of
+ * stmg_level_smooth), d_fc = R (f - A_0 U_out) (as stmg_level_restrict_residual
+ * of U_out), and when d_uc is not NULL the coarse level's first block-Jacobi
+ * sweep from zero with d_fc as right-hand side.  The residual of U_out is
+ * formed from the sweep's own residual and correction, so the result agrees
+ * with the two separate calls up to rounding.  Arrays in the level layouts
+ * [N][M][ny][nx] (d_fc, d_uc: level 1); U_in may be NULL (zero), f may be
+ * NULL (built from d_u0).  EUNSUPPORTED unless the problem is 2D, periodic
+ * and linear, level 0 coarsens in space only, nx is a multiple of 64, ny of
+ * 16, M <= 4 and the level-0 smoother chunk a multiple of the level-1 one
+ * (at most 8); EINVAL for a level other than 0. */
+int stmg_level_smooth_restrict(stmg_handle* h, int level, const double* d_f, const double* d_u0,
+                               const double* d_Uin, double* d_Uout, double* d_fc, double* d_uc);
 
 void stmg_destroy(stmg_handle* h);
 

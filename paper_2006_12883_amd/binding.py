@@ -27,7 +27,7 @@ EXPORTS = [
     "stmg_level_shape", "stmg_level_nodes", "stmg_residual", "stmg_residual_noalloc", "stmg_vcycle", "stmg_solve", "stmg_solve_end",
     "stmg_num_windows", "stmg_tuned_shape", "stmg_adjoint",
     "stmg_sdc_sweep", "stmg_pfasst_solve", "stmg_level_smooth", "stmg_level_restrict_residual",
-    "stmg_level_prolong", "stmg_level_prolong_smooth", "stmg_coarse_solve", "stmg_destroy",
+    "stmg_level_prolong", "stmg_level_prolong_smooth", "stmg_level_smooth_restrict", "stmg_coarse_solve", "stmg_destroy",
     "stmg_batch_workspace_bytes", "stmg_batch_setup", "stmg_batch_solve",
     "stmg_batch_destroy", "stmg_status_string", "stmg_last_error",
 ]
@@ -95,6 +95,7 @@ def lib():
             "stmg_level_restrict_residual": (ip, [vp, ip, vp, vp, vp, vp]),
             "stmg_level_prolong": (ip, [vp, ip, vp, vp, vp]),
             "stmg_level_prolong_smooth": (ip, [vp, ip, vp, vp, vp, vp, vp]),
+            "stmg_level_smooth_restrict": (ip, [vp, ip, vp, vp, vp, vp, vp, vp]),
             "stmg_coarse_solve": (ip, [vp, vp, vp]),
             "stmg_destroy": (None, [vp]),
             "stmg_batch_workspace_bytes": (sz, [ctypes.c_int32, P, O]),

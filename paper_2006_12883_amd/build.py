@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstmg.so")
 SOURCES = ["inst_smooth_f64.hip", "inst_smooth_f32.hip", "inst_restrict_f64.hip", "inst_restrict_f32.hip",
-           "inst_resid.hip", "inst_prolong.hip", "inst_fft.hip", "inst_galerkin.hip", "kernels_misc.hip", "krylov.hip", "coarse_coef.hip", "coarse_scan.hip", "solver.hip", "pfasst.hip", "capi.hip", "batch.hip", "tables.cpp"]
+           "inst_resid.hip", "inst_prolong.hip", "inst_fft.hip", "inst_galerkin.hip", "smooth_restrict.hip", "kernels_misc.hip", "krylov.hip", "coarse_coef.hip", "coarse_scan.hip", "solver.hip", "pfasst.hip", "capi.hip", "batch.hip", "tables.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

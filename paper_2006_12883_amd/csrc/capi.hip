@@ -288,6 +288,22 @@ int stmg_level_prolong_smooth(stmg_handle* h, int level, const double* d_f, cons
   return e == hipSuccess ? STMG_OK : STMG_EHIP;
 }
 
+int stmg_level_smooth_restrict(stmg_handle* h, int level, const double* d_f, const double* d_u0,
+                               const double* d_Uin, double* d_Uout, double* d_fc, double* d_uc) {
+  if (!h || !d_Uout || !d_fc || level != 0 || h->s.lv.size() < 2) {
+    stmg::set_error("bad argument");
+    return STMG_EINVAL;
+  }
+  if (h->s.win) { stmg::set_error("windowed handle"); return STMG_EUNSUPPORTED; }
+  if (!h->s.sr_usable(stmg::REACT_CONST)) {
+    stmg::set_error("fused smoothing + restriction: 2D periodic linear problems with space coarsening on level 0, "
+                    "nx a multiple of 64, ny of 16, M <= 4, the smoother chunk a multiple of the coarse one");
+    return STMG_EUNSUPPORTED;
+  }
+  hipError_t e = h->s.smooth_restrict<double>(false, d_Uin, d_f, d_u0, d_Uout, d_fc, d_uc, nullptr, nullptr);
+  return e == hipSuccess ? STMG_OK : STMG_EHIP;
+}
+
 int stmg_coarse_solve(stmg_handle* h, const double* d_f, double* d_U) {
   if (!h || !d_U) { stmg::set_error("bad argument"); return STMG_EINVAL; }
   if (h->s.win) { stmg::set_error("windowed handle"); return STMG_EUNSUPPORTED; }

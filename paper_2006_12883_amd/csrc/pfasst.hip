@@ -363,7 +363,8 @@ int Solver::pfasst(const double* u0, double* U, stmg_stats* st) {
     if (rel <= opt.rtol) { status = STMG_OK; break; }
     if (rel0 < 0.0) rel0 = rel;
     if (rel > 1e3 * (rel0 > 0.0 ? rel0 : 1.0)) { status = STMG_EDIVERGED; break; }
-    incr = (it > 0 && rel > prev) ? incr + 1 : 0;
+    // growth of more than 10% per iteration, five in a row (not rounding-floor noise)
+    incr = (it > 0 && rel > 1.1 * prev) ? incr + 1 : 0;
     if (incr >= 5) { status = STMG_EDIVERGED; break; }
     prev = rel;
   }

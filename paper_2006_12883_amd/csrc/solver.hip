@@ -21,6 +21,7 @@ constexpr size_t kCoarseInvMaxBytes = size_t(1) << 30;  // Newton coarsest inver
 constexpr int kScanMinSlabs = 32;  // shorter coarsest levels keep the one-kernel recurrence
 constexpr int kTransferSlabs = 4;
 constexpr int kInnerMax = 64;  // inner_cycles bound
+constexpr double kGrowth = 1.1;  // divergence test: per-cycle growth that counts
 
 // Elements -> points per dimension.
 int points(int e, int bc) { return bc == STMG_BC_PERIODIC ? e : e + 1; }
@@ -470,6 +471,22 @@ size_t Solver::plan(char* ws) {
     kpart = pl.take<double>(static_cast<size_t>(kKrylovParts) * (kKrylovMax + 2));
     kdev = pl.take<double>(1 + 3 * (kKrylovMax + 2));
   }
+  // level-0 pre-smoothing fused with the restriction: space coarsening by
+  // two of a 2D periodic level whose tiles cover the coarse grid, linear
+  // constant reaction, the point-block smoother on both levels
+  sr = false;
+  if (lv.size() >= 2) {
+    const Level& l = lv[0];
+    const Level& c = lv[1];
+    sr = fuse && !allen_cahn && !l.g9 && !c.g9 && (l.kind & 1) && !(l.kind & 2) && !(l.kind & 4) &&
+         smooth_restrict_ok(l.op, REACT_CONST, c.nx, c.ny, c.N, chunk_of(0), chunk_of(1)) &&
+         smooth_restrict_ok(l.opT, REACT_CONST, c.nx, c.ny, c.N, chunk_of(0), chunk_of(1));
+    if (sr) {
+      const size_t zn = smooth_restrict_zbuf(l.op, chunk_of(0));
+      sr_z64 = zn ? pl.take<double>(zn) : nullptr;
+      sr_z32 = (zn && mixed) ? pl.take<float>(zn) : nullptr;
+    }
+  }
   // partial sums: the largest residual launch is on level 0
   {
     const Level& l = lv[0];
@@ -478,6 +495,7 @@ size_t Solver::plan(char* ws) {
     max_parts = tiles * chunks;
     const int sb = smooth_blocks(l.op, chunk_of(0));
     if (max_parts < sb) max_parts = sb;
+    if (sr && max_parts < smooth_restrict_blocks(l.op, chunk_of(0))) max_parts = smooth_restrict_blocks(l.op, chunk_of(0));
     if (max_parts < 1024) max_parts = 1024;
   }
   part = pl.take<double>(static_cast<size_t>(max_parts));
@@ -928,6 +946,32 @@ hipError_t Solver::smooth(int l, bool adj, int react, const T* U, const T* f, co
   return launch_smooth<T>(adj ? L.opT : L.op, react, a, chunk_of(l), stream);
 }
 
+bool Solver::sr_usable(int react) const {
+  return sr && fuse && react == REACT_CONST && opt.smoother == STMG_SMOOTH_PBJ;
+}
+
+template <typename T>
+T* sr_zbuf(double* z64, float* z32);
+template <>
+double* sr_zbuf<double>(double* z64, float*) { return z64; }
+template <>
+float* sr_zbuf<float>(double*, float* z32) { return z32; }
+
+template <typename T>
+hipError_t Solver::smooth_restrict(bool adj, const T* U, const T* f, const double* u0, T* out, T* fc, T* uc,
+                                   double* part_out, bool* smoothed) {
+  const Level& L = lv[0];
+  const Level& C = lv[1];
+  SweepPtrs<T> a{U, f, u0, nullptr, out, part_out};
+  if (part_out && smooth_restrict_blocks(L.op, chunk_of(0)) > max_parts) {
+    set_error("partial buffer too small");
+    return hipErrorInvalidValue;
+  }
+  if (smoothed) *smoothed = uc != nullptr;
+  return launch_smooth_restrict<T>(adj ? L.opT : L.op, a, C.nx, C.ny, fc, chunk_of(0), adj ? &C.opT : &C.op, uc,
+                                   chunk_of(1), sr_zbuf<T>(sr_z64, sr_z32), stream);
+}
+
 template <typename T>
 hipError_t Solver::restrict_residual(int l, bool adj, int react, const T* U, const T* f,
                                      const double* u0, T* fc, T* uc, bool* smoothed) {
@@ -1063,11 +1107,6 @@ hipError_t Solver::vcycle(int l, bool adj, int react, T* cur, T* oth, const T* f
       return hipSuccess;
     }
   }
-  for (int s = skip_pre; s < opt.nu_pre; ++s) {
-    HIP_TRY(smooth<T>(l, adj, react, zero ? nullptr : cur, f, u0, oth));
-    std::swap(cur, oth);
-    zero = false;
-  }
   Level& C = lv[l + 1];
   T* cf = nullptr;
   T* ca = nullptr;
@@ -1075,11 +1114,32 @@ hipError_t Solver::vcycle(int l, bool adj, int react, T* cur, T* oth, const T* f
   if constexpr (sizeof(T) == 8) { cf = C.f64; ca = C.A64; cb = C.B64; }
   else { cf = C.f32; ca = C.A32; cb = C.B32; }
   // Descend: the restriction also does the coarse level's first smoothing
-  // sweep from a zero iterate when the kernel supports it.
+  // sweep from a zero iterate when the kernel supports it.  On level 0 the
+  // last pre-smoothing sweep and the restriction are one kernel where the
+  // grid allows it (or were, when the caller's sweep already restricted).
   const bool want = fuse && opt.nu_pre >= 1 && l + 1 < last;
   bool smoothed = false;
-  HIP_TRY(restrict_residual<T>(l, adj, react, zero ? nullptr : cur, f, u0, cf,
-                               want ? ca : nullptr, &smoothed));
+  bool restricted = false;
+  if (l == 0 && skip_pre >= 1 && sr_pending) {
+    restricted = true;
+    smoothed = sr_smoothed;
+    sr_pending = false;
+  }
+  const bool use_sr = l == 0 && !restricted && sr_usable(react) && opt.nu_pre > skip_pre;
+  for (int s = skip_pre; s < opt.nu_pre; ++s) {
+    if (use_sr && s == opt.nu_pre - 1) {
+      HIP_TRY(smooth_restrict<T>(adj, zero ? nullptr : cur, f, u0, oth, cf, want ? ca : nullptr, nullptr,
+                                 &smoothed));
+      restricted = true;
+    } else {
+      HIP_TRY(smooth<T>(l, adj, react, zero ? nullptr : cur, f, u0, oth));
+    }
+    std::swap(cur, oth);
+    zero = false;
+  }
+  if (!restricted)
+    HIP_TRY(restrict_residual<T>(l, adj, react, zero ? nullptr : cur, f, u0, cf,
+                                 want ? ca : nullptr, &smoothed));
   if (l == 0 && gate0) {
     // Nothing written so far touches the caller's iterate.
     bool stop = false;
@@ -1194,8 +1254,16 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
   // Queues ||f - A U||^2 of the current iterate, written straight into the
   // pinned host slot, and an event behind it.
   double* const out = hnorm.d;
+  sr_pending = false;
   auto launch_norm = [&]() -> hipError_t {
-    if (fused) {
+    if (fused && opt.nu_pre == 1 && lv.size() > 1 && sr_usable(react)) {
+      // the only pre-smoothing sweep also restricts
+      Level& C = lv[1];
+      const bool want = fuse && lv.size() > 2;
+      HIP_TRY(smooth_restrict<double>(adj, U, f, u0, L0.B64, C.f64, want ? C.A64 : nullptr, part, &sr_smoothed));
+      sr_pending = true;
+      HIP_TRY(launch_sum_partials(part, smooth_restrict_blocks(op0, chunk_of(0)), out, stream));
+    } else if (fused) {
       SweepPtrs<double> a{U, f, u0, L0.coef64, L0.B64, part};
       HIP_TRY(launch_smooth<double>(op0, react, a, chunk_of(0), stream));
       HIP_TRY(launch_sum_partials(part, smooth_blocks(op0, chunk_of(0)), out, stream));
@@ -1241,7 +1309,9 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
     if (rel <= rtol) return hipSuccess;
     if (c > 0) {
       if (rel > 1e3 * (rel0 > 0 ? rel0 : 1.0)) { status = STMG_EDIVERGED; return hipSuccess; }
-      incr = rel > prev ? incr + 1 : 0;
+      // growth of more than 10% per cycle, five cycles in a row (at the rounding
+      // floor the norm moves by far less, either way)
+      incr = rel > kGrowth * prev ? incr + 1 : 0;
       if (incr >= 5) { status = STMG_EDIVERGED; return hipSuccess; }
     }
     prev = rel;
@@ -1341,6 +1411,7 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
     double* fin = ecur ? Unext : Ucur;
     if (fin != U) HIP_CHECK(hipMemcpyAsync(U, fin, L0.n * sizeof(double), hipMemcpyDeviceToDevice, stream));
   }
+  sr_pending = false;
   *cycles += vc;
   if (refinements) *refinements += mixed ? c : 0;
   *rel_out = rel;
@@ -1917,6 +1988,8 @@ int Solver::sdc_core(const double* u0, double* U, int sweeps) {
 // explicit instantiations used by the C ABI
 template hipError_t Solver::smooth<double>(int, bool, int, const double*, const double*, const double*, double*);
 template hipError_t Solver::restrict_residual<double>(int, bool, int, const double*, const double*, const double*, double*, double*, bool*);
+template hipError_t Solver::smooth_restrict<double>(bool, const double*, const double*, const double*, double*, double*,
+                                                    double*, double*, bool*);
 template hipError_t Solver::prolong<double>(int, const double*, const double*, double*);
 template hipError_t Solver::coarse<double>(bool, int, const double*, const double*, double*);
 template hipError_t Solver::residual64<double>(bool, int, const double*, const double*, const double*, double*,
@@ -2032,5 +2105,7 @@ int Solver::autotune() {
 }
 
 template hipError_t Solver::restrict_residual<float>(int, bool, int, const float*, const float*, const double*, float*, float*, bool*);
+template hipError_t Solver::smooth_restrict<float>(bool, const float*, const float*, const double*, float*, float*,
+                                                   float*, double*, bool*);
 
 }  // namespace stmg

@@ -171,6 +171,16 @@ struct Solver {
   const double* up_in = nullptr;
   double* up_out = nullptr;
   bool up_done = false;
+  // Level-0 pre-smoothing fused with the residual restriction
+  // (launch_smooth_restrict): possible for this hierarchy (sr), its run
+  // boundary planes, and the hand-over from the FP64 solve's norm sweep to
+  // the cycle (sr_pending: the sweep in the cycle's iterate buffer has also
+  // restricted; sr_smoothed: with the coarse first sweep).
+  bool sr = false;
+  double* sr_z64 = nullptr;
+  float* sr_z32 = nullptr;
+  bool sr_pending = false;
+  bool sr_smoothed = false;
 
   // Time windows (adjoint checkpointing).  When the options' memory budget
   // cannot hold the trajectory, the handle drives a sub-solver for W slabs
@@ -245,6 +255,12 @@ struct Solver {
   template <typename T>
   hipError_t restrict_residual(int l, bool adj, int react, const T* U, const T* f,
                                const double* u0, T* fc, T* uc = nullptr, bool* smoothed = nullptr);
+  // Level 0: one smoothing sweep U -> out fused with f_c = R (f - A out)
+  // (uc: the coarse first sweep), part: per-workgroup ||f - A U||^2 or null.
+  bool sr_usable(int react) const;
+  template <typename T>
+  hipError_t smooth_restrict(bool adj, const T* U, const T* f, const double* u0, T* out, T* fc, T* uc,
+                             double* part_out, bool* smoothed);
   template <typename T>
   hipError_t prolong_smooth(int l, bool adj, int react, const T* Uin, const T* ec, const T* f,
                             const double* u0, T* out);

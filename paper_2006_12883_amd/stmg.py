@@ -154,6 +154,10 @@ class Handle:
         B.check(B.lib().stmg_level_prolong(self.h, level, _ptr(Uin), _ptr(ec), _ptr(Uout)),
                 "stmg_level_prolong")
 
+    def smooth_restrict(self, level, Uout, fc, Uin=None, uc=None, f=None, u0=None):
+        B.check(B.lib().stmg_level_smooth_restrict(self.h, level, _ptr(f), _ptr(u0), _ptr(Uin), _ptr(Uout),
+                                                   _ptr(fc), _ptr(uc)), "stmg_level_smooth_restrict")
+
     def prolong_smooth(self, level, ec, Uout, Uin=None, f=None, u0=None):
         B.check(B.lib().stmg_level_prolong_smooth(self.h, level, _ptr(f), _ptr(u0), _ptr(Uin), _ptr(ec),
                                                   _ptr(Uout)), "stmg_level_prolong_smooth")
