@@ -305,3 +305,40 @@ def test_neumann_fixed_points_and_vcycle(prob):
     U, hist = mg.solve(prob, u0, rtol=1e-12, max_cycles=150, fft_coarse=0, min_coarse=16)
     assert hist[-1] <= 1e-12
     assert np.linalg.norm(U - Ue) <= 1e-10 * np.linalg.norm(Ue)
+
+
+@pytest.mark.parametrize("dim,M,chunk", [(2, 3, 16), (2, 2, 3), (1, 4, 1), (2, 1, 5)])
+def test_swept_residual_identity(dim, M, chunk):
+    """The residual after one block-Jacobi sweep (Sec. 4.2), f - A (U + omega d)
+    with d = C^{-1}(f - A U), equals
+
+      (1 - omega) r + omega dt b (cx (d_W + d_E) + cy (d_S + d_N))
+        + omega l(0) d_{n-1,M} at chunk starts n > 0,
+
+    the form in which the fused level-0 sweep + restriction forms it (C: the
+    slab block on the diagonal and the chunk-internal coupling).  Periodic
+    neighbours by rolling the arrays; a dropped coupling term, a wrong sign of
+    the neighbour sum or a chunk-start term at the wrong slabs fails."""
+    prob = si.problem(dim, 32 if dim == 2 else 64, M, 12, 0.3, nu=0.03, lam=0.7)
+    levels, kinds = mg.hierarchy(prob, coarsen="space")
+    lev = levels[0]
+    rng = np.random.default_rng(11)
+    U = rng.standard_normal(lev.shape)
+    f = rng.standard_normal(lev.shape)
+    omega = 0.8
+    r = f - lev.apply(U)
+    Us = lev.smooth(U, f, omega, chunk)
+    d = (Us - U) / omega
+    direct = f - lev.apply(Us)
+    nb = lev.cx * (np.roll(d, 1, axis=-1) + np.roll(d, -1, axis=-1))
+    if dim == 2:
+        nb = nb + lev.cy * (np.roll(d, 1, axis=-2) + np.roll(d, -1, axis=-2))
+    form = (1 - omega) * r + omega * lev.dt * lev.b[None, :, None, None] * nb
+    for n in range(chunk, lev.N, chunk):
+        form[n] += omega * lev.l0[:, None, None] * d[n - 1, -1][None]
+    scale = np.abs(direct).max()
+    assert np.abs(form - direct).max() <= 1e-12 * scale
+    # the chunk-start term matters: without it the first slab of a chunk is off
+    if chunk < lev.N:
+        wrong = (1 - omega) * r + omega * lev.dt * lev.b[None, :, None, None] * nb
+        assert np.abs(wrong - direct).max() > 1e-6 * scale
