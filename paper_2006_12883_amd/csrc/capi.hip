@@ -295,12 +295,13 @@ int stmg_level_smooth_restrict(stmg_handle* h, int level, const double* d_f, con
     return STMG_EINVAL;
   }
   if (h->s.win) { stmg::set_error("windowed handle"); return STMG_EUNSUPPORTED; }
-  if (!h->s.sr_usable(stmg::REACT_CONST)) {
+  if (h->s.allen_cahn || !h->s.sr_usable(stmg::REACT_CONST, true)) {
     stmg::set_error("fused smoothing + restriction: 2D periodic linear problems with space coarsening on level 0, "
                     "nx a multiple of 64, ny of 16, M <= 4, the smoother chunk a multiple of the coarse one");
     return STMG_EUNSUPPORTED;
   }
-  hipError_t e = h->s.smooth_restrict<double>(false, d_Uin, d_f, d_u0, d_Uout, d_fc, d_uc, nullptr, nullptr);
+  hipError_t e = h->s.smooth_restrict<double>(false, stmg::REACT_CONST, d_Uin, d_f, d_u0, d_Uout, d_fc, d_uc, nullptr,
+                                              nullptr);
   return e == hipSuccess ? STMG_OK : STMG_EHIP;
 }
 

@@ -114,7 +114,8 @@ hipError_t launch_prolong_smooth(const OpParams& p, int react, const SweepPtrs<T
 bool blocked_layout(const OpParams& p);
 
 // Level-0 smoothing sweep fused with the restriction of the swept iterate's
-// residual (2D periodic, constant reaction, space coarsening by 2, nx a
+// residual (2D periodic, constant reaction or REACT_COEF with a.coef and the
+// coarse coefficients coefc, space coarsening by 2, nx a
 // multiple of 64, ny of 16, M <= 4; the smoother's chunks of `chunk` slabs,
 // a multiple of the coarse chunk cs): a.out = U + omega C^{-1}(f - A U),
 // fc = R (f - A a.out) and, with pc and uc, the coarse level's first sweep
@@ -125,8 +126,9 @@ bool smooth_restrict_ok(const OpParams& p, int react, int ncx, int ncy, int Nc, 
 int smooth_restrict_blocks(const OpParams& p, int chunk);
 size_t smooth_restrict_zbuf(const OpParams& p, int chunk);
 template <typename T>
-hipError_t launch_smooth_restrict(const OpParams& p, const SweepPtrs<T>& a, int ncx, int ncy, T* fc, int chunk,
-                                  const OpParams* pc, T* uc, int cs, T* zbuf, hipStream_t s);
+hipError_t launch_smooth_restrict(const OpParams& p, int react, const SweepPtrs<T>& a, int ncx, int ncy, T* fc,
+                                  int chunk, const OpParams* pc, T* uc, const T* coefc, int cs, T* zbuf,
+                                  hipStream_t s);
 
 // Galerkin levels: r = f - A U (U may be null: zero) into out, and one
 // block-Jacobi sweep over chunks of `chunk` slabs (point-diagonal parts of

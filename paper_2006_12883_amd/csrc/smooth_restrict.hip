@@ -1,11 +1,13 @@
 // Level-0 pre-smoothing sweep fused with the restriction of the smoothed
 // iterate's residual (Sec. 4.2: one block-Jacobi sweep, then R (f - A U')),
-// for 2D periodic levels with a constant reaction, space coarsening, and
-// tiles of 32 x 8 coarse points that cover the coarse grid exactly.
+// for 2D periodic levels with a constant reaction or (FP32) a per-point
+// reaction coefficient (the Newton linearization), space coarsening, and tiles of
+// 32 x 8 coarse points that cover the coarse grid exactly.
 //
 // With the sweep U' = U + omega d, d = C^{-1} r, r = f - A U (C: the slab
 // blocks B on the diagonal and -cin cout^T below it inside a chunk), the
-// residual of U' needs no second stencil pass over U':
+// residual of U' needs no second stencil pass over U' (the reaction is
+// pointwise, so a reaction coefficient sits in C's point blocks):
 //   f - A U' = (1 - omega) r - omega (A - C) d,
 //   (A - C) d = -db (cx (d_W + d_E) + cy (d_S + d_N)) - [chunk start] cin (cout . d_{n-1}),
 // so a tile needs r on its points and d on their spatial neighbours.  One
@@ -55,11 +57,12 @@ __device__ __forceinline__ void sr_ring_point(int t, int& lx, int& ly) {
   else { lx = t - 181; ly = kSrFY; }
 }
 
-template <int M, typename T, bool ZS, bool HASF>
+template <int M, typename T, int REACT, bool ZS, bool HASF>
 __global__ __launch_bounds__(kBlock) void k_smooth_restrict(const OpParams p, const SweepPtrs<T> a, int ncx,
                                                             int ncy, T* __restrict__ fc, int RL, int chunk, int tiles_x,
                                                             int tiles, int nblocks, const OpParams pc,
-                                                            T* __restrict__ uc, int cs, T* __restrict__ zbuf) {
+                                                            T* __restrict__ uc, const T* __restrict__ coefc, int cs,
+                                                            T* __restrict__ zbuf) {
   __shared__ T Dt[M * kSrDH * kSrDW];
   __shared__ T Rt[M * kSrRH * kSrRW];
   auto dt = [&](int i, int ly, int lx) -> T& { return Dt[(i * kSrDH + ly + 2) * kSrDW + lx + 2]; };
@@ -71,6 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_restrict(const OpParams p, co
   if (n0 < p.N) {
     const int n1 = min(n0 + RL, p.N);
     const Consts<M, T> c(p);
+    const T dg = T(2) * c.cx + T(2) * c.cy;
     const int nx = p.nx, ny = p.ny, P = nx * ny, Pc = ncx * ncy;
     const int X0 = (tile % tiles_x) * kSrTCX, Y0 = (tile / tiles_x) * kSrTCY;
     const int tx = threadIdx.x % kSrTCX, ty = threadIdx.x / kSrTCX;
@@ -118,6 +122,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_restrict(const OpParams p, co
 #pragma unroll
           for (int m = 0; m < M; ++m) u[k][m] = lap[k][m] = T(0);
       }
+      T cv[4][M];
+      if (REACT == REACT_COEF) load_own<M, T, 2>(a.coef, base, P, nx, b, cv);
       if (HASF) {
         load_own<M, T, 2>(a.f, base, P, nx, b, fv);
       } else {
@@ -135,21 +141,18 @@ __global__ __launch_bounds__(kBlock) void k_smooth_restrict(const OpParams p, co
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         zp[k] = dprev[k];
-        resid_vals<M, T, REACT_CONST>(c, u[k], lap[k], fv[k], fv[k], prev[k], r[k]);
+        resid_vals<M, T, REACT>(c, u[k], lap[k], fv[k], cv[k], prev[k], r[k]);
         if (a.part) ssq_add<M, T>(p, r[k], ssq);
         T x[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) x[i] = cstart ? r[k][i] : r[k][i] + c.cin[i] * dprev[k];
-        T np = T(0), nd = T(0);
+        // the point block solve (with the point's reaction coefficient for REACT_COEF)
+        const T nd = point_correction<M, T, REACT>(c, dg, cv[k], x, d[k]);
+        T np = T(0);
 #pragma unroll
         for (int i = 0; i < M; ++i) {
-          T sm = T(0);
-#pragma unroll
-          for (int j = 0; j < M; ++j) sm += c.Bi[i][j] * x[j];
-          d[k][i] = sm;
-          o[k & 1][i] = u[k][i] + c.omega * sm;
+          o[k & 1][i] = u[k][i] + c.omega * d[k][i];
           np += c.cout[i] * u[k][i];
-          nd += c.cout[i] * sm;
         }
         prev[k] = np;
         dprev[k] = nd;
@@ -179,19 +182,19 @@ __global__ __launch_bounds__(kBlock) void k_smooth_restrict(const OpParams p, co
 #pragma unroll
           for (int m = 0; m < M; ++m) ru[m] = rl[m] = T(0);
         }
-        point_residual<M, T, REACT_CONST>(c, ru, rl, nullptr, HASF ? a.f : nullptr, base, P, rq, rprev, hr);
-        T x[M];
-#pragma unroll
-        for (int i = 0; i < M; ++i) x[i] = cstart ? hr[i] : hr[i] + c.cin[i] * rdprev;
-        T np = T(0), nd = T(0);
+        point_residual<M, T, REACT>(c, ru, rl, a.coef, HASF ? a.f : nullptr, base, P, rq, rprev, hr);
+        T x[M], rd[M], rcv[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) {
-          T sm = T(0);
+          x[i] = cstart ? hr[i] : hr[i] + c.cin[i] * rdprev;
+          rcv[i] = REACT == REACT_COEF ? a.coef[base + (size_t)i * P + rq] : T(0);
+        }
+        const T nd = point_correction<M, T, REACT>(c, dg, rcv, x, rd);
+        T np = T(0);
 #pragma unroll
-          for (int j = 0; j < M; ++j) sm += c.Bi[i][j] * x[j];
-          dt(i, rly, rlx) = sm;
+        for (int i = 0; i < M; ++i) {
+          dt(i, rly, rlx) = rd[i];
           np += c.cout[i] * ru[i];
-          nd += c.cout[i] * sm;
         }
         rprev = np;
         rdprev = nd;
@@ -242,19 +245,16 @@ __global__ __launch_bounds__(kBlock) void k_smooth_restrict(const OpParams p, co
       for (int i = 0; i < M; ++i) __builtin_nontemporal_store(rc[i], fc + cb + (size_t)i * Pc + qc);
       if (ZS) {
         const Consts<M, T> k(pc);
-        T rr[M];
-#pragma unroll
-        for (int i = 0; i < M; ++i) rr[i] = rc[i] + ((n % cs) != 0 ? k.cin[i] * zdprev : T(0));
-        T nd = T(0);
+        const T dgc = T(2) * k.cx + T(2) * k.cy;
+        T rr[M], cvv[M], dd[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) {
-          T sm = T(0);
-#pragma unroll
-          for (int j = 0; j < M; ++j) sm += k.Bi[i][j] * rr[j];
-          __builtin_nontemporal_store(k.omega * sm, uc + cb + (size_t)i * Pc + qc);
-          nd += k.cout[i] * sm;
+          rr[i] = rc[i] + ((n % cs) != 0 ? k.cin[i] * zdprev : T(0));
+          cvv[i] = REACT == REACT_COEF ? coefc[cb + (size_t)i * Pc + qc] : T(0);
         }
-        zdprev = nd;
+        zdprev = point_correction<M, T, REACT>(k, dgc, cvv, rr, dd);
+#pragma unroll
+        for (int i = 0; i < M; ++i) __builtin_nontemporal_store(k.omega * dd[i], uc + cb + (size_t)i * Pc + qc);
       }
     }
     // cout . d of the run's last slab, for the next run's first slab
@@ -273,10 +273,11 @@ __global__ __launch_bounds__(kBlock) void k_smooth_restrict(const OpParams p, co
 // The first slab J of every run but the first: f_c[J] += omega cin R z with
 // z = cout . d of slab J - 1 (full weighting, periodic), and with ZS the
 // coarse sweep's response along the coarse chunk that J starts.
-template <int M, typename T, bool ZS>
+template <int M, typename T, int REACT, bool ZS>
 __global__ __launch_bounds__(kBlock) void k_sr_fixup(const OpParams p, int ncx, int ncy, int RL, int nbound,
                                                      T* __restrict__ fc, const OpParams pc, T* __restrict__ uc,
-                                                     int cs, const T* __restrict__ zbuf) {
+                                                     const T* __restrict__ coefc, int cs,
+                                                     const T* __restrict__ zbuf) {
   const int Pc = ncx * ncy;
   const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= (long long)Pc * nbound) return;
@@ -298,6 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_sr_fixup(const OpParams p, int ncx, 
   for (int i = 0; i < M; ++i) fc[cb + (size_t)i * Pc + qc] += c.cin[i] * s;
   if (ZS) {
     const Consts<M, T> k(pc);
+    const T dgc = T(2) * k.cx + T(2) * k.cy;
     const int nj = min(cs, p.N - J);
     // the chunk's values are read before the recurrence (at most kSrMaxCs slabs)
     T ucv[kSrMaxCs][M];
@@ -309,20 +311,16 @@ __global__ __launch_bounds__(kBlock) void k_sr_fixup(const OpParams p, int ncx, 
 #pragma unroll
     for (int jj = 0; jj < kSrMaxCs; ++jj) {
       if (jj < nj) {
-        T rr[M];
-#pragma unroll
-        for (int i = 0; i < M; ++i) rr[i] = jj == 0 ? c.cin[i] * s : k.cin[i] * zd;
-        T nd = T(0);
+        T rr[M], cvv[M], dd[M];
         const size_t cj = (size_t)(J + jj) * M * Pc;
 #pragma unroll
         for (int i = 0; i < M; ++i) {
-          T sm = T(0);
-#pragma unroll
-          for (int j = 0; j < M; ++j) sm += k.Bi[i][j] * rr[j];
-          uc[cj + (size_t)i * Pc + qc] = ucv[jj][i] + k.omega * sm;
-          nd += k.cout[i] * sm;
+          rr[i] = jj == 0 ? c.cin[i] * s : k.cin[i] * zd;
+          cvv[i] = REACT == REACT_COEF ? coefc[cj + (size_t)i * Pc + qc] : T(0);
         }
-        zd = nd;
+        zd = point_correction<M, T, REACT>(k, dgc, cvv, rr, dd);
+#pragma unroll
+        for (int i = 0; i < M; ++i) uc[cj + (size_t)i * Pc + qc] = ucv[jj][i] + k.omega * dd[i];
       }
     }
   }
@@ -331,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_sr_fixup(const OpParams p, int ncx, 
 }  // namespace
 
 bool smooth_restrict_ok(const OpParams& p, int react, int ncx, int ncy, int Nc, int chunk, int cs) {
-  return p.bc == 0 && p.ny > 1 && react == REACT_CONST && p.M >= 1 && p.M <= 4 && p.nx % kSrFX == 0 &&
+  return p.bc == 0 && p.ny > 1 && (react == REACT_CONST || react == REACT_COEF) && p.M >= 1 && p.M <= 4 && p.nx % kSrFX == 0 &&
          p.ny % kSrFY == 0 && ncx * 2 == p.nx && ncy * 2 == p.ny && Nc == p.N && chunk >= 1 && cs >= 1 &&
          cs <= kSrMaxCs && chunk % cs == 0;
 }
@@ -357,10 +355,13 @@ size_t smooth_restrict_zbuf(const OpParams& p, int chunk) {
 }
 
 template <typename T>
-hipError_t launch_smooth_restrict(const OpParams& p, const SweepPtrs<T>& a, int ncx, int ncy, T* fc, int chunk,
-                                  const OpParams* pc, T* uc, int cs, T* zbuf, hipStream_t s) {
-  if (!smooth_restrict_ok(p, REACT_CONST, ncx, ncy, p.N, chunk, cs) || !a.out || !fc) return hipErrorInvalidValue;
+hipError_t launch_smooth_restrict(const OpParams& p, int react, const SweepPtrs<T>& a, int ncx, int ncy, T* fc,
+                                  int chunk, const OpParams* pc, T* uc, const T* coefc, int cs, T* zbuf,
+                                  hipStream_t s) {
+  if (!smooth_restrict_ok(p, react, ncx, ncy, p.N, chunk, cs) || !a.out || !fc) return hipErrorInvalidValue;
+  const bool coef = react == REACT_COEF;
   const bool zs = uc != nullptr && pc != nullptr;
+  if (coef && (!a.coef || (zs && !coefc))) return hipErrorInvalidValue;
   const OpParams& pcc = zs ? *pc : p;
   const int tiles_x = ncx / kSrTCX;
   const int tiles = tiles_x * (ncy / kSrTCY);
@@ -368,22 +369,26 @@ hipError_t launch_smooth_restrict(const OpParams& p, const SweepPtrs<T>& a, int 
   const int nb = smooth_restrict_blocks(p, chunk);
   const int runs = (p.N + rl - 1) / rl;
   if (runs > 1 && !zbuf) return hipErrorInvalidValue;
-#define LK(MM, ZZ, FF) \
-  hipLaunchKernelGGL((k_smooth_restrict<MM, T, ZZ, FF>), dim3(nb), dim3(kBlock), 0, s, p, a, ncx, ncy, fc, rl, chunk, \
-                     tiles_x, tiles, nb, pcc, uc, cs, zbuf)
-#define L(MM)                                                                                                  \
-  if (zs) { if (a.f) LK(MM, true, true); else LK(MM, true, false); }                                           \
-  else { if (a.f) LK(MM, false, true); else LK(MM, false, false); }                                            \
-  if (runs > 1) {                                                                                              \
-    const long long work = (long long)ncx * ncy * (runs - 1);                                                  \
-    const int fb = (int)((work + kBlock - 1) / kBlock);                                                        \
-    if (zs)                                                                                                    \
-      hipLaunchKernelGGL((k_sr_fixup<MM, T, true>), dim3(fb), dim3(kBlock), 0, s, p, ncx, ncy, rl, runs - 1, \
-                         fc, pcc, uc, cs, zbuf);                                                               \
-    else                                                                                                       \
-      hipLaunchKernelGGL((k_sr_fixup<MM, T, false>), dim3(fb), dim3(kBlock), 0, s, p, ncx, ncy, rl,             \
-                         runs - 1, fc, pcc, uc, cs, zbuf);                                                     \
+  const long long work = (long long)ncx * ncy * (runs - 1);
+  const int fb = (int)((work + kBlock - 1) / kBlock);
+#define LK(MM, RE, ZZ, FF)                                                                                     \
+  hipLaunchKernelGGL((k_smooth_restrict<MM, T, RE, ZZ, FF>), dim3(nb), dim3(kBlock), 0, s, p, a, ncx, ncy, fc, rl, \
+                     chunk, tiles_x, tiles, nb, pcc, uc, coefc, cs, zbuf)
+#define LF(MM, RE, ZZ)                                                                                         \
+  hipLaunchKernelGGL((k_sr_fixup<MM, T, RE, ZZ>), dim3(fb), dim3(kBlock), 0, s, p, ncx, ncy, rl, runs - 1, fc, \
+                     pcc, uc, coefc, cs, zbuf)
+#define LR(MM, RE)                                                                                             \
+  if (zs) { if (a.f) LK(MM, RE, true, true); else LK(MM, RE, true, false); }                                   \
+  else { if (a.f) LK(MM, RE, false, true); else LK(MM, RE, false, false); }                                    \
+  if (runs > 1) { if (zs) LF(MM, RE, true); else LF(MM, RE, false); }
+  // FP64 with a reaction coefficient needs over 240 registers (one or two
+  // waves per SIMD): the separate kernels serve it
+  if constexpr (sizeof(T) == 8) {
+    if (coef) return hipErrorNotSupported;
   }
+#define L(MM)                                             \
+  if constexpr (sizeof(T) == 8) { LR(MM, REACT_CONST) }   \
+  else { if (coef) { LR(MM, REACT_COEF) } else { LR(MM, REACT_CONST) } }
   switch (p.M) {
     case 1: L(1); break;
     case 2: L(2); break;
@@ -392,13 +397,16 @@ hipError_t launch_smooth_restrict(const OpParams& p, const SweepPtrs<T>& a, int 
     default: return hipErrorInvalidValue;
   }
 #undef L
+#undef LR
+#undef LF
 #undef LK
   return hipGetLastError();
 }
 
-template hipError_t launch_smooth_restrict<double>(const OpParams&, const SweepPtrs<double>&, int, int, double*,
-                                                   int, const OpParams*, double*, int, double*, hipStream_t);
-template hipError_t launch_smooth_restrict<float>(const OpParams&, const SweepPtrs<float>&, int, int, float*, int,
-                                                  const OpParams*, float*, int, float*, hipStream_t);
+template hipError_t launch_smooth_restrict<double>(const OpParams&, int, const SweepPtrs<double>&, int, int, double*,
+                                                   int, const OpParams*, double*, const double*, int, double*,
+                                                   hipStream_t);
+template hipError_t launch_smooth_restrict<float>(const OpParams&, int, const SweepPtrs<float>&, int, int, float*, int,
+                                                  const OpParams*, float*, const float*, int, float*, hipStream_t);
 
 }  // namespace stmg

@@ -478,7 +478,7 @@ size_t Solver::plan(char* ws) {
   if (lv.size() >= 2) {
     const Level& l = lv[0];
     const Level& c = lv[1];
-    sr = fuse && !allen_cahn && !l.g9 && !c.g9 && (l.kind & 1) && !(l.kind & 2) && !(l.kind & 4) &&
+    sr = fuse && !l.g9 && !c.g9 && (l.kind & 1) && !(l.kind & 2) && !(l.kind & 4) &&
          smooth_restrict_ok(l.op, REACT_CONST, c.nx, c.ny, c.N, chunk_of(0), chunk_of(1)) &&
          smooth_restrict_ok(l.opT, REACT_CONST, c.nx, c.ny, c.N, chunk_of(0), chunk_of(1));
     if (sr) {
@@ -946,8 +946,10 @@ hipError_t Solver::smooth(int l, bool adj, int react, const T* U, const T* f, co
   return launch_smooth<T>(adj ? L.opT : L.op, react, a, chunk_of(l), stream);
 }
 
-bool Solver::sr_usable(int react) const {
-  return sr && fuse && react == REACT_CONST && opt.smoother == STMG_SMOOTH_PBJ;
+bool Solver::sr_usable(int react, bool fp64) const {
+  // a reaction coefficient (Newton) in FP32 only: the FP64 kernel with it needs
+  // too many registers, the separate kernels serve it
+  return sr && fuse && (react == REACT_CONST || (react == REACT_COEF && !fp64)) && opt.smoother == STMG_SMOOTH_PBJ;
 }
 
 template <typename T>
@@ -958,17 +960,18 @@ template <>
 float* sr_zbuf<float>(double*, float* z32) { return z32; }
 
 template <typename T>
-hipError_t Solver::smooth_restrict(bool adj, const T* U, const T* f, const double* u0, T* out, T* fc, T* uc,
-                                   double* part_out, bool* smoothed) {
+hipError_t Solver::smooth_restrict(bool adj, int react, const T* U, const T* f, const double* u0, T* out, T* fc,
+                                   T* uc, double* part_out, bool* smoothed) {
   const Level& L = lv[0];
   const Level& C = lv[1];
-  SweepPtrs<T> a{U, f, u0, nullptr, out, part_out};
+  SweepPtrs<T> a{U, f, u0, react == REACT_COEF ? coef_of<T>(L) : nullptr, out, part_out};
   if (part_out && smooth_restrict_blocks(L.op, chunk_of(0)) > max_parts) {
     set_error("partial buffer too small");
     return hipErrorInvalidValue;
   }
   if (smoothed) *smoothed = uc != nullptr;
-  return launch_smooth_restrict<T>(adj ? L.opT : L.op, a, C.nx, C.ny, fc, chunk_of(0), adj ? &C.opT : &C.op, uc,
+  return launch_smooth_restrict<T>(adj ? L.opT : L.op, react, a, C.nx, C.ny, fc, chunk_of(0),
+                                   adj ? &C.opT : &C.op, uc, react == REACT_COEF ? coef_of<T>(C) : nullptr,
                                    chunk_of(1), sr_zbuf<T>(sr_z64, sr_z32), stream);
 }
 
@@ -1125,10 +1128,10 @@ hipError_t Solver::vcycle(int l, bool adj, int react, T* cur, T* oth, const T* f
     smoothed = sr_smoothed;
     sr_pending = false;
   }
-  const bool use_sr = l == 0 && !restricted && sr_usable(react) && opt.nu_pre > skip_pre;
+  const bool use_sr = l == 0 && !restricted && sr_usable(react, sizeof(T) == 8) && opt.nu_pre > skip_pre;
   for (int s = skip_pre; s < opt.nu_pre; ++s) {
     if (use_sr && s == opt.nu_pre - 1) {
-      HIP_TRY(smooth_restrict<T>(adj, zero ? nullptr : cur, f, u0, oth, cf, want ? ca : nullptr, nullptr,
+      HIP_TRY(smooth_restrict<T>(adj, react, zero ? nullptr : cur, f, u0, oth, cf, want ? ca : nullptr, nullptr,
                                  &smoothed));
       restricted = true;
     } else {
@@ -1256,11 +1259,12 @@ int Solver::solve_linear(bool adj, int react, const double* f, const double* u0,
   double* const out = hnorm.d;
   sr_pending = false;
   auto launch_norm = [&]() -> hipError_t {
-    if (fused && opt.nu_pre == 1 && lv.size() > 1 && sr_usable(react)) {
+    if (fused && opt.nu_pre == 1 && lv.size() > 1 && sr_usable(react, true)) {
       // the only pre-smoothing sweep also restricts
       Level& C = lv[1];
       const bool want = fuse && lv.size() > 2;
-      HIP_TRY(smooth_restrict<double>(adj, U, f, u0, L0.B64, C.f64, want ? C.A64 : nullptr, part, &sr_smoothed));
+      HIP_TRY(smooth_restrict<double>(adj, react, U, f, u0, L0.B64, C.f64, want ? C.A64 : nullptr, part,
+                                      &sr_smoothed));
       sr_pending = true;
       HIP_TRY(launch_sum_partials(part, smooth_restrict_blocks(op0, chunk_of(0)), out, stream));
     } else if (fused) {
@@ -1988,8 +1992,8 @@ int Solver::sdc_core(const double* u0, double* U, int sweeps) {
 // explicit instantiations used by the C ABI
 template hipError_t Solver::smooth<double>(int, bool, int, const double*, const double*, const double*, double*);
 template hipError_t Solver::restrict_residual<double>(int, bool, int, const double*, const double*, const double*, double*, double*, bool*);
-template hipError_t Solver::smooth_restrict<double>(bool, const double*, const double*, const double*, double*, double*,
-                                                    double*, double*, bool*);
+template hipError_t Solver::smooth_restrict<double>(bool, int, const double*, const double*, const double*, double*,
+                                                    double*, double*, double*, bool*);
 template hipError_t Solver::prolong<double>(int, const double*, const double*, double*);
 template hipError_t Solver::coarse<double>(bool, int, const double*, const double*, double*);
 template hipError_t Solver::residual64<double>(bool, int, const double*, const double*, const double*, double*,
@@ -2105,7 +2109,7 @@ int Solver::autotune() {
 }
 
 template hipError_t Solver::restrict_residual<float>(int, bool, int, const float*, const float*, const double*, float*, float*, bool*);
-template hipError_t Solver::smooth_restrict<float>(bool, const float*, const float*, const double*, float*, float*,
-                                                   float*, double*, bool*);
+template hipError_t Solver::smooth_restrict<float>(bool, int, const float*, const float*, const double*, float*,
+                                                   float*, float*, double*, bool*);
 
 }  // namespace stmg

@@ -257,9 +257,9 @@ struct Solver {
                                const double* u0, T* fc, T* uc = nullptr, bool* smoothed = nullptr);
   // Level 0: one smoothing sweep U -> out fused with f_c = R (f - A out)
   // (uc: the coarse first sweep), part: per-workgroup ||f - A U||^2 or null.
-  bool sr_usable(int react) const;
+  bool sr_usable(int react, bool fp64) const;
   template <typename T>
-  hipError_t smooth_restrict(bool adj, const T* U, const T* f, const double* u0, T* out, T* fc, T* uc,
+  hipError_t smooth_restrict(bool adj, int react, const T* U, const T* f, const double* u0, T* out, T* fc, T* uc,
                              double* part_out, bool* smoothed);
   template <typename T>
   hipError_t prolong_smooth(int l, bool adj, int react, const T* Uin, const T* ec, const T* f,
