@@ -763,18 +763,35 @@ struct Blk {
   __device__ __forceinline__ int q(int k, int nx) const { return (y0 + (k >> 1)) * nx + x0 + (k & 1); }
 };
 
-// Values and scaled 5-point Laplacians of the block's points, all M nodes.
+// The block's own rows (x0, x0 + 1 of rows y0 .. y0 + BY - 1), all M nodes.
+template <int M, typename T, int BY>
+__device__ __forceinline__ void load_rows(const T* __restrict__ U, size_t base, int P,
+                                          const Blk<BY>& b, T own[M][BY][2]) {
+  constexpr unsigned E = sizeof(T);
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const gcptr Um = ubase(U + base + (size_t)m * P);
+#pragma unroll
+    for (int j = 0; j < BY; ++j) ld2o(Um, b.orow[j + 1] * E, own[m][j][0], own[m][j][1]);
+  }
+}
+
+// Values and scaled 5-point Laplacians of the block's points, all M nodes,
+// from the block's own rows (already loaded) and its neighbours.
 template <int M, typename T, int BY, bool TWOD>
-__device__ __forceinline__ void load_blk(const T* __restrict__ U, size_t base, int P, int nx,
-                                         const Blk<BY>& b, T cx, T cy, T u[2 * BY][M],
-                                         T lap[2 * BY][M]) {
+__device__ __forceinline__ void blk_from_rows(const T* __restrict__ U, size_t base, int P,
+                                              const Blk<BY>& b, T cx, T cy, const T own[M][BY][2],
+                                              T u[2 * BY][M], T lap[2 * BY][M]) {
   constexpr unsigned E = sizeof(T);
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const gcptr Um = ubase(U + base + (size_t)m * P);
     T rw[BY + 2][2];
 #pragma unroll
-    for (int j = 0; j < BY; ++j) ld2o(Um, b.orow[j + 1] * E, rw[j + 1][0], rw[j + 1][1]);
+    for (int j = 0; j < BY; ++j) {
+      rw[j + 1][0] = own[m][j][0];
+      rw[j + 1][1] = own[m][j][1];
+    }
     if (TWOD) {
       ld2o(Um, b.orow[0] * E, rw[0][0], rw[0][1]);
       ld2o(Um, b.orow[BY + 1] * E, rw[BY + 1][0], rw[BY + 1][1]);
@@ -795,6 +812,16 @@ __device__ __forceinline__ void load_blk(const T* __restrict__ U, size_t base, i
       lap[2 * j + 1][m] = l1;
     }
   }
+}
+
+// Values and scaled 5-point Laplacians of the block's points, all M nodes.
+template <int M, typename T, int BY, bool TWOD>
+__device__ __forceinline__ void load_blk(const T* __restrict__ U, size_t base, int P, int nx,
+                                         const Blk<BY>& b, T cx, T cy, T u[2 * BY][M],
+                                         T lap[2 * BY][M]) {
+  T own[M][BY][2];
+  load_rows<M, T, BY>(U, base, P, b, own);
+  blk_from_rows<M, T, BY, TWOD>(U, base, P, b, cx, cy, own, u, lap);
 }
 
 // Loads an M-node field (f or coef) on the block's own points.

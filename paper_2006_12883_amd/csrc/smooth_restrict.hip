@@ -110,17 +110,34 @@ __global__ __launch_bounds__(kBlock) void k_smooth_restrict(const OpParams p, co
     }
     const int qc = Y * ncx + X;
     T zdprev = T(0);
+    // the block's own rows of the next slab are loaded at the end of the
+    // current slab's sweep, so their memory latency overlaps its residual
+    // and restriction phases
+    T own[M][2][2];
+    if (a.U) load_rows<M, T, 2>(a.U, (size_t)n0 * M * P, P, b, own);
     for (int n = n0; n < n1; ++n) {
       const size_t base = (size_t)n * M * P;
       // (1) the sweep: own block, then the ring point
       T u[4][M], lap[4][M], fv[4][M], r[4][M], d[4][M], o[2][M];
+      // the ring point's values are loaded with the block's (every thread
+      // loads a valid point: without a ring point, the tile's corner), so a
+      // slab step waits for one round of loads
+      T ru[M], rl[M], rfv[M], rcv[M];
       if (a.U) {
-        load_blk<M, T, 2, true>(a.U, base, P, nx, b, c.cx, c.cy, u, lap);
+        blk_from_rows<M, T, 2, true>(a.U, base, P, b, c.cx, c.cy, own, u, lap);
+        load_point<M, T>(a.U, base, P, rq, rn, true, c.cx, c.cy, ru, rl);
       } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
           for (int m = 0; m < M; ++m) u[k][m] = lap[k][m] = T(0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) ru[m] = rl[m] = T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        rcv[i] = REACT == REACT_COEF ? a.coef[base + (size_t)i * P + rq] : T(0);
+        rfv[i] = HASF ? a.f[base + (size_t)i * P + rq] : T(0);
       }
       T cv[4][M];
       if (REACT == REACT_COEF) load_own<M, T, 2>(a.coef, base, P, nx, b, cv);
@@ -174,21 +191,11 @@ __global__ __launch_bounds__(kBlock) void k_smooth_restrict(const OpParams p, co
       }
       T hr[M];
       const T rzp = rdprev;
+      resid_vals<M, T, REACT>(c, ru, rl, rfv, rcv, rprev, hr);
       if (ring) {
-        T ru[M], rl[M];
-        if (a.U) {
-          load_point<M, T>(a.U, base, P, rq, rn, true, c.cx, c.cy, ru, rl);
-        } else {
+        T x[M], rd[M];
 #pragma unroll
-          for (int m = 0; m < M; ++m) ru[m] = rl[m] = T(0);
-        }
-        point_residual<M, T, REACT>(c, ru, rl, a.coef, HASF ? a.f : nullptr, base, P, rq, rprev, hr);
-        T x[M], rd[M], rcv[M];
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-          x[i] = cstart ? hr[i] : hr[i] + c.cin[i] * rdprev;
-          rcv[i] = REACT == REACT_COEF ? a.coef[base + (size_t)i * P + rq] : T(0);
-        }
+        for (int i = 0; i < M; ++i) x[i] = cstart ? hr[i] : hr[i] + c.cin[i] * rdprev;
         const T nd = point_correction<M, T, REACT>(c, dg, rcv, x, rd);
         T np = T(0);
 #pragma unroll
@@ -199,6 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_restrict(const OpParams p, co
         rprev = np;
         rdprev = nd;
       }
+      if (a.U && n + 1 < n1) load_rows<M, T, 2>(a.U, base + (size_t)M * P, P, b, own);
       __syncthreads();
       // (2) residuals of U': (1 - omega) r + omega db (cx (d_W + d_E) + cy (d_S + d_N))
       const T om = c.omega, om1 = T(1) - c.omega;
