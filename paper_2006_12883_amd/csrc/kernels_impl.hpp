@@ -735,6 +735,43 @@ __device__ __forceinline__ void st2o_nt(gptr b, unsigned o, T x, T y) {
   __builtin_nontemporal_store(v, (__attribute__((address_space(1))) v2*)(b + o));
 }
 
+// Lane exchanges inside a wave (DPP wavefront shifts): lane l receives the
+// value of lane l - 1 (from_below) or lane l + 1 (from_above); a lane
+// without a source lane receives 0.  Values move unchanged.  The whole wave
+// must reach them (never inside a divergent branch).
+__device__ __forceinline__ int dpp_from_below(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+__device__ __forceinline__ int dpp_from_above(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);  // wave_shl:1
+}
+__device__ __forceinline__ float lane_from_below(float v) {
+  return __int_as_float(dpp_from_below(__float_as_int(v)));
+}
+__device__ __forceinline__ float lane_from_above(float v) {
+  return __int_as_float(dpp_from_above(__float_as_int(v)));
+}
+__device__ __forceinline__ double lane_from_below(double v) {
+  const unsigned long long x = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = static_cast<unsigned>(dpp_from_below(static_cast<int>(x)));
+  const unsigned hi = static_cast<unsigned>(dpp_from_below(static_cast<int>(x >> 32)));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+__device__ __forceinline__ double lane_from_above(double v) {
+  const unsigned long long x = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = static_cast<unsigned>(dpp_from_above(static_cast<int>(x)));
+  const unsigned hi = static_cast<unsigned>(dpp_from_above(static_cast<int>(x >> 32)));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Which x neighbours of a thread's block the adjacent lanes hold: xl, the
+// block to the left is lane l - 1's; xr, the block to the right is lane
+// l + 1's.  Callers that exchange through them guarantee that no lane has
+// both false (it would need two loads).
+struct LaneNbrs {
+  bool xl, xr;
+};
+
 // Geometry of the 2 x BY block owned by thread t of a plane (periodic), with
 // the element offsets (inside a plane) of its rows and side points.
 template <int BY>
@@ -762,6 +799,19 @@ struct Blk {
   // plane offset of block point k (k = j * 2 + i)
   __device__ __forceinline__ int q(int k, int nx) const { return (y0 + (k >> 1)) * nx + x0 + (k & 1); }
 };
+
+// Lane neighbours when thread t owns block t (consecutive lanes hold
+// consecutive blocks of a row): the left block is lane l - 1's unless l is
+// the wave's first lane or the block starts its row, the right block lane
+// l + 1's unless l is the last lane or the block ends its row.  Lanes past
+// the plane's last block are never a source (that block ends its row).  A
+// row of nx / 2 blocks with nx a multiple of 4 never both starts and ends on
+// one lane's block at a wave boundary, so no lane lacks both neighbours.
+template <int BY>
+__device__ __forceinline__ LaneNbrs lane_nbrs(const Blk<BY>& b, int nx) {
+  const int lane = threadIdx.x & 63;
+  return LaneNbrs{lane > 0 && b.x0 > 0, lane < 63 && b.x0 + 2 < nx};
+}
 
 // The block's own rows (x0, x0 + 1 of rows y0 .. y0 + BY - 1), all M nodes.
 template <int M, typename T, int BY>
@@ -1939,10 +1989,13 @@ struct CoarseNbr {
 // rows' dx = -1..2 and the halo rows' dx = 0..1 are used.  Space
 // interpolation is linear per dimension (fine 2X = coarse X), time
 // interpolation linear in slab end points (coarse slab -1 is zero).
-template <int M, typename T, bool SP, bool TM, int BY, bool TWOD>
+// With XS (space prolongation) a lane loads its coarse column X and, for a
+// lane at a row or wave end, the column beyond that end; column X + 1 comes
+// from lane l + 1 where ln.xr (column X - 1 is needed only where !ln.xl).
+template <int M, typename T, bool SP, bool TM, int BY, bool TWOD, bool XS = false>
 __device__ __forceinline__ void corr_blk(const T* __restrict__ ec, int n, int m, int Pc,
                                          const Blk<BY>& b, const CoarseNbr<T, SP, TWOD, BY>& cn,
-                                         T cr[BY + 2][4]) {
+                                         T cr[BY + 2][4], LaneNbrs ln = LaneNbrs{false, false}) {
   constexpr unsigned E = sizeof(T);
   int js[2];
   T wt[2];
@@ -1963,10 +2016,25 @@ __device__ __forceinline__ void corr_blk(const T* __restrict__ ec, int n, int m,
     const T w = wt[tt];
     if (SP) {
       T cv[3][3];
+      if (XS) {
+        T ce[3];
 #pragma unroll
-      for (int yy = 0; yy < (TWOD ? 3 : 1); ++yy)
+        for (int yy = 0; yy < (TWOD ? 3 : 1); ++yy) {
+          cv[yy][1] = ldo<T>(Ec, cn.ocy[yy] + cn.ocx[1]);
+          ce[yy] = ldo<T>(Ec, cn.ocy[yy] + (ln.xl ? cn.ocx[2] : cn.ocx[0]));
+        }
 #pragma unroll
-        for (int xx = 0; xx < 3; ++xx) cv[yy][xx] = ldo<T>(Ec, cn.ocy[yy] + cn.ocx[xx]);
+        for (int yy = 0; yy < (TWOD ? 3 : 1); ++yy) {
+          const T fa = lane_from_above(cv[yy][1]);
+          cv[yy][0] = ce[yy];
+          cv[yy][2] = ln.xr ? fa : ce[yy];
+        }
+      } else {
+#pragma unroll
+        for (int yy = 0; yy < (TWOD ? 3 : 1); ++yy)
+#pragma unroll
+          for (int xx = 0; xx < 3; ++xx) cv[yy][xx] = ldo<T>(Ec, cn.ocy[yy] + cn.ocx[xx]);
+      }
       // x interpolation of each coarse row at fine dx = -1, 0, 1, 2
       T rx[3][4];
 #pragma unroll
@@ -2008,17 +2076,20 @@ __device__ __forceinline__ void corr_blk(const T* __restrict__ ec, int n, int m,
 // U' = U + P e_c on the own points of block b in fine slab n: node values
 // and scaled 5-point Laplacians (U' is formed on the halo too, never stored).
 // U may be null (zero).
-template <int M, typename T, bool SP, bool TM, int BY, bool TWOD>
+// With XS the side values of U' come from the adjacent lanes where ln says
+// so (each lane at a row or wave end loads its one missing side).
+template <int M, typename T, bool SP, bool TM, int BY, bool TWOD, bool XS = false>
 __device__ __forceinline__ void prolonged_blk(const Consts<M, T>& c, const T* __restrict__ U,
                                               const T* __restrict__ ec, int n, int P, int Pc,
                                               const Blk<BY>& b,
                                               const CoarseNbr<T, SP, TWOD, BY>& cn,
-                                              T u[2 * BY][M], T lap[2 * BY][M]) {
+                                              T u[2 * BY][M], T lap[2 * BY][M],
+                                              LaneNbrs ln = LaneNbrs{false, false}) {
   constexpr unsigned E = sizeof(T);
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     T cr[BY + 2][4];
-    corr_blk<M, T, SP, TM, BY, TWOD>(ec, n, m, Pc, b, cn, cr);
+    corr_blk<M, T, SP, TM, BY, TWOD, XS && SP>(ec, n, m, Pc, b, cn, cr, ln);
     const gcptr Um = U ? ubase(U + (size_t)(n * M + m) * P) : nullptr;
     T rw[BY + 2][2];
 #pragma unroll
@@ -2029,11 +2100,24 @@ __device__ __forceinline__ void prolonged_blk(const Consts<M, T>& c, const T* __
       rw[j][0] = v0 + cr[j][1];
       rw[j][1] = v1 + cr[j][2];
     }
+    T es[BY];
+    if (XS) {
+#pragma unroll
+      for (int j = 0; j < BY; ++j)
+        es[j] = Um ? ldo<T>(Um, (ln.xl ? b.oside[j][1] : b.oside[j][0]) * E) : T(0);
+    }
 #pragma unroll
     for (int j = 0; j < BY; ++j) {
-      const T l = (Um ? ldo<T>(Um, b.oside[j][0] * E) : T(0)) + cr[j + 1][0];
-      const T r = (Um ? ldo<T>(Um, b.oside[j][1] * E) : T(0)) + cr[j + 1][3];
       const T c0 = rw[j + 1][0], c1 = rw[j + 1][1];
+      T l, r;
+      if (XS) {
+        const T fl = lane_from_below(c1), fr = lane_from_above(c0);
+        l = ln.xl ? fl : es[j] + cr[j + 1][0];
+        r = ln.xr ? fr : es[j] + cr[j + 1][3];
+      } else {
+        l = (Um ? ldo<T>(Um, b.oside[j][0] * E) : T(0)) + cr[j + 1][0];
+        r = (Um ? ldo<T>(Um, b.oside[j][1] * E) : T(0)) + cr[j + 1][3];
+      }
       T l0 = c.cx * (l + c1 - c0 - c0);
       T l1 = c.cx * (c0 + r - c1 - c1);
       if (TWOD) {
@@ -2078,7 +2162,7 @@ __device__ __forceinline__ void prolonged_cout(const Consts<M, T>& c, const T* _
 // Prolongation fused with the first post-smoothing sweep:
 //   U' = U + P e_c,  U_out = U' + omega D^{-1} (f - A U')
 // on 2 x BY blocks, each thread marching through its run of S slabs.
-template <int M, typename T, int REACT, bool SP, bool TM, int BY, bool TWOD>
+template <int M, typename T, int REACT, bool SP, bool TM, int BY, bool TWOD, bool XS = false>
 __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const SweepPtrs<T>& a, int ncx,
                                                     int ncy, int Nc, const T* __restrict__ ec, int S,
                                                     int tile, int n0, int pslot) {
@@ -2109,10 +2193,11 @@ __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const Swe
     } else {
       prolonged_cout<M, T, SP, TM, BY, TWOD>(c, a.U, ec, n0 - 1, P, Pc, b, cn, prev);
     }
+    const LaneNbrs ln = lane_nbrs<BY>(b, nx);
     for (int n = n0; n < n1; ++n) {
       const size_t base = (size_t)n * M * P;
       T u[NP][M], lap[NP][M], fv[NP][M], cv[NP][M], o[NP][M];
-      prolonged_blk<M, T, SP, TM, BY, TWOD>(c, a.U, ec, n, P, Pc, b, cn, u, lap);
+      prolonged_blk<M, T, SP, TM, BY, TWOD, XS>(c, a.U, ec, n, P, Pc, b, cn, u, lap, ln);
       if (a.f) {
         load_own<M, T, BY>(a.f, base, P, nx, b, fv);
       } else {
@@ -2161,14 +2246,15 @@ __device__ __forceinline__ void prolong_smooth_body(const OpParams& p, const Swe
   }
 }
 
-template <int M, typename T, int REACT, bool SP, bool TM, int BY, bool TWOD>
+// XS: x neighbours exchanged between lanes (nx a multiple of 4).
+template <int M, typename T, int REACT, bool SP, bool TM, int BY, bool TWOD, bool XS = false>
 __global__ __launch_bounds__(kBlock) void k_prolong_smooth_blk(const OpParams p, const SweepPtrs<T> a,
                                                                int ncx, int ncy, int Nc,
                                                                const T* __restrict__ ec, int S,
                                                                int tiles, int nblocks) {
   const int lb = xcd_remap(blockIdx.x, nblocks);
-  prolong_smooth_body<M, T, REACT, SP, TM, BY, TWOD>(p, a, ncx, ncy, Nc, ec, S, lb % tiles,
-                                                     (lb / tiles) * S, lb);
+  prolong_smooth_body<M, T, REACT, SP, TM, BY, TWOD, XS>(p, a, ncx, ncy, Nc, ec, S, lb % tiles,
+                                                         (lb / tiles) * S, lb);
 }
 
 // Slab-parallel form of the fused prolongation + post-smoothing for small

@@ -353,15 +353,20 @@ hipError_t launch_prolong_smooth(const OpParams& p, int react, const SweepPtrs<T
   }
   const int nb = smooth_blocks(p, chunk);
   const int tiles = (plane_threads(p) + kBlock - 1) / kBlock;
-#define LF(MM, RE, SPc, TMc, BYc, TWc)                                                            \
-  hipLaunchKernelGGL((k_prolong_smooth_blk<MM, T, RE, SPc, TMc, BYc, TWc>), dim3(nb), dim3(kBlock), \
+  // x neighbours exchanged between lanes (2D, nx a multiple of 4; M = 3,
+  // where it cuts the loads per slab without costing a wave per SIMD)
+  const bool xs = twod && (p.nx % 4) == 0;
+#define LF(MM, RE, SPc, TMc, BYc, TWc, XSc)                                                          \
+  hipLaunchKernelGGL((k_prolong_smooth_blk<MM, T, RE, SPc, TMc, BYc, TWc, XSc>), dim3(nb), dim3(kBlock), \
                      0, s, p, a, ncx, ncy, Nc, ec, chunk, tiles, nb)
-#define LFS(MM, RE, BYc, TWc)                                   \
-  if (space && time) LF(MM, RE, true, true, BYc, TWc);          \
-  else if (space) LF(MM, RE, true, false, BYc, TWc);            \
-  else LF(MM, RE, false, true, BYc, TWc);
-#define LFR(MM, RE) \
-  if (twod) { LFS(MM, RE, 2, true) } else { LFS(MM, RE, 1, false) }
+#define LFS(MM, RE, BYc, TWc, XSc)                                   \
+  if (space && time) LF(MM, RE, true, true, BYc, TWc, XSc);          \
+  else if (space) LF(MM, RE, true, false, BYc, TWc, XSc);            \
+  else LF(MM, RE, false, true, BYc, TWc, XSc);
+#define LFR(MM, RE)                                                   \
+  if (twod && xs) { LFS(MM, RE, 2, true, (MM == 3)) }                \
+  else if (twod) { LFS(MM, RE, 2, true, false) }                      \
+  else { LFS(MM, RE, 1, false, false) }
 #define L(MM) \
   if (react == REACT_COEF) { LFR(MM, REACT_COEF) } else { LFR(MM, REACT_CONST) }
   STMG_DISPATCH_M(L)
