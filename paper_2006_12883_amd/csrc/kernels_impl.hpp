@@ -2077,26 +2077,29 @@ __device__ __forceinline__ void corr_blk(const T* __restrict__ ec, int n, int m,
 // and scaled 5-point Laplacians (U' is formed on the halo too, never stored).
 // U may be null (zero).
 // With XS the side values of U' come from the adjacent lanes where ln says
-// so (each lane at a row or wave end loads its one missing side).
-template <int M, typename T, bool SP, bool TM, int BY, bool TWOD, bool XS = false>
-__device__ __forceinline__ void prolonged_blk(const Consts<M, T>& c, const T* __restrict__ U,
-                                              const T* __restrict__ ec, int n, int P, int Pc,
-                                              const Blk<BY>& b,
-                                              const CoarseNbr<T, SP, TWOD, BY>& cn,
-                                              T u[2 * BY][M], T lap[2 * BY][M],
-                                              LaneNbrs ln = LaneNbrs{false, false}) {
+// so (each lane at a row or wave end loads its one missing side).  UM: 0
+// tests U for null at every access, 1 and 2 take U as present and as null
+// (zero), so that the loads of all nodes form one straight run the compiler
+// issues together ahead of the lane exchanges.
+template <int M, typename T, bool SP, bool TM, int BY, bool TWOD, bool XS, int UM>
+__device__ __forceinline__ void prolonged_blk_u(const Consts<M, T>& c, const T* __restrict__ U,
+                                                const T* __restrict__ ec, int n, int P, int Pc,
+                                                const Blk<BY>& b,
+                                                const CoarseNbr<T, SP, TWOD, BY>& cn,
+                                                T u[2 * BY][M], T lap[2 * BY][M], LaneNbrs ln) {
   constexpr unsigned E = sizeof(T);
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     T cr[BY + 2][4];
     corr_blk<M, T, SP, TM, BY, TWOD, XS && SP>(ec, n, m, Pc, b, cn, cr, ln);
-    const gcptr Um = U ? ubase(U + (size_t)(n * M + m) * P) : nullptr;
+    const gcptr Um = UM == 2 ? nullptr : (UM == 1 || U) ? ubase(U + (size_t)(n * M + m) * P) : nullptr;
+    const bool hu = UM == 1 ? true : UM == 2 ? false : Um != nullptr;
     T rw[BY + 2][2];
 #pragma unroll
     for (int j = 0; j < BY + 2; ++j) {
       if (!TWOD && j != 1) continue;
       T v0 = T(0), v1 = T(0);
-      if (Um) ld2o(Um, b.orow[j] * E, v0, v1);
+      if (hu) ld2o(Um, b.orow[j] * E, v0, v1);
       rw[j][0] = v0 + cr[j][1];
       rw[j][1] = v1 + cr[j][2];
     }
@@ -2104,7 +2107,7 @@ __device__ __forceinline__ void prolonged_blk(const Consts<M, T>& c, const T* __
     if (XS) {
 #pragma unroll
       for (int j = 0; j < BY; ++j)
-        es[j] = Um ? ldo<T>(Um, (ln.xl ? b.oside[j][1] : b.oside[j][0]) * E) : T(0);
+        es[j] = hu ? ldo<T>(Um, (ln.xl ? b.oside[j][1] : b.oside[j][0]) * E) : T(0);
     }
 #pragma unroll
     for (int j = 0; j < BY; ++j) {
@@ -2115,8 +2118,8 @@ __device__ __forceinline__ void prolonged_blk(const Consts<M, T>& c, const T* __
         l = ln.xl ? fl : es[j] + cr[j + 1][0];
         r = ln.xr ? fr : es[j] + cr[j + 1][3];
       } else {
-        l = (Um ? ldo<T>(Um, b.oside[j][0] * E) : T(0)) + cr[j + 1][0];
-        r = (Um ? ldo<T>(Um, b.oside[j][1] * E) : T(0)) + cr[j + 1][3];
+        l = (hu ? ldo<T>(Um, b.oside[j][0] * E) : T(0)) + cr[j + 1][0];
+        r = (hu ? ldo<T>(Um, b.oside[j][1] * E) : T(0)) + cr[j + 1][3];
       }
       T l0 = c.cx * (l + c1 - c0 - c0);
       T l1 = c.cx * (c0 + r - c1 - c1);
@@ -2129,6 +2132,22 @@ __device__ __forceinline__ void prolonged_blk(const Consts<M, T>& c, const T* __
       lap[2 * j][m] = l0;
       lap[2 * j + 1][m] = l1;
     }
+  }
+}
+
+template <int M, typename T, bool SP, bool TM, int BY, bool TWOD, bool XS = false>
+__device__ __forceinline__ void prolonged_blk(const Consts<M, T>& c, const T* __restrict__ U,
+                                              const T* __restrict__ ec, int n, int P, int Pc,
+                                              const Blk<BY>& b,
+                                              const CoarseNbr<T, SP, TWOD, BY>& cn,
+                                              T u[2 * BY][M], T lap[2 * BY][M],
+                                              LaneNbrs ln = LaneNbrs{false, false}) {
+  if (!XS) {
+    prolonged_blk_u<M, T, SP, TM, BY, TWOD, false, 0>(c, U, ec, n, P, Pc, b, cn, u, lap, ln);
+  } else if (U) {
+    prolonged_blk_u<M, T, SP, TM, BY, TWOD, XS, 1>(c, U, ec, n, P, Pc, b, cn, u, lap, ln);
+  } else {
+    prolonged_blk_u<M, T, SP, TM, BY, TWOD, XS, 2>(c, U, ec, n, P, Pc, b, cn, u, lap, ln);
   }
 }
 
