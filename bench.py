@@ -30,27 +30,34 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of the V-cycle's longest kernels from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, scaled by what the counters read for a device copy of known
 # size (FETCH x 2, WRITE x 1; profiles/k_prolong_smooth_blk_rd2d_level0.md),
-# valid only for the kernel source the counters were taken on.
+# valid only while the kernel's source files (one hash over their
+# concatenation) are the ones the counters were taken on.
 TRAFFIC = {
-    "k_prolong_smooth_blk": {"source": "kernels_impl.hpp", "sha256_prefix": "29c79ebcf9cc7990",
-                             "bytes_per_launch": 520.8e6 + 402.7e6},
+    "k_prolong_smooth_blk": {"sources": ["kernels_impl.hpp", "launchers.hpp"],
+                             "sha256_prefix": "e684e6ec938869c4",
+                             "bytes_per_launch": 531.6e6 + 402.7e6},
     # the fused level-0 sweep + restriction and its run-boundary pass
     # (profiles/k_smooth_restrict_rd2d_level0.md)
-    "k_smooth_restrict": {"source": "smooth_restrict.hip", "sha256_prefix": "5ee25d65e866eb5f",
-                          "bytes_per_launch": 414.7e6 + 607.7e6 + 18.4e6 + 13.8e6},
+    "k_smooth_restrict": {"sources": ["smooth_restrict.hip", "kernels_impl.hpp"],
+                          "sha256_prefix": "4ecd665be0ad03a9",
+                          "bytes_per_launch": 424.8e6 + 607.7e6 + 18.4e6 + 13.8e6},
 }
+
+
+def sources_hash(files):
+    """sha256 prefix (16 hex digits) of the concatenated kernel sources."""
+    import hashlib
+    d = b"".join(open(os.path.join(ROOT, "paper_2006_12883_amd", "csrc", f), "rb").read() for f in files)
+    return hashlib.sha256(d).hexdigest()[:16]
 
 
 def measured_traffic(kernel):
     """Counter-measured HBM bytes per launch of `kernel`, while its source
-    file hashes to the one the counters were taken on (else None)."""
-    import hashlib
+    files hash to the ones the counters were taken on (else None)."""
     t = TRAFFIC.get(kernel)
     if t is None:
         return None
-    src = os.path.join(ROOT, "paper_2006_12883_amd", "csrc", t["source"])
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    return t["bytes_per_launch"] if h == t["sha256_prefix"] else None
+    return t["bytes_per_launch"] if sources_hash(t["sources"]) == t["sha256_prefix"] else None
 
 
 def sr_run_len(nx, ny, N, chunk=16):
