@@ -330,7 +330,8 @@ def test_full_size_smoother_and_vcycle():
 def test_prolong_smooth_each_level(name, prob):
     """The fused way up (stmg_level_prolong_smooth): U' = U + P e_c, then one
     block-Jacobi sweep, against the oracle's prolongation followed by its
-    smoother; on level 0 also with the right-hand side built from u0."""
+    smoother, from a given and from a zero (NULL) iterate; on level 0 also
+    with the right-hand side built from u0."""
     print("case", name, flush=True)
     levels, kinds = mg.hierarchy(prob, fft_coarse=0)
     h = H(prob, fft_coarse=0)
@@ -351,6 +352,10 @@ def test_prolong_smooth_each_level(name, prob):
         ref = lev.smooth(Up, f, 0.8, 16 if l == 0 else 4)
         h.prolong_smooth(l, T(ec), out, Uin=T(U), f=T(f))
         assert_close(out.cpu().numpy(), ref, 1e-12, "prolong+smooth level %d kind %s" % (l, kinds[l]))
+        # zero iterate (U passed as NULL): U' = P e_c
+        refz = lev.smooth(mg.prolong(ec, kinds[l], lev.dim, lev.Pm), f, 0.8, 16 if l == 0 else 4)
+        h.prolong_smooth(l, T(ec), out, f=T(f))
+        assert_close(out.cpu().numpy(), refz, 1e-12, "prolong+smooth level %d from zero" % l)
         if l == 0:
             u0 = rng.standard_normal((ny, nx))
             f0 = mg.rhs(levels, u0)
